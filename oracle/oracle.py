@@ -1,0 +1,189 @@
+"""ctypes wrapper of the FP64 oracle (``liboracle.so`` built from ``tsr_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the test-suite, the smoke check and the CPU-baseline
+leg of the benchmark.  It never imports the HIP package; the only thing the two sides share
+is the seeded input arrays.
+
+Inputs are normally the float32 arrays the GPU path also receives; they are promoted to FP64
+exactly.  Float64 inputs pass unchanged, which lets finite differences perturb them freely.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+SOURCE = os.path.join(_HERE, "tsr_oracle.c")
+# Compiler line used by the build step (kept here so the build and a stale-check agree).
+CFLAGS = ["-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-std=c11"]
+
+
+class _Scene(C.Structure):
+    _fields_ = [("pos", C.c_void_p), ("col", C.c_void_p), ("opa", C.c_void_p),
+                ("faces", C.c_void_p), ("n_vertices", C.c_int64), ("n_faces", C.c_int64)]
+
+
+class _Cam(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_double), ("fy", C.c_double),
+                ("cx", C.c_double), ("cy", C.c_double)]
+
+
+class _Par(C.Structure):
+    _fields_ = [("sigma", C.c_double), ("z_near", C.c_double), ("r_min", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"oracle library not built: {LIB_PATH} (run __graft_entry__.build())")
+        _lib = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        _lib.orc_render.argtypes = [P, P, P, P, P, C.c_int64, P, P, P]
+        _lib.orc_backward.argtypes = [P, P, P, P, P, C.c_int64, P, P, P, P, P, P, P]
+        _lib.orc_project.argtypes = [P, P, P, P, P, P, P, P]
+        _lib.orc_bin.argtypes = [P, P, P, C.c_int, P, C.c_int64, P, P, P, P, P]
+        _lib.orc_l1_seeds.argtypes = [P, P, P, P, C.c_int64, C.c_int64, C.c_double, C.c_double, P, P]
+        _lib.orc_l1_seeds.restype = C.c_double
+        _lib.orc_set_threads.argtypes = [C.c_int]
+        _lib.orc_max_threads.restype = C.c_int
+        _lib.orc_state.argtypes = [P, P, P, P, P, C.c_int64, C.c_double, P]
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+class _Args:
+    """Keeps the contiguous arrays alive for the duration of a call."""
+
+    def __init__(self, scene, pose, intr, sigma, z_near, r_min):
+        # float32 inputs are promoted exactly; float64 inputs (finite differences) pass as is
+        self.pos = np.ascontiguousarray(scene.pos, dtype=np.float64)
+        self.col = np.ascontiguousarray(scene.col, dtype=np.float64)
+        self.opa = np.ascontiguousarray(scene.opa, dtype=np.float64)
+        self.faces = None if scene.faces is None else np.ascontiguousarray(scene.faces, dtype=np.int32)
+        self.sc = _Scene(_ptr(self.pos), _ptr(self.col), _ptr(self.opa), _ptr(self.faces),
+                         self.pos.shape[1], scene.n_faces)
+        self.pose = np.ascontiguousarray(np.asarray(pose, dtype=np.float64).reshape(-1))
+        self.cam = _cam(intr)
+        self.par = _Par(sigma, z_near, r_min)
+
+
+def _cam(intr) -> _Cam:
+    w, h, fx, fy, cx, cy = intr.as_tuple() if hasattr(intr, "as_tuple") else intr
+    return _Cam(int(w), int(h), fx, fy, cx, cy)
+
+
+def set_threads(n: int) -> None:
+    lib().orc_set_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().orc_max_threads())
+
+
+def render(scene, pose, intr, sigma=1.0, z_near=0.1, r_min=1e-3,
+           pixels: Optional[np.ndarray] = None) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Colour [3, P], depth [P], final transmittance [P] of the listed pixel indices
+    (y*W + x), or of the whole frame when `pixels` is None (P = H*W)."""
+    a = _Args(scene, pose, intr, sigma, z_near, r_min)
+    pix = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int64)
+    n = a.cam.width * a.cam.height if pix is None else pix.shape[0]
+    col = np.zeros((3, n)); dep = np.zeros(n); tr = np.zeros(n)
+    rc = lib().orc_render(C.byref(a.sc), _ptr(a.pose), C.byref(a.cam), C.byref(a.par), _ptr(pix),
+                          n, _ptr(col), _ptr(dep), _ptr(tr))
+    if rc:
+        raise ValueError(f"orc_render failed ({rc})")
+    return col, dep, tr
+
+
+def backward(scene, pose, intr, g_color: np.ndarray, g_depth: np.ndarray,
+             g_trans: Optional[np.ndarray] = None, sigma=1.0, z_near=0.1, r_min=1e-3,
+             pixels: Optional[np.ndarray] = None):
+    """Gradients (pos [3,N], col [3,N], opa [N], pose [6]) from the listed pixels' upstream
+    gradients g_color [3,P], g_depth [P], g_trans [P]."""
+    a = _Args(scene, pose, intr, sigma, z_near, r_min)
+    pix = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int64)
+    n = a.cam.width * a.cam.height if pix is None else pix.shape[0]
+    gc = np.ascontiguousarray(np.asarray(g_color, np.float64).reshape(3, n))
+    gd = np.ascontiguousarray(np.asarray(g_depth, np.float64).reshape(n))
+    gt = None if g_trans is None else np.ascontiguousarray(np.asarray(g_trans, np.float64).reshape(n))
+    N = a.pos.shape[1]
+    gpos = np.zeros((3, N)); gcol = np.zeros((3, N)); gopa = np.zeros(N); gpose = np.zeros(6)
+    rc = lib().orc_backward(C.byref(a.sc), _ptr(a.pose), C.byref(a.cam), C.byref(a.par), _ptr(pix), n,
+                            _ptr(gc), _ptr(gd), _ptr(gt), _ptr(gpos), _ptr(gcol), _ptr(gopa), _ptr(gpose))
+    if rc:
+        raise ValueError(f"orc_backward failed ({rc})")
+    return gpos, gcol, gopa, gpose
+
+
+def project(scene, pose, intr, sigma=1.0, z_near=0.1, r_min=1e-3):
+    """Per-face q [6, M], (r, o_F, z_F, zkey) [4, M], pixel rect [4, M], tile count [M]."""
+    a = _Args(scene, pose, intr, sigma, z_near, r_min)
+    M = scene.n_faces
+    q = np.zeros((6, M)); f = np.zeros((4, M)); rect = np.zeros((4, M), np.int32)
+    tiles = np.zeros(M, np.int64)
+    rc = lib().orc_project(C.byref(a.sc), _ptr(a.pose), C.byref(a.cam), C.byref(a.par), _ptr(q),
+                           _ptr(f), _ptr(rect), _ptr(tiles))
+    if rc:
+        raise ValueError(f"orc_project failed ({rc})")
+    return q, f, rect, tiles
+
+
+def bin_pairs(scene, poses: Sequence[np.ndarray], intrs: Sequence, sigma=1.0, z_near=0.1, r_min=1e-3):
+    """Reference tile lists: (tile[K], zbits[K], face[K], ranges[T_total, 2])."""
+    a = _Args(scene, poses[0], intrs[0], sigma, z_near, r_min)
+    V = len(poses)
+    ps = np.ascontiguousarray(np.stack([np.asarray(p, np.float64).reshape(12) for p in poses]))
+    cams = (_Cam * V)(*[_cam(i) for i in intrs])
+    t_total = sum(((c.width + 15) // 16) * ((c.height + 15) // 16) for c in cams)
+    K = C.c_int64(0)
+    rc = lib().orc_bin(C.byref(a.sc), _ptr(ps), cams, V, C.byref(a.par), 0, C.byref(K),
+                       None, None, None, None)
+    if rc not in (0, -2):
+        raise ValueError(f"orc_bin failed ({rc})")
+    k = K.value
+    tile = np.zeros(max(k, 1), np.int64); zb = np.zeros(max(k, 1), np.uint32)
+    face = np.zeros(max(k, 1), np.int64); ranges = np.zeros((max(t_total, 1), 2), np.int64)
+    rc = lib().orc_bin(C.byref(a.sc), _ptr(ps), cams, V, C.byref(a.par), k, C.byref(K),
+                       _ptr(tile), _ptr(zb), _ptr(face), _ptr(ranges))
+    if rc:
+        raise ValueError(f"orc_bin failed ({rc})")
+    return tile[:k], zb[:k], face[:k], ranges[:t_total]
+
+
+def l1_seeds(color, depth, target_color, target_depth, norm_pix: int, w_c=0.8, w_d=0.05):
+    """L1 loss (means, weights w_c, w_d; depth masked where the target is <= 0) and its
+    per-pixel derivatives.  Arrays are [3, P] / [P]."""
+    color = np.ascontiguousarray(color, np.float64); depth = np.ascontiguousarray(depth, np.float64)
+    tc = np.ascontiguousarray(target_color, np.float32).reshape(color.shape)
+    td = np.ascontiguousarray(target_depth, np.float32).reshape(depth.shape)
+    n = depth.shape[0]
+    gc = np.zeros_like(color); gd = np.zeros_like(depth)
+    L = lib().orc_l1_seeds(_ptr(color), _ptr(depth), _ptr(tc), _ptr(td), n, int(norm_pix), w_c, w_d,
+                           _ptr(gc), _ptr(gd))
+    return float(L), gc, gd
+
+
+def state(scene, pose, intr, sigma=1.0, z_near=0.1, r_min=1e-3, pixels=None, rho_eps=1e-3):
+    """Per-pixel hash of the piecewise-constant rendering state (covering set and order,
+    maximising edge, clamp and steep-edge flags); equal hashes at both ends of a finite
+    difference mean no discontinuity was crossed."""
+    a = _Args(scene, pose, intr, sigma, z_near, r_min)
+    pix = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int64)
+    n = a.cam.width * a.cam.height if pix is None else pix.shape[0]
+    out = np.zeros(n, np.uint64)
+    rc = lib().orc_state(C.byref(a.sc), _ptr(a.pose), C.byref(a.cam), C.byref(a.par), _ptr(pix), n,
+                         rho_eps, _ptr(out))
+    if rc:
+        raise ValueError(f"orc_state failed ({rc})")
+    return out

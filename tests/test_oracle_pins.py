@@ -1,0 +1,306 @@
+"""Pins of the FP64 oracle to facts fixed by the paper and by mathematics (no GPU).
+
+Each test states the passage or property it follows.  A plausible mistake in the oracle --
+a dropped term, a wrong sign or index, a transposed operand -- should fail at least one.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2605_31419_amd import scenes as S
+from tests.helpers import IDENTITY, left_perturb, plain_scene, tiny_scene, unit_cam
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _tri_scene(verts2d, z=1.0, col=None, opa=None):
+    v = np.array([[x, y, z] for x, y in verts2d], dtype=np.float64)[None]
+    return plain_scene(v, col=col, opa=opa)
+
+
+def _pix(cam, pts):
+    return np.array([v * cam.width + u for u, v in pts], dtype=np.int64)
+
+
+# ---------------------------------------------------------------------------- window (eq. 3)
+
+@pytest.mark.parametrize("sigma", [0.5, 1.0, 2.0])
+def test_window_closed_forms_right_triangle(sigma):
+    """Eq. (3) on the 6-8-10 right triangle: I = 1 at the incentre, known interior values,
+    0 on edges, at vertices and outside (golden fixture, hand-derived)."""
+    g = json.load(open(os.path.join(GOLD, "window_right_triangle.json")))
+    cam = unit_cam(g["camera"]["width"], g["camera"]["height"])
+    onehot = np.eye(3)[None]                                # vertex i has colour e_i
+    sc = _tri_scene(g["vertices"], col=onehot, opa=np.ones((1, 3)))
+    pts = [tuple(p["p"]) for p in g["points"]]
+    C, D, T = O.render(sc, IDENTITY, cam, sigma=sigma, pixels=_pix(cam, pts))
+    for k, p in enumerate(g["points"]):
+        I = p["rho"] ** sigma if p["rho"] > 0 else 0.0
+        assert abs((1.0 - T[k]) - I) < 1e-12, (p, T[k])           # opacity 1: T = 1 - I
+        assert abs(D[k] - 1.0 * I) < 1e-12                       # z = 1 everywhere
+        if "bary" in p:
+            np.testing.assert_allclose(C[:, k], np.array(p["bary"]) * I, atol=1e-12)
+        else:
+            assert np.all(C[:, k] == 0)
+
+
+def test_window_incentre_and_inradius_equilateral():
+    """An equilateral triangle of side a has incentre = centroid and r = a / (2 sqrt 3)."""
+    a = 12.0
+    c = (16.0, 15.0)
+    h = a * math.sqrt(3) / 2
+    verts = [(c[0] - a / 2, c[1] + h / 3), (c[0] + a / 2, c[1] + h / 3), (c[0], c[1] - 2 * h / 3)]
+    cam = unit_cam()
+    sc = _tri_scene(verts, opa=np.ones((1, 3)))
+    q, f, rect, tiles = O.project(sc, IDENTITY, cam)
+    assert abs(f[0, 0] - a / (2 * math.sqrt(3))) < 1e-5      # float32 vertex rounding
+    _, _, T = O.render(sc, IDENTITY, cam, pixels=_pix(cam, [(16, 15)]))
+    assert T[0] < 1e-5                                       # I(centroid) = 1
+
+
+@pytest.mark.parametrize("sigma", [0.5, 1.0, 2.0])
+def test_window_invariances(sigma):
+    """I depends only on the triangle as a set (vertex order, winding) and is invariant under
+    uniform scaling of the triangle and the sample point about the incentre (eq. 3)."""
+    base = [(20.0, 20.0), (28.0, 20.0), (20.0, 26.0)]
+    cam = unit_cam(64, 64)
+    pts = [(21, 21), (24, 22), (22, 24), (23, 21), (22, 22)]
+    ref = O.render(_tri_scene(base), IDENTITY, cam, sigma=sigma, pixels=_pix(cam, pts))[2]
+    for perm in [(1, 2, 0), (2, 1, 0), (0, 2, 1)]:
+        T = O.render(_tri_scene([base[i] for i in perm]), IDENTITY, cam, sigma=sigma,
+                     pixels=_pix(cam, pts))[2]
+        np.testing.assert_allclose(T, ref, atol=1e-12)
+    s = np.array([22.0, 22.0])
+    scaled = [tuple(s + 2 * (np.array(v) - s)) for v in base]
+    spts = [tuple((s + 2 * (np.array(p) - s)).astype(int)) for p in pts]
+    T2 = O.render(_tri_scene(scaled), IDENTITY, cam, sigma=sigma, pixels=_pix(cam, spts))[2]
+    np.testing.assert_allclose(T2, ref, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------- barycentrics
+
+def test_barycentric_partition_and_linear_precision():
+    """Sec. 3.1: sum(lambda) = 1, lambda >= 0 inside; linear precision sum(lambda_i q_i) = p,
+    checked through colours that encode the vertex coordinates."""
+    verts = [(5.3, 4.1), (27.2, 9.7), (11.8, 28.4)]
+    col = np.array([[v[0] / 32, v[1] / 32, 1.0] for v in verts])[None]
+    cam = unit_cam()
+    sc = _tri_scene(verts, col=col, opa=np.full((1, 3), 0.7))
+    pts = [(u, v) for u in range(32) for v in range(32)]
+    C, D, T = O.render(sc, IDENTITY, cam, pixels=_pix(cam, pts))
+    a = 1.0 - T
+    inside = a > 1e-9
+    assert inside.sum() > 100
+    uv = np.array(pts, np.float64)
+    np.testing.assert_allclose(C[0, inside] / a[inside], uv[inside, 0] / 32, atol=1e-6)
+    np.testing.assert_allclose(C[1, inside] / a[inside], uv[inside, 1] / 32, atol=1e-6)
+    np.testing.assert_allclose(C[2, inside] / a[inside], 1.0, atol=1e-6)
+
+
+# ---------------------------------------------------------------------------- compositing (eq. 4)
+
+def test_partition_of_unity_and_constant_depth():
+    """Eq. (4): with all colours 1, C = sum alpha T = 1 - T_final; with every face at the same
+    depth z, D = z (1 - T_final)."""
+    g = np.random.default_rng(3)
+    cam = unit_cam(48, 40)
+    m = 30
+    xy = g.uniform(0, 48, size=(m, 3, 2))
+    verts = np.concatenate([xy, np.full((m, 3, 1), 2.0)], axis=2)
+    verts[..., :2] *= 2.0                                   # z = 2 with focal 1: q = xy
+    sc = plain_scene(verts, col=np.ones((m, 3, 3)), opa=g.uniform(0.3, 1.0, size=(m, 3)))
+    C, D, T = O.render(sc, IDENTITY, cam)
+    for ch in range(3):
+        np.testing.assert_allclose(C[ch], 1 - T, atol=1e-12)
+    np.testing.assert_allclose(D, 2.0 * (1 - T), atol=1e-12)
+    assert (T < 0.999).mean() > 0.3
+
+
+def test_two_faces_closed_form_and_order():
+    """Two overlapping faces: C = c1 a1 + c2 a2 (1 - a1) with face 1 the nearer one, whatever
+    the array order; T = (1 - a1)(1 - a2)."""
+    cam = unit_cam()
+    big = [(2.0, 2.0), (30.0, 2.0), (2.0, 30.0)]
+    near = np.array([[x, y, 1.0] for x, y in big])
+    far = np.array([[2 * x, 2 * y, 2.0] for x, y in big])   # same image footprint at z = 2
+    p = (8, 9)
+    cam_pix = _pix(cam, [p])
+    one = lambda v, c, o: plain_scene(v[None], col=np.tile(c, (1, 3, 1)), opa=np.full((1, 3), o))
+    _, _, Tn = O.render(one(near, [1, 0, 0], 0.6), IDENTITY, cam, pixels=cam_pix)
+    _, _, Tf = O.render(one(far, [0, 1, 0], 0.5), IDENTITY, cam, pixels=cam_pix)
+    a1, a2 = 1 - Tn[0], 1 - Tf[0]
+    for order in [(near, far), (far, near)]:
+        vs = np.stack(order)
+        cols = np.array([[[1, 0, 0]] * 3, [[0, 1, 0]] * 3]) if order[0] is near else np.array([[[0, 1, 0]] * 3, [[1, 0, 0]] * 3])
+        opas = np.array([[0.6] * 3, [0.5] * 3]) if order[0] is near else np.array([[0.5] * 3, [0.6] * 3])
+        C, D, T = O.render(plain_scene(vs, col=cols, opa=opas), IDENTITY, cam, pixels=cam_pix)
+        np.testing.assert_allclose(C[:, 0], [a1, a2 * (1 - a1), 0], atol=1e-12)
+        np.testing.assert_allclose(T[0], (1 - a1) * (1 - a2), atol=1e-12)
+        np.testing.assert_allclose(D[0], 1.0 * a1 + 2.0 * a2 * (1 - a1), atol=1e-12)
+
+
+def test_empty_scene():
+    """No faces: C = D = 0, T = 1, all gradients zero."""
+    sc = S.Scene(np.zeros((3, 0), np.float32), np.zeros((3, 0), np.float32), np.zeros(0, np.float32))
+    cam = unit_cam(16, 16)
+    C, D, T = O.render(sc, IDENTITY, cam)
+    assert np.all(C == 0) and np.all(D == 0) and np.all(T == 1)
+    gp, gc, go, gpose = O.backward(sc, IDENTITY, cam, np.ones((3, 256)), np.ones(256), np.ones(256))
+    assert np.all(gpose == 0)
+
+
+def test_full_occlusion():
+    """An opaque face whose incentre is a pixel centre gives alpha = 1 there: T = 0, C = c(s),
+    D = z_F, and a face behind it contributes nothing and gets no gradient from that pixel."""
+    cam = unit_cam()
+    front = np.array([[20, 20, 1.0], [28, 20, 1.0], [20, 26, 1.0]])
+    back = np.array([[30, 30, 1.5], [45, 30, 1.5], [30, 45, 1.5]])     # covers (22,22) at z 1.5
+    sc = plain_scene(np.stack([front, back]), col=np.array([[[0.2, 0.4, 0.6]] * 3, [[1, 1, 1]] * 3]),
+                     opa=np.ones((2, 3)))
+    pix = _pix(cam, [(22, 22)])
+    C, D, T = O.render(sc, IDENTITY, cam, pixels=pix)
+    assert abs(T[0]) < 1e-12
+    np.testing.assert_allclose(C[:, 0], [0.2, 0.4, 0.6], atol=1e-12)
+    assert abs(D[0] - 1.0) < 1e-12
+    gp, gc, go, gpose = O.backward(sc, IDENTITY, cam, np.ones((3, 1)), np.ones(1), np.ones(1), pixels=pix)
+    # rho at the incentre is 1 up to FP64 rounding, so 'nothing' means below 1e-12
+    assert np.abs(gc[:, 3:]).max() < 1e-12 and np.abs(go[3:]).max() < 1e-12 and np.abs(gp[:, 3:]).max() < 1e-12
+    assert np.any(gc[:, :3] != 0)
+
+
+def test_single_frontal_opaque_face():
+    """One fronto-parallel opaque face at depth z0: C = c(p) I(p), D = z0 I(p), T = 1 - I(p)."""
+    cam = unit_cam()
+    z0 = 1.7
+    xy = [(3.0, 4.0), (29.0, 7.0), (12.0, 30.0)]
+    verts = np.array([[x * z0, y * z0, z0] for x, y in xy])[None]
+    sc = plain_scene(verts, col=np.tile([0.3, 0.5, 0.9], (1, 3, 1)), opa=np.ones((1, 3)))
+    C, D, T = O.render(sc, IDENTITY, cam)
+    I = 1 - T
+    assert I.max() > 0.9 and (I > 0).sum() > 50
+    np.testing.assert_allclose(D, z0 * I, atol=1e-12)
+    np.testing.assert_allclose(C, np.array([[0.3], [0.5], [0.9]]) * I[None], atol=1e-12)
+
+
+def test_face_order_in_arrays_is_irrelevant():
+    """Eq. (4) sorts by depth: permuting the faces in the input arrays changes nothing
+    (no exact depth ties in this scene)."""
+    sc, intr = tiny_scene(11, n_faces=12)
+    ref = O.render(sc, IDENTITY, intr)
+    perm = np.random.default_rng(0).permutation(sc.n_faces)
+    out = O.render(sc.subset(perm), IDENTITY, intr)
+    for a, b in zip(ref, out):
+        np.testing.assert_allclose(a, b, atol=1e-13)
+
+
+# ---------------------------------------------------------------------------- projection (eq. 1)
+
+def test_projection_pinhole():
+    """Eq. (1) with the pinhole reading: a point on the optical axis maps to (cx, cy); a point
+    at (x, y, z) maps to (fx x/z + cx, fy y/z + cy); the pose is applied first."""
+    intr = S.Intrinsics(64, 48, 50.0, 52.0, 31.5, 23.5)
+    verts = np.array([[[0, 0, 2.0], [0.4, 0, 2.0], [0, 0.3, 4.0]]])
+    sc = plain_scene(verts)
+    q, f, rect, tiles = O.project(sc, IDENTITY, intr)
+    np.testing.assert_allclose(q[:, 0], [31.5, 23.5, 50 * 0.2 + 31.5, 23.5, 31.5, 52 * 0.075 + 23.5], atol=1e-5)
+    # camera translated by +1 m along x: world point x=1 is on the axis
+    pose = np.concatenate([np.eye(3).reshape(9), [-1.0, 0, 0]]).astype(np.float32)
+    verts2 = verts.copy()
+    verts2[..., 0] += 1.0
+    q2 = O.project(plain_scene(verts2), pose, intr)[0]
+    np.testing.assert_allclose(q2, q, atol=1e-5)
+    assert abs(f[2, 0] - (2 + 2 + 4) / 3) < 1e-6                        # z_F = mean depth
+    assert abs(f[1, 0] - 1.0) < 1e-12                                    # o_F = mean opacity
+
+
+def test_near_plane_and_degenerate_cull():
+    """Faces with a vertex in front of z_near, or with inradius below r_min, are culled."""
+    cam = unit_cam()
+    behind = np.array([[[1, 1, 0.05], [20, 1, 1.0], [1, 20, 1.0]]])
+    sliver = np.array([[[5, 5, 1.0], [25, 5, 1.0], [15, 5.00001, 1.0]]])
+    for v in (behind, sliver):
+        _, _, T = O.render(plain_scene(v), IDENTITY, cam)
+        assert np.all(T == 1)
+
+
+# ---------------------------------------------------------------------------- binning
+
+def test_binner_against_brute_force():
+    """Reference tile lists equal a direct enumeration over tiles of each face's pixel
+    rectangle, sorted by (tile, float32 depth key, face); every pixel a face covers lies in
+    its rectangle (the binning is conservative)."""
+    sc, intr = tiny_scene(5, n_faces=40, w=50, h=37, f=40.0, size=(0.05, 1.5))
+    tile, zb, face, ranges = O.bin_pairs(sc, [IDENTITY], [intr])
+    q, f, rect, tiles = O.project(sc, IDENTITY, intr)
+    tx = (intr.width + 15) // 16
+    ref = []
+    for m in range(sc.n_faces):
+        if tiles[m] == 0:
+            continue
+        u0, u1, v0, v1 = rect[:, m]
+        key = np.float32(f[3, m]).view(np.uint32)
+        for ty in range(v0 // 16, v1 // 16 + 1):
+            for txx in range(u0 // 16, u1 // 16 + 1):
+                # the tile must really intersect the rectangle
+                assert txx * 16 <= u1 and txx * 16 + 15 >= u0 and ty * 16 <= v1 and ty * 16 + 15 >= v0
+                ref.append((ty * tx + txx, int(key), m))
+    ref.sort()
+    got = list(zip(tile.tolist(), zb.tolist(), face.tolist()))
+    assert got == ref
+    for t in range(ranges.shape[0]):
+        s, e = ranges[t]
+        assert np.all(tile[s:e] == t)
+    # conservativeness: render each face alone
+    for m in range(sc.n_faces):
+        _, _, T = O.render(sc.subset([m]), IDENTITY, intr)
+        cov = np.nonzero(T < 1)[0]
+        if cov.size == 0:
+            continue
+        assert tiles[m] > 0
+        u, v = cov % intr.width, cov // intr.width
+        u0, u1, v0, v1 = rect[:, m]
+        assert u.min() >= u0 and u.max() <= u1 and v.min() >= v0 and v.max() <= v1
+
+
+def test_binner_multi_view_numbering():
+    """Views are stacked view-major: face ids v*M + m and tile ids offset by earlier views."""
+    sc, intr = tiny_scene(6, n_faces=25)
+    intr2 = S.Intrinsics(40, 20, 30.0, 30.0, 19.5, 9.5)
+    t1, z1, f1, r1 = O.bin_pairs(sc, [IDENTITY], [intr])
+    t2, z2, f2, r2 = O.bin_pairs(sc, [IDENTITY], [intr2])
+    t, z, f, r = O.bin_pairs(sc, [IDENTITY, IDENTITY], [intr, intr2])
+    nt1 = r1.shape[0]
+    assert np.array_equal(t, np.concatenate([t1, t2 + nt1]))
+    assert np.array_equal(f, np.concatenate([f1, f2 + sc.n_faces]))
+    assert np.array_equal(z, np.concatenate([z1, z2]))
+
+
+# ---------------------------------------------------------------------------- loss seeds (eqs. 8-10)
+
+def test_l1_seeds_by_finite_differences():
+    """The per-pixel derivatives of the L1 loss equal central differences of the loss value
+    (away from the kinks); depth is masked where the target is <= 0."""
+    g = np.random.default_rng(1)
+    n = 50
+    C = g.uniform(0, 1, (3, n)); D = g.uniform(0.5, 4, n)
+    tc = g.uniform(0, 1, (3, n)).astype(np.float32); td = g.uniform(0.5, 4, n).astype(np.float32)
+    td[::7] = 0
+    L, gc, gd = O.l1_seeds(C, D, tc, td, norm_pix=200)
+    h = 1e-7
+    for k in range(0, n, 5):
+        for ch in range(3):
+            Cp = C.copy(); Cp[ch, k] += h
+            Cm = C.copy(); Cm[ch, k] -= h
+            fd = (O.l1_seeds(Cp, D, tc, td, 200)[0] - O.l1_seeds(Cm, D, tc, td, 200)[0]) / (2 * h)
+            assert abs(fd - gc[ch, k]) < 1e-6
+        Dp = D.copy(); Dp[k] += h
+        Dm = D.copy(); Dm[k] -= h
+        fd = (O.l1_seeds(C, Dp, tc, td, 200)[0] - O.l1_seeds(C, Dm, tc, td, 200)[0]) / (2 * h)
+        assert abs(fd - gd[k]) < 1e-6
+    assert np.all(gd[::7] == 0)
+    expect = 0.8 * np.abs(C - tc).sum() / 600 + 0.05 * (np.abs(D - td) * (td > 0)).sum() / 200
+    assert abs(L - expect) < 1e-12
