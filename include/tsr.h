@@ -1,0 +1,185 @@
+/*
+ * tsr.h -- C ABI of the MI355X (gfx950) differentiable triangle-soup rasterizer.
+ *
+ * The operation is the differentiable rasterisation of "Triangle Splatting SLAM":
+ *   - vertices with world position, RGB colour and opacity; faces are vertex triplets
+ *     (Sec. 3.1); the default layout is a soup, face m = vertices 3m, 3m+1, 3m+2;
+ *   - projection v_I = pi(T_CW v_W) with a pinhole pi (eq. 1);
+ *   - window I(p) = min(1, max(0, phi(p)/phi(s)))^sigma of the edge-distance field phi
+ *     (eqs. 2-3), face opacity o_F = mean of the vertex opacities and barycentric vertex
+ *     colour (Sec. 3.1);
+ *   - front-to-back alpha compositing in depth order (eq. 4), of colour and of depth
+ *     D = sum z_F alpha T (the rendered depth of eqs. 9 and 13);
+ *   - the analytic backward pass to vertex positions, colours, opacities and the se(3)
+ *     left perturbation of T_CW (eqs. 5-7).
+ *
+ * Conventions shared by every entry point
+ *   - Pointers are DEVICE pointers unless marked (host).  Structs passed by pointer are host
+ *     memory.  Float arrays are float32, integer arrays int32 / uint32 / uint64 as stated.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Every call only enqueues work
+ *     on `stream` and returns without synchronising, except tsr_check / tsr_count.
+ *   - The caller owns every buffer, the workspace included; the library never allocates or
+ *     frees device memory.  The workspace carries the binning between tsr_bin_and_sort,
+ *     tsr_render_forward and tsr_render_backward; reusing it for another scene, pose set or
+ *     view set invalidates that state.
+ *   - A pose is T_CW (world -> camera): 12 floats, R row-major then t.  Camera frame x right,
+ *     y down, z forward; pixel (u, v) samples the image point (u, v) (integer pixel centres).
+ *   - Several views may be rendered in one call (1 <= n_views <= TSR_MAX_VIEWS), each with
+ *     its own pose and intrinsics.  Per-view images are packed view after view: view v
+ *     starts at pixel offset P_v = sum_{v'<v} H_v' W_v'; colour is [3][H_v][W_v] at float
+ *     offset 3 P_v, depth and transmittance [H_v][W_v] at offset P_v.
+ *   - Outputs are overwritten.  Gradient outputs are sums over all views of the call.
+ *     A NULL gradient output pointer skips that output.
+ *   - Errors: functions never abort.  They return TSR_OK (0) or a negative code and set a
+ *     thread-local message readable with tsr_last_error():
+ *       TSR_EINVAL     null required pointer, n_views out of range, width/height outside
+ *                      (0, 16384], sigma <= 0, t_min outside [0, 1), negative sizes,
+ *                      n_views * n_faces >= 2^31;
+ *       TSR_EWORKSPACE workspace smaller than tsr_workspace_size() for zero pairs;
+ *       TSR_ECAPACITY  more (tile, face) pairs than the workspace holds.  Detected on the
+ *                      device: tsr_bin_and_sort then leaves every tile list empty (all later
+ *                      kernels do no work), and the condition is reported by tsr_check;
+ *       TSR_EHIP       a HIP runtime call or launch failed (message has the HIP error).
+ *   - NaN or infinite inputs give unspecified image values but no fault.  Faces with a
+ *     vertex closer than z_near, or with inradius below r_min pixels, are culled.
+ *     Opacities are used as given (the caller applies any activation).
+ *   - Thread safety: calls are safe from several host threads when each uses its own
+ *     workspace and stream.
+ */
+#ifndef TSR_H
+#define TSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define TSR_API __attribute__((visibility("default")))
+#else
+#define TSR_API
+#endif
+
+#define TSR_OK 0
+#define TSR_EINVAL (-1)
+#define TSR_EWORKSPACE (-2)
+#define TSR_ECAPACITY (-3)
+#define TSR_EHIP (-4)
+
+#define TSR_MAX_VIEWS 32
+#define TSR_TILE 16
+
+/* Pinhole intrinsics of one view (host). */
+typedef struct {
+    int32_t width, height;   /* image size in pixels, each in (0, 16384] */
+    float fx, fy, cx, cy;    /* u = fx x/z + cx, v = fy y/z + cy */
+} tsr_intrinsics;
+
+/* Rendering parameters (host). */
+typedef struct {
+    float sigma;    /* window exponent of eq. 3, > 0 (1: linear, 0.5: square root) */
+    float t_min;    /* a pixel stops after the face that brings its transmittance below
+                       t_min (0 disables the early stop) */
+    float z_near;   /* near-plane cull distance in metres */
+    float r_min;    /* cull faces whose projected inradius is below r_min pixels */
+    float w_color;  /* L1 colour weight of the fused training loss (eq. 8, 1 - lambda) */
+    float w_depth;  /* L1 depth weight of the fused training loss (eq. 10, lambda_dep) */
+} tsr_params;
+
+/* Scene (host struct of device pointers). */
+typedef struct {
+    const float *pos;        /* [3][N] world positions, SoA */
+    const float *col;        /* [3][N] RGB, SoA */
+    const float *opa;        /* [N] opacities */
+    const int32_t *faces;    /* [M][3] vertex indices, or NULL for a soup (N = 3M) */
+    int64_t n_vertices;      /* N */
+    int64_t n_faces;         /* M */
+} tsr_scene;
+
+/* Read-only view of the binning held in a workspace (device pointers). */
+typedef struct {
+    const uint64_t *pairs;     /* [capacity] sorted pairs; pair i = (float32 bits of z_F << 32) | face,
+                                  face = v * M + m; valid entries are those inside a tile range */
+    const uint32_t *ranges;    /* [n_tiles][2] start, end of each tile's run in `pairs`;
+                                  tile ids are view-major: tile_offset(v) + ty * tiles_x + tx */
+    const int64_t *n_pairs;    /* device scalar: total pairs K emitted (also when it overflowed) */
+    const uint32_t *overflow;  /* device scalar: nonzero when K exceeded the capacity */
+    const uint32_t *tile_counts; /* [V * M] number of tiles each (view, face) overlaps, 0 = culled */
+    const float *records;      /* [V * M][24] per-face setup records (visible faces only) */
+    int64_t capacity;          /* pairs the workspace holds */
+    int64_t n_tiles;           /* total tiles over all views */
+    int64_t n_pixels;          /* total pixels over all views */
+} tsr_binning;
+
+/* Bytes of workspace needed for this scene size, view set and a capacity of `pair_capacity`
+ * (tile, face) pairs.  Workspace size depends only on M, the intrinsics and the capacity. */
+TSR_API int tsr_workspace_size(const tsr_scene *scene, const tsr_intrinsics *intr /* (host)[n_views] */,
+                       int n_views, int64_t pair_capacity, size_t *bytes /* (host) out */);
+
+/* Projection, per-face setup, tile binning and per-tile depth sort (eqs. 1-3 and the depth
+ * order of eq. 4): every visible face is listed in each 16x16 tile its pixel bounding box
+ * overlaps; each tile's list is sorted by (float32 z_F, face).  z_F is the mean camera-space
+ * depth of the face's vertices.  Poses: [n_views][12]. */
+TSR_API int tsr_bin_and_sort(const tsr_scene *scene, const float *poses, const tsr_intrinsics *intr,
+                     int n_views, const tsr_params *params, void *ws, size_t ws_bytes,
+                     void *stream);
+
+/* Exact pair count K for the given views without sorting; synchronises `stream`.
+ * Uses the fixed part of `ws` only (any capacity, even 0, suffices). */
+TSR_API int tsr_count(const tsr_scene *scene, const float *poses, const tsr_intrinsics *intr,
+              int n_views, const tsr_params *params, void *ws, size_t ws_bytes, void *stream,
+              int64_t *n_pairs /* (host) out */);
+
+/* Device pointers into the binning state of `ws` (no device access, no synchronisation). */
+TSR_API int tsr_binning_view(const tsr_scene *scene, const tsr_intrinsics *intr, int n_views,
+                     const void *ws, size_t ws_bytes, tsr_binning *out /* (host) */);
+
+/* Forward render (eq. 4) of the binned views: colour [3][H][W], depth, final transmittance
+ * per view (packed as above).  Also stores in `ws` each pixel's last blended face and its
+ * transmittance before that face, which the backward pass starts from.  Requires a
+ * preceding tsr_bin_and_sort on the same workspace and inputs.  trans may be NULL. */
+TSR_API int tsr_render_forward(const tsr_scene *scene, const float *poses, const tsr_intrinsics *intr,
+                       int n_views, const tsr_params *params, void *ws, size_t ws_bytes,
+                       float *color, float *depth, float *trans, void *stream);
+
+/* Backward of tsr_render_forward (Sec. 3.3): given dL/dcolour, dL/ddepth and optionally
+ * dL/dtrans (NULL = 0), packed like the outputs, writes dL/dpos [3][N], dL/dcol [3][N],
+ * dL/dopa [N] and the pose gradient [n_views][6] = (dL/drho, dL/dtheta) of the left
+ * perturbation Exp(tau) T_CW (eqs. 6-7).  Walks each tile back to front, recovering the
+ * transmittance by division from the stored per-pixel state. */
+TSR_API int tsr_render_backward(const tsr_scene *scene, const float *poses, const tsr_intrinsics *intr,
+                        int n_views, const tsr_params *params, void *ws, size_t ws_bytes,
+                        const float *grad_color, const float *grad_depth, const float *grad_trans,
+                        float *grad_pos, float *grad_col, float *grad_opa, float *grad_pose,
+                        void *stream);
+
+/* Fused training step on binned views: forward render, the L1 loss of eqs. 8-10 without the
+ * D-SSIM term, L = w_color mean|C - Cbar| + w_depth mean([Dbar > 0] |D - Dbar|) per view,
+ * and its backward, with each tile's forward state kept on chip between the two passes.
+ * Targets are packed like the outputs.  color/depth/trans/loss may be NULL (loss: [n_views]).
+ * Gradients as in tsr_render_backward. */
+TSR_API int tsr_render_train_l1(const tsr_scene *scene, const float *poses, const tsr_intrinsics *intr,
+                        int n_views, const tsr_params *params, void *ws, size_t ws_bytes,
+                        const float *target_color, const float *target_depth,
+                        float *color, float *depth, float *trans, float *loss,
+                        float *grad_pos, float *grad_col, float *grad_opa, float *grad_pose,
+                        void *stream);
+
+/* Gradient-descent pose step on the device: T_CW <- Exp(-(lr_trans g_rho, lr_rot g_theta)) T_CW
+ * for each view (the tracking update of Sec. 3.4); poses [n_views][12] updated in place. */
+TSR_API int tsr_pose_step(float *poses, const float *grad_pose, int n_views, float lr_trans, float lr_rot,
+                  void *stream);
+
+/* Synchronise `stream` and report device-side conditions of `ws`: TSR_ECAPACITY when the
+ * last binning overflowed.  Writes K to *n_pairs when non-NULL. */
+TSR_API int tsr_check(const void *ws, void *stream, int64_t *n_pairs /* (host) out, nullable */);
+
+/* Message of the last failure on this thread ("" if none). */
+TSR_API const char *tsr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TSR_H */

@@ -533,6 +533,7 @@ int orc_bin(const orc_scene *s, const double *poses, const orc_cam *cams, int n_
     free(F);
     *K = total;
     if (cap < total) { free(pairs); return ORC_ECAP; }
+    if (!tile_out || !zbits_out || !face_out || !ranges) { free(pairs); return ORC_OK; }  /* size query */
     qsort(pairs, (size_t)total, sizeof(pair_t), pair_cmp);
     for (int64_t t = 0; t < T_total; t++) { ranges[2 * t] = 0; ranges[2 * t + 1] = 0; }
     for (int64_t i = 0; i < total; i++) {

@@ -1,0 +1,84 @@
+"""ctypes binding of ``libtsr.so`` (the C ABI declared in ``include/tsr.h``).
+
+Argument marshalling only: every step of the rasterizer runs in the HIP kernels behind the
+C ABI.  The library must have been built (``paper_2605_31419_amd.build``); loading fails
+loudly otherwise -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtsr.so")
+
+TSR_OK = 0
+TSR_EINVAL = -1
+TSR_EWORKSPACE = -2
+TSR_ECAPACITY = -3
+TSR_EHIP = -4
+TSR_MAX_VIEWS = 32
+TSR_TILE = 16
+
+EXPORTED = ["tsr_workspace_size", "tsr_bin_and_sort", "tsr_count", "tsr_binning_view", "tsr_render_forward",
+            "tsr_render_backward", "tsr_render_train_l1", "tsr_pose_step", "tsr_check", "tsr_last_error"]
+
+
+class TsrIntrinsics(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_float), ("fy", C.c_float),
+                ("cx", C.c_float), ("cy", C.c_float)]
+
+
+class TsrParams(C.Structure):
+    _fields_ = [("sigma", C.c_float), ("t_min", C.c_float), ("z_near", C.c_float), ("r_min", C.c_float),
+                ("w_color", C.c_float), ("w_depth", C.c_float)]
+
+
+class TsrScene(C.Structure):
+    _fields_ = [("pos", C.c_void_p), ("col", C.c_void_p), ("opa", C.c_void_p), ("faces", C.c_void_p),
+                ("n_vertices", C.c_int64), ("n_faces", C.c_int64)]
+
+
+class TsrBinning(C.Structure):
+    _fields_ = [("pairs", C.c_void_p), ("ranges", C.c_void_p), ("n_pairs", C.c_void_p), ("overflow", C.c_void_p),
+                ("tile_counts", C.c_void_p), ("records", C.c_void_p), ("capacity", C.c_int64),
+                ("n_tiles", C.c_int64), ("n_pixels", C.c_int64)]
+
+
+class TsrError(RuntimeError):
+    def __init__(self, code: int, where: str, msg: str):
+        super().__init__(f"{where} failed ({code}): {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Load libtsr.so; raises when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+    lib = C.CDLL(LIB_PATH)
+    P, I64, I = C.c_void_p, C.c_int64, C.c_int
+    lib.tsr_workspace_size.argtypes = [P, P, I, I64, P]
+    lib.tsr_bin_and_sort.argtypes = [P, P, P, I, P, P, C.c_size_t, P]
+    lib.tsr_count.argtypes = [P, P, P, I, P, P, C.c_size_t, P, P]
+    lib.tsr_binning_view.argtypes = [P, P, I, P, C.c_size_t, P]
+    lib.tsr_render_forward.argtypes = [P, P, P, I, P, P, C.c_size_t, P, P, P, P]
+    lib.tsr_render_backward.argtypes = [P, P, P, I, P, P, C.c_size_t, P, P, P, P, P, P, P, P]
+    lib.tsr_render_train_l1.argtypes = [P, P, P, I, P, P, C.c_size_t, P, P, P, P, P, P, P, P, P, P, P]
+    lib.tsr_pose_step.argtypes = [P, P, I, C.c_float, C.c_float, P]
+    lib.tsr_check.argtypes = [P, P, P]
+    lib.tsr_last_error.restype = C.c_char_p
+    for fn in EXPORTED:
+        getattr(lib, fn).restype = C.c_char_p if fn == "tsr_last_error" else C.c_int
+    _lib = lib
+    return lib
+
+
+def check(rc: int, where: str) -> None:
+    if rc != TSR_OK:
+        raise TsrError(rc, where, load().tsr_last_error().decode())

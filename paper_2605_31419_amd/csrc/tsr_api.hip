@@ -1,0 +1,289 @@
+// C ABI of the rasterizer: argument validation, workspace layout, launch sequences and
+// error reporting.  Every entry point only enqueues work on the caller's stream except
+// tsr_check and tsr_count, which synchronise it.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+#include "tsr_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(TSR_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+using tsr::ViewTable;
+using tsr::WsLayout;
+
+int check_scene(const tsr_scene* sc) {
+  if (!sc) return fail(TSR_EINVAL, "scene is NULL");
+  if (sc->n_faces < 0 || sc->n_vertices < 0) return fail(TSR_EINVAL, "negative scene size");
+  if (sc->n_faces > 0 && (!sc->pos || !sc->col || !sc->opa))
+    return fail(TSR_EINVAL, "scene pos/col/opa pointer is NULL");
+  if (!sc->faces && sc->n_vertices < 3 * sc->n_faces)
+    return fail(TSR_EINVAL, "soup needs n_vertices >= 3 * n_faces (%lld < %lld)", (long long)sc->n_vertices,
+                (long long)(3 * sc->n_faces));
+  return TSR_OK;
+}
+
+int build_views(const tsr_scene* sc, const tsr_intrinsics* intr, int n_views, ViewTable* vt) {
+  if (!intr) return fail(TSR_EINVAL, "intrinsics pointer is NULL");
+  if (n_views < 1 || n_views > TSR_MAX_VIEWS) return fail(TSR_EINVAL, "n_views = %d outside [1, %d]", n_views, TSR_MAX_VIEWS);
+  memset(vt, 0, sizeof *vt);
+  int64_t tiles = 0, pix = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const tsr_intrinsics& c = intr[v];
+    if (c.width <= 0 || c.height <= 0 || c.width > 16384 || c.height > 16384)
+      return fail(TSR_EINVAL, "view %d: image size %dx%d outside (0, 16384]", v, c.width, c.height);
+    tsr::ViewDesc& d = vt->v[v];
+    d.width = c.width;
+    d.height = c.height;
+    d.tiles_x = (c.width + TSR_TILE - 1) / TSR_TILE;
+    d.tiles_y = (c.height + TSR_TILE - 1) / TSR_TILE;
+    d.tile_off = (int32_t)tiles;
+    d.pix_off = pix;
+    d.fx = c.fx;
+    d.fy = c.fy;
+    d.cx = c.cx;
+    d.cy = c.cy;
+    tiles += (int64_t)d.tiles_x * d.tiles_y;
+    pix += (int64_t)c.width * c.height;
+  }
+  if (tiles >= (1ll << 31)) return fail(TSR_EINVAL, "too many tiles");
+  vt->n_views = n_views;
+  vt->n_tiles = (int32_t)tiles;
+  vt->n_faces = sc->n_faces;
+  if ((int64_t)n_views * sc->n_faces >= (1ll << 31))
+    return fail(TSR_EINVAL, "n_views * n_faces = %lld must be below 2^31", (long long)n_views * sc->n_faces);
+  return TSR_OK;
+}
+
+int64_t total_pixels(const ViewTable& vt) {
+  const tsr::ViewDesc& d = vt.v[vt.n_views - 1];
+  return d.pix_off + (int64_t)d.width * d.height;
+}
+
+WsLayout layout(const ViewTable& vt, int64_t cap) {
+  WsLayout L;
+  const int64_t nf = (int64_t)vt.n_views * vt.n_faces;
+  const int64_t P = total_pixels(vt);
+  size_t o = 0;
+  L.hdr_k = 0;
+  L.hdr_overflow = 8;
+  L.hdr_queue = 12;
+  o = 256;
+  L.pose_acc = o; o = align_up(o + sizeof(double) * 6 * vt.n_views);
+  L.loss_acc = o; o = align_up(o + sizeof(double) * vt.n_views);
+  L.counts = o; o = align_up(o + sizeof(uint32_t) * nf);
+  L.records = o; o = align_up(o + sizeof(float) * tsr::kRecDwords * nf);
+  L.grad_acc = o; o = align_up(o + sizeof(float) * tsr::kGradDwords * nf);
+  L.tile_cnt = o; o = align_up(o + sizeof(uint32_t) * vt.n_tiles);
+  L.ranges = o; o = align_up(o + sizeof(uint32_t) * 2 * vt.n_tiles);
+  L.n_last = o; o = align_up(o + sizeof(int32_t) * P);
+  L.t_last = o; o = align_up(o + sizeof(float) * P);
+  L.fixed_end = o;
+  L.pairs = o; o = align_up(o + sizeof(uint64_t) * cap);
+  L.temp = o; o = align_up(o + sizeof(uint64_t) * cap);
+  L.total = o;
+  L.capacity = cap;
+  return L;
+}
+
+// Capacity implied by a workspace of ws_bytes, or an error when it cannot hold the fixed part.
+int layout_for(const ViewTable& vt, size_t ws_bytes, WsLayout* L) {
+  WsLayout z = layout(vt, 0);
+  if (ws_bytes < z.total) return fail(TSR_EWORKSPACE, "workspace of %zu bytes is below the %zu-byte minimum", ws_bytes, z.total);
+  int64_t cap = (int64_t)((ws_bytes - z.total) / 16);
+  if (cap > (int64_t)0x7fffffff) cap = 0x7fffffff;
+  while (cap > 0 && layout(vt, cap).total > ws_bytes) --cap;
+  *L = layout(vt, cap);
+  return TSR_OK;
+}
+
+int check_params(const tsr_params* p) {
+  if (!p) return fail(TSR_EINVAL, "params is NULL");
+  if (!(p->sigma > 0.f)) return fail(TSR_EINVAL, "sigma must be > 0");
+  if (!(p->t_min >= 0.f && p->t_min < 1.f)) return fail(TSR_EINVAL, "t_min must be in [0, 1)");
+  if (!(p->r_min >= 0.f) || !(p->z_near == p->z_near)) return fail(TSR_EINVAL, "bad r_min / z_near");
+  return TSR_OK;
+}
+
+tsr::tsr_scene_dev dev_scene(const tsr_scene* sc) {
+  tsr::tsr_scene_dev d;
+  d.pos = sc->pos;
+  d.col = sc->col;
+  d.opa = sc->opa;
+  d.faces = sc->faces;
+  d.n_vertices = sc->n_vertices;
+  d.n_faces = sc->n_faces;
+  return d;
+}
+
+// Common argument checks of the per-call entry points.
+int prepare(const tsr_scene* sc, const float* poses, const tsr_intrinsics* intr, int n_views, const tsr_params* p,
+            void* ws, size_t ws_bytes, ViewTable* vt, WsLayout* L) {
+  int rc;
+  if ((rc = check_scene(sc))) return rc;
+  if ((rc = check_params(p))) return rc;
+  if (!poses) return fail(TSR_EINVAL, "poses is NULL");
+  if (!ws) return fail(TSR_EINVAL, "workspace is NULL");
+  if ((rc = build_views(sc, intr, n_views, vt))) return rc;
+  return layout_for(*vt, ws_bytes, L);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tsr_last_error(void) { return g_err.c_str(); }
+
+int tsr_workspace_size(const tsr_scene* scene, const tsr_intrinsics* intr, int n_views, int64_t pair_capacity,
+                       size_t* bytes) {
+  int rc;
+  if ((rc = check_scene(scene))) return rc;
+  if (!bytes) return fail(TSR_EINVAL, "bytes is NULL");
+  if (pair_capacity < 0 || pair_capacity > 0x7fffffff) return fail(TSR_EINVAL, "pair_capacity outside [0, 2^31)");
+  ViewTable vt;
+  if ((rc = build_views(scene, intr, n_views, &vt))) return rc;
+  *bytes = layout(vt, pair_capacity).total;
+  return TSR_OK;
+}
+
+int tsr_bin_and_sort(const tsr_scene* scene, const float* poses, const tsr_intrinsics* intr, int n_views,
+                     const tsr_params* params, void* ws, size_t ws_bytes, void* stream) {
+  ViewTable vt;
+  WsLayout L;
+  int rc = prepare(scene, poses, intr, n_views, params, ws, ws_bytes, &vt, &L);
+  if (rc) return rc;
+  hipError_t e = tsr::launch_bin(dev_scene(scene), poses, vt, *params, L, static_cast<char*>(ws), true,
+                                 static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_bin_and_sort launch");
+}
+
+int tsr_count(const tsr_scene* scene, const float* poses, const tsr_intrinsics* intr, int n_views,
+              const tsr_params* params, void* ws, size_t ws_bytes, void* stream, int64_t* n_pairs) {
+  ViewTable vt;
+  WsLayout L;
+  int rc = prepare(scene, poses, intr, n_views, params, ws, ws_bytes, &vt, &L);
+  if (rc) return rc;
+  if (!n_pairs) return fail(TSR_EINVAL, "n_pairs is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = tsr::launch_bin(dev_scene(scene), poses, vt, *params, L, static_cast<char*>(ws), false, st);
+  if (e != hipSuccess) return hip_fail(e, "tsr_count launch");
+  if ((e = hipMemcpyAsync(n_pairs, static_cast<char*>(ws) + L.hdr_k, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess)
+    return hip_fail(e, "tsr_count copy");
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "tsr_count sync");
+  return TSR_OK;
+}
+
+int tsr_binning_view(const tsr_scene* scene, const tsr_intrinsics* intr, int n_views, const void* ws,
+                     size_t ws_bytes, tsr_binning* out) {
+  int rc;
+  if ((rc = check_scene(scene))) return rc;
+  if (!ws || !out) return fail(TSR_EINVAL, "workspace or out is NULL");
+  ViewTable vt;
+  WsLayout L;
+  if ((rc = build_views(scene, intr, n_views, &vt))) return rc;
+  if ((rc = layout_for(vt, ws_bytes, &L))) return rc;
+  const char* b = static_cast<const char*>(ws);
+  out->pairs = reinterpret_cast<const uint64_t*>(b + L.pairs);
+  out->ranges = reinterpret_cast<const uint32_t*>(b + L.ranges);
+  out->n_pairs = reinterpret_cast<const int64_t*>(b + L.hdr_k);
+  out->overflow = reinterpret_cast<const uint32_t*>(b + L.hdr_overflow);
+  out->tile_counts = reinterpret_cast<const uint32_t*>(b + L.counts);
+  out->records = reinterpret_cast<const float*>(b + L.records);
+  out->capacity = L.capacity;
+  out->n_tiles = vt.n_tiles;
+  out->n_pixels = total_pixels(vt);
+  return TSR_OK;
+}
+
+int tsr_render_forward(const tsr_scene* scene, const float* poses, const tsr_intrinsics* intr, int n_views,
+                       const tsr_params* params, void* ws, size_t ws_bytes, float* color, float* depth, float* trans,
+                       void* stream) {
+  ViewTable vt;
+  WsLayout L;
+  int rc = prepare(scene, poses, intr, n_views, params, ws, ws_bytes, &vt, &L);
+  if (rc) return rc;
+  if (!color || !depth) return fail(TSR_EINVAL, "color or depth output is NULL");
+  hipError_t e = tsr::launch_forward(vt, *params, L, static_cast<char*>(ws), color, depth, trans,
+                                     static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_render_forward launch");
+}
+
+int tsr_render_backward(const tsr_scene* scene, const float* poses, const tsr_intrinsics* intr, int n_views,
+                        const tsr_params* params, void* ws, size_t ws_bytes, const float* grad_color,
+                        const float* grad_depth, const float* grad_trans, float* grad_pos, float* grad_col,
+                        float* grad_opa, float* grad_pose, void* stream) {
+  ViewTable vt;
+  WsLayout L;
+  int rc = prepare(scene, poses, intr, n_views, params, ws, ws_bytes, &vt, &L);
+  if (rc) return rc;
+  if (!grad_color || !grad_depth) return fail(TSR_EINVAL, "grad_color or grad_depth is NULL");
+  tsr::TrainSchedule sched{0, 0, 0};
+  hipError_t e = tsr::launch_backward(dev_scene(scene), poses, vt, *params, L, static_cast<char*>(ws), grad_color,
+                                      grad_depth, grad_trans, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                      grad_pos, grad_col, grad_opa, grad_pose, false, sched,
+                                      static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_render_backward launch");
+}
+
+int tsr_render_train_l1(const tsr_scene* scene, const float* poses, const tsr_intrinsics* intr, int n_views,
+                        const tsr_params* params, void* ws, size_t ws_bytes, const float* target_color,
+                        const float* target_depth, float* color, float* depth, float* trans, float* loss,
+                        float* grad_pos, float* grad_col, float* grad_opa, float* grad_pose, void* stream) {
+  ViewTable vt;
+  WsLayout L;
+  int rc = prepare(scene, poses, intr, n_views, params, ws, ws_bytes, &vt, &L);
+  if (rc) return rc;
+  if (!target_color || !target_depth) return fail(TSR_EINVAL, "target_color or target_depth is NULL");
+  tsr::TrainSchedule sched{0, 0, 0};
+  hipError_t e = tsr::launch_backward(dev_scene(scene), poses, vt, *params, L, static_cast<char*>(ws), nullptr,
+                                      nullptr, nullptr, target_color, target_depth, color, depth, trans, loss,
+                                      grad_pos, grad_col, grad_opa, grad_pose, true, sched,
+                                      static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_render_train_l1 launch");
+}
+
+int tsr_pose_step(float* poses, const float* grad_pose, int n_views, float lr_trans, float lr_rot, void* stream) {
+  if (!poses || !grad_pose) return fail(TSR_EINVAL, "poses or grad_pose is NULL");
+  if (n_views < 1 || n_views > TSR_MAX_VIEWS) return fail(TSR_EINVAL, "n_views = %d outside [1, %d]", n_views, TSR_MAX_VIEWS);
+  hipError_t e = tsr::launch_pose_step(poses, grad_pose, n_views, lr_trans, lr_rot, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_pose_step launch");
+}
+
+int tsr_check(const void* ws, void* stream, int64_t* n_pairs) {
+  if (!ws) return fail(TSR_EINVAL, "workspace is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  struct {
+    int64_t k;
+    uint32_t overflow;
+    uint32_t pad;
+  } h;
+  hipError_t e = hipMemcpyAsync(&h, ws, sizeof h, hipMemcpyDeviceToHost, st);
+  if (e != hipSuccess) return hip_fail(e, "tsr_check copy");
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "tsr_check sync");
+  if (n_pairs) *n_pairs = h.k;
+  if (h.overflow) return fail(TSR_ECAPACITY, "binning produced %lld pairs, above the workspace capacity", (long long)h.k);
+  return TSR_OK;
+}
+
+}  // extern "C"

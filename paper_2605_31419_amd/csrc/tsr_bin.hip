@@ -1,0 +1,407 @@
+// Binning half of the hot path (gfx950): projection and per-face setup, tile counting,
+// exclusive scan of tile counts, wave-cooperative key emission, per-tile depth sort.
+//
+// Projection (eq. 1), edge functions (eq. 2), inradius / incentre normalisation of the
+// window (eq. 3), face opacity as the vertex mean and barycentric colour (Sec. 3.1) are
+// evaluated once per (view, face) in FP64 and stored as an FP32 face-local record, so that
+// the per-pixel work in the blend kernels is FP32 on small numbers.
+#include "tsr_device.h"
+#include "tsr_internal.h"
+
+namespace tsr {
+
+// ---------------------------------------------------------------------------- face setup
+
+struct FaceSetup {
+  double vc[3][3];     // camera-space vertices
+  double q[3][2];      // projected vertices
+  double n[3][2];      // outward unit edge normals
+  double len[3];       // edge lengths, edge k = q_k -> q_{k+1}
+  double perim, area2, r, so;
+  double zf;
+  int u0, u1, v0, v1;  // pixel rectangle (inclusive), valid when visible
+};
+
+__device__ __forceinline__ void load_pose(const float* __restrict__ poses, int v, double R[9], double t[3]) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) R[i] = (double)poses[12 * v + i];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) t[i] = (double)poses[12 * v + 9 + i];
+}
+
+__device__ __forceinline__ void face_vertices(const tsr_scene_dev& sc, int64_t m, int64_t vid[3]) {
+  if (sc.faces) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) vid[k] = (int64_t)sc.faces[3 * m + k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) vid[k] = 3 * m + k;
+  }
+}
+
+// Returns true when the face survives culling and overlaps the image.
+__device__ bool setup_face(const tsr_scene_dev& sc, const int64_t vid[3], const double R[9], const double t[3],
+                           const ViewDesc& vd, float z_near, float r_min, FaceSetup& f) {
+  const int64_t N = sc.n_vertices;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    double w0 = (double)sc.pos[vid[k]], w1 = (double)sc.pos[N + vid[k]], w2 = (double)sc.pos[2 * N + vid[k]];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) f.vc[k][a] = R[3 * a] * w0 + R[3 * a + 1] * w1 + R[3 * a + 2] * w2 + t[a];
+  }
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) ok = ok && (f.vc[k][2] >= (double)z_near);
+  if (!ok) return false;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    f.q[k][0] = (double)vd.fx * f.vc[k][0] / f.vc[k][2] + (double)vd.cx;
+    f.q[k][1] = (double)vd.fy * f.vc[k][1] / f.vc[k][2] + (double)vd.cy;
+  }
+  double a2 = (f.q[1][0] - f.q[0][0]) * (f.q[2][1] - f.q[0][1]) - (f.q[1][1] - f.q[0][1]) * (f.q[2][0] - f.q[0][0]);
+  f.so = a2 >= 0.0 ? 1.0 : -1.0;
+  f.area2 = fabs(a2);
+  f.perim = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int k1 = (k + 1) % 3;
+    double ex = f.q[k1][0] - f.q[k][0], ey = f.q[k1][1] - f.q[k][1];
+    f.len[k] = sqrt(ex * ex + ey * ey);
+    f.perim += f.len[k];
+  }
+  f.r = f.area2 / f.perim;
+  if (!(f.r >= (double)r_min)) return false;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int k1 = (k + 1) % 3;
+    double ex = f.q[k1][0] - f.q[k][0], ey = f.q[k1][1] - f.q[k][1];
+    f.n[k][0] = f.so * ey / f.len[k];
+    f.n[k][1] = -f.so * ex / f.len[k];
+  }
+  f.zf = (f.vc[0][2] + f.vc[1][2] + f.vc[2][2]) / 3.0;
+  double umin = fmin(f.q[0][0], fmin(f.q[1][0], f.q[2][0]));
+  double umax = fmax(f.q[0][0], fmax(f.q[1][0], f.q[2][0]));
+  double vmin = fmin(f.q[0][1], fmin(f.q[1][1], f.q[2][1]));
+  double vmax = fmax(f.q[0][1], fmax(f.q[1][1], f.q[2][1]));
+  // pixel range [ceil(max(min,-1)), floor(min(max, W))] clipped to the image
+  double lu = ceil(fmax(umin, -1.0)), hu = floor(fmin(umax, (double)vd.width));
+  double lv = ceil(fmax(vmin, -1.0)), hv = floor(fmin(vmax, (double)vd.height));
+  f.u0 = (int)fmax(lu, 0.0);
+  f.u1 = (int)fmin(hu, (double)(vd.width - 1));
+  f.v0 = (int)fmax(lv, 0.0);
+  f.v1 = (int)fmin(hv, (double)(vd.height - 1));
+  return f.u0 <= f.u1 && f.v0 <= f.v1;
+}
+
+// ---------------------------------------------------------------------------- wave expansion
+// Spreads per-lane work lists (lane l owns cnt_l items) evenly over the 64 lanes: a wave
+// prefix scan of the counts, then each lane finds the owner of its item by binary search
+// over the inclusive prefix (held in lanes, read with ds_bpermute).  All lanes must be
+// active.  fn(owner_lane, item_index_within_owner) runs once per item.
+template <class F>
+__device__ __forceinline__ void wave_expand(int cnt, F&& fn) {
+  const int lane = threadIdx.x & 63;
+  int incl = cnt;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  const int total = __shfl(incl, 63, 64);
+  for (int base = 0; base < total; base += 64) {
+    const int j = base + lane;
+    int lo = 0, hi = 63;
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {               // smallest lane with incl > j
+      int mid = (lo + hi) >> 1;
+      int im = __shfl(incl, mid, 64);
+      if (im > j) hi = mid; else lo = mid + 1;
+    }
+    const int owner = lo;
+    const int excl_owner = __shfl(incl, owner, 64) - __shfl(cnt, owner, 64);
+    fn(j < total, owner, j - excl_owner);
+  }
+}
+
+// ---------------------------------------------------------------------------- kernels
+
+// One thread per (view, face); faces are numbered g = v * M + m.
+__global__ __launch_bounds__(256) void k_project(tsr_scene_dev sc, const float* __restrict__ poses, ViewTable vt,
+                                                 float z_near, float r_min, uint32_t* __restrict__ counts,
+                                                 float* __restrict__ records, uint32_t* __restrict__ tile_cnt) {
+  const int64_t M = vt.n_faces;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = g < (int64_t)vt.n_views * M;
+  int ntiles = 0, tx0 = 0, ty0 = 0, tw = 1, tile_base = 0, tiles_x = 1;
+  if (live) {
+    const int v = (int)(g / M);
+    const int64_t m = g - (int64_t)v * M;
+    const ViewDesc vd = vt.v[v];
+    double R[9], t[3];
+    load_pose(poses, v, R, t);
+    int64_t vid[3];
+    face_vertices(sc, m, vid);
+    FaceSetup f;
+    if (setup_face(sc, vid, R, t, vd, z_near, r_min, f)) {
+      tx0 = f.u0 >> 4;
+      ty0 = f.v0 >> 4;
+      tw = (f.u1 >> 4) - tx0 + 1;
+      ntiles = tw * ((f.v1 >> 4) - ty0 + 1);
+      tile_base = vd.tile_off;
+      tiles_x = vd.tiles_x;
+      // ---- record
+      float rec[kRecDwords];
+      const double inv_r = 1.0 / f.r;
+      double a[3], b[3], c[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        a[k] = -f.n[k][0] * inv_r;
+        b[k] = -f.n[k][1] * inv_r;
+        c[k] = -(f.n[k][0] * ((double)f.u0 - f.q[k][0]) + f.n[k][1] * ((double)f.v0 - f.q[k][1])) * inv_r;
+        rec[kRecEdge + 3 * k] = (float)a[k];
+        rec[kRecEdge + 3 * k + 1] = (float)b[k];
+        rec[kRecEdge + 3 * k + 2] = (float)c[k];
+      }
+      const int64_t N = sc.n_vertices;
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        // lambda_opp(k) = E_k len_k / perimeter; opp(k) = (k + 2) % 3 is the vertex facing edge k
+        double P = 0, Q = 0, Rr = 0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          double beta = f.len[k] * (double)sc.col[ch * N + vid[(k + 2) % 3]] / f.perim;
+          P += beta * a[k];
+          Q += beta * b[k];
+          Rr += beta * c[k];
+        }
+        rec[kRecCol + 3 * ch] = (float)P;
+        rec[kRecCol + 3 * ch + 1] = (float)Q;
+        rec[kRecCol + 3 * ch + 2] = (float)Rr;
+      }
+      rec[kRecOpa] = (float)(((double)sc.opa[vid[0]] + (double)sc.opa[vid[1]] + (double)sc.opa[vid[2]]) / 3.0);
+      rec[kRecZ] = (float)f.zf;
+      rec[kRecU0] = __int_as_float(f.u0);
+      rec[kRecV0] = __int_as_float(f.v0);
+      rec[kRecU1] = __int_as_float(f.u1);
+      rec[kRecV1] = __int_as_float(f.v1);
+      float4* dst = reinterpret_cast<float4*>(records + g * kRecDwords);
+#pragma unroll
+      for (int i = 0; i < kRecDwords / 4; ++i)
+        dst[i] = make_float4(rec[4 * i], rec[4 * i + 1], rec[4 * i + 2], rec[4 * i + 3]);
+    }
+    counts[g] = (uint32_t)ntiles;
+  }
+  // ---- per-tile counts: small faces loop on their own lane, large ones are spread
+  const int maxc = wave_max_int(ntiles);
+  if (maxc == 0) return;
+  if (maxc <= 4) {
+    for (int i = 0; i < ntiles; ++i)
+      atomicAdd(&tile_cnt[tile_base + (ty0 + i / tw) * tiles_x + tx0 + i % tw], 1u);
+    return;
+  }
+  wave_expand(ntiles, [&](bool valid, int owner, int i) {
+    const int otx0 = __shfl(tx0, owner, 64), oty0 = __shfl(ty0, owner, 64), otw = __shfl(tw, owner, 64);
+    const int obase = __shfl(tile_base, owner, 64), otx = __shfl(tiles_x, owner, 64);
+    if (valid) atomicAdd(&tile_cnt[obase + (oty0 + i / otw) * otx + otx0 + i % otw], 1u);
+  });
+}
+
+// Single workgroup: exclusive scan of the tile counts into ranges, pair total K, overflow
+// check against the capacity, and reset of the counts (reused as emission cursors).
+__global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* __restrict__ tile_cnt, uint32_t* __restrict__ ranges,
+                                                     int n_tiles, int64_t capacity, int64_t* __restrict__ K_out,
+                                                     uint32_t* __restrict__ overflow) {
+  __shared__ unsigned long long part[1024];
+  const int tid = threadIdx.x;
+  const int chunk = (n_tiles + 1023) / 1024;
+  const int lo = min(n_tiles, tid * chunk), hi = min(n_tiles, lo + chunk);
+  unsigned long long s = 0;
+  for (int i = lo; i < hi; ++i) s += tile_cnt[i];
+  part[tid] = s;
+  __syncthreads();
+  // Hillis-Steele inclusive scan over the 1024 partial sums
+  for (int o = 1; o < 1024; o <<= 1) {
+    unsigned long long y = tid >= o ? part[tid - o] : 0ull;
+    __syncthreads();
+    part[tid] += y;
+    __syncthreads();
+  }
+  const unsigned long long total = part[1023];
+  const bool over = total > (unsigned long long)capacity;
+  unsigned long long run = part[tid] - s;
+  for (int i = lo; i < hi; ++i) {
+    const uint32_t c = tile_cnt[i];
+    ranges[2 * i] = over ? 0u : (uint32_t)run;
+    ranges[2 * i + 1] = over ? 0u : (uint32_t)(run + c);
+    run += c;
+    tile_cnt[i] = 0u;
+  }
+  if (tid == 0) {
+    *K_out = (int64_t)total;
+    *overflow = over ? 1u : 0u;
+  }
+}
+
+// Emission of (float32 z_F bits << 32 | face) into each overlapped tile's bucket.
+__global__ __launch_bounds__(256) void k_emit(ViewTable vt, const uint32_t* __restrict__ counts,
+                                              const float* __restrict__ records, const uint32_t* __restrict__ ranges,
+                                              uint32_t* __restrict__ cursor, const uint32_t* __restrict__ overflow,
+                                              uint64_t* __restrict__ pairs) {
+  if (*overflow) return;
+  const int64_t M = vt.n_faces;
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = g < (int64_t)vt.n_views * M;
+  int ntiles = live ? (int)counts[g] : 0;
+  int tx0 = 0, ty0 = 0, tw = 1, tile_base = 0, tiles_x = 1;
+  uint64_t key = 0;
+  if (ntiles > 0) {
+    const float* rec = records + g * kRecDwords;
+    const int u0 = __float_as_int(rec[kRecU0]), v0 = __float_as_int(rec[kRecV0]);
+    const int u1 = __float_as_int(rec[kRecU1]);
+    tx0 = u0 >> 4;
+    ty0 = v0 >> 4;
+    tw = (u1 >> 4) - tx0 + 1;
+    const ViewDesc& vd = vt.v[(int)(g / M)];
+    tile_base = vd.tile_off;
+    tiles_x = vd.tiles_x;
+    key = ((uint64_t)__float_as_uint(rec[kRecZ]) << 32) | (uint64_t)(uint32_t)g;
+  }
+  const int maxc = wave_max_int(ntiles);
+  if (maxc == 0) return;
+  if (maxc <= 4) {
+    for (int i = 0; i < ntiles; ++i) {
+      const int t = tile_base + (ty0 + i / tw) * tiles_x + tx0 + i % tw;
+      const uint32_t pos = ranges[2 * t] + atomicAdd(&cursor[t], 1u);
+      pairs[pos] = key;
+    }
+    return;
+  }
+  const uint32_t key_hi = (uint32_t)(key >> 32), key_lo = (uint32_t)key;
+  wave_expand(ntiles, [&](bool valid, int owner, int i) {
+    const int otx0 = __shfl(tx0, owner, 64), oty0 = __shfl(ty0, owner, 64), otw = __shfl(tw, owner, 64);
+    const int obase = __shfl(tile_base, owner, 64), otx = __shfl(tiles_x, owner, 64);
+    const uint32_t khi = __shfl(key_hi, owner, 64), klo = __shfl(key_lo, owner, 64);
+    if (valid) {
+      const int t = obase + (oty0 + i / otw) * otx + otx0 + i % otw;
+      const uint32_t pos = ranges[2 * t] + atomicAdd(&cursor[t], 1u);
+      pairs[pos] = ((uint64_t)khi << 32) | klo;
+    }
+  });
+}
+
+// ---------------------------------------------------------------------------- per-tile sort
+constexpr int kSortLds = 4096;     // keys sorted in one LDS pass (32 KiB)
+
+__device__ __forceinline__ void bitonic_lds(uint64_t* s, int n2) {
+  for (int k = 2; k <= n2; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < n2; i += blockDim.x) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t a = s[i], b = s[ixj];
+          const bool up = (i & k) == 0;
+          if ((a > b) == up) {
+            s[i] = b;
+            s[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__device__ __forceinline__ int lower_bound_u64(const uint64_t* a, int n, uint64_t x) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    int mid = (lo + hi) >> 1;
+    if (a[mid] < x) lo = mid + 1; else hi = mid;
+  }
+  return lo;
+}
+
+// One workgroup per tile: sort the tile's bucket ascending by (z bits, face).  Buckets up to
+// kSortLds keys are bitonic-sorted in LDS; longer ones are sorted in LDS-sized chunks and
+// merged pairwise in global memory through `temp` (keys are unique, so a rank by binary
+// search places every key).
+__global__ __launch_bounds__(256) void k_tile_sort(const uint32_t* __restrict__ ranges, int n_tiles,
+                                                   uint64_t* __restrict__ pairs, uint64_t* __restrict__ temp) {
+  __shared__ uint64_t s[kSortLds];
+  const int t = blockIdx.x;
+  if (t >= n_tiles) return;
+  const uint32_t start = ranges[2 * t], end = ranges[2 * t + 1];
+  const int n = (int)(end - start);
+  if (n <= 1) return;
+  uint64_t* base = pairs + start;
+  for (int c0 = 0; c0 < n; c0 += kSortLds) {
+    const int cn = min(kSortLds, n - c0);
+    int n2 = 1;
+    while (n2 < cn) n2 <<= 1;
+    for (int i = threadIdx.x; i < n2; i += blockDim.x) s[i] = i < cn ? base[c0 + i] : ~0ull;
+    __syncthreads();
+    bitonic_lds(s, n2);
+    for (int i = threadIdx.x; i < cn; i += blockDim.x) base[c0 + i] = s[i];
+    __syncthreads();
+  }
+  if (n <= kSortLds) return;
+  uint64_t* src = base;
+  uint64_t* dst = temp + start;
+  for (int width = kSortLds; width < n; width <<= 1) {
+    __threadfence();
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const int run = i / width;
+      const int pair_lo = (run & ~1) * width;
+      const int a_lo = pair_lo, a_n = min(width, n - a_lo);
+      const int b_lo = pair_lo + width, b_n = max(0, min(width, n - b_lo));
+      const uint64_t x = src[i];
+      int outpos;
+      if ((run & 1) == 0) outpos = pair_lo + (i - a_lo) + lower_bound_u64(src + b_lo, b_n, x);
+      else outpos = pair_lo + (i - b_lo) + lower_bound_u64(src + a_lo, a_n, x);
+      dst[outpos] = x;
+    }
+    uint64_t* tmp = src;
+    src = dst;
+    dst = tmp;
+  }
+  __threadfence();
+  __syncthreads();
+  if (src != base)
+    for (int i = threadIdx.x; i < n; i += blockDim.x) base[i] = src[i];
+}
+
+__global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------- launchers
+
+static inline unsigned grid_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_bin(const tsr_scene_dev& sc, const float* poses, const ViewTable& vt, const tsr_params& p,
+                      const WsLayout& L, char* ws, bool sort, hipStream_t st) {
+  uint32_t* counts = reinterpret_cast<uint32_t*>(ws + L.counts);
+  float* records = reinterpret_cast<float*>(ws + L.records);
+  uint32_t* tile_cnt = reinterpret_cast<uint32_t*>(ws + L.tile_cnt);
+  uint32_t* ranges = reinterpret_cast<uint32_t*>(ws + L.ranges);
+  int64_t* K = reinterpret_cast<int64_t*>(ws + L.hdr_k);
+  uint32_t* overflow = reinterpret_cast<uint32_t*>(ws + L.hdr_overflow);
+  uint64_t* pairs = reinterpret_cast<uint64_t*>(ws + L.pairs);
+  uint64_t* temp = reinterpret_cast<uint64_t*>(ws + L.temp);
+  const int64_t nf = (int64_t)vt.n_views * vt.n_faces;
+
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(vt.n_tiles, 256)), dim3(256), 0, st, tile_cnt, (int64_t)vt.n_tiles, 0u);
+  if (nf > 0)
+    hipLaunchKernelGGL(k_project, dim3(grid_for(nf, 256)), dim3(256), 0, st, sc, poses, vt, p.z_near, p.r_min, counts,
+                       records, tile_cnt);
+  hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, tile_cnt, ranges, vt.n_tiles,
+                     sort ? L.capacity : (int64_t)0x7fffffffffffffffll, K, overflow);
+  if (!sort) return hipGetLastError();
+  if (nf > 0)
+    hipLaunchKernelGGL(k_emit, dim3(grid_for(nf, 256)), dim3(256), 0, st, vt, counts, records, ranges, tile_cnt,
+                       overflow, pairs);
+  hipLaunchKernelGGL(k_tile_sort, dim3(vt.n_tiles), dim3(256), 0, st, ranges, vt.n_tiles, pairs, temp);
+  return hipGetLastError();
+}
+
+}  // namespace tsr

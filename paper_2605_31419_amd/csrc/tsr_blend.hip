@@ -1,0 +1,740 @@
+// Blend half of the hot path (gfx950): per-tile front-to-back compositing (eq. 4) of the
+// window-weighted (eq. 3) barycentric colours and depths, its back-to-front backward pass,
+// and the fused forward + L1 seeds + backward training kernel.
+//
+// Work mapping: one 256-lane workgroup per 16x16 tile, one pixel per lane; wave w owns the
+// 8x8 quadrant (w & 1, w >> 1), so a face whose pixel rectangle misses a quadrant is skipped
+// by that wave with one scalar test.  Face records are staged in LDS in batches of kBatch,
+// loaded once per workgroup with coalesced 16-byte loads and read by all lanes as broadcasts.
+#include "tsr_internal.h"
+
+namespace tsr {
+
+constexpr int kBatch = 64;
+
+// XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so give each XCD a
+// contiguous range of tiles (neighbouring tiles share faces, which then hit the same L2).
+__device__ __forceinline__ int tile_of_block(int n_tiles) {
+  const int per = (n_tiles + 7) >> 3;
+  const int idx = blockIdx.x >> 3;
+  const int t = (int)(blockIdx.x & 7) * per + idx;
+  return (idx < per && t < n_tiles) ? t : -1;
+}
+
+// Window value for rho in (0, 1): I = rho^sigma (eq. 3).  Mode 1: sigma = 1, 2: sigma = 0.5,
+// 3: sigma = 2, 0: any sigma.
+template <int SM>
+__device__ __forceinline__ float window_pow(float rho, float sigma) {
+  if constexpr (SM == 1) return rho;
+  else if constexpr (SM == 2) return __builtin_sqrtf(rho);
+  else if constexpr (SM == 3) return rho * rho;
+  else return exp2f(sigma * log2f(rho));
+}
+
+struct PixelEval {
+  float rho, I, alpha, c0, c1, c2;
+  int kstar;       // edge attaining the minimum of E_k (lowest index on ties)
+};
+
+// Evaluates one face at face-local pixel offset (dx, dy).  Identical instructions in the
+// forward and backward walks, so the backward recomputes alpha bit for bit.
+template <int SM>
+__device__ __forceinline__ bool eval_face(const float* __restrict__ r, float dx, float dy, float sigma,
+                                          PixelEval& e) {
+  const float E0 = fmaf(r[kRecEdge + 0], dx, fmaf(r[kRecEdge + 1], dy, r[kRecEdge + 2]));
+  const float E1 = fmaf(r[kRecEdge + 3], dx, fmaf(r[kRecEdge + 4], dy, r[kRecEdge + 5]));
+  const float E2 = fmaf(r[kRecEdge + 6], dx, fmaf(r[kRecEdge + 7], dy, r[kRecEdge + 8]));
+  e.kstar = (E0 <= E1 && E0 <= E2) ? 0 : (E1 <= E2 ? 1 : 2);
+  e.rho = fminf(E0, fminf(E1, E2));
+  if (!(e.rho > 0.f)) return false;
+  e.I = e.rho >= 1.f ? 1.f : window_pow<SM>(e.rho, sigma);
+  e.alpha = r[kRecOpa] * e.I;
+  if (!(e.alpha > 0.f)) return false;
+  e.c0 = fmaf(r[kRecCol + 0], dx, fmaf(r[kRecCol + 1], dy, r[kRecCol + 2]));
+  e.c1 = fmaf(r[kRecCol + 3], dx, fmaf(r[kRecCol + 4], dy, r[kRecCol + 5]));
+  e.c2 = fmaf(r[kRecCol + 6], dx, fmaf(r[kRecCol + 7], dy, r[kRecCol + 8]));
+  return true;
+}
+
+// Geometry of this lane's pixel inside the tile.
+struct TileCtx {
+  int tile, view;
+  ViewDesc vd;
+  int bx, by;            // top-left pixel of this wave's 8x8 quadrant
+  int px, py;
+  bool inside;
+  int64_t pix;           // packed pixel index (valid when inside)
+  uint32_t start, end;   // tile list range
+};
+
+__device__ __forceinline__ void tile_ctx(const ViewTable& vt, const uint32_t* __restrict__ ranges, int tile,
+                                         TileCtx& c) {
+  c.tile = tile;
+  c.view = view_of_tile(vt, tile);
+  c.vd = vt.v[c.view];
+  const int lt = tile - c.vd.tile_off;
+  const int tx = lt % c.vd.tiles_x, ty = lt / c.vd.tiles_x;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  c.bx = tx * kTile + (wave & 1) * 8;
+  c.by = ty * kTile + (wave >> 1) * 8;
+  c.px = c.bx + (lane & 7);
+  c.py = c.by + (lane >> 3);
+  c.inside = c.px < c.vd.width && c.py < c.vd.height;
+  c.pix = c.vd.pix_off + (int64_t)c.py * c.vd.width + c.px;
+  c.start = ranges[2 * tile];
+  c.end = ranges[2 * tile + 1];
+}
+
+// Stages records of pair positions [b0, b0 + n) into LDS (all lanes call).
+__device__ __forceinline__ void stage_batch(const float* __restrict__ records, const uint64_t* __restrict__ pairs,
+                                            uint32_t b0, int n, float4* srec, uint32_t* sface) {
+  for (int i = threadIdx.x; i < n * 6; i += kBlock) {
+    const uint32_t face = (uint32_t)pairs[b0 + i / 6];
+    srec[i] = reinterpret_cast<const float4*>(records)[(size_t)face * 6 + i % 6];
+  }
+  if (threadIdx.x < n) sface[threadIdx.x] = (uint32_t)pairs[b0 + threadIdx.x];
+}
+
+// Wave-uniform test: does the face's pixel rectangle meet this wave's 8x8 quadrant?
+__device__ __forceinline__ bool rect_hits_quadrant(const float* r, int bx, int by) {
+  const int u0 = uniform_int(__float_as_int(r[kRecU0])), v0 = uniform_int(__float_as_int(r[kRecV0]));
+  const int u1 = uniform_int(__float_as_int(r[kRecU1])), v1 = uniform_int(__float_as_int(r[kRecV1]));
+  return !(u1 < bx || u0 > bx + 7 || v1 < by || v0 > by + 7);
+}
+
+struct FwdState {
+  float T, C0, C1, C2, D, Tb;
+  int last;
+};
+
+// Front-to-back walk over the tile list (eq. 4).  A pixel stops after the face that takes
+// its transmittance below t_min.  Records each pixel's last blended face and the
+// transmittance just before it.
+template <int SM>
+__device__ __forceinline__ void forward_walk(const TileCtx& c, const float* __restrict__ records,
+                                             const uint64_t* __restrict__ pairs, float sigma, float t_min,
+                                             float4* srec, uint32_t* sface, FwdState& s) {
+  s.T = 1.f; s.C0 = s.C1 = s.C2 = s.D = 0.f; s.Tb = 1.f; s.last = -1;
+  bool done = !c.inside;
+  for (uint32_t b0 = c.start; b0 < c.end; b0 += kBatch) {
+    if (__syncthreads_count(!done) == 0) break;
+    const int n = (int)min((uint32_t)kBatch, c.end - b0);
+    stage_batch(records, pairs, b0, n, srec, sface);
+    __syncthreads();
+    if (__ballot(!done) == 0) continue;
+    const float dxb = (float)c.px, dyb = (float)c.py;
+    for (int j = 0; j < n; ++j) {
+      const float* r = reinterpret_cast<const float*>(&srec[j * 6]);
+      if (!rect_hits_quadrant(r, c.bx, c.by)) continue;
+      if (!done) {
+        PixelEval e;
+        const float dx = dxb - (float)__float_as_int(r[kRecU0]);
+        const float dy = dyb - (float)__float_as_int(r[kRecV0]);
+        if (eval_face<SM>(r, dx, dy, sigma, e)) {
+          const float w = e.alpha * s.T;
+          s.C0 = fmaf(e.c0, w, s.C0);
+          s.C1 = fmaf(e.c1, w, s.C1);
+          s.C2 = fmaf(e.c2, w, s.C2);
+          s.D = fmaf(r[kRecZ], w, s.D);
+          s.Tb = s.T;
+          s.T = s.T * (1.f - e.alpha);
+          s.last = (int)(b0 + j);
+          // stop once T < t_min; also at T == 0 so the backward never divides by 1 - alpha = 0
+          if (s.T < t_min || s.T == 0.f) done = true;
+        }
+      }
+      if (__ballot(!done) == 0) break;
+    }
+  }
+}
+
+// Per-pixel upstream gradients.
+struct PixGrad {
+  float g0, g1, g2, gd, gt;
+};
+
+// Back-to-front walk (Sec. 3.3).  T before each face is recovered by division from the
+// transmittance before the last blended face, B* hold what lies behind the current face
+// composited from transmittance 1, and per-face sums of the 20 record-parameter gradients
+// are reduced over the wave and added to grad_acc.
+template <int SM>
+__device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __restrict__ records,
+                                              const uint64_t* __restrict__ pairs, float sigma, int last, float Tb,
+                                              const PixGrad& pg, float4* srec, uint32_t* sface, int* sint,
+                                              float* __restrict__ grad_acc) {
+  const int lane = threadIdx.x & 63;
+  // block-wide highest list position any pixel blended
+  if (threadIdx.x == 0) sint[0] = -1;
+  __syncthreads();
+  const int wlast = wave_max_int(last);
+  if (lane == 0) atomicMax(&sint[0], wlast);
+  __syncthreads();
+  const int top = sint[0];
+  float Tcur = Tb;
+  float B0 = 0.f, B1 = 0.f, B2 = 0.f, BD = 0.f, BA = 0.f;
+  const float dxb = (float)c.px, dyb = (float)c.py;
+  for (int b1 = top + 1; b1 > (int)c.start; b1 -= kBatch) {
+    const int b0 = max((int)c.start, b1 - kBatch);
+    const int n = b1 - b0;
+    __syncthreads();
+    stage_batch(records, pairs, (uint32_t)b0, n, srec, sface);
+    __syncthreads();
+    if (b0 > wlast) continue;
+    for (int j = n - 1; j >= 0; --j) {
+      const int idx = b0 + j;
+      if (idx > wlast) continue;
+      const float* r = reinterpret_cast<const float*>(&srec[j * 6]);
+      if (!rect_hits_quadrant(r, c.bx, c.by)) continue;
+      float acc[kGradDwords];
+#pragma unroll
+      for (int k = 0; k < kGradDwords; ++k) acc[k] = 0.f;
+      bool act = false;
+      if (idx <= last) {
+        PixelEval e;
+        const float dx = dxb - (float)__float_as_int(r[kRecU0]);
+        const float dy = dyb - (float)__float_as_int(r[kRecV0]);
+        if (eval_face<SM>(r, dx, dy, sigma, e)) {
+          act = true;
+          const float om = 1.f - e.alpha;
+          const float Tj = (idx == last) ? Tb : Tcur / om;
+          Tcur = Tj;
+          const float zf = r[kRecZ];
+          const float w = e.alpha * Tj;
+          // colour plane gradients: dL/dc_ch(p) = gC_ch alpha T, and c_ch = P dx + Q dy + R
+          const float gc0 = pg.g0 * w, gc1 = pg.g1 * w, gc2 = pg.g2 * w;
+          acc[kGCol + 0] = gc0 * dx; acc[kGCol + 1] = gc0 * dy; acc[kGCol + 2] = gc0;
+          acc[kGCol + 3] = gc1 * dx; acc[kGCol + 4] = gc1 * dy; acc[kGCol + 5] = gc1;
+          acc[kGCol + 6] = gc2 * dx; acc[kGCol + 7] = gc2 * dy; acc[kGCol + 8] = gc2;
+          acc[kGZ] = pg.gd * w;
+          // dL/dalpha = T (gC.(c - B) + gD (z - BD) - gT (1 - BA))
+          const float galpha = Tj * (pg.g0 * (e.c0 - B0) + pg.g1 * (e.c1 - B1) + pg.g2 * (e.c2 - B2) +
+                                     pg.gd * (zf - BD) - pg.gt * (1.f - BA));
+          acc[kGOpa] = galpha * e.I;
+          const float gI = galpha * r[kRecOpa];
+          float grho = 0.f;
+          if (e.rho < 1.f) {
+            if constexpr (SM == 1) grho = gI;
+            else grho = gI * sigma * e.I / e.rho;     // dI/drho = sigma I / rho
+          }
+          const float ge0 = grho * dx, ge1 = grho * dy;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            const bool on = e.kstar == k;
+            acc[kGEdge + 3 * k + 0] = on ? ge0 : 0.f;
+            acc[kGEdge + 3 * k + 1] = on ? ge1 : 0.f;
+            acc[kGEdge + 3 * k + 2] = on ? grho : 0.f;
+          }
+          B0 = fmaf(e.c0, e.alpha, om * B0);
+          B1 = fmaf(e.c1, e.alpha, om * B1);
+          B2 = fmaf(e.c2, e.alpha, om * B2);
+          BD = fmaf(zf, e.alpha, om * BD);
+          BA = fmaf(1.f, e.alpha, om * BA);
+        }
+      }
+      if (__ballot(act) == 0) continue;
+      float sum[kGradDwords];
+#pragma unroll
+      for (int k = 0; k < kGradDwords; ++k) sum[k] = wave_sum(acc[k]);
+      float mine = 0.f;
+#pragma unroll
+      for (int k = 0; k < kGradDwords; ++k) mine = lane == k ? sum[k] : mine;
+      if (lane < kGradDwords) unsafeAtomicAdd(&grad_acc[(size_t)sface[j] * kGradDwords + lane], mine);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------- kernels
+
+template <int SM>
+__global__ __launch_bounds__(kBlock) void k_blend_fwd(ViewTable vt, const float* __restrict__ records,
+                                                      const uint64_t* __restrict__ pairs,
+                                                      const uint32_t* __restrict__ ranges, float sigma, float t_min,
+                                                      float* __restrict__ color, float* __restrict__ depth,
+                                                      float* __restrict__ trans, int* __restrict__ n_last,
+                                                      float* __restrict__ t_last) {
+  __shared__ float4 srec[kBatch * 6];
+  __shared__ uint32_t sface[kBatch];
+  const int tile = tile_of_block(vt.n_tiles);
+  if (tile < 0) return;
+  TileCtx c;
+  tile_ctx(vt, ranges, tile, c);
+  FwdState s;
+  forward_walk<SM>(c, records, pairs, sigma, t_min, srec, sface, s);
+  if (!c.inside) return;
+  const int64_t hw = (int64_t)c.vd.width * c.vd.height;
+  const int64_t off = (int64_t)c.py * c.vd.width + c.px;
+  float* cb = color + 3 * c.vd.pix_off + off;
+  cb[0] = s.C0;
+  cb[hw] = s.C1;
+  cb[2 * hw] = s.C2;
+  depth[c.pix] = s.D;
+  if (trans) trans[c.pix] = s.T;
+  n_last[c.pix] = s.last;
+  t_last[c.pix] = s.Tb;
+}
+
+template <int SM>
+__global__ __launch_bounds__(kBlock) void k_blend_bwd(ViewTable vt, const float* __restrict__ records,
+                                                      const uint64_t* __restrict__ pairs,
+                                                      const uint32_t* __restrict__ ranges, float sigma,
+                                                      const int* __restrict__ n_last, const float* __restrict__ t_last,
+                                                      const float* __restrict__ gcolor, const float* __restrict__ gdepth,
+                                                      const float* __restrict__ gtrans, float* __restrict__ grad_acc) {
+  __shared__ float4 srec[kBatch * 6];
+  __shared__ uint32_t sface[kBatch];
+  __shared__ int sint[4];
+  const int tile = tile_of_block(vt.n_tiles);
+  if (tile < 0) return;
+  TileCtx c;
+  tile_ctx(vt, ranges, tile, c);
+  int last = -1;
+  float Tb = 0.f;
+  PixGrad pg{0.f, 0.f, 0.f, 0.f, 0.f};
+  if (c.inside) {
+    last = n_last[c.pix];
+    Tb = t_last[c.pix];
+    // state from a forward over another binning must not index outside this tile's list
+    if (last < (int)c.start || last >= (int)c.end) last = -1;
+    const int64_t hw = (int64_t)c.vd.width * c.vd.height;
+    const float* gb = gcolor + 3 * c.vd.pix_off + (int64_t)c.py * c.vd.width + c.px;
+    pg.g0 = gb[0];
+    pg.g1 = gb[hw];
+    pg.g2 = gb[2 * hw];
+    pg.gd = gdepth[c.pix];
+    pg.gt = gtrans ? gtrans[c.pix] : 0.f;
+  }
+  backward_walk<SM>(c, records, pairs, sigma, last, Tb, pg, srec, sface, sint, grad_acc);
+}
+
+// Fused training kernel: forward walk, L1 seeds of eqs. 8-10 (D-SSIM omitted), backward
+// walk, without leaving the workgroup.  Also accumulates the per-view loss in FP64.
+template <int SM>
+__global__ __launch_bounds__(kBlock) void k_train_fused(ViewTable vt, const float* __restrict__ records,
+                                                        const uint64_t* __restrict__ pairs,
+                                                        const uint32_t* __restrict__ ranges, float sigma, float t_min,
+                                                        float w_color, float w_depth,
+                                                        const float* __restrict__ tcolor, const float* __restrict__ tdepth,
+                                                        float* __restrict__ color, float* __restrict__ depth,
+                                                        float* __restrict__ trans, double* __restrict__ loss_acc,
+                                                        float* __restrict__ grad_acc,
+                                                        const int* __restrict__ order, int* __restrict__ queue,
+                                                        int persistent) {
+  __shared__ float4 srec[kBatch * 6];
+  __shared__ uint32_t sface[kBatch];
+  __shared__ int sint[4];
+  __shared__ float sloss[4];
+  int item = persistent ? 0 : (int)blockIdx.x;
+  for (;;) {
+    int tile;
+    if (persistent) {
+      __syncthreads();
+      if (threadIdx.x == 0) sint[1] = atomicAdd(queue, 1);
+      __syncthreads();
+      item = sint[1];
+      if (item >= vt.n_tiles) break;
+      tile = order ? order[item] : item;
+    } else {
+      tile = order ? (item < vt.n_tiles ? order[item] : -1) : tile_of_block(vt.n_tiles);
+      if (tile < 0) break;
+    }
+    TileCtx c;
+    tile_ctx(vt, ranges, tile, c);
+    FwdState s;
+    forward_walk<SM>(c, records, pairs, sigma, t_min, srec, sface, s);
+    PixGrad pg{0.f, 0.f, 0.f, 0.f, 0.f};
+    float lpix = 0.f;
+    if (c.inside) {
+      const int64_t hw = (int64_t)c.vd.width * c.vd.height;
+      const int64_t off = (int64_t)c.py * c.vd.width + c.px;
+      const float inv_c = w_color / (3.f * (float)hw), inv_d = w_depth / (float)hw;
+      const float* tc = tcolor + 3 * c.vd.pix_off + off;
+      const float r0 = s.C0 - tc[0], r1 = s.C1 - tc[hw], r2 = s.C2 - tc[2 * hw];
+      const float td = tdepth[c.pix];
+      const float rd = s.D - td;
+      const float md = td > 0.f ? 1.f : 0.f;
+      pg.g0 = inv_c * (float)((r0 > 0.f) - (r0 < 0.f));
+      pg.g1 = inv_c * (float)((r1 > 0.f) - (r1 < 0.f));
+      pg.g2 = inv_c * (float)((r2 > 0.f) - (r2 < 0.f));
+      pg.gd = md * inv_d * (float)((rd > 0.f) - (rd < 0.f));
+      lpix = inv_c * (fabsf(r0) + fabsf(r1) + fabsf(r2)) + md * inv_d * fabsf(rd);
+      if (color) {
+        float* cb = color + 3 * c.vd.pix_off + off;
+        cb[0] = s.C0;
+        cb[hw] = s.C1;
+        cb[2 * hw] = s.C2;
+      }
+      if (depth) depth[c.pix] = s.D;
+      if (trans) trans[c.pix] = s.T;
+    }
+    if (loss_acc) {
+      const float ws = wave_sum(lpix);
+      if ((threadIdx.x & 63) == 0) sloss[threadIdx.x >> 6] = ws;
+      __syncthreads();
+      if (threadIdx.x == 0)
+        unsafeAtomicAdd(&loss_acc[c.view], (double)sloss[0] + (double)sloss[1] + (double)sloss[2] + (double)sloss[3]);
+    }
+    backward_walk<SM>(c, records, pairs, sigma, s.last, s.Tb, pg, srec, sface, sint, grad_acc);
+    if (!persistent) break;
+  }
+}
+
+// ---------------------------------------------------------------------------- face backward
+// Chain rule from the record parameters to the projected vertices (eq. 2-3 setup, in FP64),
+// then through the pinhole projection to camera space, to world space (R^T) and to the
+// se(3) pose (eq. 7: dv_C/dtau = [I, -[v_C]x]); vertex opacities get dL/do_F / 3 and
+// vertex colours the barycentric weights' share.  One thread per face; loops over views.
+
+__device__ __forceinline__ void load_pose_d(const float* __restrict__ poses, int v, double R[9], double t[3]) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) R[i] = (double)poses[12 * v + i];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) t[i] = (double)poses[12 * v + 9 + i];
+}
+
+__global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float* __restrict__ poses, ViewTable vt,
+                                                  const uint32_t* __restrict__ counts, const float* __restrict__ records,
+                                                  const float* __restrict__ grad_acc, float* __restrict__ grad_pos,
+                                                  float* __restrict__ grad_col, float* __restrict__ grad_opa,
+                                                  double* __restrict__ pose_acc, int atomic_vertices) {
+  __shared__ double red[6][4];
+  const int64_t M = vt.n_faces;
+  const int64_t N = sc.n_vertices;
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool live = m < M;
+  int64_t vid[3] = {0, 0, 0};
+  if (live) {
+    if (sc.faces) {
+      for (int k = 0; k < 3; ++k) vid[k] = (int64_t)sc.faces[3 * m + k];
+    } else {
+      for (int k = 0; k < 3; ++k) vid[k] = 3 * m + k;
+    }
+  }
+  double gW[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};   // dL/dv_W per vertex
+  double gcolv[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // dL/dc per vertex, channel
+  double gop = 0.0;
+  bool any = false;
+  for (int v = 0; v < vt.n_views; ++v) {
+    double pose6[6] = {0, 0, 0, 0, 0, 0};
+    const int64_t g = (int64_t)v * M + m;
+    if (live && counts[g] > 0) {
+      any = true;
+      const float* A = grad_acc + g * kGradDwords;
+      const float* rec = records + g * kRecDwords;
+      const ViewDesc vd = vt.v[v];
+      double R[9], t[3];
+      load_pose_d(poses, v, R, t);
+      double vc[3][3], q[3][2];
+      for (int k = 0; k < 3; ++k) {
+        const double w0 = (double)sc.pos[vid[k]], w1 = (double)sc.pos[N + vid[k]], w2 = (double)sc.pos[2 * N + vid[k]];
+        for (int a = 0; a < 3; ++a) vc[k][a] = R[3 * a] * w0 + R[3 * a + 1] * w1 + R[3 * a + 2] * w2 + t[a];
+        q[k][0] = (double)vd.fx * vc[k][0] / vc[k][2] + (double)vd.cx;
+        q[k][1] = (double)vd.fy * vc[k][1] / vc[k][2] + (double)vd.cy;
+      }
+      // ---- forward quantities of the setup
+      const double a2 = (q[1][0] - q[0][0]) * (q[2][1] - q[0][1]) - (q[1][1] - q[0][1]) * (q[2][0] - q[0][0]);
+      const double so = a2 >= 0.0 ? 1.0 : -1.0;
+      const double area = fabs(a2);
+      double e[3][2], len[3], n[3][2], perim = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        const int k1 = (k + 1) % 3;
+        e[k][0] = q[k1][0] - q[k][0];
+        e[k][1] = q[k1][1] - q[k][1];
+        len[k] = sqrt(e[k][0] * e[k][0] + e[k][1] * e[k][1]);
+        perim += len[k];
+      }
+      const double r = area / perim;
+      for (int k = 0; k < 3; ++k) {
+        n[k][0] = so * e[k][1] / len[k];
+        n[k][1] = -so * e[k][0] / len[k];
+      }
+      const double U0 = (double)__float_as_int(rec[kRecU0]), V0 = (double)__float_as_int(rec[kRecV0]);
+      double ca[3], cb[3], cc[3];       // edge coefficients a_k, b_k, c_k
+      for (int k = 0; k < 3; ++k) {
+        ca[k] = -n[k][0] / r;
+        cb[k] = -n[k][1] / r;
+        cc[k] = -(n[k][0] * (U0 - q[k][0]) + n[k][1] * (V0 - q[k][1])) / r;
+      }
+      double colv[3][3];                // vertex colours [vertex][ch]
+      for (int i = 0; i < 3; ++i)
+        for (int ch = 0; ch < 3; ++ch) colv[i][ch] = (double)sc.col[ch * N + vid[i]];
+      // ---- reverse: colour planes P_ch = sum_k beta_k,ch a_k (same for Q with b, R with c),
+      //      beta_k,ch = len_k col[opp(k)][ch] / perim
+      double gA[3], gB[3], gCc[3], glen[3] = {0, 0, 0}, gperim = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        gA[k] = (double)A[kGEdge + 3 * k];
+        gB[k] = (double)A[kGEdge + 3 * k + 1];
+        gCc[k] = (double)A[kGEdge + 3 * k + 2];
+      }
+      for (int k = 0; k < 3; ++k) {
+        const int o = (k + 2) % 3;
+        for (int ch = 0; ch < 3; ++ch) {
+          const double GP = (double)A[kGCol + 3 * ch], GQ = (double)A[kGCol + 3 * ch + 1], GR = (double)A[kGCol + 3 * ch + 2];
+          const double beta = len[k] * colv[o][ch] / perim;
+          gA[k] += beta * GP;
+          gB[k] += beta * GQ;
+          gCc[k] += beta * GR;
+          const double gbeta = GP * ca[k] + GQ * cb[k] + GR * cc[k];
+          gcolv[o][ch] += gbeta * len[k] / perim;
+          glen[k] += gbeta * colv[o][ch] / perim;
+          gperim -= gbeta * beta / perim;
+        }
+      }
+      // ---- reverse: edge coefficients a = -n_x / r, b = -n_y / r, c = -n.(anchor - q_k) / r
+      double gq[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+      double gr = 0.0;
+      double gn[3][2];
+      for (int k = 0; k < 3; ++k) {
+        gn[k][0] = -(gA[k] + gCc[k] * (U0 - q[k][0])) / r;
+        gn[k][1] = -(gB[k] + gCc[k] * (V0 - q[k][1])) / r;
+        gq[k][0] += gCc[k] * n[k][0] / r;
+        gq[k][1] += gCc[k] * n[k][1] / r;
+        gr -= (gA[k] * ca[k] + gB[k] * cb[k] + gCc[k] * cc[k]) / r;
+      }
+      // ---- n_k = so (e_y, -e_x) / |e|
+      double ge[3][2];
+      for (int k = 0; k < 3; ++k) {
+        const double dot = gn[k][0] * n[k][0] + gn[k][1] * n[k][1];
+        const double gmx = (gn[k][0] - dot * n[k][0]) / len[k];
+        const double gmy = (gn[k][1] - dot * n[k][1]) / len[k];
+        ge[k][0] = -so * gmy;
+        ge[k][1] = so * gmx;
+      }
+      // ---- r = area / perim; perim = sum len
+      const double garea = gr / perim;
+      gperim += -gr * r / perim;
+      for (int k = 0; k < 3; ++k) {
+        glen[k] += gperim;
+        ge[k][0] += glen[k] * e[k][0] / len[k];
+        ge[k][1] += glen[k] * e[k][1] / len[k];
+      }
+      // ---- area = so * a2, a2 = (q1 - q0) x (q2 - q0)
+      const double ga2 = so * garea;
+      gq[1][0] += ga2 * (q[2][1] - q[0][1]);
+      gq[1][1] -= ga2 * (q[2][0] - q[0][0]);
+      gq[2][0] -= ga2 * (q[1][1] - q[0][1]);
+      gq[2][1] += ga2 * (q[1][0] - q[0][0]);
+      gq[0][0] -= ga2 * ((q[2][1] - q[0][1]) - (q[1][1] - q[0][1]));
+      gq[0][1] -= ga2 * ((q[1][0] - q[0][0]) - (q[2][0] - q[0][0]));
+      // ---- e_k = q_{k+1} - q_k
+      for (int k = 0; k < 3; ++k) {
+        const int k1 = (k + 1) % 3;
+        gq[k1][0] += ge[k][0];
+        gq[k1][1] += ge[k][1];
+        gq[k][0] -= ge[k][0];
+        gq[k][1] -= ge[k][1];
+      }
+      // ---- projection and depth: q = (fx x / z + cx, fy y / z + cy), z_F = mean z
+      const double gz3 = (double)A[kGZ] / 3.0;
+      for (int k = 0; k < 3; ++k) {
+        const double iz = 1.0 / vc[k][2];
+        double gc[3];
+        gc[0] = gq[k][0] * (double)vd.fx * iz;
+        gc[1] = gq[k][1] * (double)vd.fy * iz;
+        gc[2] = -(gq[k][0] * (double)vd.fx * vc[k][0] + gq[k][1] * (double)vd.fy * vc[k][1]) * iz * iz + gz3;
+        for (int a = 0; a < 3; ++a) gW[k][a] += R[a] * gc[0] + R[3 + a] * gc[1] + R[6 + a] * gc[2];
+        pose6[0] += gc[0];
+        pose6[1] += gc[1];
+        pose6[2] += gc[2];
+        pose6[3] += vc[k][1] * gc[2] - vc[k][2] * gc[1];
+        pose6[4] += vc[k][2] * gc[0] - vc[k][0] * gc[2];
+        pose6[5] += vc[k][0] * gc[1] - vc[k][1] * gc[0];
+      }
+      gop += (double)A[kGOpa] / 3.0;
+    }
+    // ---- per-view pose gradient: block reduction in FP64, one atomic per block and component
+    if (pose_acc) {
+      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+      for (int i = 0; i < 6; ++i) {
+        double x = pose6[i];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        if (lane == 0) red[i][wave] = x;
+      }
+      __syncthreads();
+      if (threadIdx.x < 6) {
+        const double s = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
+        if (s != 0.0) unsafeAtomicAdd(&pose_acc[6 * v + threadIdx.x], s);
+      }
+      __syncthreads();
+    }
+  }
+  if (!live) return;
+  if (atomic_vertices) {
+    if (!any) return;
+    for (int k = 0; k < 3; ++k) {
+      for (int a = 0; a < 3; ++a) {
+        if (grad_pos) unsafeAtomicAdd(&grad_pos[a * N + vid[k]], (float)gW[k][a]);
+        if (grad_col) unsafeAtomicAdd(&grad_col[a * N + vid[k]], (float)gcolv[k][a]);
+      }
+      if (grad_opa) unsafeAtomicAdd(&grad_opa[vid[k]], (float)gop);
+    }
+  } else {
+    for (int k = 0; k < 3; ++k) {
+      for (int a = 0; a < 3; ++a) {
+        if (grad_pos) grad_pos[a * N + vid[k]] = (float)gW[k][a];
+        if (grad_col) grad_col[a * N + vid[k]] = (float)gcolv[k][a];
+      }
+      if (grad_opa) grad_opa[vid[k]] = (float)gop;
+    }
+  }
+}
+
+// Zero the gradient accumulators of faces visible in some view, and the per-view FP64
+// pose and loss accumulators.
+__global__ void k_zero_acc(const uint32_t* __restrict__ counts, int64_t nf, float* __restrict__ grad_acc,
+                           double* __restrict__ pose_acc, double* __restrict__ loss_acc, int n_views) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nf && counts[i] > 0) {
+    float4* p = reinterpret_cast<float4*>(grad_acc + i * kGradDwords);
+#pragma unroll
+    for (int k = 0; k < kGradDwords / 4; ++k) p[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  if (i < 6 * n_views) pose_acc[i] = 0.0;
+  if (i < n_views && loss_acc) loss_acc[i] = 0.0;
+}
+
+__global__ void k_zero_i32(int* __restrict__ p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
+}
+
+__global__ void k_fill_f32(float* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0.f;
+}
+
+__global__ void k_finalize(const double* __restrict__ pose_acc, float* __restrict__ grad_pose,
+                           const double* __restrict__ loss_acc, float* __restrict__ loss, int n_views) {
+  const int i = threadIdx.x;
+  if (grad_pose && i < 6 * n_views) grad_pose[i] = (float)pose_acc[i];
+  if (loss && i < n_views) loss[i] = (float)loss_acc[i];
+}
+
+// ---------------------------------------------------------------------------- pose step
+// T <- Exp(delta) T with delta = -(lr_t g_rho, lr_r g_theta), Exp of se(3) in closed form
+// (Rodrigues for the rotation, the left Jacobian for the translation part).
+__global__ void k_pose_step(float* __restrict__ poses, const float* __restrict__ grad_pose, int n_views, float lr_t,
+                            float lr_r) {
+  const int v = threadIdx.x;
+  if (v >= n_views) return;
+  double rho[3], th[3];
+  for (int i = 0; i < 3; ++i) {
+    rho[i] = -(double)lr_t * (double)grad_pose[6 * v + i];
+    th[i] = -(double)lr_r * (double)grad_pose[6 * v + 3 + i];
+  }
+  const double a2 = th[0] * th[0] + th[1] * th[1] + th[2] * th[2];
+  const double a = sqrt(a2);
+  double A, B, Cc;            // sin(a)/a, (1-cos a)/a^2, (a - sin a)/a^3
+  if (a < 1e-4) {
+    A = 1.0 - a2 / 6.0;
+    B = 0.5 - a2 / 24.0;
+    Cc = 1.0 / 6.0 - a2 / 120.0;
+  } else {
+    A = sin(a) / a;
+    B = (1.0 - cos(a)) / a2;
+    Cc = (a - sin(a)) / (a2 * a);
+  }
+  const double K[9] = {0, -th[2], th[1], th[2], 0, -th[0], -th[1], th[0], 0};
+  double K2[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) K2[3 * i + j] = K[3 * i] * K[j] + K[3 * i + 1] * K[3 + j] + K[3 * i + 2] * K[6 + j];
+  double dR[9], Vm[9];
+  for (int i = 0; i < 9; ++i) {
+    const double I = (i % 4 == 0) ? 1.0 : 0.0;
+    dR[i] = I + A * K[i] + B * K2[i];
+    Vm[i] = I + B * K[i] + Cc * K2[i];
+  }
+  double R[9], t[3];
+  for (int i = 0; i < 9; ++i) R[i] = (double)poses[12 * v + i];
+  for (int i = 0; i < 3; ++i) t[i] = (double)poses[12 * v + 9 + i];
+  double nR[9], nt[3];
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j) nR[3 * i + j] = dR[3 * i] * R[j] + dR[3 * i + 1] * R[3 + j] + dR[3 * i + 2] * R[6 + j];
+    nt[i] = dR[3 * i] * t[0] + dR[3 * i + 1] * t[1] + dR[3 * i + 2] * t[2] + Vm[3 * i] * rho[0] + Vm[3 * i + 1] * rho[1] +
+            Vm[3 * i + 2] * rho[2];
+  }
+  for (int i = 0; i < 9; ++i) poses[12 * v + i] = (float)nR[i];
+  for (int i = 0; i < 3; ++i) poses[12 * v + 9 + i] = (float)nt[i];
+}
+
+// ---------------------------------------------------------------------------- launchers
+
+static inline unsigned grid_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+static int sigma_mode(float s) { return s == 1.f ? 1 : (s == 0.5f ? 2 : (s == 2.f ? 3 : 0)); }
+
+static unsigned tile_grid(int n_tiles) { return 8u * (unsigned)((n_tiles + 7) / 8); }
+
+hipError_t launch_forward(const ViewTable& vt, const tsr_params& p, const WsLayout& L, char* ws, float* color,
+                          float* depth, float* trans, hipStream_t st) {
+  const float* records = reinterpret_cast<const float*>(ws + L.records);
+  const uint64_t* pairs = reinterpret_cast<const uint64_t*>(ws + L.pairs);
+  const uint32_t* ranges = reinterpret_cast<const uint32_t*>(ws + L.ranges);
+  int* n_last = reinterpret_cast<int*>(ws + L.n_last);
+  float* t_last = reinterpret_cast<float*>(ws + L.t_last);
+  const dim3 grid(tile_grid(vt.n_tiles)), block(kBlock);
+  switch (sigma_mode(p.sigma)) {
+    case 1: hipLaunchKernelGGL(k_blend_fwd<1>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last); break;
+    case 2: hipLaunchKernelGGL(k_blend_fwd<2>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last); break;
+    case 3: hipLaunchKernelGGL(k_blend_fwd<3>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last); break;
+    default: hipLaunchKernelGGL(k_blend_fwd<0>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const ViewTable& vt, const tsr_params& p,
+                           const WsLayout& L, char* ws, const float* gcolor, const float* gdepth,
+                           const float* gtrans, const float* tcolor, const float* tdepth, float* color,
+                           float* depth, float* trans, float* loss, float* grad_pos, float* grad_col,
+                           float* grad_opa, float* grad_pose, bool fused_train, const TrainSchedule& sched,
+                           hipStream_t st) {
+  const uint32_t* counts = reinterpret_cast<const uint32_t*>(ws + L.counts);
+  const float* records = reinterpret_cast<const float*>(ws + L.records);
+  const uint64_t* pairs = reinterpret_cast<const uint64_t*>(ws + L.pairs);
+  const uint32_t* ranges = reinterpret_cast<const uint32_t*>(ws + L.ranges);
+  const int* n_last = reinterpret_cast<const int*>(ws + L.n_last);
+  const float* t_last = reinterpret_cast<const float*>(ws + L.t_last);
+  float* grad_acc = reinterpret_cast<float*>(ws + L.grad_acc);
+  double* pose_acc = reinterpret_cast<double*>(ws + L.pose_acc);
+  double* loss_acc = reinterpret_cast<double*>(ws + L.loss_acc);
+  const int64_t nf = (int64_t)vt.n_views * vt.n_faces;
+  const int64_t zn = nf > 6 * vt.n_views ? nf : 6 * vt.n_views;
+  hipLaunchKernelGGL(k_zero_acc, dim3(grid_for(zn, 256)), dim3(256), 0, st, counts, nf, grad_acc, pose_acc, loss_acc,
+                     vt.n_views);
+  const dim3 block(kBlock);
+  const int sm = sigma_mode(p.sigma);
+  if (!fused_train) {
+    const dim3 grid(tile_grid(vt.n_tiles));
+#define TSR_BWD(S) hipLaunchKernelGGL(k_blend_bwd<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, n_last, t_last, gcolor, gdepth, gtrans, grad_acc)
+    switch (sm) { case 1: TSR_BWD(1); break; case 2: TSR_BWD(2); break; case 3: TSR_BWD(3); break; default: TSR_BWD(0); }
+#undef TSR_BWD
+  } else {
+    const int* order = nullptr;
+    int* queue = nullptr;
+    dim3 grid(tile_grid(vt.n_tiles));
+    if (sched.persistent) {
+      queue = reinterpret_cast<int*>(ws + L.hdr_queue);
+      grid = dim3(sched.grid > 0 ? sched.grid : 2048);
+      hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, queue, 1);
+    }
+#define TSR_TRAIN(S) hipLaunchKernelGGL(k_train_fused<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, p.w_color, p.w_depth, tcolor, tdepth, color, depth, trans, loss ? loss_acc : nullptr, grad_acc, order, queue, sched.persistent)
+    switch (sm) { case 1: TSR_TRAIN(1); break; case 2: TSR_TRAIN(2); break; case 3: TSR_TRAIN(3); break; default: TSR_TRAIN(0); }
+#undef TSR_TRAIN
+  }
+  const bool atomic_vertices = sc.faces != nullptr;
+  if (atomic_vertices) {
+    const int64_t N = sc.n_vertices;
+    if (grad_pos) hipLaunchKernelGGL(k_fill_f32, dim3(1024), dim3(256), 0, st, grad_pos, 3 * N);
+    if (grad_col) hipLaunchKernelGGL(k_fill_f32, dim3(1024), dim3(256), 0, st, grad_col, 3 * N);
+    if (grad_opa) hipLaunchKernelGGL(k_fill_f32, dim3(1024), dim3(256), 0, st, grad_opa, N);
+  }
+  if (vt.n_faces > 0)
+    hipLaunchKernelGGL(k_face_bwd, dim3(grid_for(vt.n_faces, 256)), dim3(256), 0, st, sc, poses, vt, counts, records,
+                       grad_acc, grad_pos, grad_col, grad_opa, grad_pose ? pose_acc : nullptr, atomic_vertices ? 1 : 0);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, pose_acc, grad_pose, loss_acc, loss, vt.n_views);
+  return hipGetLastError();
+}
+
+hipError_t launch_pose_step(float* poses, const float* grad_pose, int n_views, float lr_t, float lr_r, hipStream_t st) {
+  hipLaunchKernelGGL(k_pose_step, dim3(1), dim3(64), 0, st, poses, grad_pose, n_views, lr_t, lr_r);
+  return hipGetLastError();
+}
+
+}  // namespace tsr

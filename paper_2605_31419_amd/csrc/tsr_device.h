@@ -1,0 +1,91 @@
+// Internal device-side definitions of the gfx950 rasterizer: per-face record layout, the
+// per-call view table, and wave64 primitives.  Included by the .hip sources only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tsr.h"
+
+namespace tsr {
+
+constexpr int kTile = TSR_TILE;          // 16x16 pixel tiles
+constexpr int kBlock = 256;              // one pixel per lane, 4 waves of 8x8 pixels per tile
+constexpr int kWave = 64;
+
+// Per-(view, face) setup record, 24 dwords (96 B), written by the projection kernel for
+// visible faces only.  Coordinates are face-local: dx = u - u0, dy = v - v0 with (u0, v0)
+// the top-left pixel of the face's pixel rectangle, so per-pixel FP32 math works on small
+// exact integers.
+//   E_k(p) = a_k dx + b_k dy + c_k = -L_k(p) / r  (eq. 2 edge function over phi(s) = -r)
+//   rho(p) = min_k E_k(p) = phi(p) / phi(s)      (eq. 3 before ReLU and exponent)
+//   colour_ch(p) = P_ch dx + Q_ch dy + R_ch        (barycentric interpolation is affine in p)
+enum RecordField : int {
+  kRecEdge = 0,      // [3][3] a_k, b_k, c_k
+  kRecCol = 9,       // [3][3] P_ch, Q_ch, R_ch
+  kRecOpa = 18,      // o_F
+  kRecZ = 19,        // z_F
+  kRecU0 = 20,       // int u0
+  kRecV0 = 21,       // int v0
+  kRecU1 = 22,       // int u1
+  kRecV1 = 23,       // int v1
+  kRecDwords = 24
+};
+
+// Per-(view, face) gradient accumulator, 20 floats, filled by the backward blend:
+// dL/d(a_k, b_k, c_k) for the three edges, dL/d(P, Q, R) per channel, dL/do_F, dL/dz_F.
+enum GradField : int { kGEdge = 0, kGCol = 9, kGOpa = 18, kGZ = 19, kGradDwords = 20 };
+
+struct ViewDesc {
+  int32_t width, height, tiles_x, tiles_y;
+  int32_t tile_off;        // first global tile id of this view
+  int32_t pad;
+  int64_t pix_off;         // first packed pixel of this view
+  float fx, fy, cx, cy;
+};
+
+struct ViewTable {
+  ViewDesc v[TSR_MAX_VIEWS];
+  int32_t n_views;
+  int32_t n_tiles;         // total tiles
+  int64_t n_faces;         // M
+};
+
+__device__ __forceinline__ int view_of_tile(const ViewTable& vt, int tile) {
+  int v = 0;
+  for (int i = 1; i < vt.n_views; ++i)
+    if (tile >= vt.v[i].tile_off) v = i;
+  return v;
+}
+
+// ---------------------------------------------------------------------------- wave64 DPP
+// Row-wise DPP butterflies, then the legacy gfx9 row broadcasts, leave the wave total in
+// lane 63.  Every lane must be active.
+
+#define TSR_DPP(v, ctrl, rmask, bmask)                                                     \
+  __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, rmask, bmask, false))
+
+__device__ __forceinline__ float wave_sum_to_lane63(float v) {
+  v += TSR_DPP(v, 0xB1, 0xF, 0xF);     // quad_perm [1,0,3,2]
+  v += TSR_DPP(v, 0x4E, 0xF, 0xF);     // quad_perm [2,3,0,1]
+  v += TSR_DPP(v, 0x124, 0xF, 0xF);    // row_ror:4
+  v += TSR_DPP(v, 0x128, 0xF, 0xF);    // row_ror:8  -> every lane holds its row's sum
+  v += TSR_DPP(v, 0x142, 0xA, 0xF);    // row_bcast:15 into rows 1 and 3
+  v += TSR_DPP(v, 0x143, 0xC, 0xF);    // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_to_lane63(v)), 63));
+}
+
+__device__ __forceinline__ int wave_max_int(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ unsigned long long ballot(bool p) { return __ballot(p); }
+
+}  // namespace tsr

