@@ -1,0 +1,267 @@
+#!/usr/bin/env python
+"""Benchmark of the differentiable triangle-soup rasterizer on one MI355X.
+
+One step = one pass of the whole hot path over one synthetic input: projection and setup,
+tile binning and per-tile depth sort (tsr_bin_and_sort), then the fused forward render,
+L1 colour + depth loss seeds and backward pass to vertex positions, colours, opacities and
+the se(3) pose (tsr_render_train_l1).  Inputs are resident in HBM before timing starts.
+
+Workload (default): a 1,000,000-face synthetic room soup (90 % of faces 0.5-2 cm, 10 %
+5-20 cm), one 1200x680 view; targets rendered from the pose perturbed by 1 cm / 0.5 deg.
+Also reported: the same step over a batch of 8 views of 1200x680 along a keyframe path,
+the unfused path (forward, then backward from external seeds), per-kernel times (HIP events
+on the launch stream), rooflines, and the FP64 oracle timed on the host cores.
+
+Prints one JSON line.  --gpus N > 1 is not supported (one GPU per process, one GPU here).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
+FP32_VECTOR_PEAK_TF = 157.3    # MI355X FP32 vector, published (packed); 78.6 without packed FP32
+# FLOPs per (pixel, face) window evaluation, counted from the inner loops of the blend kernels:
+# forward 40 (3 edge functions 12, min 2, alpha 1, colour plane 12, blend 11, offsets 2);
+# backward 70 (re-evaluation 29, transmittance recovery 2, colour/depth moments 10,
+# dL/dalpha 12, opacity/window 4, edge moments 3, behind-accumulators 10).
+FLOP_FWD = 40
+FLOP_BWD = 70
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--faces", type=int, default=1_000_000)
+    ap.add_argument("--views", type=int, default=8, help="views of the batched measurement")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-pixels", type=int, default=8192)
+    ap.add_argument("--profile-steps", type=int, default=10)
+    return ap.parse_args()
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class Case:
+    """A rasterizer with its inputs, outputs and gradient buffers resident on the device."""
+
+    def __init__(self, raster, scenes, dev_scene, poses, intrs, target_poses):
+        import torch
+
+        self.torch = torch
+        self.rast = raster.Rasterizer(dev_scene, intrs, raster.Params(sigma=1.0))
+        self.poses = raster.poses_tensor(poses)
+        tposes = raster.poses_tensor(target_poses)
+        self.K = self.rast.fit(self.poses, slack=1.5)
+        Kt = self.rast.count(tposes)
+        self.rast.ensure_capacity(int(max(self.K, Kt) * 1.5) + 4096)
+        # targets: the same map rendered from the perturbed poses
+        self.rast.bin_and_sort(tposes)
+        tc, td, _ = self.rast.forward(tposes)
+        self.tc, self.td = tc.clone(), td.clone()
+        P = self.rast.total_pixels
+        self.color = torch.empty(3 * P, device="cuda")
+        self.depth = torch.empty(P, device="cuda")
+        self.trans = torch.empty(P, device="cuda")
+        self.loss = torch.empty(len(intrs), device="cuda")
+        self.grads = self.rast.grad_buffers()
+        self.pixels = P
+        torch.cuda.synchronize()
+
+    def step(self):
+        self.rast.bin_and_sort(self.poses, check_capacity=False)
+        self.rast.train_l1(self.poses, self.tc, self.td, color=self.color, depth=self.depth, trans=self.trans,
+                           loss=self.loss, out=self.grads)
+
+    def step_unfused(self, gc, gd):
+        self.rast.bin_and_sort(self.poses, check_capacity=False)
+        self.rast.forward(self.poses, self.color, self.depth, self.trans)
+        self.rast.backward(self.poses, gc, gd, None, out=self.grads)
+
+    def check(self):
+        from paper_2605_31419_amd import _lib, raster
+
+        _lib.check(self.rast.lib.tsr_check(raster._ptr(self.rast.ws), raster._stream(), None), "tsr_check")
+
+    def evaluations(self):
+        """Pixel-face window evaluations of one pass: sum over tiles of (pixels in the tile)
+        x (faces in its list), and the tile-list statistics."""
+        import ctypes as C
+
+        b = self.rast.binning()
+        ws = self.rast.ws
+        off = b.ranges - ws.data_ptr()
+        rng = ws[off:off + 8 * b.n_tiles].cpu().numpy().view(np.uint32).reshape(-1, 2).astype(np.int64)
+        lens = rng[:, 1] - rng[:, 0]
+        npx = []
+        for it in self.rast.intrs:
+            tx, ty = (it.width + 15) // 16, (it.height + 15) // 16
+            wx = np.minimum(16, it.width - 16 * np.arange(tx))
+            wy = np.minimum(16, it.height - 16 * np.arange(ty))
+            npx.append((wy[:, None] * wx[None, :]).reshape(-1))
+        npx = np.concatenate(npx)
+        kk = int(ws[b.n_pairs - ws.data_ptr():b.n_pairs - ws.data_ptr() + 8].cpu().numpy().view(np.int64)[0])
+        cnt_off = b.tile_counts - ws.data_ptr()
+        counts = ws[cnt_off:cnt_off + 4 * self.rast.n_views * self.rast.scene.n_faces].cpu().numpy().view(np.uint32)
+        return int((lens * npx).sum()), kk, int((counts > 0).sum()), int(lens.max()), float(lens.mean())
+
+
+def time_steps(fn, steps, warmup):
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(st)
+    for _ in range(steps):
+        fn()
+    b.record(st)
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def kernel_times(fn, steps):
+    from paper_2605_31419_amd import _lib
+    import torch
+
+    torch.cuda.synchronize()
+    _lib.profile_reset()
+    _lib.profile_enable(True)
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    prof = _lib.profile_read()
+    _lib.profile_enable(False)
+    _lib.profile_reset()
+    return {k: v[1] / v[0] for k, v in prof.items()}, {k: v[0] // steps for k, v in prof.items()}
+
+
+def bin_sort_bytes(M, V, m_vis, K, n_tiles):
+    """Algorithmic HBM bytes of projection + binning + sort with one sort pass (lower bound):
+    positions 36 B/face, setup records 96 B per visible (view, face), counts 8 B per
+    (view, face), emission 12 B per pair, one sort pass 24 B per pair, ranges 8 B per pair and
+    8 B per tile."""
+    return M * 36 + m_vis * 96 + V * M * 8 + K * 12 + K * 24 + K * 8 + n_tiles * 8
+
+
+def cpu_baseline(w, n_pix, seed=7):
+    from oracle import oracle as O
+
+    intr = w.intr[0]
+    g = np.random.default_rng(seed)
+    pix = np.sort(g.choice(intr.width * intr.height, size=n_pix, replace=False)).astype(np.int64)
+    t0 = time.perf_counter()
+    C, D, T = O.render(w.scene, w.poses[0], intr, pixels=pix)
+    t1 = time.perf_counter()
+    gc = np.full((3, n_pix), 1.0 / (3 * intr.width * intr.height))
+    gd = np.full(n_pix, 0.05 / (intr.width * intr.height))
+    O.backward(w.scene, w.poses[0], intr, gc, gd, None, pixels=pix)
+    t2 = time.perf_counter()
+    return {"value": n_pix / (t2 - t0) / 1e6, "unit": "Mpix/s", "cores": O.max_threads(), "kind": "oracle",
+            "sample": f"{n_pix} seeded pixels of the 1200x680 view, forward + backward over all "
+                      f"{w.scene.n_faces} faces (forward {t1 - t0:.2f} s, backward {t2 - t1:.2f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU sharding of views "
+              "is designed but not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2605_31419_amd import raster, scenes
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    log(f"[bench] generating the {args.faces}-face room soup")
+    w = scenes.workload("track_1200x680_1M", n_faces=args.faces)
+    dev = raster.DeviceScene.from_numpy(w.scene)
+    single = Case(raster, scenes, dev, w.poses, w.intr, w.target_poses)
+    E, K, m_vis, maxlen, meanlen = single.evaluations()
+    log(f"[bench] single view: K={K} visible={m_vis} max list {maxlen} mean {meanlen:.1f} evals {E}")
+    ms = time_steps(single.step, args.steps, args.warmup)
+    single.check()
+    mpix = single.pixels / (ms * 1e-3) / 1e6
+    log(f"[bench] fused step {ms:.3f} ms -> {mpix:.1f} Mpix/s")
+    ktimes, klaunch = kernel_times(single.step, args.profile_steps)
+    log(f"[bench] kernels (ms): {json.dumps({k: round(v, 4) for k, v in ktimes.items()})}")
+
+    # unfused path (forward, then backward from external per-pixel seeds)
+    gc = torch.full((3 * single.pixels,), 1e-6, device="cuda")
+    gd = torch.full((single.pixels,), 1e-7, device="cuda")
+    ms_unf = time_steps(lambda: single.step_unfused(gc, gd), args.steps, args.warmup)
+    kt_unf, _ = kernel_times(lambda: single.step_unfused(gc, gd), args.profile_steps)
+
+    batched = None
+    if not args.no_batched:
+        g = scenes.rng(5500)
+        bposes = scenes.room_trajectory(g, args.views)
+        btargets = [scenes.perturb_pose(p, g) for p in bposes]
+        bcase = Case(raster, scenes, dev, bposes, [w.intr[0]] * args.views, btargets)
+        Eb, Kb, mvb, maxb, meanb = bcase.evaluations()
+        msb = time_steps(bcase.step, max(5, args.steps // 4), args.warmup)
+        bcase.check()
+        ktb, _ = kernel_times(bcase.step, max(2, args.profile_steps // 2))
+        batched = {"n_views": args.views, "ms_per_step": msb, "mpix_s": bcase.pixels / (msb * 1e-3) / 1e6,
+                   "K": Kb, "visible": mvb, "kernels_ms": {k: round(v, 4) for k, v in ktb.items()}}
+        log(f"[bench] batched {args.views} views: {msb:.3f} ms -> {batched['mpix_s']:.1f} Mpix/s")
+        del bcase
+        torch.cuda.empty_cache()
+
+    # rooflines
+    bs_names = ["fill_tiles", "project", "scan_tiles", "emit", "tile_sort"]
+    bs_ms = sum(ktimes.get(k, 0.0) for k in bs_names)
+    n_tiles = single.rast.binning().n_tiles
+    bs_bytes = bin_sort_bytes(args.faces, 1, m_vis, K, n_tiles)
+    dom = max(ktimes, key=ktimes.get)
+    if dom == "train_fused":
+        flops = E * (FLOP_FWD + FLOP_BWD)
+        ach = flops / (ktimes[dom] * 1e-3) / 1e12
+        roof = {"kernel": dom, "bound": "alu", "achieved": ach, "peak": FP32_VECTOR_PEAK_TF, "unit": "TFLOP/s",
+                "frac": ach / FP32_VECTOR_PEAK_TF, "traffic": None,
+                "work": f"{E} pixel-face evaluations x {FLOP_FWD + FLOP_BWD} FLOP"}
+    else:
+        ach = bs_bytes / (bs_ms * 1e-3) / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": None}
+    bs_ach = bs_bytes / (bs_ms * 1e-3) / 1e9
+    out = {
+        "metric": "fwd+bwd Mpix/s at 1200x680, 1M tris (1 view vs batched); p50/p99 render latency",
+        "value": mpix, "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"1200x680 single view, {args.faces}-face synthetic room soup "
+                               "(90% 0.5-2 cm, 10% 5-20 cm), fused fwd + L1 + bwd incl. pose",
+                   "faces": args.faces, "pairs": K, "visible_faces": m_vis},
+        "roofline": roof,
+        "bin_sort_roofline": {"bound": "hbm", "achieved": bs_ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": bs_ach / HBM_PEAK_GBS, "ms": bs_ms, "algorithmic_bytes": bs_bytes},
+        "kernels_ms": {k: round(v, 4) for k, v in ktimes.items()},
+        "unfused": {"ms_per_step": ms_unf, "mpix_s": single.pixels / (ms_unf * 1e-3) / 1e6,
+                    "kernels_ms": {k: round(v, 4) for k, v in kt_unf.items()}},
+        "batched": batched,
+    }
+    if not args.no_cpu_baseline:
+        log(f"[bench] oracle on {args.cpu_pixels} pixels")
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_pixels)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

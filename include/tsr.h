@@ -98,6 +98,17 @@ typedef struct {
     int64_t n_faces;         /* M */
 } tsr_scene;
 
+/* Work schedule of the fused training kernel (host).  NULL selects the default
+ * {persistent = 0, order = 0, grid = 0}.  Results do not depend on the schedule except for
+ * the summation order of the floating-point gradient atomics. */
+typedef struct {
+    int32_t persistent;  /* 0: one workgroup per tile; 1: persistent workgroups pull tiles from a
+                            device-side queue */
+    int32_t order;       /* 0: tiles in id order (XCD-interleaved when not persistent);
+                            1: longest tile lists first (computed on the device) */
+    int32_t grid;        /* persistent workgroups; 0 = 2048 */
+} tsr_schedule;
+
 /* Read-only view of the binning held in a workspace (device pointers). */
 typedef struct {
     const uint64_t *pairs;     /* [capacity] sorted pairs; pair i = (float32 bits of z_F << 32) | face,
@@ -159,13 +170,13 @@ TSR_API int tsr_render_backward(const tsr_scene *scene, const float *poses, cons
  * D-SSIM term, L = w_color mean|C - Cbar| + w_depth mean([Dbar > 0] |D - Dbar|) per view,
  * and its backward, with each tile's forward state kept on chip between the two passes.
  * Targets are packed like the outputs.  color/depth/trans/loss may be NULL (loss: [n_views]).
- * Gradients as in tsr_render_backward. */
+ * Gradients as in tsr_render_backward.  `schedule` (nullable) picks the tile schedule. */
 TSR_API int tsr_render_train_l1(const tsr_scene *scene, const float *poses, const tsr_intrinsics *intr,
                         int n_views, const tsr_params *params, void *ws, size_t ws_bytes,
                         const float *target_color, const float *target_depth,
                         float *color, float *depth, float *trans, float *loss,
                         float *grad_pos, float *grad_col, float *grad_opa, float *grad_pose,
-                        void *stream);
+                        const tsr_schedule *schedule, void *stream);
 
 /* Gradient-descent pose step on the device: T_CW <- Exp(-(lr_trans g_rho, lr_rot g_theta)) T_CW
  * for each view (the tracking update of Sec. 3.4); poses [n_views][12] updated in place. */
@@ -173,8 +184,19 @@ TSR_API int tsr_pose_step(float *poses, const float *grad_pose, int n_views, flo
                   void *stream);
 
 /* Synchronise `stream` and report device-side conditions of `ws`: TSR_ECAPACITY when the
- * last binning overflowed.  Writes K to *n_pairs when non-NULL. */
+ * last binning, or any binning since the previous tsr_check (e.g. inside a replayed graph),
+ * overflowed; that condition is then cleared.  Writes the last K to *n_pairs when non-NULL.
+ * Never call it while `stream` is being captured. */
 TSR_API int tsr_check(const void *ws, void *stream, int64_t *n_pairs /* (host) out, nullable */);
+
+/* Kernel timing (diagnostics).  While enabled, every kernel the library launches is
+ * bracketed by two HIP events recorded on its launch stream.  tsr_profile_read synchronises
+ * on those events and writes a JSON object {"kernel name": [launches, total milliseconds], ...}
+ * accumulated since the last reset into buf (host, len bytes).  Do not enable during HIP
+ * graph capture.  Process-wide state, guarded by a mutex. */
+TSR_API int tsr_profile_enable(int on);
+TSR_API int tsr_profile_reset(void);
+TSR_API int tsr_profile_read(char *buf, size_t len);
 
 /* Message of the last failure on this thread ("" if none). */
 TSR_API const char *tsr_last_error(void);

@@ -21,7 +21,8 @@ TSR_MAX_VIEWS = 32
 TSR_TILE = 16
 
 EXPORTED = ["tsr_workspace_size", "tsr_bin_and_sort", "tsr_count", "tsr_binning_view", "tsr_render_forward",
-            "tsr_render_backward", "tsr_render_train_l1", "tsr_pose_step", "tsr_check", "tsr_last_error"]
+            "tsr_render_backward", "tsr_render_train_l1", "tsr_pose_step", "tsr_check", "tsr_last_error",
+            "tsr_profile_enable", "tsr_profile_reset", "tsr_profile_read"]
 
 
 class TsrIntrinsics(C.Structure):
@@ -37,6 +38,10 @@ class TsrParams(C.Structure):
 class TsrScene(C.Structure):
     _fields_ = [("pos", C.c_void_p), ("col", C.c_void_p), ("opa", C.c_void_p), ("faces", C.c_void_p),
                 ("n_vertices", C.c_int64), ("n_faces", C.c_int64)]
+
+
+class TsrSchedule(C.Structure):
+    _fields_ = [("persistent", C.c_int32), ("order", C.c_int32), ("grid", C.c_int32)]
 
 
 class TsrBinning(C.Structure):
@@ -69,10 +74,13 @@ def load() -> C.CDLL:
     lib.tsr_binning_view.argtypes = [P, P, I, P, C.c_size_t, P]
     lib.tsr_render_forward.argtypes = [P, P, P, I, P, P, C.c_size_t, P, P, P, P]
     lib.tsr_render_backward.argtypes = [P, P, P, I, P, P, C.c_size_t, P, P, P, P, P, P, P, P]
-    lib.tsr_render_train_l1.argtypes = [P, P, P, I, P, P, C.c_size_t, P, P, P, P, P, P, P, P, P, P, P]
+    lib.tsr_render_train_l1.argtypes = [P, P, P, I, P, P, C.c_size_t, P, P, P, P, P, P, P, P, P, P, P, P]
     lib.tsr_pose_step.argtypes = [P, P, I, C.c_float, C.c_float, P]
     lib.tsr_check.argtypes = [P, P, P]
     lib.tsr_last_error.restype = C.c_char_p
+    lib.tsr_profile_enable.argtypes = [I]
+    lib.tsr_profile_reset.argtypes = []
+    lib.tsr_profile_read.argtypes = [C.c_char_p, C.c_size_t]
     for fn in EXPORTED:
         getattr(lib, fn).restype = C.c_char_p if fn == "tsr_last_error" else C.c_int
     _lib = lib
@@ -82,3 +90,20 @@ def load() -> C.CDLL:
 def check(rc: int, where: str) -> None:
     if rc != TSR_OK:
         raise TsrError(rc, where, load().tsr_last_error().decode())
+
+
+def profile_enable(on: bool = True) -> None:
+    check(load().tsr_profile_enable(1 if on else 0), "tsr_profile_enable")
+
+
+def profile_reset() -> None:
+    check(load().tsr_profile_reset(), "tsr_profile_reset")
+
+
+def profile_read() -> dict:
+    """{kernel: (launches, total_ms)} since the last reset (synchronises the recorded events)."""
+    import json
+
+    buf = C.create_string_buffer(1 << 16)
+    check(load().tsr_profile_read(buf, len(buf)), "tsr_profile_read")
+    return {k: (int(v[0]), float(v[1])) for k, v in json.loads(buf.value.decode()).items()}

@@ -5,9 +5,56 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "tsr_internal.h"
+
+// ---------------------------------------------------------------------------- kernel timing
+namespace tsr {
+namespace {
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_pending;
+std::vector<hipEvent_t> g_prof_pool;
+std::map<std::string, std::pair<long long, double>> g_prof_acc;   // name -> (launches, total ms)
+
+hipEvent_t pool_event() {
+  if (!g_prof_pool.empty()) {
+    hipEvent_t e = g_prof_pool.back();
+    g_prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+}  // namespace
+
+int prof_begin(hipStream_t st) {
+  if (!g_prof_on) return -1;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  ProfRec r{nullptr, pool_event(), pool_event()};
+  if (!r.a || !r.b) return -1;
+  (void)hipEventRecord(r.a, st);
+  g_prof_pending.push_back(r);
+  return (int)g_prof_pending.size() - 1;
+}
+
+void prof_end(int token, const char* name, hipStream_t st) {
+  if (token < 0) return;
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  if (token >= (int)g_prof_pending.size()) return;
+  g_prof_pending[token].name = name;
+  (void)hipEventRecord(g_prof_pending[token].b, st);
+}
+}  // namespace tsr
 
 namespace {
 
@@ -89,6 +136,7 @@ WsLayout layout(const ViewTable& vt, int64_t cap) {
   L.hdr_k = 0;
   L.hdr_overflow = 8;
   L.hdr_queue = 12;
+  L.hdr_sticky = 16;
   o = 256;
   L.pose_acc = o; o = align_up(o + sizeof(double) * 6 * vt.n_views);
   L.loss_acc = o; o = align_up(o + sizeof(double) * vt.n_views);
@@ -97,6 +145,8 @@ WsLayout layout(const ViewTable& vt, int64_t cap) {
   L.grad_acc = o; o = align_up(o + sizeof(float) * tsr::kGradDwords * nf);
   L.tile_cnt = o; o = align_up(o + sizeof(uint32_t) * vt.n_tiles);
   L.ranges = o; o = align_up(o + sizeof(uint32_t) * 2 * vt.n_tiles);
+  L.order = o; o = align_up(o + sizeof(int32_t) * vt.n_tiles);
+  L.order_hist = o; o = align_up(o + sizeof(uint32_t) * 2 * tsr::kOrderBuckets);
   L.n_last = o; o = align_up(o + sizeof(int32_t) * P);
   L.t_last = o; o = align_up(o + sizeof(float) * P);
   L.fixed_end = o;
@@ -249,13 +299,20 @@ int tsr_render_backward(const tsr_scene* scene, const float* poses, const tsr_in
 int tsr_render_train_l1(const tsr_scene* scene, const float* poses, const tsr_intrinsics* intr, int n_views,
                         const tsr_params* params, void* ws, size_t ws_bytes, const float* target_color,
                         const float* target_depth, float* color, float* depth, float* trans, float* loss,
-                        float* grad_pos, float* grad_col, float* grad_opa, float* grad_pose, void* stream) {
+                        float* grad_pos, float* grad_col, float* grad_opa, float* grad_pose,
+                        const tsr_schedule* schedule, void* stream) {
   ViewTable vt;
   WsLayout L;
   int rc = prepare(scene, poses, intr, n_views, params, ws, ws_bytes, &vt, &L);
   if (rc) return rc;
   if (!target_color || !target_depth) return fail(TSR_EINVAL, "target_color or target_depth is NULL");
   tsr::TrainSchedule sched{0, 0, 0};
+  if (schedule) {
+    if (schedule->persistent < 0 || schedule->persistent > 1 || schedule->order < 0 || schedule->order > 1 ||
+        schedule->grid < 0 || schedule->grid > (1 << 20))
+      return fail(TSR_EINVAL, "bad schedule");
+    sched = {schedule->persistent, schedule->order, schedule->grid};
+  }
   hipError_t e = tsr::launch_backward(dev_scene(scene), poses, vt, *params, L, static_cast<char*>(ws), nullptr,
                                       nullptr, nullptr, target_color, target_depth, color, depth, trans, loss,
                                       grad_pos, grad_col, grad_opa, grad_pose, true, sched,
@@ -270,19 +327,76 @@ int tsr_pose_step(float* poses, const float* grad_pose, int n_views, float lr_tr
   return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_pose_step launch");
 }
 
+int tsr_profile_enable(int on) {
+  std::lock_guard<std::mutex> lk(tsr::g_prof_mu);
+  tsr::g_prof_on = on != 0;
+  return TSR_OK;
+}
+
+int tsr_profile_reset(void) {
+  std::lock_guard<std::mutex> lk(tsr::g_prof_mu);
+  for (auto& r : tsr::g_prof_pending) {
+    (void)hipEventSynchronize(r.b);
+    tsr::g_prof_pool.push_back(r.a);
+    tsr::g_prof_pool.push_back(r.b);
+  }
+  tsr::g_prof_pending.clear();
+  tsr::g_prof_acc.clear();
+  return TSR_OK;
+}
+
+int tsr_profile_read(char* buf, size_t len) {
+  if (!buf || len == 0) return fail(TSR_EINVAL, "profile buffer is NULL");
+  std::lock_guard<std::mutex> lk(tsr::g_prof_mu);
+  for (auto& r : tsr::g_prof_pending) {
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e != hipSuccess) return hip_fail(e, "tsr_profile_read sync");
+    float ms = 0.f;
+    if ((e = hipEventElapsedTime(&ms, r.a, r.b)) != hipSuccess) return hip_fail(e, "tsr_profile_read elapsed");
+    auto& acc = tsr::g_prof_acc[r.name ? r.name : "?"];
+    acc.first += 1;
+    acc.second += (double)ms;
+    tsr::g_prof_pool.push_back(r.a);
+    tsr::g_prof_pool.push_back(r.b);
+  }
+  tsr::g_prof_pending.clear();
+  std::string out = "{";
+  bool first = true;
+  for (auto& kv : tsr::g_prof_acc) {
+    char item[256];
+    snprintf(item, sizeof item, "%s\"%s\": [%lld, %.9g]", first ? "" : ", ", kv.first.c_str(), kv.second.first,
+             kv.second.second);
+    out += item;
+    first = false;
+  }
+  out += "}";
+  if (out.size() + 1 > len) return fail(TSR_EINVAL, "profile buffer too small (%zu bytes needed)", out.size() + 1);
+  memcpy(buf, out.c_str(), out.size() + 1);
+  return TSR_OK;
+}
+
 int tsr_check(const void* ws, void* stream, int64_t* n_pairs) {
   if (!ws) return fail(TSR_EINVAL, "workspace is NULL");
   hipStream_t st = static_cast<hipStream_t>(stream);
   struct {
     int64_t k;
     uint32_t overflow;
+    uint32_t queue;
+    uint32_t sticky;
     uint32_t pad;
   } h;
   hipError_t e = hipMemcpyAsync(&h, ws, sizeof h, hipMemcpyDeviceToHost, st);
   if (e != hipSuccess) return hip_fail(e, "tsr_check copy");
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "tsr_check sync");
   if (n_pairs) *n_pairs = h.k;
-  if (h.overflow) return fail(TSR_ECAPACITY, "binning produced %lld pairs, above the workspace capacity", (long long)h.k);
+  if (h.sticky) {
+    // clear the sticky flag (synchronous: tsr_check is never part of a captured graph)
+    if ((e = hipMemsetAsync(static_cast<char*>(const_cast<void*>(ws)) + 16, 0, 4, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess)
+      return hip_fail(e, "tsr_check clear");
+  }
+  if (h.overflow || h.sticky)
+    return fail(TSR_ECAPACITY, "a binning produced more pairs than the workspace capacity (last K = %lld)", (long long)h.k);
   return TSR_OK;
 }
 

@@ -238,7 +238,8 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* __restrict__ tile
   }
   if (tid == 0) {
     *K_out = (int64_t)total;
-    *overflow = over ? 1u : 0u;
+    overflow[0] = over ? 1u : 0u;     // this binning
+    if (over) overflow[2] = 1u;       // sticky until tsr_check reads it (spans graph replays)
   }
 }
 
@@ -390,17 +391,17 @@ hipError_t launch_bin(const tsr_scene_dev& sc, const float* poses, const ViewTab
   uint64_t* temp = reinterpret_cast<uint64_t*>(ws + L.temp);
   const int64_t nf = (int64_t)vt.n_views * vt.n_faces;
 
-  hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(vt.n_tiles, 256)), dim3(256), 0, st, tile_cnt, (int64_t)vt.n_tiles, 0u);
+  TSR_LAUNCH("fill_tiles", k_fill_u32, dim3(grid_for(vt.n_tiles, 256)), dim3(256), 0, st, tile_cnt, (int64_t)vt.n_tiles, 0u);
   if (nf > 0)
-    hipLaunchKernelGGL(k_project, dim3(grid_for(nf, 256)), dim3(256), 0, st, sc, poses, vt, p.z_near, p.r_min, counts,
+    TSR_LAUNCH("project", k_project, dim3(grid_for(nf, 256)), dim3(256), 0, st, sc, poses, vt, p.z_near, p.r_min, counts,
                        records, tile_cnt);
-  hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(1024), 0, st, tile_cnt, ranges, vt.n_tiles,
+  TSR_LAUNCH("scan_tiles", k_scan_tiles, dim3(1), dim3(1024), 0, st, tile_cnt, ranges, vt.n_tiles,
                      sort ? L.capacity : (int64_t)0x7fffffffffffffffll, K, overflow);
   if (!sort) return hipGetLastError();
   if (nf > 0)
-    hipLaunchKernelGGL(k_emit, dim3(grid_for(nf, 256)), dim3(256), 0, st, vt, counts, records, ranges, tile_cnt,
+    TSR_LAUNCH("emit", k_emit, dim3(grid_for(nf, 256)), dim3(256), 0, st, vt, counts, records, ranges, tile_cnt,
                        overflow, pairs);
-  hipLaunchKernelGGL(k_tile_sort, dim3(vt.n_tiles), dim3(256), 0, st, ranges, vt.n_tiles, pairs, temp);
+  TSR_LAUNCH("tile_sort", k_tile_sort, dim3(vt.n_tiles), dim3(256), 0, st, ranges, vt.n_tiles, pairs, temp);
   return hipGetLastError();
 }
 

@@ -592,6 +592,35 @@ __global__ void k_zero_acc(const uint32_t* __restrict__ counts, int64_t nf, floa
   if (i < n_views && loss_acc) loss_acc[i] = 0.0;
 }
 
+// Longest-first tile order: counting sort of the tiles by list length (lengths above
+// kOrderBuckets - 1 share the top bucket), descending.  One workgroup.
+__global__ __launch_bounds__(1024) void k_tile_order(const uint32_t* __restrict__ ranges, int n_tiles,
+                                                     uint32_t* __restrict__ scratch, int* __restrict__ order) {
+  __shared__ uint32_t hist[kOrderBuckets];
+  __shared__ uint32_t base[kOrderBuckets];
+  for (int b = threadIdx.x; b < kOrderBuckets; b += blockDim.x) hist[b] = 0u;
+  __syncthreads();
+  for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) {
+    const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+    atomicAdd(&hist[min(len, (uint32_t)kOrderBuckets - 1u)], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {          // descending exclusive scan (1024 entries, once per launch)
+    uint32_t run = 0;
+    for (int b = kOrderBuckets - 1; b >= 0; --b) {
+      base[b] = run;
+      run += hist[b];
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) {
+    const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+    const uint32_t pos = atomicAdd(&base[min(len, (uint32_t)kOrderBuckets - 1u)], 1u);
+    order[pos] = t;
+  }
+  (void)scratch;
+}
+
 __global__ void k_zero_i32(int* __restrict__ p, int n) {
   if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
@@ -671,10 +700,10 @@ hipError_t launch_forward(const ViewTable& vt, const tsr_params& p, const WsLayo
   float* t_last = reinterpret_cast<float*>(ws + L.t_last);
   const dim3 grid(tile_grid(vt.n_tiles)), block(kBlock);
   switch (sigma_mode(p.sigma)) {
-    case 1: hipLaunchKernelGGL(k_blend_fwd<1>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last); break;
-    case 2: hipLaunchKernelGGL(k_blend_fwd<2>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last); break;
-    case 3: hipLaunchKernelGGL(k_blend_fwd<3>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last); break;
-    default: hipLaunchKernelGGL(k_blend_fwd<0>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last); break;
+    case 1: TSR_LAUNCH("blend_fwd", k_blend_fwd<1>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last); break;
+    case 2: TSR_LAUNCH("blend_fwd", k_blend_fwd<2>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last); break;
+    case 3: TSR_LAUNCH("blend_fwd", k_blend_fwd<3>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last); break;
+    default: TSR_LAUNCH("blend_fwd", k_blend_fwd<0>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last); break;
   }
   return hipGetLastError();
 }
@@ -696,44 +725,51 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
   double* loss_acc = reinterpret_cast<double*>(ws + L.loss_acc);
   const int64_t nf = (int64_t)vt.n_views * vt.n_faces;
   const int64_t zn = nf > 6 * vt.n_views ? nf : 6 * vt.n_views;
-  hipLaunchKernelGGL(k_zero_acc, dim3(grid_for(zn, 256)), dim3(256), 0, st, counts, nf, grad_acc, pose_acc, loss_acc,
+  TSR_LAUNCH("zero_acc", k_zero_acc, dim3(grid_for(zn, 256)), dim3(256), 0, st, counts, nf, grad_acc, pose_acc, loss_acc,
                      vt.n_views);
   const dim3 block(kBlock);
   const int sm = sigma_mode(p.sigma);
   if (!fused_train) {
     const dim3 grid(tile_grid(vt.n_tiles));
-#define TSR_BWD(S) hipLaunchKernelGGL(k_blend_bwd<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, n_last, t_last, gcolor, gdepth, gtrans, grad_acc)
+#define TSR_BWD(S) TSR_LAUNCH("blend_bwd", k_blend_bwd<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, n_last, t_last, gcolor, gdepth, gtrans, grad_acc)
     switch (sm) { case 1: TSR_BWD(1); break; case 2: TSR_BWD(2); break; case 3: TSR_BWD(3); break; default: TSR_BWD(0); }
 #undef TSR_BWD
   } else {
     const int* order = nullptr;
     int* queue = nullptr;
     dim3 grid(tile_grid(vt.n_tiles));
+    if (sched.order) {
+      int* ord = reinterpret_cast<int*>(ws + L.order);
+      TSR_LAUNCH("tile_order", k_tile_order, dim3(1), dim3(1024), 0, st, ranges, vt.n_tiles,
+                 reinterpret_cast<uint32_t*>(ws + L.order_hist), ord);
+      order = ord;
+      if (!sched.persistent) grid = dim3(vt.n_tiles);
+    }
     if (sched.persistent) {
       queue = reinterpret_cast<int*>(ws + L.hdr_queue);
       grid = dim3(sched.grid > 0 ? sched.grid : 2048);
-      hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, queue, 1);
+      TSR_LAUNCH("zero_queue", k_zero_i32, dim3(1), dim3(64), 0, st, queue, 1);
     }
-#define TSR_TRAIN(S) hipLaunchKernelGGL(k_train_fused<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, p.w_color, p.w_depth, tcolor, tdepth, color, depth, trans, loss ? loss_acc : nullptr, grad_acc, order, queue, sched.persistent)
+#define TSR_TRAIN(S) TSR_LAUNCH("train_fused", k_train_fused<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, p.w_color, p.w_depth, tcolor, tdepth, color, depth, trans, loss ? loss_acc : nullptr, grad_acc, order, queue, sched.persistent)
     switch (sm) { case 1: TSR_TRAIN(1); break; case 2: TSR_TRAIN(2); break; case 3: TSR_TRAIN(3); break; default: TSR_TRAIN(0); }
 #undef TSR_TRAIN
   }
   const bool atomic_vertices = sc.faces != nullptr;
   if (atomic_vertices) {
     const int64_t N = sc.n_vertices;
-    if (grad_pos) hipLaunchKernelGGL(k_fill_f32, dim3(1024), dim3(256), 0, st, grad_pos, 3 * N);
-    if (grad_col) hipLaunchKernelGGL(k_fill_f32, dim3(1024), dim3(256), 0, st, grad_col, 3 * N);
-    if (grad_opa) hipLaunchKernelGGL(k_fill_f32, dim3(1024), dim3(256), 0, st, grad_opa, N);
+    if (grad_pos) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(1024), dim3(256), 0, st, grad_pos, 3 * N);
+    if (grad_col) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(1024), dim3(256), 0, st, grad_col, 3 * N);
+    if (grad_opa) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(1024), dim3(256), 0, st, grad_opa, N);
   }
   if (vt.n_faces > 0)
-    hipLaunchKernelGGL(k_face_bwd, dim3(grid_for(vt.n_faces, 256)), dim3(256), 0, st, sc, poses, vt, counts, records,
+    TSR_LAUNCH("face_bwd", k_face_bwd, dim3(grid_for(vt.n_faces, 256)), dim3(256), 0, st, sc, poses, vt, counts, records,
                        grad_acc, grad_pos, grad_col, grad_opa, grad_pose ? pose_acc : nullptr, atomic_vertices ? 1 : 0);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, pose_acc, grad_pose, loss_acc, loss, vt.n_views);
+  TSR_LAUNCH("finalize", k_finalize, dim3(1), dim3(256), 0, st, pose_acc, grad_pose, loss_acc, loss, vt.n_views);
   return hipGetLastError();
 }
 
 hipError_t launch_pose_step(float* poses, const float* grad_pose, int n_views, float lr_t, float lr_r, hipStream_t st) {
-  hipLaunchKernelGGL(k_pose_step, dim3(1), dim3(64), 0, st, poses, grad_pose, n_views, lr_t, lr_r);
+  TSR_LAUNCH("pose_step", k_pose_step, dim3(1), dim3(64), 0, st, poses, grad_pose, n_views, lr_t, lr_r);
   return hipGetLastError();
 }
 

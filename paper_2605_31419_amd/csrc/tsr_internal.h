@@ -25,6 +25,7 @@ struct tsr_scene_dev {
 struct WsLayout {
   size_t hdr_k, hdr_overflow;      // int64 K, uint32 overflow flag
   size_t hdr_queue;                // int32 work-queue counter of the persistent training kernel
+  size_t hdr_sticky;               // uint32: some binning since the last tsr_check overflowed
   size_t pose_acc;                 // double [V][6]
   size_t loss_acc;                 // double [V]
   size_t counts;                   // uint32 [V*M]
@@ -32,6 +33,8 @@ struct WsLayout {
   size_t grad_acc;                 // float  [V*M][20]
   size_t tile_cnt;                 // uint32 [T]
   size_t ranges;                   // uint32 [T][2]
+  size_t order;                    // int32  [T] tile schedule (longest lists first)
+  size_t order_hist;               // uint32 [2][kOrderBuckets]
   size_t n_last;                   // int32  [P]
   size_t t_last;                   // float  [P]
   size_t fixed_end;
@@ -41,12 +44,26 @@ struct WsLayout {
   int64_t capacity;
 };
 
-// Training-kernel schedule (chosen by the autotuner; defaults are the static schedule).
+constexpr int kOrderBuckets = 1024;   // tile-length buckets of the longest-first schedule
+
+// Training-kernel schedule (chosen by the autotuner; the default is one workgroup per tile).
 struct TrainSchedule {
   int persistent;       // 0: one workgroup per tile; 1: persistent workgroups pull tiles from a queue
-  int order;            // 0: raster order; 1: heaviest tiles first (needs a sort of tile lengths)
-  int grid;             // persistent workgroups (0 = 8 per CU)
+  int order;            // 0: tile-id order; 1: longest tile lists first
+  int grid;             // persistent workgroups (0 = 2048)
 };
+
+// Optional per-kernel timing with HIP events recorded on the launch stream (off by default).
+// prof_begin returns a token (-1 when profiling is off); prof_end closes it under `name`.
+int prof_begin(hipStream_t st);
+void prof_end(int token, const char* name, hipStream_t st);
+
+#define TSR_LAUNCH(name, kernel, grid, block, shmem, st, ...)                 \
+  do {                                                                        \
+    const int tsr_tok_ = ::tsr::prof_begin(st);                               \
+    hipLaunchKernelGGL(kernel, grid, block, shmem, st, __VA_ARGS__);          \
+    ::tsr::prof_end(tsr_tok_, name, st);                                      \
+  } while (0)
 
 hipError_t launch_bin(const tsr_scene_dev& sc, const float* poses, const ViewTable& vt, const tsr_params& p,
                       const WsLayout& L, char* ws, bool sort, hipStream_t st);

@@ -17,7 +17,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import TsrBinning, TsrIntrinsics, TsrParams, TsrScene, check
+from ._lib import TsrBinning, TsrIntrinsics, TsrParams, TsrScene, TsrSchedule, check
 
 
 @dataclasses.dataclass
@@ -104,6 +104,7 @@ class Rasterizer:
         self.total_pixels = sum(self.pixels)
         self.ws: Optional[torch.Tensor] = None
         self.capacity = 0
+        self.schedule: Optional[Tuple[int, int, int]] = None   # (persistent, order, grid) for train_l1
         self.ensure_capacity(capacity)
 
     # ----------------------------------------------------------------- workspace
@@ -172,11 +173,13 @@ class Rasterizer:
         return gp, gc, go, gpose
 
     def train_l1(self, poses: torch.Tensor, target_color, target_depth, color=None, depth=None, trans=None,
-                 loss=None, out=None, stream=None):
+                 loss=None, out=None, schedule=None, stream=None):
         gp, gc, go, gpose = out if out is not None else self.grad_buffers()
+        sched = self.schedule if schedule is None else schedule
+        sp = None if sched is None else C.byref(TsrSchedule(*sched))
         check(self.lib.tsr_render_train_l1(*self._args(poses), _ptr(target_color), _ptr(target_depth), _ptr(color),
                                            _ptr(depth), _ptr(trans), _ptr(loss), _ptr(gp), _ptr(gc), _ptr(go),
-                                           _ptr(gpose), _stream(stream)), "tsr_render_train_l1")
+                                           _ptr(gpose), sp, _stream(stream)), "tsr_render_train_l1")
         return gp, gc, go, gpose
 
     def pose_step(self, poses: torch.Tensor, grad_pose: torch.Tensor, lr_trans: float, lr_rot: float,

@@ -1,0 +1,271 @@
+"""Render serving with the map resident in HBM: continuous batching of colour + depth queries
+of mixed resolutions and poses, admitted against a device-memory budget, executed on several
+streams so that batches overlap on the GPU; latency (completion - arrival) is recorded per
+query and summarised as p50 / p99 beside throughput.
+
+Structure
+  * ``Request``: one query (intrinsics, pose) with arrival / completion timestamps.
+  * ``Server``: an admission queue and ``n_slots`` worker threads.  A request is admitted when
+    its memory estimate fits in what the budget has left; a worker that becomes free takes as
+    many admitted requests as fit its batch limits (FIFO), launches them as one multi-view
+    call on its own stream, waits for that stream only, then releases the memory and completes
+    the requests.  Requests arriving while batches run are admitted as memory frees up, so
+    work from different arrivals overlaps on the device.
+  * ``GpuExecutor``: runs a batch through the C ABI (tsr_bin_and_sort + tsr_render_forward)
+    on the worker's stream; ``FakeExecutor`` (tests) sleeps instead.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import threading
+import time
+from typing import Callable, Deque, List, Optional, Sequence
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    intr: object                  # scenes.Intrinsics
+    pose: np.ndarray              # [12] float32 T_CW
+    arrival: float = 0.0
+    admitted: float = 0.0
+    done: float = 0.0
+    nbytes: int = 0
+    color: object = None          # [3, H, W] device tensor after completion
+    depth: object = None          # [H, W]
+    error: Optional[str] = None
+    event: threading.Event = dataclasses.field(default_factory=threading.Event)
+
+    @property
+    def pixels(self) -> int:
+        return int(self.intr.width) * int(self.intr.height)
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class FakeExecutor:
+    """Scheduler tests: 'renders' by sleeping `per_pixel_s` per pixel; can inject failures."""
+
+    def __init__(self, per_pixel_s: float = 1e-8, fail_ids: Sequence[int] = ()):
+        self.per_pixel_s = per_pixel_s
+        self.fail_ids = set(fail_ids)
+        self.batches: List[List[int]] = []
+        self.lock = threading.Lock()
+        self.active = 0
+        self.max_active = 0
+
+    def estimate_bytes(self, req: Request) -> int:
+        return 20 * req.pixels
+
+    def make_slot(self, i: int):
+        return None
+
+    def run(self, slot, batch: List[Request]) -> None:
+        with self.lock:
+            self.batches.append([r.rid for r in batch])
+            self.active += 1
+            self.max_active = max(self.max_active, self.active)
+        try:
+            time.sleep(self.per_pixel_s * sum(r.pixels for r in batch))
+            for r in batch:
+                if r.rid in self.fail_ids:
+                    r.error = "injected failure"
+        finally:
+            with self.lock:
+                self.active -= 1
+
+
+class GpuExecutor:
+    """Executes batches through the rasterizer on per-slot HIP streams."""
+
+    def __init__(self, dev_scene, params=None, pairs_per_tile: float = 160.0):
+        import torch
+
+        from . import raster
+
+        self.torch = torch
+        self.raster = raster
+        self.scene = dev_scene
+        self.params = params or raster.Params()
+        self.pairs_per_tile = pairs_per_tile          # capacity estimate, corrected on overflow
+        self.lock = threading.Lock()
+        self.retries = 0
+
+    def _capacity(self, intrs) -> int:
+        tiles = sum(((i.width + 15) // 16) * ((i.height + 15) // 16) for i in intrs)
+        return int(self.pairs_per_tile * tiles) + 4096
+
+    def estimate_bytes(self, req: Request) -> int:
+        # workspace of a one-view call plus outputs (colour, depth, transmittance)
+        import ctypes as C
+
+        from ._lib import check, load
+
+        lib = load()
+        out = C.c_size_t(0)
+        sc = self.scene.c()
+        check(lib.tsr_workspace_size(C.byref(sc), self.raster.intrinsics_array([req.intr]), 1,
+                                     self._capacity([req.intr]), C.byref(out)), "tsr_workspace_size")
+        return int(out.value) + 5 * 4 * req.pixels
+
+    def make_slot(self, i: int):
+        return self.torch.cuda.Stream()
+
+    def run(self, stream, batch: List[Request]) -> None:
+        torch, raster = self.torch, self.raster
+        intrs = [r.intr for r in batch]
+        with torch.cuda.stream(stream):
+            rast = raster.Rasterizer(self.scene, intrs, self.params, capacity=self._capacity(intrs))
+            poses = raster.poses_tensor([r.pose for r in batch])
+            rast.bin_and_sort(poses, stream=stream, check_capacity=False)
+            color, depth, _ = rast.forward(poses, stream=stream)
+            rc = rast.lib.tsr_check(raster._ptr(rast.ws), raster._stream(stream), None)   # syncs this stream
+            if rc != 0:                              # capacity estimate too small: exact count, redo
+                with self.lock:
+                    self.retries += 1
+                rast.fit(poses, slack=1.1)
+                rast.bin_and_sort(poses, stream=stream, check_capacity=True)
+                color, depth, _ = rast.forward(poses, stream=stream)
+                stream.synchronize()
+        cs, ds = rast.split_views(color, 3), rast.split_views(depth, 1)
+        for r, c, d in zip(batch, cs, ds):
+            r.color, r.depth = c, d[0]
+        del rast
+
+
+class Server:
+    def __init__(self, executor, n_slots: int = 4, mem_budget: int = 8 << 30, max_batch_views: int = 8,
+                 max_batch_pixels: int = 8 * 1200 * 680, clock: Callable[[], float] = time.perf_counter):
+        self.ex = executor
+        self.n_slots = n_slots
+        self.budget = mem_budget
+        self.used = 0
+        self.max_views = max_batch_views
+        self.max_pixels = max_batch_pixels
+        self.clock = clock
+        self.cv = threading.Condition()
+        self.waiting: Deque[Request] = collections.deque()     # arrived, not admitted
+        self.ready: Deque[Request] = collections.deque()       # admitted, not launched
+        self.completed: List[Request] = []
+        self.stop_flag = False
+        self.threads: List[threading.Thread] = []
+        self.peak_used = 0
+        self.inflight_batches = 0
+        self.peak_inflight = 0
+
+    # ------------------------------------------------------------------ public
+    def start(self) -> None:
+        for i in range(self.n_slots):
+            slot = self.ex.make_slot(i)
+            t = threading.Thread(target=self._worker, args=(slot,), daemon=True)
+            t.start()
+            self.threads.append(t)
+
+    def submit(self, req: Request) -> Request:
+        req.arrival = self.clock()
+        req.nbytes = self.ex.estimate_bytes(req)
+        with self.cv:
+            if req.nbytes > self.budget:
+                req.error = f"request needs {req.nbytes} B, above the whole budget of {self.budget} B"
+                req.done = self.clock()
+                self.completed.append(req)
+                req.event.set()
+                return req
+            self.waiting.append(req)
+            self._admit_locked()
+            self.cv.notify_all()
+        return req
+
+    def drain(self, timeout: float = 600.0) -> None:
+        end = time.monotonic() + timeout
+        with self.cv:
+            while self.waiting or self.ready or self.inflight_batches:
+                left = end - time.monotonic()
+                if left <= 0:
+                    raise TimeoutError("server did not drain")
+                self.cv.wait(min(left, 0.05))
+
+    def stop(self) -> None:
+        with self.cv:
+            self.stop_flag = True
+            self.cv.notify_all()
+        for t in self.threads:
+            t.join(timeout=10)
+
+    def stats(self) -> dict:
+        ok = [r for r in self.completed if r.error is None]
+        lat = np.array([r.latency for r in ok]) * 1e3
+        if not ok:
+            return {"completed": 0, "errors": len(self.completed)}
+        span = max(r.done for r in ok) - min(r.arrival for r in ok)
+        return {"completed": len(ok), "errors": len(self.completed) - len(ok),
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "mean_ms": float(lat.mean()), "qps": len(ok) / span if span > 0 else float("nan"),
+                "mpix_s": sum(r.pixels for r in ok) / span / 1e6 if span > 0 else float("nan"),
+                "peak_mem": self.peak_used, "peak_inflight_batches": self.peak_inflight}
+
+    # ------------------------------------------------------------------ internals
+    def _admit_locked(self) -> None:
+        while self.waiting and self.used + self.waiting[0].nbytes <= self.budget:
+            r = self.waiting.popleft()
+            self.used += r.nbytes
+            self.peak_used = max(self.peak_used, self.used)
+            r.admitted = self.clock()
+            self.ready.append(r)
+
+    def _take_batch_locked(self) -> List[Request]:
+        batch, px = [], 0
+        while self.ready and len(batch) < self.max_views:
+            r = self.ready[0]
+            if batch and px + r.pixels > self.max_pixels:
+                break
+            batch.append(self.ready.popleft())
+            px += r.pixels
+        return batch
+
+    def _worker(self, slot) -> None:
+        while True:
+            with self.cv:
+                while not self.ready and not self.stop_flag:
+                    self.cv.wait(0.05)
+                if self.stop_flag and not self.ready:
+                    return
+                batch = self._take_batch_locked()
+                self.inflight_batches += 1
+                self.peak_inflight = max(self.peak_inflight, self.inflight_batches)
+            try:
+                self.ex.run(slot, batch)
+            except Exception as e:                         # a failed batch fails only its requests
+                for r in batch:
+                    r.error = f"{type(e).__name__}: {e}"
+            now = self.clock()
+            with self.cv:
+                for r in batch:
+                    r.done = now
+                    self.used -= r.nbytes
+                    self.completed.append(r)
+                    r.event.set()
+                self.inflight_batches -= 1
+                self._admit_locked()
+                self.cv.notify_all()
+
+
+def run_poisson(server: Server, queries, time_scale: float = 1.0, warmup: int = 0) -> dict:
+    """Submit (arrival_s, intr, pose) queries at their Poisson arrival times; returns stats of
+    the queries after the first `warmup`."""
+    t0 = time.perf_counter()
+    reqs = []
+    for i, (t_arr, intr, pose) in enumerate(queries):
+        delay = t0 + t_arr * time_scale - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        reqs.append(server.submit(Request(i, intr, pose)))
+    server.drain()
+    keep = {r.rid for r in reqs[warmup:]}
+    server.completed = [r for r in server.completed if r.rid in keep]
+    return server.stats()

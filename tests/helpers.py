@@ -66,4 +66,7 @@ def grad_close(g, ref, rel=1e-3, abs_frac=1e-5, name=""):
     bad = np.nonzero(np.abs(g - ref) > rel * np.abs(ref) + abs_frac * inf + 1e-30)[0]
     msg = (f"{name}: |d|/|ref| = {np.linalg.norm(g - ref) / max(nr, 1e-300):.3e}, "
            f"{bad.size} elementwise outliers of {g.size}")
+    if bad.size:
+        worst = bad[np.argsort(-np.abs(g[bad] - ref[bad]))[:5]]
+        msg += " [" + "; ".join(f"i={i} got={g[i]:.6e} ref={ref[i]:.6e}" for i in worst) + f"] max|ref|={inf:.3e}"
     return norm_ok and bad.size == 0, msg, bad

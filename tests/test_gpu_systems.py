@@ -1,0 +1,210 @@
+"""GPU tests of the systems built around the kernels: the autograd Function, the batched
+mapping window with autotuned schedules, the captured tracking loop, and the serving loop."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2605_31419_amd import autotune, raster
+from paper_2605_31419_amd import scenes as S
+from paper_2605_31419_amd.serve import GpuExecutor, Request, Server
+from paper_2605_31419_amd.track import Tracker
+from paper_2605_31419_amd.window import MappingWindow
+from tests import gpu_util as G
+from tests.helpers import IDENTITY, grad_close, left_perturb, tiny_scene
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+# ---------------------------------------------------------------------------- autograd
+
+def test_autograd_function_matches_oracle():
+    sc, intr = tiny_scene(21, n_faces=40, w=48, h=36, f=36.0)
+    pose = left_perturb(IDENTITY, np.array([0.01, -0.02, 0.0, 0.02, 0.01, -0.01])).astype(np.float32)
+    dev = raster.DeviceScene.from_numpy(sc)
+    for t in (dev.pos, dev.col, dev.opa):
+        t.requires_grad_(True)
+    rast = raster.Rasterizer(dev, [intr])
+    poses = raster.poses_tensor([pose])
+    rast.fit(poses)
+    tau = torch.zeros(1, 6, device="cuda", requires_grad=True)
+    color, depth, trans = raster.rasterize(rast, poses, tau)
+    P = intr.width * intr.height
+    g = np.random.default_rng(3)
+    wc, wd, wt = (torch.as_tensor(g.normal(size=n).astype(np.float32), device="cuda") for n in (3 * P, P, P))
+    loss = (wc * color).sum() + (wd * depth).sum() + (wt * trans).sum()
+    loss.backward()
+    ref = O.backward(sc, pose, intr, wc.cpu().numpy().reshape(3, P), wd.cpu().numpy(), wt.cpu().numpy())
+    got = [dev.pos.grad, dev.col.grad, dev.opa.grad, tau.grad.reshape(-1)]
+    for nm, a, b in zip(["pos", "col", "opa", "tau"], got, ref):
+        ok, msg, _ = grad_close(a.detach().cpu().numpy(), b, name=nm)
+        _say("  " + msg)
+        assert ok, msg
+
+
+def test_autograd_keeps_no_per_pixel_lists():
+    """The workspace grows by 8 bytes per pixel (last-face index, transmittance before it)
+    plus per-tile bookkeeping -- independent of how many faces cover a pixel."""
+    sc, intr = tiny_scene(22, n_faces=40)
+    dev = raster.DeviceScene.from_numpy(sc)
+    small = raster.Rasterizer(dev, [S.Intrinsics(64, 64, 50.0, 50.0, 31.5, 31.5)])
+    big = raster.Rasterizer(dev, [S.Intrinsics(128, 128, 50.0, 50.0, 63.5, 63.5)])
+    d = big.workspace_bytes(0) - small.workspace_bytes(0)
+    px = 128 * 128 - 64 * 64
+    tiles = 64 - 16
+    assert d <= 8 * px + 16 * tiles + 4 * 256, d
+
+
+# ---------------------------------------------------------------------------- mapping window
+
+def _room(n_faces, seed=31):
+    return S.room_soup(seed, n_faces, size_range=(0.005, 0.03))
+
+
+def _window_inputs(n_views=4, n_faces=60_000, w=320, h=240, seed=41):
+    sc = _room(n_faces)
+    g = S.rng(seed)
+    poses = S.room_trajectory(g, n_views)
+    intr = S.intrinsics_for(w, h)
+    targets = [S.perturb_pose(p, g) for p in poses]
+    dev = raster.DeviceScene.from_numpy(sc)
+    tr = raster.Rasterizer(dev, [intr] * n_views)
+    tp = raster.poses_tensor(targets)
+    tr.fit(tp)
+    tr.bin_and_sort(tp)
+    tc, td, _ = tr.forward(tp)
+    return sc, dev, poses, [intr] * n_views, tc.clone(), td.clone()
+
+
+def test_window_batched_equals_sum_of_single_views():
+    sc, dev, poses, intrs, tc, td = _window_inputs()
+    win = MappingWindow(dev, intrs, schedule=(1, 1, 2048))
+    p = raster.poses_tensor(poses)
+    win.prepare(p)
+    gp, gc, go, gpose = [x.clone() for x in win.step(p, tc, td, check_capacity=True)]
+    loss_b = win.loss.clone()
+    P = intrs[0].width * intrs[0].height
+    acc = [torch.zeros_like(gp), torch.zeros_like(gc), torch.zeros_like(go)]
+    for v in range(len(poses)):
+        r = raster.Rasterizer(dev, [intrs[v]])
+        pv = raster.poses_tensor([poses[v]])
+        r.fit(pv)
+        r.bin_and_sort(pv)
+        lv = torch.zeros(1, device="cuda")
+        a, b, c, d = r.train_l1(pv, tc[3 * P * v:3 * P * (v + 1)], td[P * v:P * (v + 1)], loss=lv)
+        acc[0] += a; acc[1] += b; acc[2] += c
+        np.testing.assert_allclose(d.cpu().numpy(), gpose[6 * v:6 * (v + 1)].cpu().numpy(), rtol=1e-3, atol=1e-9)
+        np.testing.assert_allclose(lv.cpu().numpy(), loss_b[v:v + 1].cpu().numpy(), rtol=1e-5)
+    for nm, a, b in zip(["pos", "col", "opa"], [gp, gc, go], acc):
+        ok, msg, _ = grad_close(a.cpu().numpy(), b.cpu().numpy(), name=nm)
+        _say("  " + msg)
+        assert ok, msg
+
+
+def test_every_schedule_gives_the_same_step():
+    sc, dev, poses, intrs, tc, td = _window_inputs(n_views=3, n_faces=40_000)
+    p = raster.poses_tensor(poses)
+    win = MappingWindow(dev, intrs, schedule=(0, 0, 0))
+    win.prepare(p)
+    ref = [x.clone().cpu().numpy() for x in win.step(p, tc, td, check_capacity=True)]
+    for cand in autotune.CANDIDATES[1:]:
+        win.rast.schedule = cand
+        got = [x.cpu().numpy() for x in win.step(p, tc, td)]
+        for nm, a, b in zip(["pos", "col", "opa", "pose"], got, ref):
+            ok, msg, _ = grad_close(a, b, rel=1e-4, name=f"{cand} {nm}")
+            assert ok, msg
+
+
+def test_autotuner_picks_and_records_a_schedule(tmp_path):
+    sc, dev, poses, intrs, tc, td = _window_inputs(n_views=2, n_faces=30_000)
+    p = raster.poses_tensor(poses)
+    win = MappingWindow(dev, intrs, schedule=(0, 0, 0))
+    k = win.prepare(p)
+    best, times = autotune.tune(win.rast, p, tc, td, reps=3)
+    assert best in autotune.CANDIDATES and len(times) == len(autotune.CANDIDATES)
+    path = str(tmp_path / "table.json")
+    tab = {}
+    autotune.record(tab, intrs, k, best, times)
+    autotune.save_table(tab, path)
+    assert autotune.lookup(intrs, k, path) == best
+
+
+# ---------------------------------------------------------------------------- tracking graph
+
+def test_tracking_graph_replay_matches_eager():
+    sc = _room(80_000, seed=33)
+    g = S.rng(34)
+    pose0 = S.random_room_pose(g)
+    truth = S.perturb_pose(pose0, g)
+    intr = S.intrinsics_for(320, 240)
+    dev = raster.DeviceScene.from_numpy(sc)
+    tr = raster.Rasterizer(dev, [intr])
+    tp = raster.poses_tensor([truth])
+    tr.fit(tp)
+    tr.bin_and_sort(tp)
+    tc, td, _ = tr.forward(tp)
+    trk = Tracker(dev, intr, iters=30)
+    p0 = torch.as_tensor(pose0, device="cuda")
+    trk.set_frame(p0, tc, td)
+    eager = trk.run_eager().clone()
+    loss_eager = trk.loss_hist.clone()
+    trk.check()
+    trk.set_frame(p0, tc, td)
+    trk.capture()
+    trk.set_frame(p0, tc, td)
+    for rep in range(3):                       # replay several times with eager work between
+        trk.set_frame(p0, tc, td)
+        out = trk.replay().clone()
+        torch.cuda.synchronize()
+        trk.check()
+        _say(f"  replay {rep}: |pose - eager| = {np.abs(out.cpu().numpy() - eager.cpu().numpy()).max():.2e}")
+        np.testing.assert_allclose(out.cpu().numpy(), eager.cpu().numpy(), atol=1e-5)
+        np.testing.assert_allclose(trk.loss_hist.cpu().numpy(), loss_eager.cpu().numpy(), rtol=1e-4, atol=1e-8)
+    lh = loss_eager.cpu().numpy()
+    _say(f"  loss {lh[0]:.5f} -> {lh[-1]:.5f}")
+    assert lh[-1] < lh[0]
+
+
+# ---------------------------------------------------------------------------- serving
+
+def test_served_results_equal_alone_results():
+    sc = _room(100_000, seed=35)
+    dev = raster.DeviceScene.from_numpy(sc)
+    queries = S.serving_queries(36, 24, qps=1e6)
+    ex = GpuExecutor(dev, pairs_per_tile=20.0)        # small estimate: exercises the overflow retry
+    srv = Server(ex, n_slots=3, mem_budget=3 << 30, max_batch_views=6)
+    srv.start()
+    try:
+        reqs = [srv.submit(Request(i, intr, pose)) for i, (_, intr, pose) in enumerate(queries)]
+        srv.drain()
+    finally:
+        srv.stop()
+    assert all(r.error is None for r in reqs), [r.error for r in reqs if r.error]
+    _say(f"  stats {srv.stats()} retries {ex.retries}")
+    for r in reqs:
+        c, d, _ = G.render(*G.make(sc, [r.intr], [r.pose]))
+        W, H = r.intr.width, r.intr.height
+        assert np.array_equal(r.color.cpu().numpy().reshape(-1), c.reshape(-1)), r.rid
+        assert np.array_equal(r.depth.cpu().numpy().reshape(-1), d.reshape(-1)), r.rid
+
+
+def test_serving_under_a_tight_memory_budget():
+    sc = _room(50_000, seed=37)
+    dev = raster.DeviceScene.from_numpy(sc)
+    queries = S.serving_queries(38, 10, qps=1e6)
+    ex = GpuExecutor(dev)
+    one = max(ex.estimate_bytes(Request(0, q[1], q[2])) for q in queries)
+    srv = Server(ex, n_slots=2, mem_budget=one + 1, max_batch_views=4)
+    srv.start()
+    try:
+        reqs = [srv.submit(Request(i, intr, pose)) for i, (_, intr, pose) in enumerate(queries)]
+        srv.drain()
+    finally:
+        srv.stop()
+    assert all(r.error is None for r in reqs)
+    assert srv.peak_used <= one + 1
+    assert srv.stats()["peak_inflight_batches"] >= 1
