@@ -58,6 +58,25 @@ def lib():
     return _lib
 
 
+class use_library:
+    """Context manager that points this wrapper at another build of the oracle (used by the
+    mutation tests, which compile deliberately broken copies and check the pins reject them)."""
+
+    def __init__(self, path: str):
+        self.path = path
+
+    def __enter__(self):
+        global _lib, LIB_PATH
+        self.saved = (_lib, LIB_PATH)
+        _lib, LIB_PATH = None, self.path
+        return self
+
+    def __exit__(self, *exc):
+        global _lib, LIB_PATH
+        _lib, LIB_PATH = self.saved
+        return False
+
+
 def _ptr(a: Optional[np.ndarray]):
     return None if a is None else a.ctypes.data_as(C.c_void_p)
 

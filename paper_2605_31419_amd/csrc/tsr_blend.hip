@@ -12,6 +12,12 @@ namespace tsr {
 
 constexpr int kBatch = 64;
 
+// Wave reduction of the 20 per-face gradient sums: 1 = transposing permlane-swap butterfly,
+// 0 = one DPP reduction per value.
+#ifndef TSR_REDUCE_SWAP
+#define TSR_REDUCE_SWAP 0
+#endif
+
 // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so give each XCD a
 // contiguous range of tiles (neighbouring tiles share faces, which then hit the same L2).
 __device__ __forceinline__ int tile_of_block(int n_tiles) {
@@ -232,6 +238,11 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
         }
       }
       if (__ballot(act) == 0) continue;
+#if TSR_REDUCE_SWAP
+      int k_out;
+      const float tot = wave_sum20(acc, &k_out);
+      if (k_out >= 0) unsafeAtomicAdd(&grad_acc[(size_t)sface[j] * kGradDwords + k_out], tot);
+#else
       float sum[kGradDwords];
 #pragma unroll
       for (int k = 0; k < kGradDwords; ++k) sum[k] = wave_sum(acc[k]);
@@ -239,6 +250,7 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
 #pragma unroll
       for (int k = 0; k < kGradDwords; ++k) mine = lane == k ? sum[k] : mine;
       if (lane < kGradDwords) unsafeAtomicAdd(&grad_acc[(size_t)sface[j] * kGradDwords + lane], mine);
+#endif
     }
   }
 }

@@ -79,6 +79,47 @@ __device__ __forceinline__ float wave_sum(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_to_lane63(v)), 63));
 }
 
+// Sum of 16 lanes within each row, left in every lane of the row.
+__device__ __forceinline__ float row_sum16(float v) {
+  v += TSR_DPP(v, 0xB1, 0xF, 0xF);     // quad_perm [1,0,3,2]
+  v += TSR_DPP(v, 0x4E, 0xF, 0xF);     // quad_perm [2,3,0,1]
+  v += TSR_DPP(v, 0x124, 0xF, 0xF);    // row_ror:4
+  v += TSR_DPP(v, 0x128, 0xF, 0xF);    // row_ror:8
+  return v;
+}
+
+// Wave totals of 20 per-lane values with a transposing butterfly (gfx950 permlane swaps):
+//   v_permlane32_swap pairs values (2i, 2i+1): after swap + add, lanes 0-31 hold value 2i and
+//   lanes 32-63 value 2i+1, each summed over the two half-waves (10 vectors);
+//   v_permlane16_swap pairs those vectors again: each 16-lane row then holds one value summed
+//   over all four rows (5 vectors, 4 values each);
+//   a DPP reduction inside each row finishes the sums.
+// Lane 16 r + j (j < 5) returns the total of value index 4 j + {0, 2, 1, 3}[r] in *idx;
+// all other lanes get *idx = -1.  Every lane must be active.
+__device__ __forceinline__ float wave_sum20(const float* v, int* idx) {
+  float s[10];
+#pragma unroll
+  for (int i = 0; i < 10; ++i) {
+    const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[2 * i]), __float_as_uint(v[2 * i + 1]), false,
+                                                    false);
+    s[i] = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+  }
+  float t[5];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(s[2 * j]), __float_as_uint(s[2 * j + 1]), false,
+                                                    false);
+    t[j] = row_sum16(__uint_as_float(p[0]) + __uint_as_float(p[1]));
+  }
+  const int lane = threadIdx.x & 63, r = lane >> 4, j = lane & 15;
+  float out = t[0];
+#pragma unroll
+  for (int k = 1; k < 5; ++k) out = j == k ? t[k] : out;
+  const int rmap = (r == 0) ? 0 : (r == 1 ? 2 : (r == 2 ? 1 : 3));
+  *idx = j < 5 ? 4 * j + rmap : -1;
+  return out;
+}
+
 __device__ __forceinline__ int wave_max_int(int v) {
   for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
   return v;

@@ -88,6 +88,58 @@ def test_gradients_match_finite_differences(sigma, seed):
     print(f"sigma={sigma}: {checked} parameters checked, {rejected} rejected, worst rel err {worst:.2e}")
 
 
+def _stacked_scene(seed, n=6, w=24, h=20, f=20.0):
+    """Large faces stacked in depth over the whole image (every pixel sees several layers)."""
+    g = np.random.default_rng(seed)
+    intr = S.Intrinsics(w, h, f, f, (w - 1) / 2.0, (h - 1) / 2.0)
+    verts = []
+    for i in range(n):
+        z = 1.0 + 0.4 * i + g.uniform(0, 0.1)
+        c = g.uniform(-0.1, 0.1, size=2)
+        ang = g.uniform(0, 2 * np.pi) + np.array([0, 2.1, 4.2])
+        rad = z * g.uniform(0.9, 1.3)
+        verts.append(np.stack([c[0] + rad * np.cos(ang), c[1] + rad * np.sin(ang), z + g.uniform(-0.05, 0.05, 3)], 1))
+    sc = S.Scene(np.ascontiguousarray(np.concatenate(verts).T), g.uniform(0, 1, (3, 3 * n)),
+                 g.uniform(0.3, 0.8, 3 * n), None)
+    return sc, intr
+
+
+@pytest.mark.parametrize("sigma", [1.0, 2.0])
+def test_gradients_with_deep_overlap(sigma):
+    """Finite differences where every pixel composites several layers, so the behind-colour
+    accumulation of the backward (eq. 4 derivative) is exercised beyond one layer."""
+    sc, intr = _stacked_scene(5)
+    g = np.random.default_rng(5)
+    pose = _random_pose(g)
+    P = intr.width * intr.height
+    wC, wD, wT = g.normal(size=(3, P)), g.normal(size=P), g.normal(size=P)
+    gpos, gcol, gopa, gpose = O.backward(sc, pose, intr, wC, wD, wT, sigma=sigma)
+    C, D, T = O.render(sc, pose, intr, sigma=sigma)
+    assert (T < 0.7).mean() > 0.5                        # deep overlap indeed
+    base = O.state(sc, pose, intr, sigma=sigma)
+    checked = 0
+    for k in range(sc.n_vertices):
+        for (arr, an) in ((sc.col, gcol), (sc.pos, gpos)):
+            for a in range(3):
+                def mk(h, arr=arr, a=a, k=k):
+                    x = arr.copy(); x[a, k] += h
+                    return S.Scene(x, sc.col, sc.opa) if arr is sc.pos else S.Scene(sc.pos, x, sc.opa)
+                sp, sm = mk(H), mk(-H)
+                if not (np.array_equal(O.state(sp, pose, intr, sigma=sigma), base)
+                        and np.array_equal(O.state(sm, pose, intr, sigma=sigma), base)):
+                    continue
+                num = (_loss(sp, pose, intr, sigma, wC, wD, wT) - _loss(sm, pose, intr, sigma, wC, wD, wT)) / (2 * H)
+                assert abs(num - an[a, k]) <= 1e-5 * abs(an[a, k]) + 1e-7 * np.abs(an).max(), (k, a, num, an[a, k])
+                checked += 1
+    for k in range(sc.n_vertices):
+        def mko(h, k=k):
+            o = sc.opa.copy(); o[k] += h
+            return S.Scene(sc.pos, sc.col, o)
+        num = (_loss(mko(H), pose, intr, sigma, wC, wD, wT) - _loss(mko(-H), pose, intr, sigma, wC, wD, wT)) / (2 * H)
+        assert abs(num - gopa[k]) <= 1e-5 * abs(gopa[k]) + 1e-7 * np.abs(gopa).max()
+    assert checked > 50
+
+
 @pytest.mark.parametrize("seed", [7, 8])
 def test_pose_gradient_identities(seed):
     """Eq. (7): dL/drho = sum_i dL/dv_C,i = R sum_i dL/dv_W,i and dL/dtheta = sum_i v_C,i x

@@ -186,6 +186,45 @@ def test_single_frontal_opaque_face():
     np.testing.assert_allclose(C, np.array([[0.3], [0.5], [0.9]]) * I[None], atol=1e-12)
 
 
+def test_depth_order_uses_the_centroid_depth():
+    """Eq. (4) composites in depth order with z_F the mean vertex depth: a face tilted toward
+    the camera (one vertex at 1 m, two at 3 m; z_F = 7/3) lies behind a fronto-parallel face at
+    2 m even though its first vertex is nearer.  The sort key is float32(z_F)."""
+    cam = unit_cam()
+    big = [(2.0, 2.0), (30.0, 2.0), (2.0, 30.0)]
+    tilted = np.array([[big[0][0] * 1.0, big[0][1] * 1.0, 1.0], [big[1][0] * 3.0, big[1][1] * 3.0, 3.0],
+                       [big[2][0] * 3.0, big[2][1] * 3.0, 3.0]])
+    flat = np.array([[x * 2.0, y * 2.0, 2.0] for x, y in big])
+    sc = plain_scene(np.stack([tilted, flat]), col=np.array([[[1, 0, 0]] * 3, [[0, 1, 0]] * 3]),
+                     opa=np.ones((2, 3)))
+    q, f, rect, tiles = O.project(sc, IDENTITY, cam)
+    np.testing.assert_allclose(f[2], [7.0 / 3.0, 2.0], rtol=1e-12)
+    assert np.all(f[3] == f[2].astype(np.float32))
+    C, D, T = O.render(sc, IDENTITY, cam, pixels=_pix(cam, [(8, 9)]))
+    assert C[1, 0] > 0.5 and C[0, 0] < C[1, 0]        # the flat (green) face is in front
+
+
+def test_three_layer_compositing():
+    """Eq. (4) with three stacked layers: C = c1 a1 + c2 a2 (1 - a1) + c3 a3 (1 - a1)(1 - a2)."""
+    cam = unit_cam()
+    big = [(2.0, 2.0), (30.0, 2.0), (2.0, 30.0)]
+    vs, cols, opas = [], [], []
+    for z, c, o in [(1.0, [1, 0, 0], 0.5), (2.0, [0, 1, 0], 0.6), (3.0, [0, 0, 1], 0.7)]:
+        vs.append(np.array([[x * z, y * z, z] for x, y in big]))
+        cols.append([c] * 3)
+        opas.append([o] * 3)
+    p = _pix(cam, [(8, 9)])
+    a = []
+    for i in range(3):
+        _, _, T = O.render(plain_scene(vs[i][None], col=np.array([cols[i]]), opa=np.array([opas[i]])), IDENTITY,
+                           cam, pixels=p)
+        a.append(1 - T[0])
+    C, D, T = O.render(plain_scene(np.stack(vs[::-1]), col=np.array(cols[::-1]), opa=np.array(opas[::-1])),
+                       IDENTITY, cam, pixels=p)
+    np.testing.assert_allclose(C[:, 0], [a[0], a[1] * (1 - a[0]), a[2] * (1 - a[0]) * (1 - a[1])], atol=1e-12)
+    np.testing.assert_allclose(D[0], 1 * a[0] + 2 * a[1] * (1 - a[0]) + 3 * a[2] * (1 - a[0]) * (1 - a[1]), atol=1e-12)
+
+
 def test_face_order_in_arrays_is_irrelevant():
     """Eq. (4) sorts by depth: permuting the faces in the input arrays changes nothing
     (no exact depth ties in this scene)."""
