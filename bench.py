@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=8192)
     ap.add_argument("--profile-steps", type=int, default=10)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 256 MiB device-to-device copy (counter calibration in profiler runs)")
+    ap.add_argument("--only-single", action="store_true", help="skip the unfused and batched legs")
     return ap.parse_args()
 
 
@@ -202,6 +205,27 @@ def main():
     ktimes, klaunch = kernel_times(single.step, args.profile_steps)
     log(f"[bench] kernels (ms): {json.dumps({k: round(v, 4) for k, v in ktimes.items()})}")
 
+    copy_gbs = None
+    if args.copy_calibration:
+        n = 256 << 20
+        src = torch.empty(n // 4, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(5):
+            dst.copy_(src)
+        b.record()
+        torch.cuda.synchronize()
+        copy_gbs = 2 * n * 5 / (a.elapsed_time(b) * 1e-3) / 1e9
+        log(f"[bench] device copy of 256 MiB: {copy_gbs:.0f} GB/s (read + write)")
+        del src, dst
+    if args.only_single:
+        print(json.dumps({"metric": "fwd+bwd Mpix/s (single view only)", "value": mpix, "unit": "Mpix/s",
+                          "ms_per_step": ms, "kernels_ms": ktimes, "copy_gbs": copy_gbs}), flush=True)
+        return
+
     # unfused path (forward, then backward from external per-pixel seeds)
     gc = torch.full((3 * single.pixels,), 1e-6, device="cuda")
     gd = torch.full((single.pixels,), 1e-7, device="cuda")
@@ -256,6 +280,7 @@ def main():
         "unfused": {"ms_per_step": ms_unf, "mpix_s": single.pixels / (ms_unf * 1e-3) / 1e6,
                     "kernels_ms": {k: round(v, 4) for k, v in kt_unf.items()}},
         "batched": batched,
+        "copy_gbs": copy_gbs,
     }
     if not args.no_cpu_baseline:
         log(f"[bench] oracle on {args.cpu_pixels} pixels")

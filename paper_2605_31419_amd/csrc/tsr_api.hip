@@ -143,7 +143,10 @@ WsLayout layout(const ViewTable& vt, int64_t cap) {
   L.counts = o; o = align_up(o + sizeof(uint32_t) * nf);
   L.records = o; o = align_up(o + sizeof(float) * tsr::kRecDwords * nf);
   L.grad_acc = o; o = align_up(o + sizeof(float) * tsr::kGradDwords * nf);
-  L.tile_cnt = o; o = align_up(o + sizeof(uint32_t) * vt.n_tiles);
+  L.tile_cnt = o;
+  L.vis_cnt = o + sizeof(uint32_t) * vt.n_tiles;
+  o = align_up(o + sizeof(uint32_t) * (vt.n_tiles + vt.n_views));
+  L.vis_list = o; o = align_up(o + sizeof(uint32_t) * nf);
   L.ranges = o; o = align_up(o + sizeof(uint32_t) * 2 * vt.n_tiles);
   L.order = o; o = align_up(o + sizeof(int32_t) * vt.n_tiles);
   L.order_hist = o; o = align_up(o + sizeof(uint32_t) * 2 * tsr::kOrderBuckets);

@@ -128,7 +128,10 @@ __device__ __forceinline__ void wave_expand(int cnt, F&& fn) {
 // One thread per (view, face); faces are numbered g = v * M + m.
 __global__ __launch_bounds__(256) void k_project(tsr_scene_dev sc, const float* __restrict__ poses, ViewTable vt,
                                                  float z_near, float r_min, uint32_t* __restrict__ counts,
-                                                 float* __restrict__ records, uint32_t* __restrict__ tile_cnt) {
+                                                 float* __restrict__ records, uint32_t* __restrict__ tile_cnt,
+                                                 uint32_t* __restrict__ vis_cnt, uint32_t* __restrict__ vis_list) {
+  __shared__ uint32_t s_wave[4];
+  __shared__ uint32_t s_base;
   const int64_t M = vt.n_faces;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = g < (int64_t)vt.n_views * M;
@@ -190,6 +193,32 @@ __global__ __launch_bounds__(256) void k_project(tsr_scene_dev sc, const float* 
         dst[i] = make_float4(rec[4 * i], rec[4 * i + 1], rec[4 * i + 2], rec[4 * i + 3]);
     }
     counts[g] = (uint32_t)ntiles;
+  }
+  // ---- visible-face list of each view: ballot within the wave, one LDS add per wave, one
+  //      global atomic per workgroup (workgroups straddling two views use per-lane atomics)
+  {
+    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t g1 = min(g0 + (int64_t)blockDim.x, (int64_t)vt.n_views * M) - 1;
+    const int vlo = (int)(g0 / M), vhi = (int)(g1 / M);
+    const bool vis = ntiles > 0;
+    if (vlo == vhi) {
+      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+      const unsigned long long mask = __ballot(vis);
+      const uint32_t below = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+      if (lane == 0) s_wave[wave] = (uint32_t)__popcll(mask);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        const uint32_t tot = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+        s_base = tot ? atomicAdd(&vis_cnt[vlo], tot) : 0u;
+      }
+      __syncthreads();
+      uint32_t off = s_base;
+      for (int w = 0; w < wave; ++w) off += s_wave[w];
+      if (vis) vis_list[(int64_t)vlo * M + off + below] = (uint32_t)(g - (int64_t)vlo * M);
+    } else if (vis) {
+      const int v = (int)(g / M);
+      vis_list[(int64_t)v * M + atomicAdd(&vis_cnt[v], 1u)] = (uint32_t)(g - (int64_t)v * M);
+    }
   }
   // ---- per-tile counts: small faces loop on their own lane, large ones are spread
   const int maxc = wave_max_int(ntiles);
@@ -391,10 +420,14 @@ hipError_t launch_bin(const tsr_scene_dev& sc, const float* poses, const ViewTab
   uint64_t* temp = reinterpret_cast<uint64_t*>(ws + L.temp);
   const int64_t nf = (int64_t)vt.n_views * vt.n_faces;
 
-  TSR_LAUNCH("fill_tiles", k_fill_u32, dim3(grid_for(vt.n_tiles, 256)), dim3(256), 0, st, tile_cnt, (int64_t)vt.n_tiles, 0u);
+  uint32_t* vis_cnt = reinterpret_cast<uint32_t*>(ws + L.vis_cnt);
+  uint32_t* vis_list = reinterpret_cast<uint32_t*>(ws + L.vis_list);
+  // tile counters and per-view visible counters are contiguous: one fill
+  TSR_LAUNCH("fill_tiles", k_fill_u32, dim3(grid_for(vt.n_tiles + vt.n_views, 256)), dim3(256), 0, st, tile_cnt,
+             (int64_t)(vt.n_tiles + vt.n_views), 0u);
   if (nf > 0)
     TSR_LAUNCH("project", k_project, dim3(grid_for(nf, 256)), dim3(256), 0, st, sc, poses, vt, p.z_near, p.r_min, counts,
-                       records, tile_cnt);
+                       records, tile_cnt, vis_cnt, vis_list);
   TSR_LAUNCH("scan_tiles", k_scan_tiles, dim3(1), dim3(1024), 0, st, tile_cnt, ranges, vt.n_tiles,
                      sort ? L.capacity : (int64_t)0x7fffffffffffffffll, K, overflow);
   if (!sort) return hipGetLastError();

@@ -101,11 +101,17 @@ __device__ __forceinline__ void stage_batch(const float* __restrict__ records, c
   if (threadIdx.x < n) sface[threadIdx.x] = (uint32_t)pairs[b0 + threadIdx.x];
 }
 
-// Wave-uniform test: does the face's pixel rectangle meet this wave's 8x8 quadrant?
-__device__ __forceinline__ bool rect_hits_quadrant(const float* r, int bx, int by) {
-  const int u0 = uniform_int(__float_as_int(r[kRecU0])), v0 = uniform_int(__float_as_int(r[kRecV0]));
-  const int u1 = uniform_int(__float_as_int(r[kRecU1])), v1 = uniform_int(__float_as_int(r[kRecV1]));
-  return !(u1 < bx || u0 > bx + 7 || v1 < by || v0 > by + 7);
+// Faces of the staged batch whose pixel rectangle meets this wave's 8x8 quadrant: lane j
+// tests face j, one ballot gives the wave-uniform 64-bit mask the walks iterate over.
+__device__ __forceinline__ unsigned long long batch_hit_mask(const float4* srec, int n, int bx, int by) {
+  const int j = threadIdx.x & 63;
+  bool hit = false;
+  if (j < n) {
+    const float4 rc = srec[j * 6 + kRecU0 / 4];
+    const int u0 = __float_as_int(rc.x), v0 = __float_as_int(rc.y), u1 = __float_as_int(rc.z), v1 = __float_as_int(rc.w);
+    hit = !(u1 < bx || u0 > bx + 7 || v1 < by || v0 > by + 7);
+  }
+  return __ballot(hit);
 }
 
 struct FwdState {
@@ -129,9 +135,11 @@ __device__ __forceinline__ void forward_walk(const TileCtx& c, const float* __re
     __syncthreads();
     if (__ballot(!done) == 0) continue;
     const float dxb = (float)c.px, dyb = (float)c.py;
-    for (int j = 0; j < n; ++j) {
+    unsigned long long mask = batch_hit_mask(srec, n, c.bx, c.by);
+    while (mask) {
+      const int j = __builtin_ctzll(mask);
+      mask &= mask - 1;
       const float* r = reinterpret_cast<const float*>(&srec[j * 6]);
-      if (!rect_hits_quadrant(r, c.bx, c.by)) continue;
       if (!done) {
         PixelEval e;
         const float dx = dxb - (float)__float_as_int(r[kRecU0]);
@@ -186,11 +194,13 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
     stage_batch(records, pairs, (uint32_t)b0, n, srec, sface);
     __syncthreads();
     if (b0 > wlast) continue;
-    for (int j = n - 1; j >= 0; --j) {
+    unsigned long long mask = batch_hit_mask(srec, n, c.bx, c.by);
+    if (wlast - b0 < 63) mask &= (2ull << (wlast - b0)) - 1ull;     // faces after the wave's last
+    while (mask) {
+      const int j = 63 - __builtin_clzll(mask);
+      mask &= ~(1ull << j);
       const int idx = b0 + j;
-      if (idx > wlast) continue;
       const float* r = reinterpret_cast<const float*>(&srec[j * 6]);
-      if (!rect_hits_quadrant(r, c.bx, c.by)) continue;
       float acc[kGradDwords];
 #pragma unroll
       for (int k = 0; k < kGradDwords; ++k) acc[k] = 0.f;
@@ -404,204 +414,203 @@ __device__ __forceinline__ void load_pose_d(const float* __restrict__ poses, int
 }
 
 __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float* __restrict__ poses, ViewTable vt,
-                                                  const uint32_t* __restrict__ counts, const float* __restrict__ records,
+                                                  const uint32_t* __restrict__ vis_cnt,
+                                                  const uint32_t* __restrict__ vis_list, const float* __restrict__ records,
                                                   const float* __restrict__ grad_acc, float* __restrict__ grad_pos,
                                                   float* __restrict__ grad_col, float* __restrict__ grad_opa,
                                                   double* __restrict__ pose_acc, int atomic_vertices) {
   __shared__ double red[6][4];
   const int64_t M = vt.n_faces;
   const int64_t N = sc.n_vertices;
-  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool live = m < M;
-  int64_t vid[3] = {0, 0, 0};
-  if (live) {
+  const int v = blockIdx.y;
+  const uint32_t cnt = vis_cnt[v];
+  if ((uint32_t)blockIdx.x * blockDim.x >= cnt) return;             // whole workgroup past the list
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  double pose6[6] = {0, 0, 0, 0, 0, 0};
+  if (i < cnt) {
+    const int64_t m = (int64_t)vis_list[(int64_t)v * M + i];
+    const int64_t g = (int64_t)v * M + m;
+    int64_t vid[3];
     if (sc.faces) {
       for (int k = 0; k < 3; ++k) vid[k] = (int64_t)sc.faces[3 * m + k];
     } else {
       for (int k = 0; k < 3; ++k) vid[k] = 3 * m + k;
     }
-  }
-  double gW[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};   // dL/dv_W per vertex
-  double gcolv[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // dL/dc per vertex, channel
-  double gop = 0.0;
-  bool any = false;
-  for (int v = 0; v < vt.n_views; ++v) {
-    double pose6[6] = {0, 0, 0, 0, 0, 0};
-    const int64_t g = (int64_t)v * M + m;
-    if (live && counts[g] > 0) {
-      any = true;
-      const float* A = grad_acc + g * kGradDwords;
-      const float* rec = records + g * kRecDwords;
-      const ViewDesc vd = vt.v[v];
-      double R[9], t[3];
-      load_pose_d(poses, v, R, t);
-      double vc[3][3], q[3][2];
-      for (int k = 0; k < 3; ++k) {
-        const double w0 = (double)sc.pos[vid[k]], w1 = (double)sc.pos[N + vid[k]], w2 = (double)sc.pos[2 * N + vid[k]];
-        for (int a = 0; a < 3; ++a) vc[k][a] = R[3 * a] * w0 + R[3 * a + 1] * w1 + R[3 * a + 2] * w2 + t[a];
-        q[k][0] = (double)vd.fx * vc[k][0] / vc[k][2] + (double)vd.cx;
-        q[k][1] = (double)vd.fy * vc[k][1] / vc[k][2] + (double)vd.cy;
+    double gW[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};   // dL/dv_W per vertex
+    double gcolv[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // dL/dc per vertex, channel
+    const float* A = grad_acc + g * kGradDwords;
+    const float* rec = records + g * kRecDwords;
+    const ViewDesc vd = vt.v[v];
+    double R[9], t[3];
+    load_pose_d(poses, v, R, t);
+    double vc[3][3], q[3][2];
+    for (int k = 0; k < 3; ++k) {
+      const double w0 = (double)sc.pos[vid[k]], w1 = (double)sc.pos[N + vid[k]], w2 = (double)sc.pos[2 * N + vid[k]];
+      for (int a = 0; a < 3; ++a) vc[k][a] = R[3 * a] * w0 + R[3 * a + 1] * w1 + R[3 * a + 2] * w2 + t[a];
+      q[k][0] = (double)vd.fx * vc[k][0] / vc[k][2] + (double)vd.cx;
+      q[k][1] = (double)vd.fy * vc[k][1] / vc[k][2] + (double)vd.cy;
+    }
+    // ---- forward quantities of the setup
+    const double a2 = (q[1][0] - q[0][0]) * (q[2][1] - q[0][1]) - (q[1][1] - q[0][1]) * (q[2][0] - q[0][0]);
+    const double so = a2 >= 0.0 ? 1.0 : -1.0;
+    const double area = fabs(a2);
+    double e[3][2], len[3], n[3][2], perim = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const int k1 = (k + 1) % 3;
+      e[k][0] = q[k1][0] - q[k][0];
+      e[k][1] = q[k1][1] - q[k][1];
+      len[k] = sqrt(e[k][0] * e[k][0] + e[k][1] * e[k][1]);
+      perim += len[k];
+    }
+    const double r = area / perim;
+    for (int k = 0; k < 3; ++k) {
+      n[k][0] = so * e[k][1] / len[k];
+      n[k][1] = -so * e[k][0] / len[k];
+    }
+    const double U0 = (double)__float_as_int(rec[kRecU0]), V0 = (double)__float_as_int(rec[kRecV0]);
+    double ca[3], cb[3], cc[3];       // edge coefficients a_k, b_k, c_k
+    for (int k = 0; k < 3; ++k) {
+      ca[k] = -n[k][0] / r;
+      cb[k] = -n[k][1] / r;
+      cc[k] = -(n[k][0] * (U0 - q[k][0]) + n[k][1] * (V0 - q[k][1])) / r;
+    }
+    double colv[3][3];                // vertex colours [vertex][ch]
+    for (int k = 0; k < 3; ++k)
+      for (int ch = 0; ch < 3; ++ch) colv[k][ch] = (double)sc.col[ch * N + vid[k]];
+    // ---- reverse: colour planes P_ch = sum_k beta_k,ch a_k (same for Q with b, R with c),
+    //      beta_k,ch = len_k col[opp(k)][ch] / perim
+    double gA[3], gB[3], gCc[3], glen[3] = {0, 0, 0}, gperim = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      gA[k] = (double)A[kGEdge + 3 * k];
+      gB[k] = (double)A[kGEdge + 3 * k + 1];
+      gCc[k] = (double)A[kGEdge + 3 * k + 2];
+    }
+    for (int k = 0; k < 3; ++k) {
+      const int o = (k + 2) % 3;
+      for (int ch = 0; ch < 3; ++ch) {
+        const double GP = (double)A[kGCol + 3 * ch], GQ = (double)A[kGCol + 3 * ch + 1], GR = (double)A[kGCol + 3 * ch + 2];
+        const double beta = len[k] * colv[o][ch] / perim;
+        gA[k] += beta * GP;
+        gB[k] += beta * GQ;
+        gCc[k] += beta * GR;
+        const double gbeta = GP * ca[k] + GQ * cb[k] + GR * cc[k];
+        gcolv[o][ch] += gbeta * len[k] / perim;
+        glen[k] += gbeta * colv[o][ch] / perim;
+        gperim -= gbeta * beta / perim;
       }
-      // ---- forward quantities of the setup
-      const double a2 = (q[1][0] - q[0][0]) * (q[2][1] - q[0][1]) - (q[1][1] - q[0][1]) * (q[2][0] - q[0][0]);
-      const double so = a2 >= 0.0 ? 1.0 : -1.0;
-      const double area = fabs(a2);
-      double e[3][2], len[3], n[3][2], perim = 0.0;
+    }
+    // ---- reverse: edge coefficients a = -n_x / r, b = -n_y / r, c = -n.(anchor - q_k) / r
+    double gq[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+    double gr = 0.0;
+    double gn[3][2];
+    for (int k = 0; k < 3; ++k) {
+      gn[k][0] = -(gA[k] + gCc[k] * (U0 - q[k][0])) / r;
+      gn[k][1] = -(gB[k] + gCc[k] * (V0 - q[k][1])) / r;
+      gq[k][0] += gCc[k] * n[k][0] / r;
+      gq[k][1] += gCc[k] * n[k][1] / r;
+      gr -= (gA[k] * ca[k] + gB[k] * cb[k] + gCc[k] * cc[k]) / r;
+    }
+    // ---- n_k = so (e_y, -e_x) / |e|
+    double ge[3][2];
+    for (int k = 0; k < 3; ++k) {
+      const double dot = gn[k][0] * n[k][0] + gn[k][1] * n[k][1];
+      const double gmx = (gn[k][0] - dot * n[k][0]) / len[k];
+      const double gmy = (gn[k][1] - dot * n[k][1]) / len[k];
+      ge[k][0] = -so * gmy;
+      ge[k][1] = so * gmx;
+    }
+    // ---- r = area / perim; perim = sum len
+    const double garea = gr / perim;
+    gperim += -gr * r / perim;
+    for (int k = 0; k < 3; ++k) {
+      glen[k] += gperim;
+      ge[k][0] += glen[k] * e[k][0] / len[k];
+      ge[k][1] += glen[k] * e[k][1] / len[k];
+    }
+    // ---- area = so * a2, a2 = (q1 - q0) x (q2 - q0)
+    const double ga2 = so * garea;
+    gq[1][0] += ga2 * (q[2][1] - q[0][1]);
+    gq[1][1] -= ga2 * (q[2][0] - q[0][0]);
+    gq[2][0] -= ga2 * (q[1][1] - q[0][1]);
+    gq[2][1] += ga2 * (q[1][0] - q[0][0]);
+    gq[0][0] -= ga2 * ((q[2][1] - q[0][1]) - (q[1][1] - q[0][1]));
+    gq[0][1] -= ga2 * ((q[1][0] - q[0][0]) - (q[2][0] - q[0][0]));
+    // ---- e_k = q_{k+1} - q_k
+    for (int k = 0; k < 3; ++k) {
+      const int k1 = (k + 1) % 3;
+      gq[k1][0] += ge[k][0];
+      gq[k1][1] += ge[k][1];
+      gq[k][0] -= ge[k][0];
+      gq[k][1] -= ge[k][1];
+    }
+    // ---- projection and depth: q = (fx x / z + cx, fy y / z + cy), z_F = mean z
+    const double gz3 = (double)A[kGZ] / 3.0;
+    for (int k = 0; k < 3; ++k) {
+      const double iz = 1.0 / vc[k][2];
+      double gc[3];
+      gc[0] = gq[k][0] * (double)vd.fx * iz;
+      gc[1] = gq[k][1] * (double)vd.fy * iz;
+      gc[2] = -(gq[k][0] * (double)vd.fx * vc[k][0] + gq[k][1] * (double)vd.fy * vc[k][1]) * iz * iz + gz3;
+      for (int a = 0; a < 3; ++a) gW[k][a] += R[a] * gc[0] + R[3 + a] * gc[1] + R[6 + a] * gc[2];
+      pose6[0] += gc[0];
+      pose6[1] += gc[1];
+      pose6[2] += gc[2];
+      pose6[3] += vc[k][1] * gc[2] - vc[k][2] * gc[1];
+      pose6[4] += vc[k][2] * gc[0] - vc[k][0] * gc[2];
+      pose6[5] += vc[k][0] * gc[1] - vc[k][1] * gc[0];
+    }
+    const double gop = (double)A[kGOpa] / 3.0;
+    if (atomic_vertices) {
       for (int k = 0; k < 3; ++k) {
-        const int k1 = (k + 1) % 3;
-        e[k][0] = q[k1][0] - q[k][0];
-        e[k][1] = q[k1][1] - q[k][1];
-        len[k] = sqrt(e[k][0] * e[k][0] + e[k][1] * e[k][1]);
-        perim += len[k];
-      }
-      const double r = area / perim;
-      for (int k = 0; k < 3; ++k) {
-        n[k][0] = so * e[k][1] / len[k];
-        n[k][1] = -so * e[k][0] / len[k];
-      }
-      const double U0 = (double)__float_as_int(rec[kRecU0]), V0 = (double)__float_as_int(rec[kRecV0]);
-      double ca[3], cb[3], cc[3];       // edge coefficients a_k, b_k, c_k
-      for (int k = 0; k < 3; ++k) {
-        ca[k] = -n[k][0] / r;
-        cb[k] = -n[k][1] / r;
-        cc[k] = -(n[k][0] * (U0 - q[k][0]) + n[k][1] * (V0 - q[k][1])) / r;
-      }
-      double colv[3][3];                // vertex colours [vertex][ch]
-      for (int i = 0; i < 3; ++i)
-        for (int ch = 0; ch < 3; ++ch) colv[i][ch] = (double)sc.col[ch * N + vid[i]];
-      // ---- reverse: colour planes P_ch = sum_k beta_k,ch a_k (same for Q with b, R with c),
-      //      beta_k,ch = len_k col[opp(k)][ch] / perim
-      double gA[3], gB[3], gCc[3], glen[3] = {0, 0, 0}, gperim = 0.0;
-      for (int k = 0; k < 3; ++k) {
-        gA[k] = (double)A[kGEdge + 3 * k];
-        gB[k] = (double)A[kGEdge + 3 * k + 1];
-        gCc[k] = (double)A[kGEdge + 3 * k + 2];
-      }
-      for (int k = 0; k < 3; ++k) {
-        const int o = (k + 2) % 3;
-        for (int ch = 0; ch < 3; ++ch) {
-          const double GP = (double)A[kGCol + 3 * ch], GQ = (double)A[kGCol + 3 * ch + 1], GR = (double)A[kGCol + 3 * ch + 2];
-          const double beta = len[k] * colv[o][ch] / perim;
-          gA[k] += beta * GP;
-          gB[k] += beta * GQ;
-          gCc[k] += beta * GR;
-          const double gbeta = GP * ca[k] + GQ * cb[k] + GR * cc[k];
-          gcolv[o][ch] += gbeta * len[k] / perim;
-          glen[k] += gbeta * colv[o][ch] / perim;
-          gperim -= gbeta * beta / perim;
+        for (int a = 0; a < 3; ++a) {
+          if (grad_pos) unsafeAtomicAdd(&grad_pos[a * N + vid[k]], (float)gW[k][a]);
+          if (grad_col) unsafeAtomicAdd(&grad_col[a * N + vid[k]], (float)gcolv[k][a]);
         }
+        if (grad_opa) unsafeAtomicAdd(&grad_opa[vid[k]], (float)gop);
       }
-      // ---- reverse: edge coefficients a = -n_x / r, b = -n_y / r, c = -n.(anchor - q_k) / r
-      double gq[3][2] = {{0, 0}, {0, 0}, {0, 0}};
-      double gr = 0.0;
-      double gn[3][2];
+    } else {
       for (int k = 0; k < 3; ++k) {
-        gn[k][0] = -(gA[k] + gCc[k] * (U0 - q[k][0])) / r;
-        gn[k][1] = -(gB[k] + gCc[k] * (V0 - q[k][1])) / r;
-        gq[k][0] += gCc[k] * n[k][0] / r;
-        gq[k][1] += gCc[k] * n[k][1] / r;
-        gr -= (gA[k] * ca[k] + gB[k] * cb[k] + gCc[k] * cc[k]) / r;
+        for (int a = 0; a < 3; ++a) {
+          if (grad_pos) grad_pos[a * N + vid[k]] = (float)gW[k][a];
+          if (grad_col) grad_col[a * N + vid[k]] = (float)gcolv[k][a];
+        }
+        if (grad_opa) grad_opa[vid[k]] = (float)gop;
       }
-      // ---- n_k = so (e_y, -e_x) / |e|
-      double ge[3][2];
-      for (int k = 0; k < 3; ++k) {
-        const double dot = gn[k][0] * n[k][0] + gn[k][1] * n[k][1];
-        const double gmx = (gn[k][0] - dot * n[k][0]) / len[k];
-        const double gmy = (gn[k][1] - dot * n[k][1]) / len[k];
-        ge[k][0] = -so * gmy;
-        ge[k][1] = so * gmx;
-      }
-      // ---- r = area / perim; perim = sum len
-      const double garea = gr / perim;
-      gperim += -gr * r / perim;
-      for (int k = 0; k < 3; ++k) {
-        glen[k] += gperim;
-        ge[k][0] += glen[k] * e[k][0] / len[k];
-        ge[k][1] += glen[k] * e[k][1] / len[k];
-      }
-      // ---- area = so * a2, a2 = (q1 - q0) x (q2 - q0)
-      const double ga2 = so * garea;
-      gq[1][0] += ga2 * (q[2][1] - q[0][1]);
-      gq[1][1] -= ga2 * (q[2][0] - q[0][0]);
-      gq[2][0] -= ga2 * (q[1][1] - q[0][1]);
-      gq[2][1] += ga2 * (q[1][0] - q[0][0]);
-      gq[0][0] -= ga2 * ((q[2][1] - q[0][1]) - (q[1][1] - q[0][1]));
-      gq[0][1] -= ga2 * ((q[1][0] - q[0][0]) - (q[2][0] - q[0][0]));
-      // ---- e_k = q_{k+1} - q_k
-      for (int k = 0; k < 3; ++k) {
-        const int k1 = (k + 1) % 3;
-        gq[k1][0] += ge[k][0];
-        gq[k1][1] += ge[k][1];
-        gq[k][0] -= ge[k][0];
-        gq[k][1] -= ge[k][1];
-      }
-      // ---- projection and depth: q = (fx x / z + cx, fy y / z + cy), z_F = mean z
-      const double gz3 = (double)A[kGZ] / 3.0;
-      for (int k = 0; k < 3; ++k) {
-        const double iz = 1.0 / vc[k][2];
-        double gc[3];
-        gc[0] = gq[k][0] * (double)vd.fx * iz;
-        gc[1] = gq[k][1] * (double)vd.fy * iz;
-        gc[2] = -(gq[k][0] * (double)vd.fx * vc[k][0] + gq[k][1] * (double)vd.fy * vc[k][1]) * iz * iz + gz3;
-        for (int a = 0; a < 3; ++a) gW[k][a] += R[a] * gc[0] + R[3 + a] * gc[1] + R[6 + a] * gc[2];
-        pose6[0] += gc[0];
-        pose6[1] += gc[1];
-        pose6[2] += gc[2];
-        pose6[3] += vc[k][1] * gc[2] - vc[k][2] * gc[1];
-        pose6[4] += vc[k][2] * gc[0] - vc[k][0] * gc[2];
-        pose6[5] += vc[k][0] * gc[1] - vc[k][1] * gc[0];
-      }
-      gop += (double)A[kGOpa] / 3.0;
-    }
-    // ---- per-view pose gradient: block reduction in FP64, one atomic per block and component
-    if (pose_acc) {
-      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-      for (int i = 0; i < 6; ++i) {
-        double x = pose6[i];
-        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-        if (lane == 0) red[i][wave] = x;
-      }
-      __syncthreads();
-      if (threadIdx.x < 6) {
-        const double s = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
-        if (s != 0.0) unsafeAtomicAdd(&pose_acc[6 * v + threadIdx.x], s);
-      }
-      __syncthreads();
     }
   }
-  if (!live) return;
-  if (atomic_vertices) {
-    if (!any) return;
-    for (int k = 0; k < 3; ++k) {
-      for (int a = 0; a < 3; ++a) {
-        if (grad_pos) unsafeAtomicAdd(&grad_pos[a * N + vid[k]], (float)gW[k][a]);
-        if (grad_col) unsafeAtomicAdd(&grad_col[a * N + vid[k]], (float)gcolv[k][a]);
-      }
-      if (grad_opa) unsafeAtomicAdd(&grad_opa[vid[k]], (float)gop);
+  // ---- pose gradient of this view: FP64 block reduction, one atomic per block and component
+  if (pose_acc) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int c = 0; c < 6; ++c) {
+      double x = pose6[c];
+      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+      if (lane == 0) red[c][wave] = x;
     }
-  } else {
-    for (int k = 0; k < 3; ++k) {
-      for (int a = 0; a < 3; ++a) {
-        if (grad_pos) grad_pos[a * N + vid[k]] = (float)gW[k][a];
-        if (grad_col) grad_col[a * N + vid[k]] = (float)gcolv[k][a];
-      }
-      if (grad_opa) grad_opa[vid[k]] = (float)gop;
+    __syncthreads();
+    if (threadIdx.x < 6) {
+      const double t = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
+      if (t != 0.0) unsafeAtomicAdd(&pose_acc[6 * v + threadIdx.x], t);
     }
   }
 }
 
-// Zero the gradient accumulators of faces visible in some view, and the per-view FP64
+// Zero the gradient accumulators of the visible (view, face) pairs, and the per-view FP64
 // pose and loss accumulators.
-__global__ void k_zero_acc(const uint32_t* __restrict__ counts, int64_t nf, float* __restrict__ grad_acc,
-                           double* __restrict__ pose_acc, double* __restrict__ loss_acc, int n_views) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nf && counts[i] > 0) {
-    float4* p = reinterpret_cast<float4*>(grad_acc + i * kGradDwords);
+__global__ void k_zero_acc(ViewTable vt, const uint32_t* __restrict__ vis_cnt, const uint32_t* __restrict__ vis_list,
+                           float* __restrict__ grad_acc, double* __restrict__ pose_acc, double* __restrict__ loss_acc) {
+  const int v = blockIdx.y;
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < vis_cnt[v]) {
+    const int64_t g = (int64_t)v * vt.n_faces + vis_list[(int64_t)v * vt.n_faces + i];
+    float4* p = reinterpret_cast<float4*>(grad_acc + g * kGradDwords);
 #pragma unroll
     for (int k = 0; k < kGradDwords / 4; ++k) p[k] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
-  if (i < 6 * n_views) pose_acc[i] = 0.0;
-  if (i < n_views && loss_acc) loss_acc[i] = 0.0;
+  if (blockIdx.x == 0 && blockIdx.y == 0) {
+    for (int k = threadIdx.x; k < 6 * vt.n_views; k += blockDim.x) pose_acc[k] = 0.0;
+    if (loss_acc)
+      for (int k = threadIdx.x; k < vt.n_views; k += blockDim.x) loss_acc[k] = 0.0;
+  }
 }
 
 // Longest-first tile order: counting sort of the tiles by list length (lengths above
@@ -726,7 +735,8 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
                            float* depth, float* trans, float* loss, float* grad_pos, float* grad_col,
                            float* grad_opa, float* grad_pose, bool fused_train, const TrainSchedule& sched,
                            hipStream_t st) {
-  const uint32_t* counts = reinterpret_cast<const uint32_t*>(ws + L.counts);
+  const uint32_t* vis_cnt = reinterpret_cast<const uint32_t*>(ws + L.vis_cnt);
+  const uint32_t* vis_list = reinterpret_cast<const uint32_t*>(ws + L.vis_list);
   const float* records = reinterpret_cast<const float*>(ws + L.records);
   const uint64_t* pairs = reinterpret_cast<const uint64_t*>(ws + L.pairs);
   const uint32_t* ranges = reinterpret_cast<const uint32_t*>(ws + L.ranges);
@@ -735,10 +745,8 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
   float* grad_acc = reinterpret_cast<float*>(ws + L.grad_acc);
   double* pose_acc = reinterpret_cast<double*>(ws + L.pose_acc);
   double* loss_acc = reinterpret_cast<double*>(ws + L.loss_acc);
-  const int64_t nf = (int64_t)vt.n_views * vt.n_faces;
-  const int64_t zn = nf > 6 * vt.n_views ? nf : 6 * vt.n_views;
-  TSR_LAUNCH("zero_acc", k_zero_acc, dim3(grid_for(zn, 256)), dim3(256), 0, st, counts, nf, grad_acc, pose_acc, loss_acc,
-                     vt.n_views);
+  const dim3 face_grid(grid_for(vt.n_faces > 0 ? vt.n_faces : 1, 256), vt.n_views);
+  TSR_LAUNCH("zero_acc", k_zero_acc, face_grid, dim3(256), 0, st, vt, vis_cnt, vis_list, grad_acc, pose_acc, loss_acc);
   const dim3 block(kBlock);
   const int sm = sigma_mode(p.sigma);
   if (!fused_train) {
@@ -766,16 +774,15 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
     switch (sm) { case 1: TSR_TRAIN(1); break; case 2: TSR_TRAIN(2); break; case 3: TSR_TRAIN(3); break; default: TSR_TRAIN(0); }
 #undef TSR_TRAIN
   }
-  const bool atomic_vertices = sc.faces != nullptr;
-  if (atomic_vertices) {
-    const int64_t N = sc.n_vertices;
-    if (grad_pos) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(1024), dim3(256), 0, st, grad_pos, 3 * N);
-    if (grad_col) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(1024), dim3(256), 0, st, grad_col, 3 * N);
-    if (grad_opa) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(1024), dim3(256), 0, st, grad_opa, N);
-  }
+  // vertex gradients: dense zero fill, then the visible faces write (soup, one view) or add theirs
+  const bool atomic_vertices = sc.faces != nullptr || vt.n_views > 1;
+  const int64_t N = sc.n_vertices;
+  if (grad_pos) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(2048), dim3(256), 0, st, grad_pos, 3 * N);
+  if (grad_col) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(2048), dim3(256), 0, st, grad_col, 3 * N);
+  if (grad_opa) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(2048), dim3(256), 0, st, grad_opa, N);
   if (vt.n_faces > 0)
-    TSR_LAUNCH("face_bwd", k_face_bwd, dim3(grid_for(vt.n_faces, 256)), dim3(256), 0, st, sc, poses, vt, counts, records,
-                       grad_acc, grad_pos, grad_col, grad_opa, grad_pose ? pose_acc : nullptr, atomic_vertices ? 1 : 0);
+    TSR_LAUNCH("face_bwd", k_face_bwd, face_grid, dim3(256), 0, st, sc, poses, vt, vis_cnt, vis_list, records,
+               grad_acc, grad_pos, grad_col, grad_opa, grad_pose ? pose_acc : nullptr, atomic_vertices ? 1 : 0);
   TSR_LAUNCH("finalize", k_finalize, dim3(1), dim3(256), 0, st, pose_acc, grad_pose, loss_acc, loss, vt.n_views);
   return hipGetLastError();
 }

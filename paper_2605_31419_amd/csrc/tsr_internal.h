@@ -31,7 +31,9 @@ struct WsLayout {
   size_t counts;                   // uint32 [V*M]
   size_t records;                  // float  [V*M][24]
   size_t grad_acc;                 // float  [V*M][20]
-  size_t tile_cnt;                 // uint32 [T]
+  size_t tile_cnt;                 // uint32 [T], then uint32 vis_cnt [V] (filled together)
+  size_t vis_cnt;                  // uint32 [V]: visible faces per view
+  size_t vis_list;                 // uint32 [V][M]: face ids visible in each view (first vis_cnt[v])
   size_t ranges;                   // uint32 [T][2]
   size_t order;                    // int32  [T] tile schedule (longest lists first)
   size_t order_hist;               // uint32 [2][kOrderBuckets]
