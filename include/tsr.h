@@ -19,7 +19,7 @@
  *   - `stream` is a hipStream_t (NULL = the default stream).  Every call only enqueues work
  *     on `stream` and returns without synchronising, except tsr_check / tsr_count.
  *   - The caller owns every buffer, the workspace included; the library never allocates or
- *     frees device memory.  The workspace carries the binning between tsr_bin_and_sort,
+ *     frees device memory.  A new workspace is initialised once with tsr_workspace_init.  The workspace carries the binning between tsr_bin_and_sort,
  *     tsr_render_forward and tsr_render_backward; reusing it for another scene, pose set or
  *     view set invalidates that state.
  *   - A pose is T_CW (world -> camera): 12 floats, R row-major then t.  Camera frame x right,
@@ -128,6 +128,11 @@ typedef struct {
  * (tile, face) pairs.  Workspace size depends only on M, the intrinsics and the capacity. */
 TSR_API int tsr_workspace_size(const tsr_scene *scene, const tsr_intrinsics *intr /* (host)[n_views] */,
                        int n_views, int64_t pair_capacity, size_t *bytes /* (host) out */);
+
+/* Clears the workspace header (pair count, overflow flags, queue counter).  Call once on
+ * every newly allocated workspace before its first use (enqueued on `stream`; a kernel, so
+ * it may also be captured). */
+TSR_API int tsr_workspace_init(void *ws, size_t ws_bytes, void *stream);
 
 /* Projection, per-face setup, tile binning and per-tile depth sort (eqs. 1-3 and the depth
  * order of eq. 4): every visible face is listed in each 16x16 tile its pixel bounding box

@@ -48,6 +48,7 @@ def lib():
         P = C.c_void_p
         _lib.orc_render.argtypes = [P, P, P, P, P, C.c_int64, P, P, P]
         _lib.orc_backward.argtypes = [P, P, P, P, P, C.c_int64, P, P, P, P, P, P, P]
+        _lib.orc_backward_abs.argtypes = [P, P, P, P, P, C.c_int64, P, P, P, P, P, P, P, P, P, P]
         _lib.orc_project.argtypes = [P, P, P, P, P, P, P, P]
         _lib.orc_bin.argtypes = [P, P, P, C.c_int, P, C.c_int64, P, P, P, P, P]
         _lib.orc_l1_seeds.argtypes = [P, P, P, P, C.c_int64, C.c_int64, C.c_double, C.c_double, P, P]
@@ -127,9 +128,11 @@ def render(scene, pose, intr, sigma=1.0, z_near=0.1, r_min=1e-3,
 
 def backward(scene, pose, intr, g_color: np.ndarray, g_depth: np.ndarray,
              g_trans: Optional[np.ndarray] = None, sigma=1.0, z_near=0.1, r_min=1e-3,
-             pixels: Optional[np.ndarray] = None):
+             pixels: Optional[np.ndarray] = None, with_abs: bool = False):
     """Gradients (pos [3,N], col [3,N], opa [N], pose [6]) from the listed pixels' upstream
-    gradients g_color [3,P], g_depth [P], g_trans [P]."""
+    gradients g_color [3,P], g_depth [P], g_trans [P].  With `with_abs`, also returns the
+    per-element sums of absolute per-pixel contributions (pos, col, opa) -- the conditioning
+    that bounds the rounding error of a lower-precision implementation."""
     a = _Args(scene, pose, intr, sigma, z_near, r_min)
     pix = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int64)
     n = a.cam.width * a.cam.height if pix is None else pix.shape[0]
@@ -138,6 +141,14 @@ def backward(scene, pose, intr, g_color: np.ndarray, g_depth: np.ndarray,
     gt = None if g_trans is None else np.ascontiguousarray(np.asarray(g_trans, np.float64).reshape(n))
     N = a.pos.shape[1]
     gpos = np.zeros((3, N)); gcol = np.zeros((3, N)); gopa = np.zeros(N); gpose = np.zeros(6)
+    if with_abs:
+        apos = np.zeros((3, N)); acol = np.zeros((3, N)); aopa = np.zeros(N)
+        rc = lib().orc_backward_abs(C.byref(a.sc), _ptr(a.pose), C.byref(a.cam), C.byref(a.par), _ptr(pix), n,
+                                    _ptr(gc), _ptr(gd), _ptr(gt), _ptr(gpos), _ptr(gcol), _ptr(gopa), _ptr(gpose),
+                                    _ptr(apos), _ptr(acol), _ptr(aopa))
+        if rc:
+            raise ValueError(f"orc_backward_abs failed ({rc})")
+        return gpos, gcol, gopa, gpose, (apos, acol, aopa)
     rc = lib().orc_backward(C.byref(a.sc), _ptr(a.pose), C.byref(a.cam), C.byref(a.par), _ptr(pix), n,
                             _ptr(gc), _ptr(gd), _ptr(gt), _ptr(gpos), _ptr(gcol), _ptr(gopa), _ptr(gpose))
     if rc:

@@ -320,17 +320,22 @@ static void face_local_dual(const face_t *f, const orc_cam *c, double sigma, dou
 /* Backward of the render over the listed pixels, given per-pixel upstream gradients
  * gC[3][npix], gD[npix], gT[npix] (gT may be NULL).  Accumulates (+=) into
  * grad_pos[3][N], grad_col[3][N], grad_opa[N] and grad_pose[6] = (rho, theta); the caller
- * zeroes them.  Only contributions of the listed pixels are included. */
-int orc_backward(const orc_scene *s, const double *pose, const orc_cam *c, const orc_par *p,
-                 const int64_t *pix, int64_t npix, const double *gC, const double *gD,
-                 const double *gT, double *grad_pos, double *grad_col, double *grad_opa,
-                 double *grad_pose) {
+ * zeroes them.  Only contributions of the listed pixels are included.
+ * abs_pos / abs_col / abs_opa (nullable, same shapes) receive the sums over pixels of the
+ * absolute per-pixel contributions: the conditioning of each gradient element, which bounds
+ * the rounding error of any implementation that forms per-pixel terms in lower precision. */
+int orc_backward_abs(const orc_scene *s, const double *pose, const orc_cam *c, const orc_par *p,
+                     const int64_t *pix, int64_t npix, const double *gC, const double *gD,
+                     const double *gT, double *grad_pos, double *grad_col, double *grad_opa,
+                     double *grad_pose, double *abs_pos, double *abs_col, double *abs_opa) {
     int rc = check_args(s, pose, c, p);
     if (rc) return rc;
     int64_t M = s->n_faces, N = s->n_vertices;
     face_t *F = (face_t *)calloc((size_t)(M ? M : 1), sizeof(face_t));
     setup_all(s, pose, c, p, F);
     double *gvc = (double *)calloc((size_t)(M ? M : 1) * 9, sizeof(double)); /* dL/dv_C per face */
+    double Rw[3][3], tw[3];
+    rot(pose, Rw, tw);
     #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t k = 0; k < npix; k++) {
         int64_t id = pix ? pix[k] : k;
@@ -369,16 +374,31 @@ int orc_backward(const orc_scene *s, const double *pose, const orc_cam *c, const
                 #pragma omp atomic
                 gvc[9 * e->m + t] += acc[t];
             }
+            if (abs_pos)
+                for (int k = 0; k < 3; k++)
+                    for (int a = 0; a < 3; a++) {
+                        double w = fabs(Rw[0][a] * acc[3 * k] + Rw[1][a] * acc[3 * k + 1] + Rw[2][a] * acc[3 * k + 2]);
+                        #pragma omp atomic
+                        abs_pos[(int64_t)a * N + f->v[k]] += w;
+                    }
             for (int i = 0; i < 3; i++) {
                 int64_t vi = f->v[i];
                 for (int ch = 0; ch < 3; ch++) {
                     double val = gcol[ch] * e->lam[i];
                     #pragma omp atomic
                     grad_col[(int64_t)ch * N + vi] += val;
+                    if (abs_col) {
+                        #pragma omp atomic
+                        abs_col[(int64_t)ch * N + vi] += fabs(val);
+                    }
                 }
                 double go = galpha * e->I / 3.0;
                 #pragma omp atomic
                 grad_opa[vi] += go;
+                if (abs_opa) {
+                    #pragma omp atomic
+                    abs_opa[vi] += fabs(go);
+                }
             }
             for (int ch = 0; ch < 3; ch++) B[ch] = e->c[ch] * e->alpha + (1.0 - e->alpha) * B[ch];
             BD = e->zf * e->alpha + (1.0 - e->alpha) * BD;
@@ -409,6 +429,14 @@ int orc_backward(const orc_scene *s, const double *pose, const orc_cam *c, const
     free(gvc);
     free(F);
     return ORC_OK;
+}
+
+int orc_backward(const orc_scene *s, const double *pose, const orc_cam *c, const orc_par *p,
+                 const int64_t *pix, int64_t npix, const double *gC, const double *gD,
+                 const double *gT, double *grad_pos, double *grad_col, double *grad_opa,
+                 double *grad_pose) {
+    return orc_backward_abs(s, pose, c, p, pix, npix, gC, gD, gT, grad_pos, grad_col, grad_opa, grad_pose,
+                            NULL, NULL, NULL);
 }
 
 /* L1 loss of eqs. (8)-(10) without the D-SSIM term, as means over pixels (and channels):

@@ -10,7 +10,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libtsr.so")
+# $TSR_LIB selects another build of the same ABI (e.g. a compile-time variant being timed)
+LIB_PATH = os.environ.get("TSR_LIB") or os.path.join(HERE, "libtsr.so")
 
 TSR_OK = 0
 TSR_EINVAL = -1
@@ -20,7 +21,7 @@ TSR_EHIP = -4
 TSR_MAX_VIEWS = 32
 TSR_TILE = 16
 
-EXPORTED = ["tsr_workspace_size", "tsr_bin_and_sort", "tsr_count", "tsr_binning_view", "tsr_render_forward",
+EXPORTED = ["tsr_workspace_size", "tsr_workspace_init", "tsr_bin_and_sort", "tsr_count", "tsr_binning_view", "tsr_render_forward",
             "tsr_render_backward", "tsr_render_train_l1", "tsr_pose_step", "tsr_check", "tsr_last_error",
             "tsr_profile_enable", "tsr_profile_reset", "tsr_profile_read"]
 
@@ -69,6 +70,7 @@ def load() -> C.CDLL:
     lib = C.CDLL(LIB_PATH)
     P, I64, I = C.c_void_p, C.c_int64, C.c_int
     lib.tsr_workspace_size.argtypes = [P, P, I, I64, P]
+    lib.tsr_workspace_init.argtypes = [P, C.c_size_t, P]
     lib.tsr_bin_and_sort.argtypes = [P, P, P, I, P, P, C.c_size_t, P]
     lib.tsr_count.argtypes = [P, P, P, I, P, P, C.c_size_t, P, P]
     lib.tsr_binning_view.argtypes = [P, P, I, P, C.c_size_t, P]

@@ -142,7 +142,7 @@ WsLayout layout(const ViewTable& vt, int64_t cap) {
   L.loss_acc = o; o = align_up(o + sizeof(double) * vt.n_views);
   L.counts = o; o = align_up(o + sizeof(uint32_t) * nf);
   L.records = o; o = align_up(o + sizeof(float) * tsr::kRecDwords * nf);
-  L.grad_acc = o; o = align_up(o + sizeof(float) * tsr::kGradDwords * nf);
+  L.grad_acc = o; o = align_up(o + sizeof(tsr::acc_t) * tsr::kGradDwords * nf);
   L.tile_cnt = o;
   L.vis_cnt = o + sizeof(uint32_t) * vt.n_tiles;
   o = align_up(o + sizeof(uint32_t) * (vt.n_tiles + vt.n_views));
@@ -218,6 +218,13 @@ int tsr_workspace_size(const tsr_scene* scene, const tsr_intrinsics* intr, int n
   if ((rc = build_views(scene, intr, n_views, &vt))) return rc;
   *bytes = layout(vt, pair_capacity).total;
   return TSR_OK;
+}
+
+int tsr_workspace_init(void* ws, size_t ws_bytes, void* stream) {
+  if (!ws) return fail(TSR_EINVAL, "workspace is NULL");
+  if (ws_bytes < 256) return fail(TSR_EWORKSPACE, "workspace of %zu bytes is below the 256-byte header", ws_bytes);
+  hipError_t e = tsr::launch_ws_init(static_cast<char*>(ws), static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_workspace_init launch");
 }
 
 int tsr_bin_and_sort(const tsr_scene* scene, const float* poses, const tsr_intrinsics* intr, int n_views,

@@ -408,6 +408,11 @@ __global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
 
 static inline unsigned grid_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+hipError_t launch_ws_init(char* ws, hipStream_t st) {
+  TSR_LAUNCH("ws_init", k_fill_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t*>(ws), (int64_t)64, 0u);
+  return hipGetLastError();
+}
+
 hipError_t launch_bin(const tsr_scene_dev& sc, const float* poses, const ViewTable& vt, const tsr_params& p,
                       const WsLayout& L, char* ws, bool sort, hipStream_t st) {
   uint32_t* counts = reinterpret_cast<uint32_t*>(ws + L.counts);

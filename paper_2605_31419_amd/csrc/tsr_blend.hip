@@ -15,7 +15,7 @@ constexpr int kBatch = 64;
 // Wave reduction of the 20 per-face gradient sums: 1 = transposing permlane-swap butterfly,
 // 0 = one DPP reduction per value.
 #ifndef TSR_REDUCE_SWAP
-#define TSR_REDUCE_SWAP 0
+#define TSR_REDUCE_SWAP 1
 #endif
 
 // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so give each XCD a
@@ -175,7 +175,7 @@ template <int SM>
 __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __restrict__ records,
                                               const uint64_t* __restrict__ pairs, float sigma, int last, float Tb,
                                               const PixGrad& pg, float4* srec, uint32_t* sface, int* sint,
-                                              float* __restrict__ grad_acc) {
+                                              acc_t* __restrict__ grad_acc) {
   const int lane = threadIdx.x & 63;
   // block-wide highest list position any pixel blended
   if (threadIdx.x == 0) sint[0] = -1;
@@ -251,7 +251,7 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
 #if TSR_REDUCE_SWAP
       int k_out;
       const float tot = wave_sum20(acc, &k_out);
-      if (k_out >= 0) unsafeAtomicAdd(&grad_acc[(size_t)sface[j] * kGradDwords + k_out], tot);
+      if (k_out >= 0) unsafeAtomicAdd(&grad_acc[(size_t)sface[j] * kGradDwords + k_out], (acc_t)tot);
 #else
       float sum[kGradDwords];
 #pragma unroll
@@ -259,7 +259,7 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
       float mine = 0.f;
 #pragma unroll
       for (int k = 0; k < kGradDwords; ++k) mine = lane == k ? sum[k] : mine;
-      if (lane < kGradDwords) unsafeAtomicAdd(&grad_acc[(size_t)sface[j] * kGradDwords + lane], mine);
+      if (lane < kGradDwords) unsafeAtomicAdd(&grad_acc[(size_t)sface[j] * kGradDwords + lane], (acc_t)mine);
 #endif
     }
   }
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(ViewTable vt, const float*
                                                       const uint32_t* __restrict__ ranges, float sigma,
                                                       const int* __restrict__ n_last, const float* __restrict__ t_last,
                                                       const float* __restrict__ gcolor, const float* __restrict__ gdepth,
-                                                      const float* __restrict__ gtrans, float* __restrict__ grad_acc) {
+                                                      const float* __restrict__ gtrans, acc_t* __restrict__ grad_acc) {
   __shared__ float4 srec[kBatch * 6];
   __shared__ uint32_t sface[kBatch];
   __shared__ int sint[4];
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(kBlock) void k_train_fused(ViewTable vt, const floa
                                                         const float* __restrict__ tcolor, const float* __restrict__ tdepth,
                                                         float* __restrict__ color, float* __restrict__ depth,
                                                         float* __restrict__ trans, double* __restrict__ loss_acc,
-                                                        float* __restrict__ grad_acc,
+                                                        acc_t* __restrict__ grad_acc,
                                                         const int* __restrict__ order, int* __restrict__ queue,
                                                         int persistent) {
   __shared__ float4 srec[kBatch * 6];
@@ -416,7 +416,7 @@ __device__ __forceinline__ void load_pose_d(const float* __restrict__ poses, int
 __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float* __restrict__ poses, ViewTable vt,
                                                   const uint32_t* __restrict__ vis_cnt,
                                                   const uint32_t* __restrict__ vis_list, const float* __restrict__ records,
-                                                  const float* __restrict__ grad_acc, float* __restrict__ grad_pos,
+                                                  const acc_t* __restrict__ grad_acc, float* __restrict__ grad_pos,
                                                   float* __restrict__ grad_col, float* __restrict__ grad_opa,
                                                   double* __restrict__ pose_acc, int atomic_vertices) {
   __shared__ double red[6][4];
@@ -438,7 +438,7 @@ __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float*
     }
     double gW[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};   // dL/dv_W per vertex
     double gcolv[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // dL/dc per vertex, channel
-    const float* A = grad_acc + g * kGradDwords;
+    const acc_t* A = grad_acc + g * kGradDwords;
     const float* rec = records + g * kRecDwords;
     const ViewDesc vd = vt.v[v];
     double R[9], t[3];
@@ -597,14 +597,14 @@ __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float*
 // Zero the gradient accumulators of the visible (view, face) pairs, and the per-view FP64
 // pose and loss accumulators.
 __global__ void k_zero_acc(ViewTable vt, const uint32_t* __restrict__ vis_cnt, const uint32_t* __restrict__ vis_list,
-                           float* __restrict__ grad_acc, double* __restrict__ pose_acc, double* __restrict__ loss_acc) {
+                           acc_t* __restrict__ grad_acc, double* __restrict__ pose_acc, double* __restrict__ loss_acc) {
   const int v = blockIdx.y;
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < vis_cnt[v]) {
     const int64_t g = (int64_t)v * vt.n_faces + vis_list[(int64_t)v * vt.n_faces + i];
     float4* p = reinterpret_cast<float4*>(grad_acc + g * kGradDwords);
 #pragma unroll
-    for (int k = 0; k < kGradDwords / 4; ++k) p[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int k = 0; k < (int)(kGradDwords * sizeof(acc_t)) / 16; ++k) p[k] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
   if (blockIdx.x == 0 && blockIdx.y == 0) {
     for (int k = threadIdx.x; k < 6 * vt.n_views; k += blockDim.x) pose_acc[k] = 0.0;
@@ -742,7 +742,7 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
   const uint32_t* ranges = reinterpret_cast<const uint32_t*>(ws + L.ranges);
   const int* n_last = reinterpret_cast<const int*>(ws + L.n_last);
   const float* t_last = reinterpret_cast<const float*>(ws + L.t_last);
-  float* grad_acc = reinterpret_cast<float*>(ws + L.grad_acc);
+  acc_t* grad_acc = reinterpret_cast<acc_t*>(ws + L.grad_acc);
   double* pose_acc = reinterpret_cast<double*>(ws + L.pose_acc);
   double* loss_acc = reinterpret_cast<double*>(ws + L.loss_acc);
   const dim3 face_grid(grid_for(vt.n_faces > 0 ? vt.n_faces : 1, 256), vt.n_views);

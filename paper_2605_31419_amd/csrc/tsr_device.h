@@ -32,9 +32,18 @@ enum RecordField : int {
   kRecDwords = 24
 };
 
-// Per-(view, face) gradient accumulator, 20 floats, filled by the backward blend:
+// Per-(view, face) gradient accumulator, 20 values, filled by the backward blend:
 // dL/d(a_k, b_k, c_k) for the three edges, dL/d(P, Q, R) per channel, dL/do_F, dL/dz_F.
+// Wave partial sums are FP32; they are accumulated across waves and tiles in acc_t.
 enum GradField : int { kGEdge = 0, kGCol = 9, kGOpa = 18, kGZ = 19, kGradDwords = 20 };
+#ifndef TSR_ACC_F64
+#define TSR_ACC_F64 1
+#endif
+#if TSR_ACC_F64
+typedef double acc_t;
+#else
+typedef float acc_t;
+#endif
 
 struct ViewDesc {
   int32_t width, height, tiles_x, tiles_y;

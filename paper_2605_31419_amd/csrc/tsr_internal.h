@@ -67,6 +67,8 @@ void prof_end(int token, const char* name, hipStream_t st);
     ::tsr::prof_end(tsr_tok_, name, st);                                      \
   } while (0)
 
+hipError_t launch_ws_init(char* ws, hipStream_t st);
+
 hipError_t launch_bin(const tsr_scene_dev& sc, const float* poses, const ViewTable& vt, const tsr_params& p,
                       const WsLayout& L, char* ws, bool sort, hipStream_t st);
 

@@ -120,6 +120,7 @@ class Rasterizer:
         nbytes = self.workspace_bytes(capacity)
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.capacity = int(capacity)
+        check(self.lib.tsr_workspace_init(_ptr(self.ws), C.c_size_t(nbytes), _stream()), "tsr_workspace_init")
 
     def _args(self, poses: torch.Tensor):
         return (C.byref(self._cscene), _ptr(poses), self._cintr, self.n_views, C.byref(self._cparams),

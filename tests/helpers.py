@@ -56,14 +56,25 @@ def tiny_scene(seed, n_faces=8, w=32, h=24, f=30.0, z=(1.0, 3.0), size=(0.15, 0.
     return sc, intr
 
 
-def grad_close(g, ref, rel=1e-3, abs_frac=1e-5, name=""):
-    """Norm-wise and element-wise agreement; returns (ok, message, bad_indices)."""
+# Element-wise rounding allowance for an FP32 implementation: a few FP32 ulps (2e-6 relative)
+# of the sum of absolute per-pixel contributions to the element.  When an element is a large
+# cancellation over many pixels (e.g. random-sign upstream gradients on a face covering 1e5+
+# pixels), correlated FP32 rounding of the per-pixel terms is bounded by this, not by |g*|.
+COND_ULPS = 2e-6
+
+
+def grad_close(g, ref, rel=1e-3, abs_frac=1e-5, name="", cond=None):
+    """Norm-wise and element-wise agreement; returns (ok, message, bad_indices).
+    `cond` (optional) holds each element's sum of absolute per-pixel contributions."""
     g = np.asarray(g, np.float64).reshape(-1)
     ref = np.asarray(ref, np.float64).reshape(-1)
     nr = np.linalg.norm(ref)
     inf = np.max(np.abs(ref)) if ref.size else 0.0
     norm_ok = np.linalg.norm(g - ref) <= rel * nr + 1e-30
-    bad = np.nonzero(np.abs(g - ref) > rel * np.abs(ref) + abs_frac * inf + 1e-30)[0]
+    floor = abs_frac * inf + 1e-30
+    if cond is not None:
+        floor = floor + COND_ULPS * np.asarray(cond, np.float64).reshape(-1)
+    bad = np.nonzero(np.abs(g - ref) > rel * np.abs(ref) + floor)[0]
     msg = (f"{name}: |d|/|ref| = {np.linalg.norm(g - ref) / max(nr, 1e-300):.3e}, "
            f"{bad.size} elementwise outliers of {g.size}")
     if bad.size:

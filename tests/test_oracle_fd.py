@@ -187,3 +187,21 @@ def test_pixel_subsets_add_up():
     pb = O.backward(sc, IDENTITY, intr, wC[:, b], wD[b], wT[b], pixels=b)
     for x, y, z in zip(full, pa, pb):
         np.testing.assert_allclose(x, y + z, rtol=1e-10, atol=1e-13)
+
+
+def test_conditioning_sums_bound_the_gradient():
+    """The per-element sums of absolute per-pixel contributions bound |gradient| (triangle
+    inequality) and equal it when a single pixel contributes."""
+    sc, intr = tiny_scene(12, n_faces=15)
+    g = np.random.default_rng(12)
+    P = intr.width * intr.height
+    wC, wD, wT = g.normal(size=(3, P)), g.normal(size=P), g.normal(size=P)
+    gp, gc, go, _, (ap, ac, ao) = O.backward(sc, IDENTITY, intr, wC, wD, wT, with_abs=True)
+    for x, a in ((gp, ap), (gc, ac), (go, ao)):
+        assert np.all(a >= 0) and np.all(np.abs(x) <= a * (1 + 1e-12) + 1e-15)
+    C, D, T = O.render(sc, IDENTITY, intr)
+    pix = np.array([int(np.argmin(T))])
+    gp1, gc1, go1, _, (ap1, ac1, ao1) = O.backward(sc, IDENTITY, intr, wC[:, pix], wD[pix], wT[pix], pixels=pix,
+                                                   with_abs=True)
+    np.testing.assert_allclose(np.abs(gc1), ac1, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(np.abs(go1), ao1, rtol=1e-12, atol=1e-15)
