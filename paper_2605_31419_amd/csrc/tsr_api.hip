@@ -143,10 +143,13 @@ WsLayout layout(const ViewTable& vt, int64_t cap) {
   L.counts = o; o = align_up(o + sizeof(uint32_t) * nf);
   L.records = o; o = align_up(o + sizeof(float) * tsr::kRecDwords * nf);
   L.grad_acc = o; o = align_up(o + sizeof(tsr::acc_t) * tsr::kGradDwords * nf);
+  const int64_t nb = (nf + tsr::kProjBlock - 1) / tsr::kProjBlock;
   L.tile_cnt = o;
-  L.vis_cnt = o + sizeof(uint32_t) * vt.n_tiles;
-  o = align_up(o + sizeof(uint32_t) * (vt.n_tiles + vt.n_views));
-  L.vis_list = o; o = align_up(o + sizeof(uint32_t) * nf);
+  L.long_cnt = o + sizeof(uint32_t) * vt.n_tiles;
+  o = align_up(o + sizeof(uint32_t) * (vt.n_tiles + 1));
+  L.long_list = o; o = align_up(o + sizeof(uint32_t) * vt.n_tiles);
+  L.vis_cnt = o; o = align_up(o + sizeof(uint32_t) * nb);
+  L.vis_list = o; o = align_up(o + sizeof(uint32_t) * nb * tsr::kProjBlock);
   L.ranges = o; o = align_up(o + sizeof(uint32_t) * 2 * vt.n_tiles);
   L.order = o; o = align_up(o + sizeof(int32_t) * vt.n_tiles);
   L.order_hist = o; o = align_up(o + sizeof(uint32_t) * 2 * tsr::kOrderBuckets);

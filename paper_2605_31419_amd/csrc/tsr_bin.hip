@@ -131,7 +131,6 @@ __global__ __launch_bounds__(256) void k_project(tsr_scene_dev sc, const float* 
                                                  float* __restrict__ records, uint32_t* __restrict__ tile_cnt,
                                                  uint32_t* __restrict__ vis_cnt, uint32_t* __restrict__ vis_list) {
   __shared__ uint32_t s_wave[4];
-  __shared__ uint32_t s_base;
   const int64_t M = vt.n_faces;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = g < (int64_t)vt.n_views * M;
@@ -194,31 +193,18 @@ __global__ __launch_bounds__(256) void k_project(tsr_scene_dev sc, const float* 
     }
     counts[g] = (uint32_t)ntiles;
   }
-  // ---- visible-face list of each view: ballot within the wave, one LDS add per wave, one
-  //      global atomic per workgroup (workgroups straddling two views use per-lane atomics)
+  // ---- visible (view, face) ids of this workgroup, compacted into its own segment: a wave
+  //      ballot and per-wave counts in LDS; no global atomics
   {
-    const int64_t g0 = (int64_t)blockIdx.x * blockDim.x;
-    const int64_t g1 = min(g0 + (int64_t)blockDim.x, (int64_t)vt.n_views * M) - 1;
-    const int vlo = (int)(g0 / M), vhi = (int)(g1 / M);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const bool vis = ntiles > 0;
-    if (vlo == vhi) {
-      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-      const unsigned long long mask = __ballot(vis);
-      const uint32_t below = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-      if (lane == 0) s_wave[wave] = (uint32_t)__popcll(mask);
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        const uint32_t tot = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
-        s_base = tot ? atomicAdd(&vis_cnt[vlo], tot) : 0u;
-      }
-      __syncthreads();
-      uint32_t off = s_base;
-      for (int w = 0; w < wave; ++w) off += s_wave[w];
-      if (vis) vis_list[(int64_t)vlo * M + off + below] = (uint32_t)(g - (int64_t)vlo * M);
-    } else if (vis) {
-      const int v = (int)(g / M);
-      vis_list[(int64_t)v * M + atomicAdd(&vis_cnt[v], 1u)] = (uint32_t)(g - (int64_t)v * M);
-    }
+    const unsigned long long mask = __ballot(vis);
+    if (lane == 0) s_wave[wave] = (uint32_t)__popcll(mask);
+    __syncthreads();
+    uint32_t off = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+    for (int w = 0; w < wave; ++w) off += s_wave[w];
+    if (vis) vis_list[(int64_t)blockIdx.x * kProjBlock + off] = (uint32_t)g;
+    if (threadIdx.x == 0) vis_cnt[blockIdx.x] = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
   }
   // ---- per-tile counts: small faces loop on their own lane, large ones are spread
   const int maxc = wave_max_int(ntiles);
@@ -299,11 +285,16 @@ __global__ __launch_bounds__(256) void k_emit(ViewTable vt, const uint32_t* __re
   const int maxc = wave_max_int(ntiles);
   if (maxc == 0) return;
   if (maxc <= 4) {
-    for (int i = 0; i < ntiles; ++i) {
-      const int t = tile_base + (ty0 + i / tw) * tiles_x + tx0 + i % tw;
-      const uint32_t pos = ranges[2 * t] + atomicAdd(&cursor[t], 1u);
-      pairs[pos] = key;
-    }
+    // up to four tiles per lane: issue the cursor atomics back to back, then the stores
+    int t[4];
+    uint32_t slot[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) t[i] = tile_base + (ty0 + i / tw) * tiles_x + tx0 + i % tw;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) slot[i] = i < ntiles ? atomicAdd(&cursor[t[i]], 1u) : 0u;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (i < ntiles) pairs[ranges[2 * t[i]] + slot[i]] = key;
     return;
   }
   const uint32_t key_hi = (uint32_t)(key >> 32), key_lo = (uint32_t)key;
@@ -350,18 +341,93 @@ __device__ __forceinline__ int lower_bound_u64(const uint64_t* a, int n, uint64_
   return lo;
 }
 
-// One workgroup per tile: sort the tile's bucket ascending by (z bits, face).  Buckets up to
-// kSortLds keys are bitonic-sorted in LDS; longer ones are sorted in LDS-sized chunks and
-// merged pairwise in global memory through `temp` (keys are unique, so a rank by binary
-// search places every key).
-__global__ __launch_bounds__(256) void k_tile_sort(const uint32_t* __restrict__ ranges, int n_tiles,
-                                                   uint64_t* __restrict__ pairs, uint64_t* __restrict__ temp) {
-  __shared__ uint64_t s[kSortLds];
-  const int t = blockIdx.x;
+// Register bitonic sort of up to 64 * R keys held by one wave (key e = r * 64 + lane).
+// Exchanges between lanes go through ds_bpermute; exchanges between registers stay local.
+template <int R>
+__device__ __forceinline__ void wave_bitonic(uint64_t (&k)[R]) {
+  const int lane = threadIdx.x & 63;
+  constexpr int N = 64 * R;
+#pragma unroll
+  for (int kk = 2; kk <= N; kk <<= 1) {
+#pragma unroll
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      if (j >= 64) {
+        const int rj = j >> 6;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if (r & rj) continue;
+          const int e = r * 64 + lane;
+          const bool up = (e & kk) == 0;
+          const uint64_t a = k[r], b = k[r ^ rj];
+          if ((a > b) == up) {
+            k[r] = b;
+            k[r ^ rj] = a;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int e = r * 64 + lane;
+          const uint64_t a = k[r];
+          const uint64_t b = __shfl_xor(a, j, 64);
+          const bool up = (e & kk) == 0;
+          const bool lower = (lane & j) == 0;
+          const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+          k[r] = (lower == up) ? lo : hi;
+        }
+      }
+    }
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void wave_sort_tile(uint64_t* base, int n) {
+  const int lane = threadIdx.x & 63;
+  uint64_t k[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) k[r] = (r * 64 + lane < n) ? base[r * 64 + lane] : ~0ull;
+  wave_bitonic<R>(k);
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (r * 64 + lane < n) base[r * 64 + lane] = k[r];
+}
+
+// One wave per tile: lists of up to kRegSortMax keys are sorted in registers; longer lists are
+// queued for k_tile_sort_long.
+__global__ __launch_bounds__(256) void k_tile_sort_wave(const uint32_t* __restrict__ ranges, int n_tiles,
+                                                        uint64_t* __restrict__ pairs, uint32_t* __restrict__ long_cnt,
+                                                        uint32_t* __restrict__ long_list) {
+  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (t >= n_tiles) return;
   const uint32_t start = ranges[2 * t], end = ranges[2 * t + 1];
   const int n = (int)(end - start);
   if (n <= 1) return;
+  if (n > kRegSortMax) {
+    if ((threadIdx.x & 63) == 0) long_list[atomicAdd(long_cnt, 1u)] = (uint32_t)t;
+    return;
+  }
+  uint64_t* base = pairs + start;
+  if (n <= 64) wave_sort_tile<1>(base, n);
+  else if (n <= 128) wave_sort_tile<2>(base, n);
+  else if (n <= 256) wave_sort_tile<4>(base, n);
+  else wave_sort_tile<8>(base, n);
+}
+
+// One workgroup per tile: sort the tile's bucket ascending by (z bits, face).  Buckets up to
+// kSortLds keys are bitonic-sorted in LDS; longer ones are sorted in LDS-sized chunks and
+// merged pairwise in global memory through `temp` (keys are unique, so a rank by binary
+// search places every key).
+// Persistent over the queued long tiles (grid-stride over the device-side list).
+__global__ __launch_bounds__(256) void k_tile_sort_long(const uint32_t* __restrict__ ranges,
+                                                        const uint32_t* __restrict__ long_cnt,
+                                                        const uint32_t* __restrict__ long_list,
+                                                        uint64_t* __restrict__ pairs, uint64_t* __restrict__ temp) {
+  __shared__ uint64_t s[kSortLds];
+  const uint32_t nl = *long_cnt;
+  for (uint32_t li = blockIdx.x; li < nl; li += gridDim.x) {
+  const int t = (int)long_list[li];
+  const uint32_t start = ranges[2 * t], end = ranges[2 * t + 1];
+  const int n = (int)(end - start);
   uint64_t* base = pairs + start;
   for (int c0 = 0; c0 < n; c0 += kSortLds) {
     const int cn = min(kSortLds, n - c0);
@@ -373,7 +439,7 @@ __global__ __launch_bounds__(256) void k_tile_sort(const uint32_t* __restrict__ 
     for (int i = threadIdx.x; i < cn; i += blockDim.x) base[c0 + i] = s[i];
     __syncthreads();
   }
-  if (n <= kSortLds) return;
+  if (n <= kSortLds) continue;
   uint64_t* src = base;
   uint64_t* dst = temp + start;
   for (int width = kSortLds; width < n; width <<= 1) {
@@ -398,6 +464,8 @@ __global__ __launch_bounds__(256) void k_tile_sort(const uint32_t* __restrict__ 
   __syncthreads();
   if (src != base)
     for (int i = threadIdx.x; i < n; i += blockDim.x) base[i] = src[i];
+  __syncthreads();
+  }
 }
 
 __global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
@@ -427,11 +495,13 @@ hipError_t launch_bin(const tsr_scene_dev& sc, const float* poses, const ViewTab
 
   uint32_t* vis_cnt = reinterpret_cast<uint32_t*>(ws + L.vis_cnt);
   uint32_t* vis_list = reinterpret_cast<uint32_t*>(ws + L.vis_list);
-  // tile counters and per-view visible counters are contiguous: one fill
-  TSR_LAUNCH("fill_tiles", k_fill_u32, dim3(grid_for(vt.n_tiles + vt.n_views, 256)), dim3(256), 0, st, tile_cnt,
-             (int64_t)(vt.n_tiles + vt.n_views), 0u);
+  uint32_t* long_cnt = reinterpret_cast<uint32_t*>(ws + L.long_cnt);
+  uint32_t* long_list = reinterpret_cast<uint32_t*>(ws + L.long_list);
+  // tile counters and the long-tile counter are contiguous: one fill
+  TSR_LAUNCH("fill_tiles", k_fill_u32, dim3(grid_for(vt.n_tiles + 1, 256)), dim3(256), 0, st, tile_cnt,
+             (int64_t)(vt.n_tiles + 1), 0u);
   if (nf > 0)
-    TSR_LAUNCH("project", k_project, dim3(grid_for(nf, 256)), dim3(256), 0, st, sc, poses, vt, p.z_near, p.r_min, counts,
+    TSR_LAUNCH("project", k_project, dim3(grid_for(nf, kProjBlock)), dim3(kProjBlock), 0, st, sc, poses, vt, p.z_near, p.r_min, counts,
                        records, tile_cnt, vis_cnt, vis_list);
   TSR_LAUNCH("scan_tiles", k_scan_tiles, dim3(1), dim3(1024), 0, st, tile_cnt, ranges, vt.n_tiles,
                      sort ? L.capacity : (int64_t)0x7fffffffffffffffll, K, overflow);
@@ -439,7 +509,9 @@ hipError_t launch_bin(const tsr_scene_dev& sc, const float* poses, const ViewTab
   if (nf > 0)
     TSR_LAUNCH("emit", k_emit, dim3(grid_for(nf, 256)), dim3(256), 0, st, vt, counts, records, ranges, tile_cnt,
                        overflow, pairs);
-  TSR_LAUNCH("tile_sort", k_tile_sort, dim3(vt.n_tiles), dim3(256), 0, st, ranges, vt.n_tiles, pairs, temp);
+  TSR_LAUNCH("tile_sort", k_tile_sort_wave, dim3(grid_for(vt.n_tiles, 4)), dim3(256), 0, st, ranges, vt.n_tiles, pairs,
+             long_cnt, long_list);
+  TSR_LAUNCH("tile_sort_long", k_tile_sort_long, dim3(64), dim3(256), 0, st, ranges, long_cnt, long_list, pairs, temp);
   return hipGetLastError();
 }
 

@@ -422,14 +422,18 @@ __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float*
   __shared__ double red[6][4];
   const int64_t M = vt.n_faces;
   const int64_t N = sc.n_vertices;
-  const int v = blockIdx.y;
-  const uint32_t cnt = vis_cnt[v];
-  if ((uint32_t)blockIdx.x * blockDim.x >= cnt) return;             // whole workgroup past the list
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  // this workgroup takes the visible list segment of projection workgroup blockIdx.x
+  const uint32_t cnt = vis_cnt[blockIdx.x];
+  if (cnt == 0) return;
+  const int64_t g_lo = (int64_t)blockIdx.x * kProjBlock;
+  const int v_lo = (int)(g_lo / M);
+  const int v_hi = (int)(min(g_lo + kProjBlock, (int64_t)vt.n_views * M) - 1) / M;
   double pose6[6] = {0, 0, 0, 0, 0, 0};
-  if (i < cnt) {
-    const int64_t m = (int64_t)vis_list[(int64_t)v * M + i];
-    const int64_t g = (int64_t)v * M + m;
+  int v = v_lo;
+  if (threadIdx.x < cnt) {
+    const int64_t g = (int64_t)vis_list[g_lo + threadIdx.x];
+    v = (int)(g / M);
+    const int64_t m = g - (int64_t)v * M;
     int64_t vid[3];
     if (sc.faces) {
       for (int k = 0; k < 3; ++k) vid[k] = (int64_t)sc.faces[3 * m + k];
@@ -578,35 +582,38 @@ __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float*
       }
     }
   }
-  // ---- pose gradient of this view: FP64 block reduction, one atomic per block and component
+  // ---- pose gradient per view present in this segment (usually one): FP64 block reduction,
+  //      one atomic per view and component
   if (pose_acc) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int c = 0; c < 6; ++c) {
-      double x = pose6[c];
-      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-      if (lane == 0) red[c][wave] = x;
-    }
-    __syncthreads();
-    if (threadIdx.x < 6) {
-      const double t = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
-      if (t != 0.0) unsafeAtomicAdd(&pose_acc[6 * v + threadIdx.x], t);
+    for (int vv = v_lo; vv <= v_hi; ++vv) {
+      for (int c = 0; c < 6; ++c) {
+        double x = v == vv ? pose6[c] : 0.0;
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        if (lane == 0) red[c][wave] = x;
+      }
+      __syncthreads();
+      if (threadIdx.x < 6) {
+        const double t = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
+        if (t != 0.0) unsafeAtomicAdd(&pose_acc[6 * vv + threadIdx.x], t);
+      }
+      __syncthreads();
     }
   }
 }
 
 // Zero the gradient accumulators of the visible (view, face) pairs, and the per-view FP64
 // pose and loss accumulators.
-__global__ void k_zero_acc(ViewTable vt, const uint32_t* __restrict__ vis_cnt, const uint32_t* __restrict__ vis_list,
-                           acc_t* __restrict__ grad_acc, double* __restrict__ pose_acc, double* __restrict__ loss_acc) {
-  const int v = blockIdx.y;
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < vis_cnt[v]) {
-    const int64_t g = (int64_t)v * vt.n_faces + vis_list[(int64_t)v * vt.n_faces + i];
+__global__ void k_zero_acc(ViewTable vt, int64_t n_segments, const uint32_t* __restrict__ vis_cnt,
+                           const uint32_t* __restrict__ vis_list, acc_t* __restrict__ grad_acc,
+                           double* __restrict__ pose_acc, double* __restrict__ loss_acc) {
+  if ((int64_t)blockIdx.x < n_segments && threadIdx.x < vis_cnt[blockIdx.x]) {
+    const int64_t g = (int64_t)vis_list[(int64_t)blockIdx.x * kProjBlock + threadIdx.x];
     float4* p = reinterpret_cast<float4*>(grad_acc + g * kGradDwords);
 #pragma unroll
     for (int k = 0; k < (int)(kGradDwords * sizeof(acc_t)) / 16; ++k) p[k] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
-  if (blockIdx.x == 0 && blockIdx.y == 0) {
+  if (blockIdx.x == 0) {
     for (int k = threadIdx.x; k < 6 * vt.n_views; k += blockDim.x) pose_acc[k] = 0.0;
     if (loss_acc)
       for (int k = threadIdx.x; k < vt.n_views; k += blockDim.x) loss_acc[k] = 0.0;
@@ -745,8 +752,10 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
   acc_t* grad_acc = reinterpret_cast<acc_t*>(ws + L.grad_acc);
   double* pose_acc = reinterpret_cast<double*>(ws + L.pose_acc);
   double* loss_acc = reinterpret_cast<double*>(ws + L.loss_acc);
-  const dim3 face_grid(grid_for(vt.n_faces > 0 ? vt.n_faces : 1, 256), vt.n_views);
-  TSR_LAUNCH("zero_acc", k_zero_acc, face_grid, dim3(256), 0, st, vt, vis_cnt, vis_list, grad_acc, pose_acc, loss_acc);
+  const int64_t nf = (int64_t)vt.n_views * vt.n_faces;
+  const dim3 face_grid(nf > 0 ? grid_for(nf, kProjBlock) : 1);     // one workgroup per visible-list segment
+  TSR_LAUNCH("zero_acc", k_zero_acc, face_grid, dim3(256), 0, st, vt, (int64_t)grid_for(nf, kProjBlock), vis_cnt,
+             vis_list, grad_acc, pose_acc, loss_acc);
   const dim3 block(kBlock);
   const int sm = sigma_mode(p.sigma);
   if (!fused_train) {

@@ -31,9 +31,11 @@ struct WsLayout {
   size_t counts;                   // uint32 [V*M]
   size_t records;                  // float  [V*M][24]
   size_t grad_acc;                 // float  [V*M][20]
-  size_t tile_cnt;                 // uint32 [T], then uint32 vis_cnt [V] (filled together)
-  size_t vis_cnt;                  // uint32 [V]: visible faces per view
-  size_t vis_list;                 // uint32 [V][M]: face ids visible in each view (first vis_cnt[v])
+  size_t tile_cnt;                 // uint32 [T], then the uint32 long-tile counter (filled together)
+  size_t long_cnt;                 // uint32: tiles whose list is too long for the register sort
+  size_t long_list;                // uint32 [T]: those tiles
+  size_t vis_cnt;                  // uint32 [NB]: visible (view, face) pairs of each projection workgroup
+  size_t vis_list;                 // uint32 [NB][256]: their ids g = v * M + m (first vis_cnt[b] entries)
   size_t ranges;                   // uint32 [T][2]
   size_t order;                    // int32  [T] tile schedule (longest lists first)
   size_t order_hist;               // uint32 [2][kOrderBuckets]
@@ -46,7 +48,9 @@ struct WsLayout {
   int64_t capacity;
 };
 
-constexpr int kOrderBuckets = 1024;   // tile-length buckets of the longest-first schedule
+constexpr int kOrderBuckets = 1024;
+constexpr int kProjBlock = 256;        // faces per projection workgroup (one visible-list segment each)
+constexpr int kRegSortMax = 512;       // tile lists up to this length are sorted in registers   // tile-length buckets of the longest-first schedule
 
 // Training-kernel schedule (chosen by the autotuner; the default is one workgroup per tile).
 struct TrainSchedule {
