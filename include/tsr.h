@@ -143,7 +143,8 @@ TSR_API int tsr_bin_and_sort(const tsr_scene *scene, const float *poses, const t
                      void *stream);
 
 /* Exact pair count K for the given views without sorting; synchronises `stream`.
- * Uses the fixed part of `ws` only (any capacity, even 0, suffices). */
+ * Uses the fixed part of `ws` only (any capacity, even 0, suffices) and invalidates any
+ * binning held in `ws`. */
 TSR_API int tsr_count(const tsr_scene *scene, const float *poses, const tsr_intrinsics *intr,
               int n_views, const tsr_params *params, void *ws, size_t ws_bytes, void *stream,
               int64_t *n_pairs /* (host) out */);

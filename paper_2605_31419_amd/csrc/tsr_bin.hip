@@ -223,27 +223,54 @@ __global__ __launch_bounds__(256) void k_project(tsr_scene_dev sc, const float* 
 
 // Single workgroup: exclusive scan of the tile counts into ranges, pair total K, overflow
 // check against the capacity, and reset of the counts (reused as emission cursors).
-__global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* __restrict__ tile_cnt, uint32_t* __restrict__ ranges,
-                                                     int n_tiles, int64_t capacity, int64_t* __restrict__ K_out,
-                                                     uint32_t* __restrict__ overflow) {
-  __shared__ unsigned long long part[1024];
+// Block-wide exclusive scan of 1024 per-thread partial sums (Hillis-Steele in LDS).
+__device__ __forceinline__ unsigned long long block_excl_scan(unsigned long long* part, unsigned long long s,
+                                                              unsigned long long* total) {
   const int tid = threadIdx.x;
-  const int chunk = (n_tiles + 1023) / 1024;
-  const int lo = min(n_tiles, tid * chunk), hi = min(n_tiles, lo + chunk);
-  unsigned long long s = 0;
-  for (int i = lo; i < hi; ++i) s += tile_cnt[i];
   part[tid] = s;
   __syncthreads();
-  // Hillis-Steele inclusive scan over the 1024 partial sums
   for (int o = 1; o < 1024; o <<= 1) {
     unsigned long long y = tid >= o ? part[tid - o] : 0ull;
     __syncthreads();
     part[tid] += y;
     __syncthreads();
   }
-  const unsigned long long total = part[1023];
+  *total = part[1023];
+  const unsigned long long excl = part[tid] - s;
+  __syncthreads();
+  return excl;
+}
+
+// Single workgroup: (1) exclusive scan of the visible-face counts of the projection
+// workgroups (offsets of their segments in the dense visible list); (2) exclusive scan of the
+// tile counts into ranges, pair total K, overflow check against the capacity, and reset of the
+// counts (reused as emission cursors).
+__global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* __restrict__ tile_cnt, uint32_t* __restrict__ ranges,
+                                                     int n_tiles, int64_t capacity, int64_t* __restrict__ K_out,
+                                                     uint32_t* __restrict__ overflow, const uint32_t* __restrict__ vis_cnt,
+                                                     uint32_t* __restrict__ vis_off, uint32_t* __restrict__ vis_total,
+                                                     int n_segments) {
+  __shared__ unsigned long long part[1024];
+  {
+    const int tid = threadIdx.x;
+    const int chunk = (n_segments + 1023) / 1024;
+    const int lo = min(n_segments, tid * chunk), hi = min(n_segments, lo + chunk);
+    unsigned long long s = 0, tot;
+    for (int i = lo; i < hi; ++i) s += vis_cnt[i];
+    unsigned long long run = block_excl_scan(part, s, &tot);
+    for (int i = lo; i < hi; ++i) {
+      vis_off[i] = (uint32_t)run;
+      run += vis_cnt[i];
+    }
+    if (tid == 0) *vis_total = (uint32_t)tot;
+  }
+  const int tid = threadIdx.x;
+  const int chunk = (n_tiles + 1023) / 1024;
+  const int lo = min(n_tiles, tid * chunk), hi = min(n_tiles, lo + chunk);
+  unsigned long long s = 0, total;
+  for (int i = lo; i < hi; ++i) s += tile_cnt[i];
+  unsigned long long run = block_excl_scan(part, s, &total);
   const bool over = total > (unsigned long long)capacity;
-  unsigned long long run = part[tid] - s;
   for (int i = lo; i < hi; ++i) {
     const uint32_t c = tile_cnt[i];
     ranges[2 * i] = over ? 0u : (uint32_t)run;
@@ -262,7 +289,13 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* __restrict__ tile
 __global__ __launch_bounds__(256) void k_emit(ViewTable vt, const uint32_t* __restrict__ counts,
                                               const float* __restrict__ records, const uint32_t* __restrict__ ranges,
                                               uint32_t* __restrict__ cursor, const uint32_t* __restrict__ overflow,
-                                              uint64_t* __restrict__ pairs) {
+                                              uint64_t* __restrict__ pairs, const uint32_t* __restrict__ vis_cnt,
+                                              const uint32_t* __restrict__ vis_off, const uint32_t* __restrict__ vis_list,
+                                              uint32_t* __restrict__ vis_dense) {
+  // the visible-face segment of the projection workgroup with the same index goes to its
+  // place in the dense list (done even when the pairs overflowed: the backward uses it)
+  if (threadIdx.x < vis_cnt[blockIdx.x])
+    vis_dense[vis_off[blockIdx.x] + threadIdx.x] = vis_list[(int64_t)blockIdx.x * kProjBlock + threadIdx.x];
   if (*overflow) return;
   const int64_t M = vt.n_faces;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -503,12 +536,17 @@ hipError_t launch_bin(const tsr_scene_dev& sc, const float* poses, const ViewTab
   if (nf > 0)
     TSR_LAUNCH("project", k_project, dim3(grid_for(nf, kProjBlock)), dim3(kProjBlock), 0, st, sc, poses, vt, p.z_near, p.r_min, counts,
                        records, tile_cnt, vis_cnt, vis_list);
+  uint32_t* vis_off = reinterpret_cast<uint32_t*>(ws + L.vis_off);
+  uint32_t* vis_total = reinterpret_cast<uint32_t*>(ws + L.vis_total);
+  uint32_t* vis_dense = reinterpret_cast<uint32_t*>(ws + L.vis_dense);
+  const int n_seg = (int)((nf + kProjBlock - 1) / kProjBlock);
   TSR_LAUNCH("scan_tiles", k_scan_tiles, dim3(1), dim3(1024), 0, st, tile_cnt, ranges, vt.n_tiles,
-                     sort ? L.capacity : (int64_t)0x7fffffffffffffffll, K, overflow);
+                     sort ? L.capacity : (int64_t)0x7fffffffffffffffll, K, overflow, vis_cnt, vis_off, vis_total,
+                     n_seg);
   if (!sort) return hipGetLastError();
   if (nf > 0)
-    TSR_LAUNCH("emit", k_emit, dim3(grid_for(nf, 256)), dim3(256), 0, st, vt, counts, records, ranges, tile_cnt,
-                       overflow, pairs);
+    TSR_LAUNCH("emit", k_emit, dim3(grid_for(nf, kProjBlock)), dim3(kProjBlock), 0, st, vt, counts, records, ranges,
+               tile_cnt, overflow, pairs, vis_cnt, vis_off, vis_list, vis_dense);
   TSR_LAUNCH("tile_sort", k_tile_sort_wave, dim3(grid_for(vt.n_tiles, 4)), dim3(256), 0, st, ranges, vt.n_tiles, pairs,
              long_cnt, long_list);
   TSR_LAUNCH("tile_sort_long", k_tile_sort_long, dim3(64), dim3(256), 0, st, ranges, long_cnt, long_list, pairs, temp);

@@ -413,25 +413,33 @@ __device__ __forceinline__ void load_pose_d(const float* __restrict__ poses, int
   for (int i = 0; i < 3; ++i) t[i] = (double)poses[12 * v + 9 + i];
 }
 
+// Stage layout written into a consumed accumulator slot (floats): dL/dv_W for the three
+// vertices [0..8] (vertex k, axis a at 3k + a), vertex colour gradients [9..17]
+// (9 + 3k + ch), vertex opacity gradient [18] (the same for the three vertices).
+constexpr int kStageFloats = 19;
+
 __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float* __restrict__ poses, ViewTable vt,
-                                                  const uint32_t* __restrict__ vis_cnt,
-                                                  const uint32_t* __restrict__ vis_list, const float* __restrict__ records,
-                                                  const acc_t* __restrict__ grad_acc, float* __restrict__ grad_pos,
-                                                  float* __restrict__ grad_col, float* __restrict__ grad_opa,
-                                                  double* __restrict__ pose_acc, int atomic_vertices) {
+                                                  const uint32_t* __restrict__ vis_total,
+                                                  const uint32_t* __restrict__ vis_dense,
+                                                  const float* __restrict__ records, acc_t* grad_acc,
+                                                  double* __restrict__ pose_acc, int want_vertices) {
   __shared__ double red[6][4];
+  __shared__ int s_v[2];
   const int64_t M = vt.n_faces;
   const int64_t N = sc.n_vertices;
-  // this workgroup takes the visible list segment of projection workgroup blockIdx.x
-  const uint32_t cnt = vis_cnt[blockIdx.x];
-  if (cnt == 0) return;
-  const int64_t g_lo = (int64_t)blockIdx.x * kProjBlock;
-  const int v_lo = (int)(g_lo / M);
-  const int v_hi = (int)(min(g_lo + kProjBlock, (int64_t)vt.n_views * M) - 1) / M;
+  const int64_t nf = (int64_t)vt.n_views * M;
+  const int64_t total = min((int64_t)*vis_total, nf);
+  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x;
+  if (i0 >= total) return;                                          // whole workgroup past the list
+  const int64_t i = i0 + threadIdx.x;
   double pose6[6] = {0, 0, 0, 0, 0, 0};
-  int v = v_lo;
-  if (threadIdx.x < cnt) {
-    const int64_t g = (int64_t)vis_list[g_lo + threadIdx.x];
+  int v = -1;
+  int64_t g = -1;
+  if (i < total) {
+    g = (int64_t)vis_dense[i];
+    if (g >= nf) g = -1;                                            // never from a valid binning
+  }
+  if (g >= 0) {
     v = (int)(g / M);
     const int64_t m = g - (int64_t)v * M;
     int64_t vid[3];
@@ -442,7 +450,9 @@ __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float*
     }
     double gW[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};   // dL/dv_W per vertex
     double gcolv[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};  // dL/dc per vertex, channel
-    const acc_t* A = grad_acc + g * kGradDwords;
+    acc_t A[kGradDwords];                                  // read the whole slot before reusing it
+#pragma unroll
+    for (int k = 0; k < kGradDwords; ++k) A[k] = grad_acc[g * kGradDwords + k];
     const float* rec = records + g * kRecDwords;
     const ViewDesc vd = vt.v[v];
     double R[9], t[3];
@@ -564,27 +574,23 @@ __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float*
       pose6[5] += vc[k][0] * gc[1] - vc[k][1] * gc[0];
     }
     const double gop = (double)A[kGOpa] / 3.0;
-    if (atomic_vertices) {
-      for (int k = 0; k < 3; ++k) {
+    if (want_vertices) {
+      float* stage = reinterpret_cast<float*>(grad_acc + g * kGradDwords);
+      for (int k = 0; k < 3; ++k)
         for (int a = 0; a < 3; ++a) {
-          if (grad_pos) unsafeAtomicAdd(&grad_pos[a * N + vid[k]], (float)gW[k][a]);
-          if (grad_col) unsafeAtomicAdd(&grad_col[a * N + vid[k]], (float)gcolv[k][a]);
+          stage[3 * k + a] = (float)gW[k][a];
+          stage[9 + 3 * k + a] = (float)gcolv[k][a];
         }
-        if (grad_opa) unsafeAtomicAdd(&grad_opa[vid[k]], (float)gop);
-      }
-    } else {
-      for (int k = 0; k < 3; ++k) {
-        for (int a = 0; a < 3; ++a) {
-          if (grad_pos) grad_pos[a * N + vid[k]] = (float)gW[k][a];
-          if (grad_col) grad_col[a * N + vid[k]] = (float)gcolv[k][a];
-        }
-        if (grad_opa) grad_opa[vid[k]] = (float)gop;
-      }
+      stage[18] = (float)gop;
     }
   }
-  // ---- pose gradient per view present in this segment (usually one): FP64 block reduction,
-  //      one atomic per view and component
+  // ---- pose gradient of each view present in this workgroup (the dense list is ordered by
+  //      g, so usually one view): FP64 block reduction, one atomic per view and component
   if (pose_acc) {
+    if (threadIdx.x == 0) s_v[0] = (int)((int64_t)vis_dense[i0] / M);
+    if (threadIdx.x == 0) s_v[1] = (int)((int64_t)vis_dense[min(i0 + (int64_t)blockDim.x, total) - 1] / M);
+    __syncthreads();
+    const int v_lo = min(s_v[0], vt.n_views - 1), v_hi = min(s_v[1], vt.n_views - 1);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int vv = v_lo; vv <= v_hi; ++vv) {
       for (int c = 0; c < 6; ++c) {
@@ -602,16 +608,64 @@ __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float*
   }
 }
 
+// Per face: sum the staged vertex gradients over the views that see it and write them.
+// Soups write every vertex once (zero for faces no view sees); indexed meshes add into
+// zero-filled outputs.
+__global__ __launch_bounds__(256) void k_vertex_gather(tsr_scene_dev sc, ViewTable vt, const uint32_t* __restrict__ counts,
+                                                       const acc_t* __restrict__ grad_acc, float* __restrict__ grad_pos,
+                                                       float* __restrict__ grad_col, float* __restrict__ grad_opa) {
+  const int64_t M = vt.n_faces;
+  const int64_t N = sc.n_vertices;
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  float acc[kStageFloats];
+#pragma unroll
+  for (int k = 0; k < kStageFloats; ++k) acc[k] = 0.f;
+  bool any = false;
+  for (int v = 0; v < vt.n_views; ++v) {
+    const int64_t g = (int64_t)v * M + m;
+    if (counts[g] == 0) continue;
+    any = true;
+    const float* stage = reinterpret_cast<const float*>(grad_acc + g * kGradDwords);
+#pragma unroll
+    for (int k = 0; k < kStageFloats; ++k) acc[k] += stage[k];
+  }
+  if (sc.faces) {
+    if (!any) return;
+    for (int k = 0; k < 3; ++k) {
+      const int64_t vi = (int64_t)sc.faces[3 * m + k];
+      for (int a = 0; a < 3; ++a) {
+        if (grad_pos) unsafeAtomicAdd(&grad_pos[a * N + vi], acc[3 * k + a]);
+        if (grad_col) unsafeAtomicAdd(&grad_col[a * N + vi], acc[9 + 3 * k + a]);
+      }
+      if (grad_opa) unsafeAtomicAdd(&grad_opa[vi], acc[18]);
+    }
+  } else {
+    for (int k = 0; k < 3; ++k) {
+      const int64_t vi = 3 * m + k;
+      for (int a = 0; a < 3; ++a) {
+        if (grad_pos) grad_pos[a * N + vi] = acc[3 * k + a];
+        if (grad_col) grad_col[a * N + vi] = acc[9 + 3 * k + a];
+      }
+      if (grad_opa) grad_opa[vi] = acc[18];
+    }
+  }
+}
+
 // Zero the gradient accumulators of the visible (view, face) pairs, and the per-view FP64
 // pose and loss accumulators.
-__global__ void k_zero_acc(ViewTable vt, int64_t n_segments, const uint32_t* __restrict__ vis_cnt,
-                           const uint32_t* __restrict__ vis_list, acc_t* __restrict__ grad_acc,
+__global__ void k_zero_acc(ViewTable vt, const uint32_t* __restrict__ vis_total,
+                           const uint32_t* __restrict__ vis_dense, acc_t* __restrict__ grad_acc,
                            double* __restrict__ pose_acc, double* __restrict__ loss_acc) {
-  if ((int64_t)blockIdx.x < n_segments && threadIdx.x < vis_cnt[blockIdx.x]) {
-    const int64_t g = (int64_t)vis_list[(int64_t)blockIdx.x * kProjBlock + threadIdx.x];
-    float4* p = reinterpret_cast<float4*>(grad_acc + g * kGradDwords);
+  const int64_t nf = (int64_t)vt.n_views * vt.n_faces;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < min((int64_t)*vis_total, nf)) {
+    const int64_t g = (int64_t)vis_dense[i];
+    if (g < nf) {
+      float4* p = reinterpret_cast<float4*>(grad_acc + g * kGradDwords);
 #pragma unroll
-    for (int k = 0; k < (int)(kGradDwords * sizeof(acc_t)) / 16; ++k) p[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int k = 0; k < (int)(kGradDwords * sizeof(acc_t)) / 16; ++k) p[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
   }
   if (blockIdx.x == 0) {
     for (int k = threadIdx.x; k < 6 * vt.n_views; k += blockDim.x) pose_acc[k] = 0.0;
@@ -742,8 +796,9 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
                            float* depth, float* trans, float* loss, float* grad_pos, float* grad_col,
                            float* grad_opa, float* grad_pose, bool fused_train, const TrainSchedule& sched,
                            hipStream_t st) {
-  const uint32_t* vis_cnt = reinterpret_cast<const uint32_t*>(ws + L.vis_cnt);
-  const uint32_t* vis_list = reinterpret_cast<const uint32_t*>(ws + L.vis_list);
+  const uint32_t* vis_total = reinterpret_cast<const uint32_t*>(ws + L.vis_total);
+  const uint32_t* vis_dense = reinterpret_cast<const uint32_t*>(ws + L.vis_dense);
+  const uint32_t* counts = reinterpret_cast<const uint32_t*>(ws + L.counts);
   const float* records = reinterpret_cast<const float*>(ws + L.records);
   const uint64_t* pairs = reinterpret_cast<const uint64_t*>(ws + L.pairs);
   const uint32_t* ranges = reinterpret_cast<const uint32_t*>(ws + L.ranges);
@@ -753,9 +808,9 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
   double* pose_acc = reinterpret_cast<double*>(ws + L.pose_acc);
   double* loss_acc = reinterpret_cast<double*>(ws + L.loss_acc);
   const int64_t nf = (int64_t)vt.n_views * vt.n_faces;
-  const dim3 face_grid(nf > 0 ? grid_for(nf, kProjBlock) : 1);     // one workgroup per visible-list segment
-  TSR_LAUNCH("zero_acc", k_zero_acc, face_grid, dim3(256), 0, st, vt, (int64_t)grid_for(nf, kProjBlock), vis_cnt,
-             vis_list, grad_acc, pose_acc, loss_acc);
+  const dim3 face_grid(nf > 0 ? grid_for(nf, 256) : 1);          // covers the dense visible list
+  TSR_LAUNCH("zero_acc", k_zero_acc, face_grid, dim3(256), 0, st, vt, vis_total, vis_dense, grad_acc, pose_acc,
+             loss_acc);
   const dim3 block(kBlock);
   const int sm = sigma_mode(p.sigma);
   if (!fused_train) {
@@ -783,15 +838,26 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
     switch (sm) { case 1: TSR_TRAIN(1); break; case 2: TSR_TRAIN(2); break; case 3: TSR_TRAIN(3); break; default: TSR_TRAIN(0); }
 #undef TSR_TRAIN
   }
-  // vertex gradients: dense zero fill, then the visible faces write (soup, one view) or add theirs
-  const bool atomic_vertices = sc.faces != nullptr || vt.n_views > 1;
+  // per visible (view, face): chain rule and pose; then per face: vertex gradients summed
+  // over the views (indexed meshes add into zero-filled outputs)
+  const bool want_vertices = grad_pos || grad_col || grad_opa;
   const int64_t N = sc.n_vertices;
-  if (grad_pos) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(2048), dim3(256), 0, st, grad_pos, 3 * N);
-  if (grad_col) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(2048), dim3(256), 0, st, grad_col, 3 * N);
-  if (grad_opa) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(2048), dim3(256), 0, st, grad_opa, N);
-  if (vt.n_faces > 0)
-    TSR_LAUNCH("face_bwd", k_face_bwd, face_grid, dim3(256), 0, st, sc, poses, vt, vis_cnt, vis_list, records,
-               grad_acc, grad_pos, grad_col, grad_opa, grad_pose ? pose_acc : nullptr, atomic_vertices ? 1 : 0);
+  if (sc.faces && want_vertices) {
+    if (grad_pos) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(2048), dim3(256), 0, st, grad_pos, 3 * N);
+    if (grad_col) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(2048), dim3(256), 0, st, grad_col, 3 * N);
+    if (grad_opa) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(2048), dim3(256), 0, st, grad_opa, N);
+  }
+  if (nf > 0) {
+    TSR_LAUNCH("face_bwd", k_face_bwd, face_grid, dim3(256), 0, st, sc, poses, vt, vis_total, vis_dense, records,
+               grad_acc, grad_pose ? pose_acc : nullptr, want_vertices ? 1 : 0);
+    if (want_vertices)
+      TSR_LAUNCH("vertex_gather", k_vertex_gather, dim3(grid_for(vt.n_faces, 256)), dim3(256), 0, st, sc, vt, counts,
+                 grad_acc, grad_pos, grad_col, grad_opa);
+  } else if (want_vertices && !sc.faces) {
+    if (grad_pos) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(2048), dim3(256), 0, st, grad_pos, 3 * N);
+    if (grad_col) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(2048), dim3(256), 0, st, grad_col, 3 * N);
+    if (grad_opa) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(2048), dim3(256), 0, st, grad_opa, N);
+  }
   TSR_LAUNCH("finalize", k_finalize, dim3(1), dim3(256), 0, st, pose_acc, grad_pose, loss_acc, loss, vt.n_views);
   return hipGetLastError();
 }

@@ -35,7 +35,10 @@ struct WsLayout {
   size_t long_cnt;                 // uint32: tiles whose list is too long for the register sort
   size_t long_list;                // uint32 [T]: those tiles
   size_t vis_cnt;                  // uint32 [NB]: visible (view, face) pairs of each projection workgroup
+  size_t vis_off;                  // uint32 [NB]: exclusive scan of vis_cnt
+  size_t vis_total;                // uint32: total visible (view, face) pairs
   size_t vis_list;                 // uint32 [NB][256]: their ids g = v * M + m (first vis_cnt[b] entries)
+  size_t vis_dense;                // uint32 [V*M]: the same ids, compacted (first vis_total entries)
   size_t ranges;                   // uint32 [T][2]
   size_t order;                    // int32  [T] tile schedule (longest lists first)
   size_t order_hist;               // uint32 [2][kOrderBuckets]
@@ -50,7 +53,7 @@ struct WsLayout {
 
 constexpr int kOrderBuckets = 1024;
 constexpr int kProjBlock = 256;        // faces per projection workgroup (one visible-list segment each)
-constexpr int kRegSortMax = 512;       // tile lists up to this length are sorted in registers   // tile-length buckets of the longest-first schedule
+constexpr int kRegSortMax = 1024;      // tile lists up to this length are sorted in registers   // tile-length buckets of the longest-first schedule
 
 // Training-kernel schedule (chosen by the autotuner; the default is one workgroup per tile).
 struct TrainSchedule {
