@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device-to-device copy (counter calibration in profiler runs)")
     ap.add_argument("--only-single", action="store_true", help="skip the unfused and batched legs")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default tile schedule (no autotuning)")
     return ap.parse_args()
 
 
@@ -198,6 +199,13 @@ def main():
     single = Case(raster, scenes, dev, w.poses, w.intr, w.target_poses)
     E, K, m_vis, maxlen, meanlen = single.evaluations()
     log(f"[bench] single view: K={K} visible={m_vis} max list {maxlen} mean {meanlen:.1f} evals {E}")
+    tuned = None
+    if not args.no_tune:
+        from paper_2605_31419_amd import autotune
+        best, times = autotune.tune(single.rast, single.poses, single.tc, single.td, reps=5)
+        single.rast.schedule = best
+        tuned = {"schedule": list(best), "candidates_ms": {k: round(v, 4) for k, v in times.items()}}
+        log(f"[bench] autotuned schedule {best}: {json.dumps(tuned['candidates_ms'])}")
     ms = time_steps(single.step, args.steps, args.warmup)
     single.check()
     mpix = single.pixels / (ms * 1e-3) / 1e6
@@ -223,7 +231,7 @@ def main():
         del src, dst
     if args.only_single:
         print(json.dumps({"metric": "fwd+bwd Mpix/s (single view only)", "value": mpix, "unit": "Mpix/s",
-                          "ms_per_step": ms, "kernels_ms": ktimes, "copy_gbs": copy_gbs}), flush=True)
+                          "ms_per_step": ms, "kernels_ms": ktimes, "copy_gbs": copy_gbs, "schedule": tuned}), flush=True)
         return
 
     # unfused path (forward, then backward from external per-pixel seeds)
@@ -239,11 +247,19 @@ def main():
         btargets = [scenes.perturb_pose(p, g) for p in bposes]
         bcase = Case(raster, scenes, dev, bposes, [w.intr[0]] * args.views, btargets)
         Eb, Kb, mvb, maxb, meanb = bcase.evaluations()
+        btuned = None
+        if not args.no_tune:
+            from paper_2605_31419_amd import autotune
+            bbest, btimes = autotune.tune(bcase.rast, bcase.poses, bcase.tc, bcase.td, reps=3)
+            bcase.rast.schedule = bbest
+            btuned = {"schedule": list(bbest), "candidates_ms": {k: round(v, 4) for k, v in btimes.items()}}
+            log(f"[bench] batched autotuned schedule {bbest}: {json.dumps(btuned['candidates_ms'])}")
         msb = time_steps(bcase.step, max(5, args.steps // 4), args.warmup)
         bcase.check()
         ktb, _ = kernel_times(bcase.step, max(2, args.profile_steps // 2))
         batched = {"n_views": args.views, "ms_per_step": msb, "mpix_s": bcase.pixels / (msb * 1e-3) / 1e6,
-                   "K": Kb, "visible": mvb, "kernels_ms": {k: round(v, 4) for k, v in ktb.items()}}
+                   "K": Kb, "visible": mvb, "max_list": maxb, "mean_list": meanb,
+                   "kernels_ms": {k: round(v, 4) for k, v in ktb.items()}, "schedule": btuned}
         log(f"[bench] batched {args.views} views: {msb:.3f} ms -> {batched['mpix_s']:.1f} Mpix/s")
         del bcase
         torch.cuda.empty_cache()
@@ -280,6 +296,7 @@ def main():
         "unfused": {"ms_per_step": ms_unf, "mpix_s": single.pixels / (ms_unf * 1e-3) / 1e6,
                     "kernels_ms": {k: round(v, 4) for k, v in kt_unf.items()}},
         "batched": batched,
+        "schedule": tuned,
         "copy_gbs": copy_gbs,
     }
     if not args.no_cpu_baseline:

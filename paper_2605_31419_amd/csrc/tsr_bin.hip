@@ -443,7 +443,9 @@ __global__ __launch_bounds__(256) void k_tile_sort_wave(const uint32_t* __restri
   if (n <= 64) wave_sort_tile<1>(base, n);
   else if (n <= 128) wave_sort_tile<2>(base, n);
   else if (n <= 256) wave_sort_tile<4>(base, n);
-  else wave_sort_tile<8>(base, n);
+  else if (n <= 512) wave_sort_tile<8>(base, n);
+  else wave_sort_tile<16>(base, n);
+  static_assert(kRegSortMax <= 64 * 16, "register sort handles at most 16 keys per lane");
 }
 
 // One workgroup per tile: sort the tile's bucket ascending by (z bits, face).  Buckets up to

@@ -90,6 +90,7 @@ CASES = {
     "tiny_ragged_50x37": lambda: _with_identity(*tiny_scene(5, n_faces=60, w=50, h=37, f=40.0, size=(0.05, 1.0))),
     "equal_depth": lambda: (_equal_depth_scene(), [IDENTITY], [S.Intrinsics(64, 64, 40.0, 40.0, 31.5, 31.5)]),
     "huge_faces_640x480": lambda: (_huge_faces_scene(), [IDENTITY], [S.intrinsics_for(640, 480)]),
+    "long_tile_800": lambda: (_long_tile_scene(1000, 5), [IDENTITY], [S.Intrinsics(16, 16, 20.0, 20.0, 7.5, 7.5)]),
     "long_tile_5000": lambda: (_long_tile_scene(5000), [IDENTITY], [S.Intrinsics(16, 16, 20.0, 20.0, 7.5, 7.5)]),
     "long_tile_12000": lambda: (_long_tile_scene(12000, 3), [IDENTITY], [S.Intrinsics(16, 16, 20.0, 20.0, 7.5, 7.5)]),
     "offscreen": lambda: (_offscreen_scene(), [IDENTITY], [S.intrinsics_for(64, 48)]),
@@ -149,8 +150,8 @@ def test_capacity_overflow_is_reported_and_harmless():
 
 # ---------------------------------------------------------------------------- forward
 
-FWD_CASES = ["single_64x48", "tiny_ragged_50x37", "equal_depth", "huge_faces_640x480", "long_tile_5000",
-             "multi_view_mixed"]
+FWD_CASES = ["single_64x48", "tiny_ragged_50x37", "equal_depth", "huge_faces_640x480", "long_tile_800",
+             "long_tile_5000", "multi_view_mixed"]
 
 
 @pytest.mark.parametrize("name", FWD_CASES)
