@@ -201,52 +201,50 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
       mask &= ~(1ull << j);
       const int idx = b0 + j;
       const float* r = reinterpret_cast<const float*>(&srec[j * 6]);
+      // Every lane evaluates the face; lanes that do not blend it (not covered, or behind
+      // their last face) get zero gradient scales, so all 20 sums need no branches.
+      const float dx = dxb - (float)__float_as_int(r[kRecU0]);
+      const float dy = dyb - (float)__float_as_int(r[kRecV0]);
+      PixelEval e;
+      const bool act = (idx <= last) && eval_face<SM>(r, dx, dy, sigma, e);
+      const float alpha = act ? e.alpha : 0.f;
+      const float om = 1.f - alpha;
+      // T before this face: the stored value at the last face, else T_after / (1 - alpha)
+      const float Tj = (idx == last) ? Tb : Tcur * __builtin_amdgcn_rcpf(om);
+      if (act) Tcur = Tj;
+      const float zf = r[kRecZ];
+      const float c0 = act ? e.c0 : 0.f, c1 = act ? e.c1 : 0.f, c2 = act ? e.c2 : 0.f;
+      const float w = alpha * Tj;
       float acc[kGradDwords];
+      // colour plane gradients: dL/dc_ch(p) = gC_ch alpha T, and c_ch = P dx + Q dy + R
+      const float gc0 = pg.g0 * w, gc1 = pg.g1 * w, gc2 = pg.g2 * w;
+      acc[kGCol + 0] = gc0 * dx; acc[kGCol + 1] = gc0 * dy; acc[kGCol + 2] = gc0;
+      acc[kGCol + 3] = gc1 * dx; acc[kGCol + 4] = gc1 * dy; acc[kGCol + 5] = gc1;
+      acc[kGCol + 6] = gc2 * dx; acc[kGCol + 7] = gc2 * dy; acc[kGCol + 8] = gc2;
+      acc[kGZ] = pg.gd * w;
+      // dL/dalpha = T (gC.(c - B) + gD (z - BD) - gT (1 - BA))
+      const float galpha = act ? Tj * (pg.g0 * (c0 - B0) + pg.g1 * (c1 - B1) + pg.g2 * (c2 - B2) +
+                                       pg.gd * (zf - BD) - pg.gt * (1.f - BA))
+                               : 0.f;
+      const float I = act ? e.I : 0.f;
+      acc[kGOpa] = galpha * I;
+      const float gI = galpha * r[kRecOpa];
+      float grho = 0.f;
+      if constexpr (SM == 1) grho = (act && e.rho < 1.f) ? gI : 0.f;
+      else grho = (act && e.rho < 1.f) ? gI * sigma * I * __builtin_amdgcn_rcpf(e.rho) : 0.f;   // sigma I / rho
+      const float ge0 = grho * dx, ge1 = grho * dy;
 #pragma unroll
-      for (int k = 0; k < kGradDwords; ++k) acc[k] = 0.f;
-      bool act = false;
-      if (idx <= last) {
-        PixelEval e;
-        const float dx = dxb - (float)__float_as_int(r[kRecU0]);
-        const float dy = dyb - (float)__float_as_int(r[kRecV0]);
-        if (eval_face<SM>(r, dx, dy, sigma, e)) {
-          act = true;
-          const float om = 1.f - e.alpha;
-          const float Tj = (idx == last) ? Tb : Tcur / om;
-          Tcur = Tj;
-          const float zf = r[kRecZ];
-          const float w = e.alpha * Tj;
-          // colour plane gradients: dL/dc_ch(p) = gC_ch alpha T, and c_ch = P dx + Q dy + R
-          const float gc0 = pg.g0 * w, gc1 = pg.g1 * w, gc2 = pg.g2 * w;
-          acc[kGCol + 0] = gc0 * dx; acc[kGCol + 1] = gc0 * dy; acc[kGCol + 2] = gc0;
-          acc[kGCol + 3] = gc1 * dx; acc[kGCol + 4] = gc1 * dy; acc[kGCol + 5] = gc1;
-          acc[kGCol + 6] = gc2 * dx; acc[kGCol + 7] = gc2 * dy; acc[kGCol + 8] = gc2;
-          acc[kGZ] = pg.gd * w;
-          // dL/dalpha = T (gC.(c - B) + gD (z - BD) - gT (1 - BA))
-          const float galpha = Tj * (pg.g0 * (e.c0 - B0) + pg.g1 * (e.c1 - B1) + pg.g2 * (e.c2 - B2) +
-                                     pg.gd * (zf - BD) - pg.gt * (1.f - BA));
-          acc[kGOpa] = galpha * e.I;
-          const float gI = galpha * r[kRecOpa];
-          float grho = 0.f;
-          if (e.rho < 1.f) {
-            if constexpr (SM == 1) grho = gI;
-            else grho = gI * sigma * e.I / e.rho;     // dI/drho = sigma I / rho
-          }
-          const float ge0 = grho * dx, ge1 = grho * dy;
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            const bool on = e.kstar == k;
-            acc[kGEdge + 3 * k + 0] = on ? ge0 : 0.f;
-            acc[kGEdge + 3 * k + 1] = on ? ge1 : 0.f;
-            acc[kGEdge + 3 * k + 2] = on ? grho : 0.f;
-          }
-          B0 = fmaf(e.c0, e.alpha, om * B0);
-          B1 = fmaf(e.c1, e.alpha, om * B1);
-          B2 = fmaf(e.c2, e.alpha, om * B2);
-          BD = fmaf(zf, e.alpha, om * BD);
-          BA = fmaf(1.f, e.alpha, om * BA);
-        }
+      for (int k = 0; k < 3; ++k) {
+        const bool on = e.kstar == k;
+        acc[kGEdge + 3 * k + 0] = on ? ge0 : 0.f;
+        acc[kGEdge + 3 * k + 1] = on ? ge1 : 0.f;
+        acc[kGEdge + 3 * k + 2] = on ? grho : 0.f;
       }
+      B0 = fmaf(c0, alpha, om * B0);
+      B1 = fmaf(c1, alpha, om * B1);
+      B2 = fmaf(c2, alpha, om * B2);
+      BD = fmaf(zf, alpha, om * BD);
+      BA = fmaf(1.f, alpha, om * BA);
       if (__ballot(act) == 0) continue;
 #if TSR_REDUCE_SWAP
       int k_out;

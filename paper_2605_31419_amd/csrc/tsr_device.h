@@ -37,7 +37,7 @@ enum RecordField : int {
 // Wave partial sums are FP32; they are accumulated across waves and tiles in acc_t.
 enum GradField : int { kGEdge = 0, kGCol = 9, kGOpa = 18, kGZ = 19, kGradDwords = 20 };
 #ifndef TSR_ACC_F64
-#define TSR_ACC_F64 1
+#define TSR_ACC_F64 0
 #endif
 #if TSR_ACC_F64
 typedef double acc_t;
