@@ -53,6 +53,9 @@ def parse():
                     help="also run a 256 MiB device-to-device copy (counter calibration in profiler runs)")
     ap.add_argument("--only-single", action="store_true", help="skip the unfused and batched legs")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile schedule (no autotuning)")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-track", action="store_true", help="skip the captured tracking-loop leg")
+    ap.add_argument("--serve-queries", type=int, default=400)
     return ap.parse_args()
 
 
@@ -164,6 +167,78 @@ def bin_sort_bytes(M, V, m_vis, K, n_tiles):
     return M * 36 + m_vis * 96 + V * M * 8 + K * 12 + K * 24 + K * 8 + n_tiles * 8
 
 
+def tracking_leg(raster, w, dev, iters=100):
+    """Tracking stress: `iters` pose-gradient iterations (bin, fused fwd+L1+bwd with pose
+    gradient only, device pose step) captured once into a graph and replayed."""
+    import torch
+
+    from paper_2605_31419_amd.track import Tracker
+
+    intr = w.intr[0]
+    tr = raster.Rasterizer(dev, [intr])
+    tp = raster.poses_tensor(w.target_poses)
+    tr.fit(tp)
+    tr.bin_and_sort(tp)
+    tc, td, _ = tr.forward(tp)
+    trk = Tracker(dev, intr, iters=iters)
+    p0 = torch.as_tensor(w.poses[0], device="cuda")
+    trk.set_frame(p0, tc, td)
+    trk.capture()
+    trk.set_frame(p0, tc, td)
+    trk.replay()                                   # warm-up replay
+    torch.cuda.synchronize()
+    reps = 5
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    total = 0.0
+    for _ in range(reps):
+        trk.set_frame(p0, tc, td)
+        a.record()
+        trk.replay()
+        b.record()
+        torch.cuda.synchronize()
+        total += a.elapsed_time(b)
+    trk.check()
+    lh = trk.loss_hist.cpu().numpy()
+    eager = Tracker(dev, intr, iters=iters)
+    eager.set_frame(p0, tc, td)
+    torch.cuda.synchronize()
+    a.record()
+    eager.run_eager()
+    b.record()
+    torch.cuda.synchronize()
+    ms_eager = a.elapsed_time(b)
+    return {"iterations": iters, "ms_per_iteration": total / reps / iters,
+            "ms_per_iteration_eager": ms_eager / iters, "loss_first": float(lh[0]), "loss_last": float(lh[-1])}
+
+
+def serving_leg(raster, w, dev, n_queries, seed=4400):
+    """Continuous-batching render serving of the resident map: saturated throughput, then
+    Poisson arrivals at 25 / 50 / 80 % of it; p50 / p99 latency per rate."""
+    from paper_2605_31419_amd import scenes
+    from paper_2605_31419_amd.serve import GpuExecutor, Request, Server, run_poisson
+
+    ex = GpuExecutor(dev, pairs_per_tile=160.0)
+
+    def run(qps, n, warm):
+        srv = Server(ex, n_slots=4, mem_budget=8 << 30, max_batch_views=8)
+        srv.start()
+        try:
+            qs = scenes.serving_queries(seed + int(qps) % 1000, n + warm, qps=qps)
+            return run_poisson(srv, qs, warmup=warm)
+        finally:
+            srv.stop()
+
+    run(1e7, 40, 0)                                      # warm-up: allocator, code objects
+    sat = run(1e7, n_queries, 20)
+    out = {"saturated": sat, "rates": []}
+    for frac in (0.25, 0.5, 0.8):
+        st = run(frac * sat["qps"], n_queries, 20)
+        st["offered_qps"] = frac * sat["qps"]
+        out["rates"].append(st)
+    out["capacity_retries"] = ex.retries
+    return out
+
+
 def cpu_baseline(w, n_pix, seed=7):
     from oracle import oracle as O
 
@@ -264,6 +339,15 @@ def main():
         del bcase
         torch.cuda.empty_cache()
 
+    tracking = None
+    if not args.no_track:
+        tracking = tracking_leg(raster, w, dev)
+        log(f"[bench] tracking graph: {tracking['ms_per_iteration']:.3f} ms/iteration over {tracking['iterations']}")
+    serving = None
+    if not args.no_serve:
+        serving = serving_leg(raster, w, dev, args.serve_queries)
+        log(f"[bench] serving: {json.dumps(serving)}")
+
     # rooflines
     bs_names = ["fill_tiles", "project", "scan_tiles", "emit", "tile_sort"]
     bs_ms = sum(ktimes.get(k, 0.0) for k in bs_names)
@@ -297,6 +381,8 @@ def main():
                     "kernels_ms": {k: round(v, 4) for k, v in kt_unf.items()}},
         "batched": batched,
         "schedule": tuned,
+        "tracking": tracking,
+        "serving": serving,
         "copy_gbs": copy_gbs,
     }
     if not args.no_cpu_baseline:

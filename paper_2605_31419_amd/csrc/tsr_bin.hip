@@ -71,14 +71,6 @@ __device__ bool setup_face(const tsr_scene_dev& sc, const int64_t vid[3], const 
   }
   f.r = f.area2 / f.perim;
   if (!(f.r >= (double)r_min)) return false;
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const int k1 = (k + 1) % 3;
-    double ex = f.q[k1][0] - f.q[k][0], ey = f.q[k1][1] - f.q[k][1];
-    f.n[k][0] = f.so * ey / f.len[k];
-    f.n[k][1] = -f.so * ex / f.len[k];
-  }
-  f.zf = (f.vc[0][2] + f.vc[1][2] + f.vc[2][2]) / 3.0;
   double umin = fmin(f.q[0][0], fmin(f.q[1][0], f.q[2][0]));
   double umax = fmax(f.q[0][0], fmax(f.q[1][0], f.q[2][0]));
   double vmin = fmin(f.q[0][1], fmin(f.q[1][1], f.q[2][1]));
@@ -91,6 +83,60 @@ __device__ bool setup_face(const tsr_scene_dev& sc, const int64_t vid[3], const 
   f.v0 = (int)fmax(lv, 0.0);
   f.v1 = (int)fmin(hv, (double)(vd.height - 1));
   return f.u0 <= f.u1 && f.v0 <= f.v1;
+}
+
+// Outward unit edge normals and the depth key of a face that passed setup_face.
+__device__ __forceinline__ void face_normals(FaceSetup& f) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int k1 = (k + 1) % 3;
+    double ex = f.q[k1][0] - f.q[k][0], ey = f.q[k1][1] - f.q[k][1];
+    f.n[k][0] = f.so * ey / f.len[k];
+    f.n[k][1] = -f.so * ex / f.len[k];
+  }
+  f.zf = (f.vc[0][2] + f.vc[1][2] + f.vc[2][2]) / 3.0;
+}
+
+// Writes the FP32 face-local record of a visible face (after face_normals).
+__device__ __forceinline__ void write_record(const tsr_scene_dev& sc, const int64_t vid[3], const FaceSetup& f,
+                                             float* __restrict__ dst_rec) {
+  float rec[kRecDwords];
+  const double inv_r = 1.0 / f.r;
+  double a[3], b[3], c[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    a[k] = -f.n[k][0] * inv_r;
+    b[k] = -f.n[k][1] * inv_r;
+    c[k] = -(f.n[k][0] * ((double)f.u0 - f.q[k][0]) + f.n[k][1] * ((double)f.v0 - f.q[k][1])) * inv_r;
+    rec[kRecEdge + 3 * k] = (float)a[k];
+    rec[kRecEdge + 3 * k + 1] = (float)b[k];
+    rec[kRecEdge + 3 * k + 2] = (float)c[k];
+  }
+  const int64_t N = sc.n_vertices;
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    // lambda_opp(k) = E_k len_k / perimeter; opp(k) = (k + 2) % 3 is the vertex facing edge k
+    double P = 0, Q = 0, Rr = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double beta = f.len[k] * (double)sc.col[ch * N + vid[(k + 2) % 3]] / f.perim;
+      P += beta * a[k];
+      Q += beta * b[k];
+      Rr += beta * c[k];
+    }
+    rec[kRecCol + 3 * ch] = (float)P;
+    rec[kRecCol + 3 * ch + 1] = (float)Q;
+    rec[kRecCol + 3 * ch + 2] = (float)Rr;
+  }
+  rec[kRecOpa] = (float)(((double)sc.opa[vid[0]] + (double)sc.opa[vid[1]] + (double)sc.opa[vid[2]]) / 3.0);
+  rec[kRecZ] = (float)f.zf;
+  rec[kRecU0] = __int_as_float(f.u0);
+  rec[kRecV0] = __int_as_float(f.v0);
+  rec[kRecU1] = __int_as_float(f.u1);
+  rec[kRecV1] = __int_as_float(f.v1);
+  float4* dst = reinterpret_cast<float4*>(dst_rec);
+#pragma unroll
+  for (int i = 0; i < kRecDwords / 4; ++i) dst[i] = make_float4(rec[4 * i], rec[4 * i + 1], rec[4 * i + 2], rec[4 * i + 3]);
 }
 
 // ---------------------------------------------------------------------------- wave expansion
@@ -129,8 +175,10 @@ __device__ __forceinline__ void wave_expand(int cnt, F&& fn) {
 __global__ __launch_bounds__(256) void k_project(tsr_scene_dev sc, const float* __restrict__ poses, ViewTable vt,
                                                  float z_near, float r_min, uint32_t* __restrict__ counts,
                                                  float* __restrict__ records, uint32_t* __restrict__ tile_cnt,
+                                                 uint32_t* __restrict__ tile_cnt2, uint32_t* __restrict__ slots,
                                                  uint32_t* __restrict__ vis_cnt, uint32_t* __restrict__ vis_list) {
   __shared__ uint32_t s_wave[4];
+  __shared__ uint32_t s_vis[kProjBlock];
   const int64_t M = vt.n_faces;
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = g < (int64_t)vt.n_views * M;
@@ -151,45 +199,6 @@ __global__ __launch_bounds__(256) void k_project(tsr_scene_dev sc, const float* 
       ntiles = tw * ((f.v1 >> 4) - ty0 + 1);
       tile_base = vd.tile_off;
       tiles_x = vd.tiles_x;
-      // ---- record
-      float rec[kRecDwords];
-      const double inv_r = 1.0 / f.r;
-      double a[3], b[3], c[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        a[k] = -f.n[k][0] * inv_r;
-        b[k] = -f.n[k][1] * inv_r;
-        c[k] = -(f.n[k][0] * ((double)f.u0 - f.q[k][0]) + f.n[k][1] * ((double)f.v0 - f.q[k][1])) * inv_r;
-        rec[kRecEdge + 3 * k] = (float)a[k];
-        rec[kRecEdge + 3 * k + 1] = (float)b[k];
-        rec[kRecEdge + 3 * k + 2] = (float)c[k];
-      }
-      const int64_t N = sc.n_vertices;
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) {
-        // lambda_opp(k) = E_k len_k / perimeter; opp(k) = (k + 2) % 3 is the vertex facing edge k
-        double P = 0, Q = 0, Rr = 0;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          double beta = f.len[k] * (double)sc.col[ch * N + vid[(k + 2) % 3]] / f.perim;
-          P += beta * a[k];
-          Q += beta * b[k];
-          Rr += beta * c[k];
-        }
-        rec[kRecCol + 3 * ch] = (float)P;
-        rec[kRecCol + 3 * ch + 1] = (float)Q;
-        rec[kRecCol + 3 * ch + 2] = (float)Rr;
-      }
-      rec[kRecOpa] = (float)(((double)sc.opa[vid[0]] + (double)sc.opa[vid[1]] + (double)sc.opa[vid[2]]) / 3.0);
-      rec[kRecZ] = (float)f.zf;
-      rec[kRecU0] = __int_as_float(f.u0);
-      rec[kRecV0] = __int_as_float(f.v0);
-      rec[kRecU1] = __int_as_float(f.u1);
-      rec[kRecV1] = __int_as_float(f.v1);
-      float4* dst = reinterpret_cast<float4*>(records + g * kRecDwords);
-#pragma unroll
-      for (int i = 0; i < kRecDwords / 4; ++i)
-        dst[i] = make_float4(rec[4 * i], rec[4 * i + 1], rec[4 * i + 2], rec[4 * i + 3]);
     }
     counts[g] = (uint32_t)ntiles;
   }
@@ -203,21 +212,45 @@ __global__ __launch_bounds__(256) void k_project(tsr_scene_dev sc, const float* 
     __syncthreads();
     uint32_t off = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
     for (int w = 0; w < wave; ++w) off += s_wave[w];
-    if (vis) vis_list[(int64_t)blockIdx.x * kProjBlock + off] = (uint32_t)g;
-    if (threadIdx.x == 0) vis_cnt[blockIdx.x] = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+    if (vis) {
+      vis_list[(int64_t)blockIdx.x * kProjBlock + off] = (uint32_t)g;
+      s_vis[off] = (uint32_t)g;
+    }
+    const uint32_t nvis = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+    if (threadIdx.x == 0) vis_cnt[blockIdx.x] = nvis;
+    __syncthreads();
+    // ---- records of the visible faces, one compacted face per lane (the FP64 setup runs on
+    //      dense lanes instead of on every lane of every wave that holds a visible face)
+    if (threadIdx.x < nvis) {
+      const int64_t gv = (int64_t)s_vis[threadIdx.x];
+      const int vv = (int)(gv / M);
+      const int64_t mv = gv - (int64_t)vv * M;
+      double R[9], t[3];
+      load_pose(poses, vv, R, t);
+      int64_t vid[3];
+      face_vertices(sc, mv, vid);
+      FaceSetup f;
+      setup_face(sc, vid, R, t, vt.v[vv], z_near, r_min, f);        // same inputs: visible again
+      face_normals(f);
+      write_record(sc, vid, f, records + gv * kRecDwords);
+    }
   }
-  // ---- per-tile counts: small faces loop on their own lane, large ones are spread
-  const int maxc = wave_max_int(ntiles);
-  if (maxc == 0) return;
-  if (maxc <= 4) {
-    for (int i = 0; i < ntiles; ++i)
-      atomicAdd(&tile_cnt[tile_base + (ty0 + i / tw) * tiles_x + tx0 + i % tw], 1u);
-    return;
+  // ---- per-tile counts.  A face overlapping at most kSmallTiles tiles takes its slot in each
+  //      tile from the returning atomic and records it, so emission needs no atomics for it;
+  //      larger faces are counted separately and spread over the wave.
+  if (ntiles > 0 && ntiles <= kSmallTiles) {
+    uint32_t sl[kSmallTiles];
+#pragma unroll
+    for (int i = 0; i < kSmallTiles; ++i)
+      sl[i] = i < ntiles ? atomicAdd(&tile_cnt[tile_base + (ty0 + i / tw) * tiles_x + tx0 + i % tw], 1u) : 0u;
+    *reinterpret_cast<uint4*>(slots + g * kSmallTiles) = make_uint4(sl[0], sl[1], sl[2], sl[3]);
   }
-  wave_expand(ntiles, [&](bool valid, int owner, int i) {
+  const int big = ntiles > kSmallTiles ? ntiles : 0;
+  if (wave_max_int(big) == 0) return;
+  wave_expand(big, [&](bool valid, int owner, int i) {
     const int otx0 = __shfl(tx0, owner, 64), oty0 = __shfl(ty0, owner, 64), otw = __shfl(tw, owner, 64);
     const int obase = __shfl(tile_base, owner, 64), otx = __shfl(tiles_x, owner, 64);
-    if (valid) atomicAdd(&tile_cnt[obase + (oty0 + i / otw) * otx + otx0 + i % otw], 1u);
+    if (valid) atomicAdd(&tile_cnt2[obase + (oty0 + i / otw) * otx + otx0 + i % otw], 1u);
   });
 }
 
@@ -245,7 +278,8 @@ __device__ __forceinline__ unsigned long long block_excl_scan(unsigned long long
 // workgroups (offsets of their segments in the dense visible list); (2) exclusive scan of the
 // tile counts into ranges, pair total K, overflow check against the capacity, and reset of the
 // counts (reused as emission cursors).
-__global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* __restrict__ tile_cnt, uint32_t* __restrict__ ranges,
+__global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* __restrict__ tile_cnt, uint32_t* __restrict__ tile_cnt2,
+                                                     uint32_t* __restrict__ ranges,
                                                      int n_tiles, int64_t capacity, int64_t* __restrict__ K_out,
                                                      uint32_t* __restrict__ overflow, const uint32_t* __restrict__ vis_cnt,
                                                      uint32_t* __restrict__ vis_off, uint32_t* __restrict__ vis_total,
@@ -268,15 +302,15 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* __restrict__ tile
   const int chunk = (n_tiles + 1023) / 1024;
   const int lo = min(n_tiles, tid * chunk), hi = min(n_tiles, lo + chunk);
   unsigned long long s = 0, total;
-  for (int i = lo; i < hi; ++i) s += tile_cnt[i];
+  for (int i = lo; i < hi; ++i) s += tile_cnt[i] + tile_cnt2[i];
   unsigned long long run = block_excl_scan(part, s, &total);
   const bool over = total > (unsigned long long)capacity;
   for (int i = lo; i < hi; ++i) {
-    const uint32_t c = tile_cnt[i];
+    const uint32_t cs = tile_cnt[i], c = cs + tile_cnt2[i];
     ranges[2 * i] = over ? 0u : (uint32_t)run;
     ranges[2 * i + 1] = over ? 0u : (uint32_t)(run + c);
     run += c;
-    tile_cnt[i] = 0u;
+    tile_cnt2[i] = cs;               // larger faces are emitted after the recorded slots
   }
   if (tid == 0) {
     *K_out = (int64_t)total;
@@ -288,7 +322,8 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* __restrict__ tile
 // Emission of (float32 z_F bits << 32 | face) into each overlapped tile's bucket.
 __global__ __launch_bounds__(256) void k_emit(ViewTable vt, const uint32_t* __restrict__ counts,
                                               const float* __restrict__ records, const uint32_t* __restrict__ ranges,
-                                              uint32_t* __restrict__ cursor, const uint32_t* __restrict__ overflow,
+                                              const uint32_t* __restrict__ slots, uint32_t* __restrict__ cursor,
+                                              const uint32_t* __restrict__ overflow,
                                               uint64_t* __restrict__ pairs, const uint32_t* __restrict__ vis_cnt,
                                               const uint32_t* __restrict__ vis_off, const uint32_t* __restrict__ vis_list,
                                               uint32_t* __restrict__ vis_dense) {
@@ -315,23 +350,18 @@ __global__ __launch_bounds__(256) void k_emit(ViewTable vt, const uint32_t* __re
     tiles_x = vd.tiles_x;
     key = ((uint64_t)__float_as_uint(rec[kRecZ]) << 32) | (uint64_t)(uint32_t)g;
   }
-  const int maxc = wave_max_int(ntiles);
-  if (maxc == 0) return;
-  if (maxc <= 4) {
-    // up to four tiles per lane: issue the cursor atomics back to back, then the stores
-    int t[4];
-    uint32_t slot[4];
+  if (ntiles > 0 && ntiles <= kSmallTiles) {
+    // slots recorded during counting: plain stores
+    const uint4 sl = *reinterpret_cast<const uint4*>(slots + g * kSmallTiles);
+    const uint32_t slv[4] = {sl.x, sl.y, sl.z, sl.w};
 #pragma unroll
-    for (int i = 0; i < 4; ++i) t[i] = tile_base + (ty0 + i / tw) * tiles_x + tx0 + i % tw;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) slot[i] = i < ntiles ? atomicAdd(&cursor[t[i]], 1u) : 0u;
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-      if (i < ntiles) pairs[ranges[2 * t[i]] + slot[i]] = key;
-    return;
+    for (int i = 0; i < kSmallTiles; ++i)
+      if (i < ntiles) pairs[ranges[2 * (tile_base + (ty0 + i / tw) * tiles_x + tx0 + i % tw)] + slv[i]] = key;
   }
+  const int big = ntiles > kSmallTiles ? ntiles : 0;
+  if (wave_max_int(big) == 0) return;
   const uint32_t key_hi = (uint32_t)(key >> 32), key_lo = (uint32_t)key;
-  wave_expand(ntiles, [&](bool valid, int owner, int i) {
+  wave_expand(big, [&](bool valid, int owner, int i) {
     const int otx0 = __shfl(tx0, owner, 64), oty0 = __shfl(ty0, owner, 64), otw = __shfl(tw, owner, 64);
     const int obase = __shfl(tile_base, owner, 64), otx = __shfl(tiles_x, owner, 64);
     const uint32_t khi = __shfl(key_hi, owner, 64), klo = __shfl(key_lo, owner, 64);
@@ -532,23 +562,25 @@ hipError_t launch_bin(const tsr_scene_dev& sc, const float* poses, const ViewTab
   uint32_t* vis_list = reinterpret_cast<uint32_t*>(ws + L.vis_list);
   uint32_t* long_cnt = reinterpret_cast<uint32_t*>(ws + L.long_cnt);
   uint32_t* long_list = reinterpret_cast<uint32_t*>(ws + L.long_list);
-  // tile counters and the long-tile counter are contiguous: one fill
-  TSR_LAUNCH("fill_tiles", k_fill_u32, dim3(grid_for(vt.n_tiles + 1, 256)), dim3(256), 0, st, tile_cnt,
-             (int64_t)(vt.n_tiles + 1), 0u);
+  uint32_t* tile_cnt2 = reinterpret_cast<uint32_t*>(ws + L.tile_cnt2);
+  uint32_t* slots = reinterpret_cast<uint32_t*>(ws + L.slots);
+  // both tile counters and the long-tile counter are contiguous: one fill
+  TSR_LAUNCH("fill_tiles", k_fill_u32, dim3(grid_for(2 * vt.n_tiles + 1, 256)), dim3(256), 0, st, tile_cnt,
+             (int64_t)(2 * vt.n_tiles + 1), 0u);
   if (nf > 0)
     TSR_LAUNCH("project", k_project, dim3(grid_for(nf, kProjBlock)), dim3(kProjBlock), 0, st, sc, poses, vt, p.z_near, p.r_min, counts,
-                       records, tile_cnt, vis_cnt, vis_list);
+                       records, tile_cnt, tile_cnt2, slots, vis_cnt, vis_list);
   uint32_t* vis_off = reinterpret_cast<uint32_t*>(ws + L.vis_off);
   uint32_t* vis_total = reinterpret_cast<uint32_t*>(ws + L.vis_total);
   uint32_t* vis_dense = reinterpret_cast<uint32_t*>(ws + L.vis_dense);
   const int n_seg = (int)((nf + kProjBlock - 1) / kProjBlock);
-  TSR_LAUNCH("scan_tiles", k_scan_tiles, dim3(1), dim3(1024), 0, st, tile_cnt, ranges, vt.n_tiles,
+  TSR_LAUNCH("scan_tiles", k_scan_tiles, dim3(1), dim3(1024), 0, st, tile_cnt, tile_cnt2, ranges, vt.n_tiles,
                      sort ? L.capacity : (int64_t)0x7fffffffffffffffll, K, overflow, vis_cnt, vis_off, vis_total,
                      n_seg);
   if (!sort) return hipGetLastError();
   if (nf > 0)
     TSR_LAUNCH("emit", k_emit, dim3(grid_for(nf, kProjBlock)), dim3(kProjBlock), 0, st, vt, counts, records, ranges,
-               tile_cnt, overflow, pairs, vis_cnt, vis_off, vis_list, vis_dense);
+               slots, tile_cnt2, overflow, pairs, vis_cnt, vis_off, vis_list, vis_dense);
   TSR_LAUNCH("tile_sort", k_tile_sort_wave, dim3(grid_for(vt.n_tiles, 4)), dim3(256), 0, st, ranges, vt.n_tiles, pairs,
              long_cnt, long_list);
   TSR_LAUNCH("tile_sort_long", k_tile_sort_long, dim3(64), dim3(256), 0, st, ranges, long_cnt, long_list, pairs, temp);

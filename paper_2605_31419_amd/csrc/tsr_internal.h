@@ -31,8 +31,11 @@ struct WsLayout {
   size_t counts;                   // uint32 [V*M]
   size_t records;                  // float  [V*M][24]
   size_t grad_acc;                 // float  [V*M][20]
-  size_t tile_cnt;                 // uint32 [T], then the uint32 long-tile counter (filled together)
+  size_t tile_cnt;                 // uint32 [T] faces with <= 4 tiles, then uint32 [T] larger faces, then
+                                   // the uint32 long-tile counter (all filled together)
+  size_t tile_cnt2;                // uint32 [T] (second half of the counters)
   size_t long_cnt;                 // uint32: tiles whose list is too long for the register sort
+  size_t slots;                    // uint32 [V*M][4]: a small face's slot in each of its tiles
   size_t long_list;                // uint32 [T]: those tiles
   size_t vis_cnt;                  // uint32 [NB]: visible (view, face) pairs of each projection workgroup
   size_t vis_off;                  // uint32 [NB]: exclusive scan of vis_cnt
@@ -53,7 +56,8 @@ struct WsLayout {
 
 constexpr int kOrderBuckets = 1024;
 constexpr int kProjBlock = 256;        // faces per projection workgroup (one visible-list segment each)
-constexpr int kRegSortMax = 1024;      // tile lists up to this length are sorted in registers   // tile-length buckets of the longest-first schedule
+constexpr int kRegSortMax = 1024;      // tile lists up to this length are sorted in registers
+constexpr int kSmallTiles = 4;         // faces overlapping at most this many tiles record their slots   // tile-length buckets of the longest-first schedule
 
 // Training-kernel schedule (chosen by the autotuner; the default is one workgroup per tile).
 struct TrainSchedule {

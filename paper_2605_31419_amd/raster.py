@@ -90,7 +90,7 @@ class Rasterizer:
     ``check_capacity`` is set)."""
 
     def __init__(self, scene: DeviceScene, intrs: Sequence, params: Optional[Params] = None,
-                 capacity: int = 0, device="cuda"):
+                 capacity: int = 0, device="cuda", workspace: Optional[torch.Tensor] = None):
         self.lib = _lib.load()
         self.scene = scene
         self.intrs = list(intrs)
@@ -105,7 +105,22 @@ class Rasterizer:
         self.ws: Optional[torch.Tensor] = None
         self.capacity = 0
         self.schedule: Optional[Tuple[int, int, int]] = None   # (persistent, order, grid) for train_l1
-        self.ensure_capacity(capacity)
+        if workspace is not None and workspace.numel() >= self.workspace_bytes(capacity):
+            # caller-provided buffer (e.g. reused across requests): use all of it
+            self.ws = workspace
+            self.capacity = self._capacity_of(workspace.numel())
+            check(self.lib.tsr_workspace_init(_ptr(self.ws), C.c_size_t(self.ws.numel()), _stream()),
+                  "tsr_workspace_init")
+        else:
+            self.ensure_capacity(capacity)
+
+    def _capacity_of(self, nbytes: int) -> int:
+        """Largest pair capacity a buffer of nbytes holds (16 bytes per pair beyond the fixed part)."""
+        fixed = self.workspace_bytes(0)
+        cap = max(0, (nbytes - fixed) // 16)
+        while cap > 0 and self.workspace_bytes(cap) > nbytes:
+            cap -= 1
+        return int(cap)
 
     # ----------------------------------------------------------------- workspace
     def workspace_bytes(self, capacity: int) -> int:

@@ -59,6 +59,17 @@ class FakeExecutor:
         self.active = 0
         self.max_active = 0
 
+    def _workspace_bytes(self, intrs, cap) -> int:
+        import ctypes as C
+
+        from ._lib import check, load
+
+        out = C.c_size_t(0)
+        sc = self.scene.c()
+        check(load().tsr_workspace_size(C.byref(sc), self.raster.intrinsics_array(intrs), len(intrs), cap,
+                                        C.byref(out)), "tsr_workspace_size")
+        return int(out.value)
+
     def estimate_bytes(self, req: Request) -> int:
         return 20 * req.pixels
 
@@ -100,6 +111,17 @@ class GpuExecutor:
         tiles = sum(((i.width + 15) // 16) * ((i.height + 15) // 16) for i in intrs)
         return int(self.pairs_per_tile * tiles) + 4096
 
+    def _workspace_bytes(self, intrs, cap) -> int:
+        import ctypes as C
+
+        from ._lib import check, load
+
+        out = C.c_size_t(0)
+        sc = self.scene.c()
+        check(load().tsr_workspace_size(C.byref(sc), self.raster.intrinsics_array(intrs), len(intrs), cap,
+                                        C.byref(out)), "tsr_workspace_size")
+        return int(out.value)
+
     def estimate_bytes(self, req: Request) -> int:
         # workspace of a one-view call plus outputs (colour, depth, transmittance)
         import ctypes as C
@@ -114,13 +136,19 @@ class GpuExecutor:
         return int(out.value) + 5 * 4 * req.pixels
 
     def make_slot(self, i: int):
-        return self.torch.cuda.Stream()
+        # a stream and a workspace buffer reused by every batch of this slot
+        return {"stream": self.torch.cuda.Stream(), "ws": None}
 
-    def run(self, stream, batch: List[Request]) -> None:
+    def run(self, slot, batch: List[Request]) -> None:
         torch, raster = self.torch, self.raster
+        stream = slot["stream"]
         intrs = [r.intr for r in batch]
         with torch.cuda.stream(stream):
-            rast = raster.Rasterizer(self.scene, intrs, self.params, capacity=self._capacity(intrs))
+            cap = self._capacity(intrs)
+            need = self._workspace_bytes(intrs, cap)
+            if slot["ws"] is None or slot["ws"].numel() < need:
+                slot["ws"] = torch.empty(int(need * 1.25), dtype=torch.uint8, device="cuda")
+            rast = raster.Rasterizer(self.scene, intrs, self.params, capacity=cap, workspace=slot["ws"])
             poses = raster.poses_tensor([r.pose for r in batch])
             rast.bin_and_sort(poses, stream=stream, check_capacity=False)
             color, depth, _ = rast.forward(poses, stream=stream)
@@ -128,7 +156,8 @@ class GpuExecutor:
             if rc != 0:                              # capacity estimate too small: exact count, redo
                 with self.lock:
                     self.retries += 1
-                rast.fit(poses, slack=1.1)
+                rast.fit(poses, slack=1.1)          # grows this request's own workspace
+                slot["ws"] = rast.ws
                 rast.bin_and_sort(poses, stream=stream, check_capacity=True)
                 color, depth, _ = rast.forward(poses, stream=stream)
                 stream.synchronize()
