@@ -17,6 +17,10 @@ constexpr int kBatch = 64;
 #ifndef TSR_REDUCE_SWAP
 #define TSR_REDUCE_SWAP 1
 #endif
+// Tiles whose list is longer than this many faces raise their wave priority (0 = off).
+#ifndef TSR_PRIO_LONG
+#define TSR_PRIO_LONG 0
+#endif
 
 // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so give each XCD a
 // contiguous range of tiles (neighbouring tiles share faces, which then hit the same L2).
@@ -359,6 +363,11 @@ __global__ __launch_bounds__(kBlock) void k_train_fused(ViewTable vt, const floa
     }
     TileCtx c;
     tile_ctx(vt, ranges, tile, c);
+#if TSR_PRIO_LONG
+    // long tile lists bound the kernel's tail: let their waves win issue arbitration
+    if (c.end - c.start > TSR_PRIO_LONG) __builtin_amdgcn_s_setprio(2);
+    else __builtin_amdgcn_s_setprio(0);
+#endif
     FwdState s;
     forward_walk<SM>(c, records, pairs, sigma, t_min, srec, sface, s);
     PixGrad pg{0.f, 0.f, 0.f, 0.f, 0.f};
