@@ -404,8 +404,50 @@ __device__ __forceinline__ int lower_bound_u64(const uint64_t* a, int n, uint64_
   return lo;
 }
 
+// Value held by lane (lane ^ j), j in {1, 2, 4, 8, 16, 32}, without a trip through LDS: DPP
+// inside 16-lane rows (quad permutes; half-row mirror i^7 followed by quad permute i^3 gives
+// i^4; a row rotation by 8 is i^8), gfx950 permlane swaps across rows.  With the same
+// register as both operands, v_permlane16_swap leaves rows (0,0,2,2) in its first result and
+// (1,1,3,3) in its second; v_permlane32_swap leaves halves (0,0) and (1,1).  Every lane of
+// the wave must be active; j must fold to a constant once the caller's loops are unrolled.
+__device__ __forceinline__ uint32_t lane_xor_u32(uint32_t x, int j) {
+  const int lane = threadIdx.x & 63;
+  const int xi = (int)x;
+  switch (j) {
+    case 1: return (uint32_t)__builtin_amdgcn_update_dpp(0, xi, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    case 2: return (uint32_t)__builtin_amdgcn_update_dpp(0, xi, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    case 4: {
+      const int y = __builtin_amdgcn_update_dpp(0, xi, 0x141, 0xF, 0xF, false);          // row_half_mirror
+      return (uint32_t)__builtin_amdgcn_update_dpp(0, y, 0x1B, 0xF, 0xF, false);         // quad_perm [3,2,1,0]
+    }
+    case 8: return (uint32_t)__builtin_amdgcn_update_dpp(0, xi, 0x128, 0xF, 0xF, false);  // row_ror:8
+    case 16: {
+      const auto p = __builtin_amdgcn_permlane16_swap(x, x, false, false);
+      return (lane & 16) ? p[0] : p[1];
+    }
+    default: {
+      const auto p = __builtin_amdgcn_permlane32_swap(x, x, false, false);
+      return (lane & 32) ? p[0] : p[1];
+    }
+  }
+}
+
+__device__ __forceinline__ uint64_t lane_xor_u64(uint64_t x, int j) {
+  const uint32_t lo = lane_xor_u32((uint32_t)x, j), hi = lane_xor_u32((uint32_t)(x >> 32), j);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// One compare-exchange of a bitonic network: key a at position e meets its partner b; the
+// lower position of the pair keeps the minimum when the run of length kk ascends.
+__device__ __forceinline__ uint64_t bitonic_keep(uint64_t a, uint64_t b, int e, int j, int kk) {
+  const bool up = (e & kk) == 0;
+  const bool lower = (e & j) == 0;
+  const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+  return (lower == up) ? lo : hi;
+}
+
 // Register bitonic sort of up to 64 * R keys held by one wave (key e = r * 64 + lane).
-// Exchanges between lanes go through ds_bpermute; exchanges between registers stay local.
+// Exchanges between lanes use lane_xor_u64; exchanges between registers stay local.
 template <int R>
 __device__ __forceinline__ void wave_bitonic(uint64_t (&k)[R]) {
   const int lane = threadIdx.x & 63;
@@ -429,18 +471,50 @@ __device__ __forceinline__ void wave_bitonic(uint64_t (&k)[R]) {
         }
       } else {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const int e = r * 64 + lane;
-          const uint64_t a = k[r];
-          const uint64_t b = __shfl_xor(a, j, 64);
-          const bool up = (e & kk) == 0;
-          const bool lower = (lane & j) == 0;
-          const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
-          k[r] = (lower == up) ? lo : hi;
-        }
+        for (int r = 0; r < R; ++r) k[r] = bitonic_keep(k[r], lane_xor_u64(k[r], j), r * 64 + lane, j, kk);
       }
     }
   }
+}
+
+// Bitonic sort of 1024 keys by one workgroup of 256 threads, four keys per thread (key
+// e = r * 256 + tid): partners within a wave via lane_xor_u64, partners in another wave of the
+// same lane through LDS (double-buffered, one barrier per stage), partners in another
+// register of the same thread locally.  `s` holds 2 x 1024 keys.  Ends with a barrier.
+__device__ __forceinline__ void block_bitonic1024(uint64_t (&k)[4], uint64_t* s) {
+  const int tid = threadIdx.x;
+  int buf = 0;
+#pragma unroll
+  for (int kk = 2; kk <= 1024; kk <<= 1) {
+#pragma unroll
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      if (j >= 256) {
+        const int rj = j >> 8;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (r & rj) continue;
+          const bool up = ((r * 256 + tid) & kk) == 0;
+          const uint64_t a = k[r], b = k[r ^ rj];
+          if ((a > b) == up) {
+            k[r] = b;
+            k[r ^ rj] = a;
+          }
+        }
+      } else if (j >= 64) {
+        uint64_t* b = s + buf * 1024;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) b[r * 256 + tid] = k[r];
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) k[r] = bitonic_keep(k[r], b[(r * 256 + tid) ^ j], r * 256 + tid, j, kk);
+        buf ^= 1;
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) k[r] = bitonic_keep(k[r], lane_xor_u64(k[r], j), r * 256 + tid, j, kk);
+      }
+    }
+  }
+  __syncthreads();
 }
 
 template <int R>
@@ -455,8 +529,8 @@ __device__ __forceinline__ void wave_sort_tile(uint64_t* base, int n) {
     if (r * 64 + lane < n) base[r * 64 + lane] = k[r];
 }
 
-// One wave per tile: lists of up to kRegSortMax keys are sorted in registers; longer lists are
-// queued for k_tile_sort_long.
+// One wave per tile: lists of up to 512 keys are sorted in registers; longer lists are queued
+// for k_tile_sort_long.
 __global__ __launch_bounds__(256) void k_tile_sort_wave(const uint32_t* __restrict__ ranges, int n_tiles,
                                                         uint64_t* __restrict__ pairs, uint32_t* __restrict__ long_cnt,
                                                         uint32_t* __restrict__ long_list) {
@@ -465,7 +539,7 @@ __global__ __launch_bounds__(256) void k_tile_sort_wave(const uint32_t* __restri
   const uint32_t start = ranges[2 * t], end = ranges[2 * t + 1];
   const int n = (int)(end - start);
   if (n <= 1) return;
-  if (n > kRegSortMax) {
+  if (n > 512) {
     if ((threadIdx.x & 63) == 0) long_list[atomicAdd(long_cnt, 1u)] = (uint32_t)t;
     return;
   }
@@ -473,15 +547,14 @@ __global__ __launch_bounds__(256) void k_tile_sort_wave(const uint32_t* __restri
   if (n <= 64) wave_sort_tile<1>(base, n);
   else if (n <= 128) wave_sort_tile<2>(base, n);
   else if (n <= 256) wave_sort_tile<4>(base, n);
-  else if (n <= 512) wave_sort_tile<8>(base, n);
-  else wave_sort_tile<16>(base, n);
-  static_assert(kRegSortMax <= 64 * 16, "register sort handles at most 16 keys per lane");
+  else wave_sort_tile<8>(base, n);
 }
 
-// One workgroup per tile: sort the tile's bucket ascending by (z bits, face).  Buckets up to
-// kSortLds keys are bitonic-sorted in LDS; longer ones are sorted in LDS-sized chunks and
-// merged pairwise in global memory through `temp` (keys are unique, so a rank by binary
-// search places every key).
+// One workgroup per queued tile: sort the tile's bucket ascending by (z bits, face).  Buckets
+// of up to kRegSortMax keys are sorted in registers by the whole workgroup
+// (block_bitonic1024); up to kSortLds keys are bitonic-sorted in LDS; longer ones are sorted
+// in LDS-sized chunks and merged pairwise in global memory through `temp` (keys are unique,
+// so a rank by binary search places every key).
 // Persistent over the queued long tiles (grid-stride over the device-side list).
 __global__ __launch_bounds__(256) void k_tile_sort_long(const uint32_t* __restrict__ ranges,
                                                         const uint32_t* __restrict__ long_cnt,
@@ -494,6 +567,17 @@ __global__ __launch_bounds__(256) void k_tile_sort_long(const uint32_t* __restri
   const uint32_t start = ranges[2 * t], end = ranges[2 * t + 1];
   const int n = (int)(end - start);
   uint64_t* base = pairs + start;
+  if (n <= kRegSortMax) {
+    static_assert(kRegSortMax == 1024, "block_bitonic1024 sorts 1024 keys");
+    uint64_t k[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) k[r] = (r * 256 + (int)threadIdx.x < n) ? base[r * 256 + threadIdx.x] : ~0ull;
+    block_bitonic1024(k, s);
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      if (r * 256 + (int)threadIdx.x < n) base[r * 256 + threadIdx.x] = k[r];
+    continue;
+  }
   for (int c0 = 0; c0 < n; c0 += kSortLds) {
     const int cn = min(kSortLds, n - c0);
     int n2 = 1;

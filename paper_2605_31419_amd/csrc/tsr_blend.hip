@@ -17,9 +17,10 @@ constexpr int kBatch = 64;
 #ifndef TSR_REDUCE_SWAP
 #define TSR_REDUCE_SWAP 1
 #endif
-// Tiles whose list is longer than this many faces raise their wave priority (0 = off).
+// Tiles whose list is longer than this many faces raise their wave priority (0 = off).  The
+// longest tiles finish last; letting their waves win issue arbitration shortens the tail.
 #ifndef TSR_PRIO_LONG
-#define TSR_PRIO_LONG 0
+#define TSR_PRIO_LONG 240
 #endif
 
 // XCD-aware tile order: workgroups are dealt round-robin to the 8 XCDs, so give each XCD a

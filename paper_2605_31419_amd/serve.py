@@ -154,9 +154,12 @@ class GpuExecutor:
             color, depth, _ = rast.forward(poses, stream=stream)
             rc = rast.lib.tsr_check(raster._ptr(rast.ws), raster._stream(stream), None)   # syncs this stream
             if rc != 0:                              # capacity estimate too small: exact count, redo
+                k = rast.fit(poses, slack=1.1)      # grows this slot's workspace
+                tiles = sum(((i.width + 15) // 16) * ((i.height + 15) // 16) for i in intrs)
                 with self.lock:
                     self.retries += 1
-                rast.fit(poses, slack=1.1)          # grows this request's own workspace
+                    # later batches (and admission) start from the density seen here
+                    self.pairs_per_tile = max(self.pairs_per_tile, 1.1 * k / max(tiles, 1))
                 slot["ws"] = rast.ws
                 rast.bin_and_sort(poses, stream=stream, check_capacity=True)
                 color, depth, _ = rast.forward(poses, stream=stream)
