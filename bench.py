@@ -53,6 +53,8 @@ def parse():
                     help="also run a 256 MiB device-to-device copy (counter calibration in profiler runs)")
     ap.add_argument("--only-single", action="store_true", help="skip the unfused and batched legs")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile schedule (no autotuning)")
+    ap.add_argument("--schedule", default=None,
+                    help="fixed tile schedule 'persistent,order,grid' for the single view (no autotuning)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-track", action="store_true", help="skip the captured tracking-loop leg")
     ap.add_argument("--serve-queries", type=int, default=400)
@@ -106,9 +108,9 @@ class Case:
 
     def evaluations(self):
         """Pixel-face window evaluations of one pass: sum over tiles of (pixels in the tile)
-        x (faces in its list), and the tile-list statistics."""
-        import ctypes as C
-
+        x (faces in its list), and the tile-list statistics, for the poses the step renders."""
+        self.rast.bin_and_sort(self.poses)
+        self.torch.cuda.synchronize()
         b = self.rast.binning()
         ws = self.rast.ws
         off = b.ranges - ws.data_ptr()
@@ -157,6 +159,25 @@ def kernel_times(fn, steps):
     _lib.profile_enable(False)
     _lib.profile_reset()
     return {k: v[1] / v[0] for k, v in prof.items()}, {k: v[0] // steps for k, v in prof.items()}
+
+
+def counter_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed profiler-counter summary (FETCH_SIZE
+    and WRITE_SIZE passes, scaled by a device copy of known size), or None when no summary
+    covers this kernel or the sources changed since the counters were recorded."""
+    import glob
+    import re
+
+    from paper_2605_31419_amd.build import source_fingerprint
+
+    fp = source_fingerprint()
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as f:
+            for line in f:
+                m = re.match(r"\s*traffic: kernel=(\S+) fetch_bytes=(\d+) write_bytes=(\d+) sources=([0-9a-f]+)", line)
+                if m and m.group(1).split("<")[0] == kernel and m.group(4) == fp:
+                    return int(m.group(2)) + int(m.group(3)), os.path.relpath(path, ROOT)
+    return None, None
 
 
 def bin_sort_bytes(M, V, m_vis, K, n_tiles):
@@ -275,7 +296,10 @@ def main():
     E, K, m_vis, maxlen, meanlen = single.evaluations()
     log(f"[bench] single view: K={K} visible={m_vis} max list {maxlen} mean {meanlen:.1f} evals {E}")
     tuned = None
-    if not args.no_tune:
+    if args.schedule:
+        single.rast.schedule = tuple(int(x) for x in args.schedule.split(","))
+        tuned = {"schedule": list(single.rast.schedule), "candidates_ms": None}
+    elif not args.no_tune:
         from paper_2605_31419_amd import autotune
         best, times = autotune.tune(single.rast, single.poses, single.tc, single.td, reps=5)
         single.rast.schedule = best
@@ -349,7 +373,7 @@ def main():
         log(f"[bench] serving: {json.dumps(serving)}")
 
     # rooflines
-    bs_names = ["fill_tiles", "project", "scan_tiles", "emit", "tile_sort"]
+    bs_names = ["fill_tiles", "project", "scan_tiles", "emit", "tile_sort", "tile_sort_long"]
     bs_ms = sum(ktimes.get(k, 0.0) for k in bs_names)
     n_tiles = single.rast.binning().n_tiles
     bs_bytes = bin_sort_bytes(args.faces, 1, m_vis, K, n_tiles)
@@ -357,9 +381,12 @@ def main():
     if dom == "train_fused":
         flops = E * (FLOP_FWD + FLOP_BWD)
         ach = flops / (ktimes[dom] * 1e-3) / 1e12
+        traffic, tsrc = counter_traffic("k_" + dom)
         roof = {"kernel": dom, "bound": "alu", "achieved": ach, "peak": FP32_VECTOR_PEAK_TF, "unit": "TFLOP/s",
-                "frac": ach / FP32_VECTOR_PEAK_TF, "traffic": None,
+                "frac": ach / FP32_VECTOR_PEAK_TF, "traffic": traffic,
                 "work": f"{E} pixel-face evaluations x {FLOP_FWD + FLOP_BWD} FLOP"}
+        if tsrc:
+            roof["traffic_source"] = tsrc
     else:
         ach = bs_bytes / (bs_ms * 1e-3) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -27,6 +27,20 @@ FLAGS = [
 ]
 
 
+def source_fingerprint() -> str:
+    """SHA-256 over the kernel sources, the public header and the compiler flags: profiler
+    counters recorded under one fingerprint describe exactly that build."""
+    import hashlib
+
+    h = hashlib.sha256(" ".join(FLAGS).encode())
+    files = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".h")))
+    for f in files + ["../../include/tsr.h"]:
+        with open(os.path.normpath(os.path.join(CSRC, f)), "rb") as fh:
+            h.update(f.encode())
+            h.update(fh.read())
+    return h.hexdigest()
+
+
 def build(verbose: bool = False, extra=None, out: str = LIB) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = out + ".tmp"

@@ -157,7 +157,6 @@ WsLayout layout(const ViewTable& vt, int64_t cap) {
   L.vis_dense = o; o = align_up(o + sizeof(uint32_t) * nf);
   L.ranges = o; o = align_up(o + sizeof(uint32_t) * 2 * vt.n_tiles);
   L.order = o; o = align_up(o + sizeof(int32_t) * vt.n_tiles);
-  L.order_hist = o; o = align_up(o + sizeof(uint32_t) * 2 * tsr::kOrderBuckets);
   L.n_last = o; o = align_up(o + sizeof(int32_t) * P);
   L.t_last = o; o = align_up(o + sizeof(float) * P);
   L.fixed_end = o;

@@ -139,6 +139,50 @@ __device__ __forceinline__ void write_record(const tsr_scene_dev& sc, const int6
   for (int i = 0; i < kRecDwords / 4; ++i) dst[i] = make_float4(rec[4 * i], rec[4 * i + 1], rec[4 * i + 2], rec[4 * i + 3]);
 }
 
+// Conservative FP32 pre-test: true only when setup_face (FP64) is certain to cull the face,
+// i.e. a vertex lies behind the near plane by more than the FP32 error bound, or the face's
+// pixel range stays empty when every projected coordinate is widened by its error bound.
+// Faces it does not reject go through setup_face; non-finite values are never rejected here.
+// Error bounds: camera coordinates from three FMAs and an add of float inputs differ from the
+// FP64 value by at most 4 ulp-units of sum |R_ai w_i| + |t_a| (bound used: 1e-6 x that sum);
+// the projection adds the propagated coordinate error and two roundings (bound used: 4x the
+// first-order estimate, plus 1e-4 px).
+__device__ __forceinline__ bool surely_culled(const tsr_scene_dev& sc, const int64_t vid[3],
+                                              const float* __restrict__ pose, const ViewDesc& vd, float z_near) {
+  const int64_t N = sc.n_vertices;
+  float ulo = INFINITY, uhi = -INFINITY, vlo = INFINITY, vhi = -INFINITY;
+  bool finite = true;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float w0 = sc.pos[vid[k]], w1 = sc.pos[N + vid[k]], w2 = sc.pos[2 * N + vid[k]];
+    float c[3], e[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float r0 = pose[3 * a], r1 = pose[3 * a + 1], r2 = pose[3 * a + 2], ta = pose[9 + a];
+      c[a] = fmaf(r0, w0, fmaf(r1, w1, fmaf(r2, w2, ta)));
+      e[a] = 1e-6f * (fabsf(r0 * w0) + fabsf(r1 * w1) + fabsf(r2 * w2) + fabsf(ta));
+    }
+    if (c[2] + e[2] < z_near) return true;           // FP64 depth below z_near as well
+    const float zlo = c[2] - e[2];
+    if (!(zlo > 0.f)) return false;                   // projection bound needs z > 0
+    const float qx = c[0] / c[2], qy = c[1] / c[2];
+    const float dqx = (e[0] + fabsf(qx) * e[2]) / zlo + 1.2e-7f * fabsf(qx);
+    const float dqy = (e[1] + fabsf(qy) * e[2]) / zlo + 1.2e-7f * fabsf(qy);
+    const float u = fmaf(vd.fx, qx, vd.cx), v = fmaf(vd.fy, qy, vd.cy);
+    const float du = 4.f * (fabsf(vd.fx) * dqx + 1.2e-7f * (fabsf(vd.fx * qx) + fabsf(vd.cx) + fabsf(u))) + 1e-4f;
+    const float dv = 4.f * (fabsf(vd.fy) * dqy + 1.2e-7f * (fabsf(vd.fy * qy) + fabsf(vd.cy) + fabsf(v))) + 1e-4f;
+    finite = finite && isfinite(u) && isfinite(v) && isfinite(du) && isfinite(dv);
+    ulo = fminf(ulo, u - du);
+    uhi = fmaxf(uhi, u + du);
+    vlo = fminf(vlo, v - dv);
+    vhi = fmaxf(vhi, v + dv);
+  }
+  if (!finite) return false;
+  const float cu0 = fmaxf(ceilf(ulo), 0.f), cu1 = fminf(floorf(uhi), (float)(vd.width - 1));
+  const float cv0 = fmaxf(ceilf(vlo), 0.f), cv1 = fminf(floorf(vhi), (float)(vd.height - 1));
+  return cu0 > cu1 || cv0 > cv1;
+}
+
 // ---------------------------------------------------------------------------- wave expansion
 // Spreads per-lane work lists (lane l owns cnt_l items) evenly over the 64 lanes: a wave
 // prefix scan of the counts, then each lane finds the owner of its item by binary search
@@ -171,26 +215,49 @@ __device__ __forceinline__ void wave_expand(int cnt, F&& fn) {
 
 // ---------------------------------------------------------------------------- kernels
 
-// One thread per (view, face); faces are numbered g = v * M + m.
+// One thread per (view, face); faces are numbered g = v * M + m.  Two stages: the FP32
+// pre-test on every lane rejects faces that are certainly culled; the remaining candidates
+// of the workgroup are compacted onto the first lanes, which run the exact FP64 setup (the
+// visibility decision, the pixel rectangle and, for visible faces, the record).
 __global__ __launch_bounds__(256) void k_project(tsr_scene_dev sc, const float* __restrict__ poses, ViewTable vt,
                                                  float z_near, float r_min, uint32_t* __restrict__ counts,
                                                  float* __restrict__ records, uint32_t* __restrict__ tile_cnt,
                                                  uint32_t* __restrict__ tile_cnt2, uint32_t* __restrict__ slots,
                                                  uint32_t* __restrict__ vis_cnt, uint32_t* __restrict__ vis_list) {
   __shared__ uint32_t s_wave[4];
-  __shared__ uint32_t s_vis[kProjBlock];
+  __shared__ uint32_t s_cand[kProjBlock];
   const int64_t M = vt.n_faces;
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool live = g < (int64_t)vt.n_views * M;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool cand = false;
+    if (g < (int64_t)vt.n_views * M) {
+      const int v = (int)(g / M);
+      int64_t vid[3];
+      face_vertices(sc, g - (int64_t)v * M, vid);
+      cand = !surely_culled(sc, vid, poses + 12 * v, vt.v[v], z_near);
+      if (!cand) counts[g] = 0u;
+    }
+    const unsigned long long mask = __ballot(cand);
+    if (lane == 0) s_wave[wave] = (uint32_t)__popcll(mask);
+    __syncthreads();
+    uint32_t off = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
+    for (int w = 0; w < wave; ++w) off += s_wave[w];
+    if (cand) s_cand[off] = (uint32_t)g;
+  }
+  const uint32_t ncand = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+  __syncthreads();
+  // ---- exact setup of the candidates, one per lane (in g order)
   int ntiles = 0, tx0 = 0, ty0 = 0, tw = 1, tile_base = 0, tiles_x = 1;
-  if (live) {
+  int64_t g = 0;
+  if (threadIdx.x < ncand) {
+    g = (int64_t)s_cand[threadIdx.x];
     const int v = (int)(g / M);
-    const int64_t m = g - (int64_t)v * M;
-    const ViewDesc vd = vt.v[v];
+    const ViewDesc& vd = vt.v[v];
     double R[9], t[3];
     load_pose(poses, v, R, t);
     int64_t vid[3];
-    face_vertices(sc, m, vid);
+    face_vertices(sc, g - (int64_t)v * M, vid);
     FaceSetup f;
     if (setup_face(sc, vid, R, t, vd, z_near, r_min, f)) {
       tx0 = f.u0 >> 4;
@@ -199,41 +266,23 @@ __global__ __launch_bounds__(256) void k_project(tsr_scene_dev sc, const float* 
       ntiles = tw * ((f.v1 >> 4) - ty0 + 1);
       tile_base = vd.tile_off;
       tiles_x = vd.tiles_x;
+      face_normals(f);
+      write_record(sc, vid, f, records + g * kRecDwords);
     }
     counts[g] = (uint32_t)ntiles;
   }
-  // ---- visible (view, face) ids of this workgroup, compacted into its own segment: a wave
-  //      ballot and per-wave counts in LDS; no global atomics
+  __syncthreads();                    // s_wave is reused below
+  // ---- visible (view, face) ids of this workgroup, compacted (still in g order) into its own
+  //      segment of the visible list: a wave ballot and per-wave counts in LDS, no atomics
   {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const bool vis = ntiles > 0;
     const unsigned long long mask = __ballot(vis);
     if (lane == 0) s_wave[wave] = (uint32_t)__popcll(mask);
     __syncthreads();
     uint32_t off = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
     for (int w = 0; w < wave; ++w) off += s_wave[w];
-    if (vis) {
-      vis_list[(int64_t)blockIdx.x * kProjBlock + off] = (uint32_t)g;
-      s_vis[off] = (uint32_t)g;
-    }
-    const uint32_t nvis = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
-    if (threadIdx.x == 0) vis_cnt[blockIdx.x] = nvis;
-    __syncthreads();
-    // ---- records of the visible faces, one compacted face per lane (the FP64 setup runs on
-    //      dense lanes instead of on every lane of every wave that holds a visible face)
-    if (threadIdx.x < nvis) {
-      const int64_t gv = (int64_t)s_vis[threadIdx.x];
-      const int vv = (int)(gv / M);
-      const int64_t mv = gv - (int64_t)vv * M;
-      double R[9], t[3];
-      load_pose(poses, vv, R, t);
-      int64_t vid[3];
-      face_vertices(sc, mv, vid);
-      FaceSetup f;
-      setup_face(sc, vid, R, t, vt.v[vv], z_near, r_min, f);        // same inputs: visible again
-      face_normals(f);
-      write_record(sc, vid, f, records + gv * kRecDwords);
-    }
+    if (vis) vis_list[(int64_t)blockIdx.x * kProjBlock + off] = (uint32_t)g;
+    if (threadIdx.x == 0) vis_cnt[blockIdx.x] = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
   }
   // ---- per-tile counts.  A face overlapping at most kSmallTiles tiles takes its slot in each
   //      tile from the returning atomic and records it, so emission needs no atomics for it;
@@ -254,66 +303,80 @@ __global__ __launch_bounds__(256) void k_project(tsr_scene_dev sc, const float* 
   });
 }
 
-// Single workgroup: exclusive scan of the tile counts into ranges, pair total K, overflow
-// check against the capacity, and reset of the counts (reused as emission cursors).
-// Block-wide exclusive scan of 1024 per-thread partial sums (Hillis-Steele in LDS).
-__device__ __forceinline__ unsigned long long block_excl_scan(unsigned long long* part, unsigned long long s,
-                                                              unsigned long long* total) {
-  const int tid = threadIdx.x;
-  part[tid] = s;
-  __syncthreads();
-  for (int o = 1; o < 1024; o <<= 1) {
-    unsigned long long y = tid >= o ? part[tid - o] : 0ull;
-    __syncthreads();
-    part[tid] += y;
-    __syncthreads();
-  }
-  *total = part[1023];
-  const unsigned long long excl = part[tid] - s;
-  __syncthreads();
-  return excl;
-}
+// Single workgroup of 1024 threads: (1) exclusive scan of the visible-face counts of the
+// projection workgroups (offsets of their segments in the dense visible list); (2) exclusive
+// scan of the tile counts into ranges, pair total K, overflow check against the capacity (all
+// ranges empty on overflow), and the small-face counts left in tile_cnt2 as the base of the
+// larger faces' emission cursors.  Both scans run in rounds of 8192 entries, each thread
+// taking 8 consecutive ones.
+constexpr int kScanPer = 8;
+constexpr int kScanRound = 1024 * kScanPer;
 
-// Single workgroup: (1) exclusive scan of the visible-face counts of the projection
-// workgroups (offsets of their segments in the dense visible list); (2) exclusive scan of the
-// tile counts into ranges, pair total K, overflow check against the capacity, and reset of the
-// counts (reused as emission cursors).
-__global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* __restrict__ tile_cnt, uint32_t* __restrict__ tile_cnt2,
-                                                     uint32_t* __restrict__ ranges,
+__global__ __launch_bounds__(1024) void k_scan_tiles(const uint32_t* __restrict__ tile_cnt,
+                                                     uint32_t* __restrict__ tile_cnt2, uint32_t* __restrict__ ranges,
                                                      int n_tiles, int64_t capacity, int64_t* __restrict__ K_out,
                                                      uint32_t* __restrict__ overflow, const uint32_t* __restrict__ vis_cnt,
                                                      uint32_t* __restrict__ vis_off, uint32_t* __restrict__ vis_total,
                                                      int n_segments) {
-  __shared__ unsigned long long part[1024];
-  {
-    const int tid = threadIdx.x;
-    const int chunk = (n_segments + 1023) / 1024;
-    const int lo = min(n_segments, tid * chunk), hi = min(n_segments, lo + chunk);
-    unsigned long long s = 0, tot;
-    for (int i = lo; i < hi; ++i) s += vis_cnt[i];
-    unsigned long long run = block_excl_scan(part, s, &tot);
-    for (int i = lo; i < hi; ++i) {
-      vis_off[i] = (uint32_t)run;
-      run += vis_cnt[i];
-    }
-    if (tid == 0) *vis_total = (uint32_t)tot;
-  }
+  __shared__ unsigned long long wsum[16];
   const int tid = threadIdx.x;
-  const int chunk = (n_tiles + 1023) / 1024;
-  const int lo = min(n_tiles, tid * chunk), hi = min(n_tiles, lo + chunk);
-  unsigned long long s = 0, total;
-  for (int i = lo; i < hi; ++i) s += tile_cnt[i] + tile_cnt2[i];
-  unsigned long long run = block_excl_scan(part, s, &total);
-  const bool over = total > (unsigned long long)capacity;
-  for (int i = lo; i < hi; ++i) {
-    const uint32_t cs = tile_cnt[i], c = cs + tile_cnt2[i];
-    ranges[2 * i] = over ? 0u : (uint32_t)run;
-    ranges[2 * i + 1] = over ? 0u : (uint32_t)(run + c);
-    run += c;
-    tile_cnt2[i] = cs;               // larger faces are emitted after the recorded slots
+  unsigned long long carry = 0, tot;
+  for (int base = 0; base < n_segments; base += kScanRound) {
+    const int i0 = base + tid * kScanPer;
+    uint32_t c[kScanPer];
+    unsigned long long sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      c[k] = (i0 + k < n_segments) ? vis_cnt[i0 + k] : 0u;
+      sum += c[k];
+    }
+    unsigned long long run = carry + block_excl_scan_u64(sum, wsum, &tot);
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      if (i0 + k < n_segments) vis_off[i0 + k] = (uint32_t)run;
+      run += c[k];
+    }
+    carry += tot;
+  }
+  if (tid == 0) *vis_total = (uint32_t)carry;
+
+  carry = 0;
+  for (int base = 0; base < n_tiles; base += kScanRound) {
+    const int i0 = base + tid * kScanPer;
+    uint32_t cs[kScanPer], cb[kScanPer];
+    unsigned long long sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      const bool in = i0 + k < n_tiles;
+      cs[k] = in ? tile_cnt[i0 + k] : 0u;
+      cb[k] = in ? tile_cnt2[i0 + k] : 0u;
+      sum += (unsigned long long)cs[k] + cb[k];
+    }
+    unsigned long long run = carry + block_excl_scan_u64(sum, wsum, &tot);
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      if (i0 + k < n_tiles) {
+        const unsigned long long c = (unsigned long long)cs[k] + cb[k];
+        ranges[2 * (i0 + k)] = (uint32_t)run;
+        ranges[2 * (i0 + k) + 1] = (uint32_t)(run + c);
+        tile_cnt2[i0 + k] = cs[k];           // larger faces are emitted after the recorded slots
+        run += c;
+      }
+    }
+    carry += tot;
+  }
+  const bool over = carry > (unsigned long long)capacity;
+  if (over) {
+    // same thread-to-entry mapping as above, so these stores land after the ones they replace
+    for (int base = 0; base < n_tiles; base += kScanRound) {
+      const int i0 = base + tid * kScanPer;
+#pragma unroll
+      for (int k = 0; k < kScanPer; ++k)
+        if (i0 + k < n_tiles) ranges[2 * (i0 + k)] = ranges[2 * (i0 + k) + 1] = 0u;
+    }
   }
   if (tid == 0) {
-    *K_out = (int64_t)total;
+    *K_out = (int64_t)carry;
     overflow[0] = over ? 1u : 0u;     // this binning
     if (over) overflow[2] = 1u;       // sticky until tsr_check reads it (spans graph replays)
   }

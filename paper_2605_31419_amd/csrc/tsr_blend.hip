@@ -437,8 +437,7 @@ __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float*
   const int64_t N = sc.n_vertices;
   const int64_t nf = (int64_t)vt.n_views * M;
   const int64_t total = min((int64_t)*vis_total, nf);
-  const int64_t i0 = (int64_t)blockIdx.x * blockDim.x;
-  if (i0 >= total) return;                                          // whole workgroup past the list
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < total; i0 += (int64_t)gridDim.x * blockDim.x) {
   const int64_t i = i0 + threadIdx.x;
   double pose6[6] = {0, 0, 0, 0, 0, 0};
   int v = -1;
@@ -614,14 +613,24 @@ __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float*
       __syncthreads();
     }
   }
+  }
 }
 
 // Per face: sum the staged vertex gradients over the views that see it and write them.
 // Soups write every vertex once (zero for faces no view sees); indexed meshes add into
-// zero-filled outputs.
+// zero-filled outputs.  Workgroup 0 also converts the FP64 pose and loss sums (complete once
+// the face backward has finished) to the float outputs.
 __global__ __launch_bounds__(256) void k_vertex_gather(tsr_scene_dev sc, ViewTable vt, const uint32_t* __restrict__ counts,
                                                        const acc_t* __restrict__ grad_acc, float* __restrict__ grad_pos,
-                                                       float* __restrict__ grad_col, float* __restrict__ grad_opa) {
+                                                       float* __restrict__ grad_col, float* __restrict__ grad_opa,
+                                                       const double* __restrict__ pose_acc, float* __restrict__ grad_pose,
+                                                       const double* __restrict__ loss_acc, float* __restrict__ loss) {
+  if (blockIdx.x == 0) {
+    if (grad_pose)
+      for (int k = threadIdx.x; k < 6 * vt.n_views; k += blockDim.x) grad_pose[k] = (float)pose_acc[k];
+    if (loss)
+      for (int k = threadIdx.x; k < vt.n_views; k += blockDim.x) loss[k] = (float)loss_acc[k];
+  }
   const int64_t M = vt.n_faces;
   const int64_t N = sc.n_vertices;
   const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -660,59 +669,64 @@ __global__ __launch_bounds__(256) void k_vertex_gather(tsr_scene_dev sc, ViewTab
   }
 }
 
-// Zero the gradient accumulators of the visible (view, face) pairs, and the per-view FP64
-// pose and loss accumulators.
-__global__ void k_zero_acc(ViewTable vt, const uint32_t* __restrict__ vis_total,
-                           const uint32_t* __restrict__ vis_dense, acc_t* __restrict__ grad_acc,
-                           double* __restrict__ pose_acc, double* __restrict__ loss_acc) {
+// Longest-first tile order by one workgroup: counting sort of the tiles by list length
+// (lengths above kOrderBuckets - 1 share the top bucket), descending.  `hist` is kOrderBuckets
+// shared counters, `wsum` 16 shared slots; blockDim.x divides kOrderBuckets.
+__device__ void build_tile_order(const uint32_t* __restrict__ ranges, int n_tiles, int* __restrict__ order,
+                                 uint32_t* hist, unsigned long long* wsum) {
+  const int nb = blockDim.x;
+  for (int b = threadIdx.x; b < kOrderBuckets; b += nb) hist[b] = 0u;
+  __syncthreads();
+  // bucket kOrderBuckets - 1 - length: an ascending scan then places long lists first
+  for (int t = threadIdx.x; t < n_tiles; t += nb) {
+    const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+    atomicAdd(&hist[kOrderBuckets - 1 - (int)min(len, (uint32_t)kOrderBuckets - 1u)], 1u);
+  }
+  __syncthreads();
+  const int per = kOrderBuckets / nb;
+  unsigned long long sum = 0, tot;
+  for (int k = 0; k < per; ++k) sum += hist[threadIdx.x * per + k];
+  unsigned long long run = block_excl_scan_u64(sum, wsum, &tot);
+  for (int k = 0; k < per; ++k) {
+    const uint32_t h = hist[threadIdx.x * per + k];
+    hist[threadIdx.x * per + k] = (uint32_t)run;
+    run += h;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < n_tiles; t += nb) {
+    const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+    const uint32_t pos = atomicAdd(&hist[kOrderBuckets - 1 - (int)min(len, (uint32_t)kOrderBuckets - 1u)], 1u);
+    order[pos] = t;
+  }
+}
+
+// Set-up of a backward pass: zero the gradient accumulators of the visible (view, face) pairs
+// (one 16-byte store per thread, grid-stride); workgroup 0 also zeroes the per-view FP64 pose
+// and loss accumulators and the persistent kernel's queue counter, and builds the
+// longest-first tile order when `order` is given.
+__global__ __launch_bounds__(256) void k_prep_bwd(ViewTable vt, const uint32_t* __restrict__ vis_total,
+                                                  const uint32_t* __restrict__ vis_dense, acc_t* __restrict__ grad_acc,
+                                                  double* __restrict__ pose_acc, double* __restrict__ loss_acc,
+                                                  const uint32_t* __restrict__ ranges, int* __restrict__ order,
+                                                  int* __restrict__ queue) {
+  constexpr int kVec = (int)(kGradDwords * sizeof(acc_t)) / 16;      // 16-byte stores per row
   const int64_t nf = (int64_t)vt.n_views * vt.n_faces;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < min((int64_t)*vis_total, nf)) {
-    const int64_t g = (int64_t)vis_dense[i];
-    if (g < nf) {
-      float4* p = reinterpret_cast<float4*>(grad_acc + g * kGradDwords);
-#pragma unroll
-      for (int k = 0; k < (int)(kGradDwords * sizeof(acc_t)) / 16; ++k) p[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-    }
+  const int64_t n = min((int64_t)*vis_total, nf) * kVec;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t g = (int64_t)vis_dense[i / kVec];
+    if (g < nf) reinterpret_cast<float4*>(grad_acc + g * kGradDwords)[i % kVec] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
   if (blockIdx.x == 0) {
     for (int k = threadIdx.x; k < 6 * vt.n_views; k += blockDim.x) pose_acc[k] = 0.0;
     if (loss_acc)
       for (int k = threadIdx.x; k < vt.n_views; k += blockDim.x) loss_acc[k] = 0.0;
-  }
-}
-
-// Longest-first tile order: counting sort of the tiles by list length (lengths above
-// kOrderBuckets - 1 share the top bucket), descending.  One workgroup.
-__global__ __launch_bounds__(1024) void k_tile_order(const uint32_t* __restrict__ ranges, int n_tiles,
-                                                     uint32_t* __restrict__ scratch, int* __restrict__ order) {
-  __shared__ uint32_t hist[kOrderBuckets];
-  __shared__ uint32_t base[kOrderBuckets];
-  for (int b = threadIdx.x; b < kOrderBuckets; b += blockDim.x) hist[b] = 0u;
-  __syncthreads();
-  for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) {
-    const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
-    atomicAdd(&hist[min(len, (uint32_t)kOrderBuckets - 1u)], 1u);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {          // descending exclusive scan (1024 entries, once per launch)
-    uint32_t run = 0;
-    for (int b = kOrderBuckets - 1; b >= 0; --b) {
-      base[b] = run;
-      run += hist[b];
+    if (queue && threadIdx.x == 0) *queue = 0;
+    if (order) {
+      __shared__ uint32_t hist[kOrderBuckets];
+      __shared__ unsigned long long wsum[16];
+      build_tile_order(ranges, vt.n_tiles, order, hist, wsum);
     }
   }
-  __syncthreads();
-  for (int t = threadIdx.x; t < n_tiles; t += blockDim.x) {
-    const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
-    const uint32_t pos = atomicAdd(&base[min(len, (uint32_t)kOrderBuckets - 1u)], 1u);
-    order[pos] = t;
-  }
-  (void)scratch;
-}
-
-__global__ void k_zero_i32(int* __restrict__ p, int n) {
-  if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
 
 __global__ void k_fill_f32(float* __restrict__ p, int64_t n) {
@@ -816,9 +830,16 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
   double* pose_acc = reinterpret_cast<double*>(ws + L.pose_acc);
   double* loss_acc = reinterpret_cast<double*>(ws + L.loss_acc);
   const int64_t nf = (int64_t)vt.n_views * vt.n_faces;
-  const dim3 face_grid(nf > 0 ? grid_for(nf, 256) : 1);          // covers the dense visible list
-  TSR_LAUNCH("zero_acc", k_zero_acc, face_grid, dim3(256), 0, st, vt, vis_total, vis_dense, grad_acc, pose_acc,
-             loss_acc);
+  int* order = nullptr;
+  int* queue = nullptr;
+  if (fused_train && sched.order) order = reinterpret_cast<int*>(ws + L.order);
+  if (fused_train && sched.persistent) queue = reinterpret_cast<int*>(ws + L.hdr_queue);
+  {
+    const int64_t rows16 = nf * (int64_t)((kGradDwords * sizeof(acc_t)) / 16);
+    const unsigned g = (unsigned)std::min<int64_t>(std::max<int64_t>(grid_for(rows16, 256), 1), 2048);
+    TSR_LAUNCH("prep_bwd", k_prep_bwd, dim3(g), dim3(256), 0, st, vt, vis_total, vis_dense, grad_acc, pose_acc,
+               loss_acc, ranges, order, queue);
+  }
   const dim3 block(kBlock);
   const int sm = sigma_mode(p.sigma);
   if (!fused_train) {
@@ -827,21 +848,9 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
     switch (sm) { case 1: TSR_BWD(1); break; case 2: TSR_BWD(2); break; case 3: TSR_BWD(3); break; default: TSR_BWD(0); }
 #undef TSR_BWD
   } else {
-    const int* order = nullptr;
-    int* queue = nullptr;
     dim3 grid(tile_grid(vt.n_tiles));
-    if (sched.order) {
-      int* ord = reinterpret_cast<int*>(ws + L.order);
-      TSR_LAUNCH("tile_order", k_tile_order, dim3(1), dim3(1024), 0, st, ranges, vt.n_tiles,
-                 reinterpret_cast<uint32_t*>(ws + L.order_hist), ord);
-      order = ord;
-      if (!sched.persistent) grid = dim3(vt.n_tiles);
-    }
-    if (sched.persistent) {
-      queue = reinterpret_cast<int*>(ws + L.hdr_queue);
-      grid = dim3(sched.grid > 0 ? sched.grid : 2048);
-      TSR_LAUNCH("zero_queue", k_zero_i32, dim3(1), dim3(64), 0, st, queue, 1);
-    }
+    if (sched.order && !sched.persistent) grid = dim3(vt.n_tiles);
+    if (sched.persistent) grid = dim3(sched.grid > 0 ? sched.grid : 2048);
 #define TSR_TRAIN(S) TSR_LAUNCH("train_fused", k_train_fused<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, p.w_color, p.w_depth, tcolor, tdepth, color, depth, trans, loss ? loss_acc : nullptr, grad_acc, order, queue, sched.persistent)
     switch (sm) { case 1: TSR_TRAIN(1); break; case 2: TSR_TRAIN(2); break; case 3: TSR_TRAIN(3); break; default: TSR_TRAIN(0); }
 #undef TSR_TRAIN
@@ -856,17 +865,19 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
     if (grad_opa) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(2048), dim3(256), 0, st, grad_opa, N);
   }
   if (nf > 0) {
-    TSR_LAUNCH("face_bwd", k_face_bwd, face_grid, dim3(256), 0, st, sc, poses, vt, vis_total, vis_dense, records,
+    const dim3 fgrid(std::min<unsigned>(grid_for(nf, 256), 2048u));
+    TSR_LAUNCH("face_bwd", k_face_bwd, fgrid, dim3(256), 0, st, sc, poses, vt, vis_total, vis_dense, records,
                grad_acc, grad_pose ? pose_acc : nullptr, want_vertices ? 1 : 0);
     if (want_vertices)
       TSR_LAUNCH("vertex_gather", k_vertex_gather, dim3(grid_for(vt.n_faces, 256)), dim3(256), 0, st, sc, vt, counts,
-                 grad_acc, grad_pos, grad_col, grad_opa);
+                 grad_acc, grad_pos, grad_col, grad_opa, pose_acc, grad_pose, loss_acc, loss);
   } else if (want_vertices && !sc.faces) {
     if (grad_pos) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(2048), dim3(256), 0, st, grad_pos, 3 * N);
     if (grad_col) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(2048), dim3(256), 0, st, grad_col, 3 * N);
     if (grad_opa) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(2048), dim3(256), 0, st, grad_opa, N);
   }
-  TSR_LAUNCH("finalize", k_finalize, dim3(1), dim3(256), 0, st, pose_acc, grad_pose, loss_acc, loss, vt.n_views);
+  if ((nf <= 0 || !want_vertices) && (grad_pose || loss))     // otherwise k_vertex_gather converts them
+    TSR_LAUNCH("finalize", k_finalize, dim3(1), dim3(256), 0, st, pose_acc, grad_pose, loss_acc, loss, vt.n_views);
   return hipGetLastError();
 }
 

@@ -138,4 +138,35 @@ __device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_read
 
 __device__ __forceinline__ unsigned long long ballot(bool p) { return __ballot(p); }
 
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ unsigned long long wave_incl_scan_u64(unsigned long long v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const unsigned long long y = __shfl_up(v, (unsigned)o, 64);
+    if (lane >= o) v += y;
+  }
+  return v;
+}
+
+// Exclusive prefix sum of one value per thread over the workgroup (blockDim.x a multiple of
+// 64, at most 1024), and the workgroup total.  `wsum` is 16 shared slots.  Every thread of the
+// workgroup must call it; it contains two barriers, after which `wsum` may be reused.
+__device__ __forceinline__ unsigned long long block_excl_scan_u64(unsigned long long s, unsigned long long* wsum,
+                                                                  unsigned long long* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const unsigned long long inc = wave_incl_scan_u64(s);
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  unsigned long long before = 0, tot = 0;
+  for (int i = 0; i < nw; ++i) {
+    const unsigned long long x = wsum[i];
+    if (i < w) before += x;
+    tot += x;
+  }
+  __syncthreads();
+  *total = tot;
+  return before + inc - s;
+}
+
 }  // namespace tsr

@@ -44,7 +44,6 @@ struct WsLayout {
   size_t vis_dense;                // uint32 [V*M]: the same ids, compacted (first vis_total entries)
   size_t ranges;                   // uint32 [T][2]
   size_t order;                    // int32  [T] tile schedule (longest lists first)
-  size_t order_hist;               // uint32 [2][kOrderBuckets]
   size_t n_last;                   // int32  [P]
   size_t t_last;                   // float  [P]
   size_t fixed_end;
@@ -54,10 +53,10 @@ struct WsLayout {
   int64_t capacity;
 };
 
-constexpr int kOrderBuckets = 1024;
+constexpr int kOrderBuckets = 1024;    // tile-length buckets of the longest-first schedule
 constexpr int kProjBlock = 256;        // faces per projection workgroup (one visible-list segment each)
 constexpr int kRegSortMax = 1024;      // tile lists up to this length are sorted in registers
-constexpr int kSmallTiles = 4;         // faces overlapping at most this many tiles record their slots   // tile-length buckets of the longest-first schedule
+constexpr int kSmallTiles = 4;         // faces overlapping at most this many tiles record their slots
 
 // Training-kernel schedule (chosen by the autotuner; the default is one workgroup per tile).
 struct TrainSchedule {

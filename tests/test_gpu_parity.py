@@ -81,6 +81,52 @@ def _offscreen_scene():
     return plain_scene(v)
 
 
+def _boundary_scene(intr, pose, seed=0, z_near=0.1):
+    """Faces placed on the culling boundaries, built in camera space and mapped to the world
+    through a rotated pose (so the float32 world coordinates round differently from the
+    camera-space ones): sub-pixel faces whose pixel range starts or ends within 1e-6..1e-3 px
+    of a pixel centre, at the image borders and inside it, in u and in v; and faces whose
+    nearest vertex sits within 1e-7..1e-4 relative of the near plane."""
+    g = np.random.default_rng(seed)
+    W, H = intr.width, intr.height
+    tri = []
+    deltas = [-1e-3, -1e-4, -1e-5, -1e-6, 0.0, 1e-6, 1e-5, 1e-4, 1e-3]
+    cols = [0, 1, W // 2, W - 2, W - 1]
+    rows = [0, 1, H // 2, H - 2, H - 1]
+    for c in cols:
+        for r in rows:
+            for d in deltas:
+                z = g.uniform(0.3, 4.0)
+                # range starting just after (d > 0) or at/before (d <= 0) column c, then ending just before c
+                tri.append(([c + d, r - 0.3], [c + 0.4, r], [c + d, r + 0.3], z))
+                tri.append(([c - 0.4, r - 0.3], [c - d, r], [c - 0.4, r + 0.3], z))
+                # the same in v
+                tri.append(([c - 0.3, r + d], [c, r + 0.4], [c + 0.3, r + d], z))
+                tri.append(([c - 0.3, r - 0.4], [c, r - d], [c + 0.3, r - 0.4], z))
+    pts = []
+    for a, b, c2, z in tri:
+        pts.append([[(u - intr.cx) * z / intr.fx, (v - intr.cy) * z / intr.fy, z] for u, v in (a, b, c2)])
+    for eps in [-1e-4, -1e-5, -1e-6, -1e-7, 1e-7, 1e-6, 1e-5, 1e-4]:
+        for _ in range(12):
+            zn = z_near * (1.0 + eps)
+            u, v = g.uniform(10, W - 10), g.uniform(10, H - 10)
+            q = np.array([[u, v], [u + 5, v + 1], [u + 2, v + 6]])
+            zs = np.array([zn, zn * 1.02, zn * 1.05])
+            pts.append([[(qq[0] - intr.cx) * zz / intr.fx, (qq[1] - intr.cy) * zz / intr.fy, zz] for qq, zz in zip(q, zs)])
+    cam = np.array(pts, np.float64)                                   # [F, 3, 3] camera space
+    R = pose[:9].astype(np.float64).reshape(3, 3)
+    t = pose[9:].astype(np.float64)
+    world = np.einsum("ji,fkj->fki", R, cam - t)                     # R^T (c - t)
+    n = world.shape[0]
+    return plain_scene(world, col=g.uniform(0, 1, (n, 3, 3)), opa=g.uniform(0.3, 1, (n, 3)))
+
+
+def _boundary_case():
+    intr = S.intrinsics_for(1200, 680)
+    pose = S.look_pose([1.3, 0.7, 1.4], 0.7, 0.2)
+    return _boundary_scene(intr, pose), [pose], [intr]
+
+
 def _with_identity(sc, intr):
     return sc, [IDENTITY], [intr]
 
@@ -94,6 +140,7 @@ CASES = {
     "long_tile_5000": lambda: (_long_tile_scene(5000), [IDENTITY], [S.Intrinsics(16, 16, 20.0, 20.0, 7.5, 7.5)]),
     "long_tile_12000": lambda: (_long_tile_scene(12000, 3), [IDENTITY], [S.Intrinsics(16, 16, 20.0, 20.0, 7.5, 7.5)]),
     "offscreen": lambda: (_offscreen_scene(), [IDENTITY], [S.intrinsics_for(64, 48)]),
+    "culling_boundaries_1200x680": _boundary_case,
     "multi_view_mixed": lambda: (tiny_scene(7, n_faces=80, w=40, h=30)[0], [IDENTITY, IDENTITY, IDENTITY],
                                  [S.Intrinsics(40, 30, 30.0, 30.0, 19.5, 14.5), S.Intrinsics(33, 17, 25.0, 25.0, 16.0, 8.0),
                                   S.Intrinsics(64, 48, 45.0, 45.0, 31.5, 23.5)]),
