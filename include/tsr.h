@@ -39,7 +39,10 @@
  *       TSR_ECAPACITY  more (tile, face) pairs than the workspace holds.  Detected on the
  *                      device: tsr_bin_and_sort then leaves every tile list empty (all later
  *                      kernels do no work), and the condition is reported by tsr_check;
- *       TSR_EHIP       a HIP runtime call or launch failed (message has the HIP error).
+ *       TSR_EHIP       a HIP runtime call or launch failed (message has the HIP error);
+ *       TSR_EINTERNAL  a device-side consistency check of the binning failed (a tile slot
+ *                      outside its tile's range; the pair is dropped, never written out of
+ *                      bounds); reported by tsr_check.
  *   - NaN or infinite inputs give unspecified image values but no fault.  Faces with a
  *     vertex closer than z_near, or with inradius below r_min pixels, are culled.
  *     Opacities are used as given (the caller applies any activation).
@@ -67,6 +70,7 @@ extern "C" {
 #define TSR_EWORKSPACE (-2)
 #define TSR_ECAPACITY (-3)
 #define TSR_EHIP (-4)
+#define TSR_EINTERNAL (-5)
 
 #define TSR_MAX_VIEWS 32
 #define TSR_TILE 16

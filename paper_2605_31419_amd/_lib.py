@@ -18,6 +18,7 @@ TSR_EINVAL = -1
 TSR_EWORKSPACE = -2
 TSR_ECAPACITY = -3
 TSR_EHIP = -4
+TSR_EINTERNAL = -5
 TSR_MAX_VIEWS = 32
 TSR_TILE = 16
 

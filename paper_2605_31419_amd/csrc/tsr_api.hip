@@ -412,6 +412,7 @@ int tsr_check(const void* ws, void* stream, int64_t* n_pairs) {
         (e = hipStreamSynchronize(st)) != hipSuccess)
       return hip_fail(e, "tsr_check clear");
   }
+  if (h.sticky & 2u) return fail(TSR_EINTERNAL, "a binning found a tile slot outside its tile's range");
   if (h.overflow || h.sticky)
     return fail(TSR_ECAPACITY, "a binning produced more pairs than the workspace capacity (last K = %lld)", (long long)h.k);
   return TSR_OK;

@@ -382,23 +382,29 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(const uint32_t* __restrict_
   }
 }
 
-// Emission of (float32 z_F bits << 32 | face) into each overlapped tile's bucket.
+// Emission of (float32 z_F bits << 32 | face) into each overlapped tile's bucket.  One
+// workgroup per projection workgroup, one lane per visible face of its segment (compacted,
+// in g order).  Small faces store at their recorded slot; larger faces take positions from
+// the per-tile cursors, spread over the wave.  A position outside its tile's range (never
+// expected) is not written and is reported through tsr_check.
 __global__ __launch_bounds__(256) void k_emit(ViewTable vt, const uint32_t* __restrict__ counts,
                                               const float* __restrict__ records, const uint32_t* __restrict__ ranges,
-                                              const uint32_t* __restrict__ slots, uint32_t* __restrict__ cursor,
-                                              const uint32_t* __restrict__ overflow,
+                                              const uint32_t* __restrict__ slots,
+                                              uint32_t* __restrict__ cursor, uint32_t* __restrict__ overflow,
                                               uint64_t* __restrict__ pairs, const uint32_t* __restrict__ vis_cnt,
                                               const uint32_t* __restrict__ vis_off, const uint32_t* __restrict__ vis_list,
                                               uint32_t* __restrict__ vis_dense) {
-  // the visible-face segment of the projection workgroup with the same index goes to its
-  // place in the dense list (done even when the pairs overflowed: the backward uses it)
-  if (threadIdx.x < vis_cnt[blockIdx.x])
-    vis_dense[vis_off[blockIdx.x] + threadIdx.x] = vis_list[(int64_t)blockIdx.x * kProjBlock + threadIdx.x];
-  if (*overflow) return;
+  const uint32_t nvis = vis_cnt[blockIdx.x];
+  int64_t g = 0;
+  if (threadIdx.x < nvis) {
+    g = (int64_t)vis_list[(int64_t)blockIdx.x * kProjBlock + threadIdx.x];
+    // the segment goes to its place in the dense list (done even when the pairs overflowed:
+    // the backward uses it)
+    vis_dense[vis_off[blockIdx.x] + threadIdx.x] = (uint32_t)g;
+  }
+  if (overflow[0]) return;
   const int64_t M = vt.n_faces;
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool live = g < (int64_t)vt.n_views * M;
-  int ntiles = live ? (int)counts[g] : 0;
+  const int ntiles = threadIdx.x < nvis ? (int)counts[g] : 0;
   int tx0 = 0, ty0 = 0, tw = 1, tile_base = 0, tiles_x = 1;
   uint64_t key = 0;
   if (ntiles > 0) {
@@ -417,9 +423,16 @@ __global__ __launch_bounds__(256) void k_emit(ViewTable vt, const uint32_t* __re
     // slots recorded during counting: plain stores
     const uint4 sl = *reinterpret_cast<const uint4*>(slots + g * kSmallTiles);
     const uint32_t slv[4] = {sl.x, sl.y, sl.z, sl.w};
+    bool bad = false;
 #pragma unroll
     for (int i = 0; i < kSmallTiles; ++i)
-      if (i < ntiles) pairs[ranges[2 * (tile_base + (ty0 + i / tw) * tiles_x + tx0 + i % tw)] + slv[i]] = key;
+      if (i < ntiles) {
+        const int t = tile_base + (ty0 + i / tw) * tiles_x + tx0 + i % tw;
+        const uint32_t pos = ranges[2 * t] + slv[i];
+        if (pos < ranges[2 * t + 1]) pairs[pos] = key;
+        else bad = true;
+      }
+    if (bad) atomicOr(&overflow[2], 2u);          // reported by tsr_check; nothing written
   }
   const int big = ntiles > kSmallTiles ? ntiles : 0;
   if (wave_max_int(big) == 0) return;
@@ -431,7 +444,8 @@ __global__ __launch_bounds__(256) void k_emit(ViewTable vt, const uint32_t* __re
     if (valid) {
       const int t = obase + (oty0 + i / otw) * otx + otx0 + i % otw;
       const uint32_t pos = ranges[2 * t] + atomicAdd(&cursor[t], 1u);
-      pairs[pos] = ((uint64_t)khi << 32) | klo;
+      if (pos < ranges[2 * t + 1]) pairs[pos] = ((uint64_t)khi << 32) | klo;
+      else atomicOr(&overflow[2], 2u);
     }
   });
 }
@@ -712,8 +726,8 @@ hipError_t launch_bin(const tsr_scene_dev& sc, const float* poses, const ViewTab
   uint32_t* tile_cnt2 = reinterpret_cast<uint32_t*>(ws + L.tile_cnt2);
   uint32_t* slots = reinterpret_cast<uint32_t*>(ws + L.slots);
   // both tile counters and the long-tile counter are contiguous: one fill
-  TSR_LAUNCH("fill_tiles", k_fill_u32, dim3(grid_for(2 * vt.n_tiles + 1, 256)), dim3(256), 0, st, tile_cnt,
-             (int64_t)(2 * vt.n_tiles + 1), 0u);
+  const int64_t n_cnt = 2 * (int64_t)vt.n_tiles + 1;
+  TSR_LAUNCH("fill_tiles", k_fill_u32, dim3(grid_for(n_cnt, 256)), dim3(256), 0, st, tile_cnt, n_cnt, 0u);
   if (nf > 0)
     TSR_LAUNCH("project", k_project, dim3(grid_for(nf, kProjBlock)), dim3(kProjBlock), 0, st, sc, poses, vt, p.z_near, p.r_min, counts,
                        records, tile_cnt, tile_cnt2, slots, vis_cnt, vis_list);

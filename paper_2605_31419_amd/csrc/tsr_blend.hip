@@ -483,17 +483,23 @@ __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float*
       len[k] = sqrt(e[k][0] * e[k][0] + e[k][1] * e[k][1]);
       perim += len[k];
     }
-    const double r = area / perim;
+    // reciprocals once: the chain rule below multiplies (its results are compared within a
+    // relative tolerance, not bit for bit)
+    const double inv_perim = 1.0 / perim;
+    const double r = area * inv_perim;
+    const double inv_r = 1.0 / r;
+    double inv_len[3];
+    for (int k = 0; k < 3; ++k) inv_len[k] = 1.0 / len[k];
     for (int k = 0; k < 3; ++k) {
-      n[k][0] = so * e[k][1] / len[k];
-      n[k][1] = -so * e[k][0] / len[k];
+      n[k][0] = so * e[k][1] * inv_len[k];
+      n[k][1] = -so * e[k][0] * inv_len[k];
     }
     const double U0 = (double)__float_as_int(rec[kRecU0]), V0 = (double)__float_as_int(rec[kRecV0]);
     double ca[3], cb[3], cc[3];       // edge coefficients a_k, b_k, c_k
     for (int k = 0; k < 3; ++k) {
-      ca[k] = -n[k][0] / r;
-      cb[k] = -n[k][1] / r;
-      cc[k] = -(n[k][0] * (U0 - q[k][0]) + n[k][1] * (V0 - q[k][1])) / r;
+      ca[k] = -n[k][0] * inv_r;
+      cb[k] = -n[k][1] * inv_r;
+      cc[k] = -(n[k][0] * (U0 - q[k][0]) + n[k][1] * (V0 - q[k][1])) * inv_r;
     }
     double colv[3][3];                // vertex colours [vertex][ch]
     for (int k = 0; k < 3; ++k)
@@ -510,14 +516,14 @@ __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float*
       const int o = (k + 2) % 3;
       for (int ch = 0; ch < 3; ++ch) {
         const double GP = (double)A[kGCol + 3 * ch], GQ = (double)A[kGCol + 3 * ch + 1], GR = (double)A[kGCol + 3 * ch + 2];
-        const double beta = len[k] * colv[o][ch] / perim;
+        const double beta = len[k] * colv[o][ch] * inv_perim;
         gA[k] += beta * GP;
         gB[k] += beta * GQ;
         gCc[k] += beta * GR;
         const double gbeta = GP * ca[k] + GQ * cb[k] + GR * cc[k];
-        gcolv[o][ch] += gbeta * len[k] / perim;
-        glen[k] += gbeta * colv[o][ch] / perim;
-        gperim -= gbeta * beta / perim;
+        gcolv[o][ch] += gbeta * len[k] * inv_perim;
+        glen[k] += gbeta * colv[o][ch] * inv_perim;
+        gperim -= gbeta * beta * inv_perim;
       }
     }
     // ---- reverse: edge coefficients a = -n_x / r, b = -n_y / r, c = -n.(anchor - q_k) / r
@@ -525,28 +531,28 @@ __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float*
     double gr = 0.0;
     double gn[3][2];
     for (int k = 0; k < 3; ++k) {
-      gn[k][0] = -(gA[k] + gCc[k] * (U0 - q[k][0])) / r;
-      gn[k][1] = -(gB[k] + gCc[k] * (V0 - q[k][1])) / r;
-      gq[k][0] += gCc[k] * n[k][0] / r;
-      gq[k][1] += gCc[k] * n[k][1] / r;
-      gr -= (gA[k] * ca[k] + gB[k] * cb[k] + gCc[k] * cc[k]) / r;
+      gn[k][0] = -(gA[k] + gCc[k] * (U0 - q[k][0])) * inv_r;
+      gn[k][1] = -(gB[k] + gCc[k] * (V0 - q[k][1])) * inv_r;
+      gq[k][0] += gCc[k] * n[k][0] * inv_r;
+      gq[k][1] += gCc[k] * n[k][1] * inv_r;
+      gr -= (gA[k] * ca[k] + gB[k] * cb[k] + gCc[k] * cc[k]) * inv_r;
     }
     // ---- n_k = so (e_y, -e_x) / |e|
     double ge[3][2];
     for (int k = 0; k < 3; ++k) {
       const double dot = gn[k][0] * n[k][0] + gn[k][1] * n[k][1];
-      const double gmx = (gn[k][0] - dot * n[k][0]) / len[k];
-      const double gmy = (gn[k][1] - dot * n[k][1]) / len[k];
+      const double gmx = (gn[k][0] - dot * n[k][0]) * inv_len[k];
+      const double gmy = (gn[k][1] - dot * n[k][1]) * inv_len[k];
       ge[k][0] = -so * gmy;
       ge[k][1] = so * gmx;
     }
     // ---- r = area / perim; perim = sum len
-    const double garea = gr / perim;
-    gperim += -gr * r / perim;
+    const double garea = gr * inv_perim;
+    gperim += -gr * r * inv_perim;
     for (int k = 0; k < 3; ++k) {
       glen[k] += gperim;
-      ge[k][0] += glen[k] * e[k][0] / len[k];
-      ge[k][1] += glen[k] * e[k][1] / len[k];
+      ge[k][0] += glen[k] * e[k][0] * inv_len[k];
+      ge[k][1] += glen[k] * e[k][1] * inv_len[k];
     }
     // ---- area = so * a2, a2 = (q1 - q0) x (q2 - q0)
     const double ga2 = so * garea;
@@ -565,7 +571,7 @@ __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float*
       gq[k][1] -= ge[k][1];
     }
     // ---- projection and depth: q = (fx x / z + cx, fy y / z + cy), z_F = mean z
-    const double gz3 = (double)A[kGZ] / 3.0;
+    const double gz3 = (double)A[kGZ] * (1.0 / 3.0);
     for (int k = 0; k < 3; ++k) {
       const double iz = 1.0 / vc[k][2];
       double gc[3];
@@ -580,7 +586,7 @@ __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float*
       pose6[4] += vc[k][2] * gc[0] - vc[k][0] * gc[2];
       pose6[5] += vc[k][0] * gc[1] - vc[k][1] * gc[0];
     }
-    const double gop = (double)A[kGOpa] / 3.0;
+    const double gop = (double)A[kGOpa] * (1.0 / 3.0);
     if (want_vertices) {
       float* stage = reinterpret_cast<float*>(grad_acc + g * kGradDwords);
       for (int k = 0; k < 3; ++k)
@@ -633,22 +639,31 @@ __global__ __launch_bounds__(256) void k_vertex_gather(tsr_scene_dev sc, ViewTab
   }
   const int64_t M = vt.n_faces;
   const int64_t N = sc.n_vertices;
-  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= M) return;
-  float acc[kStageFloats];
+  const int64_t m0 = (int64_t)blockIdx.x * blockDim.x;
+  const int64_t m = m0 + threadIdx.x;
+  float acc[kStageFloats + 1];
 #pragma unroll
-  for (int k = 0; k < kStageFloats; ++k) acc[k] = 0.f;
+  for (int k = 0; k <= kStageFloats; ++k) acc[k] = 0.f;
   bool any = false;
-  for (int v = 0; v < vt.n_views; ++v) {
-    const int64_t g = (int64_t)v * M + m;
-    if (counts[g] == 0) continue;
-    any = true;
-    const float* stage = reinterpret_cast<const float*>(grad_acc + g * kGradDwords);
+  if (m < M) {
+    for (int v = 0; v < vt.n_views; ++v) {
+      const int64_t g = (int64_t)v * M + m;
+      if (counts[g] == 0) continue;
+      any = true;
+      static_assert(kGradDwords == 20 && sizeof(acc_t) == 4, "a staged row is five 16-byte vectors");
+      const float4* stage = reinterpret_cast<const float4*>(grad_acc + g * kGradDwords);
 #pragma unroll
-    for (int k = 0; k < kStageFloats; ++k) acc[k] += stage[k];
+      for (int q = 0; q < 5; ++q) {
+        const float4 x = stage[q];
+        acc[4 * q] += x.x;
+        acc[4 * q + 1] += x.y;
+        acc[4 * q + 2] += x.z;
+        acc[4 * q + 3] += x.w;
+      }
+    }
   }
   if (sc.faces) {
-    if (!any) return;
+    if (m >= M || !any) return;
     for (int k = 0; k < 3; ++k) {
       const int64_t vi = (int64_t)sc.faces[3 * m + k];
       for (int a = 0; a < 3; ++a) {
@@ -657,15 +672,32 @@ __global__ __launch_bounds__(256) void k_vertex_gather(tsr_scene_dev sc, ViewTab
       }
       if (grad_opa) unsafeAtomicAdd(&grad_opa[vi], acc[18]);
     }
-  } else {
+    return;
+  }
+  // soup: the workgroup's 3 x 256 vertices are contiguous in each of the seven output arrays;
+  // transpose through LDS so that every store instruction writes 256 contiguous bytes
+  __shared__ float s_out[7][3 * 256];
+  if (m < M) {
+#pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const int64_t vi = 3 * m + k;
+#pragma unroll
       for (int a = 0; a < 3; ++a) {
-        if (grad_pos) grad_pos[a * N + vi] = acc[3 * k + a];
-        if (grad_col) grad_col[a * N + vi] = acc[9 + 3 * k + a];
+        s_out[a][3 * threadIdx.x + k] = acc[3 * k + a];
+        s_out[3 + a][3 * threadIdx.x + k] = acc[9 + 3 * k + a];
       }
-      if (grad_opa) grad_opa[vi] = acc[18];
+      s_out[6][3 * threadIdx.x + k] = acc[18];
     }
+  }
+  __syncthreads();
+  const int nv = (int)(3 * min((int64_t)blockDim.x, M - m0));
+  const int64_t v0 = 3 * m0;
+  for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (grad_pos) grad_pos[a * N + v0 + i] = s_out[a][i];
+      if (grad_col) grad_col[a * N + v0 + i] = s_out[3 + a][i];
+    }
+    if (grad_opa) grad_opa[v0 + i] = s_out[6][i];
   }
 }
 
