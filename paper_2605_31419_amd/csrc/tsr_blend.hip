@@ -106,15 +106,33 @@ __device__ __forceinline__ void stage_batch(const float* __restrict__ records, c
   if (threadIdx.x < n) sface[threadIdx.x] = (uint32_t)pairs[b0 + threadIdx.x];
 }
 
-// Faces of the staged batch whose pixel rectangle meets this wave's 8x8 quadrant: lane j
-// tests face j, one ballot gives the wave-uniform 64-bit mask the walks iterate over.
+// Faces of the staged batch that can cover a pixel of this wave's 8x8 quadrant: lane j tests
+// face j, one ballot gives the wave-uniform 64-bit mask the walks iterate over.  A face is
+// kept when its pixel rectangle meets the quadrant and no edge function is negative over the
+// whole intersection box: the maximum of E_k = a dx + b dy + c over the box is at one of its
+// corners, and a face with that maximum below -margin has rho <= 0 (no blend, zero gradient)
+// at every pixel the walks would evaluate, so skipping it changes nothing.  The margin (1e-6 of
+// the magnitude of the terms) exceeds the FP32 rounding of both evaluations.
 __device__ __forceinline__ unsigned long long batch_hit_mask(const float4* srec, int n, int bx, int by) {
   const int j = threadIdx.x & 63;
   bool hit = false;
   if (j < n) {
     const float4 rc = srec[j * 6 + kRecU0 / 4];
     const int u0 = __float_as_int(rc.x), v0 = __float_as_int(rc.y), u1 = __float_as_int(rc.z), v1 = __float_as_int(rc.w);
-    hit = !(u1 < bx || u0 > bx + 7 || v1 < by || v0 > by + 7);
+    const int xl = max(bx, u0), xh = min(bx + 7, u1), yl = max(by, v0), yh = min(by + 7, v1);
+    hit = xl <= xh && yl <= yh;
+    if (hit) {
+      const float* r = reinterpret_cast<const float*>(&srec[j * 6]);
+      const float dxl = (float)(xl - u0), dxh = (float)(xh - u0), dyl = (float)(yl - v0), dyh = (float)(yh - v0);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float a = r[kRecEdge + 3 * k], b = r[kRecEdge + 3 * k + 1], c = r[kRecEdge + 3 * k + 2];
+        const float dx = a > 0.f ? dxh : dxl, dy = b > 0.f ? dyh : dyl;
+        const float emax = fmaf(a, dx, fmaf(b, dy, c));
+        const float margin = 1e-6f * (fabsf(a) * dxh + fabsf(b) * dyh + fabsf(c)) + 1e-30f;
+        hit = hit && !(emax < -margin);
+      }
+    }
   }
   return __ballot(hit);
 }
