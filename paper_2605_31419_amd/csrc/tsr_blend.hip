@@ -47,24 +47,43 @@ struct PixelEval {
   int kstar;       // edge attaining the minimum of E_k (lowest index on ties)
 };
 
-// Evaluates one face at face-local pixel offset (dx, dy).  Identical instructions in the
-// forward and backward walks, so the backward recomputes alpha bit for bit.
+// A face record held in registers (loaded from LDS with six 16-byte reads).
+struct Rec {
+  float f[kRecDwords];
+};
+
+__device__ __forceinline__ void load_rec(const float4* srec, int j, Rec& r) {
+#pragma unroll
+  for (int i = 0; i < kRecDwords / 4; ++i) {
+    const float4 q = srec[j * 6 + i];
+    r.f[4 * i] = q.x;
+    r.f[4 * i + 1] = q.y;
+    r.f[4 * i + 2] = q.z;
+    r.f[4 * i + 3] = q.w;
+  }
+}
+
+// Evaluates one face at face-local pixel offset (dx, dy), without branches; returns whether
+// the pixel is covered (rho > 0 and alpha > 0).  alpha and I are zero when it is not.
+// Identical instructions in the forward and backward walks, so the backward recomputes
+// alpha bit for bit.
 template <int SM>
-__device__ __forceinline__ bool eval_face(const float* __restrict__ r, float dx, float dy, float sigma,
-                                          PixelEval& e) {
+__device__ __forceinline__ bool eval_face(const Rec& rc, float dx, float dy, float sigma, PixelEval& e) {
+  const float* r = rc.f;
   const float E0 = fmaf(r[kRecEdge + 0], dx, fmaf(r[kRecEdge + 1], dy, r[kRecEdge + 2]));
   const float E1 = fmaf(r[kRecEdge + 3], dx, fmaf(r[kRecEdge + 4], dy, r[kRecEdge + 5]));
   const float E2 = fmaf(r[kRecEdge + 6], dx, fmaf(r[kRecEdge + 7], dy, r[kRecEdge + 8]));
   e.kstar = (E0 <= E1 && E0 <= E2) ? 0 : (E1 <= E2 ? 1 : 2);
   e.rho = fminf(E0, fminf(E1, E2));
-  if (!(e.rho > 0.f)) return false;
-  e.I = e.rho >= 1.f ? 1.f : window_pow<SM>(e.rho, sigma);
-  e.alpha = r[kRecOpa] * e.I;
-  if (!(e.alpha > 0.f)) return false;
+  const float I = e.rho >= 1.f ? 1.f : window_pow<SM>(e.rho, sigma);   // meaningless when rho <= 0
+  const float alpha = r[kRecOpa] * I;
+  const bool cov = e.rho > 0.f && alpha > 0.f;
+  e.I = cov ? I : 0.f;
+  e.alpha = cov ? alpha : 0.f;
   e.c0 = fmaf(r[kRecCol + 0], dx, fmaf(r[kRecCol + 1], dy, r[kRecCol + 2]));
   e.c1 = fmaf(r[kRecCol + 3], dx, fmaf(r[kRecCol + 4], dy, r[kRecCol + 5]));
   e.c2 = fmaf(r[kRecCol + 6], dx, fmaf(r[kRecCol + 7], dy, r[kRecCol + 8]));
-  return true;
+  return cov;
 }
 
 // Geometry of this lane's pixel inside the tile.
@@ -162,24 +181,24 @@ __device__ __forceinline__ void forward_walk(const TileCtx& c, const float* __re
     while (mask) {
       const int j = __builtin_ctzll(mask);
       mask &= mask - 1;
-      const float* r = reinterpret_cast<const float*>(&srec[j * 6]);
-      if (!done) {
-        PixelEval e;
-        const float dx = dxb - (float)__float_as_int(r[kRecU0]);
-        const float dy = dyb - (float)__float_as_int(r[kRecV0]);
-        if (eval_face<SM>(r, dx, dy, sigma, e)) {
-          const float w = e.alpha * s.T;
-          s.C0 = fmaf(e.c0, w, s.C0);
-          s.C1 = fmaf(e.c1, w, s.C1);
-          s.C2 = fmaf(e.c2, w, s.C2);
-          s.D = fmaf(r[kRecZ], w, s.D);
-          s.Tb = s.T;
-          s.T = s.T * (1.f - e.alpha);
-          s.last = (int)(b0 + j);
-          // stop once T < t_min; also at T == 0 so the backward never divides by 1 - alpha = 0
-          if (s.T < t_min || s.T == 0.f) done = true;
-        }
-      }
+      Rec rc;
+      load_rec(srec, j, rc);
+      PixelEval e;
+      const float dx = dxb - (float)__float_as_int(rc.f[kRecU0]);
+      const float dy = dyb - (float)__float_as_int(rc.f[kRecV0]);
+      const bool act = eval_face<SM>(rc, dx, dy, sigma, e) && !done;
+      // lanes that do not blend this face keep their state (zero weight, selects)
+      const float w = act ? e.alpha * s.T : 0.f;
+      s.C0 = fmaf(e.c0, w, s.C0);
+      s.C1 = fmaf(e.c1, w, s.C1);
+      s.C2 = fmaf(e.c2, w, s.C2);
+      s.D = fmaf(rc.f[kRecZ], w, s.D);
+      const float Tn = s.T * (1.f - e.alpha);
+      s.Tb = act ? s.T : s.Tb;
+      s.last = act ? (int)(b0 + j) : s.last;
+      // stop once T < t_min; also at T == 0 so the backward never divides by 1 - alpha = 0
+      done = done || (act && (Tn < t_min || Tn == 0.f));
+      s.T = act ? Tn : s.T;
       if (__ballot(!done) == 0) break;
     }
   }
@@ -207,6 +226,7 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
   if (lane == 0) atomicMax(&sint[0], wlast);
   __syncthreads();
   const int top = sint[0];
+  const int k_out = wave_sum20_slot();
   float Tcur = Tb;
   float B0 = 0.f, B1 = 0.f, B2 = 0.f, BD = 0.f, BA = 0.f;
   const float dxb = (float)c.px, dyb = (float)c.py;
@@ -223,13 +243,15 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
       const int j = 63 - __builtin_clzll(mask);
       mask &= ~(1ull << j);
       const int idx = b0 + j;
-      const float* r = reinterpret_cast<const float*>(&srec[j * 6]);
+      Rec rc;
+      load_rec(srec, j, rc);
+      const float* r = rc.f;
       // Every lane evaluates the face; lanes that do not blend it (not covered, or behind
       // their last face) get zero gradient scales, so all 20 sums need no branches.
       const float dx = dxb - (float)__float_as_int(r[kRecU0]);
       const float dy = dyb - (float)__float_as_int(r[kRecV0]);
       PixelEval e;
-      const bool act = (idx <= last) && eval_face<SM>(r, dx, dy, sigma, e);
+      const bool act = eval_face<SM>(rc, dx, dy, sigma, e) && (idx <= last);
       const float alpha = act ? e.alpha : 0.f;
       const float om = 1.f - alpha;
       // T before this face: the stored value at the last face, else T_after / (1 - alpha)
@@ -270,8 +292,7 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
       BA = fmaf(1.f, alpha, om * BA);
       if (__ballot(act) == 0) continue;
 #if TSR_REDUCE_SWAP
-      int k_out;
-      const float tot = wave_sum20(acc, &k_out);
+      const float tot = wave_sum20(acc);
       if (k_out >= 0) unsafeAtomicAdd(&grad_acc[(size_t)sface[j] * kGradDwords + k_out], (acc_t)tot);
 #else
       float sum[kGradDwords];

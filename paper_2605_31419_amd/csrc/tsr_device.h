@@ -103,9 +103,16 @@ __device__ __forceinline__ float row_sum16(float v) {
 //   v_permlane16_swap pairs those vectors again: each 16-lane row then holds one value summed
 //   over all four rows (5 vectors, 4 values each);
 //   a DPP reduction inside each row finishes the sums.
-// Lane 16 r + j (j < 5) returns the total of value index 4 j + {0, 2, 1, 3}[r] in *idx;
-// all other lanes get *idx = -1.  Every lane must be active.
-__device__ __forceinline__ float wave_sum20(const float* v, int* idx) {
+// Lane 16 r + j (j < 5) returns the total of value index 4 j + {0, 2, 1, 3}[r] (the index
+// wave_sum20_slot() gives that lane); other lanes return a partial sum and their slot is -1.
+// Every lane must be active.
+__device__ __forceinline__ int wave_sum20_slot() {
+  const int lane = threadIdx.x & 63, r = lane >> 4, j = lane & 15;
+  const int rmap = (r == 0) ? 0 : (r == 1 ? 2 : (r == 2 ? 1 : 3));
+  return j < 5 ? 4 * j + rmap : -1;
+}
+
+__device__ __forceinline__ float wave_sum20(const float* v) {
   float s[10];
 #pragma unroll
   for (int i = 0; i < 10; ++i) {
@@ -120,12 +127,10 @@ __device__ __forceinline__ float wave_sum20(const float* v, int* idx) {
                                                     false);
     t[j] = row_sum16(__uint_as_float(p[0]) + __uint_as_float(p[1]));
   }
-  const int lane = threadIdx.x & 63, r = lane >> 4, j = lane & 15;
+  const int j = threadIdx.x & 15;
   float out = t[0];
 #pragma unroll
   for (int k = 1; k < 5; ++k) out = j == k ? t[k] : out;
-  const int rmap = (r == 0) ? 0 : (r == 1 ? 2 : (r == 2 ? 1 : 3));
-  *idx = j < 5 ? 4 * j + rmap : -1;
   return out;
 }
 
