@@ -188,7 +188,7 @@ def bin_sort_bytes(M, V, m_vis, K, n_tiles):
     return M * 36 + m_vis * 96 + V * M * 8 + K * 12 + K * 24 + K * 8 + n_tiles * 8
 
 
-def tracking_leg(raster, w, dev, iters=100):
+def tracking_leg(raster, w, dev, iters=100, schedule=None):
     """Tracking stress: `iters` pose-gradient iterations (bin, fused fwd+L1+bwd with pose
     gradient only, device pose step) captured once into a graph and replayed."""
     import torch
@@ -201,7 +201,7 @@ def tracking_leg(raster, w, dev, iters=100):
     tr.fit(tp)
     tr.bin_and_sort(tp)
     tc, td, _ = tr.forward(tp)
-    trk = Tracker(dev, intr, iters=iters)
+    trk = Tracker(dev, intr, iters=iters, schedule=schedule)
     p0 = torch.as_tensor(w.poses[0], device="cuda")
     trk.set_frame(p0, tc, td)
     trk.capture()
@@ -365,7 +365,7 @@ def main():
 
     tracking = None
     if not args.no_track:
-        tracking = tracking_leg(raster, w, dev)
+        tracking = tracking_leg(raster, w, dev, schedule=single.rast.schedule)
         log(f"[bench] tracking graph: {tracking['ms_per_iteration']:.3f} ms/iteration over {tracking['iterations']}")
     serving = None
     if not args.no_serve:

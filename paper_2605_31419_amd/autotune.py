@@ -1,9 +1,9 @@
 """Autotuner for the tile schedule of the fused training kernel.
 
-The fused kernel (forward walk, L1 seeds, backward walk per tile) can run one workgroup per
-tile in XCD-interleaved id order, one workgroup per tile in longest-list-first order, or as
-persistent workgroups pulling tiles from a device queue in either order, with a chosen number
-of workgroups.  Tile-list lengths vary by orders of magnitude (a face near the camera spans
+The fused kernel (forward walk, L1 seeds, backward walk per tile; one wave per 8x8 quadrant)
+can run one workgroup per tile in XCD-interleaved id order, one workgroup per tile in
+longest-list-first order, or as persistent workgroups pulling tiles from a device queue in
+either order, with a chosen number of workgroups.  Tile-list lengths vary by orders of magnitude (a face near the camera spans
 hundreds of tiles), so the best schedule depends on the workload.  ``tune`` times every
 candidate on the actual inputs (device events, median of repeats), checks that each candidate
 reproduces the default's loss, and records the winner in a table keyed by

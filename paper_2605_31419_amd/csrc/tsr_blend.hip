@@ -11,6 +11,7 @@
 namespace tsr {
 
 constexpr int kBatch = 64;
+constexpr int kWaves = kBlock / kWave;     // waves per workgroup: one per 8x8 quadrant
 
 // Wave reduction of the 20 per-face gradient sums: 1 = transposing permlane-swap butterfly,
 // 0 = one DPP reduction per value.
@@ -98,15 +99,15 @@ struct TileCtx {
 };
 
 __device__ __forceinline__ void tile_ctx(const ViewTable& vt, const uint32_t* __restrict__ ranges, int tile,
-                                         TileCtx& c) {
+                                         int quad, TileCtx& c) {
   c.tile = tile;
   c.view = view_of_tile(vt, tile);
   c.vd = vt.v[c.view];
   const int lt = tile - c.vd.tile_off;
   const int tx = lt % c.vd.tiles_x, ty = lt / c.vd.tiles_x;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  c.bx = tx * kTile + (wave & 1) * 8;
-  c.by = ty * kTile + (wave >> 1) * 8;
+  const int lane = threadIdx.x & 63;
+  c.bx = tx * kTile + (quad & 1) * 8;
+  c.by = ty * kTile + (quad >> 1) * 8;
   c.px = c.bx + (lane & 7);
   c.py = c.by + (lane >> 3);
   c.inside = c.px < c.vd.width && c.py < c.vd.height;
@@ -115,14 +116,44 @@ __device__ __forceinline__ void tile_ctx(const ViewTable& vt, const uint32_t* __
   c.end = ranges[2 * tile + 1];
 }
 
-// Stages records of pair positions [b0, b0 + n) into LDS (all lanes call).
-__device__ __forceinline__ void stage_batch(const float* __restrict__ records, const uint64_t* __restrict__ pairs,
-                                            uint32_t b0, int n, float4* srec, uint32_t* sface) {
+// Makes this wave's LDS stores visible to its own later loads from other lanes.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Two ways to stage the records of pair positions [b0, b0 + n), n <= kBatch, into LDS:
+//  * cooperative (COOP): the four waves of the workgroup load one shared copy, with a barrier
+//    before and after, so all waves walk the batches in step (one copy of the records per
+//    tile is read from the caches);
+//  * per wave: each wave loads its own copy into its own LDS area and walks the list at its
+//    own pace (no barriers; four copies are read).
+// Which one is faster depends on how often the caches already hold the records.
+__device__ __forceinline__ void stage_batch_block(const float* __restrict__ records, const uint64_t* __restrict__ pairs,
+                                                  uint32_t b0, int n, float4* srec, uint32_t* sface) {
   for (int i = threadIdx.x; i < n * 6; i += kBlock) {
     const uint32_t face = (uint32_t)pairs[b0 + i / 6];
     srec[i] = reinterpret_cast<const float4*>(records)[(size_t)face * 6 + i % 6];
   }
   if (threadIdx.x < n) sface[threadIdx.x] = (uint32_t)pairs[b0 + threadIdx.x];
+}
+
+// Per-wave staging: lane l reads the face id of entry l; the 6 n sixteen-byte pieces are then
+// loaded by the lanes in turn (piece i by lane i % 64, face id taken from lane i / 6).
+__device__ __forceinline__ void stage_batch(const float* __restrict__ records, const uint64_t* __restrict__ pairs,
+                                            uint32_t b0, int n, float4* srec, uint32_t* sface) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t f = lane < n ? (uint32_t)pairs[b0 + lane] : 0u;
+  if (lane < n) sface[lane] = f;
+  const float4* rec4 = reinterpret_cast<const float4*>(records);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const int i = lane + 64 * k;
+    const uint32_t fi = (uint32_t)__shfl((int)f, i / 6, 64);
+    if (i < n * 6) srec[i] = rec4[(size_t)fi * 6 + i % 6];
+  }
+  wave_lds_sync();
 }
 
 // Faces of the staged batch that can cover a pixel of this wave's 8x8 quadrant: lane j tests
@@ -164,19 +195,24 @@ struct FwdState {
 // Front-to-back walk over the tile list (eq. 4).  A pixel stops after the face that takes
 // its transmittance below t_min.  Records each pixel's last blended face and the
 // transmittance just before it.
-template <int SM>
+template <int SM, bool COOP>
 __device__ __forceinline__ void forward_walk(const TileCtx& c, const float* __restrict__ records,
                                              const uint64_t* __restrict__ pairs, float sigma, float t_min,
                                              float4* srec, uint32_t* sface, FwdState& s) {
   s.T = 1.f; s.C0 = s.C1 = s.C2 = s.D = 0.f; s.Tb = 1.f; s.last = -1;
   bool done = !c.inside;
+  const float dxb = (float)c.px, dyb = (float)c.py;
   for (uint32_t b0 = c.start; b0 < c.end; b0 += kBatch) {
-    if (__syncthreads_count(!done) == 0) break;
     const int n = (int)min((uint32_t)kBatch, c.end - b0);
-    stage_batch(records, pairs, b0, n, srec, sface);
-    __syncthreads();
-    if (__ballot(!done) == 0) continue;
-    const float dxb = (float)c.px, dyb = (float)c.py;
+    if constexpr (COOP) {
+      if (__syncthreads_count(!done) == 0) break;
+      stage_batch_block(records, pairs, b0, n, srec, sface);
+      __syncthreads();
+      if (__ballot(!done) == 0) continue;
+    } else {
+      if (__ballot(!done) == 0) break;
+      stage_batch(records, pairs, b0, n, srec, sface);
+    }
     unsigned long long mask = batch_hit_mask(srec, n, c.bx, c.by);
     while (mask) {
       const int j = __builtin_ctzll(mask);
@@ -213,19 +249,22 @@ struct PixGrad {
 // transmittance before the last blended face, B* hold what lies behind the current face
 // composited from transmittance 1, and per-face sums of the 20 record-parameter gradients
 // are reduced over the wave and added to grad_acc.
-template <int SM>
+template <int SM, bool COOP>
 __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __restrict__ records,
                                               const uint64_t* __restrict__ pairs, float sigma, int last, float Tb,
                                               const PixGrad& pg, float4* srec, uint32_t* sface, int* sint,
                                               acc_t* __restrict__ grad_acc) {
   const int lane = threadIdx.x & 63;
-  // block-wide highest list position any pixel blended
-  if (threadIdx.x == 0) sint[0] = -1;
-  __syncthreads();
+  // highest list position any pixel of this wave (COOP: of the workgroup) blended
   const int wlast = wave_max_int(last);
-  if (lane == 0) atomicMax(&sint[0], wlast);
-  __syncthreads();
-  const int top = sint[0];
+  int top = wlast;
+  if constexpr (COOP) {
+    if (threadIdx.x == 0) sint[0] = -1;
+    __syncthreads();
+    if (lane == 0) atomicMax(&sint[0], wlast);
+    __syncthreads();
+    top = sint[0];
+  }
   const int k_out = wave_sum20_slot();
   float Tcur = Tb;
   float B0 = 0.f, B1 = 0.f, B2 = 0.f, BD = 0.f, BA = 0.f;
@@ -233,10 +272,14 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
   for (int b1 = top + 1; b1 > (int)c.start; b1 -= kBatch) {
     const int b0 = max((int)c.start, b1 - kBatch);
     const int n = b1 - b0;
-    __syncthreads();
-    stage_batch(records, pairs, (uint32_t)b0, n, srec, sface);
-    __syncthreads();
-    if (b0 > wlast) continue;
+    if constexpr (COOP) {
+      __syncthreads();
+      stage_batch_block(records, pairs, (uint32_t)b0, n, srec, sface);
+      __syncthreads();
+      if (b0 > wlast) continue;
+    } else {
+      stage_batch(records, pairs, (uint32_t)b0, n, srec, sface);
+    }
     unsigned long long mask = batch_hit_mask(srec, n, c.bx, c.by);
     if (wlast - b0 < 63) mask &= (2ull << (wlast - b0)) - 1ull;     // faces after the wave's last
     while (mask) {
@@ -316,14 +359,15 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(ViewTable vt, const float*
                                                       float* __restrict__ color, float* __restrict__ depth,
                                                       float* __restrict__ trans, int* __restrict__ n_last,
                                                       float* __restrict__ t_last) {
-  __shared__ float4 srec[kBatch * 6];
-  __shared__ uint32_t sface[kBatch];
+  __shared__ float4 srec[kWaves][kBatch * 6];
+  __shared__ uint32_t sface[kWaves][kBatch];
+  const int wv = threadIdx.x >> 6;
   const int tile = tile_of_block(vt.n_tiles);
   if (tile < 0) return;
   TileCtx c;
-  tile_ctx(vt, ranges, tile, c);
+  tile_ctx(vt, ranges, tile, wv, c);
   FwdState s;
-  forward_walk<SM>(c, records, pairs, sigma, t_min, srec, sface, s);
+  forward_walk<SM, false>(c, records, pairs, sigma, t_min, srec[wv], sface[wv], s);
   if (!c.inside) return;
   const int64_t hw = (int64_t)c.vd.width * c.vd.height;
   const int64_t off = (int64_t)c.py * c.vd.width + c.px;
@@ -344,13 +388,13 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(ViewTable vt, const float*
                                                       const int* __restrict__ n_last, const float* __restrict__ t_last,
                                                       const float* __restrict__ gcolor, const float* __restrict__ gdepth,
                                                       const float* __restrict__ gtrans, acc_t* __restrict__ grad_acc) {
-  __shared__ float4 srec[kBatch * 6];
-  __shared__ uint32_t sface[kBatch];
-  __shared__ int sint[4];
+  __shared__ float4 srec[kWaves][kBatch * 6];
+  __shared__ uint32_t sface[kWaves][kBatch];
+  const int wv = threadIdx.x >> 6;
   const int tile = tile_of_block(vt.n_tiles);
   if (tile < 0) return;
   TileCtx c;
-  tile_ctx(vt, ranges, tile, c);
+  tile_ctx(vt, ranges, tile, wv, c);
   int last = -1;
   float Tb = 0.f;
   PixGrad pg{0.f, 0.f, 0.f, 0.f, 0.f};
@@ -367,11 +411,11 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(ViewTable vt, const float*
     pg.gd = gdepth[c.pix];
     pg.gt = gtrans ? gtrans[c.pix] : 0.f;
   }
-  backward_walk<SM>(c, records, pairs, sigma, last, Tb, pg, srec, sface, sint, grad_acc);
+  backward_walk<SM, false>(c, records, pairs, sigma, last, Tb, pg, srec[wv], sface[wv], nullptr, grad_acc);
 }
 
 // Fused training kernel: forward walk, L1 seeds of eqs. 8-10 (D-SSIM omitted), backward
-// walk, without leaving the workgroup.  Also accumulates the per-view loss in FP64.
+// walk, without leaving the workgroup.  Also writes the loss of each (tile, quadrant).
 template <int SM>
 __global__ __launch_bounds__(kBlock) void k_train_fused(ViewTable vt, const float* __restrict__ records,
                                                         const uint64_t* __restrict__ pairs,
@@ -379,37 +423,40 @@ __global__ __launch_bounds__(kBlock) void k_train_fused(ViewTable vt, const floa
                                                         float w_color, float w_depth,
                                                         const float* __restrict__ tcolor, const float* __restrict__ tdepth,
                                                         float* __restrict__ color, float* __restrict__ depth,
-                                                        float* __restrict__ trans, double* __restrict__ loss_acc,
+                                                        float* __restrict__ trans, float* __restrict__ loss_part,
                                                         acc_t* __restrict__ grad_acc,
                                                         const int* __restrict__ order, int* __restrict__ queue,
                                                         int persistent) {
+  // the four waves stage each batch together (one copy of the records per tile)
   __shared__ float4 srec[kBatch * 6];
   __shared__ uint32_t sface[kBatch];
+  __shared__ int s_item;
   __shared__ int sint[4];
-  __shared__ float sloss[4];
-  int item = persistent ? 0 : (int)blockIdx.x;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   for (;;) {
     int tile;
+    const int quad = wv;
     if (persistent) {
+      // the workgroup pulls tiles; its waves take the quadrants (one barrier per tile)
       __syncthreads();
-      if (threadIdx.x == 0) sint[1] = atomicAdd(queue, 1);
+      if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
       __syncthreads();
-      item = sint[1];
+      const int item = s_item;
       if (item >= vt.n_tiles) break;
       tile = order ? order[item] : item;
     } else {
-      tile = order ? (item < vt.n_tiles ? order[item] : -1) : tile_of_block(vt.n_tiles);
+      tile = order ? ((int)blockIdx.x < vt.n_tiles ? order[blockIdx.x] : -1) : tile_of_block(vt.n_tiles);
       if (tile < 0) break;
     }
     TileCtx c;
-    tile_ctx(vt, ranges, tile, c);
+    tile_ctx(vt, ranges, tile, quad, c);
 #if TSR_PRIO_LONG
     // long tile lists bound the kernel's tail: let their waves win issue arbitration
     if (c.end - c.start > TSR_PRIO_LONG) __builtin_amdgcn_s_setprio(2);
     else __builtin_amdgcn_s_setprio(0);
 #endif
     FwdState s;
-    forward_walk<SM>(c, records, pairs, sigma, t_min, srec, sface, s);
+    forward_walk<SM, true>(c, records, pairs, sigma, t_min, srec, sface, s);
     PixGrad pg{0.f, 0.f, 0.f, 0.f, 0.f};
     float lpix = 0.f;
     if (c.inside) {
@@ -435,14 +482,12 @@ __global__ __launch_bounds__(kBlock) void k_train_fused(ViewTable vt, const floa
       if (depth) depth[c.pix] = s.D;
       if (trans) trans[c.pix] = s.T;
     }
-    if (loss_acc) {
+    if (loss_part) {
+      // one plain store per (tile, quadrant); summed per view after the backward
       const float ws = wave_sum(lpix);
-      if ((threadIdx.x & 63) == 0) sloss[threadIdx.x >> 6] = ws;
-      __syncthreads();
-      if (threadIdx.x == 0)
-        unsafeAtomicAdd(&loss_acc[c.view], (double)sloss[0] + (double)sloss[1] + (double)sloss[2] + (double)sloss[3]);
+      if (lane == 0) loss_part[kWaves * tile + quad] = ws;
     }
-    backward_walk<SM>(c, records, pairs, sigma, s.last, s.Tb, pg, srec, sface, sint, grad_acc);
+    backward_walk<SM, true>(c, records, pairs, sigma, s.last, s.Tb, pg, srec, sface, sint, grad_acc);
     if (!persistent) break;
   }
 }
@@ -661,20 +706,41 @@ __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float*
   }
 }
 
+// Per-view L1 loss: FP64 sum of the (tile, quadrant) parts of the view's tiles, by one
+// workgroup of kBlock threads (every thread calls).
+__device__ void reduce_view_losses(const ViewTable& vt, const float* __restrict__ loss_part, float* __restrict__ loss) {
+  __shared__ double red[kWaves];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int v = 0; v < vt.n_views; ++v) {
+    const int64_t p0 = (int64_t)kWaves * vt.v[v].tile_off;
+    const int np = kWaves * vt.v[v].tiles_x * vt.v[v].tiles_y;
+    double x = 0.0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) x += (double)loss_part[p0 + i];
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (lane == 0) red[wave] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double t = 0.0;
+      for (int w = 0; w < kWaves; ++w) t += red[w];
+      loss[v] = (float)t;
+    }
+    __syncthreads();
+  }
+}
+
 // Per face: sum the staged vertex gradients over the views that see it and write them.
 // Soups write every vertex once (zero for faces no view sees); indexed meshes add into
-// zero-filled outputs.  Workgroup 0 also converts the FP64 pose and loss sums (complete once
-// the face backward has finished) to the float outputs.
+// zero-filled outputs.  Workgroup 0 also converts the FP64 pose sums (complete once the face
+// backward has finished) to the float outputs and sums the per-view losses.
 __global__ __launch_bounds__(256) void k_vertex_gather(tsr_scene_dev sc, ViewTable vt, const uint32_t* __restrict__ counts,
                                                        const acc_t* __restrict__ grad_acc, float* __restrict__ grad_pos,
                                                        float* __restrict__ grad_col, float* __restrict__ grad_opa,
                                                        const double* __restrict__ pose_acc, float* __restrict__ grad_pose,
-                                                       const double* __restrict__ loss_acc, float* __restrict__ loss) {
+                                                       const float* __restrict__ loss_part, float* __restrict__ loss) {
   if (blockIdx.x == 0) {
     if (grad_pose)
       for (int k = threadIdx.x; k < 6 * vt.n_views; k += blockDim.x) grad_pose[k] = (float)pose_acc[k];
-    if (loss)
-      for (int k = threadIdx.x; k < vt.n_views; k += blockDim.x) loss[k] = (float)loss_acc[k];
+    if (loss) reduce_view_losses(vt, loss_part, loss);
   }
   const int64_t M = vt.n_faces;
   const int64_t N = sc.n_vertices;
@@ -773,11 +839,11 @@ __device__ void build_tile_order(const uint32_t* __restrict__ ranges, int n_tile
 
 // Set-up of a backward pass: zero the gradient accumulators of the visible (view, face) pairs
 // (one 16-byte store per thread, grid-stride); workgroup 0 also zeroes the per-view FP64 pose
-// and loss accumulators and the persistent kernel's queue counter, and builds the
-// longest-first tile order when `order` is given.
+// accumulators and the persistent kernel's queue counter, and builds the longest-first tile
+// order when `order` is given.
 __global__ __launch_bounds__(256) void k_prep_bwd(ViewTable vt, const uint32_t* __restrict__ vis_total,
                                                   const uint32_t* __restrict__ vis_dense, acc_t* __restrict__ grad_acc,
-                                                  double* __restrict__ pose_acc, double* __restrict__ loss_acc,
+                                                  double* __restrict__ pose_acc,
                                                   const uint32_t* __restrict__ ranges, int* __restrict__ order,
                                                   int* __restrict__ queue) {
   constexpr int kVec = (int)(kGradDwords * sizeof(acc_t)) / 16;      // 16-byte stores per row
@@ -789,8 +855,6 @@ __global__ __launch_bounds__(256) void k_prep_bwd(ViewTable vt, const uint32_t* 
   }
   if (blockIdx.x == 0) {
     for (int k = threadIdx.x; k < 6 * vt.n_views; k += blockDim.x) pose_acc[k] = 0.0;
-    if (loss_acc)
-      for (int k = threadIdx.x; k < vt.n_views; k += blockDim.x) loss_acc[k] = 0.0;
     if (queue && threadIdx.x == 0) *queue = 0;
     if (order) {
       __shared__ uint32_t hist[kOrderBuckets];
@@ -804,11 +868,12 @@ __global__ void k_fill_f32(float* __restrict__ p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0.f;
 }
 
-__global__ void k_finalize(const double* __restrict__ pose_acc, float* __restrict__ grad_pose,
-                           const double* __restrict__ loss_acc, float* __restrict__ loss, int n_views) {
+__global__ __launch_bounds__(kBlock) void k_finalize(ViewTable vt, const double* __restrict__ pose_acc,
+                                                     float* __restrict__ grad_pose, const float* __restrict__ loss_part,
+                                                     float* __restrict__ loss) {
   const int i = threadIdx.x;
-  if (grad_pose && i < 6 * n_views) grad_pose[i] = (float)pose_acc[i];
-  if (loss && i < n_views) loss[i] = (float)loss_acc[i];
+  if (grad_pose && i < 6 * vt.n_views) grad_pose[i] = (float)pose_acc[i];
+  if (loss) reduce_view_losses(vt, loss_part, loss);
 }
 
 // ---------------------------------------------------------------------------- pose step
@@ -899,7 +964,7 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
   const float* t_last = reinterpret_cast<const float*>(ws + L.t_last);
   acc_t* grad_acc = reinterpret_cast<acc_t*>(ws + L.grad_acc);
   double* pose_acc = reinterpret_cast<double*>(ws + L.pose_acc);
-  double* loss_acc = reinterpret_cast<double*>(ws + L.loss_acc);
+  float* loss_part = reinterpret_cast<float*>(ws + L.loss_part);
   const int64_t nf = (int64_t)vt.n_views * vt.n_faces;
   int* order = nullptr;
   int* queue = nullptr;
@@ -909,7 +974,7 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
     const int64_t rows16 = nf * (int64_t)((kGradDwords * sizeof(acc_t)) / 16);
     const unsigned g = (unsigned)std::min<int64_t>(std::max<int64_t>(grid_for(rows16, 256), 1), 2048);
     TSR_LAUNCH("prep_bwd", k_prep_bwd, dim3(g), dim3(256), 0, st, vt, vis_total, vis_dense, grad_acc, pose_acc,
-               loss_acc, ranges, order, queue);
+               ranges, order, queue);
   }
   const dim3 block(kBlock);
   const int sm = sigma_mode(p.sigma);
@@ -922,7 +987,7 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
     dim3 grid(tile_grid(vt.n_tiles));
     if (sched.order && !sched.persistent) grid = dim3(vt.n_tiles);
     if (sched.persistent) grid = dim3(sched.grid > 0 ? sched.grid : 2048);
-#define TSR_TRAIN(S) TSR_LAUNCH("train_fused", k_train_fused<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, p.w_color, p.w_depth, tcolor, tdepth, color, depth, trans, loss ? loss_acc : nullptr, grad_acc, order, queue, sched.persistent)
+#define TSR_TRAIN(S) TSR_LAUNCH("train_fused", k_train_fused<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, p.w_color, p.w_depth, tcolor, tdepth, color, depth, trans, loss ? loss_part : nullptr, grad_acc, order, queue, sched.persistent)
     switch (sm) { case 1: TSR_TRAIN(1); break; case 2: TSR_TRAIN(2); break; case 3: TSR_TRAIN(3); break; default: TSR_TRAIN(0); }
 #undef TSR_TRAIN
   }
@@ -941,14 +1006,14 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
                grad_acc, grad_pose ? pose_acc : nullptr, want_vertices ? 1 : 0);
     if (want_vertices)
       TSR_LAUNCH("vertex_gather", k_vertex_gather, dim3(grid_for(vt.n_faces, 256)), dim3(256), 0, st, sc, vt, counts,
-                 grad_acc, grad_pos, grad_col, grad_opa, pose_acc, grad_pose, loss_acc, loss);
+                 grad_acc, grad_pos, grad_col, grad_opa, pose_acc, grad_pose, loss_part, loss);
   } else if (want_vertices && !sc.faces) {
     if (grad_pos) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(2048), dim3(256), 0, st, grad_pos, 3 * N);
     if (grad_col) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(2048), dim3(256), 0, st, grad_col, 3 * N);
     if (grad_opa) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(2048), dim3(256), 0, st, grad_opa, N);
   }
   if ((nf <= 0 || !want_vertices) && (grad_pose || loss))     // otherwise k_vertex_gather converts them
-    TSR_LAUNCH("finalize", k_finalize, dim3(1), dim3(256), 0, st, pose_acc, grad_pose, loss_acc, loss, vt.n_views);
+    TSR_LAUNCH("finalize", k_finalize, dim3(1), dim3(kBlock), 0, st, vt, pose_acc, grad_pose, loss_part, loss);
   return hipGetLastError();
 }
 

@@ -27,7 +27,7 @@ struct WsLayout {
   size_t hdr_queue;                // int32 work-queue counter of the persistent training kernel
   size_t hdr_sticky;               // uint32: some binning since the last tsr_check overflowed
   size_t pose_acc;                 // double [V][6]
-  size_t loss_acc;                 // double [V]
+  size_t loss_part;                // float [T][4]: L1 loss of each (tile, 8x8 quadrant)
   size_t counts;                   // uint32 [V*M]
   size_t records;                  // float  [V*M][24]
   size_t grad_acc;                 // float  [V*M][20]

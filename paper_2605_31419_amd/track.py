@@ -18,8 +18,10 @@ from . import _lib, raster
 
 class Tracker:
     def __init__(self, scene: raster.DeviceScene, intr, params: Optional[raster.Params] = None,
-                 lr_trans: float = 0.001, lr_rot: float = 0.003, iters: int = 100, capacity_slack: float = 2.0):
+                 lr_trans: float = 0.001, lr_rot: float = 0.003, iters: int = 100, capacity_slack: float = 2.0,
+                 schedule=None):
         self.rast = raster.Rasterizer(scene, [intr], params or raster.Params())
+        self.rast.schedule = schedule            # tile schedule of the fused kernel (autotuner's choice)
         self.lr_t, self.lr_r, self.iters = lr_trans, lr_rot, iters
         self.slack = capacity_slack
         P = self.rast.total_pixels
