@@ -306,8 +306,8 @@ __global__ __launch_bounds__(256) void k_project(tsr_scene_dev sc, const float* 
 // Single workgroup of 1024 threads: (1) exclusive scan of the visible-face counts of the
 // projection workgroups (offsets of their segments in the dense visible list); (2) exclusive
 // scan of the tile counts into ranges, pair total K, overflow check against the capacity (all
-// ranges empty on overflow), and the small-face counts left in tile_cnt2 as the base of the
-// larger faces' emission cursors.  Both scans run in rounds of 8192 entries, each thread
+// ranges empty on overflow), the small-face counts left in tile_cnt2 as the base of the
+// larger faces' emission cursors, and the list of tiles too long for the one-wave sort.  Both scans run in rounds of 8192 entries, each thread
 // taking 8 consecutive ones.
 constexpr int kScanPer = 8;
 constexpr int kScanRound = 1024 * kScanPer;
@@ -317,7 +317,8 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(const uint32_t* __restrict_
                                                      int n_tiles, int64_t capacity, int64_t* __restrict__ K_out,
                                                      uint32_t* __restrict__ overflow, const uint32_t* __restrict__ vis_cnt,
                                                      uint32_t* __restrict__ vis_off, uint32_t* __restrict__ vis_total,
-                                                     int n_segments) {
+                                                     int n_segments, uint32_t* __restrict__ long_cnt,
+                                                     uint32_t* __restrict__ long_list) {
   __shared__ unsigned long long wsum[16];
   const int tid = threadIdx.x;
   unsigned long long carry = 0, tot;
@@ -341,18 +342,22 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(const uint32_t* __restrict_
   if (tid == 0) *vis_total = (uint32_t)carry;
 
   carry = 0;
+  unsigned long long carry_long = 0;
   for (int base = 0; base < n_tiles; base += kScanRound) {
     const int i0 = base + tid * kScanPer;
     uint32_t cs[kScanPer], cb[kScanPer];
-    unsigned long long sum = 0;
+    unsigned long long sum = 0, nlong = 0;
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
       const bool in = i0 + k < n_tiles;
       cs[k] = in ? tile_cnt[i0 + k] : 0u;
       cb[k] = in ? tile_cnt2[i0 + k] : 0u;
       sum += (unsigned long long)cs[k] + cb[k];
+      nlong += (unsigned long long)cs[k] + cb[k] > (unsigned long long)kWaveSortMax;
     }
     unsigned long long run = carry + block_excl_scan_u64(sum, wsum, &tot);
+    unsigned long long tot_long;
+    unsigned long long lpos = carry_long + block_excl_scan_u64(nlong, wsum, &tot_long);
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
       if (i0 + k < n_tiles) {
@@ -360,11 +365,14 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(const uint32_t* __restrict_
         ranges[2 * (i0 + k)] = (uint32_t)run;
         ranges[2 * (i0 + k) + 1] = (uint32_t)(run + c);
         tile_cnt2[i0 + k] = cs[k];           // larger faces are emitted after the recorded slots
+        if (c > (unsigned long long)kWaveSortMax) long_list[lpos++] = (uint32_t)(i0 + k);
         run += c;
       }
     }
     carry += tot;
+    carry_long += tot_long;
   }
+  if (tid == 0) *long_cnt = (uint32_t)carry_long;
   const bool over = carry > (unsigned long long)capacity;
   if (over) {
     // same thread-to-entry mapping as above, so these stores land after the ones they replace
@@ -606,40 +614,21 @@ __device__ __forceinline__ void wave_sort_tile(uint64_t* base, int n) {
     if (r * 64 + lane < n) base[r * 64 + lane] = k[r];
 }
 
-// One wave per tile: lists of up to 512 keys are sorted in registers; longer lists are queued
-// for k_tile_sort_long.
-__global__ __launch_bounds__(256) void k_tile_sort_wave(const uint32_t* __restrict__ ranges, int n_tiles,
-                                                        uint64_t* __restrict__ pairs, uint32_t* __restrict__ long_cnt,
-                                                        uint32_t* __restrict__ long_list) {
-  const int t = blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (t >= n_tiles) return;
-  const uint32_t start = ranges[2 * t], end = ranges[2 * t + 1];
-  const int n = (int)(end - start);
-  if (n <= 1) return;
-  if (n > 512) {
-    if ((threadIdx.x & 63) == 0) long_list[atomicAdd(long_cnt, 1u)] = (uint32_t)t;
-    return;
-  }
-  uint64_t* base = pairs + start;
-  if (n <= 64) wave_sort_tile<1>(base, n);
-  else if (n <= 128) wave_sort_tile<2>(base, n);
-  else if (n <= 256) wave_sort_tile<4>(base, n);
-  else wave_sort_tile<8>(base, n);
-}
-
-// One workgroup per queued tile: sort the tile's bucket ascending by (z bits, face).  Buckets
-// of up to kRegSortMax keys are sorted in registers by the whole workgroup
+// Per-tile depth sort, ascending by (z bits, face), in one launch with two kinds of
+// workgroups: the first kLongBlocks are persistent over the list of tiles longer than
+// kWaveSortMax keys (built by k_scan_tiles), so they start first and overlap the rest; each
+// remaining workgroup sorts four tiles, one wave each, in registers.
+//   Long lists of up to kRegSortMax keys are sorted in registers by the whole workgroup
 // (block_bitonic1024); up to kSortLds keys are bitonic-sorted in LDS; longer ones are sorted
 // in LDS-sized chunks and merged pairwise in global memory through `temp` (keys are unique,
 // so a rank by binary search places every key).
-// Persistent over the queued long tiles (grid-stride over the device-side list).
-__global__ __launch_bounds__(256) void k_tile_sort_long(const uint32_t* __restrict__ ranges,
-                                                        const uint32_t* __restrict__ long_cnt,
-                                                        const uint32_t* __restrict__ long_list,
-                                                        uint64_t* __restrict__ pairs, uint64_t* __restrict__ temp) {
-  __shared__ uint64_t s[kSortLds];
+constexpr int kLongBlocks = 64;
+
+__device__ __forceinline__ void sort_long_tiles(const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ long_cnt,
+                                                const uint32_t* __restrict__ long_list, uint64_t* __restrict__ pairs,
+                                                uint64_t* __restrict__ temp, uint64_t* s) {
   const uint32_t nl = *long_cnt;
-  for (uint32_t li = blockIdx.x; li < nl; li += gridDim.x) {
+  for (uint32_t li = blockIdx.x; li < nl; li += kLongBlocks) {
   const int t = (int)long_list[li];
   const uint32_t start = ranges[2 * t], end = ranges[2 * t + 1];
   const int n = (int)(end - start);
@@ -694,6 +683,27 @@ __global__ __launch_bounds__(256) void k_tile_sort_long(const uint32_t* __restri
   }
 }
 
+__global__ __launch_bounds__(256) void k_tile_sort(const uint32_t* __restrict__ ranges, int n_tiles,
+                                                   uint64_t* __restrict__ pairs, const uint32_t* __restrict__ long_cnt,
+                                                   const uint32_t* __restrict__ long_list, uint64_t* __restrict__ temp) {
+  __shared__ uint64_t s[kSortLds];
+  if (blockIdx.x < kLongBlocks) {
+    sort_long_tiles(ranges, long_cnt, long_list, pairs, temp, s);
+    return;
+  }
+  const int t = (int)(blockIdx.x - kLongBlocks) * 4 + (int)(threadIdx.x >> 6);
+  if (t >= n_tiles) return;
+  const uint32_t start = ranges[2 * t], end = ranges[2 * t + 1];
+  const int n = (int)(end - start);
+  if (n <= 1 || n > kWaveSortMax) return;
+  static_assert(kWaveSortMax == 512, "the one-wave sort holds at most 8 keys per lane");
+  uint64_t* base = pairs + start;
+  if (n <= 64) wave_sort_tile<1>(base, n);
+  else if (n <= 128) wave_sort_tile<2>(base, n);
+  else if (n <= 256) wave_sort_tile<4>(base, n);
+  else wave_sort_tile<8>(base, n);
+}
+
 __global__ void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
 }
@@ -737,14 +747,13 @@ hipError_t launch_bin(const tsr_scene_dev& sc, const float* poses, const ViewTab
   const int n_seg = (int)((nf + kProjBlock - 1) / kProjBlock);
   TSR_LAUNCH("scan_tiles", k_scan_tiles, dim3(1), dim3(1024), 0, st, tile_cnt, tile_cnt2, ranges, vt.n_tiles,
                      sort ? L.capacity : (int64_t)0x7fffffffffffffffll, K, overflow, vis_cnt, vis_off, vis_total,
-                     n_seg);
+                     n_seg, long_cnt, long_list);
   if (!sort) return hipGetLastError();
   if (nf > 0)
     TSR_LAUNCH("emit", k_emit, dim3(grid_for(nf, kProjBlock)), dim3(kProjBlock), 0, st, vt, counts, records, ranges,
                slots, tile_cnt2, overflow, pairs, vis_cnt, vis_off, vis_list, vis_dense);
-  TSR_LAUNCH("tile_sort", k_tile_sort_wave, dim3(grid_for(vt.n_tiles, 4)), dim3(256), 0, st, ranges, vt.n_tiles, pairs,
-             long_cnt, long_list);
-  TSR_LAUNCH("tile_sort_long", k_tile_sort_long, dim3(64), dim3(256), 0, st, ranges, long_cnt, long_list, pairs, temp);
+  TSR_LAUNCH("tile_sort", k_tile_sort, dim3(kLongBlocks + grid_for(vt.n_tiles, 4)), dim3(256), 0, st, ranges,
+             vt.n_tiles, pairs, long_cnt, long_list, temp);
   return hipGetLastError();
 }
 

@@ -514,9 +514,32 @@ __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float*
                                                   const uint32_t* __restrict__ vis_total,
                                                   const uint32_t* __restrict__ vis_dense,
                                                   const float* __restrict__ records, acc_t* grad_acc,
-                                                  double* __restrict__ pose_acc, int want_vertices) {
+                                                  double* __restrict__ pose_acc, int want_vertices,
+                                                  const float* __restrict__ loss_part, double* __restrict__ loss_acc) {
   __shared__ double red[6][4];
   __shared__ int s_v[2];
+  if (loss_part) {
+    // per-view loss: each thread adds one tile's four quadrant parts; waves whose tiles all
+    // belong to one view (all but at most one wave per view boundary) add one FP64 atomic
+    const int lane = threadIdx.x & 63;
+    for (int64_t t0 = (int64_t)blockIdx.x * blockDim.x; t0 < vt.n_tiles; t0 += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t t = t0 + threadIdx.x;
+      double x = 0.0;
+      int v = -1;
+      if (t < vt.n_tiles) {
+        const float4 q = reinterpret_cast<const float4*>(loss_part)[t];
+        x = ((double)q.x + (double)q.y) + ((double)q.z + (double)q.w);
+        v = view_of_tile(vt, (int)t);
+      }
+      const int v0 = __shfl(v, 0, 64);
+      if (__ballot(v == v0 || v < 0) == ~0ull) {
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        if (lane == 0 && v0 >= 0) unsafeAtomicAdd(&loss_acc[v0], x);
+      } else if (v >= 0) {
+        unsafeAtomicAdd(&loss_acc[v], x);
+      }
+    }
+  }
   const int64_t M = vt.n_faces;
   const int64_t N = sc.n_vertices;
   const int64_t nf = (int64_t)vt.n_views * M;
@@ -730,17 +753,18 @@ __device__ void reduce_view_losses(const ViewTable& vt, const float* __restrict_
 
 // Per face: sum the staged vertex gradients over the views that see it and write them.
 // Soups write every vertex once (zero for faces no view sees); indexed meshes add into
-// zero-filled outputs.  Workgroup 0 also converts the FP64 pose sums (complete once the face
-// backward has finished) to the float outputs and sums the per-view losses.
+// zero-filled outputs.  Workgroup 0 also converts the FP64 pose and loss sums (complete once
+// the face backward has finished) to the float outputs.
 __global__ __launch_bounds__(256) void k_vertex_gather(tsr_scene_dev sc, ViewTable vt, const uint32_t* __restrict__ counts,
                                                        const acc_t* __restrict__ grad_acc, float* __restrict__ grad_pos,
                                                        float* __restrict__ grad_col, float* __restrict__ grad_opa,
                                                        const double* __restrict__ pose_acc, float* __restrict__ grad_pose,
-                                                       const float* __restrict__ loss_part, float* __restrict__ loss) {
+                                                       const double* __restrict__ loss_acc, float* __restrict__ loss) {
   if (blockIdx.x == 0) {
     if (grad_pose)
       for (int k = threadIdx.x; k < 6 * vt.n_views; k += blockDim.x) grad_pose[k] = (float)pose_acc[k];
-    if (loss) reduce_view_losses(vt, loss_part, loss);
+    if (loss)
+      for (int k = threadIdx.x; k < vt.n_views; k += blockDim.x) loss[k] = (float)loss_acc[k];
   }
   const int64_t M = vt.n_faces;
   const int64_t N = sc.n_vertices;
@@ -839,11 +863,11 @@ __device__ void build_tile_order(const uint32_t* __restrict__ ranges, int n_tile
 
 // Set-up of a backward pass: zero the gradient accumulators of the visible (view, face) pairs
 // (one 16-byte store per thread, grid-stride); workgroup 0 also zeroes the per-view FP64 pose
-// accumulators and the persistent kernel's queue counter, and builds the longest-first tile
-// order when `order` is given.
+// and loss accumulators and the persistent kernel's queue counter, and builds the
+// longest-first tile order when `order` is given.
 __global__ __launch_bounds__(256) void k_prep_bwd(ViewTable vt, const uint32_t* __restrict__ vis_total,
                                                   const uint32_t* __restrict__ vis_dense, acc_t* __restrict__ grad_acc,
-                                                  double* __restrict__ pose_acc,
+                                                  double* __restrict__ pose_acc, double* __restrict__ loss_acc,
                                                   const uint32_t* __restrict__ ranges, int* __restrict__ order,
                                                   int* __restrict__ queue) {
   constexpr int kVec = (int)(kGradDwords * sizeof(acc_t)) / 16;      // 16-byte stores per row
@@ -855,6 +879,7 @@ __global__ __launch_bounds__(256) void k_prep_bwd(ViewTable vt, const uint32_t* 
   }
   if (blockIdx.x == 0) {
     for (int k = threadIdx.x; k < 6 * vt.n_views; k += blockDim.x) pose_acc[k] = 0.0;
+    for (int k = threadIdx.x; k < vt.n_views; k += blockDim.x) loss_acc[k] = 0.0;
     if (queue && threadIdx.x == 0) *queue = 0;
     if (order) {
       __shared__ uint32_t hist[kOrderBuckets];
@@ -868,12 +893,16 @@ __global__ void k_fill_f32(float* __restrict__ p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0.f;
 }
 
+// Float outputs of the pose and loss sums.  `loss_part` is given when the face backward did
+// not run (no faces): the per-view losses are then summed here from the (tile, quadrant) parts.
 __global__ __launch_bounds__(kBlock) void k_finalize(ViewTable vt, const double* __restrict__ pose_acc,
-                                                     float* __restrict__ grad_pose, const float* __restrict__ loss_part,
-                                                     float* __restrict__ loss) {
+                                                     float* __restrict__ grad_pose, const double* __restrict__ loss_acc,
+                                                     const float* __restrict__ loss_part, float* __restrict__ loss) {
   const int i = threadIdx.x;
   if (grad_pose && i < 6 * vt.n_views) grad_pose[i] = (float)pose_acc[i];
-  if (loss) reduce_view_losses(vt, loss_part, loss);
+  if (!loss) return;
+  if (loss_part) reduce_view_losses(vt, loss_part, loss);
+  else if (i < vt.n_views) loss[i] = (float)loss_acc[i];
 }
 
 // ---------------------------------------------------------------------------- pose step
@@ -965,6 +994,7 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
   acc_t* grad_acc = reinterpret_cast<acc_t*>(ws + L.grad_acc);
   double* pose_acc = reinterpret_cast<double*>(ws + L.pose_acc);
   float* loss_part = reinterpret_cast<float*>(ws + L.loss_part);
+  double* loss_acc = reinterpret_cast<double*>(ws + L.loss_acc);
   const int64_t nf = (int64_t)vt.n_views * vt.n_faces;
   int* order = nullptr;
   int* queue = nullptr;
@@ -974,7 +1004,7 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
     const int64_t rows16 = nf * (int64_t)((kGradDwords * sizeof(acc_t)) / 16);
     const unsigned g = (unsigned)std::min<int64_t>(std::max<int64_t>(grid_for(rows16, 256), 1), 2048);
     TSR_LAUNCH("prep_bwd", k_prep_bwd, dim3(g), dim3(256), 0, st, vt, vis_total, vis_dense, grad_acc, pose_acc,
-               ranges, order, queue);
+               loss_acc, ranges, order, queue);
   }
   const dim3 block(kBlock);
   const int sm = sigma_mode(p.sigma);
@@ -1003,17 +1033,19 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
   if (nf > 0) {
     const dim3 fgrid(std::min<unsigned>(grid_for(nf, 256), 2048u));
     TSR_LAUNCH("face_bwd", k_face_bwd, fgrid, dim3(256), 0, st, sc, poses, vt, vis_total, vis_dense, records,
-               grad_acc, grad_pose ? pose_acc : nullptr, want_vertices ? 1 : 0);
+               grad_acc, grad_pose ? pose_acc : nullptr, want_vertices ? 1 : 0, loss ? loss_part : nullptr,
+               loss_acc);
     if (want_vertices)
       TSR_LAUNCH("vertex_gather", k_vertex_gather, dim3(grid_for(vt.n_faces, 256)), dim3(256), 0, st, sc, vt, counts,
-                 grad_acc, grad_pos, grad_col, grad_opa, pose_acc, grad_pose, loss_part, loss);
+                 grad_acc, grad_pos, grad_col, grad_opa, pose_acc, grad_pose, loss_acc, loss);
   } else if (want_vertices && !sc.faces) {
     if (grad_pos) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(2048), dim3(256), 0, st, grad_pos, 3 * N);
     if (grad_col) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(2048), dim3(256), 0, st, grad_col, 3 * N);
     if (grad_opa) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(2048), dim3(256), 0, st, grad_opa, N);
   }
   if ((nf <= 0 || !want_vertices) && (grad_pose || loss))     // otherwise k_vertex_gather converts them
-    TSR_LAUNCH("finalize", k_finalize, dim3(1), dim3(kBlock), 0, st, vt, pose_acc, grad_pose, loss_part, loss);
+    TSR_LAUNCH("finalize", k_finalize, dim3(1), dim3(kBlock), 0, st, vt, pose_acc, grad_pose, loss_acc,
+               nf <= 0 ? loss_part : nullptr, loss);
   return hipGetLastError();
 }
 

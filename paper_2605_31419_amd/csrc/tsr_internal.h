@@ -27,6 +27,7 @@ struct WsLayout {
   size_t hdr_queue;                // int32 work-queue counter of the persistent training kernel
   size_t hdr_sticky;               // uint32: some binning since the last tsr_check overflowed
   size_t pose_acc;                 // double [V][6]
+  size_t loss_acc;                 // double [V]
   size_t loss_part;                // float [T][4]: L1 loss of each (tile, 8x8 quadrant)
   size_t counts;                   // uint32 [V*M]
   size_t records;                  // float  [V*M][24]
@@ -56,6 +57,7 @@ struct WsLayout {
 constexpr int kOrderBuckets = 1024;    // tile-length buckets of the longest-first schedule
 constexpr int kProjBlock = 256;        // faces per projection workgroup (one visible-list segment each)
 constexpr int kRegSortMax = 1024;      // tile lists up to this length are sorted in registers
+constexpr int kWaveSortMax = 512;      // ... by one wave (longer ones by a whole workgroup)
 constexpr int kSmallTiles = 4;         // faces overlapping at most this many tiles record their slots
 
 // Training-kernel schedule (chosen by the autotuner; the default is one workgroup per tile).
