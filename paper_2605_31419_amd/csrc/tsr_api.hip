@@ -138,8 +138,8 @@ WsLayout layout(const ViewTable& vt, int64_t cap) {
   L.hdr_queue = 12;
   L.hdr_sticky = 16;
   o = 256;
-  L.pose_acc = o; o = align_up(o + sizeof(double) * 6 * vt.n_views);
-  L.loss_acc = o; o = align_up(o + sizeof(double) * vt.n_views);
+  L.pose_acc = o; o = align_up(o + sizeof(double) * tsr::kSumCopies * 6 * vt.n_views);
+  L.loss_acc = o; o = align_up(o + sizeof(double) * tsr::kSumCopies * vt.n_views);
   L.loss_part = o; o = align_up(o + sizeof(float) * 4 * vt.n_tiles);
   L.counts = o; o = align_up(o + sizeof(uint32_t) * nf);
   L.records = o; o = align_up(o + sizeof(float) * tsr::kRecDwords * nf);

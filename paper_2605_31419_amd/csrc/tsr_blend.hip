@@ -433,15 +433,21 @@ __global__ __launch_bounds__(kBlock) void k_train_fused(ViewTable vt, const floa
   __shared__ int s_item;
   __shared__ int sint[4];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int round = 0;
   for (;;) {
     int tile;
     const int quad = wv;
     if (persistent) {
-      // the workgroup pulls tiles; its waves take the quadrants (one barrier per tile)
-      __syncthreads();
-      if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
-      __syncthreads();
-      const int item = s_item;
+      // the workgroup's first tile is its own id; later ones come from the queue (items
+      // gridDim.x onward), so the launch does not start with gridDim.x atomics on one address
+      int item = (int)blockIdx.x;
+      if (round > 0) {
+        __syncthreads();
+        if (threadIdx.x == 0) s_item = (int)gridDim.x + atomicAdd(queue, 1);
+        __syncthreads();
+        item = s_item;
+      }
+      ++round;
       if (item >= vt.n_tiles) break;
       tile = order ? order[item] : item;
     } else {
@@ -532,11 +538,12 @@ __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float*
         v = view_of_tile(vt, (int)t);
       }
       const int v0 = __shfl(v, 0, 64);
+      double* lc = loss_acc + (int64_t)(blockIdx.x % kSumCopies) * vt.n_views;
       if (__ballot(v == v0 || v < 0) == ~0ull) {
         for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-        if (lane == 0 && v0 >= 0) unsafeAtomicAdd(&loss_acc[v0], x);
+        if (lane == 0 && v0 >= 0) unsafeAtomicAdd(&lc[v0], x);
       } else if (v >= 0) {
-        unsafeAtomicAdd(&loss_acc[v], x);
+        unsafeAtomicAdd(&lc[v], x);
       }
     }
   }
@@ -721,11 +728,30 @@ __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float*
       __syncthreads();
       if (threadIdx.x < 6) {
         const double t = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
-        if (t != 0.0) unsafeAtomicAdd(&pose_acc[6 * vv + threadIdx.x], t);
+        if (t != 0.0)
+          unsafeAtomicAdd(&pose_acc[((int64_t)(blockIdx.x % kSumCopies) * vt.n_views + vv) * 6 + threadIdx.x], t);
       }
       __syncthreads();
     }
   }
+  }
+}
+
+// Float outputs of the FP64 pose and loss sums (adding their kSumCopies copies).
+__device__ __forceinline__ void write_sums(const ViewTable& vt, const double* __restrict__ pose_acc,
+                                           float* __restrict__ grad_pose, const double* __restrict__ loss_acc,
+                                           float* __restrict__ loss) {
+  const int nv = vt.n_views;
+  for (int k = threadIdx.x; k < 7 * nv; k += blockDim.x) {
+    const bool is_pose = k < 6 * nv;
+    if (is_pose ? !grad_pose : !loss) continue;
+    const double* src = is_pose ? pose_acc + k : loss_acc + (k - 6 * nv);
+    const int stride = is_pose ? 6 * nv : nv;
+    double t = 0.0;
+#pragma unroll 8
+    for (int c = 0; c < kSumCopies; ++c) t += src[(int64_t)c * stride];
+    if (is_pose) grad_pose[k] = (float)t;
+    else loss[k - 6 * nv] = (float)t;
   }
 }
 
@@ -760,12 +786,7 @@ __global__ __launch_bounds__(256) void k_vertex_gather(tsr_scene_dev sc, ViewTab
                                                        float* __restrict__ grad_col, float* __restrict__ grad_opa,
                                                        const double* __restrict__ pose_acc, float* __restrict__ grad_pose,
                                                        const double* __restrict__ loss_acc, float* __restrict__ loss) {
-  if (blockIdx.x == 0) {
-    if (grad_pose)
-      for (int k = threadIdx.x; k < 6 * vt.n_views; k += blockDim.x) grad_pose[k] = (float)pose_acc[k];
-    if (loss)
-      for (int k = threadIdx.x; k < vt.n_views; k += blockDim.x) loss[k] = (float)loss_acc[k];
-  }
+  if (blockIdx.x == 0) write_sums(vt, pose_acc, grad_pose, loss_acc, loss);
   const int64_t M = vt.n_faces;
   const int64_t N = sc.n_vertices;
   const int64_t m0 = (int64_t)blockIdx.x * blockDim.x;
@@ -878,8 +899,8 @@ __global__ __launch_bounds__(256) void k_prep_bwd(ViewTable vt, const uint32_t* 
     if (g < nf) reinterpret_cast<float4*>(grad_acc + g * kGradDwords)[i % kVec] = make_float4(0.f, 0.f, 0.f, 0.f);
   }
   if (blockIdx.x == 0) {
-    for (int k = threadIdx.x; k < 6 * vt.n_views; k += blockDim.x) pose_acc[k] = 0.0;
-    for (int k = threadIdx.x; k < vt.n_views; k += blockDim.x) loss_acc[k] = 0.0;
+    for (int k = threadIdx.x; k < kSumCopies * 6 * vt.n_views; k += blockDim.x) pose_acc[k] = 0.0;
+    for (int k = threadIdx.x; k < kSumCopies * vt.n_views; k += blockDim.x) loss_acc[k] = 0.0;
     if (queue && threadIdx.x == 0) *queue = 0;
     if (order) {
       __shared__ uint32_t hist[kOrderBuckets];
@@ -898,11 +919,12 @@ __global__ void k_fill_f32(float* __restrict__ p, int64_t n) {
 __global__ __launch_bounds__(kBlock) void k_finalize(ViewTable vt, const double* __restrict__ pose_acc,
                                                      float* __restrict__ grad_pose, const double* __restrict__ loss_acc,
                                                      const float* __restrict__ loss_part, float* __restrict__ loss) {
-  const int i = threadIdx.x;
-  if (grad_pose && i < 6 * vt.n_views) grad_pose[i] = (float)pose_acc[i];
-  if (!loss) return;
-  if (loss_part) reduce_view_losses(vt, loss_part, loss);
-  else if (i < vt.n_views) loss[i] = (float)loss_acc[i];
+  if (loss_part) {
+    write_sums(vt, pose_acc, grad_pose, loss_acc, nullptr);
+    if (loss) reduce_view_losses(vt, loss_part, loss);
+  } else {
+    write_sums(vt, pose_acc, grad_pose, loss_acc, loss);
+  }
 }
 
 // ---------------------------------------------------------------------------- pose step

@@ -26,8 +26,8 @@ struct WsLayout {
   size_t hdr_k, hdr_overflow;      // int64 K, uint32 overflow flag
   size_t hdr_queue;                // int32 work-queue counter of the persistent training kernel
   size_t hdr_sticky;               // uint32: some binning since the last tsr_check overflowed
-  size_t pose_acc;                 // double [V][6]
-  size_t loss_acc;                 // double [V]
+  size_t pose_acc;                 // double [kSumCopies][V][6]
+  size_t loss_acc;                 // double [kSumCopies][V]
   size_t loss_part;                // float [T][4]: L1 loss of each (tile, 8x8 quadrant)
   size_t counts;                   // uint32 [V*M]
   size_t records;                  // float  [V*M][24]
@@ -55,6 +55,8 @@ struct WsLayout {
 };
 
 constexpr int kOrderBuckets = 1024;    // tile-length buckets of the longest-first schedule
+constexpr int kSumCopies = 64;         // copies of the FP64 pose / loss sums (workgroup b adds into
+                                       // copy b % kSumCopies, so few atomics meet on one address)
 constexpr int kProjBlock = 256;        // faces per projection workgroup (one visible-list segment each)
 constexpr int kRegSortMax = 1024;      // tile lists up to this length are sorted in registers
 constexpr int kWaveSortMax = 512;      // ... by one wave (longer ones by a whole workgroup)
