@@ -373,7 +373,7 @@ def main():
         log(f"[bench] serving: {json.dumps(serving)}")
 
     # rooflines
-    bs_names = ["fill_tiles", "project", "scan_tiles", "emit", "tile_sort", "tile_sort_long"]
+    bs_names = ["fill_tiles", "project", "scan_tiles", "emit", "tile_sort"]
     bs_ms = sum(ktimes.get(k, 0.0) for k in bs_names)
     n_tiles = single.rast.binning().n_tiles
     bs_bytes = bin_sort_bytes(args.faces, 1, m_vis, K, n_tiles)
@@ -392,6 +392,14 @@ def main():
         roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS, "traffic": None}
     bs_ach = bs_bytes / (bs_ms * 1e-3) / 1e9
+    # measured HBM bytes of the binning kernels (profiler counters of this build), per step
+    bs_traffic = 0
+    for k in ("k_fill_u32", "k_project", "k_scan_tiles", "k_emit", "k_tile_sort"):
+        tb, _ = counter_traffic(k)
+        if tb is None:
+            bs_traffic = None
+            break
+        bs_traffic += tb
     out = {
         "metric": "fwd+bwd Mpix/s at 1200x680, 1M tris (1 view vs batched); p50/p99 render latency",
         "value": mpix, "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -402,7 +410,9 @@ def main():
                    "faces": args.faces, "pairs": K, "visible_faces": m_vis},
         "roofline": roof,
         "bin_sort_roofline": {"bound": "hbm", "achieved": bs_ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                              "frac": bs_ach / HBM_PEAK_GBS, "ms": bs_ms, "algorithmic_bytes": bs_bytes},
+                              "frac": bs_ach / HBM_PEAK_GBS, "ms": bs_ms, "algorithmic_bytes": bs_bytes,
+                              "traffic": bs_traffic,
+                              "traffic_gbs": None if bs_traffic is None else bs_traffic / (bs_ms * 1e-3) / 1e9},
         "kernels_ms": {k: round(v, 4) for k, v in ktimes.items()},
         "unfused": {"ms_per_step": ms_unf, "mpix_s": single.pixels / (ms_unf * 1e-3) / 1e6,
                     "kernels_ms": {k: round(v, 4) for k, v in kt_unf.items()}},

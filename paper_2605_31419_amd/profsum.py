@@ -86,7 +86,7 @@ def main():
     ap.add_argument("db", nargs="?")
     ap.add_argument("--fetch")
     ap.add_argument("--write")
-    ap.add_argument("--kernel", default="k_train_fused<1>")
+    ap.add_argument("--kernel", action="append", help="kernel name (repeatable); default k_train_fused<1>")
     a = ap.parse_args()
     if a.mode == "kernels":
         print_kernels(a.db)
@@ -95,11 +95,14 @@ def main():
     else:
         from .build import source_fingerprint
 
-        t = traffic(a.fetch, a.write, a.kernel)
-        print(f"calibration: fetched bytes = {t['fetch_factor']:.3f} x FETCH_SIZE, "
-              f"written bytes = {t['write_factor']:.3f} x WRITE_SIZE")
-        print(f"traffic: kernel={a.kernel} fetch_bytes={t['fetch_bytes']:.0f} write_bytes={t['write_bytes']:.0f} "
-              f"sources={source_fingerprint()}")
+        fp = source_fingerprint()
+        for i, k in enumerate(a.kernel or ["k_train_fused<1>"]):
+            t = traffic(a.fetch, a.write, k)
+            if i == 0:
+                print(f"calibration: fetched bytes = {t['fetch_factor']:.3f} x FETCH_SIZE, "
+                      f"written bytes = {t['write_factor']:.3f} x WRITE_SIZE")
+            print(f"traffic: kernel={k} fetch_bytes={t['fetch_bytes']:.0f} write_bytes={t['write_bytes']:.0f} "
+                  f"sources={fp}")
 
 
 if __name__ == "__main__":
