@@ -91,15 +91,32 @@ __device__ __forceinline__ void face_normals(FaceSetup& f) {
   for (int k = 0; k < 3; ++k) {
     const int k1 = (k + 1) % 3;
     double ex = f.q[k1][0] - f.q[k][0], ey = f.q[k1][1] - f.q[k][1];
-    f.n[k][0] = f.so * ey / f.len[k];
-    f.n[k][1] = -f.so * ex / f.len[k];
+    const double il = f.so / f.len[k];        // normals only feed the float record
+    f.n[k][0] = ey * il;
+    f.n[k][1] = -ex * il;
   }
-  f.zf = (f.vc[0][2] + f.vc[1][2] + f.vc[2][2]) / 3.0;
+  f.zf = (f.vc[0][2] + f.vc[1][2] + f.vc[2][2]) / 3.0;   // exact division: it decides the depth order
+}
+
+// Vertex colours [channel][vertex] and opacities of a face (loaded before its setup so that
+// their latency overlaps the FP64 work).
+struct FaceAttr {
+  float col[3][3];
+  float opa[3];
+};
+
+__device__ __forceinline__ void load_attr(const tsr_scene_dev& sc, const int64_t vid[3], FaceAttr& a) {
+  const int64_t N = sc.n_vertices;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) a.col[ch][k] = sc.col[ch * N + vid[k]];
+    a.opa[k] = sc.opa[vid[k]];
+  }
 }
 
 // Writes the FP32 face-local record of a visible face (after face_normals).
-__device__ __forceinline__ void write_record(const tsr_scene_dev& sc, const int64_t vid[3], const FaceSetup& f,
-                                             float* __restrict__ dst_rec) {
+__device__ __forceinline__ void write_record(const FaceAttr& at, const FaceSetup& f, float* __restrict__ dst_rec) {
   float rec[kRecDwords];
   const double inv_r = 1.0 / f.r;
   double a[3], b[3], c[3];
@@ -112,14 +129,14 @@ __device__ __forceinline__ void write_record(const tsr_scene_dev& sc, const int6
     rec[kRecEdge + 3 * k + 1] = (float)b[k];
     rec[kRecEdge + 3 * k + 2] = (float)c[k];
   }
-  const int64_t N = sc.n_vertices;
+  const double inv_perim = 1.0 / f.perim;
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) {
     // lambda_opp(k) = E_k len_k / perimeter; opp(k) = (k + 2) % 3 is the vertex facing edge k
     double P = 0, Q = 0, Rr = 0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      double beta = f.len[k] * (double)sc.col[ch * N + vid[(k + 2) % 3]] / f.perim;
+      double beta = f.len[k] * (double)at.col[ch][(k + 2) % 3] * inv_perim;
       P += beta * a[k];
       Q += beta * b[k];
       Rr += beta * c[k];
@@ -128,7 +145,7 @@ __device__ __forceinline__ void write_record(const tsr_scene_dev& sc, const int6
     rec[kRecCol + 3 * ch + 1] = (float)Q;
     rec[kRecCol + 3 * ch + 2] = (float)Rr;
   }
-  rec[kRecOpa] = (float)(((double)sc.opa[vid[0]] + (double)sc.opa[vid[1]] + (double)sc.opa[vid[2]]) / 3.0);
+  rec[kRecOpa] = (float)(((double)at.opa[0] + (double)at.opa[1] + (double)at.opa[2]) / 3.0);
   rec[kRecZ] = (float)f.zf;
   rec[kRecU0] = __int_as_float(f.u0);
   rec[kRecV0] = __int_as_float(f.v0);
@@ -145,8 +162,8 @@ __device__ __forceinline__ void write_record(const tsr_scene_dev& sc, const int6
 // Faces it does not reject go through setup_face; non-finite values are never rejected here.
 // Error bounds: camera coordinates from three FMAs and an add of float inputs differ from the
 // FP64 value by at most 4 ulp-units of sum |R_ai w_i| + |t_a| (bound used: 1e-6 x that sum);
-// the projection adds the propagated coordinate error and two roundings (bound used: 4x the
-// first-order estimate, plus 1e-4 px).
+// the projection adds the propagated coordinate error, the reciprocal (<= 1 ulp) and two
+// roundings (bound used: 4x the first-order estimate, plus 1e-4 px).
 __device__ __forceinline__ bool surely_culled(const tsr_scene_dev& sc, const int64_t vid[3],
                                               const float* __restrict__ pose, const ViewDesc& vd, float z_near) {
   const int64_t N = sc.n_vertices;
@@ -165,9 +182,11 @@ __device__ __forceinline__ bool surely_culled(const tsr_scene_dev& sc, const int
     if (c[2] + e[2] < z_near) return true;           // FP64 depth below z_near as well
     const float zlo = c[2] - e[2];
     if (!(zlo > 0.f)) return false;                   // projection bound needs z > 0
-    const float qx = c[0] / c[2], qy = c[1] / c[2];
-    const float dqx = (e[0] + fabsf(qx) * e[2]) / zlo + 1.2e-7f * fabsf(qx);
-    const float dqy = (e[1] + fabsf(qy) * e[2]) / zlo + 1.2e-7f * fabsf(qy);
+    // hardware reciprocal (<= 1 ulp) times the coordinate: <= 1.5 ulp relative for q
+    const float rz = __builtin_amdgcn_rcpf(c[2]), rzlo = __builtin_amdgcn_rcpf(zlo);
+    const float qx = c[0] * rz, qy = c[1] * rz;
+    const float dqx = (e[0] + fabsf(qx) * e[2]) * rzlo * 1.0001f + 3e-7f * fabsf(qx);
+    const float dqy = (e[1] + fabsf(qy) * e[2]) * rzlo * 1.0001f + 3e-7f * fabsf(qy);
     const float u = fmaf(vd.fx, qx, vd.cx), v = fmaf(vd.fy, qy, vd.cy);
     const float du = 4.f * (fabsf(vd.fx) * dqx + 1.2e-7f * (fabsf(vd.fx * qx) + fabsf(vd.cx) + fabsf(u))) + 1e-4f;
     const float dv = 4.f * (fabsf(vd.fy) * dqy + 1.2e-7f * (fabsf(vd.fy * qy) + fabsf(vd.cy) + fabsf(v))) + 1e-4f;
@@ -246,7 +265,15 @@ __global__ __launch_bounds__(256) void k_project(tsr_scene_dev sc, const float* 
     if (cand) s_cand[off] = (uint32_t)g;
   }
   const uint32_t ncand = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+  const int nact = (int)((ncand + 63u) >> 6);              // waves that hold a candidate below
   __syncthreads();
+  if (ncand == 0u) {
+    if (threadIdx.x == 0) vis_cnt[blockIdx.x] = 0u;
+    return;
+  }
+  // Whole waves without a candidate leave now, so their slots go to other workgroups during
+  // the FP64 stage; the barriers below then wait for the remaining waves only.
+  if (wave >= nact) return;
   // ---- exact setup of the candidates, one per lane (in g order)
   int ntiles = 0, tx0 = 0, ty0 = 0, tw = 1, tile_base = 0, tiles_x = 1;
   int64_t g = 0;
@@ -258,6 +285,8 @@ __global__ __launch_bounds__(256) void k_project(tsr_scene_dev sc, const float* 
     load_pose(poses, v, R, t);
     int64_t vid[3];
     face_vertices(sc, g - (int64_t)v * M, vid);
+    FaceAttr at;
+    load_attr(sc, vid, at);
     FaceSetup f;
     if (setup_face(sc, vid, R, t, vd, z_near, r_min, f)) {
       tx0 = f.u0 >> 4;
@@ -267,7 +296,7 @@ __global__ __launch_bounds__(256) void k_project(tsr_scene_dev sc, const float* 
       tile_base = vd.tile_off;
       tiles_x = vd.tiles_x;
       face_normals(f);
-      write_record(sc, vid, f, records + g * kRecDwords);
+      write_record(at, f, records + g * kRecDwords);
     }
     counts[g] = (uint32_t)ntiles;
   }
@@ -282,7 +311,11 @@ __global__ __launch_bounds__(256) void k_project(tsr_scene_dev sc, const float* 
     uint32_t off = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
     for (int w = 0; w < wave; ++w) off += s_wave[w];
     if (vis) vis_list[(int64_t)blockIdx.x * kProjBlock + off] = (uint32_t)g;
-    if (threadIdx.x == 0) vis_cnt[blockIdx.x] = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
+    if (threadIdx.x == 0) {
+      uint32_t nvis = 0u;
+      for (int w = 0; w < nact; ++w) nvis += s_wave[w];
+      vis_cnt[blockIdx.x] = nvis;
+    }
   }
   // ---- per-tile counts.  A face overlapping at most kSmallTiles tiles takes its slot in each
   //      tile from the returning atomic and records it, so emission needs no atomics for it;
