@@ -336,9 +336,9 @@ __global__ __launch_bounds__(256) void k_project(tsr_scene_dev sc, const float* 
   });
 }
 
-// Single workgroup of 1024 threads: (1) exclusive scan of the visible-face counts of the
-// projection workgroups (offsets of their segments in the dense visible list); (2) exclusive
-// scan of the tile counts into ranges, pair total K, overflow check against the capacity (all
+// Two workgroups of 1024 threads, working independently: (0) exclusive scan of the
+// visible-face counts of the projection workgroups (offsets of their segments in the dense
+// visible list); (1) exclusive scan of the tile counts into ranges, pair total K, overflow check against the capacity (all
 // ranges empty on overflow), the small-face counts left in tile_cnt2 as the base of the
 // larger faces' emission cursors, and the list of tiles too long for the one-wave sort.  Both scans run in rounds of 8192 entries, each thread
 // taking 8 consecutive ones.
@@ -355,36 +355,53 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(const uint32_t* __restrict_
   __shared__ unsigned long long wsum[16];
   const int tid = threadIdx.x;
   unsigned long long carry = 0, tot;
-  for (int base = 0; base < n_segments; base += kScanRound) {
-    const int i0 = base + tid * kScanPer;
-    uint32_t c[kScanPer];
-    unsigned long long sum = 0;
+  if (blockIdx.x == 0) {
+    // workgroup 0: offsets of the visible segments (the next round's loads are issued before
+    // the current round is scanned)
+    uint32_t c[kScanPer], cn[kScanPer];
 #pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
-      c[k] = (i0 + k < n_segments) ? vis_cnt[i0 + k] : 0u;
-      sum += c[k];
-    }
-    unsigned long long run = carry + block_excl_scan_u64(sum, wsum, &tot);
+    for (int k = 0; k < kScanPer; ++k) c[k] = (tid * kScanPer + k < n_segments) ? vis_cnt[tid * kScanPer + k] : 0u;
+    for (int base = 0; base < n_segments; base += kScanRound) {
+      const int i0 = base + tid * kScanPer;
 #pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
-      if (i0 + k < n_segments) vis_off[i0 + k] = (uint32_t)run;
-      run += c[k];
+      for (int k = 0; k < kScanPer; ++k) cn[k] = (i0 + kScanRound + k < n_segments) ? vis_cnt[i0 + kScanRound + k] : 0u;
+      unsigned long long sum = 0;
+#pragma unroll
+      for (int k = 0; k < kScanPer; ++k) sum += c[k];
+      unsigned long long run = carry + block_excl_scan_u64(sum, wsum, &tot);
+#pragma unroll
+      for (int k = 0; k < kScanPer; ++k) {
+        if (i0 + k < n_segments) vis_off[i0 + k] = (uint32_t)run;
+        run += c[k];
+      }
+      carry += tot;
+#pragma unroll
+      for (int k = 0; k < kScanPer; ++k) c[k] = cn[k];
     }
-    carry += tot;
+    if (tid == 0) *vis_total = (uint32_t)carry;
+    return;
   }
-  if (tid == 0) *vis_total = (uint32_t)carry;
 
-  carry = 0;
+  // workgroup 1: tile ranges
   unsigned long long carry_long = 0;
+  uint32_t cs[kScanPer], cb[kScanPer], csn[kScanPer], cbn[kScanPer];
+#pragma unroll
+  for (int k = 0; k < kScanPer; ++k) {
+    const bool in = tid * kScanPer + k < n_tiles;
+    cs[k] = in ? tile_cnt[tid * kScanPer + k] : 0u;
+    cb[k] = in ? tile_cnt2[tid * kScanPer + k] : 0u;
+  }
   for (int base = 0; base < n_tiles; base += kScanRound) {
     const int i0 = base + tid * kScanPer;
-    uint32_t cs[kScanPer], cb[kScanPer];
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      const bool in = i0 + kScanRound + k < n_tiles;
+      csn[k] = in ? tile_cnt[i0 + kScanRound + k] : 0u;
+      cbn[k] = in ? tile_cnt2[i0 + kScanRound + k] : 0u;
+    }
     unsigned long long sum = 0, nlong = 0;
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
-      const bool in = i0 + k < n_tiles;
-      cs[k] = in ? tile_cnt[i0 + k] : 0u;
-      cb[k] = in ? tile_cnt2[i0 + k] : 0u;
       sum += (unsigned long long)cs[k] + cb[k];
       nlong += (unsigned long long)cs[k] + cb[k] > (unsigned long long)kWaveSortMax;
     }
@@ -404,6 +421,11 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(const uint32_t* __restrict_
     }
     carry += tot;
     carry_long += tot_long;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      cs[k] = csn[k];
+      cb[k] = cbn[k];
+    }
   }
   if (tid == 0) *long_cnt = (uint32_t)carry_long;
   const bool over = carry > (unsigned long long)capacity;
@@ -778,7 +800,7 @@ hipError_t launch_bin(const tsr_scene_dev& sc, const float* poses, const ViewTab
   uint32_t* vis_total = reinterpret_cast<uint32_t*>(ws + L.vis_total);
   uint32_t* vis_dense = reinterpret_cast<uint32_t*>(ws + L.vis_dense);
   const int n_seg = (int)((nf + kProjBlock - 1) / kProjBlock);
-  TSR_LAUNCH("scan_tiles", k_scan_tiles, dim3(1), dim3(1024), 0, st, tile_cnt, tile_cnt2, ranges, vt.n_tiles,
+  TSR_LAUNCH("scan_tiles", k_scan_tiles, dim3(2), dim3(1024), 0, st, tile_cnt, tile_cnt2, ranges, vt.n_tiles,
                      sort ? L.capacity : (int64_t)0x7fffffffffffffffll, K, overflow, vis_cnt, vis_off, vis_total,
                      n_seg, long_cnt, long_list);
   if (!sort) return hipGetLastError();
