@@ -58,6 +58,7 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-track", action="store_true", help="skip the captured tracking-loop leg")
     ap.add_argument("--serve-queries", type=int, default=400)
+    ap.add_argument("--no-configs", action="store_true", help="skip the other configurations (64x48, 640x480, window)")
     return ap.parse_args()
 
 
@@ -178,6 +179,30 @@ def counter_traffic(kernel):
                 if m and m.group(1).split("<")[0] == kernel and m.group(4) == fp:
                     return int(m.group(2)) + int(m.group(3)), os.path.relpath(path, ROOT)
     return None, None
+
+
+def configs_leg(raster, scenes, steps, warmup):
+    """The fused step on the other configurations: 64x48 with 2k faces, 640x480 with a 200k room
+    soup (tracking step), and the 8-view 1200x680 mapping window over a 500k room soup."""
+    import torch
+
+    from paper_2605_31419_amd import autotune
+
+    out = {}
+    for name in ("single_64x48", "track_640x480", "window_8x1200x680"):
+        w = scenes.workload(name)
+        dev = raster.DeviceScene.from_numpy(w.scene)
+        case = Case(raster, scenes, dev, w.poses, w.intr, w.target_poses)
+        best, _ = autotune.tune(case.rast, case.poses, case.tc, case.td, reps=3)
+        case.rast.schedule = best
+        ms = time_steps(case.step, steps, warmup)
+        case.check()
+        out[name] = {"faces": int(w.scene.n_faces), "views": len(w.intr), "ms_per_step": ms,
+                     "mpix_s": case.pixels / (ms * 1e-3) / 1e6, "schedule": list(best)}
+        log(f"[bench] {name}: {ms:.3f} ms -> {out[name]['mpix_s']:.1f} Mpix/s")
+        del case, dev
+        torch.cuda.empty_cache()
+    return out
 
 
 def bin_sort_bytes(M, V, m_vis, K, n_tiles):
@@ -372,6 +397,8 @@ def main():
         serving = serving_leg(raster, w, dev, args.serve_queries)
         log(f"[bench] serving: {json.dumps(serving)}")
 
+    configs = None if args.no_configs else configs_leg(raster, scenes, args.steps, args.warmup)
+
     # rooflines
     bs_names = ["fill_tiles", "project", "scan_tiles", "emit", "tile_sort"]
     bs_ms = sum(ktimes.get(k, 0.0) for k in bs_names)
@@ -420,6 +447,7 @@ def main():
         "schedule": tuned,
         "tracking": tracking,
         "serving": serving,
+        "configs": configs,
         "copy_gbs": copy_gbs,
     }
     if not args.no_cpu_baseline:
