@@ -10,7 +10,8 @@
 
 namespace tsr {
 
-constexpr int kBatch = 64;
+constexpr int kBatch = 64;                 // faces per hit mask (one lane each)
+constexpr int kSpan = 128;                 // faces staged at once by a cooperative workgroup
 constexpr int kWaves = kBlock / kWave;     // waves per workgroup: one per 8x8 quadrant
 
 // Wave reduction of the 20 per-face gradient sums: 1 = transposing permlane-swap butterfly,
@@ -202,23 +203,28 @@ __device__ __forceinline__ void forward_walk(const TileCtx& c, const float* __re
   s.T = 1.f; s.C0 = s.C1 = s.C2 = s.D = 0.f; s.Tb = 1.f; s.last = -1;
   bool done = !c.inside;
   const float dxb = (float)c.px, dyb = (float)c.py;
-  for (uint32_t b0 = c.start; b0 < c.end; b0 += kBatch) {
-    const int n = (int)min((uint32_t)kBatch, c.end - b0);
+  constexpr int kStage = COOP ? kSpan : kBatch;     // faces staged at once
+  for (uint32_t s0 = c.start; s0 < c.end; s0 += kStage) {
+    const int ns = (int)min((uint32_t)kStage, c.end - s0);
     if constexpr (COOP) {
       if (__syncthreads_count(!done) == 0) break;
-      stage_batch_block(records, pairs, b0, n, srec, sface);
+      stage_batch_block(records, pairs, s0, ns, srec, sface);
       __syncthreads();
-      if (__ballot(!done) == 0) continue;
     } else {
       if (__ballot(!done) == 0) break;
-      stage_batch(records, pairs, b0, n, srec, sface);
+      stage_batch(records, pairs, s0, ns, srec, sface);
     }
-    unsigned long long mask = batch_hit_mask(srec, n, c.bx, c.by);
+    for (int h = 0; h < ns; h += kBatch) {
+    if (__ballot(!done) == 0) break;
+    const int n = min(kBatch, ns - h);
+    const uint32_t b0 = s0 + (uint32_t)h;
+    const float4* sr = srec + h * 6;
+    unsigned long long mask = batch_hit_mask(sr, n, c.bx, c.by);
     while (mask) {
       const int j = __builtin_ctzll(mask);
       mask &= mask - 1;
       Rec rc;
-      load_rec(srec, j, rc);
+      load_rec(sr, j, rc);
       PixelEval e;
       const float dx = dxb - (float)__float_as_int(rc.f[kRecU0]);
       const float dy = dyb - (float)__float_as_int(rc.f[kRecV0]);
@@ -236,6 +242,7 @@ __device__ __forceinline__ void forward_walk(const TileCtx& c, const float* __re
       done = done || (act && (Tn < t_min || Tn == 0.f));
       s.T = act ? Tn : s.T;
       if (__ballot(!done) == 0) break;
+    }
     }
   }
 }
@@ -269,25 +276,31 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
   float Tcur = Tb;
   float B0 = 0.f, B1 = 0.f, B2 = 0.f, BD = 0.f, BA = 0.f;
   const float dxb = (float)c.px, dyb = (float)c.py;
-  for (int b1 = top + 1; b1 > (int)c.start; b1 -= kBatch) {
-    const int b0 = max((int)c.start, b1 - kBatch);
-    const int n = b1 - b0;
+  constexpr int kStage = COOP ? kSpan : kBatch;     // faces staged at once
+  for (int s1 = top + 1; s1 > (int)c.start; s1 -= kStage) {
+    const int s0 = max((int)c.start, s1 - kStage);
+    const int ns = s1 - s0;
     if constexpr (COOP) {
       __syncthreads();
-      stage_batch_block(records, pairs, (uint32_t)b0, n, srec, sface);
+      stage_batch_block(records, pairs, (uint32_t)s0, ns, srec, sface);
       __syncthreads();
-      if (b0 > wlast) continue;
     } else {
-      stage_batch(records, pairs, (uint32_t)b0, n, srec, sface);
+      stage_batch(records, pairs, (uint32_t)s0, ns, srec, sface);
     }
-    unsigned long long mask = batch_hit_mask(srec, n, c.bx, c.by);
+    for (int h = ((ns - 1) / kBatch) * kBatch; h >= 0; h -= kBatch) {
+    const int b0 = s0 + h;
+    const int n = min(kBatch, ns - h);
+    if (b0 > wlast) continue;
+    const float4* sr = srec + h * 6;
+    const uint32_t* sf = sface + h;
+    unsigned long long mask = batch_hit_mask(sr, n, c.bx, c.by);
     if (wlast - b0 < 63) mask &= (2ull << (wlast - b0)) - 1ull;     // faces after the wave's last
     while (mask) {
       const int j = 63 - __builtin_clzll(mask);
       mask &= ~(1ull << j);
       const int idx = b0 + j;
       Rec rc;
-      load_rec(srec, j, rc);
+      load_rec(sr, j, rc);
       const float* r = rc.f;
       // Every lane evaluates the face; lanes that do not blend it (not covered, or behind
       // their last face) get zero gradient scales, so all 20 sums need no branches.
@@ -336,7 +349,7 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
       if (__ballot(act) == 0) continue;
 #if TSR_REDUCE_SWAP
       const float tot = wave_sum20(acc);
-      if (k_out >= 0) unsafeAtomicAdd(&grad_acc[(size_t)sface[j] * kGradDwords + k_out], (acc_t)tot);
+      if (k_out >= 0) unsafeAtomicAdd(&grad_acc[(size_t)sf[j] * kGradDwords + k_out], (acc_t)tot);
 #else
       float sum[kGradDwords];
 #pragma unroll
@@ -344,8 +357,9 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
       float mine = 0.f;
 #pragma unroll
       for (int k = 0; k < kGradDwords; ++k) mine = lane == k ? sum[k] : mine;
-      if (lane < kGradDwords) unsafeAtomicAdd(&grad_acc[(size_t)sface[j] * kGradDwords + lane], (acc_t)mine);
+      if (lane < kGradDwords) unsafeAtomicAdd(&grad_acc[(size_t)sf[j] * kGradDwords + lane], (acc_t)mine);
 #endif
+    }
     }
   }
 }
@@ -427,9 +441,9 @@ __global__ __launch_bounds__(kBlock) void k_train_fused(ViewTable vt, const floa
                                                         acc_t* __restrict__ grad_acc,
                                                         const int* __restrict__ order, int* __restrict__ queue,
                                                         int persistent) {
-  // the four waves stage each batch together (one copy of the records per tile)
-  __shared__ float4 srec[kBatch * 6];
-  __shared__ uint32_t sface[kBatch];
+  // the four waves stage each span together (one copy of the records per tile)
+  __shared__ float4 srec[kSpan * 6];
+  __shared__ uint32_t sface[kSpan];
   __shared__ int s_item;
   __shared__ int sint[4];
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
