@@ -11,7 +11,7 @@
 namespace tsr {
 
 constexpr int kBatch = 64;                 // faces per hit mask (one lane each)
-constexpr int kSpan = 128;                 // faces staged at once by a cooperative workgroup
+constexpr int kSpan = 256;                 // faces staged at once by a cooperative workgroup
 constexpr int kWaves = kBlock / kWave;     // waves per workgroup: one per 8x8 quadrant
 
 // Wave reduction of the 20 per-face gradient sums: 1 = transposing permlane-swap butterfly,
@@ -137,7 +137,7 @@ __device__ __forceinline__ void stage_batch_block(const float* __restrict__ reco
     const uint32_t face = (uint32_t)pairs[b0 + i / 6];
     srec[i] = reinterpret_cast<const float4*>(records)[(size_t)face * 6 + i % 6];
   }
-  if (threadIdx.x < n) sface[threadIdx.x] = (uint32_t)pairs[b0 + threadIdx.x];
+  for (int i = threadIdx.x; i < n; i += kBlock) sface[i] = (uint32_t)pairs[b0 + i];
 }
 
 // Per-wave staging: lane l reads the face id of entry l; the 6 n sixteen-byte pieces are then

@@ -65,13 +65,14 @@ def _huge_faces_scene(seed=0):
     return plain_scene(allv, col=col, opa=opa)
 
 
-def _long_tile_scene(n, seed=0):
-    """n small faces inside one 16x16 tile (tile list longer than one LDS sort pass)."""
+def _long_tile_scene(n, seed=0, opa=(0.3, 1.0)):
+    """n small faces inside one 16x16 tile (tile list longer than one LDS sort pass, and
+    longer than the span of faces a blending workgroup stages at once)."""
     g = np.random.default_rng(seed)
     c = g.uniform(1, 15, size=(n, 1, 2)) + g.uniform(-1.5, 1.5, size=(n, 3, 2))
     z = g.uniform(1, 3, size=(n, 1, 1)) * np.ones((n, 3, 1))
     v = np.concatenate([(c - 7.5) * z / 20.0, z], axis=2)
-    return plain_scene(v, col=g.uniform(0, 1, (n, 3, 3)), opa=g.uniform(0.3, 1, (n, 3)))
+    return plain_scene(v, col=g.uniform(0, 1, (n, 3, 3)), opa=g.uniform(*opa, (n, 3)))
 
 
 def _offscreen_scene():
@@ -137,6 +138,9 @@ CASES = {
     "equal_depth": lambda: (_equal_depth_scene(), [IDENTITY], [S.Intrinsics(64, 64, 40.0, 40.0, 31.5, 31.5)]),
     "huge_faces_640x480": lambda: (_huge_faces_scene(), [IDENTITY], [S.intrinsics_for(640, 480)]),
     "long_tile_800": lambda: (_long_tile_scene(1000, 5), [IDENTITY], [S.Intrinsics(16, 16, 20.0, 20.0, 7.5, 7.5)]),
+    # faint faces: the walks reach the end of the 1000-face list (several staged spans)
+    "long_tile_faint_1000": lambda: (_long_tile_scene(1000, 7, opa=(0.01, 0.05)), [IDENTITY],
+                                     [S.Intrinsics(16, 16, 20.0, 20.0, 7.5, 7.5)]),
     "long_tile_5000": lambda: (_long_tile_scene(5000), [IDENTITY], [S.Intrinsics(16, 16, 20.0, 20.0, 7.5, 7.5)]),
     "long_tile_12000": lambda: (_long_tile_scene(12000, 3), [IDENTITY], [S.Intrinsics(16, 16, 20.0, 20.0, 7.5, 7.5)]),
     "offscreen": lambda: (_offscreen_scene(), [IDENTITY], [S.intrinsics_for(64, 48)]),
@@ -198,7 +202,7 @@ def test_capacity_overflow_is_reported_and_harmless():
 # ---------------------------------------------------------------------------- forward
 
 FWD_CASES = ["single_64x48", "tiny_ragged_50x37", "equal_depth", "huge_faces_640x480", "long_tile_800",
-             "long_tile_5000", "multi_view_mixed"]
+             "long_tile_faint_1000", "long_tile_5000", "multi_view_mixed"]
 
 
 @pytest.mark.parametrize("name", FWD_CASES)
@@ -228,7 +232,8 @@ def test_forward_is_deterministic():
 
 # ---------------------------------------------------------------------------- backward
 
-BWD_CASES = ["single_64x48", "tiny_ragged_50x37", "equal_depth", "multi_view_mixed", "huge_faces_640x480"]
+BWD_CASES = ["single_64x48", "tiny_ragged_50x37", "equal_depth", "multi_view_mixed", "huge_faces_640x480",
+             "long_tile_800", "long_tile_faint_1000"]
 
 
 def _gpu_backward(rast, p, gc, gd, gt):
@@ -296,7 +301,8 @@ def _nudged_targets(oc, od, seed, shape_hw):
     return tc.astype(np.float32), td.astype(np.float32), int(near_c.sum() + near_d.sum())
 
 
-@pytest.mark.parametrize("name", ["single_64x48", "multi_view_mixed", "tiny_ragged_50x37"])
+@pytest.mark.parametrize("name", ["single_64x48", "multi_view_mixed", "tiny_ragged_50x37", "long_tile_800",
+                                  "long_tile_faint_1000"])
 def test_train_l1_matches_oracle(name):
     _say(f"[train_l1] case={name}")
     sc, poses, intrs = _case(name)
