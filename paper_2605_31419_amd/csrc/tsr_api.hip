@@ -146,9 +146,8 @@ WsLayout layout(const ViewTable& vt, int64_t cap) {
   L.grad_acc = o; o = align_up(o + sizeof(tsr::acc_t) * tsr::kGradDwords * nf);
   const int64_t nb = (nf + tsr::kProjBlock - 1) / tsr::kProjBlock;
   L.tile_cnt = o;
-  L.tile_cnt2 = o + sizeof(uint32_t) * vt.n_tiles;
-  L.long_cnt = o + sizeof(uint32_t) * 2 * vt.n_tiles;
-  o = align_up(o + sizeof(uint32_t) * (2 * vt.n_tiles + 1));
+  L.long_cnt = o + sizeof(uint32_t) * tsr::kTileCntStride * vt.n_tiles;
+  o = align_up(o + sizeof(uint32_t) * (tsr::kTileCntStride * vt.n_tiles + 1));
   L.slots = o; o = align_up(o + sizeof(uint32_t) * tsr::kSmallTiles * nf);
   L.long_list = o; o = align_up(o + sizeof(uint32_t) * vt.n_tiles);
   L.vis_cnt = o; o = align_up(o + sizeof(uint32_t) * nb);

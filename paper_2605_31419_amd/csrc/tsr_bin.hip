@@ -241,7 +241,7 @@ __device__ __forceinline__ void wave_expand(int cnt, F&& fn) {
 __global__ __launch_bounds__(256) void k_project(tsr_scene_dev sc, const float* __restrict__ poses, ViewTable vt,
                                                  float z_near, float r_min, uint32_t* __restrict__ counts,
                                                  float* __restrict__ records, uint32_t* __restrict__ tile_cnt,
-                                                 uint32_t* __restrict__ tile_cnt2, uint32_t* __restrict__ slots,
+                                                 uint32_t* __restrict__ slots,
                                                  uint32_t* __restrict__ vis_cnt, uint32_t* __restrict__ vis_list) {
   __shared__ uint32_t s_wave[4];
   __shared__ uint32_t s_cand[kProjBlock];
@@ -324,7 +324,8 @@ __global__ __launch_bounds__(256) void k_project(tsr_scene_dev sc, const float* 
     uint32_t sl[kSmallTiles];
 #pragma unroll
     for (int i = 0; i < kSmallTiles; ++i)
-      sl[i] = i < ntiles ? atomicAdd(&tile_cnt[tile_base + (ty0 + i / tw) * tiles_x + tx0 + i % tw], 1u) : 0u;
+      sl[i] = i < ntiles ? atomicAdd(&tile_cnt[kTileCntStride * (tile_base + (ty0 + i / tw) * tiles_x + tx0 + i % tw)], 1u)
+                         : 0u;
     *reinterpret_cast<uint4*>(slots + g * kSmallTiles) = make_uint4(sl[0], sl[1], sl[2], sl[3]);
   }
   const int big = ntiles > kSmallTiles ? ntiles : 0;
@@ -332,7 +333,7 @@ __global__ __launch_bounds__(256) void k_project(tsr_scene_dev sc, const float* 
   wave_expand(big, [&](bool valid, int owner, int i) {
     const int otx0 = __shfl(tx0, owner, 64), oty0 = __shfl(ty0, owner, 64), otw = __shfl(tw, owner, 64);
     const int obase = __shfl(tile_base, owner, 64), otx = __shfl(tiles_x, owner, 64);
-    if (valid) atomicAdd(&tile_cnt2[obase + (oty0 + i / otw) * otx + otx0 + i % otw], 1u);
+    if (valid) atomicAdd(&tile_cnt[kTileCntStride * (obase + (oty0 + i / otw) * otx + otx0 + i % otw) + 2], 1u);
   });
 }
 
@@ -345,8 +346,7 @@ __global__ __launch_bounds__(256) void k_project(tsr_scene_dev sc, const float* 
 constexpr int kScanPer = 8;
 constexpr int kScanRound = 1024 * kScanPer;
 
-__global__ __launch_bounds__(1024) void k_scan_tiles(const uint32_t* __restrict__ tile_cnt,
-                                                     uint32_t* __restrict__ tile_cnt2, uint32_t* __restrict__ ranges,
+__global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* __restrict__ tile_cnt, uint32_t* __restrict__ ranges,
                                                      int n_tiles, int64_t capacity, int64_t* __restrict__ K_out,
                                                      uint32_t* __restrict__ overflow, const uint32_t* __restrict__ vis_cnt,
                                                      uint32_t* __restrict__ vis_off, uint32_t* __restrict__ vis_total,
@@ -382,23 +382,37 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(const uint32_t* __restrict_
     return;
   }
 
-  // workgroup 1: tile ranges
+  // workgroup 1: tile ranges.  The counters of a round are loaded coalesced (entry
+  // base + 1024 k + tid) and handed to their owners (8 consecutive entries each) through LDS;
+  // the next round's loads are issued before the current round is scanned.
+  __shared__ uint2 s_cnt[kScanRound];
+  const uint4* cnt4 = reinterpret_cast<const uint4*>(tile_cnt);
   unsigned long long carry_long = 0;
-  uint32_t cs[kScanPer], cb[kScanPer], csn[kScanPer], cbn[kScanPer];
+  uint32_t cs[kScanPer], cb[kScanPer];
+  uint4 ld[kScanPer];
 #pragma unroll
   for (int k = 0; k < kScanPer; ++k) {
-    const bool in = tid * kScanPer + k < n_tiles;
-    cs[k] = in ? tile_cnt[tid * kScanPer + k] : 0u;
-    cb[k] = in ? tile_cnt2[tid * kScanPer + k] : 0u;
+    const int i = 1024 * k + tid;
+    ld[k] = i < n_tiles ? cnt4[i] : make_uint4(0u, 0u, 0u, 0u);
   }
   for (int base = 0; base < n_tiles; base += kScanRound) {
     const int i0 = base + tid * kScanPer;
 #pragma unroll
+    for (int k = 0; k < kScanPer; ++k) s_cnt[1024 * k + tid] = make_uint2(ld[k].x, ld[k].z);
+#pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
-      const bool in = i0 + kScanRound + k < n_tiles;
-      csn[k] = in ? tile_cnt[i0 + kScanRound + k] : 0u;
-      cbn[k] = in ? tile_cnt2[i0 + kScanRound + k] : 0u;
+      const int i = base + kScanRound + 1024 * k + tid;
+      ld[k] = i < n_tiles ? cnt4[i] : make_uint4(0u, 0u, 0u, 0u);
     }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      const uint2 c = s_cnt[tid * kScanPer + k];
+      cs[k] = c.x;
+      cb[k] = c.y;
+    }
+    // (the barriers inside the block scans below order these reads before the next round's
+    // LDS stores)
     unsigned long long sum = 0, nlong = 0;
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
@@ -414,18 +428,13 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(const uint32_t* __restrict_
         const unsigned long long c = (unsigned long long)cs[k] + cb[k];
         ranges[2 * (i0 + k)] = (uint32_t)run;
         ranges[2 * (i0 + k) + 1] = (uint32_t)(run + c);
-        tile_cnt2[i0 + k] = cs[k];           // larger faces are emitted after the recorded slots
+        tile_cnt[kTileCntStride * (i0 + k) + 2] = cs[k];   // larger faces go after the recorded slots
         if (c > (unsigned long long)kWaveSortMax) long_list[lpos++] = (uint32_t)(i0 + k);
         run += c;
       }
     }
     carry += tot;
     carry_long += tot_long;
-#pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
-      cs[k] = csn[k];
-      cb[k] = cbn[k];
-    }
   }
   if (tid == 0) *long_cnt = (uint32_t)carry_long;
   const bool over = carry > (unsigned long long)capacity;
@@ -506,7 +515,7 @@ __global__ __launch_bounds__(256) void k_emit(ViewTable vt, const uint32_t* __re
     const uint32_t khi = __shfl(key_hi, owner, 64), klo = __shfl(key_lo, owner, 64);
     if (valid) {
       const int t = obase + (oty0 + i / otw) * otx + otx0 + i % otw;
-      const uint32_t pos = ranges[2 * t] + atomicAdd(&cursor[t], 1u);
+      const uint32_t pos = ranges[2 * t] + atomicAdd(&cursor[kTileCntStride * t + 2], 1u);
       if (pos < ranges[2 * t + 1]) pairs[pos] = ((uint64_t)khi << 32) | klo;
       else atomicOr(&overflow[2], 2u);
     }
@@ -788,25 +797,24 @@ hipError_t launch_bin(const tsr_scene_dev& sc, const float* poses, const ViewTab
   uint32_t* vis_list = reinterpret_cast<uint32_t*>(ws + L.vis_list);
   uint32_t* long_cnt = reinterpret_cast<uint32_t*>(ws + L.long_cnt);
   uint32_t* long_list = reinterpret_cast<uint32_t*>(ws + L.long_list);
-  uint32_t* tile_cnt2 = reinterpret_cast<uint32_t*>(ws + L.tile_cnt2);
   uint32_t* slots = reinterpret_cast<uint32_t*>(ws + L.slots);
-  // both tile counters and the long-tile counter are contiguous: one fill
-  const int64_t n_cnt = 2 * (int64_t)vt.n_tiles + 1;
+  // the tile counters and the long-tile counter are contiguous: one fill
+  const int64_t n_cnt = kTileCntStride * (int64_t)vt.n_tiles + 1;
   TSR_LAUNCH("fill_tiles", k_fill_u32, dim3(grid_for(n_cnt, 256)), dim3(256), 0, st, tile_cnt, n_cnt, 0u);
   if (nf > 0)
     TSR_LAUNCH("project", k_project, dim3(grid_for(nf, kProjBlock)), dim3(kProjBlock), 0, st, sc, poses, vt, p.z_near, p.r_min, counts,
-                       records, tile_cnt, tile_cnt2, slots, vis_cnt, vis_list);
+                       records, tile_cnt, slots, vis_cnt, vis_list);
   uint32_t* vis_off = reinterpret_cast<uint32_t*>(ws + L.vis_off);
   uint32_t* vis_total = reinterpret_cast<uint32_t*>(ws + L.vis_total);
   uint32_t* vis_dense = reinterpret_cast<uint32_t*>(ws + L.vis_dense);
   const int n_seg = (int)((nf + kProjBlock - 1) / kProjBlock);
-  TSR_LAUNCH("scan_tiles", k_scan_tiles, dim3(2), dim3(1024), 0, st, tile_cnt, tile_cnt2, ranges, vt.n_tiles,
+  TSR_LAUNCH("scan_tiles", k_scan_tiles, dim3(2), dim3(1024), 0, st, tile_cnt, ranges, vt.n_tiles,
                      sort ? L.capacity : (int64_t)0x7fffffffffffffffll, K, overflow, vis_cnt, vis_off, vis_total,
                      n_seg, long_cnt, long_list);
   if (!sort) return hipGetLastError();
   if (nf > 0)
     TSR_LAUNCH("emit", k_emit, dim3(grid_for(nf, kProjBlock)), dim3(kProjBlock), 0, st, vt, counts, records, ranges,
-               slots, tile_cnt2, overflow, pairs, vis_cnt, vis_off, vis_list, vis_dense);
+               slots, tile_cnt, overflow, pairs, vis_cnt, vis_off, vis_list, vis_dense);
   TSR_LAUNCH("tile_sort", k_tile_sort, dim3(kLongBlocks + grid_for(vt.n_tiles, 4)), dim3(256), 0, st, ranges,
              vt.n_tiles, pairs, long_cnt, long_list, temp);
   return hipGetLastError();

@@ -32,9 +32,10 @@ struct WsLayout {
   size_t counts;                   // uint32 [V*M]
   size_t records;                  // float  [V*M][24]
   size_t grad_acc;                 // float  [V*M][20]
-  size_t tile_cnt;                 // uint32 [T] faces with <= 4 tiles, then uint32 [T] larger faces, then
-                                   // the uint32 long-tile counter (all filled together)
-  size_t tile_cnt2;                // uint32 [T] (second half of the counters)
+  size_t tile_cnt;                 // uint32 [T][4]: [0] faces with <= 4 tiles, [2] larger faces (later
+                                   // their emission cursor), [1] and [3] unused, so that every counter
+                                   // the atomics hit sits alone in its 8-byte word; then the uint32
+                                   // long-tile counter (all filled together)
   size_t long_cnt;                 // uint32: tiles whose list is too long for the register sort
   size_t slots;                    // uint32 [V*M][4]: a small face's slot in each of its tiles
   size_t long_list;                // uint32 [T]: those tiles
@@ -61,6 +62,7 @@ constexpr int kProjBlock = 256;        // faces per projection workgroup (one vi
 constexpr int kRegSortMax = 1024;      // tile lists up to this length are sorted in registers
 constexpr int kWaveSortMax = 512;      // ... by one wave (longer ones by a whole workgroup)
 constexpr int kSmallTiles = 4;         // faces overlapping at most this many tiles record their slots
+constexpr int kTileCntStride = 4;     // dwords per tile in the tile-counter array
 
 // Training-kernel schedule (chosen by the autotuner; the default is one workgroup per tile).
 struct TrainSchedule {

@@ -48,8 +48,8 @@ def test_autograd_function_matches_oracle():
 
 def test_autograd_keeps_no_per_pixel_lists():
     """The workspace grows by 8 bytes per pixel (last-face index, transmittance before it)
-    plus per-tile bookkeeping (counters, range, order and long-list entries: at most 32
-    bytes) -- independent of how many faces cover a pixel."""
+    plus per-tile bookkeeping (loss partials 16, counters 16, range 8, order 4 and long-list
+    entry 4: 48 bytes) -- independent of how many faces cover a pixel."""
     sc, intr = tiny_scene(22, n_faces=40)
     dev = raster.DeviceScene.from_numpy(sc)
     small = raster.Rasterizer(dev, [S.Intrinsics(64, 64, 50.0, 50.0, 31.5, 31.5)])
@@ -57,7 +57,7 @@ def test_autograd_keeps_no_per_pixel_lists():
     d = big.workspace_bytes(0) - small.workspace_bytes(0)
     px = 128 * 128 - 64 * 64
     tiles = 64 - 16
-    assert d <= 8 * px + 32 * tiles + 4 * 256, d
+    assert d <= 8 * px + 48 * tiles + 4 * 256, d
 
 
 # ---------------------------------------------------------------------------- mapping window
