@@ -147,8 +147,8 @@ __device__ __forceinline__ void write_record(const FaceAttr& at, const FaceSetup
   }
   rec[kRecOpa] = (float)(((double)at.opa[0] + (double)at.opa[1] + (double)at.opa[2]) / 3.0);
   rec[kRecZ] = (float)f.zf;
-  rec[kRecU0] = __int_as_float(f.u0);
-  rec[kRecV0] = __int_as_float(f.v0);
+  rec[kRecU0] = (float)f.u0;          // exact: |u0| < 2^24
+  rec[kRecV0] = (float)f.v0;
   rec[kRecU1] = __int_as_float(f.u1);
   rec[kRecV1] = __int_as_float(f.v1);
   float4* dst = reinterpret_cast<float4*>(dst_rec);
@@ -481,7 +481,7 @@ __global__ __launch_bounds__(256) void k_emit(ViewTable vt, const uint32_t* __re
   uint64_t key = 0;
   if (ntiles > 0) {
     const float* rec = records + g * kRecDwords;
-    const int u0 = __float_as_int(rec[kRecU0]), v0 = __float_as_int(rec[kRecV0]);
+    const int u0 = (int)rec[kRecU0], v0 = (int)rec[kRecV0];
     const int u1 = __float_as_int(rec[kRecU1]);
     tx0 = u0 >> 4;
     ty0 = v0 >> 4;

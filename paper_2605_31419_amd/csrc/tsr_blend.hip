@@ -46,7 +46,8 @@ __device__ __forceinline__ float window_pow(float rho, float sigma) {
 
 struct PixelEval {
   float rho, I, alpha, c0, c1, c2;
-  int kstar;       // edge attaining the minimum of E_k (lowest index on ties)
+  bool k0, k1;     // the edge attaining the minimum of E_k is edge 0 / edge 1 (lowest index on
+                   // ties; edge 2 when neither)
 };
 
 // A face record held in registers (loaded from LDS with six 16-byte reads).
@@ -75,7 +76,8 @@ __device__ __forceinline__ bool eval_face(const Rec& rc, float dx, float dy, flo
   const float E0 = fmaf(r[kRecEdge + 0], dx, fmaf(r[kRecEdge + 1], dy, r[kRecEdge + 2]));
   const float E1 = fmaf(r[kRecEdge + 3], dx, fmaf(r[kRecEdge + 4], dy, r[kRecEdge + 5]));
   const float E2 = fmaf(r[kRecEdge + 6], dx, fmaf(r[kRecEdge + 7], dy, r[kRecEdge + 8]));
-  e.kstar = (E0 <= E1 && E0 <= E2) ? 0 : (E1 <= E2 ? 1 : 2);
+  e.k0 = E0 <= E1 && E0 <= E2;
+  e.k1 = !e.k0 && E1 <= E2;
   e.rho = fminf(E0, fminf(E1, E2));
   const float I = e.rho >= 1.f ? 1.f : window_pow<SM>(e.rho, sigma);   // meaningless when rho <= 0
   const float alpha = r[kRecOpa] * I;
@@ -169,7 +171,7 @@ __device__ __forceinline__ unsigned long long batch_hit_mask(const float4* srec,
   bool hit = false;
   if (j < n) {
     const float4 rc = srec[j * 6 + kRecU0 / 4];
-    const int u0 = __float_as_int(rc.x), v0 = __float_as_int(rc.y), u1 = __float_as_int(rc.z), v1 = __float_as_int(rc.w);
+    const int u0 = (int)rc.x, v0 = (int)rc.y, u1 = __float_as_int(rc.z), v1 = __float_as_int(rc.w);
     const int xl = max(bx, u0), xh = min(bx + 7, u1), yl = max(by, v0), yh = min(by + 7, v1);
     hit = xl <= xh && yl <= yh;
     if (hit) {
@@ -193,6 +195,11 @@ struct FwdState {
   int last;
 };
 
+// A pixel blends faces while its transmittance is at least t_min and not zero.  T never
+// increases, so this is the rule "stop after the face that takes T below t_min, or to 0"
+// (t_min < 1) without a separate state; pixels outside the image start at T = 0.
+__device__ __forceinline__ bool live(float T, float t_min) { return T >= t_min && T > 0.f; }
+
 // Front-to-back walk over the tile list (eq. 4).  A pixel stops after the face that takes
 // its transmittance below t_min.  Records each pixel's last blended face and the
 // transmittance just before it.
@@ -200,22 +207,22 @@ template <int SM, bool COOP>
 __device__ __forceinline__ void forward_walk(const TileCtx& c, const float* __restrict__ records,
                                              const uint64_t* __restrict__ pairs, float sigma, float t_min,
                                              float4* srec, uint32_t* sface, FwdState& s) {
-  s.T = 1.f; s.C0 = s.C1 = s.C2 = s.D = 0.f; s.Tb = 1.f; s.last = -1;
-  bool done = !c.inside;
+  s.T = c.inside ? 1.f : 0.f;
+  s.C0 = s.C1 = s.C2 = s.D = 0.f; s.Tb = 1.f; s.last = -1;
   const float dxb = (float)c.px, dyb = (float)c.py;
   constexpr int kStage = COOP ? kSpan : kBatch;     // faces staged at once
   for (uint32_t s0 = c.start; s0 < c.end; s0 += kStage) {
     const int ns = (int)min((uint32_t)kStage, c.end - s0);
     if constexpr (COOP) {
-      if (__syncthreads_count(!done) == 0) break;
+      if (__syncthreads_count(live(s.T, t_min)) == 0) break;
       stage_batch_block(records, pairs, s0, ns, srec, sface);
       __syncthreads();
     } else {
-      if (__ballot(!done) == 0) break;
+      if (__ballot(live(s.T, t_min)) == 0) break;
       stage_batch(records, pairs, s0, ns, srec, sface);
     }
     for (int h = 0; h < ns; h += kBatch) {
-    if (__ballot(!done) == 0) break;
+    if (__ballot(live(s.T, t_min)) == 0) break;
     const int n = min(kBatch, ns - h);
     const uint32_t b0 = s0 + (uint32_t)h;
     const float4* sr = srec + h * 6;
@@ -226,22 +233,21 @@ __device__ __forceinline__ void forward_walk(const TileCtx& c, const float* __re
       Rec rc;
       load_rec(sr, j, rc);
       PixelEval e;
-      const float dx = dxb - (float)__float_as_int(rc.f[kRecU0]);
-      const float dy = dyb - (float)__float_as_int(rc.f[kRecV0]);
-      const bool act = eval_face<SM>(rc, dx, dy, sigma, e) && !done;
-      // lanes that do not blend this face keep their state (zero weight, selects)
-      const float w = act ? e.alpha * s.T : 0.f;
+      const float dx = dxb - rc.f[kRecU0];
+      const float dy = dyb - rc.f[kRecV0];
+      // stopping also at T == 0 means the backward never divides by 1 - alpha = 0
+      const bool act = eval_face<SM>(rc, dx, dy, sigma, e) && live(s.T, t_min);
+      // lanes that do not blend this face keep their state: alpha 0 gives weight 0 and T * 1
+      const float a = act ? e.alpha : 0.f;
+      const float w = a * s.T;
       s.C0 = fmaf(e.c0, w, s.C0);
       s.C1 = fmaf(e.c1, w, s.C1);
       s.C2 = fmaf(e.c2, w, s.C2);
       s.D = fmaf(rc.f[kRecZ], w, s.D);
-      const float Tn = s.T * (1.f - e.alpha);
       s.Tb = act ? s.T : s.Tb;
       s.last = act ? (int)(b0 + j) : s.last;
-      // stop once T < t_min; also at T == 0 so the backward never divides by 1 - alpha = 0
-      done = done || (act && (Tn < t_min || Tn == 0.f));
-      s.T = act ? Tn : s.T;
-      if (__ballot(!done) == 0) break;
+      s.T = s.T * (1.f - a);
+      if (__ballot(live(s.T, t_min)) == 0) break;
     }
     }
   }
@@ -263,14 +269,14 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
                                               acc_t* __restrict__ grad_acc) {
   const int lane = threadIdx.x & 63;
   // highest list position any pixel of this wave (COOP: of the workgroup) blended
-  const int wlast = wave_max_int(last);
+  const int wlast = uniform_int(wave_max_int(last));
   int top = wlast;
   if constexpr (COOP) {
     if (threadIdx.x == 0) sint[0] = -1;
     __syncthreads();
     if (lane == 0) atomicMax(&sint[0], wlast);
     __syncthreads();
-    top = sint[0];
+    top = uniform_int(sint[0]);
   }
   const int k_out = wave_sum20_slot();
   float Tcur = Tb;
@@ -303,18 +309,20 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
       load_rec(sr, j, rc);
       const float* r = rc.f;
       // Every lane evaluates the face; lanes that do not blend it (not covered, or behind
-      // their last face) get zero gradient scales, so all 20 sums need no branches.
-      const float dx = dxb - (float)__float_as_int(r[kRecU0]);
-      const float dy = dyb - (float)__float_as_int(r[kRecV0]);
+      // their last face) get alpha = I = 0, hence zero weight and zero gradient scales, so
+      // all 20 sums need no branches.
+      const float dx = dxb - r[kRecU0];
+      const float dy = dyb - r[kRecV0];
       PixelEval e;
       const bool act = eval_face<SM>(rc, dx, dy, sigma, e) && (idx <= last);
       const float alpha = act ? e.alpha : 0.f;
+      const float I = act ? e.I : 0.f;
       const float om = 1.f - alpha;
       // T before this face: the stored value at the last face, else T_after / (1 - alpha)
       const float Tj = (idx == last) ? Tb : Tcur * __builtin_amdgcn_rcpf(om);
-      if (act) Tcur = Tj;
+      Tcur = act ? Tj : Tcur;
       const float zf = r[kRecZ];
-      const float c0 = act ? e.c0 : 0.f, c1 = act ? e.c1 : 0.f, c2 = act ? e.c2 : 0.f;
+      const float c0 = e.c0, c1 = e.c1, c2 = e.c2;
       const float w = alpha * Tj;
       float acc[kGradDwords];
       // colour plane gradients: dL/dc_ch(p) = gC_ch alpha T, and c_ch = P dx + Q dy + R
@@ -323,23 +331,22 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
       acc[kGCol + 3] = gc1 * dx; acc[kGCol + 4] = gc1 * dy; acc[kGCol + 5] = gc1;
       acc[kGCol + 6] = gc2 * dx; acc[kGCol + 7] = gc2 * dy; acc[kGCol + 8] = gc2;
       acc[kGZ] = pg.gd * w;
-      // dL/dalpha = T (gC.(c - B) + gD (z - BD) - gT (1 - BA))
-      const float galpha = act ? Tj * (pg.g0 * (c0 - B0) + pg.g1 * (c1 - B1) + pg.g2 * (c2 - B2) +
-                                       pg.gd * (zf - BD) - pg.gt * (1.f - BA))
-                               : 0.f;
-      const float I = act ? e.I : 0.f;
+      // dL/dalpha = T (gC.(c - B) + gD (z - BD) - gT (1 - BA)); finite on every lane, and
+      // only used scaled by I or masked by act
+      const float galpha = Tj * (pg.g0 * (c0 - B0) + pg.g1 * (c1 - B1) + pg.g2 * (c2 - B2) +
+                                 pg.gd * (zf - BD) - pg.gt * (1.f - BA));
       acc[kGOpa] = galpha * I;
       const float gI = galpha * r[kRecOpa];
       float grho = 0.f;
       if constexpr (SM == 1) grho = (act && e.rho < 1.f) ? gI : 0.f;
       else grho = (act && e.rho < 1.f) ? gI * sigma * I * __builtin_amdgcn_rcpf(e.rho) : 0.f;   // sigma I / rho
-      const float ge0 = grho * dx, ge1 = grho * dy;
+      // only the edge attaining the minimum receives the window gradient
+      const float gk[3] = {e.k0 ? grho : 0.f, e.k1 ? grho : 0.f, (e.k0 || e.k1) ? 0.f : grho};
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        const bool on = e.kstar == k;
-        acc[kGEdge + 3 * k + 0] = on ? ge0 : 0.f;
-        acc[kGEdge + 3 * k + 1] = on ? ge1 : 0.f;
-        acc[kGEdge + 3 * k + 2] = on ? grho : 0.f;
+        acc[kGEdge + 3 * k + 0] = gk[k] * dx;
+        acc[kGEdge + 3 * k + 1] = gk[k] * dy;
+        acc[kGEdge + 3 * k + 2] = gk[k];
       }
       B0 = fmaf(c0, alpha, om * B0);
       B1 = fmaf(c1, alpha, om * B1);
@@ -622,7 +629,7 @@ __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float*
       n[k][0] = so * e[k][1] * inv_len[k];
       n[k][1] = -so * e[k][0] * inv_len[k];
     }
-    const double U0 = (double)__float_as_int(rec[kRecU0]), V0 = (double)__float_as_int(rec[kRecV0]);
+    const double U0 = (double)rec[kRecU0], V0 = (double)rec[kRecV0];
     double ca[3], cb[3], cc[3];       // edge coefficients a_k, b_k, c_k
     for (int k = 0; k < 3; ++k) {
       ca[k] = -n[k][0] * inv_r;

@@ -25,8 +25,8 @@ enum RecordField : int {
   kRecCol = 9,       // [3][3] P_ch, Q_ch, R_ch
   kRecOpa = 18,      // o_F
   kRecZ = 19,        // z_F
-  kRecU0 = 20,       // int u0
-  kRecV0 = 21,       // int v0
+  kRecU0 = 20,       // u0 as a float (an exact integer)
+  kRecV0 = 21,       // v0 as a float (an exact integer)
   kRecU1 = 22,       // int u1
   kRecV1 = 23,       // int v1
   kRecDwords = 24
@@ -131,6 +131,9 @@ __device__ __forceinline__ float wave_sum20(const float* v) {
   float out = t[0];
 #pragma unroll
   for (int k = 1; k < 5; ++k) out = j == k ? t[k] : out;
+  // keeps the sums in this (full-wave) part of the code, where the last DPP step fuses into
+  // its add, instead of letting them move into a caller's branch on the slot
+  asm volatile("" : "+v"(out));
   return out;
 }
 
