@@ -148,12 +148,11 @@ WsLayout layout(const ViewTable& vt, int64_t cap) {
   L.tile_cnt = o;
   L.long_cnt = o + sizeof(uint32_t) * tsr::kTileCntStride * vt.n_tiles;
   o = align_up(o + sizeof(uint32_t) * (tsr::kTileCntStride * vt.n_tiles + 1));
-  L.slots = o; o = align_up(o + sizeof(uint32_t) * tsr::kSmallTiles * nf);
   L.long_list = o; o = align_up(o + sizeof(uint32_t) * vt.n_tiles);
   L.vis_cnt = o; o = align_up(o + sizeof(uint32_t) * nb);
   L.vis_off = o; o = align_up(o + sizeof(uint32_t) * nb);
   L.vis_total = o; o = align_up(o + sizeof(uint32_t));
-  L.vis_list = o; o = align_up(o + sizeof(uint32_t) * nb * tsr::kProjBlock);
+  L.vis_list = o; o = align_up(o + sizeof(tsr::VisEntry) * nb * tsr::kProjBlock);
   L.vis_dense = o; o = align_up(o + sizeof(uint32_t) * nf);
   L.ranges = o; o = align_up(o + sizeof(uint32_t) * 2 * vt.n_tiles);
   L.order = o; o = align_up(o + sizeof(int32_t) * vt.n_tiles);

@@ -241,8 +241,7 @@ __device__ __forceinline__ void wave_expand(int cnt, F&& fn) {
 __global__ __launch_bounds__(256) void k_project(tsr_scene_dev sc, const float* __restrict__ poses, ViewTable vt,
                                                  float z_near, float r_min, uint32_t* __restrict__ counts,
                                                  float* __restrict__ records, uint32_t* __restrict__ tile_cnt,
-                                                 uint32_t* __restrict__ slots,
-                                                 uint32_t* __restrict__ vis_cnt, uint32_t* __restrict__ vis_list) {
+                                                 uint32_t* __restrict__ vis_cnt, VisEntry* __restrict__ vis_list) {
   __shared__ uint32_t s_wave[4];
   __shared__ uint32_t s_cand[kProjBlock];
   const int64_t M = vt.n_faces;
@@ -275,7 +274,8 @@ __global__ __launch_bounds__(256) void k_project(tsr_scene_dev sc, const float* 
   // the FP64 stage; the barriers below then wait for the remaining waves only.
   if (wave >= nact) return;
   // ---- exact setup of the candidates, one per lane (in g order)
-  int ntiles = 0, tx0 = 0, ty0 = 0, tw = 1, tile_base = 0, tiles_x = 1;
+  int ntiles = 0, tx0 = 0, ty0 = 0, tw = 1, th = 1, tile_base = 0, tiles_x = 1;
+  uint32_t zbits = 0u;
   int64_t g = 0;
   if (threadIdx.x < ncand) {
     g = (int64_t)s_cand[threadIdx.x];
@@ -292,25 +292,31 @@ __global__ __launch_bounds__(256) void k_project(tsr_scene_dev sc, const float* 
       tx0 = f.u0 >> 4;
       ty0 = f.v0 >> 4;
       tw = (f.u1 >> 4) - tx0 + 1;
-      ntiles = tw * ((f.v1 >> 4) - ty0 + 1);
+      th = (f.v1 >> 4) - ty0 + 1;
+      ntiles = tw * th;
       tile_base = vd.tile_off;
       tiles_x = vd.tiles_x;
       face_normals(f);
       write_record(at, f, records + g * kRecDwords);
+      zbits = __float_as_uint((float)f.zf);     // the record's z_F (set by face_normals)
     }
     counts[g] = (uint32_t)ntiles;
   }
   __syncthreads();                    // s_wave is reused below
-  // ---- visible (view, face) ids of this workgroup, compacted (still in g order) into its own
-  //      segment of the visible list: a wave ballot and per-wave counts in LDS, no atomics
+  // ---- visible (view, face) pairs of this workgroup, compacted (still in g order) into its
+  //      own segment of the visible list: a wave ballot and per-wave counts in LDS, no atomics
+  const bool vis = ntiles > 0;
+  uint4* ent = nullptr;
   {
-    const bool vis = ntiles > 0;
     const unsigned long long mask = __ballot(vis);
     if (lane == 0) s_wave[wave] = (uint32_t)__popcll(mask);
     __syncthreads();
     uint32_t off = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
     for (int w = 0; w < wave; ++w) off += s_wave[w];
-    if (vis) vis_list[(int64_t)blockIdx.x * kProjBlock + off] = (uint32_t)g;
+    ent = reinterpret_cast<uint4*>(vis_list + (int64_t)blockIdx.x * kProjBlock + off);
+    if (vis)
+      ent[0] = make_uint4((uint32_t)g, (uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tw | ((uint32_t)th << 16),
+                          zbits);
     if (threadIdx.x == 0) {
       uint32_t nvis = 0u;
       for (int w = 0; w < nact; ++w) nvis += s_wave[w];
@@ -320,13 +326,13 @@ __global__ __launch_bounds__(256) void k_project(tsr_scene_dev sc, const float* 
   // ---- per-tile counts.  A face overlapping at most kSmallTiles tiles takes its slot in each
   //      tile from the returning atomic and records it, so emission needs no atomics for it;
   //      larger faces are counted separately and spread over the wave.
-  if (ntiles > 0 && ntiles <= kSmallTiles) {
+  if (vis && ntiles <= kSmallTiles) {
     uint32_t sl[kSmallTiles];
 #pragma unroll
     for (int i = 0; i < kSmallTiles; ++i)
       sl[i] = i < ntiles ? atomicAdd(&tile_cnt[kTileCntStride * (tile_base + (ty0 + i / tw) * tiles_x + tx0 + i % tw)], 1u)
                          : 0u;
-    *reinterpret_cast<uint4*>(slots + g * kSmallTiles) = make_uint4(sl[0], sl[1], sl[2], sl[3]);
+    ent[1] = make_uint4(sl[0], sl[1], sl[2], sl[3]);
   }
   const int big = ntiles > kSmallTiles ? ntiles : 0;
   if (wave_max_int(big) == 0) return;
@@ -456,44 +462,40 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* __restrict__ tile
 
 // Emission of (float32 z_F bits << 32 | face) into each overlapped tile's bucket.  One
 // workgroup per projection workgroup, one lane per visible face of its segment (compacted,
-// in g order).  Small faces store at their recorded slot; larger faces take positions from
-// the per-tile cursors, spread over the wave.  A position outside its tile's range (never
-// expected) is not written and is reported through tsr_check.
-__global__ __launch_bounds__(256) void k_emit(ViewTable vt, const uint32_t* __restrict__ counts,
-                                              const float* __restrict__ records, const uint32_t* __restrict__ ranges,
-                                              const uint32_t* __restrict__ slots,
+// in g order), each reading its 32-byte visible-list entry.  Small faces store at their
+// recorded slot; larger faces take positions from the per-tile cursors, spread over the
+// wave.  A position outside its tile's range (never expected) is not written and is reported
+// through tsr_check.
+__global__ __launch_bounds__(256) void k_emit(ViewTable vt, const uint32_t* __restrict__ ranges,
                                               uint32_t* __restrict__ cursor, uint32_t* __restrict__ overflow,
                                               uint64_t* __restrict__ pairs, const uint32_t* __restrict__ vis_cnt,
-                                              const uint32_t* __restrict__ vis_off, const uint32_t* __restrict__ vis_list,
+                                              const uint32_t* __restrict__ vis_off, const VisEntry* __restrict__ vis_list,
                                               uint32_t* __restrict__ vis_dense) {
   const uint32_t nvis = vis_cnt[blockIdx.x];
-  int64_t g = 0;
-  if (threadIdx.x < nvis) {
-    g = (int64_t)vis_list[(int64_t)blockIdx.x * kProjBlock + threadIdx.x];
+  const bool mine = threadIdx.x < nvis;
+  const uint4* ent = reinterpret_cast<const uint4*>(vis_list + (int64_t)blockIdx.x * kProjBlock + threadIdx.x);
+  uint4 e0 = make_uint4(0u, 0u, 1u | (1u << 16), 0u);
+  if (mine) {
+    e0 = ent[0];
     // the segment goes to its place in the dense list (done even when the pairs overflowed:
     // the backward uses it)
-    vis_dense[vis_off[blockIdx.x] + threadIdx.x] = (uint32_t)g;
+    vis_dense[vis_off[blockIdx.x] + threadIdx.x] = e0.x;
   }
   if (overflow[0]) return;
   const int64_t M = vt.n_faces;
-  const int ntiles = threadIdx.x < nvis ? (int)counts[g] : 0;
-  int tx0 = 0, ty0 = 0, tw = 1, tile_base = 0, tiles_x = 1;
-  uint64_t key = 0;
-  if (ntiles > 0) {
-    const float* rec = records + g * kRecDwords;
-    const int u0 = (int)rec[kRecU0], v0 = (int)rec[kRecV0];
-    const int u1 = __float_as_int(rec[kRecU1]);
-    tx0 = u0 >> 4;
-    ty0 = v0 >> 4;
-    tw = (u1 >> 4) - tx0 + 1;
-    const ViewDesc& vd = vt.v[(int)(g / M)];
+  const int tx0 = (int)(e0.y & 0xFFFFu), ty0 = (int)(e0.y >> 16);
+  const int tw = (int)(e0.z & 0xFFFFu), th = (int)(e0.z >> 16);
+  const int ntiles = mine ? tw * th : 0;
+  int tile_base = 0, tiles_x = 1;
+  if (mine) {
+    const ViewDesc& vd = vt.v[(int)((int64_t)e0.x / M)];
     tile_base = vd.tile_off;
     tiles_x = vd.tiles_x;
-    key = ((uint64_t)__float_as_uint(rec[kRecZ]) << 32) | (uint64_t)(uint32_t)g;
   }
+  const uint64_t key = ((uint64_t)e0.w << 32) | (uint64_t)e0.x;
   if (ntiles > 0 && ntiles <= kSmallTiles) {
     // slots recorded during counting: plain stores
-    const uint4 sl = *reinterpret_cast<const uint4*>(slots + g * kSmallTiles);
+    const uint4 sl = ent[1];
     const uint32_t slv[4] = {sl.x, sl.y, sl.z, sl.w};
     bool bad = false;
 #pragma unroll
@@ -690,9 +692,9 @@ constexpr int kLongBlocks = 64;
 
 __device__ __forceinline__ void sort_long_tiles(const uint32_t* __restrict__ ranges, const uint32_t* __restrict__ long_cnt,
                                                 const uint32_t* __restrict__ long_list, uint64_t* __restrict__ pairs,
-                                                uint64_t* __restrict__ temp, uint64_t* s) {
+                                                uint64_t* __restrict__ temp, uint64_t* s, uint32_t first) {
   const uint32_t nl = *long_cnt;
-  for (uint32_t li = blockIdx.x; li < nl; li += kLongBlocks) {
+  for (uint32_t li = first; li < nl; li += kLongBlocks) {
   const int t = (int)long_list[li];
   const uint32_t start = ranges[2 * t], end = ranges[2 * t + 1];
   const int n = (int)(end - start);
@@ -747,15 +749,25 @@ __device__ __forceinline__ void sort_long_tiles(const uint32_t* __restrict__ ran
   }
 }
 
+// Workgroup 0 builds the longest-first tile order when `order` is given (running beside the
+// sorts); the next kLongBlocks sort the long lists; the rest sort one short tile list per wave.
 __global__ __launch_bounds__(256) void k_tile_sort(const uint32_t* __restrict__ ranges, int n_tiles,
                                                    uint64_t* __restrict__ pairs, const uint32_t* __restrict__ long_cnt,
-                                                   const uint32_t* __restrict__ long_list, uint64_t* __restrict__ temp) {
+                                                   const uint32_t* __restrict__ long_list, uint64_t* __restrict__ temp,
+                                                   int* __restrict__ order) {
   __shared__ uint64_t s[kSortLds];
-  if (blockIdx.x < kLongBlocks) {
-    sort_long_tiles(ranges, long_cnt, long_list, pairs, temp, s);
+  static_assert(kOrderBuckets * sizeof(uint32_t) + 16 * sizeof(uint64_t) <= sizeof(s), "order scratch in LDS");
+  if (blockIdx.x == 0) {
+    if (order)
+      build_tile_order(ranges, n_tiles, order, reinterpret_cast<uint32_t*>(s),
+                       reinterpret_cast<unsigned long long*>(s + kOrderBuckets / 2));
     return;
   }
-  const int t = (int)(blockIdx.x - kLongBlocks) * 4 + (int)(threadIdx.x >> 6);
+  if (blockIdx.x <= kLongBlocks) {
+    sort_long_tiles(ranges, long_cnt, long_list, pairs, temp, s, blockIdx.x - 1);
+    return;
+  }
+  const int t = (int)(blockIdx.x - 1 - kLongBlocks) * 4 + (int)(threadIdx.x >> 6);
   if (t >= n_tiles) return;
   const uint32_t start = ranges[2 * t], end = ranges[2 * t + 1];
   const int n = (int)(end - start);
@@ -794,16 +806,15 @@ hipError_t launch_bin(const tsr_scene_dev& sc, const float* poses, const ViewTab
   const int64_t nf = (int64_t)vt.n_views * vt.n_faces;
 
   uint32_t* vis_cnt = reinterpret_cast<uint32_t*>(ws + L.vis_cnt);
-  uint32_t* vis_list = reinterpret_cast<uint32_t*>(ws + L.vis_list);
+  VisEntry* vis_list = reinterpret_cast<VisEntry*>(ws + L.vis_list);
   uint32_t* long_cnt = reinterpret_cast<uint32_t*>(ws + L.long_cnt);
   uint32_t* long_list = reinterpret_cast<uint32_t*>(ws + L.long_list);
-  uint32_t* slots = reinterpret_cast<uint32_t*>(ws + L.slots);
   // the tile counters and the long-tile counter are contiguous: one fill
   const int64_t n_cnt = kTileCntStride * (int64_t)vt.n_tiles + 1;
   TSR_LAUNCH("fill_tiles", k_fill_u32, dim3(grid_for(n_cnt, 256)), dim3(256), 0, st, tile_cnt, n_cnt, 0u);
   if (nf > 0)
     TSR_LAUNCH("project", k_project, dim3(grid_for(nf, kProjBlock)), dim3(kProjBlock), 0, st, sc, poses, vt, p.z_near, p.r_min, counts,
-                       records, tile_cnt, slots, vis_cnt, vis_list);
+                       records, tile_cnt, vis_cnt, vis_list);
   uint32_t* vis_off = reinterpret_cast<uint32_t*>(ws + L.vis_off);
   uint32_t* vis_total = reinterpret_cast<uint32_t*>(ws + L.vis_total);
   uint32_t* vis_dense = reinterpret_cast<uint32_t*>(ws + L.vis_dense);
@@ -813,10 +824,13 @@ hipError_t launch_bin(const tsr_scene_dev& sc, const float* poses, const ViewTab
                      n_seg, long_cnt, long_list);
   if (!sort) return hipGetLastError();
   if (nf > 0)
-    TSR_LAUNCH("emit", k_emit, dim3(grid_for(nf, kProjBlock)), dim3(kProjBlock), 0, st, vt, counts, records, ranges,
-               slots, tile_cnt, overflow, pairs, vis_cnt, vis_off, vis_list, vis_dense);
-  TSR_LAUNCH("tile_sort", k_tile_sort, dim3(kLongBlocks + grid_for(vt.n_tiles, 4)), dim3(256), 0, st, ranges,
-             vt.n_tiles, pairs, long_cnt, long_list, temp);
+    TSR_LAUNCH("emit", k_emit, dim3(grid_for(nf, kProjBlock)), dim3(kProjBlock), 0, st, vt, ranges, tile_cnt,
+               overflow, pairs, vis_cnt, vis_off, vis_list, vis_dense);
+  // small tile counts: the order is built beside the sorts (hidden behind them); larger ones by
+  // the backward set-up, and only for schedules that use it
+  int* order = vt.n_tiles <= kOrderInSortMax ? reinterpret_cast<int*>(ws + L.order) : nullptr;
+  TSR_LAUNCH("tile_sort", k_tile_sort, dim3(1 + kLongBlocks + grid_for(vt.n_tiles, 4)), dim3(256), 0, st, ranges,
+             vt.n_tiles, pairs, long_cnt, long_list, temp, order);
   return hipGetLastError();
 }
 

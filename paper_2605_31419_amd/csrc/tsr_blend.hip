@@ -872,41 +872,10 @@ __global__ __launch_bounds__(256) void k_vertex_gather(tsr_scene_dev sc, ViewTab
   }
 }
 
-// Longest-first tile order by one workgroup: counting sort of the tiles by list length
-// (lengths above kOrderBuckets - 1 share the top bucket), descending.  `hist` is kOrderBuckets
-// shared counters, `wsum` 16 shared slots; blockDim.x divides kOrderBuckets.
-__device__ void build_tile_order(const uint32_t* __restrict__ ranges, int n_tiles, int* __restrict__ order,
-                                 uint32_t* hist, unsigned long long* wsum) {
-  const int nb = blockDim.x;
-  for (int b = threadIdx.x; b < kOrderBuckets; b += nb) hist[b] = 0u;
-  __syncthreads();
-  // bucket kOrderBuckets - 1 - length: an ascending scan then places long lists first
-  for (int t = threadIdx.x; t < n_tiles; t += nb) {
-    const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
-    atomicAdd(&hist[kOrderBuckets - 1 - (int)min(len, (uint32_t)kOrderBuckets - 1u)], 1u);
-  }
-  __syncthreads();
-  const int per = kOrderBuckets / nb;
-  unsigned long long sum = 0, tot;
-  for (int k = 0; k < per; ++k) sum += hist[threadIdx.x * per + k];
-  unsigned long long run = block_excl_scan_u64(sum, wsum, &tot);
-  for (int k = 0; k < per; ++k) {
-    const uint32_t h = hist[threadIdx.x * per + k];
-    hist[threadIdx.x * per + k] = (uint32_t)run;
-    run += h;
-  }
-  __syncthreads();
-  for (int t = threadIdx.x; t < n_tiles; t += nb) {
-    const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
-    const uint32_t pos = atomicAdd(&hist[kOrderBuckets - 1 - (int)min(len, (uint32_t)kOrderBuckets - 1u)], 1u);
-    order[pos] = t;
-  }
-}
-
 // Set-up of a backward pass: zero the gradient accumulators of the visible (view, face) pairs
 // (one 16-byte store per thread, grid-stride); workgroup 0 also zeroes the per-view FP64 pose
 // and loss accumulators and the persistent kernel's queue counter, and builds the
-// longest-first tile order when `order` is given.
+// longest-first tile order when `order` is given (tile counts the binning leaves it to).
 __global__ __launch_bounds__(256) void k_prep_bwd(ViewTable vt, const uint32_t* __restrict__ vis_total,
                                                   const uint32_t* __restrict__ vis_dense, acc_t* __restrict__ grad_acc,
                                                   double* __restrict__ pose_acc, double* __restrict__ loss_acc,
@@ -1046,8 +1015,9 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
   {
     const int64_t rows16 = nf * (int64_t)((kGradDwords * sizeof(acc_t)) / 16);
     const unsigned g = (unsigned)std::min<int64_t>(std::max<int64_t>(grid_for(rows16, 256), 1), 2048);
+    int* order_prep = vt.n_tiles > kOrderInSortMax ? order : nullptr;   // else built with the binning
     TSR_LAUNCH("prep_bwd", k_prep_bwd, dim3(g), dim3(256), 0, st, vt, vis_total, vis_dense, grad_acc, pose_acc,
-               loss_acc, ranges, order, queue);
+               loss_acc, ranges, order_prep, queue);
   }
   const dim3 block(kBlock);
   const int sm = sigma_mode(p.sigma);

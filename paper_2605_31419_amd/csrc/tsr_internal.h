@@ -37,12 +37,12 @@ struct WsLayout {
                                    // the atomics hit sits alone in its 8-byte word; then the uint32
                                    // long-tile counter (all filled together)
   size_t long_cnt;                 // uint32: tiles whose list is too long for the register sort
-  size_t slots;                    // uint32 [V*M][4]: a small face's slot in each of its tiles
   size_t long_list;                // uint32 [T]: those tiles
   size_t vis_cnt;                  // uint32 [NB]: visible (view, face) pairs of each projection workgroup
   size_t vis_off;                  // uint32 [NB]: exclusive scan of vis_cnt
   size_t vis_total;                // uint32: total visible (view, face) pairs
-  size_t vis_list;                 // uint32 [NB][256]: their ids g = v * M + m (first vis_cnt[b] entries)
+  size_t vis_list;                 // VisEntry [NB][256]: the visible (view, face) pairs of projection
+                                   // workgroup b (first vis_cnt[b] entries)
   size_t vis_dense;                // uint32 [V*M]: the same ids, compacted (first vis_total entries)
   size_t ranges;                   // uint32 [T][2]
   size_t order;                    // int32  [T] tile schedule (longest lists first)
@@ -63,6 +63,49 @@ constexpr int kRegSortMax = 1024;      // tile lists up to this length are sorte
 constexpr int kWaveSortMax = 512;      // ... by one wave (longer ones by a whole workgroup)
 constexpr int kSmallTiles = 4;         // faces overlapping at most this many tiles record their slots
 constexpr int kTileCntStride = 4;     // dwords per tile in the tile-counter array
+
+// What the emission of one visible (view, face) pair needs, written by the projection in the
+// order of its workgroup's faces: id g = v * M + m, first tile column and row, tile extent,
+// the float32 z_F bits of its sort key, and (faces over at most kSmallTiles tiles) its slot in
+// each tile, row-major over its tile rectangle.
+struct VisEntry {
+  uint32_t g, t0, ext, zbits;   // t0 = tx0 | ty0 << 16, ext = tiles wide | tiles high << 16
+  uint32_t slot[kSmallTiles];
+};
+
+constexpr int kOrderInSortMax = 8192;  // tile counts whose longest-first order the binning builds
+
+// Longest-first order of the tiles for the training kernel's queue, by one workgroup: a
+// counting sort of the tiles by list length, descending (lengths of kOrderBuckets - 1 and more
+// share the first bucket).  `hist` is kOrderBuckets shared counters, `wsum` 16 shared slots;
+// blockDim.x divides kOrderBuckets.
+__device__ inline void build_tile_order(const uint32_t* __restrict__ ranges, int n_tiles, int* __restrict__ order,
+                                 uint32_t* hist, unsigned long long* wsum) {
+  const int nb = blockDim.x;
+  for (int b = threadIdx.x; b < kOrderBuckets; b += nb) hist[b] = 0u;
+  __syncthreads();
+  // bucket kOrderBuckets - 1 - length: an ascending scan then places long lists first
+  for (int t = threadIdx.x; t < n_tiles; t += nb) {
+    const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+    atomicAdd(&hist[kOrderBuckets - 1 - (int)min(len, (uint32_t)kOrderBuckets - 1u)], 1u);
+  }
+  __syncthreads();
+  const int per = kOrderBuckets / nb;
+  unsigned long long sum = 0, tot;
+  for (int k = 0; k < per; ++k) sum += hist[threadIdx.x * per + k];
+  unsigned long long run = block_excl_scan_u64(sum, wsum, &tot);
+  for (int k = 0; k < per; ++k) {
+    const uint32_t h = hist[threadIdx.x * per + k];
+    hist[threadIdx.x * per + k] = (uint32_t)run;
+    run += h;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < n_tiles; t += nb) {
+    const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+    const uint32_t pos = atomicAdd(&hist[kOrderBuckets - 1 - (int)min(len, (uint32_t)kOrderBuckets - 1u)], 1u);
+    order[pos] = t;
+  }
+}
 
 // Training-kernel schedule (chosen by the autotuner; the default is one workgroup per tile).
 struct TrainSchedule {

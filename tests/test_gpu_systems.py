@@ -106,8 +106,12 @@ def test_window_batched_equals_sum_of_single_views():
         assert ok, msg
 
 
-def test_every_schedule_gives_the_same_step():
-    sc, dev, poses, intrs, tc, td = _window_inputs(n_views=3, n_faces=40_000)
+@pytest.mark.parametrize("w,h", [(320, 240), (1200, 680)], ids=["900_tiles", "9675_tiles"])
+def test_every_schedule_gives_the_same_step(w, h):
+    """Every schedule reproduces the one-workgroup-per-tile step.  The longest-first tile
+    order is built with the binning for the 900-tile window and by the backward set-up for the
+    9675-tile one (above 8192 tiles)."""
+    sc, dev, poses, intrs, tc, td = _window_inputs(n_views=3, n_faces=40_000, w=w, h=h)
     p = raster.poses_tensor(poses)
     win = MappingWindow(dev, intrs, schedule=(0, 0, 0))
     win.prepare(p)
