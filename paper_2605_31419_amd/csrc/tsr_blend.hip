@@ -259,9 +259,11 @@ struct PixGrad {
 };
 
 // Back-to-front walk (Sec. 3.3).  T before each face is recovered by division from the
-// transmittance before the last blended face, B* hold what lies behind the current face
-// composited from transmittance 1, and per-face sums of the 20 record-parameter gradients
-// are reduced over the wave and added to grad_acc.
+// transmittance before the last blended face.  What lies behind the current face, composited
+// from transmittance 1 (colour B, depth BD, opacity BA), enters dL/dalpha only through
+// S = gC.B + gD BD - gT BA, so S is carried instead: with P = gC.c + gD z - gT for the face,
+// dL/dalpha = T (P - S) and S <- alpha P + (1 - alpha) S.  Per-face sums of the 20
+// record-parameter gradients are reduced over the wave and added to grad_acc.
 template <int SM, bool COOP>
 __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __restrict__ records,
                                               const uint64_t* __restrict__ pairs, float sigma, int last, float Tb,
@@ -280,7 +282,7 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
   }
   const int k_out = wave_sum20_slot();
   float Tcur = Tb;
-  float B0 = 0.f, B1 = 0.f, B2 = 0.f, BD = 0.f, BA = 0.f;
+  float S = 0.f;
   const float dxb = (float)c.px, dyb = (float)c.py;
   constexpr int kStage = COOP ? kSpan : kBatch;     // faces staged at once
   for (int s1 = top + 1; s1 > (int)c.start; s1 -= kStage) {
@@ -331,10 +333,10 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
       acc[kGCol + 3] = gc1 * dx; acc[kGCol + 4] = gc1 * dy; acc[kGCol + 5] = gc1;
       acc[kGCol + 6] = gc2 * dx; acc[kGCol + 7] = gc2 * dy; acc[kGCol + 8] = gc2;
       acc[kGZ] = pg.gd * w;
-      // dL/dalpha = T (gC.(c - B) + gD (z - BD) - gT (1 - BA)); finite on every lane, and
-      // only used scaled by I or masked by act
-      const float galpha = Tj * (pg.g0 * (c0 - B0) + pg.g1 * (c1 - B1) + pg.g2 * (c2 - B2) +
-                                 pg.gd * (zf - BD) - pg.gt * (1.f - BA));
+      // dL/dalpha = T (gC.(c - B) + gD (z - BD) - gT (1 - BA)) = T (P - S); finite on every
+      // lane, and only used scaled by I or masked by act
+      const float P = fmaf(pg.g0, c0, fmaf(pg.g1, c1, fmaf(pg.g2, c2, fmaf(pg.gd, zf, -pg.gt))));
+      const float galpha = Tj * (P - S);
       acc[kGOpa] = galpha * I;
       const float gI = galpha * r[kRecOpa];
       float grho = 0.f;
@@ -348,11 +350,7 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
         acc[kGEdge + 3 * k + 1] = gk[k] * dy;
         acc[kGEdge + 3 * k + 2] = gk[k];
       }
-      B0 = fmaf(c0, alpha, om * B0);
-      B1 = fmaf(c1, alpha, om * B1);
-      B2 = fmaf(c2, alpha, om * B2);
-      BD = fmaf(zf, alpha, om * BD);
-      BA = fmaf(1.f, alpha, om * BA);
+      S = fmaf(alpha, P, om * S);
       if (__ballot(act) == 0) continue;
 #if TSR_REDUCE_SWAP
       const float tot = wave_sum20(acc);
