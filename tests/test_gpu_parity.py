@@ -10,7 +10,7 @@ import pytest
 import torch
 
 from oracle import oracle as O
-from paper_2605_31419_amd import raster
+from paper_2605_31419_amd import _lib, raster
 from paper_2605_31419_amd import scenes as S
 from tests import gpu_util as G
 from tests.helpers import IDENTITY, grad_close, plain_scene, tiny_scene
@@ -73,6 +73,30 @@ def _long_tile_scene(n, seed=0, opa=(0.3, 1.0)):
     z = g.uniform(1, 3, size=(n, 1, 1)) * np.ones((n, 3, 1))
     v = np.concatenate([(c - 7.5) * z / 20.0, z], axis=2)
     return plain_scene(v, col=g.uniform(0, 1, (n, 3, 3)), opa=g.uniform(*opa, (n, 3)))
+
+
+def _pixel_scene(n, w, h, f=20.0, seed=0, size=3.0, opa=(0.3, 1.0)):
+    """n small faces placed in pixel space over a w x h image (focal f, centred principal
+    point), back-projected at depths 1-3."""
+    g = np.random.default_rng(seed)
+    cx, cy = (w - 1) / 2.0, (h - 1) / 2.0
+    c = np.stack([g.uniform(0, w - 1, n), g.uniform(0, h - 1, n)], axis=1)[:, None, :]
+    c = c + g.uniform(-size, size, size=(n, 3, 2))
+    z = g.uniform(1, 3, size=(n, 1, 1)) * np.ones((n, 3, 1))
+    xy = (c - np.array([cx, cy])) * z / f
+    return plain_scene(np.concatenate([xy, z], axis=2), col=g.uniform(0, 1, (n, 3, 3)), opa=g.uniform(*opa, (n, 3)))
+
+
+def _pixel_intr(w, h, f=20.0):
+    return S.Intrinsics(w, h, f, f, (w - 1) / 2.0, (h - 1) / 2.0)
+
+
+def _max_views_case():
+    """TSR_MAX_VIEWS views of one map, sizes from 1x1 and single rows/columns to several
+    ragged tiles, each camera looking at the same pixel-space soup from its own centre."""
+    sizes = [(1, 1), (17, 1), (1, 17), (16, 16), (33, 9), (2, 2), (48, 31), (5, 64)] * (_lib.TSR_MAX_VIEWS // 8)
+    assert len(sizes) == _lib.TSR_MAX_VIEWS
+    return _pixel_scene(150, 40, 40, seed=11, size=4.0), [IDENTITY] * len(sizes), [_pixel_intr(w, h) for w, h in sizes]
 
 
 def _offscreen_scene():
@@ -145,6 +169,11 @@ CASES = {
     "long_tile_12000": lambda: (_long_tile_scene(12000, 3), [IDENTITY], [S.Intrinsics(16, 16, 20.0, 20.0, 7.5, 7.5)]),
     "offscreen": lambda: (_offscreen_scene(), [IDENTITY], [S.intrinsics_for(64, 48)]),
     "culling_boundaries_1200x680": _boundary_case,
+    # boundary extremes: widest and tallest images (1024 tiles in one row / column), and the
+    # maximum number of views with 1x1, single-row and single-column images among them
+    "wide_16384x2": lambda: (_pixel_scene(400, 16384, 2, seed=3), [IDENTITY], [_pixel_intr(16384, 2)]),
+    "tall_3x16384": lambda: (_pixel_scene(400, 3, 16384, seed=4), [IDENTITY], [_pixel_intr(3, 16384)]),
+    "max_views_32": _max_views_case,
     "multi_view_mixed": lambda: (tiny_scene(7, n_faces=80, w=40, h=30)[0], [IDENTITY, IDENTITY, IDENTITY],
                                  [S.Intrinsics(40, 30, 30.0, 30.0, 19.5, 14.5), S.Intrinsics(33, 17, 25.0, 25.0, 16.0, 8.0),
                                   S.Intrinsics(64, 48, 45.0, 45.0, 31.5, 23.5)]),
@@ -202,7 +231,8 @@ def test_capacity_overflow_is_reported_and_harmless():
 # ---------------------------------------------------------------------------- forward
 
 FWD_CASES = ["single_64x48", "tiny_ragged_50x37", "equal_depth", "huge_faces_640x480", "long_tile_800",
-             "long_tile_faint_1000", "long_tile_5000", "multi_view_mixed"]
+             "long_tile_faint_1000", "long_tile_5000", "multi_view_mixed", "wide_16384x2", "tall_3x16384",
+             "max_views_32"]
 
 
 @pytest.mark.parametrize("name", FWD_CASES)
@@ -233,7 +263,7 @@ def test_forward_is_deterministic():
 # ---------------------------------------------------------------------------- backward
 
 BWD_CASES = ["single_64x48", "tiny_ragged_50x37", "equal_depth", "multi_view_mixed", "huge_faces_640x480",
-             "long_tile_800", "long_tile_faint_1000"]
+             "long_tile_800", "long_tile_faint_1000", "wide_16384x2", "tall_3x16384", "max_views_32"]
 
 
 def _gpu_backward(rast, p, gc, gd, gt):
@@ -302,7 +332,7 @@ def _nudged_targets(oc, od, seed, shape_hw):
 
 
 @pytest.mark.parametrize("name", ["single_64x48", "multi_view_mixed", "tiny_ragged_50x37", "long_tile_800",
-                                  "long_tile_faint_1000"])
+                                  "long_tile_faint_1000", "max_views_32"])
 def test_train_l1_matches_oracle(name):
     _say(f"[train_l1] case={name}")
     sc, poses, intrs = _case(name)
