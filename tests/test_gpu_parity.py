@@ -385,3 +385,46 @@ def test_pose_step_matches_matrix_exponential():
         tau = -np.concatenate([0.01 * grad[v, :3], 0.02 * grad[v, 3:]]).astype(np.float64)
         ref = left_perturb(poses[v].astype(np.float64), tau)
         np.testing.assert_allclose(out[v], ref, atol=2e-6)
+
+
+# ---------------------------------------------------------------------------- output overwrite
+
+@pytest.mark.parametrize("name", ["single_64x48", "multi_view_mixed"])
+@pytest.mark.parametrize("fused", [False, True], ids=["separate", "fused"])
+def test_gradients_overwrite_their_outputs(name, fused):
+    """Gradient outputs are overwritten, whatever they held: with NaN-filled buffers the results
+    equal those written into fresh buffers, and the vertices of faces no view sees come back
+    exactly 0 (the vertex gather writes every vertex of a soup)."""
+    _say(f"[overwrite] case={name} fused={fused}")
+    sc, poses, intrs = _case(name)
+    rast, p = G.make(sc, intrs, poses)
+    rast.bin_and_sort(p)
+    P = rast.total_pixels
+    g = np.random.default_rng(7)
+    if fused:
+        c, d, _ = rast.forward(p)
+        tc = G.to_dev(g.uniform(0, 1, 3 * P).astype(np.float32))
+        td = G.to_dev(g.uniform(0.5, 4, P).astype(np.float32))
+        run = lambda out: rast.train_l1(p, tc, td, out=out)
+    else:
+        rast.forward(p)
+        gc = G.to_dev(g.normal(size=3 * P).astype(np.float32))
+        gd = G.to_dev(g.normal(size=P).astype(np.float32))
+        run = lambda out: rast.backward(p, gc, gd, None, out=out)
+    ref = [x.clone() for x in run(None)]
+    bufs = [torch.full_like(x, float("nan")) for x in ref]
+    got = run(bufs)
+    torch.cuda.synchronize()
+    seen = np.zeros(sc.n_faces, bool)
+    for v in range(len(poses)):
+        _, _, _, tiles = O.project(sc, poses[v], intrs[v])
+        seen |= tiles > 0
+    unseen_v = np.repeat(~seen, 3)
+    assert unseen_v.any() and seen.any()
+    for nm, a, b in zip(["pos", "col", "opa", "pose"], got, ref):
+        a, b = a.cpu().numpy(), b.cpu().numpy()
+        assert np.isfinite(a).all(), nm
+        np.testing.assert_allclose(a, b, rtol=1e-5, atol=1e-9, err_msg=nm)
+        if nm != "pose":
+            per_vertex = a.reshape(-1, sc.n_vertices)
+            assert (per_vertex[:, unseen_v] == 0).all(), nm
