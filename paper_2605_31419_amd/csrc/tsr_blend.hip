@@ -14,11 +14,6 @@ constexpr int kBatch = 64;                 // faces per hit mask (one lane each)
 constexpr int kSpan = 256;                 // faces staged at once by a cooperative workgroup
 constexpr int kWaves = kBlock / kWave;     // waves per workgroup: one per 8x8 quadrant
 
-// Wave reduction of the 20 per-face gradient sums: 1 = transposing permlane-swap butterfly,
-// 0 = one DPP reduction per value.
-#ifndef TSR_REDUCE_SWAP
-#define TSR_REDUCE_SWAP 1
-#endif
 // Tiles whose list is longer than this many faces raise their wave priority (0 = off).  The
 // longest tiles finish last; letting their waves win issue arbitration shortens the tail.
 #ifndef TSR_PRIO_LONG
@@ -352,18 +347,8 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
       }
       S = fmaf(alpha, P, om * S);
       if (__ballot(act) == 0) continue;
-#if TSR_REDUCE_SWAP
       const float tot = wave_sum20(acc);
       if (k_out >= 0) unsafeAtomicAdd(&grad_acc[(size_t)sf[j] * kGradDwords + k_out], (acc_t)tot);
-#else
-      float sum[kGradDwords];
-#pragma unroll
-      for (int k = 0; k < kGradDwords; ++k) sum[k] = wave_sum(acc[k]);
-      float mine = 0.f;
-#pragma unroll
-      for (int k = 0; k < kGradDwords; ++k) mine = lane == k ? sum[k] : mine;
-      if (lane < kGradDwords) unsafeAtomicAdd(&grad_acc[(size_t)sf[j] * kGradDwords + lane], (acc_t)mine);
-#endif
     }
     }
   }

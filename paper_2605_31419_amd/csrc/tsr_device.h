@@ -88,31 +88,37 @@ __device__ __forceinline__ float wave_sum(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_to_lane63(v)), 63));
 }
 
-// Sum of 16 lanes within each row, left in every lane of the row.
-__device__ __forceinline__ float row_sum16(float v) {
-  v += TSR_DPP(v, 0xB1, 0xF, 0xF);     // quad_perm [1,0,3,2]
-  v += TSR_DPP(v, 0x4E, 0xF, 0xF);     // quad_perm [2,3,0,1]
-  v += TSR_DPP(v, 0x124, 0xF, 0xF);    // row_ror:4
-  v += TSR_DPP(v, 0x128, 0xF, 0xF);    // row_ror:8
-  return v;
+// Wave totals of 20 per-lane values with a transposing butterfly: at each level a pair of
+// vectors (x, y) becomes one, the lanes on one side of the level's partner bit keeping x summed
+// with their partner lane and the others keeping y.
+//   v_permlane32_swap (partner l ^ 32): 20 -> 10 vectors;
+//   v_permlane16_swap (rows 0 <-> 1, 2 <-> 3): 10 -> 5; row r now holds value 4 j + {0, 2, 1, 3}[r]
+//     of vector j, summed over the four rows;
+//   inside each row, bit 3 (partner l ^ 8, row_ror:8): 5 -> 3 (the odd vector is summed over
+//     the pair); bit 2 (partner l ^ 7, row_half_mirror): 3 -> 2; bits 1 and 0 (quad_perm):
+//     both summed.
+// The partners span all 64 lanes, so every kept value is a wave total.  The paired vector's
+// totals (16 values) are read on lanes x = 0, 4, 8, 12 of each row, the odd vector's (the other
+// 4, the same on every lane of a row) on lane x = 1: the result is value wave_sum20_slot() on
+// the 20 lanes where that is not -1.  Every lane must be active.
+__device__ __forceinline__ int wave_sum20_slot() {
+  const int r = (threadIdx.x & 63) >> 4, x = threadIdx.x & 15;
+  const int rmap = r == 0 ? 0 : (r == 1 ? 2 : (r == 2 ? 1 : 3));
+  return (x & 3) == 0 ? 4 * (2 * ((x >> 2) & 1) + ((x >> 3) & 1)) + rmap : (x == 1 ? 16 + rmap : -1);
 }
 
-// Wave totals of 20 per-lane values with a transposing butterfly (gfx950 permlane swaps):
-//   v_permlane32_swap pairs values (2i, 2i+1): after swap + add, lanes 0-31 hold value 2i and
-//   lanes 32-63 value 2i+1, each summed over the two half-waves (10 vectors);
-//   v_permlane16_swap pairs those vectors again: each 16-lane row then holds one value summed
-//   over all four rows (5 vectors, 4 values each);
-//   a DPP reduction inside each row finishes the sums.
-// Lane 16 r + j (j < 5) returns the total of value index 4 j + {0, 2, 1, 3}[r] (the index
-// wave_sum20_slot() gives that lane); other lanes return a partial sum and their slot is -1.
-// Every lane must be active.
-__device__ __forceinline__ int wave_sum20_slot() {
-  const int lane = threadIdx.x & 63, r = lane >> 4, j = lane & 15;
-  const int rmap = (r == 0) ? 0 : (r == 1 ? 2 : (r == 2 ? 1 : 3));
-  return j < 5 ? 4 * j + rmap : -1;
+// The adds below are kept out of FMA contraction with any product that feeds them: an FMA
+// cannot take a DPP operand, a plain add folds the lane exchange into itself.
+template <int CTRL>
+__device__ __forceinline__ float pair_level(float x, float y, bool bit) {
+#pragma clang fp contract(off)
+  const float sx = x + TSR_DPP(x, CTRL, 0xF, 0xF);
+  const float sy = y + TSR_DPP(y, CTRL, 0xF, 0xF);
+  return bit ? sy : sx;
 }
 
 __device__ __forceinline__ float wave_sum20(const float* v) {
+#pragma clang fp contract(off)
   float s[10];
 #pragma unroll
   for (int i = 0; i < 10; ++i) {
@@ -125,14 +131,22 @@ __device__ __forceinline__ float wave_sum20(const float* v) {
   for (int j = 0; j < 5; ++j) {
     const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(s[2 * j]), __float_as_uint(s[2 * j + 1]), false,
                                                     false);
-    t[j] = row_sum16(__uint_as_float(p[0]) + __uint_as_float(p[1]));
+    t[j] = __uint_as_float(p[0]) + __uint_as_float(p[1]);
   }
-  const int j = threadIdx.x & 15;
-  float out = t[0];
-#pragma unroll
-  for (int k = 1; k < 5; ++k) out = j == k ? t[k] : out;
-  // keeps the sums in this (full-wave) part of the code, where the last DPP step fuses into
-  // its add, instead of letting them move into a caller's branch on the slot
+  const int x = threadIdx.x & 15;
+  const bool b2 = x & 4, b3 = x & 8;
+  const float a0 = pair_level<0x128>(t[0], t[1], b3);                  // row_ror:8
+  const float a1 = pair_level<0x128>(t[2], t[3], b3);
+  float a2 = t[4] + TSR_DPP(t[4], 0x128, 0xF, 0xF);
+  float bb = pair_level<0x141>(a0, a1, b2);                            // row_half_mirror
+  a2 += TSR_DPP(a2, 0x141, 0xF, 0xF);
+  bb += TSR_DPP(bb, 0x4E, 0xF, 0xF);                                   // quad_perm [2,3,0,1]
+  a2 += TSR_DPP(a2, 0x4E, 0xF, 0xF);
+  bb += TSR_DPP(bb, 0xB1, 0xF, 0xF);                                   // quad_perm [1,0,3,2]
+  a2 += TSR_DPP(a2, 0xB1, 0xF, 0xF);
+  float out = (x & 3) == 0 ? bb : a2;
+  // keeps the sums in this (full-wave) part of the code instead of letting them move into a
+  // caller's branch on the slot
   asm volatile("" : "+v"(out));
   return out;
 }
