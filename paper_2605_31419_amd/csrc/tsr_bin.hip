@@ -238,7 +238,7 @@ __device__ __forceinline__ void wave_expand(int cnt, F&& fn) {
 // pre-test on every lane rejects faces that are certainly culled; the remaining candidates
 // of the workgroup are compacted onto the first lanes, which run the exact FP64 setup (the
 // visibility decision, the pixel rectangle and, for visible faces, the record).
-__global__ __launch_bounds__(256) void k_project(tsr_scene_dev sc, const float* __restrict__ poses, ViewTable vt,
+__global__ __launch_bounds__(256, 6) void k_project(tsr_scene_dev sc, const float* __restrict__ poses, ViewTable vt,
                                                  float z_near, float r_min, uint32_t* __restrict__ counts,
                                                  float* __restrict__ records, uint32_t* __restrict__ tile_cnt,
                                                  uint32_t* __restrict__ vis_cnt, VisEntry* __restrict__ vis_list) {

@@ -124,14 +124,7 @@ def test_fullsize_train_step_sampled_faces(name):
         regions.append(reg)
         tcs.append(tc)
         tds.append(td)
-    rast, p = G.make(w.scene, w.intr, w.poses)
-    rast.bin_and_sort(p)
-    out = rast.train_l1(p, G.to_dev(np.concatenate([t.reshape(-1) for t in tcs])),
-                        G.to_dev(np.concatenate(tds)))
-    torch.cuda.synchronize()
-    gp, gc, go, gpose = [x.cpu().numpy().astype(np.float64) for x in out]
     N = w.scene.n_vertices
-    gp, gc = gp.reshape(3, N), gc.reshape(3, N)
     ref_p = np.zeros((3, N)); ref_c = np.zeros((3, N)); ref_o = np.zeros(N)
     for v in range(V):
         if seeds[v] is None:
@@ -140,20 +133,31 @@ def test_fullsize_train_step_sampled_faces(name):
                                    pixels=regions[v])
         ref_p += rp; ref_c += rc; ref_o += ro
     vid = (3 * faces[:, None] + np.arange(3)[None, :]).reshape(-1)
-    for nm, a, b in [("grad_pos", gp[:, vid], ref_p[:, vid]), ("grad_col", gc[:, vid], ref_c[:, vid]),
-                     ("grad_opa", go[vid], ref_o[vid])]:
-        ok, msg, bad = grad_close(a, b, name=nm)
-        _say(f"  {msg}")
-        assert ok, msg
-    # eq. 7 identity at full size: dL/drho = sum_i R dL/dv_W,i ; dL/dtheta = sum_i v_C,i x R dL/dv_W,i
-    # (single view: the vertex gradients are those of that view)
-    if V == 1:
-        R = w.poses[0][:9].astype(np.float64).reshape(3, 3)
-        t = w.poses[0][9:].astype(np.float64)
-        gC = R @ gp
-        vC = R @ w.scene.pos.astype(np.float64) + t[:, None]
-        rho = gC.sum(axis=1)
-        th = np.cross(vC.T, gC.T).sum(axis=0)
-        ref = np.concatenate([rho, th])
-        _say(f"  pose {gpose} identity {ref}")
-        assert np.linalg.norm(gpose - ref) <= 1e-3 * np.linalg.norm(ref) + 1e-9
+    rast, p = G.make(w.scene, w.intr, w.poses)
+    rast.bin_and_sort(p)
+    tc_dev = G.to_dev(np.concatenate([t.reshape(-1) for t in tcs]))
+    td_dev = G.to_dev(np.concatenate(tds))
+    # the default launch and the schedule families the benchmark's autotuner picks from
+    # (longest-first order; persistent workgroups over it or over the tile order)
+    for sched in [None, (0, 1, 0), (1, 1, 1024), (1, 0, 4096)]:
+        out = rast.train_l1(p, tc_dev, td_dev, schedule=sched)
+        torch.cuda.synchronize()
+        gp, gc, go, gpose = [x.cpu().numpy().astype(np.float64) for x in out]
+        gp, gc = gp.reshape(3, N), gc.reshape(3, N)
+        for nm, a, b in [("grad_pos", gp[:, vid], ref_p[:, vid]), ("grad_col", gc[:, vid], ref_c[:, vid]),
+                         ("grad_opa", go[vid], ref_o[vid])]:
+            ok, msg, bad = grad_close(a, b, name=f"{sched} {nm}")
+            _say(f"  {msg}")
+            assert ok, msg
+        # eq. 7 identity at full size: dL/drho = sum_i R dL/dv_W,i ; dL/dtheta = sum_i v_C,i x R dL/dv_W,i
+        # (single view: the vertex gradients are those of that view)
+        if V == 1:
+            R = w.poses[0][:9].astype(np.float64).reshape(3, 3)
+            t = w.poses[0][9:].astype(np.float64)
+            gC = R @ gp
+            vC = R @ w.scene.pos.astype(np.float64) + t[:, None]
+            rho = gC.sum(axis=1)
+            th = np.cross(vC.T, gC.T).sum(axis=0)
+            ref = np.concatenate([rho, th])
+            _say(f"  {sched} pose {gpose} identity {ref}")
+            assert np.linalg.norm(gpose - ref) <= 1e-3 * np.linalg.norm(ref) + 1e-9
