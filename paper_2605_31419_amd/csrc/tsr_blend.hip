@@ -182,7 +182,7 @@ __device__ __forceinline__ unsigned long long batch_hit_mask(const float4* srec,
       }
     }
   }
-  return __ballot(hit);
+  return ballot(hit);
 }
 
 struct FwdState {
@@ -213,11 +213,12 @@ __device__ __forceinline__ void forward_walk(const TileCtx& c, const float* __re
       stage_batch_block(records, pairs, s0, ns, srec, sface);
       __syncthreads();
     } else {
-      if (__ballot(live(s.T, t_min)) == 0) break;
+      if (ballot(live(s.T, t_min)) == 0) break;
       stage_batch(records, pairs, s0, ns, srec, sface);
     }
     for (int h = 0; h < ns; h += kBatch) {
-    if (__ballot(live(s.T, t_min)) == 0) break;
+    bool lv = live(s.T, t_min);         // this lane still blends (carried across the visits)
+    if (ballot(lv) == 0) break;
     const int n = min(kBatch, ns - h);
     const uint32_t b0 = s0 + (uint32_t)h;
     const float4* sr = srec + h * 6;
@@ -231,7 +232,7 @@ __device__ __forceinline__ void forward_walk(const TileCtx& c, const float* __re
       const float dx = dxb - rc.f[kRecU0];
       const float dy = dyb - rc.f[kRecV0];
       // stopping also at T == 0 means the backward never divides by 1 - alpha = 0
-      const bool act = eval_face<SM>(rc, dx, dy, sigma, e) && live(s.T, t_min);
+      const bool act = eval_face<SM>(rc, dx, dy, sigma, e) && lv;
       // lanes that do not blend this face keep their state: alpha 0 gives weight 0 and T * 1
       const float a = act ? e.alpha : 0.f;
       const float w = a * s.T;
@@ -242,7 +243,8 @@ __device__ __forceinline__ void forward_walk(const TileCtx& c, const float* __re
       s.Tb = act ? s.T : s.Tb;
       s.last = act ? (int)(b0 + j) : s.last;
       s.T = s.T * (1.f - a);
-      if (__ballot(live(s.T, t_min)) == 0) break;
+      lv = live(s.T, t_min);
+      if (ballot(lv) == 0) break;
     }
     }
   }
@@ -346,7 +348,7 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
         acc[kGEdge + 3 * k + 2] = gk[k];
       }
       S = fmaf(alpha, P, om * S);
-      if (__ballot(act) == 0) continue;
+      if (ballot(act) == 0) continue;
       const float tot = wave_sum20(acc);
       if (k_out >= 0) unsafeAtomicAdd(&grad_acc[(size_t)sf[j] * kGradDwords + k_out], (acc_t)tot);
     }

@@ -158,7 +158,8 @@ __device__ __forceinline__ int wave_max_int(int v) {
 
 __device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-__device__ __forceinline__ unsigned long long ballot(bool p) { return __ballot(p); }
+// Wave ballot of a predicate, taken as a lane mask directly (no conversion to an integer first).
+__device__ __forceinline__ unsigned long long ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 // Inclusive prefix sum over the 64 lanes of a wave.
 __device__ __forceinline__ unsigned long long wave_incl_scan_u64(unsigned long long v) {
