@@ -347,9 +347,10 @@ __global__ __launch_bounds__(256, 6) void k_project(tsr_scene_dev sc, const floa
 // visible-face counts of the projection workgroups (offsets of their segments in the dense
 // visible list); (1) exclusive scan of the tile counts into ranges, pair total K, overflow check against the capacity (all
 // ranges empty on overflow), the small-face counts left in tile_cnt2 as the base of the
-// larger faces' emission cursors, and the list of tiles too long for the one-wave sort.  Both scans run in rounds of 8192 entries, each thread
-// taking 8 consecutive ones.
-constexpr int kScanPer = 8;
+// larger faces' emission cursors, and the list of tiles too long for the one-wave sort.  Both
+// scans run in rounds of kScanRound entries, each thread taking kScanPer consecutive ones (12:
+// the most the 128 registers of a 1024-thread workgroup hold without spilling).
+constexpr int kScanPer = 12;
 constexpr int kScanRound = 1024 * kScanPer;
 
 __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* __restrict__ tile_cnt, uint32_t* __restrict__ ranges,
@@ -389,26 +390,26 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* __restrict__ tile
   }
 
   // workgroup 1: tile ranges.  The counters of a round are loaded coalesced (entry
-  // base + 1024 k + tid) and handed to their owners (8 consecutive entries each) through LDS;
+  // base + 1024 k + tid) and handed to their owners (kScanPer consecutive entries each) through LDS;
   // the next round's loads are issued before the current round is scanned.
   __shared__ uint2 s_cnt[kScanRound];
-  const uint4* cnt4 = reinterpret_cast<const uint4*>(tile_cnt);
   unsigned long long carry_long = 0;
   uint32_t cs[kScanPer], cb[kScanPer];
-  uint4 ld[kScanPer];
+  uint2 ld[kScanPer];                  // (small-face count, larger-face count) of an entry
 #pragma unroll
   for (int k = 0; k < kScanPer; ++k) {
     const int i = 1024 * k + tid;
-    ld[k] = i < n_tiles ? cnt4[i] : make_uint4(0u, 0u, 0u, 0u);
+    ld[k] = i < n_tiles ? make_uint2(tile_cnt[kTileCntStride * i], tile_cnt[kTileCntStride * i + 2]) : make_uint2(0u, 0u);
   }
   for (int base = 0; base < n_tiles; base += kScanRound) {
     const int i0 = base + tid * kScanPer;
 #pragma unroll
-    for (int k = 0; k < kScanPer; ++k) s_cnt[1024 * k + tid] = make_uint2(ld[k].x, ld[k].z);
+    for (int k = 0; k < kScanPer; ++k) s_cnt[1024 * k + tid] = ld[k];
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
       const int i = base + kScanRound + 1024 * k + tid;
-      ld[k] = i < n_tiles ? cnt4[i] : make_uint4(0u, 0u, 0u, 0u);
+      ld[k] = i < n_tiles ? make_uint2(tile_cnt[kTileCntStride * i], tile_cnt[kTileCntStride * i + 2])
+                          : make_uint2(0u, 0u);
     }
     __syncthreads();
 #pragma unroll
