@@ -359,40 +359,56 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* __restrict__ tile
                                                      uint32_t* __restrict__ vis_off, uint32_t* __restrict__ vis_total,
                                                      int n_segments, uint32_t* __restrict__ long_cnt,
                                                      uint32_t* __restrict__ long_list) {
+  // Loads and stores of a round are coalesced (entry base + 1024 k + tid); the entries reach
+  // their owners (kScanPer consecutive ones each) and the results come back through s_x.  The
+  // next round's loads are issued before the current round is scanned.
   __shared__ unsigned long long wsum[16];
+  __shared__ uint2 s_x[kScanRound];
   const int tid = threadIdx.x;
   unsigned long long carry = 0, tot;
   if (blockIdx.x == 0) {
-    // workgroup 0: offsets of the visible segments (the next round's loads are issued before
-    // the current round is scanned)
-    uint32_t c[kScanPer], cn[kScanPer];
+    // workgroup 0: offsets of the visible segments
+    uint32_t ld[kScanPer], c[kScanPer];
 #pragma unroll
-    for (int k = 0; k < kScanPer; ++k) c[k] = (tid * kScanPer + k < n_segments) ? vis_cnt[tid * kScanPer + k] : 0u;
+    for (int k = 0; k < kScanPer; ++k) {
+      const int i = 1024 * k + tid;
+      ld[k] = i < n_segments ? vis_cnt[i] : 0u;
+    }
     for (int base = 0; base < n_segments; base += kScanRound) {
-      const int i0 = base + tid * kScanPer;
 #pragma unroll
-      for (int k = 0; k < kScanPer; ++k) cn[k] = (i0 + kScanRound + k < n_segments) ? vis_cnt[i0 + kScanRound + k] : 0u;
-      unsigned long long sum = 0;
-#pragma unroll
-      for (int k = 0; k < kScanPer; ++k) sum += c[k];
-      unsigned long long run = carry + block_excl_scan_u64(sum, wsum, &tot);
+      for (int k = 0; k < kScanPer; ++k) s_x[1024 * k + tid].x = ld[k];
 #pragma unroll
       for (int k = 0; k < kScanPer; ++k) {
-        if (i0 + k < n_segments) vis_off[i0 + k] = (uint32_t)run;
+        const int i = base + kScanRound + 1024 * k + tid;
+        ld[k] = i < n_segments ? vis_cnt[i] : 0u;
+      }
+      __syncthreads();
+      unsigned long long sum = 0;
+#pragma unroll
+      for (int k = 0; k < kScanPer; ++k) {
+        c[k] = s_x[tid * kScanPer + k].x;
+        sum += c[k];
+      }
+      unsigned long long run = carry + block_excl_scan_u64(sum, wsum, &tot);   // (orders the reads above)
+#pragma unroll
+      for (int k = 0; k < kScanPer; ++k) {
+        s_x[tid * kScanPer + k].x = (uint32_t)run;
         run += c[k];
       }
-      carry += tot;
+      __syncthreads();
 #pragma unroll
-      for (int k = 0; k < kScanPer; ++k) c[k] = cn[k];
+      for (int k = 0; k < kScanPer; ++k) {
+        const int i = base + 1024 * k + tid;
+        if (i < n_segments) vis_off[i] = s_x[1024 * k + tid].x;
+      }
+      carry += tot;
+      __syncthreads();                 // s_x is refilled by the next round
     }
     if (tid == 0) *vis_total = (uint32_t)carry;
     return;
   }
 
-  // workgroup 1: tile ranges.  The counters of a round are loaded coalesced (entry
-  // base + 1024 k + tid) and handed to their owners (kScanPer consecutive entries each) through LDS;
-  // the next round's loads are issued before the current round is scanned.
-  __shared__ uint2 s_cnt[kScanRound];
+  // workgroup 1: tile ranges
   unsigned long long carry_long = 0;
   uint32_t cs[kScanPer], cb[kScanPer];
   uint2 ld[kScanPer];                  // (small-face count, larger-face count) of an entry
@@ -401,10 +417,11 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* __restrict__ tile
     const int i = 1024 * k + tid;
     ld[k] = i < n_tiles ? make_uint2(tile_cnt[kTileCntStride * i], tile_cnt[kTileCntStride * i + 2]) : make_uint2(0u, 0u);
   }
+  uint2* ranges2 = reinterpret_cast<uint2*>(ranges);
   for (int base = 0; base < n_tiles; base += kScanRound) {
     const int i0 = base + tid * kScanPer;
 #pragma unroll
-    for (int k = 0; k < kScanPer; ++k) s_cnt[1024 * k + tid] = ld[k];
+    for (int k = 0; k < kScanPer; ++k) s_x[1024 * k + tid] = ld[k];
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
       const int i = base + kScanRound + 1024 * k + tid;
@@ -414,12 +431,11 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* __restrict__ tile
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
-      const uint2 c = s_cnt[tid * kScanPer + k];
+      const uint2 c = s_x[tid * kScanPer + k];
       cs[k] = c.x;
       cb[k] = c.y;
     }
-    // (the barriers inside the block scans below order these reads before the next round's
-    // LDS stores)
+    // (the barriers inside the block scans below order these reads before the stores into s_x)
     unsigned long long sum = 0, nlong = 0;
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
@@ -431,27 +447,40 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* __restrict__ tile
     unsigned long long lpos = carry_long + block_excl_scan_u64(nlong, wsum, &tot_long);
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
-      if (i0 + k < n_tiles) {
-        const unsigned long long c = (unsigned long long)cs[k] + cb[k];
-        ranges[2 * (i0 + k)] = (uint32_t)run;
-        ranges[2 * (i0 + k) + 1] = (uint32_t)(run + c);
-        tile_cnt[kTileCntStride * (i0 + k) + 2] = cs[k];   // larger faces go after the recorded slots
-        if (c > (unsigned long long)kWaveSortMax) long_list[lpos++] = (uint32_t)(i0 + k);
-        run += c;
+      const unsigned long long c = (unsigned long long)cs[k] + cb[k];
+      // start of the tile's range, and the base of its larger faces' cursor (after the
+      // recorded slots)
+      s_x[tid * kScanPer + k] = make_uint2((uint32_t)run, cs[k]);
+      if (i0 + k < n_tiles && c > (unsigned long long)kWaveSortMax) long_list[lpos++] = (uint32_t)(i0 + k);
+      run += c;
+    }
+    __syncthreads();
+    // a range ends where the next tile's starts; the round's last one at the round's total
+    const uint32_t round_end = (uint32_t)(carry + tot);
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+      const int j = 1024 * k + tid, i = base + j;
+      if (i < n_tiles) {
+        const uint2 x = s_x[j];
+        const uint32_t end = (j + 1 < kScanRound && i + 1 < n_tiles) ? s_x[j + 1].x : round_end;
+        ranges2[i] = make_uint2(x.x, end);
+        tile_cnt[kTileCntStride * i + 2] = x.y;
       }
     }
     carry += tot;
     carry_long += tot_long;
+    __syncthreads();                   // s_x is refilled by the next round
   }
   if (tid == 0) *long_cnt = (uint32_t)carry_long;
   const bool over = carry > (unsigned long long)capacity;
   if (over) {
-    // same thread-to-entry mapping as above, so these stores land after the ones they replace
+    // same thread-to-entry mapping as the stores above, so these land after the ones they replace
     for (int base = 0; base < n_tiles; base += kScanRound) {
-      const int i0 = base + tid * kScanPer;
 #pragma unroll
-      for (int k = 0; k < kScanPer; ++k)
-        if (i0 + k < n_tiles) ranges[2 * (i0 + k)] = ranges[2 * (i0 + k) + 1] = 0u;
+      for (int k = 0; k < kScanPer; ++k) {
+        const int i = base + 1024 * k + tid;
+        if (i < n_tiles) ranges2[i] = make_uint2(0u, 0u);
+      }
     }
   }
   if (tid == 0) {
