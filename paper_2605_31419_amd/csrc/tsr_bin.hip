@@ -408,8 +408,8 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* __restrict__ tile
     return;
   }
 
-  // workgroup 1: tile ranges
-  unsigned long long carry_long = 0;
+  // workgroup 1: tile ranges; tiles longer than the one-wave sort takes are appended to the
+  // long list (few; their order does not matter)
   uint32_t cs[kScanPer], cb[kScanPer];
   uint2 ld[kScanPer];                  // (small-face count, larger-face count) of an entry
 #pragma unroll
@@ -436,22 +436,17 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* __restrict__ tile
       cb[k] = c.y;
     }
     // (the barriers inside the block scans below order these reads before the stores into s_x)
-    unsigned long long sum = 0, nlong = 0;
+    unsigned long long sum = 0;
 #pragma unroll
-    for (int k = 0; k < kScanPer; ++k) {
-      sum += (unsigned long long)cs[k] + cb[k];
-      nlong += (unsigned long long)cs[k] + cb[k] > (unsigned long long)kWaveSortMax;
-    }
+    for (int k = 0; k < kScanPer; ++k) sum += (unsigned long long)cs[k] + cb[k];
     unsigned long long run = carry + block_excl_scan_u64(sum, wsum, &tot);
-    unsigned long long tot_long;
-    unsigned long long lpos = carry_long + block_excl_scan_u64(nlong, wsum, &tot_long);
 #pragma unroll
     for (int k = 0; k < kScanPer; ++k) {
       const unsigned long long c = (unsigned long long)cs[k] + cb[k];
       // start of the tile's range, and the base of its larger faces' cursor (after the
       // recorded slots)
       s_x[tid * kScanPer + k] = make_uint2((uint32_t)run, cs[k]);
-      if (i0 + k < n_tiles && c > (unsigned long long)kWaveSortMax) long_list[lpos++] = (uint32_t)(i0 + k);
+      if (i0 + k < n_tiles && c > (unsigned long long)kWaveSortMax) long_list[atomicAdd(long_cnt, 1u)] = (uint32_t)(i0 + k);
       run += c;
     }
     __syncthreads();
@@ -468,10 +463,8 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* __restrict__ tile
       }
     }
     carry += tot;
-    carry_long += tot_long;
     __syncthreads();                   // s_x is refilled by the next round
   }
-  if (tid == 0) *long_cnt = (uint32_t)carry_long;
   const bool over = carry > (unsigned long long)capacity;
   if (over) {
     // same thread-to-entry mapping as the stores above, so these land after the ones they replace
