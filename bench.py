@@ -30,12 +30,14 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 FP32_VECTOR_PEAK_TF = 157.3    # MI355X FP32 vector, published (packed); 78.6 without packed FP32
-# FLOPs per (pixel, face) window evaluation, counted from the inner loops of the blend kernels:
-# forward 40 (3 edge functions 12, min 2, alpha 1, colour plane 12, blend 11, offsets 2);
-# backward 70 (re-evaluation 29, transmittance recovery 2, colour/depth moments 10,
-# dL/dalpha 12, opacity/window 4, edge moments 3, behind-accumulators 10).
+# FLOPs per (pixel, face) window evaluation (FMA = 2), counted from the inner loops of the
+# blend kernels:
+# forward 40 (offsets 2, 3 edge functions 12, min 2, alpha 1, colour planes 12, blend 11);
+# backward 81 (re-evaluation 30, transmittance recovery 3, colour/depth weights and their
+# x/y moments 11, dL/dalpha = T (P - S) 10, opacity/window 2, x/y moments of the edge that
+# attains the minimum 2, update of S 3, summing the 20 per-pixel terms over the tile 20).
 FLOP_FWD = 40
-FLOP_BWD = 70
+FLOP_BWD = 81
 
 
 def parse():
@@ -108,26 +110,37 @@ class Case:
         _lib.check(self.rast.lib.tsr_check(raster._ptr(self.rast.ws), raster._stream(), None), "tsr_check")
 
     def evaluations(self):
-        """Pixel-face window evaluations of one pass: sum over tiles of (pixels in the tile)
-        x (faces in its list), and the tile-list statistics, for the poses the step renders."""
+        """Pixel-face window evaluations E of one pass, each pixel counting the faces of its
+        tile's list up to its early stop (the whole list when it does not stop), plus the
+        tile-list statistics, for the poses the step renders."""
         self.rast.bin_and_sort(self.poses)
+        _, _, trans = self.rast.forward(self.poses)
         self.torch.cuda.synchronize()
         b = self.rast.binning()
         ws = self.rast.ws
         off = b.ranges - ws.data_ptr()
         rng = ws[off:off + 8 * b.n_tiles].cpu().numpy().view(np.uint32).reshape(-1, 2).astype(np.int64)
         lens = rng[:, 1] - rng[:, 0]
-        npx = []
+        loff = b.last_face - ws.data_ptr()
+        last = ws[loff:loff + 4 * b.n_pixels].cpu().numpy().view(np.int32).astype(np.int64)
+        T = trans.cpu().numpy()
+        t_min = self.rast.params.t_min
+        E = 0
+        tile0 = pix0 = 0
         for it in self.rast.intrs:
             tx, ty = (it.width + 15) // 16, (it.height + 15) // 16
-            wx = np.minimum(16, it.width - 16 * np.arange(tx))
-            wy = np.minimum(16, it.height - 16 * np.arange(ty))
-            npx.append((wy[:, None] * wx[None, :]).reshape(-1))
-        npx = np.concatenate(npx)
+            ys, xs = np.mgrid[0:it.height, 0:it.width]
+            t = (tile0 + (ys // 16) * tx + xs // 16).reshape(-1)
+            P = it.width * it.height
+            lp, Tp = last[pix0:pix0 + P], T[pix0:pix0 + P]
+            stopped = (Tp < t_min) | (Tp == 0.0)
+            E += int(np.where(stopped, lp - rng[t, 0] + 1, lens[t]).sum())
+            tile0 += tx * ty
+            pix0 += P
         kk = int(ws[b.n_pairs - ws.data_ptr():b.n_pairs - ws.data_ptr() + 8].cpu().numpy().view(np.int64)[0])
         cnt_off = b.tile_counts - ws.data_ptr()
         counts = ws[cnt_off:cnt_off + 4 * self.rast.n_views * self.rast.scene.n_faces].cpu().numpy().view(np.uint32)
-        return int((lens * npx).sum()), kk, int((counts > 0).sum()), int(lens.max()), float(lens.mean())
+        return E, kk, int((counts > 0).sum()), int(lens.max()), float(lens.mean())
 
 
 def time_steps(fn, steps, warmup):
@@ -259,14 +272,16 @@ def tracking_leg(raster, w, dev, iters=100, schedule=None):
 
 def serving_leg(raster, w, dev, n_queries, seed=4400):
     """Continuous-batching render serving of the resident map: saturated throughput, then
-    Poisson arrivals at 25 / 50 / 80 % of it; p50 / p99 latency per rate."""
+    Poisson arrivals at 25 / 50 / 80 % of it; p50 / p99 latency per rate.  The plain
+    single-view path (one query at a time, one view per launch) is run on the same saturated
+    query stream for comparison."""
     from paper_2605_31419_amd import scenes
     from paper_2605_31419_amd.serve import GpuExecutor, Request, Server, run_poisson
 
     ex = GpuExecutor(dev, pairs_per_tile=160.0)
 
-    def run(qps, n, warm):
-        srv = Server(ex, n_slots=4, mem_budget=8 << 30, max_batch_views=8)
+    def run(qps, n, warm, slots=4, views=8):
+        srv = Server(ex, n_slots=slots, mem_budget=8 << 30, max_batch_views=views)
         srv.start()
         try:
             qs = scenes.serving_queries(seed + int(qps) % 1000, n + warm, qps=qps)
@@ -276,7 +291,8 @@ def serving_leg(raster, w, dev, n_queries, seed=4400):
 
     run(1e7, 40, 0)                                      # warm-up: allocator, code objects
     sat = run(1e7, n_queries, 20)
-    out = {"saturated": sat, "rates": []}
+    plain = run(1e7, n_queries, 20, slots=1, views=1)
+    out = {"saturated": sat, "plain_single_view": plain, "rates": []}
     for frac in (0.25, 0.5, 0.8):
         st = run(frac * sat["qps"], n_queries, 20)
         st["offered_qps"] = frac * sat["qps"]

@@ -126,6 +126,8 @@ typedef struct {
     int64_t capacity;          /* pairs the workspace holds */
     int64_t n_tiles;           /* total tiles over all views */
     int64_t n_pixels;          /* total pixels over all views */
+    const int32_t *last_face;  /* [n_pixels] position in `pairs` of each pixel's last blended face
+                                  in the latest tsr_render_forward (-1: none), packed per view */
 } tsr_binning;
 
 /* Bytes of workspace needed for this scene size, view set and a capacity of `pair_capacity`

@@ -49,7 +49,7 @@ class TsrSchedule(C.Structure):
 class TsrBinning(C.Structure):
     _fields_ = [("pairs", C.c_void_p), ("ranges", C.c_void_p), ("n_pairs", C.c_void_p), ("overflow", C.c_void_p),
                 ("tile_counts", C.c_void_p), ("records", C.c_void_p), ("capacity", C.c_int64),
-                ("n_tiles", C.c_int64), ("n_pixels", C.c_int64)]
+                ("n_tiles", C.c_int64), ("n_pixels", C.c_int64), ("last_face", C.c_void_p)]
 
 
 class TsrError(RuntimeError):

@@ -279,6 +279,7 @@ int tsr_binning_view(const tsr_scene* scene, const tsr_intrinsics* intr, int n_v
   out->capacity = L.capacity;
   out->n_tiles = vt.n_tiles;
   out->n_pixels = total_pixels(vt);
+  out->last_face = reinterpret_cast<const int32_t*>(b + L.n_last);
   return TSR_OK;
 }
 

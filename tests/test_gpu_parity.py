@@ -428,3 +428,36 @@ def test_gradients_overwrite_their_outputs(name, fused):
         if nm != "pose":
             per_vertex = a.reshape(-1, sc.n_vertices)
             assert (per_vertex[:, unseen_v] == 0).all(), nm
+
+
+def test_last_face_positions_are_in_their_tiles():
+    """The binning view's per-pixel last blended face: -1 only where nothing was blended (final
+    transmittance 1, and every pixel with transmittance below 1 has one), otherwise a position
+    inside the pixel's tile range whose face covers the pixel (oracle: that face alone gives
+    the pixel a nonzero alpha)."""
+    sc, poses, intrs = _case("tiny_ragged_50x37")
+    rast, p = G.make(sc, intrs, poses)
+    rast.bin_and_sort(p)
+    _, _, trans = rast.forward(p)
+    torch.cuda.synchronize()
+    b = rast.binning()
+    ws = rast.ws
+    last = ws[b.last_face - ws.data_ptr():b.last_face - ws.data_ptr() + 4 * b.n_pixels].cpu().numpy().view(np.int32)
+    rng = ws[b.ranges - ws.data_ptr():b.ranges - ws.data_ptr() + 8 * b.n_tiles].cpu().numpy().view(np.uint32)
+    rng = rng.reshape(-1, 2).astype(np.int64)
+    pairs = ws[b.pairs - ws.data_ptr():b.pairs - ws.data_ptr() + 8 * b.capacity].cpu().numpy().view(np.uint64)
+    T = trans.cpu().numpy()
+    it = intrs[0]
+    tx = (it.width + 15) // 16
+    ys, xs = np.mgrid[0:it.height, 0:it.width]
+    t = ((ys // 16) * tx + xs // 16).reshape(-1)
+    none = last < 0
+    assert (T[none] == 1.0).all() and not none[T < 1.0].any()
+    assert ((last[~none] >= rng[t[~none], 0]) & (last[~none] < rng[t[~none], 1])).all()
+    faces = (pairs[last[~none]] & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    pix = np.nonzero(~none)[0]
+    for f, q in list(zip(faces, pix))[::7]:
+        one = plain_scene(sc.pos.T.reshape(-1, 3, 3)[f:f + 1], col=sc.col.T.reshape(-1, 3, 3)[f:f + 1],
+                          opa=sc.opa.reshape(-1, 3)[f:f + 1])
+        _, _, ot = O.render(one, poses[0], it, pixels=np.array([q], np.int64))
+        assert ot[0] < 1.0, (f, q)
