@@ -234,7 +234,8 @@ __device__ __forceinline__ void wave_expand(int cnt, F&& fn) {
 
 // ---------------------------------------------------------------------------- kernels
 
-// One thread per (view, face); faces are numbered g = v * M + m.  Two stages: the FP32
+// One thread per (view, face), numbered face-major (the views of a face in adjacent lanes);
+// per-(view, face) arrays are indexed by g = v * M + m.  Two stages: the FP32
 // pre-test on every lane rejects faces that are certainly culled; the remaining candidates
 // of the workgroup are compacted onto the first lanes, which run the exact FP64 setup (the
 // visibility decision, the pixel rectangle and, for visible faces, the record).
@@ -247,12 +248,17 @@ __global__ __launch_bounds__(256, 6) void k_project(tsr_scene_dev sc, const floa
   const int64_t M = vt.n_faces;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // threads are numbered face-major (idx = m V + v), so the views of one face are adjacent
+    // lanes sharing its vertex loads; per-(view, face) arrays stay indexed by g = v M + m
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool cand = false;
-    if (g < (int64_t)vt.n_views * M) {
-      const int v = (int)(g / M);
+    int64_t g = 0;
+    if (idx < (int64_t)vt.n_views * M) {
+      const int64_t m = idx / vt.n_views;
+      const int v = (int)(idx - m * vt.n_views);
+      g = (int64_t)v * M + m;
       int64_t vid[3];
-      face_vertices(sc, g - (int64_t)v * M, vid);
+      face_vertices(sc, m, vid);
       cand = !surely_culled(sc, vid, poses + 12 * v, vt.v[v], z_near);
       if (!cand) counts[g] = 0u;
     }
@@ -273,7 +279,7 @@ __global__ __launch_bounds__(256, 6) void k_project(tsr_scene_dev sc, const floa
   // Whole waves without a candidate leave now, so their slots go to other workgroups during
   // the FP64 stage; the barriers below then wait for the remaining waves only.
   if (wave >= nact) return;
-  // ---- exact setup of the candidates, one per lane (in g order)
+  // ---- exact setup of the candidates, one per lane (in thread order)
   int ntiles = 0, tx0 = 0, ty0 = 0, tw = 1, th = 1, tile_base = 0, tiles_x = 1;
   uint32_t zbits = 0u;
   int64_t g = 0;
@@ -303,7 +309,7 @@ __global__ __launch_bounds__(256, 6) void k_project(tsr_scene_dev sc, const floa
     counts[g] = (uint32_t)ntiles;
   }
   __syncthreads();                    // s_wave is reused below
-  // ---- visible (view, face) pairs of this workgroup, compacted (still in g order) into its
+  // ---- visible (view, face) pairs of this workgroup, compacted (still in thread order) into its
   //      own segment of the visible list: a wave ballot and per-wave counts in LDS, no atomics
   const bool vis = ntiles > 0;
   uint4* ent = nullptr;
@@ -315,8 +321,8 @@ __global__ __launch_bounds__(256, 6) void k_project(tsr_scene_dev sc, const floa
     for (int w = 0; w < wave; ++w) off += s_wave[w];
     ent = reinterpret_cast<uint4*>(vis_list + (int64_t)blockIdx.x * kProjBlock + off);
     if (vis)
-      ent[0] = make_uint4((uint32_t)g, (uint32_t)tx0 | ((uint32_t)ty0 << 16), (uint32_t)tw | ((uint32_t)th << 16),
-                          zbits);
+      ent[0] = make_uint4((uint32_t)g, (uint32_t)(tile_base + ty0 * tiles_x + tx0),
+                          (uint32_t)(tw - 1) | ((uint32_t)(th - 1) << 10) | ((uint32_t)(tiles_x - 1) << 20), zbits);
     if (threadIdx.x == 0) {
       uint32_t nvis = 0u;
       for (int w = 0; w < nact; ++w) nvis += s_wave[w];
@@ -485,11 +491,11 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* __restrict__ tile
 
 // Emission of (float32 z_F bits << 32 | face) into each overlapped tile's bucket.  One
 // workgroup per projection workgroup, one lane per visible face of its segment (compacted,
-// in g order), each reading its 32-byte visible-list entry.  Small faces store at their
+// in thread order), each reading its 32-byte visible-list entry.  Small faces store at their
 // recorded slot; larger faces take positions from the per-tile cursors, spread over the
 // wave.  A position outside its tile's range (never expected) is not written and is reported
 // through tsr_check.
-__global__ __launch_bounds__(256) void k_emit(ViewTable vt, const uint32_t* __restrict__ ranges,
+__global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ranges,
                                               uint32_t* __restrict__ cursor, uint32_t* __restrict__ overflow,
                                               uint64_t* __restrict__ pairs, const uint32_t* __restrict__ vis_cnt,
                                               const uint32_t* __restrict__ vis_off, const VisEntry* __restrict__ vis_list,
@@ -497,7 +503,7 @@ __global__ __launch_bounds__(256) void k_emit(ViewTable vt, const uint32_t* __re
   const uint32_t nvis = vis_cnt[blockIdx.x];
   const bool mine = threadIdx.x < nvis;
   const uint4* ent = reinterpret_cast<const uint4*>(vis_list + (int64_t)blockIdx.x * kProjBlock + threadIdx.x);
-  uint4 e0 = make_uint4(0u, 0u, 1u | (1u << 16), 0u);
+  uint4 e0 = make_uint4(0u, 0u, 0u, 0u);
   if (mine) {
     e0 = ent[0];
     // the segment goes to its place in the dense list (done even when the pairs overflowed:
@@ -505,16 +511,9 @@ __global__ __launch_bounds__(256) void k_emit(ViewTable vt, const uint32_t* __re
     vis_dense[vis_off[blockIdx.x] + threadIdx.x] = e0.x;
   }
   if (overflow[0]) return;
-  const int64_t M = vt.n_faces;
-  const int tx0 = (int)(e0.y & 0xFFFFu), ty0 = (int)(e0.y >> 16);
-  const int tw = (int)(e0.z & 0xFFFFu), th = (int)(e0.z >> 16);
+  const int tile0 = (int)e0.y;
+  const int tw = (int)(e0.z & 1023u) + 1, th = (int)((e0.z >> 10) & 1023u) + 1, tiles_x = (int)(e0.z >> 20) + 1;
   const int ntiles = mine ? tw * th : 0;
-  int tile_base = 0, tiles_x = 1;
-  if (mine) {
-    const ViewDesc& vd = vt.v[(int)((int64_t)e0.x / M)];
-    tile_base = vd.tile_off;
-    tiles_x = vd.tiles_x;
-  }
   const uint64_t key = ((uint64_t)e0.w << 32) | (uint64_t)e0.x;
   if (ntiles > 0 && ntiles <= kSmallTiles) {
     // slots recorded during counting: plain stores
@@ -524,7 +523,7 @@ __global__ __launch_bounds__(256) void k_emit(ViewTable vt, const uint32_t* __re
 #pragma unroll
     for (int i = 0; i < kSmallTiles; ++i)
       if (i < ntiles) {
-        const int t = tile_base + (ty0 + i / tw) * tiles_x + tx0 + i % tw;
+        const int t = tile0 + (i / tw) * tiles_x + i % tw;
         const uint32_t pos = ranges[2 * t] + slv[i];
         if (pos < ranges[2 * t + 1]) pairs[pos] = key;
         else bad = true;
@@ -535,11 +534,10 @@ __global__ __launch_bounds__(256) void k_emit(ViewTable vt, const uint32_t* __re
   if (wave_max_int(big) == 0) return;
   const uint32_t key_hi = (uint32_t)(key >> 32), key_lo = (uint32_t)key;
   wave_expand(big, [&](bool valid, int owner, int i) {
-    const int otx0 = __shfl(tx0, owner, 64), oty0 = __shfl(ty0, owner, 64), otw = __shfl(tw, owner, 64);
-    const int obase = __shfl(tile_base, owner, 64), otx = __shfl(tiles_x, owner, 64);
+    const int ot0 = __shfl(tile0, owner, 64), otw = __shfl(tw, owner, 64), otx = __shfl(tiles_x, owner, 64);
     const uint32_t khi = __shfl(key_hi, owner, 64), klo = __shfl(key_lo, owner, 64);
     if (valid) {
-      const int t = obase + (oty0 + i / otw) * otx + otx0 + i % otw;
+      const int t = ot0 + (i / otw) * otx + i % otw;
       const uint32_t pos = ranges[2 * t] + atomicAdd(&cursor[kTileCntStride * t + 2], 1u);
       if (pos < ranges[2 * t + 1]) pairs[pos] = ((uint64_t)khi << 32) | klo;
       else atomicOr(&overflow[2], 2u);
@@ -847,7 +845,7 @@ hipError_t launch_bin(const tsr_scene_dev& sc, const float* poses, const ViewTab
                      n_seg, long_cnt, long_list);
   if (!sort) return hipGetLastError();
   if (nf > 0)
-    TSR_LAUNCH("emit", k_emit, dim3(grid_for(nf, kProjBlock)), dim3(kProjBlock), 0, st, vt, ranges, tile_cnt,
+    TSR_LAUNCH("emit", k_emit, dim3(grid_for(nf, kProjBlock)), dim3(kProjBlock), 0, st, ranges, tile_cnt,
                overflow, pairs, vis_cnt, vis_off, vis_list, vis_dense);
   // small tile counts: the order is built beside the sorts (hidden behind them); larger ones by
   // the backward set-up, and only for schedules that use it

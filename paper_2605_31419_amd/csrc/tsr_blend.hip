@@ -528,8 +528,9 @@ __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float*
                                                   const float* __restrict__ records, acc_t* grad_acc,
                                                   double* __restrict__ pose_acc, int want_vertices,
                                                   const float* __restrict__ loss_part, double* __restrict__ loss_acc) {
-  __shared__ double red[6][4];
-  __shared__ int s_v[2];
+  __shared__ double s_pose[TSR_MAX_VIEWS * 6];    // this workgroup's pose sums, per view
+  for (int k = threadIdx.x; k < TSR_MAX_VIEWS * 6; k += blockDim.x) s_pose[k] = 0.0;
+  __syncthreads();
   if (loss_part) {
     // per-view loss: each thread adds one tile's four quadrant parts; waves whose tiles all
     // belong to one view (all but at most one wave per view boundary) add one FP64 atomic
@@ -717,29 +718,27 @@ __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float*
       stage[18] = (float)gop;
     }
   }
-  // ---- pose gradient of each view present in this workgroup (the dense list is ordered by
-  //      g, so usually one view): FP64 block reduction, one atomic per view and component
+  // ---- pose gradient: a wave whose faces all belong to one view (always, for one view) adds
+  //      its reduced sums, other waves each lane's, into the workgroup's per-view FP64 sums
   if (pose_acc) {
-    if (threadIdx.x == 0) s_v[0] = (int)((int64_t)vis_dense[i0] / M);
-    if (threadIdx.x == 0) s_v[1] = (int)((int64_t)vis_dense[min(i0 + (int64_t)blockDim.x, total) - 1] / M);
-    __syncthreads();
-    const int v_lo = min(s_v[0], vt.n_views - 1), v_hi = min(s_v[1], vt.n_views - 1);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int vv = v_lo; vv <= v_hi; ++vv) {
+    const int lane = threadIdx.x & 63;
+    const int v0 = __shfl(v, 0, 64);
+    if (__ballot(v == v0 || v < 0) == ~0ull) {
       for (int c = 0; c < 6; ++c) {
-        double x = v == vv ? pose6[c] : 0.0;
+        double x = v >= 0 ? pose6[c] : 0.0;
         for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-        if (lane == 0) red[c][wave] = x;
+        if (lane == 0 && v0 >= 0) atomicAdd(&s_pose[v0 * 6 + c], x);
       }
-      __syncthreads();
-      if (threadIdx.x < 6) {
-        const double t = red[threadIdx.x][0] + red[threadIdx.x][1] + red[threadIdx.x][2] + red[threadIdx.x][3];
-        if (t != 0.0)
-          unsafeAtomicAdd(&pose_acc[((int64_t)(blockIdx.x % kSumCopies) * vt.n_views + vv) * 6 + threadIdx.x], t);
-      }
-      __syncthreads();
+    } else if (v >= 0) {
+      for (int c = 0; c < 6; ++c) atomicAdd(&s_pose[v * 6 + c], pose6[c]);
     }
   }
+  }
+  // ---- one FP64 atomic per view and component into this workgroup's copy
+  if (pose_acc) {
+    __syncthreads();
+    for (int k = threadIdx.x; k < 6 * vt.n_views; k += blockDim.x)
+      if (s_pose[k] != 0.0) unsafeAtomicAdd(&pose_acc[(int64_t)(blockIdx.x % kSumCopies) * vt.n_views * 6 + k], s_pose[k]);
   }
 }
 

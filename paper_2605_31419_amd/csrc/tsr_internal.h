@@ -65,11 +65,13 @@ constexpr int kSmallTiles = 4;         // faces overlapping at most this many ti
 constexpr int kTileCntStride = 4;     // dwords per tile in the tile-counter array
 
 // What the emission of one visible (view, face) pair needs, written by the projection in the
-// order of its workgroup's faces: id g = v * M + m, first tile column and row, tile extent,
-// the float32 z_F bits of its sort key, and (faces over at most kSmallTiles tiles) its slot in
-// each tile, row-major over its tile rectangle.
+// order of its workgroup's threads: id g = v * M + m, the global id of the first tile of its
+// tile rectangle, the rectangle's extent and its view's tile row pitch, the float32 z_F bits of
+// its sort key, and (faces over at most kSmallTiles tiles) its slot in each tile, row-major
+// over the rectangle.
 struct VisEntry {
-  uint32_t g, t0, ext, zbits;   // t0 = tx0 | ty0 << 16, ext = tiles wide | tiles high << 16
+  uint32_t g, tile0, ext, zbits;   // ext = (tiles wide - 1) | (tiles high - 1) << 10 |
+                                   //       (view's tiles_x - 1) << 20 (each at most 1023)
   uint32_t slot[kSmallTiles];
 };
 
