@@ -195,6 +195,29 @@ TSR_API int tsr_render_train_l1(const tsr_scene *scene, const float *poses, cons
 TSR_API int tsr_pose_step(float *poses, const float *grad_pose, int n_views, float lr_trans, float lr_rot,
                   void *stream);
 
+/* D-SSIM term of the photometric energy (Sec. 3.5, eq. 8).  Per view v,
+ *   loss[v] = 1 - mean over its 3 channels and W H pixels of SSIM(p),
+ *   SSIM = (2 mu_x mu_y + C1)(2 s_xy + C2) / ((mu_x^2 + mu_y^2 + C1)(s_x^2 + s_y^2 + C2)),
+ * x the rendered colour, y the target, mu / s^2 / s_xy the local means, variances and
+ * covariance over an 11 x 11 Gaussian window (standard deviation 1.5, weights summing to 1;
+ * pixels outside the image count as 0, the window is not renormalised), C1 = 0.01^2,
+ * C2 = 0.03^2, s_x^2 = E[x^2] - mu_x^2.  The paper names the term without its parameters;
+ * these are the usual ones.
+ * color, target: device [sum_v 3 H_v W_v] packed like tsr_render_forward's colour output.
+ * loss: device [n_views] or NULL.  grad_color: device, packed like color, or NULL; receives
+ * weight * dloss[v]/dcolor (accumulate = 0) or has it added (accumulate != 0), so the L1
+ * colour gradient of eq. 8 and this term can share one buffer for tsr_render_backward.
+ * scratch: device, 256-byte aligned, at least tsr_dssim_scratch_size bytes (36 bytes per
+ * pixel plus 8 per 32 x 16 tile and channel), owned by the caller; its contents need no
+ * clearing.  Enqueued on `stream`; no allocation, no synchronisation (capturable).
+ * Errors: TSR_EINVAL for NULL inputs, both outputs NULL, or a view size outside
+ * (0, 16384]; TSR_EWORKSPACE for a short scratch. */
+TSR_API int tsr_dssim_scratch_size(const tsr_intrinsics *intr /* (host)[n_views] */, int n_views,
+                           size_t *bytes /* (host) out */);
+TSR_API int tsr_dssim(const tsr_intrinsics *intr /* (host)[n_views] */, int n_views, const float *color,
+              const float *target, float weight, int accumulate, float *loss, float *grad_color,
+              void *scratch, size_t scratch_bytes, void *stream);
+
 /* Synchronise `stream` and report device-side conditions of `ws`: TSR_ECAPACITY when the
  * last binning, or any binning since the previous tsr_check (e.g. inside a replayed graph),
  * overflowed; that condition is then cleared.  Writes the last K to *n_pairs when non-NULL.

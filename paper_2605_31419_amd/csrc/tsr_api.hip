@@ -344,6 +344,31 @@ int tsr_pose_step(float* poses, const float* grad_pose, int n_views, float lr_tr
   return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_pose_step launch");
 }
 
+int tsr_dssim_scratch_size(const tsr_intrinsics* intr, int n_views, size_t* bytes) {
+  if (!bytes) return fail(TSR_EINVAL, "bytes is NULL");
+  tsr::SsimTable t;
+  if (!intr || tsr::build_ssim_table(intr, n_views, &t) != 0)
+    return fail(TSR_EINVAL, "D-SSIM views: need 1 <= n_views <= %d and image sizes in (0, 16384]", TSR_MAX_VIEWS);
+  *bytes = tsr::ssim_scratch_bytes(t);
+  return TSR_OK;
+}
+
+int tsr_dssim(const tsr_intrinsics* intr, int n_views, const float* color, const float* target, float weight,
+              int accumulate, float* loss, float* grad_color, void* scratch, size_t scratch_bytes, void* stream) {
+  tsr::SsimTable t;
+  if (!intr || tsr::build_ssim_table(intr, n_views, &t) != 0)
+    return fail(TSR_EINVAL, "D-SSIM views: need 1 <= n_views <= %d and image sizes in (0, 16384]", TSR_MAX_VIEWS);
+  if (!color || !target) return fail(TSR_EINVAL, "color or target is NULL");
+  if (!loss && !grad_color) return fail(TSR_EINVAL, "loss and grad_color are both NULL");
+  if (!scratch) return fail(TSR_EINVAL, "scratch is NULL");
+  const size_t need = tsr::ssim_scratch_bytes(t);
+  if (scratch_bytes < need) return fail(TSR_EWORKSPACE, "D-SSIM scratch of %zu bytes is below the %zu needed", scratch_bytes, need);
+  if (reinterpret_cast<uintptr_t>(scratch) & 255) return fail(TSR_EINVAL, "scratch must be 256-byte aligned");
+  hipError_t e = tsr::launch_dssim(t, color, target, weight, accumulate != 0, loss, grad_color,
+                                   static_cast<char*>(scratch), static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_dssim launch");
+}
+
 int tsr_profile_enable(int on) {
   std::lock_guard<std::mutex> lk(tsr::g_prof_mu);
   tsr::g_prof_on = on != 0;

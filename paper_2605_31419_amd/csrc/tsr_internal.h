@@ -143,6 +143,29 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
                            float* grad_opa, float* grad_pose, bool fused_train, const TrainSchedule& sched,
                            hipStream_t st);
 
+// D-SSIM (Sec. 3.5, eq. 8): output tile of the stencil kernels and the window radius.
+constexpr int kSsimTW = 32;
+constexpr int kSsimTH = 16;
+constexpr int kSsimR = 5;               // 11 x 11 window
+
+// Per-view geometry of the D-SSIM kernels (a kernel argument).  Workgroup b works on view v
+// with blk_off[v] <= b < blk_off[v + 1]: channel-major, then row-major over the view's tiles.
+struct SsimTable {
+  int32_t width[TSR_MAX_VIEWS], height[TSR_MAX_VIEWS];
+  int32_t tiles_x[TSR_MAX_VIEWS], tiles_y[TSR_MAX_VIEWS];
+  int64_t pix_off[TSR_MAX_VIEWS];       // pixels of the views before v
+  int32_t blk_off[TSR_MAX_VIEWS + 1];
+  int32_t n_views;
+  int64_t n_pixels;
+  float g[2 * kSsimR + 1];              // normalised 1-D Gaussian factor of the window
+};
+
+// Returns 0, or -1 when a view size is outside (0, 16384] or n_views outside [1, TSR_MAX_VIEWS].
+int build_ssim_table(const tsr_intrinsics* intr, int n_views, SsimTable* t);
+size_t ssim_scratch_bytes(const SsimTable& t);
+hipError_t launch_dssim(const SsimTable& t, const float* color, const float* target, float weight,
+                        bool accumulate, float* loss, float* grad, char* scratch, hipStream_t st);
+
 hipError_t launch_pose_step(float* poses, const float* grad_pose, int n_views, float lr_t, float lr_r,
                             hipStream_t st);
 

@@ -1,0 +1,235 @@
+// D-SSIM term of the photometric energy (Sec. 3.5, eq. 8) on gfx950: per view, the loss
+// 1 - mean SSIM over its three channels and pixels, and its gradient with respect to the
+// rendered colour.  SSIM(p) = (2 mu_x mu_y + C1)(2 s_xy + C2) / ((mu_x^2 + mu_y^2 + C1)
+// (s_x^2 + s_y^2 + C2)) over an 11 x 11 Gaussian window (standard deviation 1.5, weights
+// summing to 1), pixels outside the image counting as 0, s^2 = E[x^2] - mu^2.
+//
+// Two stencil passes, each a 32 x 16 output tile per workgroup with its 5-pixel halo staged in
+// LDS and the window applied as two 11-tap passes (the Gaussian window is separable):
+//   k_ssim_stats: the five local moments -> SSIM(p) (summed per workgroup) and the three maps
+//     A = dS/dmu_x - 2 mu_x B - mu_y C, B = dS/ds_xx, C = dS/ds_xy;
+//   k_ssim_grad: dL/dx(p) = -(1/N) (W*A + 2 x(p) W*B + y(p) W*C)(p), W* the same window sum
+//     (the window is symmetric), N = 3 W H of the view;
+// then k_ssim_loss adds the workgroups' sums of each view.
+#include "tsr_device.h"
+#include "tsr_internal.h"
+
+#include <math.h>
+#include <string.h>
+
+namespace tsr {
+
+constexpr float kSsimC1 = 0.01f * 0.01f;
+constexpr float kSsimC2 = 0.03f * 0.03f;
+constexpr int kSsimIW = kSsimTW + 2 * kSsimR;   // staged columns
+constexpr int kSsimIH = kSsimTH + 2 * kSsimR;   // staged rows
+
+struct SsimTile {
+  int v, ch, x0, y0, W, H;
+  int64_t plane;          // offset of this channel plane in the packed colour arrays
+};
+
+__device__ __forceinline__ SsimTile ssim_tile(const SsimTable& t, int b) {
+  SsimTile s;
+  int v = 0;
+  for (int i = 1; i < t.n_views; ++i)
+    if (b >= t.blk_off[i]) v = i;
+  const int local = b - t.blk_off[v];
+  const int ntile = t.tiles_x[v] * t.tiles_y[v];
+  s.v = v;
+  s.ch = local / ntile;
+  const int tile = local - s.ch * ntile;
+  s.x0 = (tile % t.tiles_x[v]) * kSsimTW;
+  s.y0 = (tile / t.tiles_x[v]) * kSsimTH;
+  s.W = t.width[v];
+  s.H = t.height[v];
+  s.plane = 3 * t.pix_off[v] + (int64_t)s.ch * s.W * s.H;
+  return s;
+}
+
+// Stages the tile's window of Q images (zero outside the image), applies the horizontal
+// 11-tap pass into hs[q][row][col] (rows of the whole staged height, columns of the tile).
+template <int Q>
+__device__ __forceinline__ void ssim_stage_h(const SsimTile& s, const float* const* src, const float* g,
+                                             float (*in)[kSsimIH][kSsimIW], float (*hs)[kSsimIH][kSsimTW]) {
+  for (int i = threadIdx.x; i < kSsimIH * kSsimIW; i += blockDim.x) {
+    const int r = i / kSsimIW, c = i - r * kSsimIW;
+    const int gx = s.x0 - kSsimR + c, gy = s.y0 - kSsimR + r;
+    const bool in_img = gx >= 0 && gx < s.W && gy >= 0 && gy < s.H;
+    const int64_t e = s.plane + (int64_t)gy * s.W + gx;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) in[q][r][c] = in_img ? src[q][e] : 0.f;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kSsimIH * kSsimTW; i += blockDim.x) {
+    const int r = i / kSsimTW, c = i - r * kSsimTW;
+    float acc[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) acc[q] = 0.f;
+#pragma unroll
+    for (int k = 0; k < 2 * kSsimR + 1; ++k) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) acc[q] = fmaf(g[k], in[q][r][c + k], acc[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) hs[q][r][c] = acc[q];
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_ssim_stats(const float* __restrict__ color, const float* __restrict__ target,
+                                                    SsimTable t, float* __restrict__ abc, int64_t n3,
+                                                    double* __restrict__ partial) {
+  __shared__ float in[2][kSsimIH][kSsimIW];
+  __shared__ float hs[5][kSsimIH][kSsimTW];
+  __shared__ double red[4];
+  const SsimTile s = ssim_tile(t, blockIdx.x);
+  // stage x and y, then the horizontal pass of x, y, x^2, y^2, x y
+  for (int i = threadIdx.x; i < kSsimIH * kSsimIW; i += blockDim.x) {
+    const int r = i / kSsimIW, c = i - r * kSsimIW;
+    const int gx = s.x0 - kSsimR + c, gy = s.y0 - kSsimR + r;
+    const bool in_img = gx >= 0 && gx < s.W && gy >= 0 && gy < s.H;
+    const int64_t e = s.plane + (int64_t)gy * s.W + gx;
+    in[0][r][c] = in_img ? color[e] : 0.f;
+    in[1][r][c] = in_img ? target[e] : 0.f;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kSsimIH * kSsimTW; i += blockDim.x) {
+    const int r = i / kSsimTW, c = i - r * kSsimTW;
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f;
+#pragma unroll
+    for (int k = 0; k < 2 * kSsimR + 1; ++k) {
+      const float x = in[0][r][c + k], y = in[1][r][c + k], w = t.g[k];
+      a0 = fmaf(w, x, a0);
+      a1 = fmaf(w, y, a1);
+      a2 = fmaf(w, x * x, a2);
+      a3 = fmaf(w, y * y, a3);
+      a4 = fmaf(w, x * y, a4);
+    }
+    hs[0][r][c] = a0; hs[1][r][c] = a1; hs[2][r][c] = a2; hs[3][r][c] = a3; hs[4][r][c] = a4;
+  }
+  __syncthreads();
+  // vertical pass and the per-pixel SSIM terms
+  double sum = 0.0;
+  for (int i = threadIdx.x; i < kSsimTH * kSsimTW; i += blockDim.x) {
+    const int r = i / kSsimTW, c = i - r * kSsimTW;
+    const int gx = s.x0 + c, gy = s.y0 + r;
+    if (gx >= s.W || gy >= s.H) continue;
+    float m[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < 2 * kSsimR + 1; ++k) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) m[q] = fmaf(t.g[k], hs[q][r + k][c], m[q]);
+    }
+    const float mx = m[0], my = m[1];
+    const float sxx = m[2] - mx * mx, syy = m[3] - my * my, sxy = m[4] - mx * my;
+    const float n1 = 2.f * mx * my + kSsimC1, n2 = 2.f * sxy + kSsimC2;
+    const float d1 = mx * mx + my * my + kSsimC1, d2 = sxx + syy + kSsimC2;
+    const float inv = 1.f / (d1 * d2);
+    const float S = n1 * n2 * inv;
+    const float B = -S / d2;
+    const float C = 2.f * n1 * inv;
+    const float A = 2.f * my * n2 * inv - 2.f * mx * S / d1 - 2.f * mx * B - my * C;
+    const int64_t e = s.plane + (int64_t)gy * s.W + gx;
+    abc[e] = A;
+    abc[n3 + e] = B;
+    abc[2 * n3 + e] = C;
+    sum += (double)S;
+  }
+  // workgroup sum of SSIM -> partial[blockIdx.x]
+  for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void k_ssim_grad(const float* __restrict__ color, const float* __restrict__ target,
+                                                   SsimTable t, const float* __restrict__ abc, int64_t n3, float weight,
+                                                   int accumulate, float* __restrict__ grad) {
+  __shared__ float in[3][kSsimIH][kSsimIW];
+  __shared__ float hs[3][kSsimIH][kSsimTW];
+  const SsimTile s = ssim_tile(t, blockIdx.x);
+  const float* src[3] = {abc, abc + n3, abc + 2 * n3};
+  ssim_stage_h<3>(s, src, t.g, in, hs);
+  const float scale = -weight / (3.f * (float)s.W * (float)s.H);
+  for (int i = threadIdx.x; i < kSsimTH * kSsimTW; i += blockDim.x) {
+    const int r = i / kSsimTW, c = i - r * kSsimTW;
+    const int gx = s.x0 + c, gy = s.y0 + r;
+    if (gx >= s.W || gy >= s.H) continue;
+    float m[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < 2 * kSsimR + 1; ++k) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) m[q] = fmaf(t.g[k], hs[q][r + k][c], m[q]);
+    }
+    const int64_t e = s.plane + (int64_t)gy * s.W + gx;
+    const float g = scale * (m[0] + 2.f * color[e] * m[1] + target[e] * m[2]);
+    grad[e] = accumulate ? grad[e] + g : g;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ssim_loss(SsimTable t, const double* __restrict__ partial,
+                                                   float* __restrict__ loss) {
+  __shared__ double red[4];
+  const int v = blockIdx.x;
+  double sum = 0.0;
+  for (int b = t.blk_off[v] + threadIdx.x; b < t.blk_off[v + 1]; b += blockDim.x) sum += partial[b];
+  for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double n = 3.0 * (double)t.width[v] * (double)t.height[v];
+    loss[v] = (float)(1.0 - ((red[0] + red[1]) + (red[2] + red[3])) / n);
+  }
+}
+
+int build_ssim_table(const tsr_intrinsics* intr, int n_views, SsimTable* t) {
+  if (!intr || n_views < 1 || n_views > TSR_MAX_VIEWS) return -1;
+  memset(t, 0, sizeof *t);
+  int64_t blocks = 0, pix = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const int W = intr[v].width, H = intr[v].height;
+    if (W <= 0 || H <= 0 || W > 16384 || H > 16384) return -1;
+    t->width[v] = W;
+    t->height[v] = H;
+    t->tiles_x[v] = (W + kSsimTW - 1) / kSsimTW;
+    t->tiles_y[v] = (H + kSsimTH - 1) / kSsimTH;
+    t->pix_off[v] = pix;
+    t->blk_off[v] = (int32_t)blocks;
+    blocks += 3ll * t->tiles_x[v] * t->tiles_y[v];
+    pix += (int64_t)W * H;
+  }
+  t->blk_off[n_views] = (int32_t)blocks;
+  t->n_views = n_views;
+  t->n_pixels = pix;
+  // the 1-D factor of the Gaussian window, normalised in FP64
+  double g[2 * kSsimR + 1], sum = 0.0;
+  for (int k = 0; k < 2 * kSsimR + 1; ++k) {
+    const double d = k - kSsimR;
+    g[k] = exp(-d * d / (2.0 * 1.5 * 1.5));
+    sum += g[k];
+  }
+  for (int k = 0; k < 2 * kSsimR + 1; ++k) t->g[k] = (float)(g[k] / sum);
+  return 0;
+}
+
+size_t ssim_scratch_bytes(const SsimTable& t) {
+  const size_t maps = sizeof(float) * 9 * (size_t)t.n_pixels;            // A, B, C per channel value
+  return ((maps + 255) & ~(size_t)255) + sizeof(double) * (size_t)t.blk_off[t.n_views];
+}
+
+hipError_t launch_dssim(const SsimTable& t, const float* color, const float* target, float weight,
+                        bool accumulate, float* loss, float* grad, char* scratch, hipStream_t st) {
+  const int64_t n3 = 3 * t.n_pixels;
+  float* abc = reinterpret_cast<float*>(scratch);
+  const size_t maps = sizeof(float) * 9 * (size_t)t.n_pixels;
+  double* partial = reinterpret_cast<double*>(scratch + ((maps + 255) & ~(size_t)255));
+  const int blocks = t.blk_off[t.n_views];
+  TSR_LAUNCH("ssim_stats", k_ssim_stats, dim3(blocks), dim3(256), 0, st, color, target, t, abc, n3, partial);
+  if (grad) TSR_LAUNCH("ssim_grad", k_ssim_grad, dim3(blocks), dim3(256), 0, st, color, target, t, abc, n3, weight,
+                         accumulate ? 1 : 0, grad);
+  if (loss) TSR_LAUNCH("ssim_loss", k_ssim_loss, dim3(t.n_views), dim3(256), 0, st, t, partial, loss);
+  return hipGetLastError();
+}
+
+}  // namespace tsr

@@ -223,6 +223,42 @@ class Rasterizer:
         return torch.cat([t.reshape(-1) for t in per_view]).contiguous()
 
 
+class DSsim:
+    """D-SSIM term of eq. (8) on packed colour images (``tsr_dssim``): per-view loss
+    1 - mean SSIM and ``weight`` times its colour gradient, written or added into ``grad``."""
+
+    def __init__(self, intrs: Sequence, device: str = "cuda"):
+        self.lib = _lib.load()
+        self.intrs = list(intrs)
+        self.n_views = len(self.intrs)
+        self.device = device
+        self._cintr = intrinsics_array(self.intrs)
+        self.n_values = 3 * sum(int(it.width) * int(it.height) for it in self.intrs)
+        nb = C.c_size_t()
+        check(self.lib.tsr_dssim_scratch_size(self._cintr, self.n_views, C.byref(nb)), "tsr_dssim_scratch_size")
+        self.scratch = torch.empty(nb.value, dtype=torch.uint8, device=device)
+
+    def _want(self, name: str, t: torch.Tensor, n: int) -> None:
+        if t.dtype != torch.float32 or not t.is_contiguous() or t.numel() != n or t.device.type != "cuda":
+            raise ValueError(f"{name}: need a contiguous float32 device tensor of {n} values")
+
+    def __call__(self, color: torch.Tensor, target: torch.Tensor, weight: float = 1.0, loss=None, grad=None,
+                 want_grad: bool = True, accumulate: bool = False, stream=None):
+        self._want("color", color, self.n_values)
+        self._want("target", target, self.n_values)
+        loss = loss if loss is not None else torch.empty(self.n_views, device=self.device)
+        if want_grad and grad is None:
+            if accumulate:
+                raise ValueError("accumulate needs a grad buffer")
+            grad = torch.empty(self.n_values, device=self.device)
+        if grad is not None:
+            self._want("grad", grad, self.n_values)
+        check(self.lib.tsr_dssim(self._cintr, self.n_views, _ptr(color), _ptr(target), float(weight),
+                                 1 if accumulate else 0, _ptr(loss), _ptr(grad), _ptr(self.scratch),
+                                 C.c_size_t(self.scratch.numel()), _stream(stream)), "tsr_dssim")
+        return loss, grad
+
+
 # ---------------------------------------------------------------------------- autograd
 
 def _exp_se3_left(tau: torch.Tensor, poses: torch.Tensor) -> torch.Tensor:

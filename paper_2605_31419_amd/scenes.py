@@ -315,6 +315,28 @@ def random_targets(seed: int, intr: Intrinsics, z_range=(0.5, 4.0)) -> Tuple[np.
     return c, d
 
 
+def image_pair(seed: int, width: int, height: int, noise: float = 0.05) -> Tuple[np.ndarray, np.ndarray]:
+    """A (rendered, target) pair of colour images [3, H, W] in [0, 1], float32: the target is
+    a smooth texture (three random plane waves per channel) with pixel noise, the rendered
+    image that texture shifted by up to a pixel with its own noise -- the kind of pair the
+    photometric term compares while tracking and mapping."""
+    g = rng(seed)
+    y, x = np.mgrid[0:height, 0:width].astype(np.float64)
+    dx, dy = g.uniform(-1, 1, size=2)
+    out = [np.empty((3, height, width)) for _ in range(2)]
+    k = g.uniform(0.02, 0.3, size=(3, 3, 2)) * g.choice([-1, 1], size=(3, 3, 2))
+    amp = g.uniform(0.05, 0.2, size=(3, 3))
+    ph = g.uniform(0, 2 * np.pi, size=(3, 3))
+    base = g.uniform(0.3, 0.7, size=3)
+    for img, (sx, sy) in zip(out, ((0.0, 0.0), (dx, dy))):
+        for ch in range(3):
+            v = np.full((height, width), base[ch])
+            for w in range(3):
+                v += amp[ch, w] * np.sin(k[ch, w, 0] * (x + sx) + k[ch, w, 1] * (y + sy) + ph[ch, w])
+            img[ch] = v + g.normal(scale=noise, size=v.shape)
+    return np.clip(out[1], 0, 1).astype(np.float32), np.clip(out[0], 0, 1).astype(np.float32)
+
+
 def random_pixel_grads(seed: int, n_pix: int) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
     """Seeded upstream gradients (colour [3, P], depth [P], transmittance [P])."""
     g = rng(seed)
