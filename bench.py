@@ -194,6 +194,28 @@ def counter_traffic(kernel):
     return None, None
 
 
+# HBM bytes per colour value of the two D-SSIM kernels of the photometric step:
+#   ssim_stats reads C and Cbar (8) and writes the maps A, B, C (12);
+#   photo_seeds reads A, B, C (12), C and Cbar (8), writes dL/dC (4), and per pixel reads D and
+#   Dbar and writes dL/dD (12 per pixel = 4 per colour value).
+DSSIM_BYTES_PER_VALUE = 20 + 28
+# The term itself needs at least C and Cbar once and dL/dC once: 12 bytes per colour value.
+DSSIM_MIN_BYTES_PER_VALUE = 12
+
+
+def photometric_summary(pixels, ms, ktimes):
+    dk = ("ssim_stats", "photo_seeds")
+    d_ms = sum(ktimes.get(k, 0.0) for k in dk)
+    values = 3 * pixels
+    ach = DSSIM_BYTES_PER_VALUE * values / (d_ms * 1e-3) / 1e9
+    return {"ms_per_step": ms, "mpix_s": pixels / (ms * 1e-3) / 1e6, "w_ssim": 0.2,
+            "kernels_ms": {k: round(v, 4) for k, v in ktimes.items()},
+            "dssim_roofline": {"kernels": list(dk), "bound": "hbm", "ms": d_ms, "achieved": ach,
+                               "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                               "algorithmic_bytes": DSSIM_BYTES_PER_VALUE * values,
+                               "minimum_bytes_gbs": DSSIM_MIN_BYTES_PER_VALUE * values / (d_ms * 1e-3) / 1e9}}
+
+
 def configs_leg(raster, scenes, steps, warmup):
     """The fused step on the other configurations: 64x48 with 2k faces, 640x480 with a 200k room
     soup (tracking step), and the 8-view 1200x680 mapping window over a 500k room soup."""
@@ -380,6 +402,18 @@ def main():
     ms_unf = time_steps(lambda: single.step_unfused(gc, gd), args.steps, args.warmup)
     kt_unf, _ = kernel_times(lambda: single.step_unfused(gc, gd), args.profile_steps)
 
+    # full photometric step of eqs. 8 and 10: forward, L1 + D-SSIM + depth seeds, backward
+    def step_photo():
+        single.rast.bin_and_sort(single.poses, check_capacity=False)
+        single.rast.train_photometric(single.poses, single.tc, single.td, w_ssim=0.2, color=single.color,
+                                      depth=single.depth, trans=single.trans, loss=single.loss, out=single.grads)
+    ms_photo = time_steps(step_photo, args.steps, args.warmup)
+    single.check()
+    kt_photo, _ = kernel_times(step_photo, args.profile_steps)
+    photometric = photometric_summary(single.pixels, ms_photo, kt_photo)
+    log(f"[bench] photometric step (L1 + D-SSIM): {ms_photo:.3f} ms; D-SSIM kernels "
+        f"{photometric['dssim_roofline']['ms'] * 1e3:.1f} us")
+
     batched = None
     if not args.no_batched:
         g = scenes.rng(5500)
@@ -457,6 +491,7 @@ def main():
                               "traffic": bs_traffic,
                               "traffic_gbs": None if bs_traffic is None else bs_traffic / (bs_ms * 1e-3) / 1e9},
         "kernels_ms": {k: round(v, 4) for k, v in ktimes.items()},
+        "photometric": photometric,
         "unfused": {"ms_per_step": ms_unf, "mpix_s": single.pixels / (ms_unf * 1e-3) / 1e6,
                     "kernels_ms": {k: round(v, 4) for k, v in kt_unf.items()}},
         "batched": batched,

@@ -207,8 +207,8 @@ TSR_API int tsr_pose_step(float *poses, const float *grad_pose, int n_views, flo
  * loss: device [n_views] or NULL.  grad_color: device, packed like color, or NULL; receives
  * weight * dloss[v]/dcolor (accumulate = 0) or has it added (accumulate != 0), so the L1
  * colour gradient of eq. 8 and this term can share one buffer for tsr_render_backward.
- * scratch: device, 256-byte aligned, at least tsr_dssim_scratch_size bytes (36 bytes per
- * pixel plus 8 per 32 x 16 tile and channel), owned by the caller; its contents need no
+ * scratch: device, 256-byte aligned, at least tsr_dssim_scratch_size bytes (52 bytes per
+ * pixel plus 16 per 32 x 16 tile and channel), owned by the caller; its contents need no
  * clearing.  Enqueued on `stream`; no allocation, no synchronisation (capturable).
  * Errors: TSR_EINVAL for NULL inputs, both outputs NULL, or a view size outside
  * (0, 16384]; TSR_EWORKSPACE for a short scratch. */
@@ -217,6 +217,22 @@ TSR_API int tsr_dssim_scratch_size(const tsr_intrinsics *intr /* (host)[n_views]
 TSR_API int tsr_dssim(const tsr_intrinsics *intr /* (host)[n_views] */, int n_views, const float *color,
               const float *target, float weight, int accumulate, float *loss, float *grad_color,
               void *scratch, size_t scratch_bytes, void *stream);
+
+/* Full training step of the photometric and depth energies (eqs. 8 and 10) on binned views:
+ * forward render into color / depth / trans, then per view
+ *   loss[v] = w_color mean|C - Cbar| + w_ssim L_D-SSIM(C, Cbar) + w_depth mean([Dbar > 0] |D - Dbar|)
+ * (w_color = 1 - lambda and w_depth = lambda_dep from params, w_ssim = lambda = 0.2 in the
+ * paper; D-SSIM as in tsr_dssim), its per-pixel seeds, and their backward as in
+ * tsr_render_backward.  Unlike tsr_render_train_l1 the forward and backward are separate
+ * passes: the D-SSIM gradient at a pixel needs the rendered colour of its 11 x 11
+ * neighbourhood.  color and depth must not be NULL; trans and loss may be.  scratch as for
+ * tsr_dssim (the seeds live there).  Requires a preceding tsr_bin_and_sort. */
+TSR_API int tsr_render_train_photometric(const tsr_scene *scene, const float *poses, const tsr_intrinsics *intr,
+                                 int n_views, const tsr_params *params, void *ws, size_t ws_bytes,
+                                 const float *target_color, const float *target_depth, float w_ssim,
+                                 float *color, float *depth, float *trans, float *loss,
+                                 float *grad_pos, float *grad_col, float *grad_opa, float *grad_pose,
+                                 void *scratch, size_t scratch_bytes, void *stream);
 
 /* Synchronise `stream` and report device-side conditions of `ws`: TSR_ECAPACITY when the
  * last binning, or any binning since the previous tsr_check (e.g. inside a replayed graph),

@@ -369,6 +369,37 @@ int tsr_dssim(const tsr_intrinsics* intr, int n_views, const float* color, const
   return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_dssim launch");
 }
 
+int tsr_render_train_photometric(const tsr_scene* scene, const float* poses, const tsr_intrinsics* intr, int n_views,
+                                 const tsr_params* params, void* ws, size_t ws_bytes, const float* target_color,
+                                 const float* target_depth, float w_ssim, float* color, float* depth, float* trans,
+                                 float* loss, float* grad_pos, float* grad_col, float* grad_opa, float* grad_pose,
+                                 void* scratch, size_t scratch_bytes, void* stream) {
+  ViewTable vt;
+  WsLayout L;
+  int rc = prepare(scene, poses, intr, n_views, params, ws, ws_bytes, &vt, &L);
+  if (rc) return rc;
+  if (!target_color || !target_depth) return fail(TSR_EINVAL, "target_color or target_depth is NULL");
+  if (!color || !depth) return fail(TSR_EINVAL, "color or depth output is NULL (the D-SSIM term reads them)");
+  tsr::SsimTable t;
+  if (tsr::build_ssim_table(intr, n_views, &t) != 0) return fail(TSR_EINVAL, "bad D-SSIM view table");
+  if (!scratch) return fail(TSR_EINVAL, "scratch is NULL");
+  const size_t need = tsr::ssim_scratch_bytes(t);
+  if (scratch_bytes < need) return fail(TSR_EWORKSPACE, "D-SSIM scratch of %zu bytes is below the %zu needed", scratch_bytes, need);
+  if (reinterpret_cast<uintptr_t>(scratch) & 255) return fail(TSR_EINVAL, "scratch must be 256-byte aligned");
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(ws);
+  hipError_t e = tsr::launch_forward(vt, *params, L, w, color, depth, trans, st);
+  if (e != hipSuccess) return hip_fail(e, "tsr_render_train_photometric forward");
+  float *gc = nullptr, *gd = nullptr;
+  e = tsr::launch_photo_seeds(t, color, target_color, depth, target_depth, w_ssim, params->w_color, params->w_depth,
+                              loss, static_cast<char*>(scratch), &gc, &gd, st);
+  if (e != hipSuccess) return hip_fail(e, "tsr_render_train_photometric seeds");
+  tsr::TrainSchedule sched{0, 0, 0};
+  e = tsr::launch_backward(dev_scene(scene), poses, vt, *params, L, w, gc, gd, nullptr, nullptr, nullptr, nullptr,
+                           nullptr, nullptr, nullptr, grad_pos, grad_col, grad_opa, grad_pose, false, sched, st);
+  return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_render_train_photometric backward");
+}
+
 int tsr_profile_enable(int on) {
   std::lock_guard<std::mutex> lk(tsr::g_prof_mu);
   tsr::g_prof_on = on != 0;

@@ -165,6 +165,11 @@ int build_ssim_table(const tsr_intrinsics* intr, int n_views, SsimTable* t);
 size_t ssim_scratch_bytes(const SsimTable& t);
 hipError_t launch_dssim(const SsimTable& t, const float* color, const float* target, float weight,
                         bool accumulate, float* loss, float* grad, char* scratch, hipStream_t st);
+// D-SSIM statistics and the colour / depth seeds of the full photometric loss in `scratch`;
+// returns the seed pointers (inside scratch) through gcolor / gdepth.
+hipError_t launch_photo_seeds(const SsimTable& t, const float* color, const float* target, const float* depth,
+                              const float* tdepth, float w_ssim, float w_color, float w_depth, float* loss,
+                              char* scratch, float** gcolor, float** gdepth, hipStream_t st);
 
 hipError_t launch_pose_step(float* poses, const float* grad_pose, int n_views, float lr_t, float lr_r,
                             hipStream_t st);

@@ -168,18 +168,80 @@ __global__ __launch_bounds__(256) void k_ssim_grad(const float* __restrict__ col
   }
 }
 
-__global__ __launch_bounds__(256) void k_ssim_loss(SsimTable t, const double* __restrict__ partial,
-                                                   float* __restrict__ loss) {
+// Photometric seeds of the full training loss (eqs. 8 and 10), the D-SSIM gradient of
+// k_ssim_grad plus the L1 terms: dL/dC = w_ssim dL_D-SSIM/dC + w_color sgn(C - Cbar) / (3 W H),
+// dL/dD = w_depth [Dbar > 0] sgn(D - Dbar) / (W H) (channel-0 workgroups), and each workgroup's
+// share of the weighted L1 loss in l1_partial.
+__global__ __launch_bounds__(256) void k_photo_seeds(const float* __restrict__ color, const float* __restrict__ target,
+                                                     const float* __restrict__ depth, const float* __restrict__ tdepth,
+                                                     SsimTable t, const float* __restrict__ abc, int64_t n3,
+                                                     float w_ssim, float w_color, float w_depth,
+                                                     float* __restrict__ gcolor, float* __restrict__ gdepth,
+                                                     double* __restrict__ l1_partial) {
+  __shared__ float in[3][kSsimIH][kSsimIW];
+  __shared__ float hs[3][kSsimIH][kSsimTW];
   __shared__ double red[4];
-  const int v = blockIdx.x;
-  double sum = 0.0;
-  for (int b = t.blk_off[v] + threadIdx.x; b < t.blk_off[v + 1]; b += blockDim.x) sum += partial[b];
+  const SsimTile s = ssim_tile(t, blockIdx.x);
+  const float* src[3] = {abc, abc + n3, abc + 2 * n3};
+  ssim_stage_h<3>(s, src, t.g, in, hs);
+  const float npix = (float)s.W * (float)s.H;
+  const float k_ssim = -w_ssim / (3.f * npix), k_col = w_color / (3.f * npix), k_dep = w_depth / npix;
+  float l1 = 0.f;
+  for (int i = threadIdx.x; i < kSsimTH * kSsimTW; i += blockDim.x) {
+    const int r = i / kSsimTW, c = i - r * kSsimTW;
+    const int gx = s.x0 + c, gy = s.y0 + r;
+    if (gx >= s.W || gy >= s.H) continue;
+    float m[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 0; k < 2 * kSsimR + 1; ++k) {
+#pragma unroll
+      for (int q = 0; q < 3; ++q) m[q] = fmaf(t.g[k], hs[q][r + k][c], m[q]);
+    }
+    const int64_t e = s.plane + (int64_t)gy * s.W + gx;
+    const float x = color[e], dc = x - target[e];
+    const float sg = (float)((dc > 0.f) - (dc < 0.f));
+    gcolor[e] = k_ssim * (m[0] + 2.f * x * m[1] + target[e] * m[2]) + k_col * sg;
+    l1 += k_col * fabsf(dc);
+    if (s.ch == 0) {
+      const int64_t d = t.pix_off[s.v] + (int64_t)gy * s.W + gx;
+      const float db = tdepth[d], dd = depth[d] - db;
+      const bool valid = db > 0.f;
+      gdepth[d] = valid ? k_dep * (float)((dd > 0.f) - (dd < 0.f)) : 0.f;
+      if (valid) l1 += k_dep * fabsf(dd);
+    }
+  }
+  double sum = (double)l1;
   for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
   __syncthreads();
+  if (threadIdx.x == 0) l1_partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// loss[v] = w_ssim (1 - sum of SSIM / (3 W H)) + the view's L1 partials (when given).
+__global__ __launch_bounds__(256) void k_ssim_loss(SsimTable t, const double* __restrict__ partial,
+                                                   const double* __restrict__ l1_partial, float w_ssim,
+                                                   float* __restrict__ loss) {
+  __shared__ double red[2][4];
+  const int v = blockIdx.x;
+  double sum = 0.0, l1 = 0.0;
+  for (int b = t.blk_off[v] + threadIdx.x; b < t.blk_off[v + 1]; b += blockDim.x) {
+    sum += partial[b];
+    if (l1_partial) l1 += l1_partial[b];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    sum += __shfl_xor(sum, o, 64);
+    l1 += __shfl_xor(l1, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = sum;
+    red[1][threadIdx.x >> 6] = l1;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     const double n = 3.0 * (double)t.width[v] * (double)t.height[v];
-    loss[v] = (float)(1.0 - ((red[0] + red[1]) + (red[2] + red[3])) / n);
+    const double ssim = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    const double l1s = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+    loss[v] = (float)((double)w_ssim * (1.0 - ssim / n) + l1s);
   }
 }
 
@@ -213,22 +275,61 @@ int build_ssim_table(const tsr_intrinsics* intr, int n_views, SsimTable* t) {
   return 0;
 }
 
-size_t ssim_scratch_bytes(const SsimTable& t) {
-  const size_t maps = sizeof(float) * 9 * (size_t)t.n_pixels;            // A, B, C per channel value
-  return ((maps + 255) & ~(size_t)255) + sizeof(double) * (size_t)t.blk_off[t.n_views];
+// Scratch layout: A, B, C maps [3][3P] | colour seeds [3P] | depth seeds [P] | SSIM partials
+// [blocks] | L1 partials [blocks] (P = pixels of all views, each part 256-byte aligned).
+struct SsimScratch {
+  size_t abc, gcolor, gdepth, partial, l1_partial, total;
+};
+
+static SsimScratch ssim_scratch(const SsimTable& t) {
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  const size_t P = (size_t)t.n_pixels, nb = (size_t)t.blk_off[t.n_views];
+  SsimScratch z;
+  z.abc = 0;
+  z.gcolor = up(z.abc + sizeof(float) * 9 * P);
+  z.gdepth = up(z.gcolor + sizeof(float) * 3 * P);
+  z.partial = up(z.gdepth + sizeof(float) * P);
+  z.l1_partial = up(z.partial + sizeof(double) * nb);
+  z.total = up(z.l1_partial + sizeof(double) * nb);
+  return z;
 }
+
+size_t ssim_scratch_bytes(const SsimTable& t) { return ssim_scratch(t).total; }
 
 hipError_t launch_dssim(const SsimTable& t, const float* color, const float* target, float weight,
                         bool accumulate, float* loss, float* grad, char* scratch, hipStream_t st) {
+  const SsimScratch z = ssim_scratch(t);
   const int64_t n3 = 3 * t.n_pixels;
-  float* abc = reinterpret_cast<float*>(scratch);
-  const size_t maps = sizeof(float) * 9 * (size_t)t.n_pixels;
-  double* partial = reinterpret_cast<double*>(scratch + ((maps + 255) & ~(size_t)255));
+  float* abc = reinterpret_cast<float*>(scratch + z.abc);
+  double* partial = reinterpret_cast<double*>(scratch + z.partial);
   const int blocks = t.blk_off[t.n_views];
   TSR_LAUNCH("ssim_stats", k_ssim_stats, dim3(blocks), dim3(256), 0, st, color, target, t, abc, n3, partial);
-  if (grad) TSR_LAUNCH("ssim_grad", k_ssim_grad, dim3(blocks), dim3(256), 0, st, color, target, t, abc, n3, weight,
-                         accumulate ? 1 : 0, grad);
-  if (loss) TSR_LAUNCH("ssim_loss", k_ssim_loss, dim3(t.n_views), dim3(256), 0, st, t, partial, loss);
+  if (grad)
+    TSR_LAUNCH("ssim_grad", k_ssim_grad, dim3(blocks), dim3(256), 0, st, color, target, t, abc, n3, weight,
+               accumulate ? 1 : 0, grad);
+  if (loss)
+    TSR_LAUNCH("ssim_loss", k_ssim_loss, dim3(t.n_views), dim3(256), 0, st, t, partial, (const double*)nullptr, 1.f,
+               loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_photo_seeds(const SsimTable& t, const float* color, const float* target, const float* depth,
+                              const float* tdepth, float w_ssim, float w_color, float w_depth, float* loss,
+                              char* scratch, float** gcolor, float** gdepth, hipStream_t st) {
+  const SsimScratch z = ssim_scratch(t);
+  const int64_t n3 = 3 * t.n_pixels;
+  float* abc = reinterpret_cast<float*>(scratch + z.abc);
+  double* partial = reinterpret_cast<double*>(scratch + z.partial);
+  double* l1_partial = reinterpret_cast<double*>(scratch + z.l1_partial);
+  *gcolor = reinterpret_cast<float*>(scratch + z.gcolor);
+  *gdepth = reinterpret_cast<float*>(scratch + z.gdepth);
+  const int blocks = t.blk_off[t.n_views];
+  TSR_LAUNCH("ssim_stats", k_ssim_stats, dim3(blocks), dim3(256), 0, st, color, target, t, abc, n3, partial);
+  TSR_LAUNCH("photo_seeds", k_photo_seeds, dim3(blocks), dim3(256), 0, st, color, target, depth, tdepth, t, abc, n3,
+             w_ssim, w_color, w_depth, *gcolor, *gdepth, l1_partial);
+  if (loss)
+    TSR_LAUNCH("ssim_loss", k_ssim_loss, dim3(t.n_views), dim3(256), 0, st, t, partial, (const double*)l1_partial,
+               w_ssim, loss);
   return hipGetLastError();
 }
 

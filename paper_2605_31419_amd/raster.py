@@ -198,6 +198,30 @@ class Rasterizer:
                                            _ptr(gpose), sp, _stream(stream)), "tsr_render_train_l1")
         return gp, gc, go, gpose
 
+    def photometric_scratch(self) -> torch.Tensor:
+        """Scratch of the D-SSIM statistics and per-pixel seeds (allocated on first use)."""
+        if getattr(self, "_pscratch", None) is None:
+            nb = C.c_size_t()
+            check(self.lib.tsr_dssim_scratch_size(self._cintr, self.n_views, C.byref(nb)), "tsr_dssim_scratch_size")
+            self._pscratch = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        return self._pscratch
+
+    def train_photometric(self, poses: torch.Tensor, target_color, target_depth, w_ssim: float = 0.2,
+                          color=None, depth=None, trans=None, loss=None, out=None, stream=None):
+        """Forward, the full loss of eqs. 8 and 10 (L1 colour, D-SSIM, masked L1 depth) and its
+        backward (``tsr_render_train_photometric``)."""
+        P = self.total_pixels
+        color = color if color is not None else torch.empty(3 * P, device=self.device)
+        depth = depth if depth is not None else torch.empty(P, device=self.device)
+        gp, gc, go, gpose = out if out is not None else self.grad_buffers()
+        sc = self.photometric_scratch()
+        check(self.lib.tsr_render_train_photometric(*self._args(poses), _ptr(target_color), _ptr(target_depth),
+                                                    float(w_ssim), _ptr(color), _ptr(depth), _ptr(trans), _ptr(loss),
+                                                    _ptr(gp), _ptr(gc), _ptr(go), _ptr(gpose), _ptr(sc),
+                                                    C.c_size_t(sc.numel()), _stream(stream)),
+              "tsr_render_train_photometric")
+        return gp, gc, go, gpose
+
     def pose_step(self, poses: torch.Tensor, grad_pose: torch.Tensor, lr_trans: float, lr_rot: float,
                   stream=None) -> None:
         check(self.lib.tsr_pose_step(_ptr(poses), _ptr(grad_pose), self.n_views, lr_trans, lr_rot, _stream(stream)),

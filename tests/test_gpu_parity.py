@@ -367,6 +367,50 @@ def test_train_l1_matches_oracle(name):
         assert np.abs(cs[v] - oc).max() <= IMG_TOL
 
 
+# ---------------------------------------------------------------------------- full photometric step
+
+@pytest.mark.parametrize("name", ["single_64x48", "multi_view_mixed", "tiny_ragged_50x37", "long_tile_800"])
+def test_train_photometric_matches_oracle(name):
+    """Eqs. 8 and 10 with the D-SSIM term: the seeds are the oracle's L1 seeds plus 0.2 times
+    the FP64 D-SSIM gradient of the oracle render, pushed through the oracle backward."""
+    from oracle import dssim as D
+    _say(f"[train_photometric] case={name}")
+    w_ssim = 0.2
+    sc, poses, intrs = _case(name)
+    rast, p = G.make(sc, intrs, poses)
+    tcs, tds, lossref, gcs, gds, ocs = [], [], [], [], [], []
+    for v in range(len(poses)):
+        W, H = intrs[v].width, intrs[v].height
+        oc, od, ot = O.render(sc, poses[v], intrs[v])
+        tc, td, _ = _nudged_targets(oc, od, 300 + v, None)
+        L, gcv, gdv = O.l1_seeds(oc, od, tc, td, W * H)
+        c3, t3 = np.asarray(oc, np.float64).reshape(3, H, W), tc.astype(np.float64).reshape(3, H, W)
+        lossref.append(L + w_ssim * D.dssim(c3, t3))
+        gcs.append(gcv + w_ssim * D.dssim_grad(c3, t3).reshape(gcv.shape))
+        gds.append(gdv)
+        tcs.append(tc); tds.append(td); ocs.append(oc)
+    rast.bin_and_sort(p)
+    P = rast.total_pixels
+    loss = torch.zeros(len(poses), device="cuda")
+    color = torch.empty(3 * P, device="cuda")
+    depth = torch.empty(P, device="cuda")
+    out = rast.train_photometric(p, G.to_dev(np.concatenate([t.reshape(-1) for t in tcs])),
+                                 G.to_dev(np.concatenate([t.reshape(-1) for t in tds])), w_ssim=w_ssim,
+                                 color=color, depth=depth, loss=loss)
+    torch.cuda.synchronize()
+    got = [x.cpu().numpy().astype(np.float64) for x in out]
+    _say(f"  loss {loss.cpu().numpy()} ref {np.array(lossref)}")
+    np.testing.assert_allclose(loss.cpu().numpy(), lossref, rtol=1e-5, atol=2e-5)
+    ref = _oracle_backward_views(sc, poses, intrs, gcs, gds, None, 1.0)
+    for nm, a, b in zip(["grad_pos", "grad_col", "grad_opa", "grad_pose"], got, ref):
+        ok, msg, bad = grad_close(a, b, name=nm)
+        _say("  " + msg)
+        assert ok, msg
+    cs = G.per_view(rast, color.cpu().numpy(), 3)
+    for v in range(len(poses)):
+        assert np.abs(cs[v] - ocs[v]).max() <= IMG_TOL
+
+
 # ---------------------------------------------------------------------------- pose step
 
 def test_pose_step_matches_matrix_exponential():
