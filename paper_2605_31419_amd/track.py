@@ -6,6 +6,10 @@ rates (translation 0.001, rotation 0.003) and 100 iterations per frame.  The who
 captured once into a HIP graph (through torch.cuda.graph) and replayed: no host
 synchronisation happens inside it, every buffer is pre-sized, and the binning capacity is
 checked after the replay through the device-side overflow flag.
+
+With ``w_ssim > 0`` the loss is the full tracking energy of eqs. 8 and 10 (w_color L1 colour +
+w_ssim D-SSIM + w_depth masked L1 depth; the paper uses 0.8, 0.2 and 0.05): forward, seeds and
+backward then run as separate passes (``tsr_render_train_photometric``), still capturable.
 """
 from __future__ import annotations
 
@@ -19,7 +23,7 @@ from . import _lib, raster
 class Tracker:
     def __init__(self, scene: raster.DeviceScene, intr, params: Optional[raster.Params] = None,
                  lr_trans: float = 0.001, lr_rot: float = 0.003, iters: int = 100, capacity_slack: float = 2.0,
-                 schedule=None):
+                 schedule=None, w_ssim: float = 0.0):
         self.rast = raster.Rasterizer(scene, [intr], params or raster.Params())
         self.rast.schedule = schedule            # tile schedule of the fused kernel (autotuner's choice)
         self.lr_t, self.lr_r, self.iters = lr_trans, lr_rot, iters
@@ -31,6 +35,11 @@ class Tracker:
         self.loss_hist = torch.zeros(iters, device="cuda")
         self.target_color = torch.zeros(3 * P, device="cuda")
         self.target_depth = torch.zeros(P, device="cuda")
+        self.w_ssim = float(w_ssim)
+        if self.w_ssim > 0:
+            self.color = torch.empty(3 * P, device="cuda")
+            self.depth = torch.empty(P, device="cuda")
+            self.rast.photometric_scratch()      # allocated before any capture
         self.graph: Optional[torch.cuda.CUDAGraph] = None
 
     def set_frame(self, pose0: torch.Tensor, target_color: torch.Tensor, target_depth: torch.Tensor) -> None:
@@ -49,8 +58,13 @@ class Tracker:
     def _iteration(self, i: int) -> None:
         p = self.pose.view(1, 12)
         self.rast.bin_and_sort(p, check_capacity=False)
-        self.rast.train_l1(p, self.target_color, self.target_depth, loss=self.loss,
-                           out=(None, None, None, self.grad_pose))
+        if self.w_ssim > 0:
+            self.rast.train_photometric(p, self.target_color, self.target_depth, w_ssim=self.w_ssim,
+                                        color=self.color, depth=self.depth, loss=self.loss,
+                                        out=(None, None, None, self.grad_pose))
+        else:
+            self.rast.train_l1(p, self.target_color, self.target_depth, loss=self.loss,
+                               out=(None, None, None, self.grad_pose))
         self.rast.pose_step(p, self.grad_pose, self.lr_t, self.lr_r)
         self.loss_hist[i:i + 1].copy_(self.loss)
 

@@ -174,6 +174,64 @@ def test_tracking_graph_replay_matches_eager():
     assert lh[-1] < lh[0]
 
 
+def test_tracking_graph_with_dssim_matches_eager():
+    """The full tracking energy (L1 colour 0.8, D-SSIM 0.2, depth 0.05) captured in a graph:
+    replays equal the eager loop and the loss decreases."""
+    sc = _room(60_000, seed=39)
+    g = S.rng(40)
+    pose0 = S.random_room_pose(g)
+    truth = S.perturb_pose(pose0, g)
+    intr = S.intrinsics_for(320, 240)
+    dev = raster.DeviceScene.from_numpy(sc)
+    tr = raster.Rasterizer(dev, [intr])
+    tp = raster.poses_tensor([truth])
+    tr.fit(tp)
+    tr.bin_and_sort(tp)
+    tc, td, _ = tr.forward(tp)
+    trk = Tracker(dev, intr, iters=20, w_ssim=0.2)
+    p0 = torch.as_tensor(pose0, device="cuda")
+    trk.set_frame(p0, tc, td)
+    eager = trk.run_eager().clone()
+    loss_eager = trk.loss_hist.clone()
+    trk.set_frame(p0, tc, td)
+    trk.capture()
+    for rep in range(2):
+        trk.set_frame(p0, tc, td)
+        out = trk.replay().clone()
+        torch.cuda.synchronize()
+        trk.check()
+        np.testing.assert_allclose(out.cpu().numpy(), eager.cpu().numpy(), atol=1e-5)
+        np.testing.assert_allclose(trk.loss_hist.cpu().numpy(), loss_eager.cpu().numpy(), rtol=1e-4, atol=1e-8)
+    lh = loss_eager.cpu().numpy()
+    _say(f"  loss {lh[0]:.5f} -> {lh[-1]:.5f}")
+    assert lh[-1] < lh[0]
+
+
+def test_window_with_dssim_equals_sum_of_single_views():
+    sc, dev, poses, intrs, tc, td = _window_inputs(n_views=3, n_faces=40_000)
+    win = MappingWindow(dev, intrs, w_ssim=0.2)
+    p = raster.poses_tensor(poses)
+    win.prepare(p)
+    gp, gc, go, gpose = [x.clone() for x in win.step(p, tc, td, check_capacity=True)]
+    loss_b = win.loss.clone()
+    P = intrs[0].width * intrs[0].height
+    acc = [torch.zeros_like(gp), torch.zeros_like(gc), torch.zeros_like(go)]
+    for v in range(len(poses)):
+        r = raster.Rasterizer(dev, [intrs[v]])
+        pv = raster.poses_tensor([poses[v]])
+        r.fit(pv)
+        r.bin_and_sort(pv)
+        lv = torch.zeros(1, device="cuda")
+        a, b, c, d = r.train_photometric(pv, tc[3 * P * v:3 * P * (v + 1)], td[P * v:P * (v + 1)], loss=lv)
+        acc[0] += a; acc[1] += b; acc[2] += c
+        np.testing.assert_allclose(d.cpu().numpy(), gpose[6 * v:6 * (v + 1)].cpu().numpy(), rtol=1e-3, atol=1e-9)
+        np.testing.assert_allclose(lv.cpu().numpy(), loss_b[v:v + 1].cpu().numpy(), rtol=1e-5)
+    for nm, a, b in zip(["pos", "col", "opa"], [gp, gc, go], acc):
+        ok, msg, _ = grad_close(a.cpu().numpy(), b.cpu().numpy(), name=nm)
+        _say("  " + msg)
+        assert ok, msg
+
+
 # ---------------------------------------------------------------------------- serving
 
 def test_served_results_equal_alone_results():
