@@ -56,6 +56,7 @@ def lib():
         _lib.orc_set_threads.argtypes = [C.c_int]
         _lib.orc_max_threads.restype = C.c_int
         _lib.orc_state.argtypes = [P, P, P, P, P, C.c_int64, C.c_double, P]
+        _lib.orc_face_stats.argtypes = [P, P, P, P, C.c_double, P, P, P, P, P]
     return _lib
 
 
@@ -217,3 +218,17 @@ def state(scene, pose, intr, sigma=1.0, z_near=0.1, r_min=1e-3, pixels=None, rho
     if rc:
         raise ValueError(f"orc_state failed ({rc})")
     return out
+
+
+def face_stats(scene, pose, intr, t_min=1e-6, sigma=1.0, z_near=0.1, r_min=1e-3):
+    """Per-face projected area [M], coverage interval (cov_lo, cov_hi) [M] and visibility
+    (certain, possible) [M] of one view; see orc_face_stats for the definitions."""
+    a = _Args(scene, pose, intr, sigma, z_near, r_min)
+    M = int(a.sc.n_faces)
+    area = np.zeros(max(M, 1))
+    lo, hi, vc, vp = (np.zeros(max(M, 1), np.int32) for _ in range(4))
+    rc = lib().orc_face_stats(C.byref(a.sc), _ptr(a.pose), C.byref(a.cam), C.byref(a.par), float(t_min),
+                              _ptr(area), _ptr(lo), _ptr(hi), _ptr(vc), _ptr(vp))
+    if rc:
+        raise ValueError(f"orc_face_stats failed ({rc})")
+    return area[:M], lo[:M], hi[:M], vc[:M].astype(bool), vp[:M].astype(bool)

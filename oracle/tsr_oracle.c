@@ -616,3 +616,97 @@ int orc_state(const orc_scene *s, const double *pose, const orc_cam *c, const or
     free(F);
     return ORC_OK;
 }
+
+/* ------------------------------------------------------------------------- per-face screen statistics */
+/* Map-management statistics of one view (Sec. 3.4: pruning by projected area, densification by
+ * pixel coverage, keyframing by visibility), with the blending decisions of eq. 4 and the early
+ * stop (a pixel blends while T >= t_min and T > 0):
+ *   area[m]   projected area (half the absolute cross product of the projected edges) of faces
+ *             that pass the culls and overlap the image, else 0;
+ *   coverage  pixels at which the face has the largest weight alpha T (first in depth order on
+ *             ties), returned as an interval [cov_lo, cov_hi]: a pixel counts in cov_lo only
+ *             when its maximum is certain (a margin of 1e-4 relative + 1e-6 over every other
+ *             candidate, and the face's blend certain), and in cov_hi for every face that is
+ *             a possible blend within that margin of the maximum;
+ *   visible   vis_certain / vis_possible: blended at one pixel with certainty / possibly.
+ * "Certain" blends have rho >= 1e-4 and T >= 1.001 t_min; "possible" ones rho > -1e-4 and
+ * T >= 0.999 t_min.  An implementation that rounds differently must land inside these
+ * intervals; near-ties are the only freedom.  Candidates are the faces whose bounding box,
+ * widened by 1e-3 pixel, contains the pixel. */
+typedef struct { float zkey; int64_t m; double rho, alpha; } cand_t;
+
+static int cand_cmp(const void *a, const void *b) {
+    const cand_t *x = (const cand_t *)a, *y = (const cand_t *)b;
+    if (x->zkey < y->zkey) return -1;
+    if (x->zkey > y->zkey) return 1;
+    return (x->m > y->m) - (x->m < y->m);
+}
+
+int orc_face_stats(const orc_scene *s, const double *pose, const orc_cam *c, const orc_par *p, double t_min,
+                   double *area, int32_t *cov_lo, int32_t *cov_hi, int32_t *vis_certain, int32_t *vis_possible) {
+    int rc = check_args(s, pose, c, p);
+    if (rc) return rc;
+    const int64_t M = s->n_faces;
+    face_t *F = (face_t *)calloc((size_t)(M ? M : 1), sizeof(face_t));
+    setup_all(s, pose, c, p, F);
+    for (int64_t m = 0; m < M; m++) {
+        int r[4];
+        area[m] = face_rect(&F[m], c, r) ? 0.5 * F[m].area2 : 0.0;
+        cov_lo[m] = cov_hi[m] = vis_certain[m] = vis_possible[m] = 0;
+    }
+    const int64_t npix = (int64_t)c->width * c->height;
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < npix; k++) {
+        const int u = (int)(k % c->width), v = (int)(k / c->width);
+        int64_t cap = 16, n = 0;
+        cand_t *h = (cand_t *)malloc(sizeof(cand_t) * cap);
+        for (int64_t m = 0; m < M; m++) {
+            const face_t *f = &F[m];
+            if (!f->ok) continue;
+            if (!(u >= f->umin - 1e-3 && u <= f->umax + 1e-3 && v >= f->vmin - 1e-3 && v <= f->vmax + 1e-3)) continue;
+            double rho, lam[3];
+            const double I = face_window(f, p->sigma, u, v, &rho, lam);
+            if (!(rho > -1e-4)) continue;
+            if (n == cap) { cap *= 2; h = (cand_t *)realloc(h, sizeof(cand_t) * cap); }
+            h[n].zkey = f->zkey; h[n].m = m; h[n].rho = rho; h[n].alpha = f->of * I;
+            n++;
+        }
+        qsort(h, (size_t)n, sizeof(cand_t), cand_cmp);
+        double *w = (double *)malloc(sizeof(double) * (size_t)(n ? n : 1));
+        char *poss = (char *)malloc((size_t)(n ? n : 1)), *cert = (char *)malloc((size_t)(n ? n : 1));
+        double T = 1.0, best_w = 0.0;
+        int64_t best = -1;
+        for (int64_t j = 0; j < n; j++) {
+            const int live = T >= t_min && T > 0.0;
+            const int blend = live && h[j].rho > 0.0 && h[j].alpha > 0.0;
+            poss[j] = (char)(T > 0.0 && T >= 0.999 * t_min);
+            cert[j] = (char)(blend && h[j].rho >= 1e-4 && T >= 1.001 * t_min);
+            w[j] = blend ? h[j].alpha * T : 0.0;
+            if (blend && w[j] > best_w) { best_w = w[j]; best = j; }
+            if (blend) T *= 1.0 - h[j].alpha;
+        }
+        const double slack = 1e-4 * best_w + 1e-6;
+        int unique = best >= 0 && cert[best] && best_w > slack;
+        for (int64_t j = 0; j < n; j++) {
+            if (!poss[j]) continue;
+            if (w[j] >= best_w - slack) {
+                #pragma omp atomic
+                cov_hi[h[j].m] += 1;
+                if (j != best) unique = 0;
+            }
+            if (cert[j]) {
+                #pragma omp atomic write
+                vis_certain[h[j].m] = 1;
+            }
+            #pragma omp atomic write
+            vis_possible[h[j].m] = 1;
+        }
+        if (unique) {
+            #pragma omp atomic
+            cov_lo[h[best].m] += 1;
+        }
+        free(w); free(poss); free(cert); free(h);
+    }
+    free(F);
+    return ORC_OK;
+}
