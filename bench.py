@@ -203,6 +203,10 @@ DSSIM_BYTES_PER_VALUE = 20 + 28
 DSSIM_MIN_BYTES_PER_VALUE = 12
 
 
+# E_equi reads the 9 coordinates of a soup face and writes their 9 gradients: 72 bytes per face.
+EQUI_BYTES_PER_FACE = 72
+
+
 def photometric_summary(pixels, ms, ktimes):
     dk = ("ssim_stats", "photo_seeds")
     d_ms = sum(ktimes.get(k, 0.0) for k in dk)
@@ -414,6 +418,25 @@ def main():
     log(f"[bench] photometric step (L1 + D-SSIM): {ms_photo:.3f} ms; D-SSIM kernels "
         f"{photometric['dssim_roofline']['ms'] * 1e3:.1f} us")
 
+    # map-management kernels: E_equi over the whole map, per-face screen statistics of the view
+    def step_equi():
+        raster.equilateral(dev, weight=1.2, grad=eq_grad, loss=eq_loss)
+    eq_grad = torch.empty(3, dev.n_vertices, device="cuda")
+    eq_loss = torch.empty(1, device="cuda")
+    ms_equi = time_steps(step_equi, args.steps, args.warmup)
+    kt_equi, _ = kernel_times(step_equi, args.profile_steps)
+    single.rast.bin_and_sort(single.poses)
+    ms_stats = time_steps(lambda: single.rast.face_stats(single.poses), args.steps, args.warmup)
+    kt_stats, _ = kernel_times(lambda: single.rast.face_stats(single.poses), args.profile_steps)
+    eq_ms = kt_equi.get("equi", 0.0)
+    eq_gbs = EQUI_BYTES_PER_FACE * dev.n_faces / (eq_ms * 1e-3) / 1e9 if eq_ms > 0 else None
+    map_mgmt = {"equi_ms": ms_equi, "equi_kernels_ms": {k: round(v, 4) for k, v in kt_equi.items()},
+                "equi_roofline": {"bound": "hbm", "achieved": eq_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": None if eq_gbs is None else eq_gbs / HBM_PEAK_GBS,
+                                  "bytes_per_face": EQUI_BYTES_PER_FACE},
+                "face_stats_ms": ms_stats, "face_stats_kernels_ms": {k: round(v, 4) for k, v in kt_stats.items()}}
+    log(f"[bench] E_equi over {dev.n_faces} faces {ms_equi * 1e3:.1f} us; face statistics {ms_stats * 1e3:.1f} us")
+
     batched = None
     if not args.no_batched:
         g = scenes.rng(5500)
@@ -492,6 +515,7 @@ def main():
                               "traffic_gbs": None if bs_traffic is None else bs_traffic / (bs_ms * 1e-3) / 1e9},
         "kernels_ms": {k: round(v, 4) for k, v in ktimes.items()},
         "photometric": photometric,
+        "map_management": map_mgmt,
         "unfused": {"ms_per_step": ms_unf, "mpix_s": single.pixels / (ms_unf * 1e-3) / 1e6,
                     "kernels_ms": {k: round(v, 4) for k, v in kt_unf.items()}},
         "batched": batched,

@@ -11,15 +11,18 @@
  *   - front-to-back alpha compositing in depth order (eq. 4), of colour and of depth
  *     D = sum z_F alpha T (the rendered depth of eqs. 9 and 13);
  *   - the analytic backward pass to vertex positions, colours, opacities and the se(3)
- *     left perturbation of T_CW (eqs. 5-7).
+ *     left perturbation of T_CW (eqs. 5-7);
+ *   - the training energies around it: the L1 photometric and depth terms and the D-SSIM
+ *     term (eqs. 8 and 10), the equilateral regulariser (eq. 14), and the per-face screen
+ *     statistics that the map-management tests of Sec. 3.4 threshold.
  *
  * Conventions shared by every entry point
  *   - Pointers are DEVICE pointers unless marked (host).  Structs passed by pointer are host
  *     memory.  Float arrays are float32, integer arrays int32 / uint32 / uint64 as stated.
  *   - `stream` is a hipStream_t (NULL = the default stream).  Every call only enqueues work
  *     on `stream` and returns without synchronising, except tsr_check / tsr_count.
- *   - The caller owns every buffer, the workspace included; the library never allocates or
- *     frees device memory.  A new workspace is initialised once with tsr_workspace_init.  The workspace carries the binning between tsr_bin_and_sort,
+ *   - The caller owns every buffer, the workspace and scratch buffers included; the library
+ *     never allocates or frees device memory.  A new workspace is initialised once with tsr_workspace_init.  The workspace carries the binning between tsr_bin_and_sort,
  *     tsr_render_forward and tsr_render_backward; reusing it for another scene, pose set or
  *     view set invalidates that state.
  *   - A pose is T_CW (world -> camera): 12 floats, R row-major then t.  Camera frame x right,
@@ -233,6 +236,38 @@ TSR_API int tsr_render_train_photometric(const tsr_scene *scene, const float *po
                                  float *color, float *depth, float *trans, float *loss,
                                  float *grad_pos, float *grad_col, float *grad_opa, float *grad_pose,
                                  void *scratch, size_t scratch_bytes, void *stream);
+
+/* Equilateral regulariser (Sec. 3.5, eq. 14):
+ *   loss = (1/M) sum over faces (1/3) sum over corners (cos theta - 1/2)^2,
+ * cos theta the dot product of the two unit edge vectors leaving the corner.  A face with a
+ * zero-length edge contributes 0, gets no gradient and still counts in M (the paper leaves
+ * it undefined).  Uses scene->pos and scene->faces only (a soup when faces is NULL).
+ * loss: device [1] or NULL.  grad_pos: device [3][N] or NULL; receives weight * dloss/dpos
+ * (accumulate = 0; vertices of no face get 0) or has it added (accumulate != 0).  Indexed
+ * meshes add with float atomics, so their gradient sums in no fixed order.  Face indices
+ * outside [0, N) skip their face.  scratch: device, 8-byte aligned, at least
+ * tsr_equilateral_scratch_size bytes (8 per 256 faces).  Per-face arithmetic in FP64.
+ * Enqueued on `stream`; no allocation, no synchronisation. */
+TSR_API int tsr_equilateral_scratch_size(int64_t n_faces, size_t *bytes /* (host) out */);
+TSR_API int tsr_equilateral(const tsr_scene *scene, float weight, int accumulate, float *loss, float *grad_pos,
+                    void *scratch, size_t scratch_bytes, void *stream);
+
+/* Per-(view, face) screen statistics behind the map-management tests of Sec. 3.4 (pruning by
+ * projected area, densification by pixel coverage, keyframing by visibility), each [V * M]
+ * indexed v * M + m, all device, each may be NULL:
+ *   area:     projected image-space area in pixels^2 (FP64 setup as in the binning, stored as
+ *             float) of faces that pass the near-plane and inradius culls and overlap the
+ *             image; 0 for the others.  Needs no binning.
+ *   coverage: number of pixels at which the face has the largest blending weight alpha T along
+ *             the ray (the first in depth order on ties), with the forward pass's blending
+ *             decisions and early stop;
+ *   visible:  1 when the face is blended at one pixel or more, else 0.
+ * coverage and visible need a preceding tsr_bin_and_sort with the same inputs; both are
+ * overwritten.  The paper names the tests, not these definitions: coverage as the number of
+ * pixels where the face dominates is the reading taken for its blur-split criterion. */
+TSR_API int tsr_face_stats(const tsr_scene *scene, const float *poses, const tsr_intrinsics *intr, int n_views,
+                   const tsr_params *params, void *ws, size_t ws_bytes, float *area, uint32_t *coverage,
+                   uint32_t *visible, void *stream);
 
 /* Synchronise `stream` and report device-side conditions of `ws`: TSR_ECAPACITY when the
  * last binning, or any binning since the previous tsr_check (e.g. inside a replayed graph),

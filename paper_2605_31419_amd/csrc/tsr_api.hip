@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <string>
@@ -398,6 +399,45 @@ int tsr_render_train_photometric(const tsr_scene* scene, const float* poses, con
   e = tsr::launch_backward(dev_scene(scene), poses, vt, *params, L, w, gc, gd, nullptr, nullptr, nullptr, nullptr,
                            nullptr, nullptr, nullptr, grad_pos, grad_col, grad_opa, grad_pose, false, sched, st);
   return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_render_train_photometric backward");
+}
+
+int tsr_equilateral_scratch_size(int64_t n_faces, size_t* bytes) {
+  if (!bytes) return fail(TSR_EINVAL, "bytes is NULL");
+  if (n_faces < 0) return fail(TSR_EINVAL, "negative n_faces");
+  *bytes = align_up(sizeof(double) * (size_t)std::max<int64_t>(1, tsr::equi_blocks(n_faces)));
+  return TSR_OK;
+}
+
+int tsr_equilateral(const tsr_scene* scene, float weight, int accumulate, float* loss, float* grad_pos,
+                    void* scratch, size_t scratch_bytes, void* stream) {
+  int rc;
+  if ((rc = check_scene(scene))) return rc;
+  if (!loss && !grad_pos) return fail(TSR_EINVAL, "loss and grad_pos are both NULL");
+  if (!scratch) return fail(TSR_EINVAL, "scratch is NULL");
+  const int64_t nb = tsr::equi_blocks(scene->n_faces);
+  if (nb > 0x7fffffff) return fail(TSR_EINVAL, "too many faces");
+  const size_t need = sizeof(double) * (size_t)std::max<int64_t>(1, nb);
+  if (scratch_bytes < need) return fail(TSR_EWORKSPACE, "E_equi scratch of %zu bytes is below the %zu needed", scratch_bytes, need);
+  if (reinterpret_cast<uintptr_t>(scratch) & 7) return fail(TSR_EINVAL, "scratch must be 8-byte aligned");
+  hipError_t e = tsr::launch_equi(dev_scene(scene), weight, accumulate != 0, loss, grad_pos,
+                                  static_cast<double*>(scratch), static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_equilateral launch");
+}
+
+int tsr_face_stats(const tsr_scene* scene, const float* poses, const tsr_intrinsics* intr, int n_views,
+                   const tsr_params* params, void* ws, size_t ws_bytes, float* area, uint32_t* coverage,
+                   uint32_t* visible, void* stream) {
+  ViewTable vt;
+  WsLayout L;
+  int rc = prepare(scene, poses, intr, n_views, params, ws, ws_bytes, &vt, &L);
+  if (rc) return rc;
+  if (!area && !coverage && !visible) return fail(TSR_EINVAL, "area, coverage and visible are all NULL");
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  hipError_t e = hipSuccess;
+  if (area) e = tsr::launch_face_area(dev_scene(scene), poses, vt, *params, area, st);
+  if (e == hipSuccess && (coverage || visible))
+    e = tsr::launch_face_stats(vt, *params, L, static_cast<char*>(ws), coverage, visible, st);
+  return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_face_stats launch");
 }
 
 int tsr_profile_enable(int on) {

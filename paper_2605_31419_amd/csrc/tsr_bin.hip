@@ -814,6 +814,34 @@ hipError_t launch_ws_init(char* ws, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Projected image-space area (pixels^2, half the absolute cross product of the projected
+// edges) of every (view, face) that survives the near-plane and inradius culls and overlaps the
+// image, 0 for the others; the same FP64 setup as the projection.  Thread idx = v * M + m.
+__global__ __launch_bounds__(256) void k_face_area(tsr_scene_dev sc, const float* __restrict__ poses, ViewTable vt,
+                                                   float z_near, float r_min, float* __restrict__ area) {
+  const int64_t M = vt.n_faces;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)vt.n_views * M) return;
+  const int v = (int)(idx / M);
+  const int64_t m = idx - (int64_t)v * M;
+  double R[9], t[3];
+  load_pose(poses, v, R, t);
+  int64_t vid[3];
+  face_vertices(sc, m, vid);
+  FaceSetup f;
+  const bool ok = setup_face(sc, vid, R, t, vt.v[v], z_near, r_min, f);
+  area[idx] = ok ? (float)(0.5 * f.area2) : 0.f;
+}
+
+hipError_t launch_face_area(const tsr_scene_dev& sc, const float* poses, const ViewTable& vt, const tsr_params& p,
+                            float* area, hipStream_t st) {
+  const int64_t n = (int64_t)vt.n_views * vt.n_faces;
+  if (n > 0)
+    TSR_LAUNCH("face_area", k_face_area, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, sc, poses, vt,
+               p.z_near, p.r_min, area);
+  return hipGetLastError();
+}
+
 hipError_t launch_bin(const tsr_scene_dev& sc, const float* poses, const ViewTable& vt, const tsr_params& p,
                       const WsLayout& L, char* ws, bool sort, hipStream_t st) {
   uint32_t* counts = reinterpret_cast<uint32_t*>(ws + L.counts);

@@ -956,6 +956,80 @@ static int sigma_mode(float s) { return s == 1.f ? 1 : (s == 0.5f ? 2 : (s == 2.
 
 static unsigned tile_grid(int n_tiles) { return 8u * (unsigned)((n_tiles + 7) / 8); }
 
+// Per-face screen statistics of binned views: the same front-to-back walk and blending
+// decisions as the forward pass (one wave per 8x8 quadrant, per-wave staging).  Each pixel
+// adds 1 to the coverage of the face with the largest blending weight alpha T along its ray
+// (the first in depth order on ties); a face blended at any pixel is marked visible (one
+// store per wave and face visit, from the first lane that blends it).
+template <int SM>
+__global__ __launch_bounds__(kBlock) void k_face_stats(ViewTable vt, const float* __restrict__ records,
+                                                       const uint64_t* __restrict__ pairs,
+                                                       const uint32_t* __restrict__ ranges, float sigma, float t_min,
+                                                       uint32_t* __restrict__ coverage, uint32_t* __restrict__ visible) {
+  __shared__ float4 srec[kWaves][kBatch * 6];
+  __shared__ uint32_t sface[kWaves][kBatch];
+  const int wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int tile = tile_of_block(vt.n_tiles);
+  if (tile < 0) return;
+  TileCtx c;
+  tile_ctx(vt, ranges, tile, wv, c);
+  float T = c.inside ? 1.f : 0.f, best_w = 0.f;
+  int best = -1;
+  const float dxb = (float)c.px, dyb = (float)c.py;
+  for (uint32_t b0 = c.start; b0 < c.end; b0 += kBatch) {
+    if (ballot(live(T, t_min)) == 0) break;
+    const int n = (int)min((uint32_t)kBatch, c.end - b0);
+    stage_batch(records, pairs, b0, n, srec[wv], sface[wv]);
+    unsigned long long mask = batch_hit_mask(srec[wv], n, c.bx, c.by);
+    bool lv = live(T, t_min);
+    while (mask) {
+      const int j = __builtin_ctzll(mask);
+      mask &= mask - 1;
+      Rec rc;
+      load_rec(srec[wv], j, rc);
+      PixelEval e;
+      const float dx = dxb - rc.f[kRecU0];
+      const float dy = dyb - rc.f[kRecV0];
+      const bool act = eval_face<SM>(rc, dx, dy, sigma, e) && lv;
+      const float a = act ? e.alpha : 0.f;
+      const float w = a * T;
+      const uint32_t g = sface[wv][j];
+      if (act && w > best_w) {
+        best_w = w;
+        best = (int)g;
+      }
+      const unsigned long long bm = ballot(act);
+      if (visible && bm != 0ull && lane == __builtin_ctzll(bm)) visible[g] = 1u;
+      T = T * (1.f - a);
+      lv = live(T, t_min);
+      if (ballot(lv) == 0) break;
+    }
+  }
+  if (coverage && best >= 0) atomicAdd(&coverage[best], 1u);
+}
+
+hipError_t launch_face_stats(const ViewTable& vt, const tsr_params& p, const WsLayout& L, char* ws,
+                             uint32_t* coverage, uint32_t* visible, hipStream_t st) {
+  const float* records = reinterpret_cast<const float*>(ws + L.records);
+  const uint64_t* pairs = reinterpret_cast<const uint64_t*>(ws + L.pairs);
+  const uint32_t* ranges = reinterpret_cast<const uint32_t*>(ws + L.ranges);
+  const int64_t nf = (int64_t)vt.n_views * vt.n_faces;
+  const unsigned fg = (unsigned)std::min<int64_t>((nf + 255) / 256, 4096);
+  if (nf > 0) {
+    if (coverage) TSR_LAUNCH("fill_stats", k_fill_f32, dim3(fg), dim3(256), 0, st, reinterpret_cast<float*>(coverage), nf);
+    if (visible) TSR_LAUNCH("fill_stats", k_fill_f32, dim3(fg), dim3(256), 0, st, reinterpret_cast<float*>(visible), nf);
+  }
+  const dim3 grid(tile_grid(vt.n_tiles)), block(kBlock);
+  switch (sigma_mode(p.sigma)) {
+    case 1: TSR_LAUNCH("face_stats", k_face_stats<1>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, coverage, visible); break;
+    case 2: TSR_LAUNCH("face_stats", k_face_stats<2>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, coverage, visible); break;
+    case 3: TSR_LAUNCH("face_stats", k_face_stats<3>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, coverage, visible); break;
+    default: TSR_LAUNCH("face_stats", k_face_stats<0>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, coverage, visible); break;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_forward(const ViewTable& vt, const tsr_params& p, const WsLayout& L, char* ws, float* color,
                           float* depth, float* trans, hipStream_t st) {
   const float* records = reinterpret_cast<const float*>(ws + L.records);

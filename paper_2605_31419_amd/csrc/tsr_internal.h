@@ -171,6 +171,18 @@ hipError_t launch_photo_seeds(const SsimTable& t, const float* color, const floa
                               const float* tdepth, float w_ssim, float w_color, float w_depth, float* loss,
                               char* scratch, float** gcolor, float** gdepth, hipStream_t st);
 
+// Equilateral regulariser (Sec. 3.5, eq. 14): workgroups of one launch over M faces, and the
+// launch (loss and/or gradient; `partial` holds one double per workgroup).
+int64_t equi_blocks(int64_t n_faces);
+hipError_t launch_equi(const tsr_scene_dev& sc, float weight, bool accumulate, float* loss, float* grad,
+                       double* partial, hipStream_t st);
+
+// Per-face screen statistics (pruning, densification and keyframing tests of Sec. 3.4).
+hipError_t launch_face_area(const tsr_scene_dev& sc, const float* poses, const ViewTable& vt, const tsr_params& p,
+                            float* area, hipStream_t st);
+hipError_t launch_face_stats(const ViewTable& vt, const tsr_params& p, const WsLayout& L, char* ws,
+                             uint32_t* coverage, uint32_t* visible, hipStream_t st);
+
 hipError_t launch_pose_step(float* poses, const float* grad_pose, int n_views, float lr_t, float lr_r,
                             hipStream_t st);
 

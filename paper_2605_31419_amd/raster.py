@@ -222,6 +222,18 @@ class Rasterizer:
               "tsr_render_train_photometric")
         return gp, gc, go, gpose
 
+    def face_stats(self, poses: torch.Tensor, want=(True, True, True), stream=None):
+        """Per-(view, face) projected area, dominant-pixel coverage and visibility
+        (``tsr_face_stats``), each [V * M] or None; coverage and visibility use the binning held
+        in the workspace (call ``bin_and_sort`` with the same poses first)."""
+        n = self.n_views * self.scene.n_faces
+        area = torch.empty(n, device=self.device) if want[0] else None
+        cov = torch.empty(n, dtype=torch.int32, device=self.device) if want[1] else None
+        vis = torch.empty(n, dtype=torch.int32, device=self.device) if want[2] else None
+        check(self.lib.tsr_face_stats(*self._args(poses), _ptr(area), _ptr(cov), _ptr(vis), _stream(stream)),
+              "tsr_face_stats")
+        return area, cov, vis
+
     def pose_step(self, poses: torch.Tensor, grad_pose: torch.Tensor, lr_trans: float, lr_rot: float,
                   stream=None) -> None:
         check(self.lib.tsr_pose_step(_ptr(poses), _ptr(grad_pose), self.n_views, lr_trans, lr_rot, _stream(stream)),
@@ -281,6 +293,30 @@ class DSsim:
                                  1 if accumulate else 0, _ptr(loss), _ptr(grad), _ptr(self.scratch),
                                  C.c_size_t(self.scratch.numel()), _stream(stream)), "tsr_dssim")
         return loss, grad
+
+
+def equilateral(scene: DeviceScene, weight: float = 1.0, grad: Optional[torch.Tensor] = None,
+                accumulate: bool = False, want_grad: bool = True, loss: Optional[torch.Tensor] = None,
+                stream=None):
+    """Equilateral regulariser of eq. (14) (``tsr_equilateral``): returns (loss [1], grad [3, N]
+    or None), the gradient scaled by ``weight`` and written or added into ``grad``."""
+    lib = _lib.load()
+    nb = C.c_size_t()
+    check(lib.tsr_equilateral_scratch_size(scene.n_faces, C.byref(nb)), "tsr_equilateral_scratch_size")
+    dev = scene.pos.device
+    scratch = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    loss = loss if loss is not None else torch.empty(1, device=dev)
+    if want_grad and grad is None:
+        if accumulate:
+            raise ValueError("accumulate needs a grad buffer")
+        grad = torch.empty(3, scene.n_vertices, device=dev)
+    if grad is not None and (grad.dtype != torch.float32 or not grad.is_contiguous()
+                             or grad.numel() != 3 * scene.n_vertices):
+        raise ValueError("grad: need a contiguous float32 tensor of 3 * n_vertices values")
+    sc = scene.c()
+    check(lib.tsr_equilateral(C.byref(sc), float(weight), 1 if accumulate else 0, _ptr(loss), _ptr(grad),
+                              _ptr(scratch), C.c_size_t(scratch.numel()), _stream(stream)), "tsr_equilateral")
+    return loss, grad
 
 
 # ---------------------------------------------------------------------------- autograd
