@@ -269,6 +269,38 @@ TSR_API int tsr_face_stats(const tsr_scene *scene, const float *poses, const tsr
                    const tsr_params *params, void *ws, size_t ws_bytes, float *area, uint32_t *coverage,
                    uint32_t *visible, void *stream);
 
+/* Sensor normals from depth (Sec. 3.4): for each pixel the back-projected points
+ * p(u, v) = D(u, v) ((u - cx)/fx, (v - cy)/fy, 1) of its left/right and upper/lower
+ * neighbours give central differences dx, dy and N_bar = (dx x dy) / |dx x dy| (camera frame;
+ * a surface facing the camera gets a normal pointing away from it).  Border pixels, pixels
+ * where the depth of the pixel or of a neighbour is <= 0, and zero cross products get
+ * N_bar = (0, 0, 0), which marks them invalid for tsr_render_train_normal.  FP64 arithmetic.
+ * depth: device [sum_v H_v W_v] packed like the rendered depth; normals: device, packed like
+ * the rendered colour ([3][H][W] per view). */
+TSR_API int tsr_sensor_normals(const float *depth, const tsr_intrinsics *intr /* (host)[n_views] */, int n_views,
+                       float *normals, void *stream);
+
+/* Normal loss of mapping (Sec. 3.4) on a soup, one step: per view
+ *   loss[v] = w_norm * mean over valid pixels of (1 - N(p) . N_bar(p))   (0 without valid pixels),
+ * N the rendered normal map (camera frame): each face's world unit normal
+ * (v1 - v0) x (v2 - v0) / |.| (vertex order, no flip) composited front to back like a colour
+ * constant over the face (eq. 4 weights), rotated by R_CW, not renormalised.  target_normals:
+ * N_bar packed like colour; a zero vector marks an invalid pixel (as tsr_sensor_normals
+ * writes).  Outputs (each may be NULL): normal_map (packed like colour), loss [n_views],
+ * grad_pos [3][N], grad_opa [N], grad_pose [n_views][6] -- all overwritten, gradients of the
+ * sum of loss[v].  Runs its own binning, forward and backward with the face normals as vertex
+ * colours: it needs no preceding tsr_bin_and_sort, and it leaves `ws` binned for that
+ * normal-coloured scene, so bin again before rendering the scene's colours with `ws`.
+ * scratch: device, 256-byte aligned, at least tsr_normal_scratch_size bytes (24 per vertex +
+ * 32 per pixel + 1.3 KB).  Soups only (faces == NULL): TSR_EINVAL otherwise. */
+TSR_API int tsr_normal_scratch_size(const tsr_scene *scene, const tsr_intrinsics *intr /* (host)[n_views] */,
+                            int n_views, size_t *bytes /* (host) out */);
+TSR_API int tsr_render_train_normal(const tsr_scene *scene, const float *poses, const tsr_intrinsics *intr,
+                            int n_views, const tsr_params *params, void *ws, size_t ws_bytes,
+                            const float *target_normals, float w_norm, float *normal_map, float *loss,
+                            float *grad_pos, float *grad_opa, float *grad_pose, void *scratch,
+                            size_t scratch_bytes, void *stream);
+
 /* Synchronise `stream` and report device-side conditions of `ws`: TSR_ECAPACITY when the
  * last binning, or any binning since the previous tsr_check (e.g. inside a replayed graph),
  * overflowed; that condition is then cleared.  Writes the last K to *n_pairs when non-NULL.

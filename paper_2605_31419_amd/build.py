@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libtsr.so")
 
-SOURCES = ["tsr_bin.hip", "tsr_blend.hip", "tsr_ssim.hip", "tsr_reg.hip", "tsr_api.hip"]
+SOURCES = ["tsr_bin.hip", "tsr_blend.hip", "tsr_ssim.hip", "tsr_reg.hip", "tsr_normal.hip", "tsr_api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

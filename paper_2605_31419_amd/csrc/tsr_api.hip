@@ -440,6 +440,60 @@ int tsr_face_stats(const tsr_scene* scene, const float* poses, const tsr_intrins
   return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_face_stats launch");
 }
 
+int tsr_sensor_normals(const float* depth, const tsr_intrinsics* intr, int n_views, float* normals, void* stream) {
+  if (!depth || !normals) return fail(TSR_EINVAL, "depth or normals is NULL");
+  if (!intr) return fail(TSR_EINVAL, "intrinsics pointer is NULL");
+  if (n_views < 1 || n_views > TSR_MAX_VIEWS) return fail(TSR_EINVAL, "n_views = %d outside [1, %d]", n_views, TSR_MAX_VIEWS);
+  ViewTable vt;
+  memset(&vt, 0, sizeof vt);
+  int64_t pix = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const tsr_intrinsics& c = intr[v];
+    if (c.width <= 0 || c.height <= 0 || c.width > 16384 || c.height > 16384)
+      return fail(TSR_EINVAL, "view %d: image size %dx%d outside (0, 16384]", v, c.width, c.height);
+    if (!(c.fx != 0.f) || !(c.fy != 0.f)) return fail(TSR_EINVAL, "view %d: zero focal length", v);
+    vt.v[v].width = c.width;
+    vt.v[v].height = c.height;
+    vt.v[v].pix_off = pix;
+    vt.v[v].fx = c.fx; vt.v[v].fy = c.fy; vt.v[v].cx = c.cx; vt.v[v].cy = c.cy;
+    pix += (int64_t)c.width * c.height;
+  }
+  vt.n_views = n_views;
+  hipError_t e = tsr::launch_sensor_normals(vt, depth, normals, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_sensor_normals launch");
+}
+
+int tsr_normal_scratch_size(const tsr_scene* scene, const tsr_intrinsics* intr, int n_views, size_t* bytes) {
+  int rc;
+  if ((rc = check_scene(scene))) return rc;
+  if (!bytes) return fail(TSR_EINVAL, "bytes is NULL");
+  ViewTable vt;
+  if ((rc = build_views(scene, intr, n_views, &vt))) return rc;
+  *bytes = tsr::normal_scratch(scene->n_vertices, total_pixels(vt)).total;
+  return TSR_OK;
+}
+
+int tsr_render_train_normal(const tsr_scene* scene, const float* poses, const tsr_intrinsics* intr, int n_views,
+                            const tsr_params* params, void* ws, size_t ws_bytes, const float* target_normals,
+                            float w_norm, float* normal_map, float* loss, float* grad_pos, float* grad_opa,
+                            float* grad_pose, void* scratch, size_t scratch_bytes, void* stream) {
+  ViewTable vt;
+  WsLayout L;
+  int rc = prepare(scene, poses, intr, n_views, params, ws, ws_bytes, &vt, &L);
+  if (rc) return rc;
+  if (scene->faces) return fail(TSR_EINVAL, "the normal loss needs a soup (faces == NULL)");
+  if (!target_normals) return fail(TSR_EINVAL, "target_normals is NULL");
+  if (!scratch) return fail(TSR_EINVAL, "scratch is NULL");
+  const int64_t P = total_pixels(vt);
+  const size_t need = tsr::normal_scratch(scene->n_vertices, P).total;
+  if (scratch_bytes < need) return fail(TSR_EWORKSPACE, "normal-loss scratch of %zu bytes is below the %zu needed", scratch_bytes, need);
+  if (reinterpret_cast<uintptr_t>(scratch) & 255) return fail(TSR_EINVAL, "scratch must be 256-byte aligned");
+  hipError_t e = tsr::launch_train_normal(dev_scene(scene), poses, vt, *params, L, static_cast<char*>(ws),
+                                          target_normals, w_norm, normal_map, loss, grad_pos, grad_opa, grad_pose,
+                                          static_cast<char*>(scratch), P, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_render_train_normal launch");
+}
+
 int tsr_profile_enable(int on) {
   std::lock_guard<std::mutex> lk(tsr::g_prof_mu);
   tsr::g_prof_on = on != 0;

@@ -234,6 +234,27 @@ class Rasterizer:
               "tsr_face_stats")
         return area, cov, vis
 
+    def train_normal(self, poses: torch.Tensor, target_normals: torch.Tensor, w_norm: float = 0.05,
+                     normal_map=None, loss=None, out=None, stream=None):
+        """Normal loss of mapping (``tsr_render_train_normal``): bins, renders the normal map
+        and back-propagates w_norm * mean(1 - N . N_bar); returns (grad_pos, grad_opa,
+        grad_pose).  Leaves the workspace binned for the normal-coloured soup."""
+        if getattr(self, "_nscratch", None) is None:
+            nb = C.c_size_t()
+            check(self.lib.tsr_normal_scratch_size(C.byref(self._cscene), self._cintr, self.n_views, C.byref(nb)),
+                  "tsr_normal_scratch_size")
+            self._nscratch = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        if out is None:
+            gp, _, go, gpose = self.grad_buffers((True, False, True, True))
+        else:
+            gp, go, gpose = out
+        sc = self._nscratch
+        check(self.lib.tsr_render_train_normal(*self._args(poses), _ptr(target_normals), float(w_norm),
+                                               _ptr(normal_map), _ptr(loss), _ptr(gp), _ptr(go), _ptr(gpose),
+                                               _ptr(sc), C.c_size_t(sc.numel()), _stream(stream)),
+              "tsr_render_train_normal")
+        return gp, go, gpose
+
     def pose_step(self, poses: torch.Tensor, grad_pose: torch.Tensor, lr_trans: float, lr_rot: float,
                   stream=None) -> None:
         check(self.lib.tsr_pose_step(_ptr(poses), _ptr(grad_pose), self.n_views, lr_trans, lr_rot, _stream(stream)),
@@ -317,6 +338,19 @@ def equilateral(scene: DeviceScene, weight: float = 1.0, grad: Optional[torch.Te
     check(lib.tsr_equilateral(C.byref(sc), float(weight), 1 if accumulate else 0, _ptr(loss), _ptr(grad),
                               _ptr(scratch), C.c_size_t(scratch.numel()), _stream(stream)), "tsr_equilateral")
     return loss, grad
+
+
+def sensor_normals(depth: torch.Tensor, intrs: Sequence, normals: Optional[torch.Tensor] = None, stream=None):
+    """Sensor normals of packed depth maps (``tsr_sensor_normals``), packed like colour; a
+    zero vector marks an invalid pixel."""
+    lib = _lib.load()
+    n = sum(int(it.width) * int(it.height) for it in intrs)
+    if depth.dtype != torch.float32 or not depth.is_contiguous() or depth.numel() != n:
+        raise ValueError(f"depth: need a contiguous float32 tensor of {n} values")
+    normals = normals if normals is not None else torch.empty(3 * n, device=depth.device)
+    check(lib.tsr_sensor_normals(_ptr(depth), intrinsics_array(intrs), len(intrs), _ptr(normals), _stream(stream)),
+          "tsr_sensor_normals")
+    return normals
 
 
 # ---------------------------------------------------------------------------- autograd
