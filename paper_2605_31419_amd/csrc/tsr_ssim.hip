@@ -218,16 +218,24 @@ __global__ __launch_bounds__(256) void k_photo_seeds(const float* __restrict__ c
 }
 
 // loss[v] = w_ssim (1 - sum of SSIM / (3 W H)) + the view's L1 partials (when given).
-__global__ __launch_bounds__(256) void k_ssim_loss(SsimTable t, const double* __restrict__ partial,
-                                                   const double* __restrict__ l1_partial, float w_ssim,
-                                                   float* __restrict__ loss) {
-  __shared__ double red[2][4];
+__global__ __launch_bounds__(1024) void k_ssim_loss(SsimTable t, const double* __restrict__ partial,
+                                                    const double* __restrict__ l1_partial, float w_ssim,
+                                                    float* __restrict__ loss) {
+  __shared__ double red[2][16];
   const int v = blockIdx.x;
-  double sum = 0.0, l1 = 0.0;
-  for (int b = t.blk_off[v] + threadIdx.x; b < t.blk_off[v + 1]; b += blockDim.x) {
-    sum += partial[b];
-    if (l1_partial) l1 += l1_partial[b];
+  double s4[4] = {0.0, 0.0, 0.0, 0.0}, l4[4] = {0.0, 0.0, 0.0, 0.0};
+  const int b0 = t.blk_off[v], b1 = t.blk_off[v + 1];
+  for (int b = b0 + threadIdx.x; b < b1; b += 4 * blockDim.x) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int bb = b + u * blockDim.x;
+      if (bb < b1) {
+        s4[u] += partial[bb];
+        if (l1_partial) l4[u] += l1_partial[bb];
+      }
+    }
   }
+  double sum = (s4[0] + s4[1]) + (s4[2] + s4[3]), l1 = (l4[0] + l4[1]) + (l4[2] + l4[3]);
   for (int o = 32; o > 0; o >>= 1) {
     sum += __shfl_xor(sum, o, 64);
     l1 += __shfl_xor(l1, o, 64);
@@ -238,10 +246,13 @@ __global__ __launch_bounds__(256) void k_ssim_loss(SsimTable t, const double* __
   }
   __syncthreads();
   if (threadIdx.x == 0) {
+    double ss = 0.0, ll = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      ss += red[0][w];
+      ll += red[1][w];
+    }
     const double n = 3.0 * (double)t.width[v] * (double)t.height[v];
-    const double ssim = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
-    const double l1s = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
-    loss[v] = (float)((double)w_ssim * (1.0 - ssim / n) + l1s);
+    loss[v] = (float)((double)w_ssim * (1.0 - ss / n) + ll);
   }
 }
 
@@ -308,7 +319,7 @@ hipError_t launch_dssim(const SsimTable& t, const float* color, const float* tar
     TSR_LAUNCH("ssim_grad", k_ssim_grad, dim3(blocks), dim3(256), 0, st, color, target, t, abc, n3, weight,
                accumulate ? 1 : 0, grad);
   if (loss)
-    TSR_LAUNCH("ssim_loss", k_ssim_loss, dim3(t.n_views), dim3(256), 0, st, t, partial, (const double*)nullptr, 1.f,
+    TSR_LAUNCH("ssim_loss", k_ssim_loss, dim3(t.n_views), dim3(1024), 0, st, t, partial, (const double*)nullptr, 1.f,
                loss);
   return hipGetLastError();
 }
@@ -328,7 +339,7 @@ hipError_t launch_photo_seeds(const SsimTable& t, const float* color, const floa
   TSR_LAUNCH("photo_seeds", k_photo_seeds, dim3(blocks), dim3(256), 0, st, color, target, depth, tdepth, t, abc, n3,
              w_ssim, w_color, w_depth, *gcolor, *gdepth, l1_partial);
   if (loss)
-    TSR_LAUNCH("ssim_loss", k_ssim_loss, dim3(t.n_views), dim3(256), 0, st, t, partial, (const double*)l1_partial,
+    TSR_LAUNCH("ssim_loss", k_ssim_loss, dim3(t.n_views), dim3(1024), 0, st, t, partial, (const double*)l1_partial,
                w_ssim, loss);
   return hipGetLastError();
 }
