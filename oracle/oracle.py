@@ -33,7 +33,7 @@ class _Cam(C.Structure):
 
 
 class _Par(C.Structure):
-    _fields_ = [("sigma", C.c_double), ("z_near", C.c_double), ("r_min", C.c_double)]
+    _fields_ = [("sigma", C.c_double), ("z_near", C.c_double), ("r_min", C.c_double), ("opa_min", C.c_double)]
 
 
 _lib = None
@@ -86,7 +86,7 @@ def _ptr(a: Optional[np.ndarray]):
 class _Args:
     """Keeps the contiguous arrays alive for the duration of a call."""
 
-    def __init__(self, scene, pose, intr, sigma, z_near, r_min):
+    def __init__(self, scene, pose, intr, sigma, z_near, r_min, opacity_min=False):
         # float32 inputs are promoted exactly; float64 inputs (finite differences) pass as is
         self.pos = np.ascontiguousarray(scene.pos, dtype=np.float64)
         self.col = np.ascontiguousarray(scene.col, dtype=np.float64)
@@ -96,7 +96,7 @@ class _Args:
                          self.pos.shape[1], scene.n_faces)
         self.pose = np.ascontiguousarray(np.asarray(pose, dtype=np.float64).reshape(-1))
         self.cam = _cam(intr)
-        self.par = _Par(sigma, z_near, r_min)
+        self.par = _Par(sigma, z_near, r_min, 1.0 if opacity_min else 0.0)
 
 
 def _cam(intr) -> _Cam:
@@ -113,10 +113,11 @@ def max_threads() -> int:
 
 
 def render(scene, pose, intr, sigma=1.0, z_near=0.1, r_min=1e-3,
-           pixels: Optional[np.ndarray] = None) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+           pixels: Optional[np.ndarray] = None, opacity_min: bool = False) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
     """Colour [3, P], depth [P], final transmittance [P] of the listed pixel indices
-    (y*W + x), or of the whole frame when `pixels` is None (P = H*W)."""
-    a = _Args(scene, pose, intr, sigma, z_near, r_min)
+    (y*W + x), or of the whole frame when `pixels` is None (P = H*W).  `opacity_min` selects
+    the face opacity min(o_i) instead of the mean."""
+    a = _Args(scene, pose, intr, sigma, z_near, r_min, opacity_min)
     pix = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int64)
     n = a.cam.width * a.cam.height if pix is None else pix.shape[0]
     col = np.zeros((3, n)); dep = np.zeros(n); tr = np.zeros(n)
@@ -129,12 +130,12 @@ def render(scene, pose, intr, sigma=1.0, z_near=0.1, r_min=1e-3,
 
 def backward(scene, pose, intr, g_color: np.ndarray, g_depth: np.ndarray,
              g_trans: Optional[np.ndarray] = None, sigma=1.0, z_near=0.1, r_min=1e-3,
-             pixels: Optional[np.ndarray] = None, with_abs: bool = False):
+             pixels: Optional[np.ndarray] = None, with_abs: bool = False, opacity_min: bool = False):
     """Gradients (pos [3,N], col [3,N], opa [N], pose [6]) from the listed pixels' upstream
     gradients g_color [3,P], g_depth [P], g_trans [P].  With `with_abs`, also returns the
     per-element sums of absolute per-pixel contributions (pos, col, opa) -- the conditioning
     that bounds the rounding error of a lower-precision implementation."""
-    a = _Args(scene, pose, intr, sigma, z_near, r_min)
+    a = _Args(scene, pose, intr, sigma, z_near, r_min, opacity_min)
     pix = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int64)
     n = a.cam.width * a.cam.height if pix is None else pix.shape[0]
     gc = np.ascontiguousarray(np.asarray(g_color, np.float64).reshape(3, n))

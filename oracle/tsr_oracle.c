@@ -49,7 +49,10 @@ typedef struct {
 } orc_scene;
 
 typedef struct { int32_t width, height; double fx, fy, cx, cy; } orc_cam;
-typedef struct { double sigma, z_near, r_min; } orc_par;
+/* opa_min: 0 = face opacity is the mean of its vertex opacities (Sec. 3.1); 1 = their minimum
+ * (the Mesh Splatting rule the paper departs from), whose derivative goes to the vertex of
+ * lowest opacity (lowest index on ties). */
+typedef struct { double sigma, z_near, r_min, opa_min; } orc_par;
 
 static int64_t vid(const orc_scene *s, int64_t m, int k) {
     return s->faces ? (int64_t)s->faces[3 * m + k] : 3 * m + k;
@@ -64,6 +67,7 @@ typedef struct {
     double n[3][2], d[3], len[3];
     double area2, perim, r;
     double zf, of;
+    int kmin;             /* vertex of lowest opacity (lowest index on ties) */
     float zkey;
     double umin, umax, vmin, vmax;
 } face_t;
@@ -117,7 +121,11 @@ static void face_setup(const orc_scene *s, const double *pose, const orc_cam *c,
     }
     f->zf = (f->vc[0][2] + f->vc[1][2] + f->vc[2][2]) / 3.0;
     f->zkey = (float)f->zf;
-    f->of = (s->opa[f->v[0]] + s->opa[f->v[1]] + s->opa[f->v[2]]) / 3.0;
+    f->kmin = 0;
+    for (int k = 1; k < 3; k++)
+        if (s->opa[f->v[k]] < s->opa[f->v[f->kmin]]) f->kmin = k;
+    f->of = p->opa_min != 0.0 ? s->opa[f->v[f->kmin]]
+                              : (s->opa[f->v[0]] + s->opa[f->v[1]] + s->opa[f->v[2]]) / 3.0;
     f->umin = fmin(f->q[0][0], fmin(f->q[1][0], f->q[2][0]));
     f->umax = fmax(f->q[0][0], fmax(f->q[1][0], f->q[2][0]));
     f->vmin = fmin(f->q[0][1], fmin(f->q[1][1], f->q[2][1]));
@@ -392,7 +400,7 @@ int orc_backward_abs(const orc_scene *s, const double *pose, const orc_cam *c, c
                         abs_col[(int64_t)ch * N + vi] += fabs(val);
                     }
                 }
-                double go = galpha * e->I / 3.0;
+                double go = p->opa_min != 0.0 ? (i == f->kmin ? galpha * e->I : 0.0) : galpha * e->I / 3.0;
                 #pragma omp atomic
                 grad_opa[vi] += go;
                 if (abs_opa) {

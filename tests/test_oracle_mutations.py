@@ -18,8 +18,8 @@ MUTATIONS = {
     "window_sign": ("double rho = -L[ks] / f->r;", "double rho = L[ks] / f->r;"),
     "barycentric_index": ("lam[0] = -L[1] * f->len[1] / f->area2;", "lam[0] = -L[2] * f->len[1] / f->area2;"),
     "transmittance_assign": ("T *= 1.0 - h[j].alpha;", "T = 1.0 - h[j].alpha;"),
-    "min_opacity_rule": ("f->of = (s->opa[f->v[0]] + s->opa[f->v[1]] + s->opa[f->v[2]]) / 3.0;",
-                         "f->of = fmin(s->opa[f->v[0]], fmin(s->opa[f->v[1]], s->opa[f->v[2]]));"),
+    "min_opacity_rule": (": (s->opa[f->v[0]] + s->opa[f->v[1]] + s->opa[f->v[2]]) / 3.0;",
+                         ": fmin(s->opa[f->v[0]], fmin(s->opa[f->v[1]], s->opa[f->v[2]]));"),
     "depth_order_reversed": ("if (x->zkey < y->zkey) return -1;\n    if (x->zkey > y->zkey) return 1;",
                              "if (x->zkey < y->zkey) return 1;\n    if (x->zkey > y->zkey) return -1;"),
     "fx_fy_transposed": ("c->fx * f->vc[k][0] / f->vc[k][2] + c->cx", "c->fy * f->vc[k][0] / f->vc[k][2] + c->cx"),
