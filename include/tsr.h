@@ -93,6 +93,10 @@ typedef struct {
     float r_min;    /* cull faces whose projected inradius is below r_min pixels */
     float w_color;  /* L1 colour weight of the fused training loss (eq. 8, 1 - lambda) */
     float w_depth;  /* L1 depth weight of the fused training loss (eq. 10, lambda_dep) */
+    int32_t opacity_min; /* 0: face opacity = mean of the vertex opacities (Sec. 3.1, the
+                            paper's choice); 1: = their minimum (the Mesh Splatting variant the
+                            paper's ablation compares with), the opacity gradient then going to
+                            the lowest-opacity vertex (the lowest index on ties) */
 } tsr_params;
 
 /* Scene (host struct of device pointers). */

@@ -183,11 +183,13 @@ int check_params(const tsr_params* p) {
   if (!(p->sigma > 0.f)) return fail(TSR_EINVAL, "sigma must be > 0");
   if (!(p->t_min >= 0.f && p->t_min < 1.f)) return fail(TSR_EINVAL, "t_min must be in [0, 1)");
   if (!(p->r_min >= 0.f) || !(p->z_near == p->z_near)) return fail(TSR_EINVAL, "bad r_min / z_near");
+  if (p->opacity_min != 0 && p->opacity_min != 1) return fail(TSR_EINVAL, "opacity_min must be 0 or 1");
   return TSR_OK;
 }
 
-tsr::tsr_scene_dev dev_scene(const tsr_scene* sc) {
+tsr::tsr_scene_dev dev_scene(const tsr_scene* sc, const tsr_params* p = nullptr) {
   tsr::tsr_scene_dev d;
+  d.opa_min = p ? p->opacity_min : 0;
   d.pos = sc->pos;
   d.col = sc->col;
   d.opa = sc->opa;
@@ -240,7 +242,7 @@ int tsr_bin_and_sort(const tsr_scene* scene, const float* poses, const tsr_intri
   WsLayout L;
   int rc = prepare(scene, poses, intr, n_views, params, ws, ws_bytes, &vt, &L);
   if (rc) return rc;
-  hipError_t e = tsr::launch_bin(dev_scene(scene), poses, vt, *params, L, static_cast<char*>(ws), true,
+  hipError_t e = tsr::launch_bin(dev_scene(scene, params), poses, vt, *params, L, static_cast<char*>(ws), true,
                                  static_cast<hipStream_t>(stream));
   return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_bin_and_sort launch");
 }
@@ -253,7 +255,7 @@ int tsr_count(const tsr_scene* scene, const float* poses, const tsr_intrinsics* 
   if (rc) return rc;
   if (!n_pairs) return fail(TSR_EINVAL, "n_pairs is NULL");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  hipError_t e = tsr::launch_bin(dev_scene(scene), poses, vt, *params, L, static_cast<char*>(ws), false, st);
+  hipError_t e = tsr::launch_bin(dev_scene(scene, params), poses, vt, *params, L, static_cast<char*>(ws), false, st);
   if (e != hipSuccess) return hip_fail(e, "tsr_count launch");
   if ((e = hipMemcpyAsync(n_pairs, static_cast<char*>(ws) + L.hdr_k, sizeof(int64_t), hipMemcpyDeviceToHost, st)) != hipSuccess)
     return hip_fail(e, "tsr_count copy");
@@ -307,7 +309,7 @@ int tsr_render_backward(const tsr_scene* scene, const float* poses, const tsr_in
   if (rc) return rc;
   if (!grad_color || !grad_depth) return fail(TSR_EINVAL, "grad_color or grad_depth is NULL");
   tsr::TrainSchedule sched{0, 0, 0};
-  hipError_t e = tsr::launch_backward(dev_scene(scene), poses, vt, *params, L, static_cast<char*>(ws), grad_color,
+  hipError_t e = tsr::launch_backward(dev_scene(scene, params), poses, vt, *params, L, static_cast<char*>(ws), grad_color,
                                       grad_depth, grad_trans, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                                       grad_pos, grad_col, grad_opa, grad_pose, false, sched,
                                       static_cast<hipStream_t>(stream));
@@ -331,7 +333,7 @@ int tsr_render_train_l1(const tsr_scene* scene, const float* poses, const tsr_in
       return fail(TSR_EINVAL, "bad schedule");
     sched = {schedule->persistent, schedule->order, schedule->grid};
   }
-  hipError_t e = tsr::launch_backward(dev_scene(scene), poses, vt, *params, L, static_cast<char*>(ws), nullptr,
+  hipError_t e = tsr::launch_backward(dev_scene(scene, params), poses, vt, *params, L, static_cast<char*>(ws), nullptr,
                                       nullptr, nullptr, target_color, target_depth, color, depth, trans, loss,
                                       grad_pos, grad_col, grad_opa, grad_pose, true, sched,
                                       static_cast<hipStream_t>(stream));
@@ -396,7 +398,7 @@ int tsr_render_train_photometric(const tsr_scene* scene, const float* poses, con
                               loss, static_cast<char*>(scratch), &gc, &gd, st);
   if (e != hipSuccess) return hip_fail(e, "tsr_render_train_photometric seeds");
   tsr::TrainSchedule sched{0, 0, 0};
-  e = tsr::launch_backward(dev_scene(scene), poses, vt, *params, L, w, gc, gd, nullptr, nullptr, nullptr, nullptr,
+  e = tsr::launch_backward(dev_scene(scene, params), poses, vt, *params, L, w, gc, gd, nullptr, nullptr, nullptr, nullptr,
                            nullptr, nullptr, nullptr, grad_pos, grad_col, grad_opa, grad_pose, false, sched, st);
   return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_render_train_photometric backward");
 }
@@ -434,7 +436,7 @@ int tsr_face_stats(const tsr_scene* scene, const float* poses, const tsr_intrins
   if (!area && !coverage && !visible) return fail(TSR_EINVAL, "area, coverage and visible are all NULL");
   const hipStream_t st = static_cast<hipStream_t>(stream);
   hipError_t e = hipSuccess;
-  if (area) e = tsr::launch_face_area(dev_scene(scene), poses, vt, *params, area, st);
+  if (area) e = tsr::launch_face_area(dev_scene(scene, params), poses, vt, *params, area, st);
   if (e == hipSuccess && (coverage || visible))
     e = tsr::launch_face_stats(vt, *params, L, static_cast<char*>(ws), coverage, visible, st);
   return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_face_stats launch");
@@ -488,7 +490,7 @@ int tsr_render_train_normal(const tsr_scene* scene, const float* poses, const ts
   const size_t need = tsr::normal_scratch(scene->n_vertices, P).total;
   if (scratch_bytes < need) return fail(TSR_EWORKSPACE, "normal-loss scratch of %zu bytes is below the %zu needed", scratch_bytes, need);
   if (reinterpret_cast<uintptr_t>(scratch) & 255) return fail(TSR_EINVAL, "scratch must be 256-byte aligned");
-  hipError_t e = tsr::launch_train_normal(dev_scene(scene), poses, vt, *params, L, static_cast<char*>(ws),
+  hipError_t e = tsr::launch_train_normal(dev_scene(scene, params), poses, vt, *params, L, static_cast<char*>(ws),
                                           target_normals, w_norm, normal_map, loss, grad_pos, grad_opa, grad_pose,
                                           static_cast<char*>(scratch), P, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_render_train_normal launch");

@@ -103,6 +103,7 @@ __device__ __forceinline__ void face_normals(FaceSetup& f) {
 struct FaceAttr {
   float col[3][3];
   float opa[3];
+  int opa_min;     // face opacity = min of the vertex opacities instead of their mean
 };
 
 __device__ __forceinline__ void load_attr(const tsr_scene_dev& sc, const int64_t vid[3], FaceAttr& a) {
@@ -113,6 +114,7 @@ __device__ __forceinline__ void load_attr(const tsr_scene_dev& sc, const int64_t
     for (int ch = 0; ch < 3; ++ch) a.col[ch][k] = sc.col[ch * N + vid[k]];
     a.opa[k] = sc.opa[vid[k]];
   }
+  a.opa_min = sc.opa_min;
 }
 
 // Writes the FP32 face-local record of a visible face (after face_normals).
@@ -145,7 +147,8 @@ __device__ __forceinline__ void write_record(const FaceAttr& at, const FaceSetup
     rec[kRecCol + 3 * ch + 1] = (float)Q;
     rec[kRecCol + 3 * ch + 2] = (float)Rr;
   }
-  rec[kRecOpa] = (float)(((double)at.opa[0] + (double)at.opa[1] + (double)at.opa[2]) / 3.0);
+  rec[kRecOpa] = at.opa_min ? fminf(at.opa[0], fminf(at.opa[1], at.opa[2]))
+                            : (float)(((double)at.opa[0] + (double)at.opa[1] + (double)at.opa[2]) / 3.0);
   rec[kRecZ] = (float)f.zf;
   rec[kRecU0] = (float)f.u0;          // exact: |u0| < 2^24
   rec[kRecV0] = (float)f.v0;

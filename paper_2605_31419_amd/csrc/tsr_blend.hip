@@ -707,7 +707,8 @@ __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float*
       pose6[4] += vc[k][2] * gc[0] - vc[k][0] * gc[2];
       pose6[5] += vc[k][0] * gc[1] - vc[k][1] * gc[0];
     }
-    const double gop = (double)A[kGOpa] * (1.0 / 3.0);
+    // dL/do_F to each vertex: a third for the mean; all of it, to one vertex, for the minimum
+    const double gop = sc.opa_min ? (double)A[kGOpa] : (double)A[kGOpa] * (1.0 / 3.0);
     if (want_vertices) {
       float* stage = reinterpret_cast<float*>(grad_acc + g * kGradDwords);
       for (int k = 0; k < 3; ++k)
@@ -817,6 +818,20 @@ __global__ __launch_bounds__(256) void k_vertex_gather(tsr_scene_dev sc, ViewTab
       }
     }
   }
+  // with the minimum rule only the face's lowest-opacity vertex (lowest index on ties) gets the
+  // opacity gradient
+  int kmin = -1;
+  if (sc.opa_min && m < M && any) {
+    float om = 0.f;
+    for (int k = 0; k < 3; ++k) {
+      const int64_t vi = sc.faces ? (int64_t)sc.faces[3 * m + k] : 3 * m + k;
+      const float o = sc.opa[vi];
+      if (k == 0 || o < om) {
+        om = o;
+        kmin = k;
+      }
+    }
+  }
   if (sc.faces) {
     if (m >= M || !any) return;
     for (int k = 0; k < 3; ++k) {
@@ -825,7 +840,7 @@ __global__ __launch_bounds__(256) void k_vertex_gather(tsr_scene_dev sc, ViewTab
         if (grad_pos) unsafeAtomicAdd(&grad_pos[a * N + vi], acc[3 * k + a]);
         if (grad_col) unsafeAtomicAdd(&grad_col[a * N + vi], acc[9 + 3 * k + a]);
       }
-      if (grad_opa) unsafeAtomicAdd(&grad_opa[vi], acc[18]);
+      if (grad_opa && (kmin < 0 || k == kmin)) unsafeAtomicAdd(&grad_opa[vi], acc[18]);
     }
     return;
   }
@@ -840,7 +855,7 @@ __global__ __launch_bounds__(256) void k_vertex_gather(tsr_scene_dev sc, ViewTab
         s_out[a][3 * threadIdx.x + k] = acc[3 * k + a];
         s_out[3 + a][3 * threadIdx.x + k] = acc[9 + 3 * k + a];
       }
-      s_out[6][3 * threadIdx.x + k] = acc[18];
+      s_out[6][3 * threadIdx.x + k] = (kmin < 0 || k == kmin) ? acc[18] : 0.f;
     }
   }
   __syncthreads();

@@ -18,6 +18,7 @@ struct tsr_scene_dev {
   const int32_t* faces;
   int64_t n_vertices;
   int64_t n_faces;
+  int32_t opa_min;       // face opacity: 0 = vertex mean, 1 = vertex minimum
 };
 
 // Byte offsets of the workspace regions.  Fixed part first (depends on M, the views and

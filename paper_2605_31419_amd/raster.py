@@ -22,17 +22,20 @@ from ._lib import TsrBinning, TsrIntrinsics, TsrParams, TsrScene, TsrSchedule, c
 
 @dataclasses.dataclass
 class Params:
-    """Rendering parameters (window exponent of eq. 3, early-stop threshold, culling, and the
-    L1 weights of the fused training loss: 0.8 = 1 - lambda of eq. 8, 0.05 = lambda_dep)."""
+    """Rendering parameters (window exponent of eq. 3, early-stop threshold, culling, the L1
+    weights of the fused training loss: 0.8 = 1 - lambda of eq. 8, 0.05 = lambda_dep, and the
+    face-opacity rule)."""
     sigma: float = 1.0
     t_min: float = 1e-6
     z_near: float = 0.1
     r_min: float = 1e-3
     w_color: float = 0.8
     w_depth: float = 0.05
+    opacity_min: bool = False     # face opacity = min of the vertex opacities (Mesh Splatting variant)
 
     def c(self) -> TsrParams:
-        return TsrParams(self.sigma, self.t_min, self.z_near, self.r_min, self.w_color, self.w_depth)
+        return TsrParams(self.sigma, self.t_min, self.z_near, self.r_min, self.w_color, self.w_depth,
+                         1 if self.opacity_min else 0)
 
 
 def _ptr(t: Optional[torch.Tensor]):

@@ -7,9 +7,9 @@ import torch
 from paper_2605_31419_amd import raster
 
 
-def make(scene, intrs, poses, sigma=1.0, t_min=1e-6, fit=True):
+def make(scene, intrs, poses, sigma=1.0, t_min=1e-6, fit=True, opacity_min=False):
     sc = raster.DeviceScene.from_numpy(scene)
-    rast = raster.Rasterizer(sc, intrs, raster.Params(sigma=sigma, t_min=t_min))
+    rast = raster.Rasterizer(sc, intrs, raster.Params(sigma=sigma, t_min=t_min, opacity_min=opacity_min))
     p = raster.poses_tensor(poses)
     if fit:
         rast.fit(p)

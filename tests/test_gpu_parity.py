@@ -411,6 +411,44 @@ def test_train_photometric_matches_oracle(name):
         assert np.abs(cs[v] - ocs[v]).max() <= IMG_TOL
 
 
+# ---------------------------------------------------------------------------- minimum opacity rule
+
+@pytest.mark.parametrize("name", ["single_64x48", "multi_view_mixed", "tiny_ragged_50x37"])
+def test_minimum_opacity_rule_matches_oracle(name):
+    """Face opacity = min of the vertex opacities: forward and backward against the oracle
+    with the same rule; opacity gradients land on one vertex per face."""
+    _say(f"[opacity_min] case={name}")
+    sc, poses, intrs = _case(name)
+    g = np.random.default_rng(9)
+    sc = S.Scene(sc.pos, sc.col, g.uniform(0.2, 0.95, size=sc.n_vertices).astype(np.float32), sc.faces)
+    rast, p = G.make(sc, intrs, poses, opacity_min=True)
+    c, d, t = G.render(rast, p)
+    cs, ds = G.per_view(rast, c, 3), G.per_view(rast, d, 1)
+    for v in range(len(poses)):
+        oc, od, ot = O.render(sc, poses[v], intrs[v], opacity_min=True)
+        err = max(np.abs(cs[v] - oc).max(), np.abs(ds[v] - od).max())
+        assert err <= IMG_TOL, (v, err)
+    P = rast.total_pixels
+    gc = g.normal(size=3 * P).astype(np.float32)
+    gd = g.normal(size=P).astype(np.float32)
+    got = _gpu_backward(rast, p, gc, gd, None)
+    acc = None
+    gposes = []
+    for v, (gcv, gdv) in enumerate(zip(G.per_view(rast, gc, 3), G.per_view(rast, gd, 1))):
+        out = O.backward(sc, poses[v], intrs[v], gcv, gdv, None, opacity_min=True)
+        acc = list(out[:3]) if acc is None else [a + b for a, b in zip(acc, out[:3])]
+        gposes.append(out[3])
+    ref = acc + [np.concatenate(gposes)]
+    for nm, a, b in zip(["grad_pos", "grad_col", "grad_opa", "grad_pose"], got, ref):
+        ok, msg, _ = grad_close(a, b, name=nm)
+        _say("  " + msg)
+        assert ok, msg
+    go = np.asarray(got[2]).reshape(-1)
+    if sc.faces is None:
+        per_face = (go.reshape(-1, 3) != 0).sum(axis=1)
+        assert per_face.max() <= 1
+
+
 # ---------------------------------------------------------------------------- pose step
 
 def test_pose_step_matches_matrix_exponential():
