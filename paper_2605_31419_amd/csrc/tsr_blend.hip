@@ -29,6 +29,16 @@ __device__ __forceinline__ int tile_of_block(int n_tiles) {
   return (idx < per && t < n_tiles) ? t : -1;
 }
 
+// Tile of a one-workgroup-per-tile launch: the longest-first order when one is given (the
+// permutation of the tile ids built with the binning; an entry outside [0, n_tiles) gives no
+// tile), else the XCD-interleaved id order.
+__device__ __forceinline__ int tile_of_block_ordered(int n_tiles, const int* __restrict__ order) {
+  if (!order) return tile_of_block(n_tiles);
+  if ((int)blockIdx.x >= n_tiles) return -1;
+  const int t = order[blockIdx.x];
+  return (t >= 0 && t < n_tiles) ? t : -1;
+}
+
 // Window value for rho in (0, 1): I = rho^sigma (eq. 3).  Mode 1: sigma = 1, 2: sigma = 0.5,
 // 3: sigma = 2, 0: any sigma.
 template <int SM>
@@ -364,11 +374,11 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(ViewTable vt, const float*
                                                       const uint32_t* __restrict__ ranges, float sigma, float t_min,
                                                       float* __restrict__ color, float* __restrict__ depth,
                                                       float* __restrict__ trans, int* __restrict__ n_last,
-                                                      float* __restrict__ t_last) {
+                                                      float* __restrict__ t_last, const int* __restrict__ order) {
   __shared__ float4 srec[kWaves][kBatch * 6];
   __shared__ uint32_t sface[kWaves][kBatch];
   const int wv = threadIdx.x >> 6;
-  const int tile = tile_of_block(vt.n_tiles);
+  const int tile = tile_of_block_ordered(vt.n_tiles, order);
   if (tile < 0) return;
   TileCtx c;
   tile_ctx(vt, ranges, tile, wv, c);
@@ -393,11 +403,12 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(ViewTable vt, const float*
                                                       const uint32_t* __restrict__ ranges, float sigma,
                                                       const int* __restrict__ n_last, const float* __restrict__ t_last,
                                                       const float* __restrict__ gcolor, const float* __restrict__ gdepth,
-                                                      const float* __restrict__ gtrans, acc_t* __restrict__ grad_acc) {
+                                                      const float* __restrict__ gtrans, acc_t* __restrict__ grad_acc,
+                                                      const int* __restrict__ order) {
   __shared__ float4 srec[kWaves][kBatch * 6];
   __shared__ uint32_t sface[kWaves][kBatch];
   const int wv = threadIdx.x >> 6;
-  const int tile = tile_of_block(vt.n_tiles);
+  const int tile = tile_of_block_ordered(vt.n_tiles, order);
   if (tile < 0) return;
   TileCtx c;
   tile_ctx(vt, ranges, tile, wv, c);
@@ -980,12 +991,13 @@ template <int SM>
 __global__ __launch_bounds__(kBlock) void k_face_stats(ViewTable vt, const float* __restrict__ records,
                                                        const uint64_t* __restrict__ pairs,
                                                        const uint32_t* __restrict__ ranges, float sigma, float t_min,
-                                                       uint32_t* __restrict__ coverage, uint32_t* __restrict__ visible) {
+                                                       uint32_t* __restrict__ coverage, uint32_t* __restrict__ visible,
+                                                       const int* __restrict__ order) {
   __shared__ float4 srec[kWaves][kBatch * 6];
   __shared__ uint32_t sface[kWaves][kBatch];
   const int wv = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
-  const int tile = tile_of_block(vt.n_tiles);
+  const int tile = tile_of_block_ordered(vt.n_tiles, order);
   if (tile < 0) return;
   TileCtx c;
   tile_ctx(vt, ranges, tile, wv, c);
@@ -1029,6 +1041,8 @@ hipError_t launch_face_stats(const ViewTable& vt, const tsr_params& p, const WsL
   const float* records = reinterpret_cast<const float*>(ws + L.records);
   const uint64_t* pairs = reinterpret_cast<const uint64_t*>(ws + L.pairs);
   const uint32_t* ranges = reinterpret_cast<const uint32_t*>(ws + L.ranges);
+  // longest-first tile order, built with the binning up to kOrderInSortMax tiles
+  const int* border = vt.n_tiles <= kOrderInSortMax ? reinterpret_cast<const int*>(ws + L.order) : nullptr;
   const int64_t nf = (int64_t)vt.n_views * vt.n_faces;
   const unsigned fg = (unsigned)std::min<int64_t>((nf + 255) / 256, 4096);
   if (nf > 0) {
@@ -1037,10 +1051,10 @@ hipError_t launch_face_stats(const ViewTable& vt, const tsr_params& p, const WsL
   }
   const dim3 grid(tile_grid(vt.n_tiles)), block(kBlock);
   switch (sigma_mode(p.sigma)) {
-    case 1: TSR_LAUNCH("face_stats", k_face_stats<1>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, coverage, visible); break;
-    case 2: TSR_LAUNCH("face_stats", k_face_stats<2>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, coverage, visible); break;
-    case 3: TSR_LAUNCH("face_stats", k_face_stats<3>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, coverage, visible); break;
-    default: TSR_LAUNCH("face_stats", k_face_stats<0>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, coverage, visible); break;
+    case 1: TSR_LAUNCH("face_stats", k_face_stats<1>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, coverage, visible, border); break;
+    case 2: TSR_LAUNCH("face_stats", k_face_stats<2>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, coverage, visible, border); break;
+    case 3: TSR_LAUNCH("face_stats", k_face_stats<3>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, coverage, visible, border); break;
+    default: TSR_LAUNCH("face_stats", k_face_stats<0>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, coverage, visible, border); break;
   }
   return hipGetLastError();
 }
@@ -1050,14 +1064,16 @@ hipError_t launch_forward(const ViewTable& vt, const tsr_params& p, const WsLayo
   const float* records = reinterpret_cast<const float*>(ws + L.records);
   const uint64_t* pairs = reinterpret_cast<const uint64_t*>(ws + L.pairs);
   const uint32_t* ranges = reinterpret_cast<const uint32_t*>(ws + L.ranges);
+  // longest-first tile order, built with the binning up to kOrderInSortMax tiles
+  const int* border = vt.n_tiles <= kOrderInSortMax ? reinterpret_cast<const int*>(ws + L.order) : nullptr;
   int* n_last = reinterpret_cast<int*>(ws + L.n_last);
   float* t_last = reinterpret_cast<float*>(ws + L.t_last);
   const dim3 grid(tile_grid(vt.n_tiles)), block(kBlock);
   switch (sigma_mode(p.sigma)) {
-    case 1: TSR_LAUNCH("blend_fwd", k_blend_fwd<1>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last); break;
-    case 2: TSR_LAUNCH("blend_fwd", k_blend_fwd<2>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last); break;
-    case 3: TSR_LAUNCH("blend_fwd", k_blend_fwd<3>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last); break;
-    default: TSR_LAUNCH("blend_fwd", k_blend_fwd<0>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last); break;
+    case 1: TSR_LAUNCH("blend_fwd", k_blend_fwd<1>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last, border); break;
+    case 2: TSR_LAUNCH("blend_fwd", k_blend_fwd<2>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last, border); break;
+    case 3: TSR_LAUNCH("blend_fwd", k_blend_fwd<3>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last, border); break;
+    default: TSR_LAUNCH("blend_fwd", k_blend_fwd<0>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last, border); break;
   }
   return hipGetLastError();
 }
@@ -1096,7 +1112,9 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
   const int sm = sigma_mode(p.sigma);
   if (!fused_train) {
     const dim3 grid(tile_grid(vt.n_tiles));
-#define TSR_BWD(S) TSR_LAUNCH("blend_bwd", k_blend_bwd<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, n_last, t_last, gcolor, gdepth, gtrans, grad_acc)
+    // longest-first tile order, built with the binning up to kOrderInSortMax tiles
+    const int* border = vt.n_tiles <= kOrderInSortMax ? reinterpret_cast<const int*>(ws + L.order) : nullptr;
+#define TSR_BWD(S) TSR_LAUNCH("blend_bwd", k_blend_bwd<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, n_last, t_last, gcolor, gdepth, gtrans, grad_acc, border)
     switch (sm) { case 1: TSR_BWD(1); break; case 2: TSR_BWD(2); break; case 3: TSR_BWD(3); break; default: TSR_BWD(0); }
 #undef TSR_BWD
   } else {
