@@ -91,3 +91,23 @@ def test_full_size_1200x680_1m_properties():
     got = area[ms]
     assert np.all(np.abs(got - ref) <= 1e-6 * np.maximum(ref, 1.0)), np.abs(got - ref).max()
     assert np.all((got > 0) == (counts[ms] > 0))     # the area is set exactly for the binned faces
+
+
+def test_tile_lists_longer_than_the_visibility_bitmap():
+    """5,000 faint faces stacked over one 16 x 16 tile: list positions past the kernel's
+    4,096-bit visibility bitmap take the direct path; every face blends (T stays above t_min)."""
+    g = np.random.default_rng(77)
+    M = 5000
+    z = g.uniform(1.0, 3.0, size=M)
+    base = np.array([[-0.5, -0.45, 0.0], [0.55, -0.4, 0.0], [0.0, 0.6, 0.0]])    # covers the view centre
+    pos = np.empty((3, 3 * M))
+    for m in range(M):
+        tri = (base + g.normal(scale=0.03, size=(3, 3))) * z[m] * 0.1
+        tri[:, 2] = z[m]
+        pos[:, 3 * m:3 * m + 3] = tri.T
+    sc = S.Scene(pos.astype(np.float32), g.uniform(0, 1, size=(3, 3 * M)).astype(np.float32),
+                 np.full(3 * M, 0.002, np.float32))
+    intr = S.Intrinsics(16, 16, 40.0, 40.0, 7.5, 7.5)
+    _, _, area, cov, vis = _gpu_stats(sc, [intr], [IDENTITY])
+    _check_view(sc, IDENTITY, intr, area, cov, vis, 1e-6)
+    assert vis.sum() > 4096
