@@ -984,9 +984,10 @@ static unsigned tile_grid(int n_tiles) { return 8u * (unsigned)((n_tiles + 7) / 
 
 // Per-face screen statistics of binned views: the same front-to-back walk and blending
 // decisions as the forward pass (one wave per 8x8 quadrant, per-wave staging).  Each pixel
-// adds 1 to the coverage of the face with the largest blending weight alpha T along its ray
-// (the first in depth order on ties); a face blended at any pixel is marked visible (one
-// store per wave and face visit, from the first lane that blends it).
+// counts 1 for the coverage of the face with the largest blending weight alpha T along its
+// ray (the first in depth order on ties), summed per wave before the atomics; a face blended
+// at any pixel is marked visible (one store per wave and face visit, from the first lane that
+// blends it).
 template <int SM>
 __global__ __launch_bounds__(kBlock) void k_face_stats(ViewTable vt, const float* __restrict__ records,
                                                        const uint64_t* __restrict__ pairs,
@@ -1033,7 +1034,20 @@ __global__ __launch_bounds__(kBlock) void k_face_stats(ViewTable vt, const float
       if (ballot(lv) == 0) break;
     }
   }
-  if (coverage && best >= 0) atomicAdd(&coverage[best], 1u);
+  if (coverage) {
+    // one atomic per distinct dominant face of the wave, adding its number of pixels (a large
+    // face dominates many pixels, and atomics on one address serialise)
+    bool pending = best >= 0;
+    for (;;) {
+      const unsigned long long pm = ballot(pending);
+      if (pm == 0ull) break;
+      const int leader = __builtin_ctzll(pm);
+      const int f = __shfl(best, leader, 64);
+      const unsigned long long same = ballot(pending && best == f);
+      if (lane == leader) atomicAdd(&coverage[f], (uint32_t)__popcll(same));
+      if (best == f) pending = false;
+    }
+  }
 }
 
 hipError_t launch_face_stats(const ViewTable& vt, const tsr_params& p, const WsLayout& L, char* ws,
