@@ -3,9 +3,9 @@
 // leaving the corner, and its gradient with respect to the vertex positions.  A face with a
 // zero-length edge contributes 0 and gets no gradient (its angles are undefined).
 //
-// One thread per face; the per-face arithmetic runs in FP64 (a few dozen operations against
-// 36 bytes of positions read, so the kernel stays bound by memory) and the loss is summed per
-// workgroup in FP64.
+// One thread per face; the per-face arithmetic runs in FP64 with three square roots and three
+// divisions (FP64 division is a long instruction sequence, so the unit edges and the gradient
+// terms multiply by the reciprocal lengths), and the loss is summed per workgroup in FP64.
 #include "tsr_device.h"
 #include "tsr_internal.h"
 
@@ -45,11 +45,13 @@ __global__ __launch_bounds__(kEquiBlock) void k_equi(const float* __restrict__ p
     ok = ok && len[0] > 0.0 && len[1] > 0.0 && len[2] > 0.0;
     double g[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     if (ok) {
-      double h[3][3];            // unit edges
+      double il[3], h[3][3];     // reciprocal edge lengths (three divisions per face), unit edges
 #pragma unroll
-      for (int k = 0; k < 3; ++k)
+      for (int k = 0; k < 3; ++k) {
+        il[k] = 1.0 / len[k];
 #pragma unroll
-        for (int ax = 0; ax < 3; ++ax) h[k][ax] = e[k][ax] / len[k];
+        for (int ax = 0; ax < 3; ++ax) h[k][ax] = e[k][ax] * il[k];
+      }
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         // corner k: towards b = k+1 along +h[k] (length len[k]), towards c = k+2 along
@@ -66,8 +68,8 @@ __global__ __launch_bounds__(kEquiBlock) void k_equi(const float* __restrict__ p
         const double s = gscale * (c - 0.5);
 #pragma unroll
         for (int ax = 0; ax < 3; ++ax) {
-          const double db = s * (vh[ax] - c * uh[ax]) / len[k];
-          const double dc = s * (uh[ax] - c * vh[ax]) / len[kc];
+          const double db = s * (vh[ax] - c * uh[ax]) * il[k];
+          const double dc = s * (uh[ax] - c * vh[ax]) * il[kc];
           g[kb][ax] += db;
           g[kc][ax] += dc;
           g[k][ax] -= db + dc;
