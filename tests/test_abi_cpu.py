@@ -108,3 +108,81 @@ def test_generators_are_seeded_and_shaped():
     edge = (((e[:, :, 1] - e[:, :, 0]) ** 2).sum(axis=0)) ** 0.5
     assert 0.002 < edge.min() and edge.max() < 0.06
     assert (r.pos[0] > -0.03).all() and (r.pos[0] < 4.03).all()      # faces straddle the walls by < one radius
+
+
+# ---------------------------------------------------------------------------- training-energy entry points
+
+def _params(**kw):
+    par = _lib.TsrParams(1.0, 1e-6, 0.1, 1e-3, 0.8, 0.05, 0)
+    for k, v in kw.items():
+        setattr(par, k, v)
+    return par
+
+
+def test_dssim_scratch_size_and_validation():
+    lib = _lib.load()
+    b1, b2 = C.c_size_t(), C.c_size_t()
+    assert lib.tsr_dssim_scratch_size(_intr((64, 48)), 1, C.byref(b1)) == 0
+    assert lib.tsr_dssim_scratch_size(_intr((64, 48), (33, 17)), 2, C.byref(b2)) == 0
+    assert b1.value >= 52 * 64 * 48 and b2.value >= b1.value + 52 * 33 * 17
+    assert lib.tsr_dssim_scratch_size(_intr((0, 48)), 1, C.byref(b1)) == _lib.TSR_EINVAL
+    assert lib.tsr_dssim_scratch_size(_intr((64, 48)), 0, C.byref(b1)) == _lib.TSR_EINVAL
+    p = C.c_void_p(256)
+    need = C.c_size_t()
+    lib.tsr_dssim_scratch_size(_intr((64, 48)), 1, C.byref(need))
+    args = lambda color, loss, grad, scratch, nbytes: lib.tsr_dssim(_intr((64, 48)), 1, color, p, 1.0, 0, loss, grad,
+                                                                  scratch, nbytes, None)
+    assert args(None, p, p, p, need) == _lib.TSR_EINVAL                      # no colour
+    assert args(p, None, None, p, need) == _lib.TSR_EINVAL                   # no output
+    assert args(p, p, p, p, C.c_size_t(need.value - 1)) == _lib.TSR_EWORKSPACE
+    assert args(p, p, p, C.c_void_p(257), need) == _lib.TSR_EINVAL          # misaligned scratch
+
+
+def test_equilateral_scratch_size_and_validation():
+    lib = _lib.load()
+    b = C.c_size_t()
+    assert lib.tsr_equilateral_scratch_size(1000, C.byref(b)) == 0 and b.value >= 8 * 4
+    assert lib.tsr_equilateral_scratch_size(-1, C.byref(b)) == _lib.TSR_EINVAL
+    sc = _scene(1000)
+    p = C.c_void_p(256)
+    assert lib.tsr_equilateral(C.byref(sc), 1.0, 0, None, None, p, b, None) == _lib.TSR_EINVAL
+    assert lib.tsr_equilateral(C.byref(sc), 1.0, 0, p, p, p, C.c_size_t(8), None) == _lib.TSR_EWORKSPACE
+
+
+def test_face_stats_and_photometric_validation():
+    lib = _lib.load()
+    sc, intr, p = _scene(10), _intr((64, 48)), C.c_void_p(256)
+    big = C.c_size_t(1 << 30)
+    assert lib.tsr_face_stats(C.byref(sc), p, intr, 1, C.byref(_params()), p, big, None, None, None,
+                              None) == _lib.TSR_EINVAL
+    assert lib.tsr_render_train_photometric(C.byref(sc), p, intr, 1, C.byref(_params()), p, big, p, p, 0.2,
+                                            None, p, None, None, None, None, None, None, p, big,
+                                            None) == _lib.TSR_EINVAL        # the D-SSIM term reads colour
+    assert lib.tsr_render_train_photometric(C.byref(sc), p, intr, 1, C.byref(_params()), p, big, p, p, 0.2,
+                                            p, p, None, None, None, None, None, None, p, C.c_size_t(16),
+                                            None) == _lib.TSR_EWORKSPACE
+    assert lib.tsr_bin_and_sort(C.byref(sc), p, intr, 1, C.byref(_params(opacity_min=2)), p, big,
+                                None) == _lib.TSR_EINVAL
+
+
+def test_normal_entry_points_validation():
+    lib = _lib.load()
+    p = C.c_void_p(256)
+    assert lib.tsr_sensor_normals(None, _intr((64, 48)), 1, p, None) == _lib.TSR_EINVAL
+    assert lib.tsr_sensor_normals(p, _intr((64, 0)), 1, p, None) == _lib.TSR_EINVAL
+    zero_f = _intr((64, 48))
+    zero_f[0].fx = 0.0
+    assert lib.tsr_sensor_normals(p, zero_f, 1, p, None) == _lib.TSR_EINVAL
+    mesh = _lib.TsrScene(1, 1, 1, 1, 30, 10)                        # indexed faces
+    big = C.c_size_t(1 << 30)
+    assert lib.tsr_render_train_normal(C.byref(mesh), p, _intr((64, 48)), 1, C.byref(_params()), p, big, p, 0.05,
+                                       None, None, None, None, None, p, big, None) == _lib.TSR_EINVAL
+    sc = _scene(10)
+    need = C.c_size_t()
+    assert lib.tsr_normal_scratch_size(C.byref(sc), _intr((64, 48)), 1, C.byref(need)) == 0
+    assert need.value >= 24 * 30 + 32 * 64 * 48
+    assert lib.tsr_render_train_normal(C.byref(sc), p, _intr((64, 48)), 1, C.byref(_params()), p, big, None, 0.05,
+                                       None, None, None, None, None, p, need, None) == _lib.TSR_EINVAL
+    assert lib.tsr_render_train_normal(C.byref(sc), p, _intr((64, 48)), 1, C.byref(_params()), p, big, p, 0.05,
+                                       None, None, None, None, None, p, C.c_size_t(need.value - 1),
+                                       None) == _lib.TSR_EWORKSPACE
