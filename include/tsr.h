@@ -290,19 +290,20 @@ TSR_API int tsr_sensor_normals(const float *depth, const tsr_intrinsics *intr /*
  * (v1 - v0) x (v2 - v0) / |.| (vertex order, no flip) composited front to back like a colour
  * constant over the face (eq. 4 weights), rotated by R_CW, not renormalised.  target_normals:
  * N_bar packed like colour; a zero vector marks an invalid pixel (as tsr_sensor_normals
- * writes).  Outputs (each may be NULL): normal_map (packed like colour), loss [n_views],
- * grad_pos [3][N], grad_opa [N], grad_pose [n_views][6] -- all overwritten, gradients of the
- * sum of loss[v].  Runs its own binning, forward and backward with the face normals as vertex
+ * writes).  Outputs (each may be NULL): normal_map (packed like colour), loss [n_views]
+ * (overwritten), grad_pos [3][N], grad_opa [N], grad_pose [n_views][6]: the gradients of the
+ * sum of loss[v], overwriting the outputs (accumulate = 0) or added to them (accumulate != 0,
+ * so that the terms of the mapping energy can share one set of gradient buffers).  Runs its own binning, forward and backward with the face normals as vertex
  * colours: it needs no preceding tsr_bin_and_sort, and it leaves `ws` binned for that
  * normal-coloured scene, so bin again before rendering the scene's colours with `ws`.
- * scratch: device, 256-byte aligned, at least tsr_normal_scratch_size bytes (24 per vertex +
- * 32 per pixel + 1.3 KB).  Soups only (faces == NULL): TSR_EINVAL otherwise. */
+ * scratch: device, 256-byte aligned, at least tsr_normal_scratch_size bytes (40 per vertex +
+ * 32 per pixel + 2.1 KB).  Soups only (faces == NULL): TSR_EINVAL otherwise. */
 TSR_API int tsr_normal_scratch_size(const tsr_scene *scene, const tsr_intrinsics *intr /* (host)[n_views] */,
                             int n_views, size_t *bytes /* (host) out */);
 TSR_API int tsr_render_train_normal(const tsr_scene *scene, const float *poses, const tsr_intrinsics *intr,
                             int n_views, const tsr_params *params, void *ws, size_t ws_bytes,
                             const float *target_normals, float w_norm, float *normal_map, float *loss,
-                            float *grad_pos, float *grad_opa, float *grad_pose, void *scratch,
+                            float *grad_pos, float *grad_opa, float *grad_pose, int accumulate, void *scratch,
                             size_t scratch_bytes, void *stream);
 
 /* Synchronise `stream` and report device-side conditions of `ws`: TSR_ECAPACITY when the

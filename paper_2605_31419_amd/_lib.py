@@ -88,7 +88,7 @@ def load() -> C.CDLL:
     lib.tsr_face_stats.argtypes = [P, P, P, I, P, P, C.c_size_t, P, P, P, P]
     lib.tsr_sensor_normals.argtypes = [P, P, I, P, P]
     lib.tsr_normal_scratch_size.argtypes = [P, P, I, P]
-    lib.tsr_render_train_normal.argtypes = [P, P, P, I, P, P, C.c_size_t, P, C.c_float, P, P, P, P, P, P,
+    lib.tsr_render_train_normal.argtypes = [P, P, P, I, P, P, C.c_size_t, P, C.c_float, P, P, P, P, P, I, P,
                                             C.c_size_t, P]
     lib.tsr_check.argtypes = [P, P, P]
     lib.tsr_last_error.restype = C.c_char_p

@@ -478,7 +478,7 @@ int tsr_normal_scratch_size(const tsr_scene* scene, const tsr_intrinsics* intr, 
 int tsr_render_train_normal(const tsr_scene* scene, const float* poses, const tsr_intrinsics* intr, int n_views,
                             const tsr_params* params, void* ws, size_t ws_bytes, const float* target_normals,
                             float w_norm, float* normal_map, float* loss, float* grad_pos, float* grad_opa,
-                            float* grad_pose, void* scratch, size_t scratch_bytes, void* stream) {
+                            float* grad_pose, int accumulate, void* scratch, size_t scratch_bytes, void* stream) {
   ViewTable vt;
   WsLayout L;
   int rc = prepare(scene, poses, intr, n_views, params, ws, ws_bytes, &vt, &L);
@@ -492,7 +492,8 @@ int tsr_render_train_normal(const tsr_scene* scene, const float* poses, const ts
   if (reinterpret_cast<uintptr_t>(scratch) & 255) return fail(TSR_EINVAL, "scratch must be 256-byte aligned");
   hipError_t e = tsr::launch_train_normal(dev_scene(scene, params), poses, vt, *params, L, static_cast<char*>(ws),
                                           target_normals, w_norm, normal_map, loss, grad_pos, grad_opa, grad_pose,
-                                          static_cast<char*>(scratch), P, static_cast<hipStream_t>(stream));
+                                          accumulate != 0, static_cast<char*>(scratch), P,
+                                          static_cast<hipStream_t>(stream));
   return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_render_train_normal launch");
 }
 

@@ -186,14 +186,14 @@ hipError_t launch_face_stats(const ViewTable& vt, const tsr_params& p, const WsL
 
 // Normal supervision (Sec. 3.4): scratch layout of the normal-loss step (byte offsets).
 struct NormalScratch {
-  size_t col, gcol, nw, seed, depth, zeros, count, acc, total;
+  size_t col, gcol, nw, seed, depth, zeros, gpos, gopa, gpose, count, acc, total;
 };
 NormalScratch normal_scratch(int64_t n_vertices, int64_t n_pixels);
 hipError_t launch_sensor_normals(const ViewTable& vt, const float* depth, float* normals, hipStream_t st);
 hipError_t launch_train_normal(const tsr_scene_dev& sc, const float* poses, const ViewTable& vt, const tsr_params& p,
                                const WsLayout& L, char* ws, const float* target, float w_norm, float* normal_map,
-                               float* loss, float* grad_pos, float* grad_opa, float* grad_pose, char* scratch,
-                               int64_t n_pixels, hipStream_t st);
+                               float* loss, float* grad_pos, float* grad_opa, float* grad_pose, bool accumulate,
+                               char* scratch, int64_t n_pixels, hipStream_t st);
 
 hipError_t launch_pose_step(float* poses, const float* grad_pose, int n_views, float lr_t, float lr_r,
                             hipStream_t st);

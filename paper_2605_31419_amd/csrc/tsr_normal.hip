@@ -232,17 +232,34 @@ NormalScratch normal_scratch(int64_t n_vertices, int64_t n_pixels) {
   z.seed = up(z.nw + sizeof(float) * 3 * (size_t)n_pixels);
   z.depth = up(z.seed + sizeof(float) * 3 * (size_t)n_pixels);
   z.zeros = up(z.depth + sizeof(float) * (size_t)n_pixels);
-  z.count = up(z.zeros + sizeof(float) * (size_t)n_pixels);
+  z.gpos = up(z.zeros + sizeof(float) * (size_t)n_pixels);
+  z.gopa = up(z.gpos + sizeof(float) * 3 * (size_t)n_vertices);
+  z.gpose = up(z.gopa + sizeof(float) * (size_t)n_vertices);
+  z.count = up(z.gpose + sizeof(float) * 6 * TSR_MAX_VIEWS);
   z.acc = up(z.count + sizeof(uint32_t) * TSR_MAX_VIEWS);
   z.total = up(z.acc + sizeof(double) * 4 * TSR_MAX_VIEWS);
   return z;
 }
 
+__global__ void k_add_f32(float* __restrict__ dst, const float* __restrict__ src, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] += src[i];
+}
+
 hipError_t launch_train_normal(const tsr_scene_dev& sc, const float* poses, const ViewTable& vt, const tsr_params& p,
                                const WsLayout& L, char* ws, const float* target, float w_norm, float* normal_map,
-                               float* loss, float* grad_pos, float* grad_opa, float* grad_pose, char* scratch,
-                               int64_t n_pixels, hipStream_t st) {
+                               float* loss, float* grad_pos, float* grad_opa, float* grad_pose, bool accumulate,
+                               char* scratch, int64_t n_pixels, hipStream_t st) {
   const NormalScratch z = normal_scratch(sc.n_vertices, n_pixels);
+  // accumulating: the gradients go to scratch first and are added to the caller's at the end
+  float* const out_pos = grad_pos;
+  float* const out_opa = grad_opa;
+  float* const out_pose = grad_pose;
+  if (accumulate) {
+    if (grad_pos) grad_pos = reinterpret_cast<float*>(scratch + z.gpos);
+    if (grad_opa) grad_opa = reinterpret_cast<float*>(scratch + z.gopa);
+    if (grad_pose) grad_pose = reinterpret_cast<float*>(scratch + z.gpose);
+  }
   float* col = reinterpret_cast<float*>(scratch + z.col);
   float* gcol = reinterpret_cast<float*>(scratch + z.gcol);
   float* nw = reinterpret_cast<float*>(scratch + z.nw);
@@ -276,6 +293,13 @@ hipError_t launch_train_normal(const tsr_scene_dev& sc, const float* poses, cons
     TSR_LAUNCH("normal_chain", k_normal_chain, dim3(fb), dim3(256), 0, st, sc.pos, N, M, gcol, grad_pos);
   TSR_LAUNCH("normal_finish", k_normal_finish, dim3(1), dim3(64), 0, st, vt.n_views, count, acc, w_norm, loss,
              grad_pose);
+  if (accumulate) {
+    const unsigned vb = (unsigned)std::min<int64_t>((3 * N + 255) / 256, 4096);
+    if (out_pos && N > 0) TSR_LAUNCH("add_grads", k_add_f32, dim3(vb), dim3(256), 0, st, out_pos, grad_pos, 3 * N);
+    if (out_opa && N > 0) TSR_LAUNCH("add_grads", k_add_f32, dim3(vb), dim3(256), 0, st, out_opa, grad_opa, N);
+    if (out_pose)
+      TSR_LAUNCH("add_grads", k_add_f32, dim3(1), dim3(256), 0, st, out_pose, grad_pose, (int64_t)6 * vt.n_views);
+  }
   return hipGetLastError();
 }
 

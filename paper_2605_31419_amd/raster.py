@@ -238,23 +238,27 @@ class Rasterizer:
         return area, cov, vis
 
     def train_normal(self, poses: torch.Tensor, target_normals: torch.Tensor, w_norm: float = 0.05,
-                     normal_map=None, loss=None, out=None, stream=None):
+                     normal_map=None, loss=None, out=None, accumulate: bool = False, stream=None):
         """Normal loss of mapping (``tsr_render_train_normal``): bins, renders the normal map
         and back-propagates w_norm * mean(1 - N . N_bar); returns (grad_pos, grad_opa,
-        grad_pose).  Leaves the workspace binned for the normal-coloured soup."""
+        grad_pose), written or (``accumulate``) added into ``out``.  Leaves the workspace binned
+        for the normal-coloured soup."""
         if getattr(self, "_nscratch", None) is None:
             nb = C.c_size_t()
             check(self.lib.tsr_normal_scratch_size(C.byref(self._cscene), self._cintr, self.n_views, C.byref(nb)),
                   "tsr_normal_scratch_size")
             self._nscratch = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
         if out is None:
+            if accumulate:
+                raise ValueError("accumulate needs the gradient buffers")
             gp, _, go, gpose = self.grad_buffers((True, False, True, True))
         else:
             gp, go, gpose = out
         sc = self._nscratch
         check(self.lib.tsr_render_train_normal(*self._args(poses), _ptr(target_normals), float(w_norm),
                                                _ptr(normal_map), _ptr(loss), _ptr(gp), _ptr(go), _ptr(gpose),
-                                               _ptr(sc), C.c_size_t(sc.numel()), _stream(stream)),
+                                               1 if accumulate else 0, _ptr(sc), C.c_size_t(sc.numel()),
+                                               _stream(stream)),
               "tsr_render_train_normal")
         return gp, go, gpose
 

@@ -7,7 +7,11 @@ autotuner picked for this workload (persistent workgroups pulling tiles from a d
 longest tile lists first, or one workgroup per tile).  Face gradients are summed across views
 in the per-face accumulators; each view keeps its own pose gradient.  With ``w_ssim > 0`` the
 step uses the full loss with the D-SSIM term (``tsr_render_train_photometric``; forward and
-backward are then separate passes and the tile schedule is the default one).
+backward are then separate passes and the tile schedule is the default one).  ``w_equi`` adds
+the equilateral regulariser (eq. 14) and ``w_norm`` the normal loss against per-view target
+normals, both accumulated on the device into the same gradient buffers, giving the mapping
+energy E_pho + lambda_dep E_dep + lambda_norm E_norm + lambda_equi E_equi (the normal loss runs
+on a second workspace, since it bins the soup with its face normals as colours).
 """
 from __future__ import annotations
 
@@ -20,7 +24,8 @@ from . import autotune, raster
 
 class MappingWindow:
     def __init__(self, scene: raster.DeviceScene, intrs: Sequence, params: Optional[raster.Params] = None,
-                 schedule=None, table: Optional[str] = None, w_ssim: float = 0.0):
+                 schedule=None, table: Optional[str] = None, w_ssim: float = 0.0, w_equi: float = 0.0,
+                 w_norm: float = 0.0):
         self.rast = raster.Rasterizer(scene, intrs, params or raster.Params())
         self.n_views = len(intrs)
         self.intrs = list(intrs)
@@ -32,10 +37,17 @@ class MappingWindow:
         self.loss = torch.zeros(self.n_views, device="cuda")
         self.grads = self.rast.grad_buffers()
         self.w_ssim = float(w_ssim)
+        self.w_equi = float(w_equi)
+        self.w_norm = float(w_norm)
+        self.equi_loss = torch.zeros(1, device="cuda")
+        self.norm_loss = torch.zeros(self.n_views, device="cuda")
+        self.nrast = raster.Rasterizer(scene, intrs, params or raster.Params()) if self.w_norm > 0 else None
 
     def prepare(self, poses: torch.Tensor, slack: float = 1.5) -> int:
         """Size the workspace and pick the schedule (table lookup) for these poses."""
         k = self.rast.fit(poses, slack)
+        if self.nrast is not None:
+            self.nrast.fit(poses, slack)
         if self._schedule is None:
             self._schedule = autotune.lookup(self.intrs, k, self._table)
         self.rast.schedule = self._schedule
@@ -46,11 +58,22 @@ class MappingWindow:
         return self._schedule
 
     def step(self, poses: torch.Tensor, target_color: torch.Tensor, target_depth: torch.Tensor,
-             check_capacity: bool = False):
+             check_capacity: bool = False, target_normals: Optional[torch.Tensor] = None):
         """One window iteration; returns (grad_pos, grad_col, grad_opa, grad_pose[V*6])."""
         self.rast.bin_and_sort(poses, check_capacity=check_capacity)
         if self.w_ssim > 0:
-            return self.rast.train_photometric(poses, target_color, target_depth, w_ssim=self.w_ssim,
-                                               color=self.color, depth=self.depth, loss=self.loss, out=self.grads)
+            self.rast.train_photometric(poses, target_color, target_depth, w_ssim=self.w_ssim,
+                                        color=self.color, depth=self.depth, loss=self.loss, out=self.grads)
+        else:
+            self._train_l1(poses, target_color, target_depth)
+        gp, _, go, gpose = self.grads
+        if self.w_equi > 0:
+            raster.equilateral(self.rast.scene, weight=self.w_equi, grad=gp, accumulate=True, loss=self.equi_loss)
+        if self.nrast is not None and target_normals is not None:
+            self.nrast.train_normal(poses, target_normals, w_norm=self.w_norm, loss=self.norm_loss,
+                                    out=(gp, go, gpose), accumulate=True)
+        return self.grads
+
+    def _train_l1(self, poses, target_color, target_depth):
         return self.rast.train_l1(poses, target_color, target_depth, color=self.color, depth=self.depth,
                                   loss=self.loss, out=self.grads)

@@ -176,13 +176,13 @@ def test_normal_entry_points_validation():
     mesh = _lib.TsrScene(1, 1, 1, 1, 30, 10)                        # indexed faces
     big = C.c_size_t(1 << 30)
     assert lib.tsr_render_train_normal(C.byref(mesh), p, _intr((64, 48)), 1, C.byref(_params()), p, big, p, 0.05,
-                                       None, None, None, None, None, p, big, None) == _lib.TSR_EINVAL
+                                       None, None, None, None, None, 0, p, big, None) == _lib.TSR_EINVAL
     sc = _scene(10)
     need = C.c_size_t()
     assert lib.tsr_normal_scratch_size(C.byref(sc), _intr((64, 48)), 1, C.byref(need)) == 0
-    assert need.value >= 24 * 30 + 32 * 64 * 48
+    assert need.value >= 40 * 30 + 32 * 64 * 48
     assert lib.tsr_render_train_normal(C.byref(sc), p, _intr((64, 48)), 1, C.byref(_params()), p, big, None, 0.05,
-                                       None, None, None, None, None, p, need, None) == _lib.TSR_EINVAL
+                                       None, None, None, None, None, 0, p, need, None) == _lib.TSR_EINVAL
     assert lib.tsr_render_train_normal(C.byref(sc), p, _intr((64, 48)), 1, C.byref(_params()), p, big, p, 0.05,
-                                       None, None, None, None, None, p, C.c_size_t(need.value - 1),
+                                       None, None, None, None, None, 1, p, C.c_size_t(need.value - 1),
                                        None) == _lib.TSR_EWORKSPACE

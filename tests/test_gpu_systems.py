@@ -238,6 +238,36 @@ def test_window_with_dssim_equals_sum_of_single_views():
         assert ok, msg
 
 
+def test_window_mapping_energy_is_the_sum_of_its_terms():
+    """The window step with D-SSIM, E_equi and E_norm (weights 0.2, 1.2, 0.05; target normals
+    from the target depth) equals the photometric step plus the separately computed
+    equilateral and normal-loss gradients."""
+    sc, dev, poses, intrs, tc, td = _window_inputs(n_views=3, n_faces=30_000)
+    p = raster.poses_tensor(poses)
+    tn = raster.sensor_normals(td, intrs)
+    win = MappingWindow(dev, intrs, w_ssim=0.2, w_equi=1.2, w_norm=0.05)
+    win.prepare(p)
+    got = [x.clone() for x in win.step(p, tc, td, check_capacity=True, target_normals=tn)]
+    torch.cuda.synchronize()
+    base = MappingWindow(dev, intrs, w_ssim=0.2)
+    base.prepare(p)
+    b = [x.clone() for x in base.step(p, tc, td, check_capacity=True)]
+    le, ge = raster.equilateral(dev, weight=1.2)
+    nr = raster.Rasterizer(dev, intrs)
+    nr.fit(p)
+    ln = torch.zeros(len(intrs), device="cuda")
+    gnp, gno, gnpose = nr.train_normal(p, tn, w_norm=0.05, loss=ln)
+    torch.cuda.synchronize()
+    want = [b[0] + ge.reshape(-1) + gnp, b[1], b[2] + gno, b[3] + gnpose]
+    for nm, a, w in zip(["pos", "col", "opa", "pose"], got, want):
+        ok, msg, _ = grad_close(a.cpu().numpy(), w.cpu().numpy(), name=nm)
+        _say("  " + msg)
+        assert ok, msg
+    np.testing.assert_allclose(win.equi_loss.cpu().numpy(), le.cpu().numpy(), rtol=1e-6)
+    np.testing.assert_allclose(win.norm_loss.cpu().numpy(), ln.cpu().numpy(), rtol=1e-5)
+    _say(f"  E_equi {float(le):.5f}, E_norm per view {ln.cpu().numpy()}")
+
+
 # ---------------------------------------------------------------------------- serving
 
 def test_served_results_equal_alone_results():
