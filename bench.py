@@ -499,6 +499,23 @@ def main():
                    "K": Kb, "visible": mvb, "max_list": maxb, "mean_list": meanb,
                    "kernels_ms": {k: round(v, 4) for k, v in ktb.items()}, "schedule": btuned}
         log(f"[bench] batched {args.views} views: {msb:.3f} ms -> {batched['mpix_s']:.1f} Mpix/s")
+        # the whole mapping energy over the same window: D-SSIM photometric term and depth L1,
+        # E_equi and E_norm against the sensor normals of the target depth
+        from paper_2605_31419_amd.window import MappingWindow
+        bintr = [w.intr[0]] * args.views
+        win = MappingWindow(dev, bintr, w_ssim=0.2, w_equi=1.2, w_norm=0.05)
+        win.prepare(bcase.poses)
+        tnorm = raster.sensor_normals(bcase.td, bintr)
+        map_step = lambda: win.step(bcase.poses, bcase.tc, bcase.td, target_normals=tnorm)
+        msm = time_steps(map_step, max(5, args.steps // 4), args.warmup)
+        from paper_2605_31419_amd import _lib
+        _lib.check(win.rast.lib.tsr_check(raster._ptr(win.rast.ws), raster._stream(), None), "tsr_check")
+        ktm, _ = kernel_times(map_step, max(2, args.profile_steps // 2))
+        batched["mapping_energy"] = {"weights": {"ssim": 0.2, "depth": 0.05, "equi": 1.2, "norm": 0.05},
+                                     "ms_per_step": msm, "mpix_s": bcase.pixels / (msm * 1e-3) / 1e6,
+                                     "kernels_ms": {k: round(v, 4) for k, v in ktm.items()}}
+        log(f"[bench] mapping energy over {args.views} views: {msm:.3f} ms")
+        del win, tnorm
         del bcase
         torch.cuda.empty_cache()
 

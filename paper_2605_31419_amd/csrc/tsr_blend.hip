@@ -1113,7 +1113,9 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
   const int64_t nf = (int64_t)vt.n_views * vt.n_faces;
   int* order = nullptr;
   int* queue = nullptr;
-  if (fused_train && sched.order) order = reinterpret_cast<int*>(ws + L.order);
+  // the separate backward always walks longest-first; the set-up builds that order above
+  // kOrderInSortMax tiles (below, the binning has built it)
+  if (!fused_train || sched.order) order = reinterpret_cast<int*>(ws + L.order);
   if (fused_train && sched.persistent) queue = reinterpret_cast<int*>(ws + L.hdr_queue);
   {
     const int64_t rows16 = nf * (int64_t)((kGradDwords * sizeof(acc_t)) / 16);
@@ -1126,8 +1128,8 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
   const int sm = sigma_mode(p.sigma);
   if (!fused_train) {
     const dim3 grid(tile_grid(vt.n_tiles));
-    // longest-first tile order, built with the binning up to kOrderInSortMax tiles
-    const int* border = vt.n_tiles <= kOrderInSortMax ? reinterpret_cast<const int*>(ws + L.order) : nullptr;
+    // longest-first tile order (built with the binning or by the set-up above)
+    const int* border = order;
 #define TSR_BWD(S) TSR_LAUNCH("blend_bwd", k_blend_bwd<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, n_last, t_last, gcolor, gdepth, gtrans, grad_acc, border)
     switch (sm) { case 1: TSR_BWD(1); break; case 2: TSR_BWD(2); break; case 3: TSR_BWD(3); break; default: TSR_BWD(0); }
 #undef TSR_BWD

@@ -213,8 +213,12 @@ def test_tracking_graph_with_dssim_matches_eager():
     assert sh[1] < sh[0]
 
 
-def test_window_with_dssim_equals_sum_of_single_views():
-    sc, dev, poses, intrs, tc, td = _window_inputs(n_views=3, n_faces=40_000)
+@pytest.mark.parametrize("w,h", [(320, 240), (1200, 680)], ids=["900_tiles", "9675_tiles"])
+def test_window_with_dssim_equals_sum_of_single_views(w, h):
+    """The separate forward and backward of the D-SSIM step walk the tiles longest-first: with
+    the order built by the binning (900 tiles, and each single view) or, above 8192 tiles, by
+    the backward set-up (9675 tiles)."""
+    sc, dev, poses, intrs, tc, td = _window_inputs(n_views=3, n_faces=40_000, w=w, h=h)
     win = MappingWindow(dev, intrs, w_ssim=0.2)
     p = raster.poses_tensor(poses)
     win.prepare(p)
