@@ -87,10 +87,19 @@ __device__ inline void build_tile_order(const uint32_t* __restrict__ ranges, int
   const int nb = blockDim.x;
   for (int b = threadIdx.x; b < kOrderBuckets; b += nb) hist[b] = 0u;
   __syncthreads();
-  // bucket kOrderBuckets - 1 - length: an ascending scan then places long lists first
-  for (int t = threadIdx.x; t < n_tiles; t += nb) {
-    const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
-    atomicAdd(&hist[kOrderBuckets - 1 - (int)min(len, (uint32_t)kOrderBuckets - 1u)], 1u);
+  // bucket kOrderBuckets - 1 - length: an ascending scan then places long lists first.  Each
+  // thread loads four tiles' ranges before their LDS atomics, so the loads overlap.
+  constexpr int kU = 4;
+  for (int t0 = threadIdx.x; t0 < n_tiles; t0 += kU * nb) {
+    uint32_t len[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int t = t0 + u * nb;
+      len[u] = t < n_tiles ? ranges[2 * t + 1] - ranges[2 * t] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (t0 + u * nb < n_tiles) atomicAdd(&hist[kOrderBuckets - 1 - (int)min(len[u], (uint32_t)kOrderBuckets - 1u)], 1u);
   }
   __syncthreads();
   const int per = kOrderBuckets / nb;
@@ -103,10 +112,21 @@ __device__ inline void build_tile_order(const uint32_t* __restrict__ ranges, int
     run += h;
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < n_tiles; t += nb) {
-    const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
-    const uint32_t pos = atomicAdd(&hist[kOrderBuckets - 1 - (int)min(len, (uint32_t)kOrderBuckets - 1u)], 1u);
-    order[pos] = t;
+  for (int t0 = threadIdx.x; t0 < n_tiles; t0 += kU * nb) {
+    uint32_t len[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int t = t0 + u * nb;
+      len[u] = t < n_tiles ? ranges[2 * t + 1] - ranges[2 * t] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int t = t0 + u * nb;
+      if (t < n_tiles) {
+        const uint32_t pos = atomicAdd(&hist[kOrderBuckets - 1 - (int)min(len[u], (uint32_t)kOrderBuckets - 1u)], 1u);
+        order[pos] = t;
+      }
+    }
   }
 }
 
