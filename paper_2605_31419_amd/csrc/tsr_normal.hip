@@ -270,6 +270,14 @@ hipError_t launch_train_normal(const tsr_scene_dev& sc, const float* poses, cons
   double* acc = reinterpret_cast<double*>(scratch + z.acc);
   const int64_t M = sc.n_faces, N = sc.n_vertices;
   const unsigned fb = (unsigned)((M + 255) / 256);
+  if (accumulate && N > 3 * M) {
+    // the backward writes the vertices of the faces only: clear the rest of the staged
+    // gradients so that adding them leaves the caller's extra vertices unchanged
+    if (grad_pos)
+      TSR_LAUNCH("zero_words", k_zero_words, dim3(1024), dim3(256), 0, st, reinterpret_cast<uint32_t*>(grad_pos), 3 * N);
+    if (grad_opa)
+      TSR_LAUNCH("zero_words", k_zero_words, dim3(1024), dim3(256), 0, st, reinterpret_cast<uint32_t*>(grad_opa), N);
+  }
   // clear the gradient-free depth seed, the valid counts and the FP64 sums
   TSR_LAUNCH("zero_words", k_zero_words, dim3(1024), dim3(256), 0, st, reinterpret_cast<uint32_t*>(zeros), n_pixels);
   TSR_LAUNCH("zero_words", k_zero_words, dim3(1), dim3(256), 0, st, count,

@@ -131,3 +131,34 @@ def test_indexed_meshes_are_refused():
     tgt = torch.zeros(3 * intr.width * intr.height, device="cuda")
     with pytest.raises(RuntimeError):
         rast.train_normal(p, tgt)
+
+
+def test_accumulate_adds_and_leaves_extra_vertices_alone():
+    """accumulate adds the gradients to the buffers; a soup's vertices past 3M (no face uses
+    them) keep their values."""
+    sc, intr = tiny_scene(37, n_faces=30, w=48, h=36, f=36.0)
+    extra = 5
+    g = np.random.default_rng(37)
+    pos = np.concatenate([sc.pos, g.normal(size=(3, extra)).astype(np.float32)], axis=1)
+    col = np.concatenate([sc.col, np.zeros((3, extra), np.float32)], axis=1)
+    opa = np.concatenate([sc.opa, np.full(extra, 0.5, np.float32)])
+    dev = raster.DeviceScene(torch.as_tensor(pos, device="cuda"), torch.as_tensor(col, device="cuda"),
+                             torch.as_tensor(opa, device="cuda"))
+    dev.n_faces = 30
+    rast = raster.Rasterizer(dev, [intr])
+    p = raster.poses_tensor([IDENTITY])
+    rast.fit(p)
+    nb, _ = _targets(38, intr.width * intr.height)
+    t = torch.as_tensor(nb.reshape(-1), device="cuda")
+    ref = [x.clone() for x in rast.train_normal(p, t, w_norm=0.05)]
+    N = pos.shape[1]
+    gp = torch.ones(3 * N, device="cuda")
+    go = torch.ones(N, device="cuda")
+    gpose = torch.ones(6, device="cuda")
+    rast.train_normal(p, t, w_norm=0.05, out=(gp, go, gpose), accumulate=True)
+    torch.cuda.synchronize()
+    gpn, gon = gp.cpu().numpy().reshape(3, N), go.cpu().numpy()
+    assert np.all(gpn[:, 90:] == 1.0) and np.all(gon[90:] == 1.0)
+    np.testing.assert_allclose(gpn[:, :90], 1.0 + ref[0].cpu().numpy().reshape(3, N)[:, :90], rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(gon[:90], 1.0 + ref[1].cpu().numpy()[:90], rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(gpose.cpu().numpy(), 1.0 + ref[2].cpu().numpy(), rtol=1e-6, atol=1e-6)
