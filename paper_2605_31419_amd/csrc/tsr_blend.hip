@@ -431,7 +431,8 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(ViewTable vt, const float*
   backward_walk<SM, false>(c, records, pairs, sigma, last, Tb, pg, srec[wv], sface[wv], nullptr, grad_acc);
 }
 
-// Fused training kernel: forward walk, L1 seeds of eqs. 8-10 (D-SSIM omitted), backward
+// Fused training kernel: forward walk, L1 seeds of eqs. 8-10 (the D-SSIM term needs whole
+// images and runs in tsr_ssim.hip between a separate forward and backward), backward
 // walk, without leaving the workgroup.  Also writes the loss of each (tile, quadrant).
 template <int SM>
 __global__ __launch_bounds__(kBlock) void k_train_fused(ViewTable vt, const float* __restrict__ records,
