@@ -890,7 +890,6 @@ __global__ __launch_bounds__(256) void k_vertex_gather(tsr_scene_dev sc, ViewTab
 __global__ __launch_bounds__(256) void k_prep_bwd(ViewTable vt, const uint32_t* __restrict__ vis_total,
                                                   const uint32_t* __restrict__ vis_dense, acc_t* __restrict__ grad_acc,
                                                   double* __restrict__ pose_acc, double* __restrict__ loss_acc,
-                                                  const uint32_t* __restrict__ ranges, int* __restrict__ order,
                                                   int* __restrict__ queue) {
   constexpr int kVec = (int)(kGradDwords * sizeof(acc_t)) / 16;      // 16-byte stores per row
   const int64_t nf = (int64_t)vt.n_views * vt.n_faces;
@@ -903,12 +902,26 @@ __global__ __launch_bounds__(256) void k_prep_bwd(ViewTable vt, const uint32_t* 
     for (int k = threadIdx.x; k < kSumCopies * 6 * vt.n_views; k += blockDim.x) pose_acc[k] = 0.0;
     for (int k = threadIdx.x; k < kSumCopies * vt.n_views; k += blockDim.x) loss_acc[k] = 0.0;
     if (queue && threadIdx.x == 0) *queue = 0;
-    if (order) {
-      __shared__ uint32_t hist[kOrderBuckets];
-      __shared__ unsigned long long wsum[16];
-      build_tile_order(ranges, vt.n_tiles, order, hist, wsum);
-    }
   }
+}
+
+// Longest-first tile order of a binning with more tiles than the binning orders itself: one
+// workgroup of 1,024 threads (a quarter of the per-thread iterations of a 256-thread one).
+__global__ __launch_bounds__(1024) void k_build_order(const uint32_t* __restrict__ ranges, int n_tiles,
+                                                      int* __restrict__ order) {
+  __shared__ uint32_t hist[kOrderBuckets];
+  __shared__ unsigned long long wsum[16];
+  build_tile_order(ranges, n_tiles, order, hist, wsum);
+}
+
+// The longest-first order of the binning held in `ws`: built with the binning up to
+// kOrderInSortMax tiles, else here (enqueued on `st` before the kernels that read it).
+static const int* tile_order(const ViewTable& vt, const WsLayout& L, char* ws, hipStream_t st) {
+  int* order = reinterpret_cast<int*>(ws + L.order);
+  if (vt.n_tiles > kOrderInSortMax)
+    TSR_LAUNCH("tile_order", k_build_order, dim3(1), dim3(1024), 0, st,
+               reinterpret_cast<const uint32_t*>(ws + L.ranges), vt.n_tiles, order);
+  return order;
 }
 
 __global__ void k_fill_f32(float* __restrict__ p, int64_t n) {
@@ -1056,8 +1069,7 @@ hipError_t launch_face_stats(const ViewTable& vt, const tsr_params& p, const WsL
   const float* records = reinterpret_cast<const float*>(ws + L.records);
   const uint64_t* pairs = reinterpret_cast<const uint64_t*>(ws + L.pairs);
   const uint32_t* ranges = reinterpret_cast<const uint32_t*>(ws + L.ranges);
-  // longest-first tile order, built with the binning up to kOrderInSortMax tiles
-  const int* border = vt.n_tiles <= kOrderInSortMax ? reinterpret_cast<const int*>(ws + L.order) : nullptr;
+  const int* border = tile_order(vt, L, ws, st);     // longest lists first
   const int64_t nf = (int64_t)vt.n_views * vt.n_faces;
   const unsigned fg = (unsigned)std::min<int64_t>((nf + 255) / 256, 4096);
   if (nf > 0) {
@@ -1079,8 +1091,7 @@ hipError_t launch_forward(const ViewTable& vt, const tsr_params& p, const WsLayo
   const float* records = reinterpret_cast<const float*>(ws + L.records);
   const uint64_t* pairs = reinterpret_cast<const uint64_t*>(ws + L.pairs);
   const uint32_t* ranges = reinterpret_cast<const uint32_t*>(ws + L.ranges);
-  // longest-first tile order, built with the binning up to kOrderInSortMax tiles
-  const int* border = vt.n_tiles <= kOrderInSortMax ? reinterpret_cast<const int*>(ws + L.order) : nullptr;
+  const int* border = tile_order(vt, L, ws, st);     // longest lists first
   int* n_last = reinterpret_cast<int*>(ws + L.n_last);
   float* t_last = reinterpret_cast<float*>(ws + L.t_last);
   const dim3 grid(tile_grid(vt.n_tiles)), block(kBlock);
@@ -1112,24 +1123,21 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
   float* loss_part = reinterpret_cast<float*>(ws + L.loss_part);
   double* loss_acc = reinterpret_cast<double*>(ws + L.loss_acc);
   const int64_t nf = (int64_t)vt.n_views * vt.n_faces;
-  int* order = nullptr;
+  const int* order = nullptr;
   int* queue = nullptr;
-  // the separate backward always walks longest-first; the set-up builds that order above
-  // kOrderInSortMax tiles (below, the binning has built it)
-  if (!fused_train || sched.order) order = reinterpret_cast<int*>(ws + L.order);
+  // the separate backward always walks longest-first; the fused kernel when its schedule says so
+  if (!fused_train || sched.order) order = tile_order(vt, L, ws, st);
   if (fused_train && sched.persistent) queue = reinterpret_cast<int*>(ws + L.hdr_queue);
   {
     const int64_t rows16 = nf * (int64_t)((kGradDwords * sizeof(acc_t)) / 16);
     const unsigned g = (unsigned)std::min<int64_t>(std::max<int64_t>(grid_for(rows16, 256), 1), 2048);
-    int* order_prep = vt.n_tiles > kOrderInSortMax ? order : nullptr;   // else built with the binning
     TSR_LAUNCH("prep_bwd", k_prep_bwd, dim3(g), dim3(256), 0, st, vt, vis_total, vis_dense, grad_acc, pose_acc,
-               loss_acc, ranges, order_prep, queue);
+               loss_acc, queue);
   }
   const dim3 block(kBlock);
   const int sm = sigma_mode(p.sigma);
   if (!fused_train) {
     const dim3 grid(tile_grid(vt.n_tiles));
-    // longest-first tile order (built with the binning or by the set-up above)
     const int* border = order;
 #define TSR_BWD(S) TSR_LAUNCH("blend_bwd", k_blend_bwd<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, n_last, t_last, gcolor, gdepth, gtrans, grad_acc, border)
     switch (sm) { case 1: TSR_BWD(1); break; case 2: TSR_BWD(2); break; case 3: TSR_BWD(3); break; default: TSR_BWD(0); }
