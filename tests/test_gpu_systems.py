@@ -109,7 +109,7 @@ def test_window_batched_equals_sum_of_single_views():
 @pytest.mark.parametrize("w,h", [(320, 240), (1200, 680)], ids=["900_tiles", "9675_tiles"])
 def test_every_schedule_gives_the_same_step(w, h):
     """Every schedule reproduces the one-workgroup-per-tile step.  The longest-first tile
-    order is built with the binning for the 900-tile window and by the backward set-up for the
+    order is built with the binning for the 900-tile window and by its own kernel for the
     9675-tile one (above 8192 tiles)."""
     sc, dev, poses, intrs, tc, td = _window_inputs(n_views=3, n_faces=40_000, w=w, h=h)
     p = raster.poses_tensor(poses)
@@ -217,7 +217,7 @@ def test_tracking_graph_with_dssim_matches_eager():
 def test_window_with_dssim_equals_sum_of_single_views(w, h):
     """The separate forward and backward of the D-SSIM step walk the tiles longest-first: with
     the order built by the binning (900 tiles, and each single view) or, above 8192 tiles, by
-    the backward set-up (9675 tiles)."""
+    its own kernel (9675 tiles)."""
     sc, dev, poses, intrs, tc, td = _window_inputs(n_views=3, n_faces=40_000, w=w, h=h)
     win = MappingWindow(dev, intrs, w_ssim=0.2)
     p = raster.poses_tensor(poses)
