@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 256 MiB device-to-device copy (counter calibration in profiler runs)")
     ap.add_argument("--only-single", action="store_true", help="skip the unfused and batched legs")
+    ap.add_argument("--only-photometric", action="store_true",
+                    help="after the headline step, time only the full photometric step (D-SSIM term)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile schedule (no autotuning)")
     ap.add_argument("--schedule", default=None,
                     help="fixed tile schedule 'persistent,order,grid' for the single view (no autotuning)")
@@ -441,17 +443,27 @@ def main():
                           "ms_per_step": ms, "kernels_ms": ktimes, "copy_gbs": copy_gbs, "schedule": tuned}), flush=True)
         return
 
+    # full photometric step of eqs. 8 and 10: forward, L1 + D-SSIM + depth seeds, backward
+    def step_photo():
+        single.rast.bin_and_sort(single.poses, check_capacity=False)
+        single.rast.train_photometric(single.poses, single.tc, single.td, w_ssim=0.2, color=single.color,
+                                      depth=single.depth, trans=single.trans, loss=single.loss, out=single.grads)
+
+    if args.only_photometric:
+        msp = time_steps(step_photo, args.steps, args.warmup)
+        single.check()
+        ktp, _ = kernel_times(step_photo, args.profile_steps)
+        print(json.dumps({"metric": "photometric step (L1 + D-SSIM + depth) Mpix/s, single view",
+                          "value": single.pixels / (msp * 1e-3) / 1e6, "unit": "Mpix/s", "ms_per_step": msp,
+                          "photometric": photometric_summary(single.pixels, msp, ktp)}), flush=True)
+        return
+
     # unfused path (forward, then backward from external per-pixel seeds)
     gc = torch.full((3 * single.pixels,), 1e-6, device="cuda")
     gd = torch.full((single.pixels,), 1e-7, device="cuda")
     ms_unf = time_steps(lambda: single.step_unfused(gc, gd), args.steps, args.warmup)
     kt_unf, _ = kernel_times(lambda: single.step_unfused(gc, gd), args.profile_steps)
 
-    # full photometric step of eqs. 8 and 10: forward, L1 + D-SSIM + depth seeds, backward
-    def step_photo():
-        single.rast.bin_and_sort(single.poses, check_capacity=False)
-        single.rast.train_photometric(single.poses, single.tc, single.td, w_ssim=0.2, color=single.color,
-                                      depth=single.depth, trans=single.trans, loss=single.loss, out=single.grads)
     ms_photo = time_steps(step_photo, args.steps, args.warmup)
     single.check()
     kt_photo, _ = kernel_times(step_photo, args.profile_steps)
