@@ -95,3 +95,12 @@ def test_loss_only_leaves_no_gradient_written():
 def test_full_frame_1200x680():
     pairs, loss, grad, _ = _run([(1200, 680)], seed=600, weight=0.2)
     _check(pairs, loss, grad, weight=0.2)
+
+
+def test_the_maximum_of_32_views():
+    """32 views of assorted small sizes (incl. 1 x 1, one row, one column) in one call: every
+    view's loss and gradient against the reference."""
+    g = np.random.default_rng(700)
+    sizes = [(1, 1), (40, 1), (1, 30)] + [(int(w), int(h)) for w, h in g.integers(2, 48, size=(29, 2))]
+    pairs, loss, grad, _ = _run(sizes, seed=700, weight=0.7)
+    _check(pairs, loss, grad, weight=0.7)

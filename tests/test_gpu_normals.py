@@ -162,3 +162,20 @@ def test_accumulate_adds_and_leaves_extra_vertices_alone():
     np.testing.assert_allclose(gpn[:, :90], 1.0 + ref[0].cpu().numpy().reshape(3, N)[:, :90], rtol=1e-6, atol=1e-6)
     np.testing.assert_allclose(gon[:90], 1.0 + ref[1].cpu().numpy()[:90], rtol=1e-6, atol=1e-6)
     np.testing.assert_allclose(gpose.cpu().numpy(), 1.0 + ref[2].cpu().numpy(), rtol=1e-6, atol=1e-6)
+
+
+def test_sensor_normals_of_32_views():
+    g = np.random.default_rng(39)
+    intrs = [S.Intrinsics(int(w), int(h), 30.0, 30.0, (int(w) - 1) / 2, (int(h) - 1) / 2)
+             for w, h in g.integers(1, 40, size=(32, 2))]
+    ds = _depths(40, intrs)
+    got = raster.sensor_normals(torch.as_tensor(np.concatenate([d.reshape(-1) for d in ds]), device="cuda"),
+                                intrs).cpu().numpy()
+    off = 0
+    for it, d in zip(intrs, ds):
+        P = it.width * it.height
+        ref, valid = NR.sensor_normals(d, it)
+        gv = got[3 * off:3 * (off + P)].reshape(3, it.height, it.width)
+        assert np.array_equal(np.any(gv != 0, axis=0), valid)
+        assert np.abs(gv - ref).max() <= 1e-6
+        off += P
