@@ -412,8 +412,13 @@ int tsr_equilateral_scratch_size(int64_t n_faces, size_t* bytes) {
 
 int tsr_equilateral(const tsr_scene* scene, float weight, int accumulate, float* loss, float* grad_pos,
                     void* scratch, size_t scratch_bytes, void* stream) {
-  int rc;
-  if ((rc = check_scene(scene))) return rc;
+  // positions and faces only: colours and opacities may be NULL here
+  if (!scene) return fail(TSR_EINVAL, "scene is NULL");
+  if (scene->n_faces < 0 || scene->n_vertices < 0) return fail(TSR_EINVAL, "negative scene size");
+  if (scene->n_faces > 0 && !scene->pos) return fail(TSR_EINVAL, "scene pos pointer is NULL");
+  if (!scene->faces && scene->n_vertices < 3 * scene->n_faces)
+    return fail(TSR_EINVAL, "soup needs n_vertices >= 3 * n_faces (%lld < %lld)", (long long)scene->n_vertices,
+                (long long)(3 * scene->n_faces));
   if (!loss && !grad_pos) return fail(TSR_EINVAL, "loss and grad_pos are both NULL");
   if (!scratch) return fail(TSR_EINVAL, "scratch is NULL");
   const int64_t nb = tsr::equi_blocks(scene->n_faces);

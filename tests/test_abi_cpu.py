@@ -147,6 +147,10 @@ def test_equilateral_scratch_size_and_validation():
     p = C.c_void_p(256)
     assert lib.tsr_equilateral(C.byref(sc), 1.0, 0, None, None, p, b, None) == _lib.TSR_EINVAL
     assert lib.tsr_equilateral(C.byref(sc), 1.0, 0, p, p, p, C.c_size_t(8), None) == _lib.TSR_EWORKSPACE
+    pos_only = _lib.TsrScene(1, None, None, None, 3000, 1000)      # colours and opacities unused
+    assert lib.tsr_equilateral(C.byref(pos_only), 1.0, 0, p, p, p, C.c_size_t(8), None) == _lib.TSR_EWORKSPACE
+    no_pos = _lib.TsrScene(None, 1, 1, None, 3000, 1000)
+    assert lib.tsr_equilateral(C.byref(no_pos), 1.0, 0, p, p, p, b, None) == _lib.TSR_EINVAL
 
 
 def test_face_stats_and_photometric_validation():
