@@ -61,3 +61,19 @@ def test_gradient_matches_central_differences(seed):
         xm[idx] -= h
         fd = (D.dssim(xp, y) - D.dssim(xm, y)) / (2 * h)
         assert abs(fd - g[idx]) <= 1e-6 * max(abs(fd), 1e-4), (idx, fd, g[idx])
+
+
+def test_loss_matches_a_library_gaussian_filter():
+    """The whole loss recomputed with SciPy's separable Gaussian filter (standard deviation 1.5,
+    radius 5 via truncate, zero padding: the same window) and the SSIM formula."""
+    from scipy.ndimage import gaussian_filter
+
+    x, y = _rand(8, (3, 19, 23)), _rand(9, (3, 19, 23))
+    f = lambda a: gaussian_filter(a, 1.5, mode="constant", cval=0.0, truncate=5.0 / 1.5)
+    tot = 0.0
+    for ch in range(3):
+        mx, my = f(x[ch]), f(y[ch])
+        sxx, syy, sxy = f(x[ch] ** 2) - mx ** 2, f(y[ch] ** 2) - my ** 2, f(x[ch] * y[ch]) - mx * my
+        s = (2 * mx * my + D.C1) * (2 * sxy + D.C2) / ((mx ** 2 + my ** 2 + D.C1) * (sxx + syy + D.C2))
+        tot += s.sum()
+    assert abs(D.dssim(x, y) - (1.0 - tot / x.size)) < 1e-12
