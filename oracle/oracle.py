@@ -221,10 +221,10 @@ def state(scene, pose, intr, sigma=1.0, z_near=0.1, r_min=1e-3, pixels=None, rho
     return out
 
 
-def face_stats(scene, pose, intr, t_min=1e-6, sigma=1.0, z_near=0.1, r_min=1e-3):
+def face_stats(scene, pose, intr, t_min=1e-6, sigma=1.0, z_near=0.1, r_min=1e-3, opacity_min=False):
     """Per-face projected area [M], coverage interval (cov_lo, cov_hi) [M] and visibility
     (certain, possible) [M] of one view; see orc_face_stats for the definitions."""
-    a = _Args(scene, pose, intr, sigma, z_near, r_min)
+    a = _Args(scene, pose, intr, sigma, z_near, r_min, opacity_min)
     M = int(a.sc.n_faces)
     area = np.zeros(max(M, 1))
     lo, hi, vc, vp = (np.zeros(max(M, 1), np.int32) for _ in range(4))

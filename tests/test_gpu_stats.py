@@ -19,16 +19,16 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def _gpu_stats(sc, intrs, poses, t_min=1e-6, sigma=1.0):
-    rast, p = G.make(sc, intrs, poses, sigma=sigma, t_min=t_min)
+def _gpu_stats(sc, intrs, poses, t_min=1e-6, sigma=1.0, opacity_min=False):
+    rast, p = G.make(sc, intrs, poses, sigma=sigma, t_min=t_min, opacity_min=opacity_min)
     rast.bin_and_sort(p)
     area, cov, vis = rast.face_stats(p)
     torch.cuda.synchronize()
     return rast, p, area.cpu().numpy(), cov.cpu().numpy(), vis.cpu().numpy()
 
 
-def _check_view(sc, pose, intr, area, cov, vis, t_min, sigma=1.0):
-    a, lo, hi, vc, vp = O.face_stats(sc, pose, intr, t_min=t_min, sigma=sigma)
+def _check_view(sc, pose, intr, area, cov, vis, t_min, sigma=1.0, opacity_min=False):
+    a, lo, hi, vc, vp = O.face_stats(sc, pose, intr, t_min=t_min, sigma=sigma, opacity_min=opacity_min)
     assert np.all(np.abs(area - a) <= 1e-6 * np.maximum(a, 1.0)), np.abs(area - a).max()
     bad = np.nonzero((cov < lo) | (cov > hi))[0]
     assert bad.size == 0, [(int(m), int(lo[m]), int(cov[m]), int(hi[m])) for m in bad[:5]]
@@ -111,3 +111,13 @@ def test_tile_lists_longer_than_the_visibility_bitmap():
     _, _, area, cov, vis = _gpu_stats(sc, [intr], [IDENTITY])
     _check_view(sc, IDENTITY, intr, area, cov, vis, 1e-6)
     assert vis.sum() > 4096
+
+
+def test_minimum_opacity_rule():
+    """Coverage and visibility follow the face opacity rule: with the minimum of the vertex
+    opacities, alpha (and so every blending decision) changes."""
+    sc, intr = tiny_scene(14, n_faces=40, w=48, h=36, f=36.0)
+    g = np.random.default_rng(14)
+    sc = S.Scene(sc.pos, sc.col, g.uniform(0.05, 1.0, size=sc.n_vertices).astype(np.float32))
+    _, _, area, cov, vis = _gpu_stats(sc, [intr], [IDENTITY], t_min=0.3, opacity_min=True)
+    _check_view(sc, IDENTITY, intr, area, cov, vis, 0.3, opacity_min=True)
