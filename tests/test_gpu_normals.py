@@ -65,8 +65,8 @@ def _targets(seed, n_pix, frac_valid=0.8):
     return nb.astype(np.float32), valid
 
 
-def _run(sc, intrs, poses, seed, w_norm=0.05):
-    rast, p = G.make(sc, intrs, poses)
+def _run(sc, intrs, poses, seed, w_norm=0.05, sigma=1.0):
+    rast, p = G.make(sc, intrs, poses, sigma=sigma)
     tgts = [_targets(seed + v, it.width * it.height) for v, it in enumerate(intrs)]
     tdev = torch.as_tensor(np.concatenate([t.reshape(-1) for t, _ in tgts]), device="cuda")
     P = rast.total_pixels
@@ -81,12 +81,12 @@ def _run(sc, intrs, poses, seed, w_norm=0.05):
     for v, (it, (nb, valid)) in enumerate(zip(intrs, tgts)):
         Pv = it.width * it.height
         nb64 = nb.astype(np.float64)
-        lref = w_norm * NR.e_norm(sc, poses[v], it, nb64, valid)
-        a, b, c = NR.e_norm_grad(sc, poses[v], it, nb64, valid)
+        lref = w_norm * NR.e_norm(sc, poses[v], it, nb64, valid, sigma=sigma)
+        a, b, c = NR.e_norm_grad(sc, poses[v], it, nb64, valid, sigma=sigma)
         ref[0] += w_norm * a
         ref[1] += w_norm * b
         ref[2].append(w_norm * c)
-        nref = NR.render_normals(sc, poses[v], it)
+        nref = NR.render_normals(sc, poses[v], it, sigma=sigma)
         err = np.abs(nm[3 * off:3 * (off + Pv)].reshape(3, Pv) - nref).max()
         _say(f"  view {v}: loss {float(loss[v]):.7f} ref {lref:.7f}, normal map err {err:.2e}")
         assert err <= 1e-5
@@ -100,11 +100,11 @@ def _run(sc, intrs, poses, seed, w_norm=0.05):
     return rast
 
 
-@pytest.mark.parametrize("seed", [31, 32])
-def test_normal_step_tiny(seed):
+@pytest.mark.parametrize("seed,sigma", [(31, 1.0), (32, 1.0), (33, 0.5), (34, 2.0)])
+def test_normal_step_tiny(seed, sigma):
     sc, intr = tiny_scene(seed, n_faces=30, w=48, h=36, f=36.0)
     pose = left_perturb(IDENTITY, np.random.default_rng(seed).normal(scale=0.03, size=6)).astype(np.float32)
-    _run(sc, [intr], [pose], seed)
+    _run(sc, [intr], [pose], seed, sigma=sigma)
 
 
 def test_normal_step_views_of_different_sizes():

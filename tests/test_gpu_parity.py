@@ -369,19 +369,20 @@ def test_train_l1_matches_oracle(name):
 
 # ---------------------------------------------------------------------------- full photometric step
 
-@pytest.mark.parametrize("name", ["single_64x48", "multi_view_mixed", "tiny_ragged_50x37", "long_tile_800"])
-def test_train_photometric_matches_oracle(name):
+@pytest.mark.parametrize("name,sigma", [("single_64x48", 1.0), ("multi_view_mixed", 1.0), ("tiny_ragged_50x37", 1.0),
+                                        ("long_tile_800", 1.0), ("single_64x48", 0.5), ("tiny_ragged_50x37", 2.0)])
+def test_train_photometric_matches_oracle(name, sigma):
     """Eqs. 8 and 10 with the D-SSIM term: the seeds are the oracle's L1 seeds plus 0.2 times
     the FP64 D-SSIM gradient of the oracle render, pushed through the oracle backward."""
     from oracle import dssim as D
-    _say(f"[train_photometric] case={name}")
+    _say(f"[train_photometric] case={name} sigma={sigma}")
     w_ssim = 0.2
     sc, poses, intrs = _case(name)
-    rast, p = G.make(sc, intrs, poses)
+    rast, p = G.make(sc, intrs, poses, sigma=sigma)
     tcs, tds, lossref, gcs, gds, ocs = [], [], [], [], [], []
     for v in range(len(poses)):
         W, H = intrs[v].width, intrs[v].height
-        oc, od, ot = O.render(sc, poses[v], intrs[v])
+        oc, od, ot = O.render(sc, poses[v], intrs[v], sigma=sigma)
         tc, td, _ = _nudged_targets(oc, od, 300 + v, None)
         L, gcv, gdv = O.l1_seeds(oc, od, tc, td, W * H)
         c3, t3 = np.asarray(oc, np.float64).reshape(3, H, W), tc.astype(np.float64).reshape(3, H, W)
@@ -401,11 +402,15 @@ def test_train_photometric_matches_oracle(name):
     got = [x.cpu().numpy().astype(np.float64) for x in out]
     _say(f"  loss {loss.cpu().numpy()} ref {np.array(lossref)}")
     np.testing.assert_allclose(loss.cpu().numpy(), lossref, rtol=1e-5, atol=2e-5)
-    ref = _oracle_backward_views(sc, poses, intrs, gcs, gds, None, 1.0)
-    for nm, a, b in zip(["grad_pos", "grad_col", "grad_opa", "grad_pose"], got, ref):
-        ok, msg, bad = grad_close(a, b, name=nm)
+    ref, conds = _oracle_backward_views(sc, poses, intrs, gcs, gds, None, sigma, with_abs=True)
+    for nm, a, b, cond in zip(["grad_pos", "grad_col", "grad_opa", "grad_pose"], got, ref, conds + [None]):
+        ok, msg, bad = grad_close(a, b, name=nm, cond=cond)
         _say("  " + msg)
-        assert ok, msg
+        if sigma < 1.0 and not ok:
+            # sigma < 1: the window slope is unbounded at the edge; norm-wise agreement only
+            assert np.linalg.norm(a - b) <= 1e-3 * np.linalg.norm(b), msg
+        else:
+            assert ok, msg
     cs = G.per_view(rast, color.cpu().numpy(), 3)
     for v in range(len(poses)):
         assert np.abs(cs[v] - ocs[v]).max() <= IMG_TOL
