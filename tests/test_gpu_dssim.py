@@ -104,3 +104,28 @@ def test_the_maximum_of_32_views():
     sizes = [(1, 1), (40, 1), (1, 30)] + [(int(w), int(h)) for w, h in g.integers(2, 48, size=(29, 2))]
     pairs, loss, grad, _ = _run(sizes, seed=700, weight=0.7)
     _check(pairs, loss, grad, weight=0.7)
+
+
+def test_replays_from_a_captured_graph_equal_the_eager_call():
+    """tsr_dssim allocates nothing and clears nothing with memset nodes: captured once, every
+    replay (with other eager work in between) gives the eager loss and gradient."""
+    pairs, loss, grad, (ds, col, tgt) = _run([(64, 48), (37, 23)], seed=800)
+    gl = torch.empty(2, device="cuda")
+    gg = torch.empty(grad.size, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(side):
+        ds(col, tgt, loss=gl, grad=gg)                 # warm-up on the capture stream
+        with torch.cuda.graph(graph, stream=side):
+            ds(col, tgt, loss=gl, grad=gg)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        gl.fill_(float("nan"))
+        gg.fill_(float("nan"))
+        ds(tgt, col)                                    # eager work between the replays
+        graph.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(gl.cpu().numpy(), loss)
+        np.testing.assert_allclose(gg.cpu().numpy(), grad, rtol=0, atol=0)
