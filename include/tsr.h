@@ -256,6 +256,19 @@ TSR_API int tsr_equilateral_scratch_size(int64_t n_faces, size_t *bytes /* (host
 TSR_API int tsr_equilateral(const tsr_scene *scene, float weight, int accumulate, float *loss, float *grad_pos,
                     void *scratch, size_t scratch_bytes, void *stream);
 
+/* Allocation-free variant of tsr_equilateral, for callers that cannot allocate device memory
+ * or hand over a scratch buffer (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  Arguments, results and errors as tsr_equilateral without `scratch`:
+ * the per-workgroup partial sums live in a static device array of the library (128 KiB on each
+ * GPU it runs on, held until the process ends), so n_faces may be at most
+ * TSR_EQUI_NOALLOC_MAX_FACES (TSR_EINVAL beyond).  `stream` must belong to the current device
+ * (TSR_EINVAL otherwise).  The first call on a device looks up the array's address there.
+ * Every call on one GPU shares its array: calls that overlap on one GPU (other streams or host
+ * threads) race, and the caller must serialise them.  No device memory is allocated or freed. */
+#define TSR_EQUI_NOALLOC_MAX_FACES 4194304
+TSR_API int tsr_equilateral_noalloc(const tsr_scene *scene, float weight, int accumulate, float *loss,
+                                    float *grad_pos, void *stream);
+
 /* Per-(view, face) screen statistics behind the map-management tests of Sec. 3.4 (pruning by
  * projected area, densification by pixel coverage, keyframing by visibility), each [V * M]
  * indexed v * M + m, all device, each may be NULL:

@@ -20,10 +20,11 @@ TSR_ECAPACITY = -3
 TSR_EHIP = -4
 TSR_EINTERNAL = -5
 TSR_MAX_VIEWS = 32
+TSR_EQUI_NOALLOC_MAX_FACES = 4194304
 TSR_TILE = 16
 
 EXPORTED = ["tsr_workspace_size", "tsr_workspace_init", "tsr_bin_and_sort", "tsr_count", "tsr_binning_view", "tsr_render_forward",
-            "tsr_render_backward", "tsr_render_train_l1", "tsr_pose_step", "tsr_dssim_scratch_size", "tsr_dssim", "tsr_render_train_photometric", "tsr_equilateral_scratch_size", "tsr_equilateral", "tsr_face_stats", "tsr_sensor_normals", "tsr_normal_scratch_size", "tsr_render_train_normal", "tsr_check", "tsr_last_error",
+            "tsr_render_backward", "tsr_render_train_l1", "tsr_pose_step", "tsr_dssim_scratch_size", "tsr_dssim", "tsr_render_train_photometric", "tsr_equilateral_scratch_size", "tsr_equilateral", "tsr_equilateral_noalloc", "tsr_face_stats", "tsr_sensor_normals", "tsr_normal_scratch_size", "tsr_render_train_normal", "tsr_check", "tsr_last_error",
             "tsr_profile_enable", "tsr_profile_reset", "tsr_profile_read"]
 
 
@@ -85,6 +86,7 @@ def load() -> C.CDLL:
                                                  P, C.c_size_t, P]
     lib.tsr_equilateral_scratch_size.argtypes = [I64, P]
     lib.tsr_equilateral.argtypes = [P, C.c_float, I, P, P, P, C.c_size_t, P]
+    lib.tsr_equilateral_noalloc.argtypes = [P, C.c_float, I, P, P, P]
     lib.tsr_face_stats.argtypes = [P, P, P, I, P, P, C.c_size_t, P, P, P, P]
     lib.tsr_sensor_normals.argtypes = [P, P, I, P, P]
     lib.tsr_normal_scratch_size.argtypes = [P, P, I, P]

@@ -199,6 +199,19 @@ tsr::tsr_scene_dev dev_scene(const tsr_scene* sc, const tsr_params* p = nullptr)
   return d;
 }
 
+// Arguments of the E_equi entry points: positions and faces only (colours and opacities may be
+// NULL there).
+int check_equi_args(const tsr_scene* scene, const float* loss, const float* grad_pos) {
+  if (!scene) return fail(TSR_EINVAL, "scene is NULL");
+  if (scene->n_faces < 0 || scene->n_vertices < 0) return fail(TSR_EINVAL, "negative scene size");
+  if (scene->n_faces > 0 && !scene->pos) return fail(TSR_EINVAL, "scene pos pointer is NULL");
+  if (!scene->faces && scene->n_vertices < 3 * scene->n_faces)
+    return fail(TSR_EINVAL, "soup needs n_vertices >= 3 * n_faces (%lld < %lld)", (long long)scene->n_vertices,
+                (long long)(3 * scene->n_faces));
+  if (!loss && !grad_pos) return fail(TSR_EINVAL, "loss and grad_pos are both NULL");
+  return TSR_OK;
+}
+
 // Common argument checks of the per-call entry points.
 int prepare(const tsr_scene* sc, const float* poses, const tsr_intrinsics* intr, int n_views, const tsr_params* p,
             void* ws, size_t ws_bytes, ViewTable* vt, WsLayout* L) {
@@ -412,14 +425,8 @@ int tsr_equilateral_scratch_size(int64_t n_faces, size_t* bytes) {
 
 int tsr_equilateral(const tsr_scene* scene, float weight, int accumulate, float* loss, float* grad_pos,
                     void* scratch, size_t scratch_bytes, void* stream) {
-  // positions and faces only: colours and opacities may be NULL here
-  if (!scene) return fail(TSR_EINVAL, "scene is NULL");
-  if (scene->n_faces < 0 || scene->n_vertices < 0) return fail(TSR_EINVAL, "negative scene size");
-  if (scene->n_faces > 0 && !scene->pos) return fail(TSR_EINVAL, "scene pos pointer is NULL");
-  if (!scene->faces && scene->n_vertices < 3 * scene->n_faces)
-    return fail(TSR_EINVAL, "soup needs n_vertices >= 3 * n_faces (%lld < %lld)", (long long)scene->n_vertices,
-                (long long)(3 * scene->n_faces));
-  if (!loss && !grad_pos) return fail(TSR_EINVAL, "loss and grad_pos are both NULL");
+  int rc = check_equi_args(scene, loss, grad_pos);
+  if (rc) return rc;
   if (!scratch) return fail(TSR_EINVAL, "scratch is NULL");
   const int64_t nb = tsr::equi_blocks(scene->n_faces);
   if (nb > 0x7fffffff) return fail(TSR_EINVAL, "too many faces");
@@ -429,6 +436,30 @@ int tsr_equilateral(const tsr_scene* scene, float weight, int accumulate, float*
   hipError_t e = tsr::launch_equi(dev_scene(scene), weight, accumulate != 0, loss, grad_pos,
                                   static_cast<double*>(scratch), static_cast<hipStream_t>(stream));
   return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_equilateral launch");
+}
+
+int tsr_equilateral_noalloc(const tsr_scene* scene, float weight, int accumulate, float* loss, float* grad_pos,
+                            void* stream) {
+  int rc = check_equi_args(scene, loss, grad_pos);
+  if (rc) return rc;
+  const int64_t nb = tsr::equi_blocks(scene->n_faces);
+  if (nb > tsr::kEquiStaticPartials)
+    return fail(TSR_EINVAL, "tsr_equilateral_noalloc takes at most %d faces (got %lld)", TSR_EQUI_NOALLOC_MAX_FACES,
+                (long long)scene->n_faces);
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "tsr_equilateral_noalloc current device");
+  if (st) {
+    int sdev = 0;
+    if ((e = hipStreamGetDevice(st, &sdev)) != hipSuccess) return hip_fail(e, "tsr_equilateral_noalloc stream device");
+    if (sdev != dev) return fail(TSR_EINVAL, "stream belongs to device %d, the current device is %d", sdev, dev);
+  }
+  double* partial = nullptr;
+  if ((e = tsr::equi_static_scratch(dev, &partial)) != hipSuccess)
+    return hip_fail(e, "tsr_equilateral_noalloc static scratch address");
+  e = tsr::launch_equi(dev_scene(scene), weight, accumulate != 0, loss, grad_pos, partial, st);
+  return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_equilateral_noalloc launch");
 }
 
 int tsr_face_stats(const tsr_scene* scene, const float* poses, const tsr_intrinsics* intr, int n_views,

@@ -195,6 +195,11 @@ hipError_t launch_photo_seeds(const SsimTable& t, const float* color, const floa
 // Equilateral regulariser (Sec. 3.5, eq. 14): workgroups of one launch over M faces, and the
 // launch (loss and/or gradient; `partial` holds one double per workgroup).
 int64_t equi_blocks(int64_t n_faces);
+// Partials of the allocation-free variant: one double per 256-face workgroup in a static
+// device array of this many entries (128 KiB per GPU).
+constexpr int64_t kEquiStaticPartials = 16384;
+// Device address of that array on `device` (which must be current), looked up on first use.
+hipError_t equi_static_scratch(int device, double** out);
 hipError_t launch_equi(const tsr_scene_dev& sc, float weight, bool accumulate, float* loss, float* grad,
                        double* partial, hipStream_t st);
 

@@ -6,6 +6,8 @@
 // One thread per face; the per-face arithmetic runs in FP64 with three square roots and three
 // divisions (FP64 division is a long instruction sequence, so the unit edges and the gradient
 // terms multiply by the reciprocal lengths), and the loss is summed per workgroup in FP64.
+#include <mutex>
+
 #include "tsr_device.h"
 #include "tsr_internal.h"
 
@@ -134,6 +136,34 @@ hipError_t launch_equi(const tsr_scene_dev& sc, float weight, bool accumulate, f
                accumulate ? 1 : 0, grad, partial);
   if (loss) TSR_LAUNCH("equi_loss", k_equi_loss, dim3(1), dim3(256), 0, st, partial, nb, M, loss);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------- no-allocation variant
+// The partial sums of tsr_equilateral_noalloc live in this file-scope device array (one copy per
+// GPU, held until the process ends) instead of a caller-provided scratch buffer.  Host code never
+// passes the array's name to a kernel: the name is a host-side stand-in, not a device address.
+// The device address is looked up once per device with hipGetSymbolAddress and cached.
+static __device__ __align__(256) double scratch[kEquiStaticPartials];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t equi_static_scratch(int device, double** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    // the caller made `device` current
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = static_cast<double*>(p);
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
 }
 
 }  // namespace tsr

@@ -325,14 +325,18 @@ class DSsim:
 
 def equilateral(scene: DeviceScene, weight: float = 1.0, grad: Optional[torch.Tensor] = None,
                 accumulate: bool = False, want_grad: bool = True, loss: Optional[torch.Tensor] = None,
-                stream=None):
+                stream=None, noalloc: bool = False):
     """Equilateral regulariser of eq. (14) (``tsr_equilateral``): returns (loss [1], grad [3, N]
-    or None), the gradient scaled by ``weight`` and written or added into ``grad``."""
+    or None), the gradient scaled by ``weight`` and written or added into ``grad``.  With
+    ``noalloc`` the call goes to ``tsr_equilateral_noalloc`` (no scratch buffer; the library's
+    static per-device partials, up to TSR_EQUI_NOALLOC_MAX_FACES faces)."""
     lib = _lib.load()
-    nb = C.c_size_t()
-    check(lib.tsr_equilateral_scratch_size(scene.n_faces, C.byref(nb)), "tsr_equilateral_scratch_size")
     dev = scene.pos.device
-    scratch = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    scratch = None
+    if not noalloc:
+        nb = C.c_size_t()
+        check(lib.tsr_equilateral_scratch_size(scene.n_faces, C.byref(nb)), "tsr_equilateral_scratch_size")
+        scratch = torch.empty(nb.value, dtype=torch.uint8, device=dev)
     loss = loss if loss is not None else torch.empty(1, device=dev)
     if want_grad and grad is None:
         if accumulate:
@@ -342,8 +346,12 @@ def equilateral(scene: DeviceScene, weight: float = 1.0, grad: Optional[torch.Te
                              or grad.numel() != 3 * scene.n_vertices):
         raise ValueError("grad: need a contiguous float32 tensor of 3 * n_vertices values")
     sc = scene.c()
-    check(lib.tsr_equilateral(C.byref(sc), float(weight), 1 if accumulate else 0, _ptr(loss), _ptr(grad),
-                              _ptr(scratch), C.c_size_t(scratch.numel()), _stream(stream)), "tsr_equilateral")
+    if noalloc:
+        check(lib.tsr_equilateral_noalloc(C.byref(sc), float(weight), 1 if accumulate else 0, _ptr(loss), _ptr(grad),
+                                          _stream(stream)), "tsr_equilateral_noalloc")
+    else:
+        check(lib.tsr_equilateral(C.byref(sc), float(weight), 1 if accumulate else 0, _ptr(loss), _ptr(grad),
+                                  _ptr(scratch), C.c_size_t(scratch.numel()), _stream(stream)), "tsr_equilateral")
     return loss, grad
 
 

@@ -190,3 +190,19 @@ def test_normal_entry_points_validation():
     assert lib.tsr_render_train_normal(C.byref(sc), p, _intr((64, 48)), 1, C.byref(_params()), p, big, p, 0.05,
                                        None, None, None, None, None, 1, p, C.c_size_t(need.value - 1),
                                        None) == _lib.TSR_EWORKSPACE
+
+
+def test_equilateral_noalloc_validation():
+    """The allocation-free E_equi variant validates like tsr_equilateral and refuses more than
+    TSR_EQUI_NOALLOC_MAX_FACES faces before any device call."""
+    lib = _lib.load()
+    p = C.c_void_p(256)
+    M = _lib.TSR_EQUI_NOALLOC_MAX_FACES
+    too_big = _lib.TsrScene(1, None, None, None, 3 * (M + 1), M + 1)
+    assert lib.tsr_equilateral_noalloc(C.byref(too_big), 1.0, 0, p, p, None) == _lib.TSR_EINVAL
+    assert b"at most" in lib.tsr_last_error()
+    sc = _scene(10)
+    assert lib.tsr_equilateral_noalloc(C.byref(sc), 1.0, 0, None, None, None) == _lib.TSR_EINVAL
+    assert lib.tsr_equilateral_noalloc(None, 1.0, 0, p, p, None) == _lib.TSR_EINVAL
+    short_soup = _lib.TsrScene(1, None, None, None, 20, 10)
+    assert lib.tsr_equilateral_noalloc(C.byref(short_soup), 1.0, 0, p, p, None) == _lib.TSR_EINVAL
