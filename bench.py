@@ -49,10 +49,12 @@ def parse():
     ap.add_argument("--views", type=int, default=8, help="views of the batched measurement")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-pixels", type=int, default=8192)
+    ap.add_argument("--cpu-pixels", type=int, default=4096)
     ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run a 256 MiB device-to-device copy (counter calibration in profiler runs)")
+                    help="(kept for older profiler commands: the 256 MiB device copy now always runs)")
+    ap.add_argument("--no-sigma-half", action="store_true", help="skip the headline step at the paper's sigma = 0.5")
+    ap.add_argument("--serve-warmup", type=int, default=500)
     ap.add_argument("--only-single", action="store_true", help="skip the unfused and batched legs")
     ap.add_argument("--only-photometric", action="store_true",
                     help="after the headline step, time only the full photometric step (D-SSIM term)")
@@ -61,7 +63,7 @@ def parse():
                     help="fixed tile schedule 'persistent,order,grid' for the single view (no autotuning)")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-track", action="store_true", help="skip the captured tracking-loop leg")
-    ap.add_argument("--serve-queries", type=int, default=400)
+    ap.add_argument("--serve-queries", type=int, default=10000)
     ap.add_argument("--no-configs", action="store_true", help="skip the other configurations (64x48, 640x480, window)")
     return ap.parse_args()
 
@@ -73,11 +75,11 @@ def log(*a):
 class Case:
     """A rasterizer with its inputs, outputs and gradient buffers resident on the device."""
 
-    def __init__(self, raster, scenes, dev_scene, poses, intrs, target_poses):
+    def __init__(self, raster, scenes, dev_scene, poses, intrs, target_poses, sigma=1.0):
         import torch
 
         self.torch = torch
-        self.rast = raster.Rasterizer(dev_scene, intrs, raster.Params(sigma=1.0))
+        self.rast = raster.Rasterizer(dev_scene, intrs, raster.Params(sigma=sigma))
         self.poses = raster.poses_tensor(poses)
         tposes = raster.poses_tensor(target_poses)
         self.K = self.rast.fit(self.poses, slack=1.5)
@@ -159,6 +161,26 @@ def time_steps(fn, steps, warmup):
     b.record(st)
     torch.cuda.synchronize()
     return a.elapsed_time(b) / steps
+
+
+def step_stats(fn, steps, warmup):
+    """Mean over `steps` back-to-back steps (events around the whole run, as the headline
+    figure), plus the median, p99 and minimum of per-step times (an event between steps)."""
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record(st)
+    for i in range(steps):
+        fn()
+        ev[i + 1].record(st)
+    torch.cuda.synchronize()
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    return {"mean": ev[0].elapsed_time(ev[-1]) / steps, "median": float(np.median(per)),
+            "p99": float(np.percentile(per, 99)), "min": float(per.min()), "steps": steps}
 
 
 def graph_steps(case, steps, warmup):
@@ -330,53 +352,125 @@ def tracking_leg(raster, w, dev, iters=100, schedule=None):
             "ms_per_iteration_eager": ms_eager / iters, "loss_first": float(lh[0]), "loss_last": float(lh[-1])}
 
 
-def serving_leg(raster, w, dev, n_queries, seed=4400):
-    """Continuous-batching render serving of the resident map: saturated throughput, then
-    Poisson arrivals at 25 / 50 / 80 % of it; p50 / p99 latency per rate.  The plain
-    single-view path (one query at a time, one view per launch) is run on the same saturated
-    query stream for comparison."""
+def serving_leg(raster, w, dev, n_queries, n_warm, seed=4400):
+    """Continuous-batching render serving of the resident 1M-face map (forward colour + depth,
+    resolutions uniform over 320x240 / 640x480 / 1200x680, random poses in the room):
+    saturated throughput, then open-loop Poisson arrivals at 25 / 50 / 80 % of it, each over
+    n_queries after n_warm warm-up queries, p50 / p99 latency per rate (8 GB budget, 4 slots,
+    batches of up to 8 views).  The plain single-view path (one slot, one view per launch) is
+    run at the same offered rates, and the batched server again under a tight 512 MB budget.
+    Outputs are dropped at completion, so the budget bounds the server's memory."""
     from paper_2605_31419_amd import scenes
-    from paper_2605_31419_amd.serve import GpuExecutor, Request, Server, run_poisson
+    from paper_2605_31419_amd.serve import GpuExecutor, Server, run_poisson
 
     ex = GpuExecutor(dev, pairs_per_tile=160.0)
 
-    def run(qps, n, warm, slots=4, views=8):
-        srv = Server(ex, n_slots=slots, mem_budget=8 << 30, max_batch_views=views)
+    def run(qps, slots=4, views=8, budget=8 << 30, n=n_queries, warm=n_warm):
+        srv = Server(ex, n_slots=slots, mem_budget=budget, max_batch_views=views, keep_outputs=False)
         srv.start()
         try:
             qs = scenes.serving_queries(seed + int(qps) % 1000, n + warm, qps=qps)
-            return run_poisson(srv, qs, warmup=warm)
+            st = run_poisson(srv, qs, warmup=warm)
         finally:
             srv.stop()
+        st.update({"offered_qps": None if qps >= 1e6 else qps, "slots": slots, "budget_bytes": budget})
+        return st
 
-    run(1e7, 40, 0)                                      # warm-up: allocator, code objects
-    sat = run(1e7, n_queries, 20)
-    plain = run(1e7, n_queries, 20, slots=1, views=1)
-    out = {"saturated": sat, "plain_single_view": plain, "rates": []}
+    run(1e7, n=40, warm=0)                               # warm-up: allocator, code objects
+    sat = run(1e7)
+    log(f"[bench] serving saturated: {sat['qps']:.0f} qps, p99 {sat['p99_ms']:.2f} ms")
+    plain = run(1e7, slots=1, views=1)
+    out = {"queries": n_queries, "warmup_queries": n_warm, "saturated": sat, "plain_single_view": plain,
+           "rates": [], "plain_rates": []}
     for frac in (0.25, 0.5, 0.8):
-        st = run(frac * sat["qps"], n_queries, 20)
-        st["offered_qps"] = frac * sat["qps"]
+        q = frac * sat["qps"]
+        st = run(q)
         out["rates"].append(st)
+        pl = run(q, slots=1, views=1)
+        out["plain_rates"].append(pl)
+        log(f"[bench] serving at {q:.0f} qps: p50 {st['p50_ms']:.2f} / p99 {st['p99_ms']:.2f} ms "
+            f"(plain single view p50 {pl['p50_ms']:.2f} / p99 {pl['p99_ms']:.2f} ms)")
+    try:
+        tight_sat = run(1e7, slots=2, budget=512 << 20)
+        tight_q = run(0.25 * sat["qps"], slots=2, budget=512 << 20)
+        out["tight_512MB"] = {"saturated": tight_sat, "at_25pct": tight_q}
+        log(f"[bench] serving, 512 MB budget: {tight_sat['qps']:.0f} qps saturated, "
+            f"p99 {tight_q['p99_ms']:.2f} ms at {tight_q['offered_qps']:.0f} qps")
+    except ValueError as e:                              # budget too small for one slot
+        out["tight_512MB"] = {"error": str(e)}
     out["capacity_retries"] = ex.retries
     return out
 
 
-def cpu_baseline(w, n_pix, seed=7):
-    from oracle import oracle as O
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
+
+def _median_of_3(fn):
+    runs = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        fn()
+        runs.append(time.perf_counter() - t0)
+    return float(np.median(runs)), [round(r, 4) for r in runs]
+
+
+def cpu_baseline(w, n_pix, seed=7):
+    """The FP64 oracle on the host cores (median of 3 runs each): the headline frame's
+    forward + backward on a seeded pixel sample at all threads and at one thread, the 64x48
+    frame in full, a 640x480 forward sample, and the reference binner on the headline frame."""
+    from oracle import oracle as O
+    from paper_2605_31419_amd import scenes
+
+    nproc = O.max_threads()
     intr = w.intr[0]
     g = np.random.default_rng(seed)
     pix = np.sort(g.choice(intr.width * intr.height, size=n_pix, replace=False)).astype(np.int64)
-    t0 = time.perf_counter()
-    C, D, T = O.render(w.scene, w.poses[0], intr, pixels=pix)
-    t1 = time.perf_counter()
-    gc = np.full((3, n_pix), 1.0 / (3 * intr.width * intr.height))
-    gd = np.full(n_pix, 0.05 / (intr.width * intr.height))
-    O.backward(w.scene, w.poses[0], intr, gc, gd, None, pixels=pix)
-    t2 = time.perf_counter()
-    return {"value": n_pix / (t2 - t0) / 1e6, "unit": "Mpix/s", "cores": O.max_threads(), "kind": "oracle",
+    n1 = max(64, n_pix // 16)
+    pix1 = np.sort(g.choice(pix, size=n1, replace=False))
+
+    def fwd_bwd(wl, pixels):
+        it = wl.intr[0]
+        n = it.width * it.height if pixels is None else pixels.size
+        O.render(wl.scene, wl.poses[0], it, pixels=pixels)
+        O.backward(wl.scene, wl.poses[0], it, np.full((3, n), 1.0 / (3 * it.width * it.height)),
+                   np.full(n, 0.05 / (it.width * it.height)), None, pixels=pixels)
+
+    O.set_threads(nproc)
+    t_n, runs_n = _median_of_3(lambda: fwd_bwd(w, pix))
+    O.set_threads(1)
+    t_1, runs_1 = _median_of_3(lambda: fwd_bwd(w, pix1))
+    O.set_threads(nproc)
+    c1 = scenes.workload("single_64x48")
+    c1_px = c1.intr[0].width * c1.intr[0].height
+    t_c1, _ = _median_of_3(lambda: fwd_bwd(c1, None))
+    O.set_threads(1)
+    t_c1_1, _ = _median_of_3(lambda: fwd_bwd(c1, None))
+    O.set_threads(nproc)
+    c2 = scenes.workload("track_640x480")
+    c2_pix = np.sort(g.choice(640 * 480, size=8192, replace=False)).astype(np.int64)
+    t_c2, _ = _median_of_3(lambda: O.render(c2.scene, c2.poses[0], c2.intr[0], pixels=c2_pix))
+    t_bin, _ = _median_of_3(lambda: O.bin_pairs(w.scene, w.poses, w.intr))
+    return {"value": n_pix / t_n / 1e6, "unit": "Mpix/s", "cores": nproc, "kind": "oracle",
             "sample": f"{n_pix} seeded pixels of the 1200x680 view, forward + backward over all "
-                      f"{w.scene.n_faces} faces (forward {t1 - t0:.2f} s, backward {t2 - t1:.2f} s)"}
+                      f"{w.scene.n_faces} faces, median of 3 runs ({t_n:.2f} s)",
+            "cpu_model": _cpu_model(), "runs_s": runs_n,
+            "single_thread": {"value": n1 / t_1 / 1e6, "unit": "Mpix/s", "pixels": n1, "runs_s": runs_1},
+            "full_frame_extrapolated_s": {"threads_all": t_n * intr.width * intr.height / n_pix,
+                                          "threads_1": t_1 * intr.width * intr.height / n1},
+            "configs": {
+                "single_64x48_fwd_bwd_full_frame": {"ms_all_threads": 1e3 * t_c1, "ms_1_thread": 1e3 * t_c1_1,
+                                                    "mpix_s": c1_px / t_c1 / 1e6},
+                "track_640x480_forward": {"pixels": 8192, "s": t_c2, "mpix_s": 8192 / t_c2 / 1e6,
+                                          "full_frame_extrapolated_s": t_c2 * 640 * 480 / 8192},
+                "reference_binner_1200x680_1M": {"s": t_bin, "note": "orc_bin: FP64 projection, pairs, std sort"}}}
 
 
 def main():
@@ -406,7 +500,8 @@ def main():
         single.rast.schedule = best
         tuned = {"schedule": list(best), "candidates_ms": {k: round(v, 4) for k, v in times.items()}}
         log(f"[bench] autotuned schedule {best}: {json.dumps(tuned['candidates_ms'])}")
-    ms_eager = time_steps(single.step, args.steps, args.warmup)
+    head_stats = step_stats(single.step, args.steps, args.warmup)
+    ms_eager = head_stats["mean"]
     single.check()
     log(f"[bench] fused step, eager launches: {ms_eager:.3f} ms -> {single.pixels / (ms_eager * 1e-3) / 1e6:.1f} Mpix/s")
     ms_graph, graph_dev = graph_steps(single, args.steps, args.warmup)
@@ -422,22 +517,21 @@ def main():
     ktimes, klaunch = kernel_times(single.step, args.profile_steps)
     log(f"[bench] kernels (ms): {json.dumps({k: round(v, 4) for k, v in ktimes.items()})}")
 
-    copy_gbs = None
-    if args.copy_calibration:
-        n = 256 << 20
-        src = torch.empty(n // 4, device="cuda")
-        dst = torch.empty_like(src)
+    # measured device-copy bandwidth (also the calibration copy of the profiler-counter runs)
+    n = 256 << 20
+    src = torch.empty(n // 4, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(5):
         dst.copy_(src)
-        torch.cuda.synchronize()
-        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        a.record()
-        for _ in range(5):
-            dst.copy_(src)
-        b.record()
-        torch.cuda.synchronize()
-        copy_gbs = 2 * n * 5 / (a.elapsed_time(b) * 1e-3) / 1e9
-        log(f"[bench] device copy of 256 MiB: {copy_gbs:.0f} GB/s (read + write)")
-        del src, dst
+    b.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * n * 5 / (a.elapsed_time(b) * 1e-3) / 1e9
+    log(f"[bench] device copy of 256 MiB: {copy_gbs:.0f} GB/s (read + write)")
+    del src, dst
     if args.only_single:
         print(json.dumps({"metric": "fwd+bwd Mpix/s (single view only)", "value": mpix, "unit": "Mpix/s",
                           "ms_per_step": ms, "kernels_ms": ktimes, "copy_gbs": copy_gbs, "schedule": tuned}), flush=True)
@@ -504,10 +598,12 @@ def main():
             bcase.rast.schedule = bbest
             btuned = {"schedule": list(bbest), "candidates_ms": {k: round(v, 4) for k, v in btimes.items()}}
             log(f"[bench] batched autotuned schedule {bbest}: {json.dumps(btuned['candidates_ms'])}")
-        msb = time_steps(bcase.step, max(5, args.steps // 4), args.warmup)
+        bst = step_stats(bcase.step, max(10, args.steps // 2), args.warmup)
+        msb = bst["mean"]
         bcase.check()
         ktb, _ = kernel_times(bcase.step, max(2, args.profile_steps // 2))
-        batched = {"n_views": args.views, "ms_per_step": msb, "mpix_s": bcase.pixels / (msb * 1e-3) / 1e6,
+        batched = {"n_views": args.views, "ms_per_step": msb, "step_stats_ms": bst,
+                   "mpix_s": bcase.pixels / (msb * 1e-3) / 1e6,
                    "K": Kb, "visible": mvb, "max_list": maxb, "mean_list": meanb,
                    "kernels_ms": {k: round(v, 4) for k, v in ktb.items()}, "schedule": btuned}
         log(f"[bench] batched {args.views} views: {msb:.3f} ms -> {batched['mpix_s']:.1f} Mpix/s")
@@ -531,14 +627,30 @@ def main():
         del bcase
         torch.cuda.empty_cache()
 
+    sigma_half = None
+    if not args.no_sigma_half:
+        # the headline step at the paper's rendering exponent (sigma = 0.5, square-root window)
+        hcase = Case(raster, scenes, dev, w.poses, w.intr, w.target_poses, sigma=0.5)
+        htuned = None
+        if not args.no_tune:
+            from paper_2605_31419_amd import autotune
+            hbest, _ = autotune.tune(hcase.rast, hcase.poses, hcase.tc, hcase.td, reps=5)
+            hcase.rast.schedule = hbest
+            htuned = list(hbest)
+        hst = step_stats(hcase.step, args.steps, args.warmup)
+        hcase.check()
+        sigma_half = {"sigma": 0.5, "ms_per_step": hst["mean"], "mpix_s": hcase.pixels / (hst["mean"] * 1e-3) / 1e6,
+                      "step_stats_ms": hst, "schedule": htuned}
+        log(f"[bench] sigma = 0.5: {hst['mean']:.3f} ms -> {sigma_half['mpix_s']:.1f} Mpix/s")
+        del hcase
+
     tracking = None
     if not args.no_track:
         tracking = tracking_leg(raster, w, dev, schedule=single.rast.schedule)
         log(f"[bench] tracking graph: {tracking['ms_per_iteration']:.3f} ms/iteration over {tracking['iterations']}")
     serving = None
     if not args.no_serve:
-        serving = serving_leg(raster, w, dev, args.serve_queries)
-        log(f"[bench] serving: {json.dumps(serving)}")
+        serving = serving_leg(raster, w, dev, args.serve_queries, args.serve_warmup)
 
     configs = None if args.no_configs else configs_leg(raster, scenes, args.steps, args.warmup)
 
@@ -573,7 +685,7 @@ def main():
     out = {
         "metric": "fwd+bwd Mpix/s at 1200x680, 1M tris (1 view vs batched); p50/p99 render latency",
         "value": mpix, "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms, "ms_per_step_graph": ms_graph, "graph_vs_eager_rel": graph_dev,
+        "ms_per_step": ms, "step_stats_ms": head_stats, "ms_per_step_graph": ms_graph, "graph_vs_eager_rel": graph_dev,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"1200x680 single view, {args.faces}-face synthetic room soup "
@@ -590,6 +702,7 @@ def main():
         "unfused": {"ms_per_step": ms_unf, "mpix_s": single.pixels / (ms_unf * 1e-3) / 1e6,
                     "kernels_ms": {k: round(v, 4) for k, v in kt_unf.items()}},
         "batched": batched,
+        "sigma_0_5": sigma_half,
         "schedule": tuned,
         "tracking": tracking,
         "serving": serving,

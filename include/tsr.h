@@ -202,7 +202,22 @@ TSR_API int tsr_render_train_l1(const tsr_scene *scene, const float *poses, cons
 TSR_API int tsr_pose_step(float *poses, const float *grad_pose, int n_views, float lr_trans, float lr_rot,
                   void *stream);
 
-/* D-SSIM term of the photometric energy (Sec. 3.5, eq. 8).  Per view v,
+/* Left perturbation of poses (eq. 6): out_poses[v] = Exp(tau_v) T_v for tau [n_views][6] =
+ * (rho, theta), translation first, Exp of se(3) in closed form (Rodrigues rotation, SO(3) left
+ * Jacobian on rho), evaluated in FP64 and stored as float32.  poses and out_poses [n_views][12]
+ * may be the same buffer.  Errors: TSR_EINVAL for NULL pointers or n_views outside
+ * [1, TSR_MAX_VIEWS].  Enqueued on `stream`. */
+TSR_API int tsr_pose_compose(const float *tau, const float *poses, int n_views, float *out_poses, void *stream);
+
+/* Gradient with respect to tau of a loss evaluated at the composed pose Exp(tau) T (eqs. 6-7):
+ * given grad_pose [n_views][6], the left-perturbation gradient at Exp(tau) T that
+ * tsr_render_backward returns for those poses, writes grad_tau [n_views][6] = J_l(tau)^T
+ * grad_pose, J_l the left Jacobian of SE(3) (series of the se(3) adjoint, FP64).  At tau = 0
+ * J_l = I.  grad_tau may alias grad_pose.  Errors as tsr_pose_compose. */
+TSR_API int tsr_pose_tau_grad(const float *tau, const float *grad_pose, int n_views, float *grad_tau,
+                              void *stream);
+
+/* D-SSIM term of the photometric energy (Sec. 3.4, eq. 8).  Per view v,
  *   loss[v] = 1 - mean over its 3 channels and W H pixels of SSIM(p),
  *   SSIM = (2 mu_x mu_y + C1)(2 s_xy + C2) / ((mu_x^2 + mu_y^2 + C1)(s_x^2 + s_y^2 + C2)),
  * x the rendered colour, y the target, mu / s^2 / s_xy the local means, variances and
@@ -241,7 +256,7 @@ TSR_API int tsr_render_train_photometric(const tsr_scene *scene, const float *po
                                  float *grad_pos, float *grad_col, float *grad_opa, float *grad_pose,
                                  void *scratch, size_t scratch_bytes, void *stream);
 
-/* Equilateral regulariser (Sec. 3.5, eq. 14):
+/* Equilateral regulariser (Sec. 3.4, eq. 14):
  *   loss = (1/M) sum over faces (1/3) sum over corners (cos theta - 1/2)^2,
  * cos theta the dot product of the two unit edge vectors leaving the corner.  A face with a
  * zero-length edge contributes 0, gets no gradient and still counts in M (the paper leaves

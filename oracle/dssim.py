@@ -1,4 +1,4 @@
-"""FP64 reference of the D-SSIM term of the photometric energy (Sec. 3.5, eq. 8).
+"""FP64 reference of the D-SSIM term of the photometric energy (Sec. 3.4, eq. 8).
 
 TEST INFRASTRUCTURE ONLY: imported by the test-suite and the benchmark's oracle leg; it
 never imports the HIP package.

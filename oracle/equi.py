@@ -1,4 +1,4 @@
-"""FP64 reference of the equilateral regulariser E_equi (Sec. 3.5, eq. 14).
+"""FP64 reference of the equilateral regulariser E_equi (Sec. 3.4, eq. 14).
 
 TEST INFRASTRUCTURE ONLY: imported by the test-suite; it never imports the HIP package.
 

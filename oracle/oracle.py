@@ -57,6 +57,7 @@ def lib():
         _lib.orc_max_threads.restype = C.c_int
         _lib.orc_state.argtypes = [P, P, P, P, P, C.c_int64, C.c_double, P]
         _lib.orc_face_stats.argtypes = [P, P, P, P, C.c_double, P, P, P, P, P]
+        _lib.orc_min_rho.argtypes = [P, P, P, P, P, C.c_int64, P]
     return _lib
 
 
@@ -218,6 +219,19 @@ def state(scene, pose, intr, sigma=1.0, z_near=0.1, r_min=1e-3, pixels=None, rho
                          rho_eps, _ptr(out))
     if rc:
         raise ValueError(f"orc_state failed ({rc})")
+    return out
+
+
+def min_rho(scene, pose, intr, sigma=1.0, z_near=0.1, r_min=1e-3, pixels=None, opacity_min=False):
+    """Per pixel, the smallest |rho| = |phi/phi(s)| over the faces whose bounding box contains
+    it (+inf where none); |rho| < 1e-3 marks the steep-edge band of sigma < 1 windows."""
+    a = _Args(scene, pose, intr, sigma, z_near, r_min, opacity_min)
+    pix = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int64)
+    n = a.cam.width * a.cam.height if pix is None else pix.shape[0]
+    out = np.zeros(n)
+    rc = lib().orc_min_rho(C.byref(a.sc), _ptr(a.pose), C.byref(a.cam), C.byref(a.par), _ptr(pix), n, _ptr(out))
+    if rc:
+        raise ValueError(f"orc_min_rho failed ({rc})")
     return out
 
 

@@ -625,6 +625,36 @@ int orc_state(const orc_scene *s, const double *pose, const orc_cam *c, const or
     return ORC_OK;
 }
 
+/* Smallest |rho| = |phi/phi(s)| (eq. 3) over the faces whose bounding box contains each listed
+ * pixel (faces that pass the culls), +infinity where there is none.  For sigma < 1 the
+ * window's slope grows without bound as rho -> 0+, so pixels near any face's edge -- on
+ * either side, since an implementation that rounds rho differently may blend a face there
+ * that this oracle does not -- are where the gradient cannot be compared at a relative bar;
+ * tests exclude them on both sides. */
+int orc_min_rho(const orc_scene *s, const double *pose, const orc_cam *c, const orc_par *p,
+                const int64_t *pix, int64_t npix, double *min_rho) {
+    int rc = check_args(s, pose, c, p);
+    if (rc) return rc;
+    face_t *F = (face_t *)calloc((size_t)(s->n_faces ? s->n_faces : 1), sizeof(face_t));
+    setup_all(s, pose, c, p, F);
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < npix; k++) {
+        int64_t id = pix ? pix[k] : k;
+        int u = (int)(id % c->width), v = (int)(id / c->width);
+        double r = INFINITY;
+        for (int64_t m = 0; m < s->n_faces; m++) {
+            const face_t *f = &F[m];
+            if (!f->ok || !in_box(f, u, v)) continue;
+            double rho, lam[3];
+            face_window(f, p->sigma, u, v, &rho, lam);
+            if (fabs(rho) < r) r = fabs(rho);
+        }
+        min_rho[k] = r;
+    }
+    free(F);
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------------------------- per-face screen statistics */
 /* Map-management statistics of one view (Sec. 3.4: pruning by projected area, densification by
  * pixel coverage, keyframing by visibility), with the blending decisions of eq. 4 and the early

@@ -360,6 +360,20 @@ int tsr_pose_step(float* poses, const float* grad_pose, int n_views, float lr_tr
   return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_pose_step launch");
 }
 
+int tsr_pose_compose(const float* tau, const float* poses, int n_views, float* out_poses, void* stream) {
+  if (!tau || !poses || !out_poses) return fail(TSR_EINVAL, "tau, poses or out_poses is NULL");
+  if (n_views < 1 || n_views > TSR_MAX_VIEWS) return fail(TSR_EINVAL, "n_views = %d outside [1, %d]", n_views, TSR_MAX_VIEWS);
+  hipError_t e = tsr::launch_pose_compose(tau, poses, n_views, out_poses, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_pose_compose launch");
+}
+
+int tsr_pose_tau_grad(const float* tau, const float* grad_pose, int n_views, float* grad_tau, void* stream) {
+  if (!tau || !grad_pose || !grad_tau) return fail(TSR_EINVAL, "tau, grad_pose or grad_tau is NULL");
+  if (n_views < 1 || n_views > TSR_MAX_VIEWS) return fail(TSR_EINVAL, "n_views = %d outside [1, %d]", n_views, TSR_MAX_VIEWS);
+  hipError_t e = tsr::launch_pose_tau_grad(tau, grad_pose, n_views, grad_tau, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_pose_tau_grad launch");
+}
+
 int tsr_dssim_scratch_size(const tsr_intrinsics* intr, int n_views, size_t* bytes) {
   if (!bytes) return fail(TSR_EINVAL, "bytes is NULL");
   tsr::SsimTable t;

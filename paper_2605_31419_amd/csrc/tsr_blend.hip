@@ -138,6 +138,11 @@ __device__ __forceinline__ void wave_lds_sync() {
 //  * per wave: each wave loads its own copy into its own LDS area and walks the list at its
 //    own pace (no barriers; four copies are read).
 // Which one is faster depends on how often the caches already hold the records.
+// Cooperative kernels always run kBlock threads; the staging loops below stride by kBlock, so
+// a span of any length up to kSpan is staged completely (every entry's face id and record).
+static_assert(kSpan % kBatch == 0 && kSpan >= kBatch, "a staged span is walked as whole 64-face batches");
+static_assert(kSpan * (6 * sizeof(float4) + sizeof(uint32_t)) <= 48 * 1024, "a staged span fits the LDS budget");
+static_assert(kWaves * kWave == kBlock && kWaves == 4, "one wave per 8x8 quadrant of a 16x16 tile");
 __device__ __forceinline__ void stage_batch_block(const float* __restrict__ records, const uint64_t* __restrict__ pairs,
                                                   uint32_t b0, int n, float4* srec, uint32_t* sface) {
   for (int i = threadIdx.x; i < n * 6; i += kBlock) {
@@ -941,21 +946,32 @@ __global__ __launch_bounds__(kBlock) void k_finalize(ViewTable vt, const double*
   }
 }
 
-// ---------------------------------------------------------------------------- pose step
-// T <- Exp(delta) T with delta = -(lr_t g_rho, lr_r g_theta), Exp of se(3) in closed form
-// (Rodrigues for the rotation, the left Jacobian for the translation part).
-__global__ void k_pose_step(float* __restrict__ poses, const float* __restrict__ grad_pose, int n_views, float lr_t,
-                            float lr_r) {
-  const int v = threadIdx.x;
-  if (v >= n_views) return;
-  double rho[3], th[3];
-  for (int i = 0; i < 3; ++i) {
-    rho[i] = -(double)lr_t * (double)grad_pose[6 * v + i];
-    th[i] = -(double)lr_r * (double)grad_pose[6 * v + 3 + i];
+// Soups may hold more vertices than the 3 M of their faces: those vertices get zero gradients
+// (the vertex gather writes the faces' vertices only).
+__global__ void k_zero_soup_tail(float* __restrict__ gp, float* __restrict__ gc, float* __restrict__ go, int64_t N,
+                                 int64_t v0) {
+  const int64_t n = N - v0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (gp) gp[a * N + v0 + i] = 0.f;
+      if (gc) gc[a * N + v0 + i] = 0.f;
+    }
+    if (go) go[v0 + i] = 0.f;
   }
+}
+
+// ---------------------------------------------------------------------------- pose arithmetic
+// Exp of tau = (rho, theta) in se(3), applied on the left of (R, t) (eq. 6):
+//   R' = dR R,  t' = dR t + J rho,
+// dR = I + A K + B K^2 (Rodrigues), J = I + B K + C K^2 (the left Jacobian of SO(3)),
+// K = [theta]x, a = |theta|, A = sin a / a, B = (1 - cos a) / a^2, C = (a - sin a) / a^3
+// (two-term series below a = 1e-4, where the closed forms lose digits).
+__device__ void se3_exp_left(const double rho[3], const double th[3], const double R[9], const double t[3],
+                             double nR[9], double nt[3]) {
   const double a2 = th[0] * th[0] + th[1] * th[1] + th[2] * th[2];
   const double a = sqrt(a2);
-  double A, B, Cc;            // sin(a)/a, (1-cos a)/a^2, (a - sin a)/a^3
+  double A, B, Cc;
   if (a < 1e-4) {
     A = 1.0 - a2 / 6.0;
     B = 0.5 - a2 / 24.0;
@@ -969,23 +985,109 @@ __global__ void k_pose_step(float* __restrict__ poses, const float* __restrict__
   double K2[9];
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j) K2[3 * i + j] = K[3 * i] * K[j] + K[3 * i + 1] * K[3 + j] + K[3 * i + 2] * K[6 + j];
-  double dR[9], Vm[9];
+  double dR[9], Jm[9];
   for (int i = 0; i < 9; ++i) {
     const double I = (i % 4 == 0) ? 1.0 : 0.0;
     dR[i] = I + A * K[i] + B * K2[i];
-    Vm[i] = I + B * K[i] + Cc * K2[i];
+    Jm[i] = I + B * K[i] + Cc * K2[i];
   }
-  double R[9], t[3];
-  for (int i = 0; i < 9; ++i) R[i] = (double)poses[12 * v + i];
-  for (int i = 0; i < 3; ++i) t[i] = (double)poses[12 * v + 9 + i];
-  double nR[9], nt[3];
   for (int i = 0; i < 3; ++i) {
     for (int j = 0; j < 3; ++j) nR[3 * i + j] = dR[3 * i] * R[j] + dR[3 * i + 1] * R[3 + j] + dR[3 * i + 2] * R[6 + j];
-    nt[i] = dR[3 * i] * t[0] + dR[3 * i + 1] * t[1] + dR[3 * i + 2] * t[2] + Vm[3 * i] * rho[0] + Vm[3 * i + 1] * rho[1] +
-            Vm[3 * i + 2] * rho[2];
+    nt[i] = dR[3 * i] * t[0] + dR[3 * i + 1] * t[1] + dR[3 * i + 2] * t[2] + Jm[3 * i] * rho[0] + Jm[3 * i + 1] * rho[1] +
+            Jm[3 * i + 2] * rho[2];
   }
-  for (int i = 0; i < 9; ++i) poses[12 * v + i] = (float)nR[i];
-  for (int i = 0; i < 3; ++i) poses[12 * v + 9 + i] = (float)nt[i];
+}
+
+__device__ __forceinline__ void load_pose_f64(const float* __restrict__ pose, double R[9], double t[3]) {
+  for (int i = 0; i < 9; ++i) R[i] = (double)pose[i];
+  for (int i = 0; i < 3; ++i) t[i] = (double)pose[9 + i];
+}
+
+__device__ __forceinline__ void store_pose_f64(float* __restrict__ pose, const double R[9], const double t[3]) {
+  for (int i = 0; i < 9; ++i) pose[i] = (float)R[i];
+  for (int i = 0; i < 3; ++i) pose[9 + i] = (float)t[i];
+}
+
+// Tracking step: T <- Exp(delta) T with delta = -(lr_t g_rho, lr_r g_theta).
+__global__ void k_pose_step(float* __restrict__ poses, const float* __restrict__ grad_pose, int n_views, float lr_t,
+                            float lr_r) {
+  const int v = threadIdx.x;
+  if (v >= n_views) return;
+  double rho[3], th[3], R[9], t[3], nR[9], nt[3];
+  for (int i = 0; i < 3; ++i) {
+    rho[i] = -(double)lr_t * (double)grad_pose[6 * v + i];
+    th[i] = -(double)lr_r * (double)grad_pose[6 * v + 3 + i];
+  }
+  load_pose_f64(poses + 12 * v, R, t);
+  se3_exp_left(rho, th, R, t, nR, nt);
+  store_pose_f64(poses + 12 * v, nR, nt);
+}
+
+// Poses of Exp(tau_v) T_v for a perturbation tau [V][6] = (rho, theta).
+__global__ void k_pose_compose(const float* __restrict__ tau, const float* __restrict__ poses, int n_views,
+                               float* __restrict__ out) {
+  const int v = threadIdx.x;
+  if (v >= n_views) return;
+  double rho[3], th[3], R[9], t[3], nR[9], nt[3];
+  for (int i = 0; i < 3; ++i) {
+    rho[i] = (double)tau[6 * v + i];
+    th[i] = (double)tau[6 * v + 3 + i];
+  }
+  load_pose_f64(poses + 12 * v, R, t);
+  se3_exp_left(rho, th, R, t, nR, nt);
+  store_pose_f64(out + 12 * v, nR, nt);
+}
+
+// Gradient with respect to tau of a loss evaluated at Exp(tau) T, from its left-perturbation
+// gradient g at Exp(tau) T: Exp(tau + d) = Exp(J_l(tau) d) Exp(tau) to first order, so
+// dL/dtau = J_l(tau)^T g.  J_l(tau) = sum_n ad(tau)^n / (n+1)! with the se(3) adjoint
+// ad(rho, theta) = [[theta]x, [rho]x; 0, [theta]x] (translation first); the series is summed
+// in FP64 until its terms fall below 1e-17 of the running sum (at most 80 terms).
+__global__ void k_pose_tau_grad(const float* __restrict__ tau, const float* __restrict__ grad_pose, int n_views,
+                                float* __restrict__ grad_tau) {
+  const int v = threadIdx.x;
+  if (v >= n_views) return;
+  double ad[6][6];
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) ad[i][j] = 0.0;
+  const double r0 = tau[6 * v], r1 = tau[6 * v + 1], r2 = tau[6 * v + 2];
+  const double t0 = tau[6 * v + 3], t1 = tau[6 * v + 4], t2 = tau[6 * v + 5];
+  for (int b = 0; b < 2; ++b) {          // [theta]x on the two diagonal blocks
+    const int o = 3 * b;
+    ad[o][o + 1] = -t2; ad[o][o + 2] = t1;
+    ad[o + 1][o] = t2;  ad[o + 1][o + 2] = -t0;
+    ad[o + 2][o] = -t1; ad[o + 2][o + 1] = t0;
+  }
+  ad[0][4] = -r2; ad[0][5] = r1;          // [rho]x in the upper right block
+  ad[1][3] = r2;  ad[1][5] = -r0;
+  ad[2][3] = -r1; ad[2][4] = r0;
+  double term[6][6], J[6][6], nxt[6][6];
+  for (int i = 0; i < 6; ++i)
+    for (int j = 0; j < 6; ++j) term[i][j] = J[i][j] = (i == j) ? 1.0 : 0.0;
+  for (int n = 1; n <= 80; ++n) {        // term = ad^n / (n+1)!
+    double tmax = 0.0, jmax = 0.0;
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < 6; ++k) s += term[i][k] * ad[k][j];
+        nxt[i][j] = s / (double)(n + 1);
+      }
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) {
+        term[i][j] = nxt[i][j];
+        J[i][j] += term[i][j];
+        tmax = fmax(tmax, fabs(term[i][j]));
+        jmax = fmax(jmax, fabs(J[i][j]));
+      }
+    if (tmax <= 1e-17 * jmax) break;
+  }
+  double g[6];
+  for (int i = 0; i < 6; ++i) g[i] = (double)grad_pose[6 * v + i];   // (grad_tau may alias grad_pose)
+  for (int j = 0; j < 6; ++j) {
+    double s = 0.0;
+    for (int i = 0; i < 6; ++i) s += J[i][j] * g[i];
+    grad_tau[6 * v + j] = (float)s;
+  }
 }
 
 // ---------------------------------------------------------------------------- launchers
@@ -1167,6 +1269,9 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
     if (want_vertices)
       TSR_LAUNCH("vertex_gather", k_vertex_gather, dim3(grid_for(vt.n_faces, 256)), dim3(256), 0, st, sc, vt, counts,
                  grad_acc, grad_pos, grad_col, grad_opa, pose_acc, grad_pose, loss_acc, loss);
+    if (want_vertices && !sc.faces && N > 3 * vt.n_faces)
+      TSR_LAUNCH("zero_grads", k_zero_soup_tail, dim3(std::min<unsigned>(grid_for(N - 3 * vt.n_faces, 256), 1024u)),
+                 dim3(256), 0, st, grad_pos, grad_col, grad_opa, N, 3 * vt.n_faces);
   } else if (want_vertices && !sc.faces) {
     if (grad_pos) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(2048), dim3(256), 0, st, grad_pos, 3 * N);
     if (grad_col) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(2048), dim3(256), 0, st, grad_col, 3 * N);
@@ -1180,6 +1285,16 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
 
 hipError_t launch_pose_step(float* poses, const float* grad_pose, int n_views, float lr_t, float lr_r, hipStream_t st) {
   TSR_LAUNCH("pose_step", k_pose_step, dim3(1), dim3(64), 0, st, poses, grad_pose, n_views, lr_t, lr_r);
+  return hipGetLastError();
+}
+
+hipError_t launch_pose_compose(const float* tau, const float* poses, int n_views, float* out, hipStream_t st) {
+  TSR_LAUNCH("pose_compose", k_pose_compose, dim3(1), dim3(64), 0, st, tau, poses, n_views, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pose_tau_grad(const float* tau, const float* grad_pose, int n_views, float* grad_tau, hipStream_t st) {
+  TSR_LAUNCH("pose_tau_grad", k_pose_tau_grad, dim3(1), dim3(64), 0, st, tau, grad_pose, n_views, grad_tau);
   return hipGetLastError();
 }
 

@@ -164,7 +164,7 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
                            float* grad_opa, float* grad_pose, bool fused_train, const TrainSchedule& sched,
                            hipStream_t st);
 
-// D-SSIM (Sec. 3.5, eq. 8): output tile of the stencil kernels and the window radius.
+// D-SSIM (Sec. 3.4, eq. 8): output tile of the stencil kernels and the window radius.
 constexpr int kSsimTW = 32;
 constexpr int kSsimTH = 16;
 constexpr int kSsimR = 5;               // 11 x 11 window
@@ -192,7 +192,7 @@ hipError_t launch_photo_seeds(const SsimTable& t, const float* color, const floa
                               const float* tdepth, float w_ssim, float w_color, float w_depth, float* loss,
                               char* scratch, float** gcolor, float** gdepth, hipStream_t st);
 
-// Equilateral regulariser (Sec. 3.5, eq. 14): workgroups of one launch over M faces, and the
+// Equilateral regulariser (Sec. 3.4, eq. 14): workgroups of one launch over M faces, and the
 // launch (loss and/or gradient; `partial` holds one double per workgroup).
 int64_t equi_blocks(int64_t n_faces);
 // Partials of the allocation-free variant: one double per 256-face workgroup in a static
@@ -222,5 +222,8 @@ hipError_t launch_train_normal(const tsr_scene_dev& sc, const float* poses, cons
 
 hipError_t launch_pose_step(float* poses, const float* grad_pose, int n_views, float lr_t, float lr_r,
                             hipStream_t st);
+hipError_t launch_pose_compose(const float* tau, const float* poses, int n_views, float* out, hipStream_t st);
+hipError_t launch_pose_tau_grad(const float* tau, const float* grad_pose, int n_views, float* grad_tau,
+                                hipStream_t st);
 
 }  // namespace tsr

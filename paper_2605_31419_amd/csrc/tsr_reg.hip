@@ -1,4 +1,4 @@
-// Equilateral regulariser E_equi (Sec. 3.5, eq. 14): the mean over faces of the mean over the
+// Equilateral regulariser E_equi (Sec. 3.4, eq. 14): the mean over faces of the mean over the
 // three corners of (cos theta - 1/2)^2, cos theta the dot product of the unit edge vectors
 // leaving the corner, and its gradient with respect to the vertex positions.  A face with a
 // zero-length edge contributes 0 and gets no gradient (its angles are undefined).

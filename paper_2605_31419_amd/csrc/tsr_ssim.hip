@@ -1,4 +1,4 @@
-// D-SSIM term of the photometric energy (Sec. 3.5, eq. 8) on gfx950: per view, the loss
+// D-SSIM term of the photometric energy (Sec. 3.4, eq. 8) on gfx950: per view, the loss
 // 1 - mean SSIM over its three channels and pixels, and its gradient with respect to the
 // rendered colour.  SSIM(p) = (2 mu_x mu_y + C1)(2 s_xy + C2) / ((mu_x^2 + mu_y^2 + C1)
 // (s_x^2 + s_y^2 + C2)) over an 11 x 11 Gaussian window (standard deviation 1.5, weights

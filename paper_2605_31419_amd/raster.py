@@ -108,6 +108,9 @@ class Rasterizer:
         self.ws: Optional[torch.Tensor] = None
         self.capacity = 0
         self.schedule: Optional[Tuple[int, int, int]] = None   # (persistent, order, grid) for train_l1
+        # bumped by every call that rewrites the binning or the per-pixel state in the workspace
+        # (the autograd Function checks it between its forward and backward)
+        self.generation = 0
         if workspace is not None and workspace.numel() >= self.workspace_bytes(capacity):
             # caller-provided buffer (e.g. reused across requests): use all of it
             self.ws = workspace
@@ -136,6 +139,7 @@ class Rasterizer:
         if self.ws is not None and capacity <= self.capacity:
             return
         nbytes = self.workspace_bytes(capacity)
+        self.generation += 1
         self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         self.capacity = int(capacity)
         check(self.lib.tsr_workspace_init(_ptr(self.ws), C.c_size_t(nbytes), _stream()), "tsr_workspace_init")
@@ -145,6 +149,7 @@ class Rasterizer:
                 _ptr(self.ws), C.c_size_t(self.ws.numel()))
 
     def count(self, poses: torch.Tensor, stream=None) -> int:
+        self.generation += 1
         k = C.c_int64(0)
         check(self.lib.tsr_count(*self._args(poses), _stream(stream), C.byref(k)), "tsr_count")
         return int(k.value)
@@ -157,6 +162,7 @@ class Rasterizer:
 
     # ----------------------------------------------------------------- C ABI calls
     def bin_and_sort(self, poses: torch.Tensor, stream=None, check_capacity: bool = True) -> None:
+        self.generation += 1
         check(self.lib.tsr_bin_and_sort(*self._args(poses), _stream(stream)), "tsr_bin_and_sort")
         if check_capacity:
             rc = self.lib.tsr_check(_ptr(self.ws), _stream(stream), None)
@@ -168,6 +174,7 @@ class Rasterizer:
                 check(rc, "tsr_check")
 
     def forward(self, poses: torch.Tensor, color=None, depth=None, trans=None, stream=None):
+        self.generation += 1
         P = self.total_pixels
         color = color if color is not None else torch.empty(3 * P, device=self.device)
         depth = depth if depth is not None else torch.empty(P, device=self.device)
@@ -193,6 +200,7 @@ class Rasterizer:
 
     def train_l1(self, poses: torch.Tensor, target_color, target_depth, color=None, depth=None, trans=None,
                  loss=None, out=None, schedule=None, stream=None):
+        self.generation += 1
         gp, gc, go, gpose = out if out is not None else self.grad_buffers()
         sched = self.schedule if schedule is None else schedule
         sp = None if sched is None else C.byref(TsrSchedule(*sched))
@@ -213,6 +221,7 @@ class Rasterizer:
                           color=None, depth=None, trans=None, loss=None, out=None, stream=None):
         """Forward, the full loss of eqs. 8 and 10 (L1 colour, D-SSIM, masked L1 depth) and its
         backward (``tsr_render_train_photometric``)."""
+        self.generation += 1
         P = self.total_pixels
         color = color if color is not None else torch.empty(3 * P, device=self.device)
         depth = depth if depth is not None else torch.empty(P, device=self.device)
@@ -243,6 +252,7 @@ class Rasterizer:
         and back-propagates w_norm * mean(1 - N . N_bar); returns (grad_pos, grad_opa,
         grad_pose), written or (``accumulate``) added into ``out``.  Leaves the workspace binned
         for the normal-coloured soup."""
+        self.generation += 1
         if getattr(self, "_nscratch", None) is None:
             nb = C.c_size_t()
             check(self.lib.tsr_normal_scratch_size(C.byref(self._cscene), self._cintr, self.n_views, C.byref(nb)),
@@ -370,62 +380,69 @@ def sensor_normals(depth: torch.Tensor, intrs: Sequence, normals: Optional[torch
 
 # ---------------------------------------------------------------------------- autograd
 
-def _exp_se3_left(tau: torch.Tensor, poses: torch.Tensor) -> torch.Tensor:
-    """Poses of Exp(tau) o T for tau [V, 6] = (rho, theta) (torch, small-angle safe)."""
-    V = tau.shape[0]
-    rho, th = tau[:, :3].double(), tau[:, 3:].double()
-    a = th.norm(dim=1, keepdim=True)
-    K = torch.zeros(V, 3, 3, dtype=torch.float64, device=tau.device)
-    K[:, 0, 1], K[:, 0, 2], K[:, 1, 2] = -th[:, 2], th[:, 1], -th[:, 0]
-    K[:, 1, 0], K[:, 2, 0], K[:, 2, 1] = th[:, 2], -th[:, 1], th[:, 0]
-    a2 = (a * a).unsqueeze(-1)
-    small = a2 < 1e-12
-    A = torch.where(small, 1 - a2 / 6, torch.sin(a).unsqueeze(-1) / a.unsqueeze(-1).clamp_min(1e-30))
-    B = torch.where(small, 0.5 - a2 / 24, (1 - torch.cos(a)).unsqueeze(-1) / a2.clamp_min(1e-30))
-    Cc = torch.where(small, 1 / 6 - a2 / 120, (a - torch.sin(a)).unsqueeze(-1) / (a2 * a.unsqueeze(-1)).clamp_min(1e-30))
-    I = torch.eye(3, dtype=torch.float64, device=tau.device).expand(V, 3, 3)
-    KK = K @ K
-    dR = I + A * K + B * KK
-    Vm = I + B * K + Cc * KK
-    P = poses.double().reshape(V, 12)
-    R = P[:, :9].reshape(V, 3, 3)
-    t = P[:, 9:]
-    R2 = dR @ R
-    t2 = (dR @ t.unsqueeze(-1)).squeeze(-1) + (Vm @ rho.unsqueeze(-1)).squeeze(-1)
-    return torch.cat([R2.reshape(V, 9), t2], dim=1).float().contiguous()
+def compose_poses(tau: torch.Tensor, poses: torch.Tensor, stream=None) -> torch.Tensor:
+    """Poses of Exp(tau) o T for tau [V, 6] = (rho, theta) (``tsr_pose_compose``)."""
+    lib = _lib.load()
+    tau = tau.detach().to(torch.float32).contiguous()
+    poses = poses.detach().to(torch.float32).reshape(-1, 12).contiguous()
+    if tau.shape != (poses.shape[0], 6):
+        raise ValueError(f"tau must be [{poses.shape[0]}, 6]")
+    out = torch.empty_like(poses)
+    check(lib.tsr_pose_compose(_ptr(tau), _ptr(poses), poses.shape[0], _ptr(out), _stream(stream)),
+          "tsr_pose_compose")
+    return out
+
+
+def tau_gradient(tau: torch.Tensor, grad_pose: torch.Tensor, stream=None) -> torch.Tensor:
+    """dL/dtau = J_l(tau)^T grad_pose for a loss evaluated at Exp(tau) o T (``tsr_pose_tau_grad``)."""
+    lib = _lib.load()
+    tau = tau.detach().to(torch.float32).contiguous()
+    g = grad_pose.detach().to(torch.float32).reshape(-1, 6).contiguous()
+    out = torch.empty_like(g)
+    check(lib.tsr_pose_tau_grad(_ptr(tau), _ptr(g), g.shape[0], _ptr(out), _stream(stream)), "tsr_pose_tau_grad")
+    return out
 
 
 class TriangleRasterFn(torch.autograd.Function):
     """Differentiable render: forward = bin_and_sort + render_forward (the workspace keeps
     the binning and each pixel's last-face state, not per-pixel blend lists); backward =
-    render_backward (transmittance recovered by division, Sec. 3.3)."""
+    render_backward (transmittance recovered by division, Sec. 3.3).  The pose enters as
+    Exp(tau) o T (eq. 6); the pose gradient of the composed pose is mapped to tau through the
+    left Jacobian of SE(3), so tau need not be zero.  The backward refuses to run once the
+    rasterizer's workspace has been re-binned or re-rendered by another call."""
 
     @staticmethod
     def forward(ctx, pos, col, opa, tau, rast: Rasterizer, poses: torch.Tensor):
-        eff = poses if tau is None else _exp_se3_left(tau.detach(), poses)
+        eff = poses if tau is None else compose_poses(tau, poses)
         rast.bin_and_sort(eff)
         color, depth, trans = rast.forward(eff)
         ctx.rast = rast
-        ctx.save_for_backward(eff)
+        ctx.generation = rast.generation
+        ctx.save_for_backward(eff, tau.detach() if tau is not None else None)
         ctx.has_tau = tau is not None
         return color, depth, trans
 
     @staticmethod
     def backward(ctx, g_color, g_depth, g_trans):
-        (eff,) = ctx.saved_tensors
+        eff, tau = ctx.saved_tensors
         rast: Rasterizer = ctx.rast
+        if rast.generation != ctx.generation:
+            raise RuntimeError("TriangleRasterFn.backward: the rasterizer's workspace was re-binned or re-rendered "
+                               "after this forward (call backward before the next render, or use one Rasterizer "
+                               "per pending graph)")
         g_color = g_color.contiguous() if g_color is not None else torch.zeros(3 * rast.total_pixels, device=eff.device)
         g_depth = g_depth.contiguous() if g_depth is not None else torch.zeros(rast.total_pixels, device=eff.device)
         g_trans = g_trans.contiguous() if g_trans is not None else None
         gp, gc, go, gpose = rast.backward(eff, g_color, g_depth, g_trans)
         N = rast.scene.n_vertices
-        gtau = gpose.view(rast.n_views, 6) if ctx.has_tau else None
+        gtau = tau_gradient(tau, gpose) if ctx.has_tau else None
         return gp.view(3, N), gc.view(3, N), go.view(N), gtau, None, None
 
 
 def rasterize(rast: Rasterizer, poses: torch.Tensor, tau: Optional[torch.Tensor] = None):
     """Differentiable colour [3P], depth [P], transmittance [P] (packed per view) of the
     rasterizer's scene.  Gradients flow to rast.scene.pos / col / opa (when they require
-    grad) and to ``tau`` ([V, 6] se(3) left perturbation at which T_CW is evaluated)."""
+    grad) and to ``tau`` ([V, 6] se(3) left perturbation: the scene is rendered at
+    Exp(tau) o T_CW)."""
     sc = rast.scene
     return TriangleRasterFn.apply(sc.pos, sc.col, sc.opa, tau, rast, poses)

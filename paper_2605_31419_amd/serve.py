@@ -5,14 +5,19 @@ query and summarised as p50 / p99 beside throughput.
 
 Structure
   * ``Request``: one query (intrinsics, pose) with arrival / completion timestamps.
-  * ``Server``: an admission queue and ``n_slots`` worker threads.  A request is admitted when
-    its memory estimate fits in what the budget has left; a worker that becomes free takes as
-    many admitted requests as fit its batch limits (FIFO), launches them as one multi-view
-    call on its own stream, waits for that stream only, then releases the memory and completes
-    the requests.  Requests arriving while batches run are admitted as memory frees up, so
-    work from different arrivals overlaps on the device.
+  * ``Server``: an admission queue and ``n_slots`` worker threads.  The device-memory budget
+    covers two things: each slot's workspace, sized once when the server starts (the largest
+    batch whose workspace and outputs fit n_slots times in the budget) and charged for the
+    server's lifetime; and the outputs (colour, depth, transmittance) of every admitted
+    request, charged at admission and released at completion.  A worker that becomes free
+    takes as many admitted requests as fit its batch limits and its slot's workspace (FIFO),
+    launches them as one multi-view call on its own stream, waits for that stream only, then
+    releases the memory and completes the requests.  Requests arriving while batches run are
+    admitted as memory frees up, so work from different arrivals overlaps on the device.
+    Completed outputs belong to the caller (``keep_outputs``) or are dropped.
   * ``GpuExecutor``: runs a batch through the C ABI (tsr_bin_and_sort + tsr_render_forward)
-    on the worker's stream; ``FakeExecutor`` (tests) sleeps instead.
+    on the worker's stream in the slot's fixed workspace; a batch whose pairs overflow it is
+    split in halves.  ``FakeExecutor`` (tests) sleeps instead.
 """
 from __future__ import annotations
 
@@ -59,16 +64,14 @@ class FakeExecutor:
         self.active = 0
         self.max_active = 0
 
-    def _workspace_bytes(self, intrs, cap) -> int:
-        import ctypes as C
+    def setup(self, n_slots: int, budget: int, max_views: int, max_pixels: int):
+        return 0, max_views
 
-        from ._lib import check, load
+    def batch_fits(self, intrs) -> bool:
+        return True
 
-        out = C.c_size_t(0)
-        sc = self.scene.c()
-        check(load().tsr_workspace_size(C.byref(sc), self.raster.intrinsics_array(intrs), len(intrs), cap,
-                                        C.byref(out)), "tsr_workspace_size")
-        return int(out.value)
+    def request_error(self, req: Request) -> Optional[str]:
+        return None
 
     def estimate_bytes(self, req: Request) -> int:
         return 20 * req.pixels
@@ -92,9 +95,12 @@ class FakeExecutor:
 
 
 class GpuExecutor:
-    """Executes batches through the rasterizer on per-slot HIP streams."""
+    """Executes batches through the rasterizer on per-slot HIP streams, each slot with one
+    workspace buffer sized when the server starts."""
 
-    def __init__(self, dev_scene, params=None, pairs_per_tile: float = 160.0):
+    OUT_BYTES_PER_PIXEL = 20          # colour (12), depth (4), transmittance (4)
+
+    def __init__(self, dev_scene, params=None, pairs_per_tile: float = 160.0, max_resolution=(1200, 680)):
         import torch
 
         from . import raster
@@ -103,9 +109,11 @@ class GpuExecutor:
         self.raster = raster
         self.scene = dev_scene
         self.params = params or raster.Params()
-        self.pairs_per_tile = pairs_per_tile          # capacity estimate, corrected on overflow
+        self.pairs_per_tile = pairs_per_tile          # capacity estimate, raised on overflow
+        self.max_resolution = tuple(max_resolution)
         self.lock = threading.Lock()
         self.retries = 0
+        self.slot_bytes = 0
 
     def _capacity(self, intrs) -> int:
         tiles = sum(((i.width + 15) // 16) * ((i.height + 15) // 16) for i in intrs)
@@ -122,61 +130,86 @@ class GpuExecutor:
                                         C.byref(out)), "tsr_workspace_size")
         return int(out.value)
 
+    def setup(self, n_slots: int, budget: int, max_views: int, max_pixels: int):
+        """Slot workspace size: the largest batch of v <= max_views views at max_resolution
+        whose workspace plus outputs fit n_slots times in the budget.  Returns (bytes the
+        slots hold for the server's lifetime, v)."""
+        from .scenes import intrinsics_for
+
+        intr = intrinsics_for(*self.max_resolution)
+        px = intr.width * intr.height
+        for v in range(max(1, max_views), 0, -1):
+            if v > 1 and v * px > max_pixels:
+                continue
+            ws = self._workspace_bytes([intr] * v, self._capacity([intr] * v))
+            if n_slots * (ws + v * px * self.OUT_BYTES_PER_PIXEL) <= budget:
+                self.slot_bytes = ws
+                return n_slots * ws, v
+        raise ValueError(f"a budget of {budget} B cannot hold {n_slots} slot workspaces of one "
+                         f"{intr.width}x{intr.height} view each")
+
+    def batch_fits(self, intrs) -> bool:
+        return self._workspace_bytes(intrs, self._capacity(intrs)) <= self.slot_bytes
+
+    def request_error(self, req: Request) -> Optional[str]:
+        if not self.batch_fits([req.intr]):
+            return f"a {req.intr.width}x{req.intr.height} view needs more workspace than a slot's {self.slot_bytes} B"
+        return None
+
     def estimate_bytes(self, req: Request) -> int:
-        # workspace of a one-view call plus outputs (colour, depth, transmittance)
-        import ctypes as C
-
-        from ._lib import check, load
-
-        lib = load()
-        out = C.c_size_t(0)
-        sc = self.scene.c()
-        check(lib.tsr_workspace_size(C.byref(sc), self.raster.intrinsics_array([req.intr]), 1,
-                                     self._capacity([req.intr]), C.byref(out)), "tsr_workspace_size")
-        return int(out.value) + 5 * 4 * req.pixels
+        return self.OUT_BYTES_PER_PIXEL * req.pixels
 
     def make_slot(self, i: int):
-        # a stream and a workspace buffer reused by every batch of this slot
-        return {"stream": self.torch.cuda.Stream(), "ws": None}
+        # a stream and the workspace buffer every batch of this slot reuses
+        return {"stream": self.torch.cuda.Stream(),
+                "ws": self.torch.empty(self.slot_bytes, dtype=self.torch.uint8, device="cuda")}
 
-    def run(self, slot, batch: List[Request]) -> None:
+    def _render(self, slot, batch: List[Request]) -> None:
         torch, raster = self.torch, self.raster
         stream = slot["stream"]
         intrs = [r.intr for r in batch]
-        with torch.cuda.stream(stream):
-            cap = self._capacity(intrs)
-            need = self._workspace_bytes(intrs, cap)
-            if slot["ws"] is None or slot["ws"].numel() < need:
-                slot["ws"] = torch.empty(int(need * 1.25), dtype=torch.uint8, device="cuda")
-            rast = raster.Rasterizer(self.scene, intrs, self.params, capacity=cap, workspace=slot["ws"])
-            poses = raster.poses_tensor([r.pose for r in batch])
-            rast.bin_and_sort(poses, stream=stream, check_capacity=False)
-            color, depth, _ = rast.forward(poses, stream=stream)
-            rc = rast.lib.tsr_check(raster._ptr(rast.ws), raster._stream(stream), None)   # syncs this stream
-            if rc != 0:                              # capacity estimate too small: exact count, redo
-                k = rast.fit(poses, slack=1.1)      # grows this slot's workspace
-                tiles = sum(((i.width + 15) // 16) * ((i.height + 15) // 16) for i in intrs)
-                with self.lock:
-                    self.retries += 1
-                    # later batches (and admission) start from the density seen here
-                    self.pairs_per_tile = max(self.pairs_per_tile, 1.1 * k / max(tiles, 1))
-                slot["ws"] = rast.ws
-                rast.bin_and_sort(poses, stream=stream, check_capacity=True)
-                color, depth, _ = rast.forward(poses, stream=stream)
-                stream.synchronize()
+        if self._workspace_bytes(intrs, 0) > slot["ws"].numel():
+            raise RuntimeError("batch does not fit the slot's workspace")
+        rast = raster.Rasterizer(self.scene, intrs, self.params, workspace=slot["ws"])
+        poses = raster.poses_tensor([r.pose for r in batch])
+        rast.bin_and_sort(poses, stream=stream, check_capacity=False)
+        color, depth, _ = rast.forward(poses, stream=stream)
+        rc = rast.lib.tsr_check(raster._ptr(rast.ws), raster._stream(stream), None)   # syncs this stream
+        if rc == raster._lib.TSR_ECAPACITY:
+            # more pairs than the slot's buffer holds: raise the density estimate for later
+            # batches and admission, and render the batch in halves
+            k = rast.count(poses, stream=stream)
+            tiles = sum(((i.width + 15) // 16) * ((i.height + 15) // 16) for i in intrs)
+            with self.lock:
+                self.retries += 1
+                self.pairs_per_tile = max(self.pairs_per_tile, 1.1 * k / max(tiles, 1))
+            if len(batch) == 1:
+                raise RuntimeError(f"one view with {k} pairs does not fit a slot's workspace ({rast.capacity} pairs)")
+            del rast, color, depth
+            h = len(batch) // 2
+            self._render(slot, batch[:h])
+            self._render(slot, batch[h:])
+            return
+        raster.check(rc, "tsr_check")
         cs, ds = rast.split_views(color, 3), rast.split_views(depth, 1)
         for r, c, d in zip(batch, cs, ds):
             r.color, r.depth = c, d[0]
-        del rast
+
+    def run(self, slot, batch: List[Request]) -> None:
+        with self.torch.cuda.stream(slot["stream"]):
+            self._render(slot, batch)
 
 
 class Server:
     def __init__(self, executor, n_slots: int = 4, mem_budget: int = 8 << 30, max_batch_views: int = 8,
-                 max_batch_pixels: int = 8 * 1200 * 680, clock: Callable[[], float] = time.perf_counter):
+                 max_batch_pixels: int = 8 * 1200 * 680, clock: Callable[[], float] = time.perf_counter,
+                 keep_outputs: bool = True):
         self.ex = executor
         self.n_slots = n_slots
         self.budget = mem_budget
         self.used = 0
+        self.fixed = 0                  # slot workspaces, charged while the server runs
+        self.keep_outputs = keep_outputs
         self.max_views = max_batch_views
         self.max_pixels = max_batch_pixels
         self.clock = clock
@@ -192,6 +225,12 @@ class Server:
 
     # ------------------------------------------------------------------ public
     def start(self) -> None:
+        fixed, views = self.ex.setup(self.n_slots, self.budget, self.max_views, self.max_pixels)
+        with self.cv:
+            self.fixed = int(fixed)
+            self.max_views = min(self.max_views, int(views))
+            self.used += self.fixed
+            self.peak_used = max(self.peak_used, self.used)
         for i in range(self.n_slots):
             slot = self.ex.make_slot(i)
             t = threading.Thread(target=self._worker, args=(slot,), daemon=True)
@@ -201,9 +240,13 @@ class Server:
     def submit(self, req: Request) -> Request:
         req.arrival = self.clock()
         req.nbytes = self.ex.estimate_bytes(req)
+        err = self.ex.request_error(req)
         with self.cv:
-            if req.nbytes > self.budget:
-                req.error = f"request needs {req.nbytes} B, above the whole budget of {self.budget} B"
+            if err is None and req.nbytes > self.budget - self.fixed:
+                err = (f"request needs {req.nbytes} B, above the budget of {self.budget} B less the "
+                       f"{self.fixed} B the slots hold")
+            if err is not None:
+                req.error = err
                 req.done = self.clock()
                 self.completed.append(req)
                 req.event.set()
@@ -228,6 +271,9 @@ class Server:
             self.cv.notify_all()
         for t in self.threads:
             t.join(timeout=10)
+        with self.cv:
+            self.used -= self.fixed
+            self.fixed = 0
 
     def stats(self) -> dict:
         ok = [r for r in self.completed if r.error is None]
@@ -235,11 +281,12 @@ class Server:
         if not ok:
             return {"completed": 0, "errors": len(self.completed)}
         span = max(r.done for r in ok) - min(r.arrival for r in ok)
-        return {"completed": len(ok), "errors": len(self.completed) - len(ok),
+        return {"completed": len(ok), "errors": len(self.completed) - len(ok), "samples": int(lat.size),
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "mean_ms": float(lat.mean()), "qps": len(ok) / span if span > 0 else float("nan"),
                 "mpix_s": sum(r.pixels for r in ok) / span / 1e6 if span > 0 else float("nan"),
-                "peak_mem": self.peak_used, "peak_inflight_batches": self.peak_inflight}
+                "peak_mem": self.peak_used, "peak_inflight_batches": self.peak_inflight,
+                "max_batch_views": self.max_views}
 
     # ------------------------------------------------------------------ internals
     def _admit_locked(self) -> None:
@@ -254,7 +301,7 @@ class Server:
         batch, px = [], 0
         while self.ready and len(batch) < self.max_views:
             r = self.ready[0]
-            if batch and px + r.pixels > self.max_pixels:
+            if batch and (px + r.pixels > self.max_pixels or not self.ex.batch_fits([q.intr for q in batch + [r]])):
                 break
             batch.append(self.ready.popleft())
             px += r.pixels
@@ -279,6 +326,8 @@ class Server:
             with self.cv:
                 for r in batch:
                     r.done = now
+                    if not self.keep_outputs:
+                        r.color = r.depth = None
                     self.used -= r.nbytes
                     self.completed.append(r)
                     r.event.set()

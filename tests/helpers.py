@@ -72,11 +72,18 @@ def grad_close(g, ref, rel=1e-3, abs_frac=1e-5, name="", cond=None):
     inf = np.max(np.abs(ref)) if ref.size else 0.0
     norm_ok = np.linalg.norm(g - ref) <= rel * nr + 1e-30
     floor = abs_frac * inf + 1e-30
+    err = np.abs(g - ref)
+    base_bar = rel * np.abs(ref) + floor
+    n_cond = 0
     if cond is not None:
         floor = floor + COND_ULPS * np.asarray(cond, np.float64).reshape(-1)
-    bad = np.nonzero(np.abs(g - ref) > rel * np.abs(ref) + floor)[0]
+        # elements inside the bar only thanks to the rounding allowance of their conditioning
+        n_cond = int(np.count_nonzero((err > base_bar) & (err <= rel * np.abs(ref) + floor)))
+    bad = np.nonzero(err > rel * np.abs(ref) + floor)[0]
     msg = (f"{name}: |d|/|ref| = {np.linalg.norm(g - ref) / max(nr, 1e-300):.3e}, "
            f"{bad.size} elementwise outliers of {g.size}")
+    if cond is not None:
+        msg += f", {n_cond} within the bar only through the conditioning allowance"
     if bad.size:
         worst = bad[np.argsort(-np.abs(g[bad] - ref[bad]))[:5]]
         msg += " [" + "; ".join(f"i={i} got={g[i]:.6e} ref={ref[i]:.6e}" for i in worst) + f"] max|ref|={inf:.3e}"

@@ -1,4 +1,4 @@
-"""GPU parity of the D-SSIM term (Sec. 3.5, eq. 8) against the FP64 reference: per-view loss
+"""GPU parity of the D-SSIM term (Sec. 3.4, eq. 8) against the FP64 reference: per-view loss
 and colour gradient through the C ABI, on images smaller than the window, ragged tile
 edges, several views of different sizes and the 1200 x 680 frame.
 
@@ -6,8 +6,8 @@ Tolerances.  The kernel computes in FP32; its largest error is the cancellation 
 s^2 = E[x^2] - mu^2, about 22 roundings of values <= 1 (two 11-tap passes), i.e. ~1e-6
 absolute against a denominator >= C2 = 9e-4: a relative error of up to ~1e-3 in SSIM(p) and
 in the gradient maps at the flattest pixels, averaging out over the image.  Hence the loss
-to 2e-5 absolute and the gradient to 2e-3 relative (norm and element-wise, with a floor of
-1e-3 of the largest entry for entries that nearly cancel)."""
+to 2e-5 absolute and the gradient to 1e-3 relative (norm and element-wise, with a floor of
+1e-5 of the largest entry)."""
 import numpy as np
 import pytest
 import torch
@@ -20,8 +20,8 @@ from tests.helpers import grad_close
 pytestmark = pytest.mark.gpu
 
 LOSS_ATOL = 2e-5
-GRAD_REL = 2e-3
-GRAD_FLOOR = 1e-3
+GRAD_REL = 1e-3
+GRAD_FLOOR = 1e-5
 
 
 def _say(*a):

@@ -1,4 +1,4 @@
-"""GPU parity of the equilateral regulariser (Sec. 3.5, eq. 14) against the FP64 reference:
+"""GPU parity of the equilateral regulariser (Sec. 3.4, eq. 14) against the FP64 reference:
 soups of 1 face to the 1M-face map, an indexed mesh with shared vertices, degenerate faces,
 accumulate mode and the empty scene.  The kernel computes each face in FP64 and stores FP32
 gradients, so gradients agree to FP32 rounding (1e-6 relative, floor 1e-7 of the largest

@@ -2,11 +2,13 @@
 
 * Tile lists: bit-exact against the oracle binner for the whole frame(s).
 * Images: seeded pixel samples (random pixels plus two whole tiles per view) within 1e-4.
-* Gradients: the complete gradients of a seeded sample of visible faces -- a face's
+* Gradients: the complete gradients of a seeded sample of visible faces -- small ones and,
+  on the mixed-size map, 5-20 cm ones whose rectangles cover thousands of pixels -- (a face's
   gradient only involves the pixels of its bounding rectangle, so the oracle backward over
-  the union of those rectangles gives them exactly -- within 1e-3 relative.  The pose
-  gradient, which involves every pixel, is checked through the exact identity of eq. 7 that
-  ties it to the vertex gradients.
+  the union of those rectangles gives them exactly) within 1e-3 relative, through the fused
+  training step under each tile schedule.  Through the separate backward, with upstream
+  gradients that vanish outside that union, every vertex gradient and every view's pose
+  gradient are those of the oracle backward over the union: compared in full.
 Targets are seeded uniform images; those inside the checked rectangles are nudged at least
 1e-3 away from the oracle render so the L1 sign is the same in FP32 and FP64.
 """
@@ -87,19 +89,26 @@ def _rect_pixels(rect, m, W):
     return (ys * W + xs).reshape(-1)
 
 
-@pytest.mark.parametrize("name", ["track_640x480", "track_1200x680_1M", "window_8x1200x680"])
-def test_fullsize_train_step_sampled_faces(name):
-    _say(f"[fullsize train] case={name}")
-    w = _workload(name)
-    V = len(w.poses)
-    g = np.random.default_rng(77)
-    # faces to check: visible in view 0, small enough for the oracle (rect <= 400 pixels)
+def _sample_faces(w, g):
+    """Faces visible in view 0: 24 with rectangles of at most 400 pixels and, where the map
+    has them, 3 with rectangles of 2,000-20,000 pixels (the 5-20 cm faces)."""
     q, f, rect, tiles = O.project(w.scene, w.poses[0], w.intr[0])
     area = (rect[1] - rect[0] + 1) * (rect[3] - rect[2] + 1)
-    cand = np.nonzero((tiles > 0) & (area <= 400))[0]
-    faces = np.sort(g.choice(cand, size=min(24, cand.size), replace=False))
+    small = np.nonzero((tiles > 0) & (area <= 400))[0]
+    large = np.nonzero((tiles > 0) & (area >= 2000) & (area <= 20000))[0]
+    pick = [g.choice(small, size=min(24, small.size), replace=False)]
+    if large.size:
+        pick.append(g.choice(large, size=min(3, large.size), replace=False))
+    faces = np.sort(np.concatenate(pick))
+    _say(f"  sampled faces: {faces.size} ({min(3, large.size)} large), rect pixels {int(area[faces].sum())}")
+    return faces
+
+
+def _regions_and_targets(w, faces, g):
+    """Per view: the union of the sampled faces' rectangles, seeded targets nudged at least
+    1e-3 away from the oracle render inside it, and the oracle's L1 seeds there."""
     tcs, tds, seeds, regions = [], [], [], []
-    for v in range(V):
+    for v in range(len(w.poses)):
         intr = w.intr[v]
         W, H = intr.width, intr.height
         tc = g.uniform(0, 1, size=(3, H * W)).astype(np.float32)
@@ -124,14 +133,38 @@ def test_fullsize_train_step_sampled_faces(name):
         regions.append(reg)
         tcs.append(tc)
         tds.append(td)
+    return tcs, tds, seeds, regions
+
+
+def _oracle_region_backward(w, seeds, regions):
+    """Oracle gradients over the region pixels, and each element's sum of absolute per-pixel
+    contributions (the conditioning that bounds FP32 rounding of a cancelling sum)."""
     N = w.scene.n_vertices
     ref_p = np.zeros((3, N)); ref_c = np.zeros((3, N)); ref_o = np.zeros(N)
-    for v in range(V):
+    abs_p = np.zeros((3, N)); abs_c = np.zeros((3, N)); abs_o = np.zeros(N)
+    poses = []
+    for v in range(len(w.poses)):
         if seeds[v] is None:
+            poses.append(np.zeros(6))
             continue
-        rp, rc, ro, _ = O.backward(w.scene, w.poses[v], w.intr[v], seeds[v][0], seeds[v][1], None,
-                                   pixels=regions[v])
+        rp, rc, ro, rpose, (ap, ac, ao) = O.backward(w.scene, w.poses[v], w.intr[v], seeds[v][0], seeds[v][1],
+                                                     None, pixels=regions[v], with_abs=True)
         ref_p += rp; ref_c += rc; ref_o += ro
+        abs_p += ap; abs_c += ac; abs_o += ao
+        poses.append(rpose)
+    return ref_p, ref_c, ref_o, np.concatenate(poses), (abs_p, abs_c, abs_o)
+
+
+@pytest.mark.parametrize("name", ["track_640x480", "track_1200x680_1M", "window_8x1200x680"])
+def test_fullsize_train_step_sampled_faces(name):
+    _say(f"[fullsize train] case={name}")
+    w = _workload(name)
+    V = len(w.poses)
+    g = np.random.default_rng(77)
+    faces = _sample_faces(w, g)
+    tcs, tds, seeds, regions = _regions_and_targets(w, faces, g)
+    N = w.scene.n_vertices
+    ref_p, ref_c, ref_o, _, (abs_p, abs_c, abs_o) = _oracle_region_backward(w, seeds, regions)
     vid = (3 * faces[:, None] + np.arange(3)[None, :]).reshape(-1)
     rast, p = G.make(w.scene, w.intr, w.poses)
     rast.bin_and_sort(p)
@@ -144,9 +177,10 @@ def test_fullsize_train_step_sampled_faces(name):
         torch.cuda.synchronize()
         gp, gc, go, gpose = [x.cpu().numpy().astype(np.float64) for x in out]
         gp, gc = gp.reshape(3, N), gc.reshape(3, N)
-        for nm, a, b in [("grad_pos", gp[:, vid], ref_p[:, vid]), ("grad_col", gc[:, vid], ref_c[:, vid]),
-                         ("grad_opa", go[vid], ref_o[vid])]:
-            ok, msg, bad = grad_close(a, b, name=f"{sched} {nm}")
+        for nm, a, b, cond in [("grad_pos", gp[:, vid], ref_p[:, vid], abs_p[:, vid]),
+                               ("grad_col", gc[:, vid], ref_c[:, vid], abs_c[:, vid]),
+                               ("grad_opa", go[vid], ref_o[vid], abs_o[vid])]:
+            ok, msg, bad = grad_close(a, b, name=f"{sched} {nm}", cond=cond)
             _say(f"  {msg}")
             assert ok, msg
         # eq. 7 identity at full size: dL/drho = sum_i R dL/dv_W,i ; dL/dtheta = sum_i v_C,i x R dL/dv_W,i
@@ -161,3 +195,38 @@ def test_fullsize_train_step_sampled_faces(name):
             ref = np.concatenate([rho, th])
             _say(f"  {sched} pose {gpose} identity {ref}")
             assert np.linalg.norm(gpose - ref) <= 1e-3 * np.linalg.norm(ref) + 1e-9
+
+
+@pytest.mark.parametrize("name", ["track_640x480", "track_1200x680_1M", "window_8x1200x680"])
+def test_fullsize_separate_backward_region_seeds(name):
+    """Separate forward and backward at full size (longest-first walks) with upstream
+    gradients that vanish outside the sampled faces' rectangles: every vertex gradient and
+    each view's pose gradient equal the oracle backward over those pixels."""
+    _say(f"[fullsize backward] case={name}")
+    w = _workload(name)
+    g = np.random.default_rng(78)
+    faces = _sample_faces(w, g)
+    tcs, tds, seeds, regions = _regions_and_targets(w, faces, g)
+    ref_p, ref_c, ref_o, ref_pose, conds = _oracle_region_backward(w, seeds, regions)
+    rast, p = G.make(w.scene, w.intr, w.poses)
+    P = rast.total_pixels
+    gc = np.zeros(3 * P, np.float32)
+    gd = np.zeros(P, np.float32)
+    off = 0
+    for v in range(len(w.poses)):
+        n = w.intr[v].width * w.intr[v].height
+        if seeds[v] is not None:
+            view_c = gc[3 * off:3 * (off + n)].reshape(3, n)
+            view_c[:, regions[v]] = seeds[v][0]
+            gd[off + regions[v]] = seeds[v][1]
+        off += n
+    rast.bin_and_sort(p)
+    rast.forward(p)
+    out = rast.backward(p, G.to_dev(gc), G.to_dev(gd), None)
+    torch.cuda.synchronize()
+    got = [x.cpu().numpy().astype(np.float64) for x in out]
+    for nm, a, b, cond in zip(["grad_pos", "grad_col", "grad_opa", "grad_pose"], got, [ref_p, ref_c, ref_o, ref_pose],
+                              list(conds) + [None]):
+        ok, msg, bad = grad_close(a, b, name=nm, cond=cond)
+        _say(f"  {msg}")
+        assert ok, msg

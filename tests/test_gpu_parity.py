@@ -236,7 +236,7 @@ FWD_CASES = ["single_64x48", "tiny_ragged_50x37", "equal_depth", "huge_faces_640
 
 
 @pytest.mark.parametrize("name", FWD_CASES)
-@pytest.mark.parametrize("sigma", [1.0, 0.5, 2.0])
+@pytest.mark.parametrize("sigma", [1.0, 0.5, 2.0, 0.75, 1.5])
 def test_forward_matches_oracle(name, sigma):
     _say(f"[forward] case={name} sigma={sigma}")
     sc, poses, intrs = _case(name)
@@ -290,8 +290,38 @@ def _oracle_backward_views(sc, poses, intrs, gcs, gds, gts, sigma, with_abs=Fals
     return (res, absacc) if with_abs else res
 
 
+# Steep-edge band (sigma < 1): the window's slope sigma rho^(sigma-1) grows without bound as
+# rho -> 0+, so at pixels within |rho| < 1e-3 of any face's edge the FP32 kernels' rounding of
+# rho (a few 1e-7) changes per-pixel gradient terms by more than the relative bar, and a face
+# can be blended on one side and not on the other.  Upstream gradients are zeroed at those
+# pixels on both sides (the same seeds go to the GPU and to the oracle); every other pixel is
+# compared element-wise.
+STEEP_RHO = 1e-3
+
+
+def _steep_masks(sc, poses, intrs, sigma):
+    out = []
+    for v in range(len(poses)):
+        n = intrs[v].width * intrs[v].height
+        if sigma >= 1.0:
+            out.append(np.zeros(n, bool))
+        else:
+            out.append(O.min_rho(sc, poses[v], intrs[v], sigma=sigma) < STEEP_RHO)
+    return out
+
+
+def _apply_masks(flat, masks, ch):
+    """Zero a packed per-view seed array at the masked pixels (in place)."""
+    off = 0
+    for m in masks:
+        n = m.size
+        seg = flat[off * ch:(off + n) * ch].reshape(ch, n) if ch > 1 else flat[off:off + n]
+        seg[..., m] = 0.0
+        off += n
+
+
 @pytest.mark.parametrize("name", BWD_CASES)
-@pytest.mark.parametrize("sigma", [1.0, 0.5, 2.0])
+@pytest.mark.parametrize("sigma", [1.0, 0.5, 2.0, 0.75, 1.5])
 def test_backward_matches_oracle(name, sigma):
     _say(f"[backward] case={name} sigma={sigma}")
     sc, poses, intrs = _case(name)
@@ -301,6 +331,10 @@ def test_backward_matches_oracle(name, sigma):
     gc = g.normal(size=3 * P).astype(np.float32)
     gd = g.normal(size=P).astype(np.float32)
     gt = g.normal(size=P).astype(np.float32)
+    masks = _steep_masks(sc, poses, intrs, sigma)
+    for a, ch in ((gc, 3), (gd, 1), (gt, 1)):
+        _apply_masks(a, masks, ch)
+    _say(f"  steep-edge pixels masked on both sides: {sum(int(m.sum()) for m in masks)} of {P}")
     got = _gpu_backward(rast, p, gc, gd, gt)
     gcs = G.per_view(rast, gc, 3)
     gds, gts = G.per_view(rast, gd, 1), G.per_view(rast, gt, 1)
@@ -308,12 +342,7 @@ def test_backward_matches_oracle(name, sigma):
     for nm, a, b, cond in zip(["grad_pos", "grad_col", "grad_opa", "grad_pose"], got, ref, conds + [None]):
         ok, msg, bad = grad_close(a, b, name=nm, cond=cond)
         _say("  " + msg)
-        if sigma < 1.0 and not ok:
-            # sigma < 1: the window slope is unbounded at the edge (rho -> 0); report but
-            # require only norm-wise agreement
-            assert np.linalg.norm(a - b) <= 1e-3 * np.linalg.norm(b), msg
-        else:
-            assert ok, msg
+        assert ok, msg
 
 
 # ---------------------------------------------------------------------------- fused L1 step
@@ -331,15 +360,16 @@ def _nudged_targets(oc, od, seed, shape_hw):
     return tc.astype(np.float32), td.astype(np.float32), int(near_c.sum() + near_d.sum())
 
 
-@pytest.mark.parametrize("name", ["single_64x48", "multi_view_mixed", "tiny_ragged_50x37", "long_tile_800",
-                                  "long_tile_faint_1000", "max_views_32"])
-def test_train_l1_matches_oracle(name):
-    _say(f"[train_l1] case={name}")
+@pytest.mark.parametrize("name,sigma", [("single_64x48", 1.0), ("multi_view_mixed", 1.0), ("tiny_ragged_50x37", 1.0),
+                                        ("long_tile_800", 1.0), ("long_tile_faint_1000", 1.0), ("max_views_32", 1.0),
+                                        ("single_64x48", 2.0), ("multi_view_mixed", 1.5), ("tiny_ragged_50x37", 1.5)])
+def test_train_l1_matches_oracle(name, sigma):
+    _say(f"[train_l1] case={name} sigma={sigma}")
     sc, poses, intrs = _case(name)
-    rast, p = G.make(sc, intrs, poses)
+    rast, p = G.make(sc, intrs, poses, sigma=sigma)
     tcs, tds, ocs, ods, lossref, gseeds = [], [], [], [], [], []
     for v in range(len(poses)):
-        oc, od, ot = O.render(sc, poses[v], intrs[v])
+        oc, od, ot = O.render(sc, poses[v], intrs[v], sigma=sigma)
         tc, td, nudged = _nudged_targets(oc, od, 100 + v, None)
         tcs.append(tc); tds.append(td)
         L, gcv, gdv = O.l1_seeds(oc, od, tc, td, intrs[v].width * intrs[v].height)
@@ -356,21 +386,22 @@ def test_train_l1_matches_oracle(name):
     torch.cuda.synchronize()
     got = [x.cpu().numpy().astype(np.float64) for x in out]
     np.testing.assert_allclose(loss.cpu().numpy(), lossref, rtol=1e-5)
-    ref = _oracle_backward_views(sc, poses, intrs, [s[0] for s in gseeds], [s[1] for s in gseeds], None, 1.0)
+    ref = _oracle_backward_views(sc, poses, intrs, [s[0] for s in gseeds], [s[1] for s in gseeds], None, sigma)
     for nm, a, b in zip(["grad_pos", "grad_col", "grad_opa", "grad_pose"], got, ref):
         ok, msg, bad = grad_close(a, b, name=nm)
         _say("  " + msg)
         assert ok, msg
     cs = G.per_view(rast, color.cpu().numpy(), 3)
     for v in range(len(poses)):
-        oc, od, ot = O.render(sc, poses[v], intrs[v])
+        oc, od, ot = O.render(sc, poses[v], intrs[v], sigma=sigma)
         assert np.abs(cs[v] - oc).max() <= IMG_TOL
 
 
 # ---------------------------------------------------------------------------- full photometric step
 
 @pytest.mark.parametrize("name,sigma", [("single_64x48", 1.0), ("multi_view_mixed", 1.0), ("tiny_ragged_50x37", 1.0),
-                                        ("long_tile_800", 1.0), ("single_64x48", 0.5), ("tiny_ragged_50x37", 2.0)])
+                                        ("long_tile_800", 1.0), ("single_64x48", 0.5), ("tiny_ragged_50x37", 2.0),
+                                        ("tiny_ragged_50x37", 0.75), ("multi_view_mixed", 1.5)])
 def test_train_photometric_matches_oracle(name, sigma):
     """Eqs. 8 and 10 with the D-SSIM term: the seeds are the oracle's L1 seeds plus 0.2 times
     the FP64 D-SSIM gradient of the oracle render, pushed through the oracle backward."""
@@ -406,11 +437,7 @@ def test_train_photometric_matches_oracle(name, sigma):
     for nm, a, b, cond in zip(["grad_pos", "grad_col", "grad_opa", "grad_pose"], got, ref, conds + [None]):
         ok, msg, bad = grad_close(a, b, name=nm, cond=cond)
         _say("  " + msg)
-        if sigma < 1.0 and not ok:
-            # sigma < 1: the window slope is unbounded at the edge; norm-wise agreement only
-            assert np.linalg.norm(a - b) <= 1e-3 * np.linalg.norm(b), msg
-        else:
-            assert ok, msg
+        assert ok, msg
     cs = G.per_view(rast, color.cpu().numpy(), 3)
     for v in range(len(poses)):
         assert np.abs(cs[v] - ocs[v]).max() <= IMG_TOL

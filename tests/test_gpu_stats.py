@@ -121,3 +121,12 @@ def test_minimum_opacity_rule():
     sc = S.Scene(sc.pos, sc.col, g.uniform(0.05, 1.0, size=sc.n_vertices).astype(np.float32))
     _, _, area, cov, vis = _gpu_stats(sc, [intr], [IDENTITY], t_min=0.3, opacity_min=True)
     _check_view(sc, IDENTITY, intr, area, cov, vis, 0.3, opacity_min=True)
+
+
+@pytest.mark.parametrize("sigma", [0.5, 0.75, 1.5, 2.0])
+def test_other_window_exponents(sigma):
+    """Coverage and visibility at the paper's sigma = 0.5 and at exponents served by the
+    generic-exponent kernels (0.75, 1.5)."""
+    sc, intr = tiny_scene(15, n_faces=40, w=48, h=36, f=36.0)
+    _, _, area, cov, vis = _gpu_stats(sc, [intr], [IDENTITY], t_min=0.3, sigma=sigma)
+    _check_view(sc, IDENTITY, intr, area, cov, vis, 0.3, sigma=sigma)

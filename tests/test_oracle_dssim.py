@@ -1,4 +1,4 @@
-"""Pins of the FP64 D-SSIM reference (Sec. 3.5, eq. 8; window, constants and border rule as
+"""Pins of the FP64 D-SSIM reference (Sec. 3.4, eq. 8; window, constants and border rule as
 read in the reference's header): library routines, closed forms, invariants and finite
 differences."""
 import numpy as np

@@ -1,4 +1,4 @@
-"""Pins of the FP64 equilateral-regulariser reference (Sec. 3.5, eq. 14): law of cosines,
+"""Pins of the FP64 equilateral-regulariser reference (Sec. 3.4, eq. 14): law of cosines,
 angle sum, closed forms, invariances of the loss and the gradient, finite differences."""
 import numpy as np
 import pytest

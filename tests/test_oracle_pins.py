@@ -48,6 +48,41 @@ def test_window_closed_forms_right_triangle(sigma):
             assert np.all(C[:, k] == 0)
 
 
+def test_min_rho_golden_values():
+    """The per-pixel smallest |rho| over the faces whose box holds the pixel (the steep-edge
+    mask of the sigma < 1 parity tests): the hand-derived rho of the golden right triangle
+    inside it; |rho| of the most violated edge at a box point outside it ((26, 25): inside
+    distances 5, -2.8 and 6, r = 2, so rho = -1.4); +inf outside the open box (edges along it,
+    vertices, far points).  Under a second face covering the triangle, the smaller value."""
+    g = json.load(open(os.path.join(GOLD, "window_right_triangle.json")))
+    cam = unit_cam(g["camera"]["width"], g["camera"]["height"])
+    sc = _tri_scene(g["vertices"], opa=np.ones((1, 3)))
+    pts = [tuple(p["p"]) for p in g["points"]]
+    r = O.min_rho(sc, IDENTITY, cam, sigma=0.5, pixels=_pix(cam, pts))
+    want = []
+    for p in g["points"]:
+        u, v = p["p"]
+        if p["rho"] > 0:
+            want.append(p["rho"])
+        elif (u, v) == (26, 25):
+            want.append(1.4)
+        else:
+            assert not (20 < u < 28 and 20 < v < 26), p
+            want.append(np.inf)
+    want = np.array(want)
+    fin = np.isfinite(want)
+    np.testing.assert_allclose(r[fin], want[fin], atol=1e-12)
+    assert np.all(np.isinf(r[~fin]))
+    # a large face over the whole triangle, nearer the camera
+    big = np.array([[[-15.0, -15.0, 0.5], [45.0, -15.0, 0.5], [11.0, 45.0, 0.5]]])
+    tri = np.array([[[x, y, 1.0] for x, y in g["vertices"]]])
+    sc2 = plain_scene(np.concatenate([tri, big]), opa=np.full((2, 3), 0.5))
+    r2 = O.min_rho(sc2, IDENTITY, cam, pixels=_pix(cam, pts))
+    rb = O.min_rho(plain_scene(big, opa=np.full((1, 3), 0.5)), IDENTITY, cam, pixels=_pix(cam, pts))
+    assert np.all(np.isfinite(rb)) and np.all(rb > 0.3)
+    np.testing.assert_allclose(r2, np.minimum(rb, want), atol=1e-12)
+
+
 def test_window_incentre_and_inradius_equilateral():
     """An equilateral triangle of side a has incentre = centroid and r = a / (2 sqrt 3)."""
     a = 12.0

@@ -127,3 +127,85 @@ def test_oversized_request_is_rejected_immediately():
         assert r.event.is_set() and "budget" in r.error
     finally:
         srv.stop()
+
+
+class _Slots(FakeExecutor):
+    """Fake executor whose slots hold `ws` bytes each and fit at most `views` views."""
+
+    def __init__(self, ws, views, **kw):
+        super().__init__(**kw)
+        self.ws, self.views = ws, views
+
+    def setup(self, n_slots, budget, max_views, max_pixels):
+        return n_slots * self.ws, min(max_views, self.views)
+
+    def batch_fits(self, intrs):
+        return len(intrs) <= self.views
+
+
+def test_slot_workspaces_are_charged_for_the_servers_lifetime():
+    per = 20 * 320 * 240
+    ex = _Slots(ws=10 * per, views=2, per_pixel_s=1e-8)
+    srv = Server(ex, n_slots=2, mem_budget=22 * per, max_batch_views=8)
+    srv.start()
+    try:
+        assert srv.used == 20 * per and srv.max_views == 2
+        reqs = [srv.submit(_req(i)) for i in range(10)]
+        big = srv.submit(_req(99, 640, 480))              # 4 per: above the 2 per left
+        srv.drain()
+        assert srv.used == 20 * per
+    finally:
+        srv.stop()
+    assert srv.used == 0
+    assert big.error and "slots hold" in big.error
+    assert all(r.error is None for r in reqs)
+    assert srv.peak_used <= 22 * per
+    assert max(len(b) for b in ex.batches) <= 2
+
+
+def test_concurrent_submitters_keep_the_books():
+    """Race check of the scheduler (a stand-in for a thread sanitizer, which does not apply to
+    Python code): 8 submitting threads, 4 slots, random service times.  Every request
+    completes exactly once, the charged memory stays within [0, budget] at every batch, and
+    the books balance at the end."""
+    import random
+
+    per = 20 * 320 * 240
+    budget = 6 * per
+    seen = []
+
+    class Checking(FakeExecutor):
+        def run(self, slot, batch):
+            with srv.cv:
+                seen.append(srv.used)
+                assert 0 <= srv.used <= budget
+            time.sleep(random.uniform(0, 2e-3))
+            super().run(slot, batch)
+
+    ex = Checking(per_pixel_s=1e-9)
+    srv = Server(ex, n_slots=4, mem_budget=budget, max_batch_views=3)
+    srv.start()
+    out = []
+    lock = threading.Lock()
+
+    def submitter(k):
+        for i in range(50):
+            r = srv.submit(_req(1000 * k + i))
+            with lock:
+                out.append(r)
+            time.sleep(random.uniform(0, 1e-4))
+
+    try:
+        ts = [threading.Thread(target=submitter, args=(k,)) for k in range(8)]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+        srv.drain()
+    finally:
+        srv.stop()
+    assert len(out) == 400 and all(r.event.is_set() and r.error is None for r in out)
+    ids = [r.rid for r in srv.completed]
+    assert len(ids) == len(set(ids)) == 400
+    assert srv.used == 0 and srv.peak_used <= budget and max(seen) <= budget
+    assert sorted(r for b in ex.batches for r in b) == sorted(ids)
