@@ -24,7 +24,8 @@ CFLAGS = ["-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-std=c11"
 
 class _Scene(C.Structure):
     _fields_ = [("pos", C.c_void_p), ("col", C.c_void_p), ("opa", C.c_void_p),
-                ("faces", C.c_void_p), ("n_vertices", C.c_int64), ("n_faces", C.c_int64)]
+                ("faces", C.c_void_p), ("n_vertices", C.c_int64), ("n_faces", C.c_int64),
+                ("face_sigma", C.c_void_p)]
 
 
 class _Cam(C.Structure):
@@ -49,6 +50,7 @@ def lib():
         _lib.orc_render.argtypes = [P, P, P, P, P, C.c_int64, P, P, P]
         _lib.orc_backward.argtypes = [P, P, P, P, P, C.c_int64, P, P, P, P, P, P, P]
         _lib.orc_backward_abs.argtypes = [P, P, P, P, P, C.c_int64, P, P, P, P, P, P, P, P, P, P]
+        _lib.orc_backward_sigma.argtypes = [P, P, P, P, P, C.c_int64, P, P, P, P, P, P, P, P]
         _lib.orc_project.argtypes = [P, P, P, P, P, P, P, P]
         _lib.orc_bin.argtypes = [P, P, P, C.c_int, P, C.c_int64, P, P, P, P, P]
         _lib.orc_l1_seeds.argtypes = [P, P, P, P, C.c_int64, C.c_int64, C.c_double, C.c_double, P, P]
@@ -93,8 +95,10 @@ class _Args:
         self.col = np.ascontiguousarray(scene.col, dtype=np.float64)
         self.opa = np.ascontiguousarray(scene.opa, dtype=np.float64)
         self.faces = None if scene.faces is None else np.ascontiguousarray(scene.faces, dtype=np.int32)
+        fs = getattr(scene, "face_sigma", None)
+        self.face_sigma = None if fs is None else np.ascontiguousarray(fs, dtype=np.float64)
         self.sc = _Scene(_ptr(self.pos), _ptr(self.col), _ptr(self.opa), _ptr(self.faces),
-                         self.pos.shape[1], scene.n_faces)
+                         self.pos.shape[1], scene.n_faces, _ptr(self.face_sigma))
         self.pose = np.ascontiguousarray(np.asarray(pose, dtype=np.float64).reshape(-1))
         self.cam = _cam(intr)
         self.par = _Par(sigma, z_near, r_min, 1.0 if opacity_min else 0.0)
@@ -131,11 +135,13 @@ def render(scene, pose, intr, sigma=1.0, z_near=0.1, r_min=1e-3,
 
 def backward(scene, pose, intr, g_color: np.ndarray, g_depth: np.ndarray,
              g_trans: Optional[np.ndarray] = None, sigma=1.0, z_near=0.1, r_min=1e-3,
-             pixels: Optional[np.ndarray] = None, with_abs: bool = False, opacity_min: bool = False):
+             pixels: Optional[np.ndarray] = None, with_abs: bool = False, opacity_min: bool = False,
+             want_sigma: bool = False):
     """Gradients (pos [3,N], col [3,N], opa [N], pose [6]) from the listed pixels' upstream
     gradients g_color [3,P], g_depth [P], g_trans [P].  With `with_abs`, also returns the
     per-element sums of absolute per-pixel contributions (pos, col, opa) -- the conditioning
-    that bounds the rounding error of a lower-precision implementation."""
+    that bounds the rounding error of a lower-precision implementation.  With `want_sigma`
+    (scenes with per-face exponents), also returns dL/dsigma per face [M]."""
     a = _Args(scene, pose, intr, sigma, z_near, r_min, opacity_min)
     pix = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int64)
     n = a.cam.width * a.cam.height if pix is None else pix.shape[0]
@@ -144,6 +150,14 @@ def backward(scene, pose, intr, g_color: np.ndarray, g_depth: np.ndarray,
     gt = None if g_trans is None else np.ascontiguousarray(np.asarray(g_trans, np.float64).reshape(n))
     N = a.pos.shape[1]
     gpos = np.zeros((3, N)); gcol = np.zeros((3, N)); gopa = np.zeros(N); gpose = np.zeros(6)
+    if want_sigma:
+        gsig = np.zeros(max(int(a.sc.n_faces), 1))
+        rc = lib().orc_backward_sigma(C.byref(a.sc), _ptr(a.pose), C.byref(a.cam), C.byref(a.par), _ptr(pix), n,
+                                      _ptr(gc), _ptr(gd), _ptr(gt), _ptr(gpos), _ptr(gcol), _ptr(gopa), _ptr(gpose),
+                                      _ptr(gsig))
+        if rc:
+            raise ValueError(f"orc_backward_sigma failed ({rc})")
+        return gpos, gcol, gopa, gpose, gsig[:int(a.sc.n_faces)]
     if with_abs:
         apos = np.zeros((3, N)); acol = np.zeros((3, N)); aopa = np.zeros(N)
         rc = lib().orc_backward_abs(C.byref(a.sc), _ptr(a.pose), C.byref(a.cam), C.byref(a.par), _ptr(pix), n,

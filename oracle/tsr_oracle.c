@@ -46,6 +46,9 @@ typedef struct {
     const double *opa;  /* [N]    */
     const int32_t *faces; /* [M][3] or NULL for a soup */
     int64_t n_vertices, n_faces;
+    const double *face_sigma; /* [M] per-face window exponents, or NULL: every face uses the
+                                 parameters' sigma (Sec. 3.2: learnable per triangle in Triangle
+                                 Splatting, one global constant in Mesh Splatting) */
 } orc_scene;
 
 typedef struct { int32_t width, height; double fx, fy, cx, cy; } orc_cam;
@@ -67,6 +70,7 @@ typedef struct {
     double n[3][2], d[3], len[3];
     double area2, perim, r;
     double zf, of;
+    double sig;           /* the face's window exponent sigma (eq. 3) */
     int kmin;             /* vertex of lowest opacity (lowest index on ties) */
     float zkey;
     double umin, umax, vmin, vmax;
@@ -86,6 +90,7 @@ static void face_setup(const orc_scene *s, const double *pose, const orc_cam *c,
     rot(pose, R, t);
     int64_t N = s->n_vertices;
     f->ok = 0;
+    f->sig = s->face_sigma ? s->face_sigma[m] : p->sigma;
     for (int k = 0; k < 3; k++) {
         int64_t i = vid(s, m, k);
         f->v[k] = i;
@@ -134,8 +139,7 @@ static void face_setup(const orc_scene *s, const double *pose, const orc_cam *c,
 }
 
 /* Steps 4-6 at pixel centre (u, v).  Returns I(p); writes rho and the barycentrics. */
-static double face_window(const face_t *f, double sigma, double u, double v, double *rho_out,
-                          double lam[3]) {
+static double face_window(const face_t *f, double u, double v, double *rho_out, double lam[3]) {
     double L[3];
     for (int k = 0; k < 3; k++) L[k] = f->n[k][0] * u + f->n[k][1] * v + f->d[k];
     int ks = 0;
@@ -149,7 +153,7 @@ static double face_window(const face_t *f, double sigma, double u, double v, dou
     lam[2] = -L[0] * f->len[0] / f->area2;
     if (!(rho > 0)) return 0.0;
     if (rho >= 1) return 1.0;
-    return pow(rho, sigma);
+    return pow(rho, f->sig);
 }
 
 static int in_box(const face_t *f, double u, double v) {
@@ -171,15 +175,14 @@ static int hit_cmp(const void *a, const void *b) {
 }
 
 /* Collect and depth-sort every face covering pixel (u, v).  Caller frees *out. */
-static int64_t pixel_hits(const orc_scene *s, const face_t *F, double sigma, int u, int v,
-                          hit_t **out) {
+static int64_t pixel_hits(const orc_scene *s, const face_t *F, int u, int v, hit_t **out) {
     int64_t cap = 16, n = 0;
     hit_t *h = (hit_t *)malloc(sizeof(hit_t) * cap);
     for (int64_t m = 0; m < s->n_faces; m++) {
         const face_t *f = &F[m];
         if (!f->ok || !in_box(f, u, v)) continue;
         double rho, lam[3];
-        double I = face_window(f, sigma, u, v, &rho, lam);
+        double I = face_window(f, u, v, &rho, lam);
         double alpha = f->of * I;
         if (!(alpha > 0)) continue;
         if (n == cap) { cap *= 2; h = (hit_t *)realloc(h, sizeof(hit_t) * cap); }
@@ -209,6 +212,9 @@ static int check_args(const orc_scene *s, const double *pose, const orc_cam *c, 
     if (s->n_faces < 0 || s->n_vertices < 0 || c->width <= 0 || c->height <= 0 || !(p->sigma > 0))
         return ORC_EINVAL;
     if (!s->faces && s->n_vertices < 3 * s->n_faces) return ORC_EINVAL;
+    if (s->face_sigma)
+        for (int64_t m = 0; m < s->n_faces; m++)
+            if (!(s->face_sigma[m] > 0)) return ORC_EINVAL;
     return ORC_OK;
 }
 
@@ -241,7 +247,7 @@ int orc_render(const orc_scene *s, const double *pose, const orc_cam *c, const o
         int64_t id = pix ? pix[k] : k;
         int u = (int)(id % c->width), v = (int)(id / c->width);
         hit_t *h;
-        int64_t n = pixel_hits(s, F, p->sigma, u, v, &h);
+        int64_t n = pixel_hits(s, F, u, v, &h);
         double C[3] = {0, 0, 0}, D = 0, T = 1;
         for (int64_t j = 0; j < n; j++) {
             double w = h[j].alpha * T;
@@ -281,8 +287,9 @@ static dn dn_sqrt(dn a) {
 
 /* Window, barycentrics and depth of face f at (u, v) as functions of its nine camera-space
  * vertex coordinates (tangent index 3*vertex + axis).  Same steps as face_setup/face_window. */
-static void face_local_dual(const face_t *f, const orc_cam *c, double sigma, double u, double v,
+static void face_local_dual(const face_t *f, const orc_cam *c, double u, double v,
                             dn *I_out, dn lam[3], dn *zf_out) {
+    const double sigma = f->sig;
     dn q[3][2];
     for (int k = 0; k < 3; k++) {
         dn x = dn_var(f->vc[k][0], 3 * k), y = dn_var(f->vc[k][1], 3 * k + 1),
@@ -332,10 +339,11 @@ static void face_local_dual(const face_t *f, const orc_cam *c, double sigma, dou
  * abs_pos / abs_col / abs_opa (nullable, same shapes) receive the sums over pixels of the
  * absolute per-pixel contributions: the conditioning of each gradient element, which bounds
  * the rounding error of any implementation that forms per-pixel terms in lower precision. */
-int orc_backward_abs(const orc_scene *s, const double *pose, const orc_cam *c, const orc_par *p,
-                     const int64_t *pix, int64_t npix, const double *gC, const double *gD,
-                     const double *gT, double *grad_pos, double *grad_col, double *grad_opa,
-                     double *grad_pose, double *abs_pos, double *abs_col, double *abs_opa) {
+static int backward_impl(const orc_scene *s, const double *pose, const orc_cam *c, const orc_par *p,
+                         const int64_t *pix, int64_t npix, const double *gC, const double *gD,
+                         const double *gT, double *grad_pos, double *grad_col, double *grad_opa,
+                         double *grad_pose, double *abs_pos, double *abs_col, double *abs_opa,
+                         double *grad_sigma) {
     int rc = check_args(s, pose, c, p);
     if (rc) return rc;
     int64_t M = s->n_faces, N = s->n_vertices;
@@ -351,7 +359,7 @@ int orc_backward_abs(const orc_scene *s, const double *pose, const orc_cam *c, c
         double g[3] = {gC[k], gC[npix + k], gC[2 * npix + k]};
         double gd = gD[k], gt = gT ? gT[k] : 0.0;
         hit_t *h;
-        int64_t n = pixel_hits(s, F, p->sigma, u, v, &h);
+        int64_t n = pixel_hits(s, F, u, v, &h);
         double *Tn = (double *)malloc(sizeof(double) * (size_t)(n ? n : 1));
         double T = 1;
         for (int64_t j = 0; j < n; j++) { Tn[j] = T; T *= 1.0 - h[j].alpha; }
@@ -367,7 +375,7 @@ int orc_backward_abs(const orc_scene *s, const double *pose, const orc_cam *c, c
             double gcol[3] = {g[0] * w, g[1] * w, g[2] * w};
             double gz = gd * w;
             dn I, lam[3], zf;
-            face_local_dual(f, c, p->sigma, u, v, &I, lam, &zf);
+            face_local_dual(f, c, u, v, &I, lam, &zf);
             double acc[9];
             for (int t = 0; t < 9; t++) {
                 double dc = 0;
@@ -408,6 +416,12 @@ int orc_backward_abs(const orc_scene *s, const double *pose, const orc_cam *c, c
                     abs_opa[vi] += fabs(go);
                 }
             }
+            /* per-face exponent: dI/dsigma = I ln(rho) inside (0 < rho < 1), 0 where I is 0 or 1 */
+            if (grad_sigma && e->rho > 0 && e->rho < 1) {
+                double gs = galpha * f->of * e->I * log(e->rho);
+                #pragma omp atomic
+                grad_sigma[e->m] += gs;
+            }
             for (int ch = 0; ch < 3; ch++) B[ch] = e->c[ch] * e->alpha + (1.0 - e->alpha) * B[ch];
             BD = e->zf * e->alpha + (1.0 - e->alpha) * BD;
             BA = e->alpha + (1.0 - e->alpha) * BA;
@@ -439,12 +453,30 @@ int orc_backward_abs(const orc_scene *s, const double *pose, const orc_cam *c, c
     return ORC_OK;
 }
 
+int orc_backward_abs(const orc_scene *s, const double *pose, const orc_cam *c, const orc_par *p,
+                     const int64_t *pix, int64_t npix, const double *gC, const double *gD,
+                     const double *gT, double *grad_pos, double *grad_col, double *grad_opa,
+                     double *grad_pose, double *abs_pos, double *abs_col, double *abs_opa) {
+    return backward_impl(s, pose, c, p, pix, npix, gC, gD, gT, grad_pos, grad_col, grad_opa, grad_pose,
+                         abs_pos, abs_col, abs_opa, NULL);
+}
+
 int orc_backward(const orc_scene *s, const double *pose, const orc_cam *c, const orc_par *p,
                  const int64_t *pix, int64_t npix, const double *gC, const double *gD,
                  const double *gT, double *grad_pos, double *grad_col, double *grad_opa,
                  double *grad_pose) {
-    return orc_backward_abs(s, pose, c, p, pix, npix, gC, gD, gT, grad_pos, grad_col, grad_opa, grad_pose,
-                            NULL, NULL, NULL);
+    return backward_impl(s, pose, c, p, pix, npix, gC, gD, gT, grad_pos, grad_col, grad_opa, grad_pose,
+                         NULL, NULL, NULL, NULL);
+}
+
+/* As orc_backward, plus (+=) the gradient with respect to each face's window exponent:
+ * grad_sigma[M] = sum over blended pixels of dL/dalpha o_F I ln(rho). */
+int orc_backward_sigma(const orc_scene *s, const double *pose, const orc_cam *c, const orc_par *p,
+                       const int64_t *pix, int64_t npix, const double *gC, const double *gD,
+                       const double *gT, double *grad_pos, double *grad_col, double *grad_opa,
+                       double *grad_pose, double *grad_sigma) {
+    return backward_impl(s, pose, c, p, pix, npix, gC, gD, gT, grad_pos, grad_col, grad_opa, grad_pose,
+                         NULL, NULL, NULL, grad_sigma);
 }
 
 /* L1 loss of eqs. (8)-(10) without the D-SSIM term, as means over pixels (and channels):
@@ -605,7 +637,7 @@ int orc_state(const orc_scene *s, const double *pose, const orc_cam *c, const or
         int64_t id = pix ? pix[k] : k;
         int u = (int)(id % c->width), v = (int)(id / c->width);
         hit_t *h;
-        int64_t n = pixel_hits(s, F, p->sigma, u, v, &h);
+        int64_t n = pixel_hits(s, F, u, v, &h);
         uint64_t x = 1469598103934665603ull;                 /* FNV-1a over the state words */
         for (int64_t j = 0; j < n; j++) {
             const face_t *f = &F[h[j].m];
@@ -646,7 +678,7 @@ int orc_min_rho(const orc_scene *s, const double *pose, const orc_cam *c, const 
             const face_t *f = &F[m];
             if (!f->ok || !in_box(f, u, v)) continue;
             double rho, lam[3];
-            face_window(f, p->sigma, u, v, &rho, lam);
+            face_window(f, u, v, &rho, lam);
             if (fabs(rho) < r) r = fabs(rho);
         }
         min_rho[k] = r;
@@ -703,7 +735,7 @@ int orc_face_stats(const orc_scene *s, const double *pose, const orc_cam *c, con
             if (!f->ok) continue;
             if (!(u >= f->umin - 1e-3 && u <= f->umax + 1e-3 && v >= f->vmin - 1e-3 && v <= f->vmax + 1e-3)) continue;
             double rho, lam[3];
-            const double I = face_window(f, p->sigma, u, v, &rho, lam);
+            const double I = face_window(f, u, v, &rho, lam);
             if (!(rho > -1e-4)) continue;
             if (n == cap) { cap *= 2; h = (cand_t *)realloc(h, sizeof(cand_t) * cap); }
             h[n].zkey = f->zkey; h[n].m = m; h[n].rho = rho; h[n].alpha = f->of * I;

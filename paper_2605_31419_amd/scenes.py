@@ -67,6 +67,7 @@ class Scene:
     col: np.ndarray            # [3, N] float32
     opa: np.ndarray            # [N] float32
     faces: Optional[np.ndarray] = None   # [M, 3] int32, None = soup
+    face_sigma: Optional[np.ndarray] = None   # [M] float32 per-face window exponents, None = global
 
     @property
     def n_vertices(self) -> int:
@@ -83,8 +84,9 @@ class Scene:
             vid = (3 * face_ids[:, None] + np.arange(3)[None, :]).reshape(-1)
         else:
             vid = self.faces[face_ids].reshape(-1).astype(np.int64)
+        fs = None if self.face_sigma is None else np.ascontiguousarray(self.face_sigma[face_ids])
         return Scene(np.ascontiguousarray(self.pos[:, vid]), np.ascontiguousarray(self.col[:, vid]),
-                     np.ascontiguousarray(self.opa[vid]), None)
+                     np.ascontiguousarray(self.opa[vid]), None, fs)
 
 
 # ----------------------------------------------------------------------------- poses

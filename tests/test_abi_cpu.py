@@ -206,3 +206,22 @@ def test_equilateral_noalloc_validation():
     assert lib.tsr_equilateral_noalloc(None, 1.0, 0, p, p, None) == _lib.TSR_EINVAL
     short_soup = _lib.TsrScene(1, None, None, None, 20, 10)
     assert lib.tsr_equilateral_noalloc(C.byref(short_soup), 1.0, 0, p, p, None) == _lib.TSR_EINVAL
+
+
+def test_packaged_schedule_table_covers_the_standard_workloads():
+    """The committed tile-schedule table (written on an MI355X by tune_table.py) has an entry
+    for each standard workload's key and ``lookup`` returns it (nearest pair-count bucket for
+    a nearby count)."""
+    from paper_2605_31419_amd import autotune
+    from paper_2605_31419_amd import scenes as S
+
+    tab = autotune.load_table(autotune.DEFAULT_TABLE)
+    assert len(tab) >= 5
+    i1200 = S.intrinsics_for(1200, 680)
+    for intrs, k in (([S.intrinsics_for(64, 48)], 512), ([S.intrinsics_for(640, 480)], 18000),
+                     ([i1200] * 8, 280000), ([i1200], 392216), ([i1200] * 8, 1930600)):
+        key = autotune.key_for(intrs, k)
+        assert key in tab, key
+        sched = autotune.lookup(intrs, k, autotune.DEFAULT_TABLE)
+        assert sched == tuple(tab[key]["schedule"]) and sched in autotune.CANDIDATES
+    assert autotune.lookup([i1200], 300000, autotune.DEFAULT_TABLE) is not None     # nearest bucket

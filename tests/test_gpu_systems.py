@@ -473,3 +473,15 @@ def test_serving_under_a_tight_memory_budget():
     assert all(r.error is None for r in reqs), [r.error for r in reqs if r.error]
     assert srv.peak_used <= budget and srv.used == 0
     assert peak <= budget
+
+
+def test_mapping_window_takes_the_tabulated_schedule():
+    """A window built without a schedule looks its workload up in the packaged table (written
+    on this GPU model by tune_table.py) and runs that schedule."""
+    w = S.workload("window_8x1200x680")
+    dev = raster.DeviceScene.from_numpy(w.scene)
+    win = MappingWindow(dev, w.intr)
+    k = win.prepare(raster.poses_tensor(w.poses))
+    want = autotune.lookup(w.intr, k)
+    _say(f"  K = {k}, key {autotune.key_for(w.intr, k)}, schedule {win.schedule}")
+    assert want is not None and win.schedule == want and win.rast.schedule == want

@@ -9,6 +9,7 @@ import tempfile
 import pytest
 
 from oracle import oracle as O
+from tests import test_oracle_face_sigma as FSIG
 from tests import test_oracle_fd as FD
 from tests import test_oracle_pins as PINS
 
@@ -39,6 +40,11 @@ MUTATIONS = {
     "dual_barycentric_index": ("lam[1] = dn_scale(dn_div(dn_mul(L[2], len[2]), area), -1.0);",
                                "lam[1] = dn_scale(dn_div(dn_mul(L[0], len[2]), area), -1.0);"),
     "dual_depth_weight": ("*zf_out = dn_scale(zf, 1.0 / 3.0);", "*zf_out = dn_scale(zf, 1.0 / 2.0);"),
+    "face_sigma_ignored": ("f->sig = s->face_sigma ? s->face_sigma[m] : p->sigma;", "f->sig = p->sigma;"),
+    "sigma_grad_log2": ("double gs = galpha * f->of * e->I * log(e->rho);",
+                        "double gs = galpha * f->of * e->I * log2(e->rho);"),
+    "sigma_grad_no_opacity": ("double gs = galpha * f->of * e->I * log(e->rho);",
+                              "double gs = galpha * e->I * log(e->rho);"),
 }
 
 
@@ -59,6 +65,9 @@ def _pin_checks():
             lambda: FD.test_pose_gradient_identities(7), FD.test_opacity_mean_rule]
     for sigma, seed in [(1.0, 1), (0.5, 2), (2.0, 3)]:
         out.append(lambda sigma=sigma, seed=seed: FD.test_gradients_match_finite_differences(sigma, seed))
+    out += [lambda: FSIG.test_golden_right_triangle_with_its_own_exponent(0.7),
+            FSIG.test_two_faces_use_their_own_exponents,
+            lambda: FSIG.test_gradients_under_face_sigma_match_finite_differences(41)]
     return out
 
 
