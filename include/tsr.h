@@ -107,6 +107,15 @@ typedef struct {
     const int32_t *faces;    /* [M][3] vertex indices, or NULL for a soup (N = 3M) */
     int64_t n_vertices;      /* N */
     int64_t n_faces;         /* M */
+    const float *face_sigma; /* [M] each face's window exponent sigma_m of eq. 3, > 0 (the
+                                Triangle Splatting variant that learns sigma per triangle,
+                                Sec. 3.2), or NULL: every face uses params->sigma (the paper's
+                                global constant).  Values <= 0 or NaN give unspecified images. */
+    float *grad_face_sigma;  /* [M] output, or NULL: dL/dsigma_m summed over the call's views
+                                (0 for faces no view blends), written by tsr_render_backward,
+                                tsr_render_train_l1 and tsr_render_train_photometric when
+                                face_sigma is set.  tsr_render_train_normal renders with the
+                                per-face exponents but leaves this output alone. */
 } tsr_scene;
 
 /* Work schedule of the fused training kernel (host).  NULL selects the default

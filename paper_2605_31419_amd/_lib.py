@@ -40,7 +40,8 @@ class TsrParams(C.Structure):
 
 class TsrScene(C.Structure):
     _fields_ = [("pos", C.c_void_p), ("col", C.c_void_p), ("opa", C.c_void_p), ("faces", C.c_void_p),
-                ("n_vertices", C.c_int64), ("n_faces", C.c_int64)]
+                ("n_vertices", C.c_int64), ("n_faces", C.c_int64), ("face_sigma", C.c_void_p),
+                ("grad_face_sigma", C.c_void_p)]
 
 
 class TsrSchedule(C.Structure):

@@ -119,6 +119,7 @@ int build_views(const tsr_scene* sc, const tsr_intrinsics* intr, int n_views, Vi
   vt->n_views = n_views;
   vt->n_tiles = (int32_t)tiles;
   vt->n_faces = sc->n_faces;
+  vt->face_sigma = sc->face_sigma ? 1 : 0;
   if ((int64_t)n_views * sc->n_faces >= (1ll << 31))
     return fail(TSR_EINVAL, "n_views * n_faces = %lld must be below 2^31", (long long)n_views * sc->n_faces);
   return TSR_OK;
@@ -145,6 +146,7 @@ WsLayout layout(const ViewTable& vt, int64_t cap) {
   L.counts = o; o = align_up(o + sizeof(uint32_t) * nf);
   L.records = o; o = align_up(o + sizeof(float) * tsr::kRecDwords * nf);
   L.grad_acc = o; o = align_up(o + sizeof(tsr::acc_t) * tsr::kGradDwords * nf);
+  L.sig_acc = o; o = align_up(o + sizeof(float) * nf);
   const int64_t nb = (nf + tsr::kProjBlock - 1) / tsr::kProjBlock;
   L.tile_cnt = o;
   L.long_cnt = o + sizeof(uint32_t) * tsr::kTileCntStride * vt.n_tiles;
@@ -196,6 +198,8 @@ tsr::tsr_scene_dev dev_scene(const tsr_scene* sc, const tsr_params* p = nullptr)
   d.faces = sc->faces;
   d.n_vertices = sc->n_vertices;
   d.n_faces = sc->n_faces;
+  d.face_sigma = sc->face_sigma;
+  d.grad_face_sigma = sc->grad_face_sigma;
   return d;
 }
 

@@ -104,10 +104,13 @@ struct FaceAttr {
   float col[3][3];
   float opa[3];
   int opa_min;     // face opacity = min of the vertex opacities instead of their mean
+  float sigma;     // window exponent of the face (eq. 3)
 };
 
-__device__ __forceinline__ void load_attr(const tsr_scene_dev& sc, const int64_t vid[3], FaceAttr& a) {
+__device__ __forceinline__ void load_attr(const tsr_scene_dev& sc, int64_t m, const int64_t vid[3], float sigma,
+                                          FaceAttr& a) {
   const int64_t N = sc.n_vertices;
+  a.sigma = sc.face_sigma ? sc.face_sigma[m] : sigma;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
 #pragma unroll
@@ -152,8 +155,8 @@ __device__ __forceinline__ void write_record(const FaceAttr& at, const FaceSetup
   rec[kRecZ] = (float)f.zf;
   rec[kRecU0] = (float)f.u0;          // exact: |u0| < 2^24
   rec[kRecV0] = (float)f.v0;
-  rec[kRecU1] = __int_as_float(f.u1);
-  rec[kRecV1] = __int_as_float(f.v1);
+  rec[kRecU1V1] = __int_as_float(f.u1 | (f.v1 << 16));    // both below 2^14
+  rec[kRecSigma] = at.sigma;
   float4* dst = reinterpret_cast<float4*>(dst_rec);
 #pragma unroll
   for (int i = 0; i < kRecDwords / 4; ++i) dst[i] = make_float4(rec[4 * i], rec[4 * i + 1], rec[4 * i + 2], rec[4 * i + 3]);
@@ -243,7 +246,7 @@ __device__ __forceinline__ void wave_expand(int cnt, F&& fn) {
 // of the workgroup are compacted onto the first lanes, which run the exact FP64 setup (the
 // visibility decision, the pixel rectangle and, for visible faces, the record).
 __global__ __launch_bounds__(256, 6) void k_project(tsr_scene_dev sc, const float* __restrict__ poses, ViewTable vt,
-                                                 float z_near, float r_min, uint32_t* __restrict__ counts,
+                                                 float z_near, float r_min, float sigma, uint32_t* __restrict__ counts,
                                                  float* __restrict__ records, uint32_t* __restrict__ tile_cnt,
                                                  uint32_t* __restrict__ vis_cnt, VisEntry* __restrict__ vis_list) {
   __shared__ uint32_t s_wave[4];
@@ -293,9 +296,10 @@ __global__ __launch_bounds__(256, 6) void k_project(tsr_scene_dev sc, const floa
     double R[9], t[3];
     load_pose(poses, v, R, t);
     int64_t vid[3];
-    face_vertices(sc, g - (int64_t)v * M, vid);
+    const int64_t m = g - (int64_t)v * M;
+    face_vertices(sc, m, vid);
     FaceAttr at;
-    load_attr(sc, vid, at);
+    load_attr(sc, m, vid, sigma, at);
     FaceSetup f;
     if (setup_face(sc, vid, R, t, vd, z_near, r_min, f)) {
       tx0 = f.u0 >> 4;
@@ -865,7 +869,7 @@ hipError_t launch_bin(const tsr_scene_dev& sc, const float* poses, const ViewTab
   const int64_t n_cnt = kTileCntStride * (int64_t)vt.n_tiles + 1;
   TSR_LAUNCH("fill_tiles", k_fill_u32, dim3(grid_for(n_cnt, 256)), dim3(256), 0, st, tile_cnt, n_cnt, 0u);
   if (nf > 0)
-    TSR_LAUNCH("project", k_project, dim3(grid_for(nf, kProjBlock)), dim3(kProjBlock), 0, st, sc, poses, vt, p.z_near, p.r_min, counts,
+    TSR_LAUNCH("project", k_project, dim3(grid_for(nf, kProjBlock)), dim3(kProjBlock), 0, st, sc, poses, vt, p.z_near, p.r_min, p.sigma, counts,
                        records, tile_cnt, vis_cnt, vis_list);
   uint32_t* vis_off = reinterpret_cast<uint32_t*>(ws + L.vis_off);
   uint32_t* vis_total = reinterpret_cast<uint32_t*>(ws + L.vis_total);

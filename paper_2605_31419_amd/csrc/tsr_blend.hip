@@ -40,13 +40,20 @@ __device__ __forceinline__ int tile_of_block_ordered(int n_tiles, const int* __r
 }
 
 // Window value for rho in (0, 1): I = rho^sigma (eq. 3).  Mode 1: sigma = 1, 2: sigma = 0.5,
-// 3: sigma = 2, 0: any sigma.
+// 3: sigma = 2, 0: any sigma, 4: each face's own sigma (passed in from its record).
 template <int SM>
 __device__ __forceinline__ float window_pow(float rho, float sigma) {
   if constexpr (SM == 1) return rho;
   else if constexpr (SM == 2) return __builtin_sqrtf(rho);
   else if constexpr (SM == 3) return rho * rho;
   else return exp2f(sigma * log2f(rho));
+}
+
+// The exponent a face is evaluated with: its record's in mode 4, else the launch's.
+template <int SM>
+__device__ __forceinline__ float face_sigma(const float* r, float sigma) {
+  if constexpr (SM == 4) return r[kRecSigma];
+  else return sigma;
 }
 
 struct PixelEval {
@@ -84,7 +91,7 @@ __device__ __forceinline__ bool eval_face(const Rec& rc, float dx, float dy, flo
   e.k0 = E0 <= E1 && E0 <= E2;
   e.k1 = !e.k0 && E1 <= E2;
   e.rho = fminf(E0, fminf(E1, E2));
-  const float I = e.rho >= 1.f ? 1.f : window_pow<SM>(e.rho, sigma);   // meaningless when rho <= 0
+  const float I = e.rho >= 1.f ? 1.f : window_pow<SM>(e.rho, face_sigma<SM>(r, sigma));   // meaningless when rho <= 0
   const float alpha = r[kRecOpa] * I;
   const bool cov = e.rho > 0.f && alpha > 0.f;
   e.I = cov ? I : 0.f;
@@ -181,7 +188,8 @@ __device__ __forceinline__ unsigned long long batch_hit_mask(const float4* srec,
   bool hit = false;
   if (j < n) {
     const float4 rc = srec[j * 6 + kRecU0 / 4];
-    const int u0 = (int)rc.x, v0 = (int)rc.y, u1 = __float_as_int(rc.z), v1 = __float_as_int(rc.w);
+    const int u1v1 = __float_as_int(rc.z);
+    const int u0 = (int)rc.x, v0 = (int)rc.y, u1 = u1v1 & 0xffff, v1 = u1v1 >> 16;
     const int xl = max(bx, u0), xh = min(bx + 7, u1), yl = max(by, v0), yh = min(by + 7, v1);
     hit = xl <= xh && yl <= yh;
     if (hit) {
@@ -280,7 +288,7 @@ template <int SM, bool COOP>
 __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __restrict__ records,
                                               const uint64_t* __restrict__ pairs, float sigma, int last, float Tb,
                                               const PixGrad& pg, float4* srec, uint32_t* sface, int* sint,
-                                              acc_t* __restrict__ grad_acc) {
+                                              acc_t* __restrict__ grad_acc, float* __restrict__ sig_acc) {
   const int lane = threadIdx.x & 63;
   // highest list position any pixel of this wave (COOP: of the workgroup) blended
   const int wlast = uniform_int(wave_max_int(last));
@@ -353,7 +361,7 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
       const float gI = galpha * r[kRecOpa];
       float grho = 0.f;
       if constexpr (SM == 1) grho = (act && e.rho < 1.f) ? gI : 0.f;
-      else grho = (act && e.rho < 1.f) ? gI * sigma * I * __builtin_amdgcn_rcpf(e.rho) : 0.f;   // sigma I / rho
+      else grho = (act && e.rho < 1.f) ? gI * face_sigma<SM>(r, sigma) * I * __builtin_amdgcn_rcpf(e.rho) : 0.f;   // sigma I / rho
       // only the edge attaining the minimum receives the window gradient
       const float gk[3] = {e.k0 ? grho : 0.f, e.k1 ? grho : 0.f, (e.k0 || e.k1) ? 0.f : grho};
 #pragma unroll
@@ -366,6 +374,12 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
       if (ballot(act) == 0) continue;
       const float tot = wave_sum20(acc);
       if (k_out >= 0) unsafeAtomicAdd(&grad_acc[(size_t)sf[j] * kGradDwords + k_out], (acc_t)tot);
+      if constexpr (SM == 4) {
+        // the face's own exponent: dI/dsigma = I ln(rho) for 0 < rho < 1 (act implies rho > 0)
+        const float gsig = (act && e.rho < 1.f) ? gI * I * (0.69314718055994531f * log2f(e.rho)) : 0.f;
+        const float ts = wave_sum(gsig);
+        if (lane == 0) unsafeAtomicAdd(&sig_acc[sf[j]], ts);
+      }
     }
     }
   }
@@ -409,7 +423,7 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(ViewTable vt, const float*
                                                       const int* __restrict__ n_last, const float* __restrict__ t_last,
                                                       const float* __restrict__ gcolor, const float* __restrict__ gdepth,
                                                       const float* __restrict__ gtrans, acc_t* __restrict__ grad_acc,
-                                                      const int* __restrict__ order) {
+                                                      float* __restrict__ sig_acc, const int* __restrict__ order) {
   __shared__ float4 srec[kWaves][kBatch * 6];
   __shared__ uint32_t sface[kWaves][kBatch];
   const int wv = threadIdx.x >> 6;
@@ -433,7 +447,7 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(ViewTable vt, const float*
     pg.gd = gdepth[c.pix];
     pg.gt = gtrans ? gtrans[c.pix] : 0.f;
   }
-  backward_walk<SM, false>(c, records, pairs, sigma, last, Tb, pg, srec[wv], sface[wv], nullptr, grad_acc);
+  backward_walk<SM, false>(c, records, pairs, sigma, last, Tb, pg, srec[wv], sface[wv], nullptr, grad_acc, sig_acc);
 }
 
 // Fused training kernel: forward walk, L1 seeds of eqs. 8-10 (the D-SSIM term needs whole
@@ -447,7 +461,7 @@ __global__ __launch_bounds__(kBlock) void k_train_fused(ViewTable vt, const floa
                                                         const float* __restrict__ tcolor, const float* __restrict__ tdepth,
                                                         float* __restrict__ color, float* __restrict__ depth,
                                                         float* __restrict__ trans, float* __restrict__ loss_part,
-                                                        acc_t* __restrict__ grad_acc,
+                                                        acc_t* __restrict__ grad_acc, float* __restrict__ sig_acc,
                                                         const int* __restrict__ order, int* __restrict__ queue,
                                                         int persistent) {
   // the four waves stage each span together (one copy of the records per tile)
@@ -516,7 +530,7 @@ __global__ __launch_bounds__(kBlock) void k_train_fused(ViewTable vt, const floa
       const float ws = wave_sum(lpix);
       if (lane == 0) loss_part[kWaves * tile + quad] = ws;
     }
-    backward_walk<SM, true>(c, records, pairs, sigma, s.last, s.Tb, pg, srec, sface, sint, grad_acc);
+    backward_walk<SM, true>(c, records, pairs, sigma, s.last, s.Tb, pg, srec, sface, sint, grad_acc, sig_acc);
     if (!persistent) break;
   }
 }
@@ -805,7 +819,8 @@ __device__ void reduce_view_losses(const ViewTable& vt, const float* __restrict_
 // zero-filled outputs.  Workgroup 0 also converts the FP64 pose and loss sums (complete once
 // the face backward has finished) to the float outputs.
 __global__ __launch_bounds__(256) void k_vertex_gather(tsr_scene_dev sc, ViewTable vt, const uint32_t* __restrict__ counts,
-                                                       const acc_t* __restrict__ grad_acc, float* __restrict__ grad_pos,
+                                                       const acc_t* __restrict__ grad_acc,
+                                                       const float* __restrict__ sig_acc, float* __restrict__ grad_pos,
                                                        float* __restrict__ grad_col, float* __restrict__ grad_opa,
                                                        const double* __restrict__ pose_acc, float* __restrict__ grad_pose,
                                                        const double* __restrict__ loss_acc, float* __restrict__ loss) {
@@ -818,11 +833,13 @@ __global__ __launch_bounds__(256) void k_vertex_gather(tsr_scene_dev sc, ViewTab
 #pragma unroll
   for (int k = 0; k <= kStageFloats; ++k) acc[k] = 0.f;
   bool any = false;
+  float gsig = 0.f;     // dL/dsigma_m over the views (per-face exponents)
   if (m < M) {
     for (int v = 0; v < vt.n_views; ++v) {
       const int64_t g = (int64_t)v * M + m;
       if (counts[g] == 0) continue;
       any = true;
+      if (sig_acc) gsig += sig_acc[g];
       static_assert(kGradDwords == 20 && sizeof(acc_t) == 4, "a staged row is five 16-byte vectors");
       const float4* stage = reinterpret_cast<const float4*>(grad_acc + g * kGradDwords);
 #pragma unroll
@@ -835,6 +852,7 @@ __global__ __launch_bounds__(256) void k_vertex_gather(tsr_scene_dev sc, ViewTab
       }
     }
   }
+  if (sc.grad_face_sigma && m < M) sc.grad_face_sigma[m] = gsig;     // 0 for faces no view blends
   // with the minimum rule only the face's lowest-opacity vertex (lowest index on ties) gets the
   // opacity gradient
   int kmin = -1;
@@ -894,14 +912,17 @@ __global__ __launch_bounds__(256) void k_vertex_gather(tsr_scene_dev sc, ViewTab
 // longest-first tile order when `order` is given (tile counts the binning leaves it to).
 __global__ __launch_bounds__(256) void k_prep_bwd(ViewTable vt, const uint32_t* __restrict__ vis_total,
                                                   const uint32_t* __restrict__ vis_dense, acc_t* __restrict__ grad_acc,
-                                                  double* __restrict__ pose_acc, double* __restrict__ loss_acc,
-                                                  int* __restrict__ queue) {
+                                                  float* __restrict__ sig_acc, double* __restrict__ pose_acc,
+                                                  double* __restrict__ loss_acc, int* __restrict__ queue) {
   constexpr int kVec = (int)(kGradDwords * sizeof(acc_t)) / 16;      // 16-byte stores per row
   const int64_t nf = (int64_t)vt.n_views * vt.n_faces;
   const int64_t n = min((int64_t)*vis_total, nf) * kVec;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t g = (int64_t)vis_dense[i / kVec];
-    if (g < nf) reinterpret_cast<float4*>(grad_acc + g * kGradDwords)[i % kVec] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (g < nf) {
+      reinterpret_cast<float4*>(grad_acc + g * kGradDwords)[i % kVec] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (sig_acc && i % kVec == 0) sig_acc[g] = 0.f;
+    }
   }
   if (blockIdx.x == 0) {
     for (int k = threadIdx.x; k < kSumCopies * 6 * vt.n_views; k += blockDim.x) pose_acc[k] = 0.0;
@@ -1096,6 +1117,9 @@ static inline unsigned grid_for(int64_t n, int b) { return (unsigned)((n + b - 1
 
 static int sigma_mode(float s) { return s == 1.f ? 1 : (s == 0.5f ? 2 : (s == 2.f ? 3 : 0)); }
 
+// Per-face exponents (mode 4) whenever the scene has them, else the global sigma's mode.
+static int sigma_mode(const ViewTable& vt, const tsr_params& p) { return vt.face_sigma ? 4 : sigma_mode(p.sigma); }
+
 static unsigned tile_grid(int n_tiles) { return 8u * (unsigned)((n_tiles + 7) / 8); }
 
 // Per-face screen statistics of binned views: the same front-to-back walk and blending
@@ -1179,7 +1203,8 @@ hipError_t launch_face_stats(const ViewTable& vt, const tsr_params& p, const WsL
     if (visible) TSR_LAUNCH("fill_stats", k_fill_f32, dim3(fg), dim3(256), 0, st, reinterpret_cast<float*>(visible), nf);
   }
   const dim3 grid(tile_grid(vt.n_tiles)), block(kBlock);
-  switch (sigma_mode(p.sigma)) {
+  switch (sigma_mode(vt, p)) {
+    case 4: TSR_LAUNCH("face_stats", k_face_stats<4>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, coverage, visible, border); break;
     case 1: TSR_LAUNCH("face_stats", k_face_stats<1>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, coverage, visible, border); break;
     case 2: TSR_LAUNCH("face_stats", k_face_stats<2>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, coverage, visible, border); break;
     case 3: TSR_LAUNCH("face_stats", k_face_stats<3>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, coverage, visible, border); break;
@@ -1197,7 +1222,8 @@ hipError_t launch_forward(const ViewTable& vt, const tsr_params& p, const WsLayo
   int* n_last = reinterpret_cast<int*>(ws + L.n_last);
   float* t_last = reinterpret_cast<float*>(ws + L.t_last);
   const dim3 grid(tile_grid(vt.n_tiles)), block(kBlock);
-  switch (sigma_mode(p.sigma)) {
+  switch (sigma_mode(vt, p)) {
+    case 4: TSR_LAUNCH("blend_fwd", k_blend_fwd<4>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last, border); break;
     case 1: TSR_LAUNCH("blend_fwd", k_blend_fwd<1>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last, border); break;
     case 2: TSR_LAUNCH("blend_fwd", k_blend_fwd<2>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last, border); break;
     case 3: TSR_LAUNCH("blend_fwd", k_blend_fwd<3>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last, border); break;
@@ -1222,6 +1248,7 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
   const float* t_last = reinterpret_cast<const float*>(ws + L.t_last);
   acc_t* grad_acc = reinterpret_cast<acc_t*>(ws + L.grad_acc);
   double* pose_acc = reinterpret_cast<double*>(ws + L.pose_acc);
+  float* sig_acc = vt.face_sigma ? reinterpret_cast<float*>(ws + L.sig_acc) : nullptr;
   float* loss_part = reinterpret_cast<float*>(ws + L.loss_part);
   double* loss_acc = reinterpret_cast<double*>(ws + L.loss_acc);
   const int64_t nf = (int64_t)vt.n_views * vt.n_faces;
@@ -1233,28 +1260,29 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
   {
     const int64_t rows16 = nf * (int64_t)((kGradDwords * sizeof(acc_t)) / 16);
     const unsigned g = (unsigned)std::min<int64_t>(std::max<int64_t>(grid_for(rows16, 256), 1), 2048);
-    TSR_LAUNCH("prep_bwd", k_prep_bwd, dim3(g), dim3(256), 0, st, vt, vis_total, vis_dense, grad_acc, pose_acc,
-               loss_acc, queue);
+    TSR_LAUNCH("prep_bwd", k_prep_bwd, dim3(g), dim3(256), 0, st, vt, vis_total, vis_dense, grad_acc, sig_acc,
+               pose_acc, loss_acc, queue);
   }
   const dim3 block(kBlock);
-  const int sm = sigma_mode(p.sigma);
+  const int sm = sigma_mode(vt, p);
   if (!fused_train) {
     const dim3 grid(tile_grid(vt.n_tiles));
     const int* border = order;
-#define TSR_BWD(S) TSR_LAUNCH("blend_bwd", k_blend_bwd<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, n_last, t_last, gcolor, gdepth, gtrans, grad_acc, border)
-    switch (sm) { case 1: TSR_BWD(1); break; case 2: TSR_BWD(2); break; case 3: TSR_BWD(3); break; default: TSR_BWD(0); }
+#define TSR_BWD(S) TSR_LAUNCH("blend_bwd", k_blend_bwd<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, n_last, t_last, gcolor, gdepth, gtrans, grad_acc, sig_acc, border)
+    switch (sm) { case 1: TSR_BWD(1); break; case 2: TSR_BWD(2); break; case 3: TSR_BWD(3); break; case 4: TSR_BWD(4); break; default: TSR_BWD(0); }
 #undef TSR_BWD
   } else {
     dim3 grid(tile_grid(vt.n_tiles));
     if (sched.order && !sched.persistent) grid = dim3(vt.n_tiles);
     if (sched.persistent) grid = dim3(sched.grid > 0 ? sched.grid : 2048);
-#define TSR_TRAIN(S) TSR_LAUNCH("train_fused", k_train_fused<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, p.w_color, p.w_depth, tcolor, tdepth, color, depth, trans, loss ? loss_part : nullptr, grad_acc, order, queue, sched.persistent)
-    switch (sm) { case 1: TSR_TRAIN(1); break; case 2: TSR_TRAIN(2); break; case 3: TSR_TRAIN(3); break; default: TSR_TRAIN(0); }
+#define TSR_TRAIN(S) TSR_LAUNCH("train_fused", k_train_fused<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, p.w_color, p.w_depth, tcolor, tdepth, color, depth, trans, loss ? loss_part : nullptr, grad_acc, sig_acc, order, queue, sched.persistent)
+    switch (sm) { case 1: TSR_TRAIN(1); break; case 2: TSR_TRAIN(2); break; case 3: TSR_TRAIN(3); break; case 4: TSR_TRAIN(4); break; default: TSR_TRAIN(0); }
 #undef TSR_TRAIN
   }
   // per visible (view, face): chain rule and pose; then per face: vertex gradients summed
   // over the views (indexed meshes add into zero-filled outputs)
   const bool want_vertices = grad_pos || grad_col || grad_opa;
+  const bool want_gather = want_vertices || sc.grad_face_sigma;
   const int64_t N = sc.n_vertices;
   if (sc.faces && want_vertices) {
     if (grad_pos) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(2048), dim3(256), 0, st, grad_pos, 3 * N);
@@ -1266,9 +1294,9 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
     TSR_LAUNCH("face_bwd", k_face_bwd, fgrid, dim3(256), 0, st, sc, poses, vt, vis_total, vis_dense, records,
                grad_acc, grad_pose ? pose_acc : nullptr, want_vertices ? 1 : 0, loss ? loss_part : nullptr,
                loss_acc);
-    if (want_vertices)
+    if (want_gather)
       TSR_LAUNCH("vertex_gather", k_vertex_gather, dim3(grid_for(vt.n_faces, 256)), dim3(256), 0, st, sc, vt, counts,
-                 grad_acc, grad_pos, grad_col, grad_opa, pose_acc, grad_pose, loss_acc, loss);
+                 grad_acc, sig_acc, grad_pos, grad_col, grad_opa, pose_acc, grad_pose, loss_acc, loss);
     if (want_vertices && !sc.faces && N > 3 * vt.n_faces)
       TSR_LAUNCH("zero_grads", k_zero_soup_tail, dim3(std::min<unsigned>(grid_for(N - 3 * vt.n_faces, 256), 1024u)),
                  dim3(256), 0, st, grad_pos, grad_col, grad_opa, N, 3 * vt.n_faces);
@@ -1277,7 +1305,7 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
     if (grad_col) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(2048), dim3(256), 0, st, grad_col, 3 * N);
     if (grad_opa) TSR_LAUNCH("zero_grads", k_fill_f32, dim3(2048), dim3(256), 0, st, grad_opa, N);
   }
-  if ((nf <= 0 || !want_vertices) && (grad_pose || loss))     // otherwise k_vertex_gather converts them
+  if ((nf <= 0 || !want_gather) && (grad_pose || loss))     // otherwise k_vertex_gather converts them
     TSR_LAUNCH("finalize", k_finalize, dim3(1), dim3(kBlock), 0, st, vt, pose_acc, grad_pose, loss_acc,
                nf <= 0 ? loss_part : nullptr, loss);
   return hipGetLastError();

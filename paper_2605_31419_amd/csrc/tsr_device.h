@@ -27,8 +27,8 @@ enum RecordField : int {
   kRecZ = 19,        // z_F
   kRecU0 = 20,       // u0 as a float (an exact integer)
   kRecV0 = 21,       // v0 as a float (an exact integer)
-  kRecU1 = 22,       // int u1
-  kRecV1 = 23,       // int v1
+  kRecU1V1 = 22,     // int u1 | (v1 << 16)  (image sizes are at most 16384)
+  kRecSigma = 23,    // the face's window exponent sigma (eq. 3)
   kRecDwords = 24
 };
 
@@ -58,6 +58,8 @@ struct ViewTable {
   int32_t n_views;
   int32_t n_tiles;         // total tiles
   int64_t n_faces;         // M
+  int32_t face_sigma;      // the scene has per-face window exponents (records hold each face's)
+  int32_t pad;
 };
 
 __device__ __forceinline__ int view_of_tile(const ViewTable& vt, int tile) {

@@ -19,6 +19,8 @@ struct tsr_scene_dev {
   int64_t n_vertices;
   int64_t n_faces;
   int32_t opa_min;       // face opacity: 0 = vertex mean, 1 = vertex minimum
+  const float* face_sigma;   // [M] per-face window exponents, or nullptr (the parameters' sigma)
+  float* grad_face_sigma;    // [M] dL/dsigma_m output of the backward, or nullptr
 };
 
 // Byte offsets of the workspace regions.  Fixed part first (depends on M, the views and
@@ -33,6 +35,7 @@ struct WsLayout {
   size_t counts;                   // uint32 [V*M]
   size_t records;                  // float  [V*M][24]
   size_t grad_acc;                 // float  [V*M][20]
+  size_t sig_acc;                  // float  [V*M]: dL/dsigma of each (view, face) (per-face exponents)
   size_t tile_cnt;                 // uint32 [T][4]: [0] faces with <= 4 tiles, [2] larger faces (later
                                    // their emission cursor), [1] and [3] unused, so that every counter
                                    // the atomics hit sits alone in its 8-byte word; then the uint32

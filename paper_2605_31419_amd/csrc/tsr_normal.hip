@@ -285,6 +285,7 @@ hipError_t launch_train_normal(const tsr_scene_dev& sc, const float* poses, cons
   if (M > 0) TSR_LAUNCH("normal_colours", k_normal_colours, dim3(fb), dim3(256), 0, st, sc.pos, N, M, col);
   tsr_scene_dev sn = sc;
   sn.col = col;
+  sn.grad_face_sigma = nullptr;     // this loss renders with the exponents but does not return their gradient
   hipError_t e = launch_bin(sn, poses, vt, p, L, ws, true, st);
   if (e != hipSuccess) return e;
   e = launch_forward(vt, p, L, ws, nw, dep, nullptr, st);

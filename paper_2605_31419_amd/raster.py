@@ -59,25 +59,33 @@ class DeviceScene:
     """Scene arrays resident on the device (SoA float32, optional int32 faces)."""
 
     def __init__(self, pos: torch.Tensor, col: torch.Tensor, opa: torch.Tensor,
-                 faces: Optional[torch.Tensor] = None):
-        for name, t in (("pos", pos), ("col", col), ("opa", opa)):
+                 faces: Optional[torch.Tensor] = None, face_sigma: Optional[torch.Tensor] = None):
+        for name, t in (("pos", pos), ("col", col), ("opa", opa)) + ((("face_sigma", face_sigma),)
+                                                                     if face_sigma is not None else ()):
             if t.device.type != "cuda" or t.dtype != torch.float32 or not t.is_contiguous():
                 raise ValueError(f"{name} must be a contiguous float32 CUDA tensor")
         self.pos, self.col, self.opa = pos, col, opa
         self.faces = faces
         self.n_vertices = int(pos.shape[1])
         self.n_faces = int(faces.shape[0]) if faces is not None else self.n_vertices // 3
+        # per-face window exponents (Triangle Splatting variant), or None for the global sigma
+        self.face_sigma = face_sigma
+        if face_sigma is not None and face_sigma.numel() != self.n_faces:
+            raise ValueError(f"face_sigma needs {self.n_faces} values")
 
     @classmethod
     def from_numpy(cls, scene, device="cuda") -> "DeviceScene":
         f = None if scene.faces is None else torch.as_tensor(scene.faces, dtype=torch.int32, device=device).contiguous()
+        fs = getattr(scene, "face_sigma", None)
+        fs = None if fs is None else torch.as_tensor(np.asarray(fs, np.float32), device=device).contiguous()
         return cls(torch.as_tensor(scene.pos, device=device).contiguous(),
                    torch.as_tensor(scene.col, device=device).contiguous(),
-                   torch.as_tensor(scene.opa, device=device).contiguous(), f)
+                   torch.as_tensor(scene.opa, device=device).contiguous(), f, fs)
 
     def c(self) -> TsrScene:
         return TsrScene(self.pos.data_ptr(), self.col.data_ptr(), self.opa.data_ptr(),
-                        None if self.faces is None else self.faces.data_ptr(), self.n_vertices, self.n_faces)
+                        None if self.faces is None else self.faces.data_ptr(), self.n_vertices, self.n_faces,
+                        None if self.face_sigma is None else self.face_sigma.data_ptr(), None)
 
 
 def poses_tensor(poses, device="cuda") -> torch.Tensor:
@@ -111,6 +119,9 @@ class Rasterizer:
         # bumped by every call that rewrites the binning or the per-pixel state in the workspace
         # (the autograd Function checks it between its forward and backward)
         self.generation = 0
+        # dL/dsigma_m of the latest backward when the scene has per-face exponents
+        self.grad_face_sigma = (torch.empty(scene.n_faces, device=device) if scene.face_sigma is not None
+                                else None)
         if workspace is not None and workspace.numel() >= self.workspace_bytes(capacity):
             # caller-provided buffer (e.g. reused across requests): use all of it
             self.ws = workspace
@@ -191,8 +202,17 @@ class Rasterizer:
         gpose = torch.empty(6 * self.n_views, device=self.device) if want[3] else None
         return gp, gc, go, gpose
 
-    def backward(self, poses: torch.Tensor, grad_color, grad_depth, grad_trans=None, out=None, stream=None):
+    def _sigma_out(self, grad_face_sigma: Optional[torch.Tensor]) -> None:
+        """Points the scene's dL/dsigma output at `grad_face_sigma` (default: this rasterizer's
+        buffer) when the scene has per-face exponents."""
+        if self.scene.face_sigma is not None:
+            buf = grad_face_sigma if grad_face_sigma is not None else self.grad_face_sigma
+            self._cscene.grad_face_sigma = buf.data_ptr()
+
+    def backward(self, poses: torch.Tensor, grad_color, grad_depth, grad_trans=None, out=None, stream=None,
+                 grad_face_sigma=None):
         gp, gc, go, gpose = out if out is not None else self.grad_buffers()
+        self._sigma_out(grad_face_sigma)
         check(self.lib.tsr_render_backward(*self._args(poses), _ptr(grad_color), _ptr(grad_depth), _ptr(grad_trans),
                                            _ptr(gp), _ptr(gc), _ptr(go), _ptr(gpose), _stream(stream)),
               "tsr_render_backward")
@@ -202,6 +222,7 @@ class Rasterizer:
                  loss=None, out=None, schedule=None, stream=None):
         self.generation += 1
         gp, gc, go, gpose = out if out is not None else self.grad_buffers()
+        self._sigma_out(None)
         sched = self.schedule if schedule is None else schedule
         sp = None if sched is None else C.byref(TsrSchedule(*sched))
         check(self.lib.tsr_render_train_l1(*self._args(poses), _ptr(target_color), _ptr(target_depth), _ptr(color),
@@ -226,6 +247,7 @@ class Rasterizer:
         color = color if color is not None else torch.empty(3 * P, device=self.device)
         depth = depth if depth is not None else torch.empty(P, device=self.device)
         gp, gc, go, gpose = out if out is not None else self.grad_buffers()
+        self._sigma_out(None)
         sc = self.photometric_scratch()
         check(self.lib.tsr_render_train_photometric(*self._args(poses), _ptr(target_color), _ptr(target_depth),
                                                     float(w_ssim), _ptr(color), _ptr(depth), _ptr(trans), _ptr(loss),
@@ -412,7 +434,7 @@ class TriangleRasterFn(torch.autograd.Function):
     rasterizer's workspace has been re-binned or re-rendered by another call."""
 
     @staticmethod
-    def forward(ctx, pos, col, opa, tau, rast: Rasterizer, poses: torch.Tensor):
+    def forward(ctx, pos, col, opa, face_sigma, tau, rast: Rasterizer, poses: torch.Tensor):
         eff = poses if tau is None else compose_poses(tau, poses)
         rast.bin_and_sort(eff)
         color, depth, trans = rast.forward(eff)
@@ -433,16 +455,17 @@ class TriangleRasterFn(torch.autograd.Function):
         g_color = g_color.contiguous() if g_color is not None else torch.zeros(3 * rast.total_pixels, device=eff.device)
         g_depth = g_depth.contiguous() if g_depth is not None else torch.zeros(rast.total_pixels, device=eff.device)
         g_trans = g_trans.contiguous() if g_trans is not None else None
-        gp, gc, go, gpose = rast.backward(eff, g_color, g_depth, g_trans)
+        gsig = torch.empty_like(rast.scene.face_sigma) if rast.scene.face_sigma is not None else None
+        gp, gc, go, gpose = rast.backward(eff, g_color, g_depth, g_trans, grad_face_sigma=gsig)
         N = rast.scene.n_vertices
         gtau = tau_gradient(tau, gpose) if ctx.has_tau else None
-        return gp.view(3, N), gc.view(3, N), go.view(N), gtau, None, None
+        return gp.view(3, N), gc.view(3, N), go.view(N), gsig, gtau, None, None
 
 
 def rasterize(rast: Rasterizer, poses: torch.Tensor, tau: Optional[torch.Tensor] = None):
     """Differentiable colour [3P], depth [P], transmittance [P] (packed per view) of the
     rasterizer's scene.  Gradients flow to rast.scene.pos / col / opa (when they require
-    grad) and to ``tau`` ([V, 6] se(3) left perturbation: the scene is rendered at
-    Exp(tau) o T_CW)."""
+    grad), to rast.scene.face_sigma (per-face window exponents, when the scene has them) and
+    to ``tau`` ([V, 6] se(3) left perturbation: the scene is rendered at Exp(tau) o T_CW)."""
     sc = rast.scene
-    return TriangleRasterFn.apply(sc.pos, sc.col, sc.opa, tau, rast, poses)
+    return TriangleRasterFn.apply(sc.pos, sc.col, sc.opa, sc.face_sigma, tau, rast, poses)

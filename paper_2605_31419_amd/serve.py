@@ -141,7 +141,10 @@ class GpuExecutor:
         for v in range(max(1, max_views), 0, -1):
             if v > 1 and v * px > max_pixels:
                 continue
-            ws = self._workspace_bytes([intr] * v, self._capacity([intr] * v))
+            # pair room for the batch at the estimated density, and for one view at four times it
+            # (a view close to a wall can list several times the average; pairs cost 16 B each)
+            cap = max(self._capacity([intr] * v), 4 * self._capacity([intr]))
+            ws = self._workspace_bytes([intr] * v, cap)
             if n_slots * (ws + v * px * self.OUT_BYTES_PER_PIXEL) <= budget:
                 self.slot_bytes = ws
                 return n_slots * ws, v
