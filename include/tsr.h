@@ -97,6 +97,12 @@ typedef struct {
                             paper's choice); 1: = their minimum (the Mesh Splatting variant the
                             paper's ablation compares with), the opacity gradient then going to
                             the lowest-opacity vertex (the lowest index on ties) */
+    int32_t tight_tiles; /* 0: a face is listed in every tile of its pixel rectangle (conservative
+                            bounding box); 1: only in the tiles whose box of pixel centres (clipped
+                            to the rectangle) reaches below 0 in every edge function of eq. 2, i.e.
+                            that can hold a pixel the face covers.  Images and gradients are the
+                            same either way (the dropped pairs have alpha = 0 at every pixel of
+                            their tile); the lists are shorter.  Decided in FP64. */
 } tsr_params;
 
 /* Scene (host struct of device pointers). */

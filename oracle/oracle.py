@@ -34,7 +34,8 @@ class _Cam(C.Structure):
 
 
 class _Par(C.Structure):
-    _fields_ = [("sigma", C.c_double), ("z_near", C.c_double), ("r_min", C.c_double), ("opa_min", C.c_double)]
+    _fields_ = [("sigma", C.c_double), ("z_near", C.c_double), ("r_min", C.c_double), ("opa_min", C.c_double),
+                ("tight_tiles", C.c_double), ("persp", C.c_double)]
 
 
 _lib = None
@@ -50,7 +51,7 @@ def lib():
         _lib.orc_render.argtypes = [P, P, P, P, P, C.c_int64, P, P, P]
         _lib.orc_backward.argtypes = [P, P, P, P, P, C.c_int64, P, P, P, P, P, P, P]
         _lib.orc_backward_abs.argtypes = [P, P, P, P, P, C.c_int64, P, P, P, P, P, P, P, P, P, P]
-        _lib.orc_backward_sigma.argtypes = [P, P, P, P, P, C.c_int64, P, P, P, P, P, P, P, P]
+        _lib.orc_backward_sigma.argtypes = [P, P, P, P, P, C.c_int64, P, P, P, P, P, P, P, P, P, P, P, P]
         _lib.orc_project.argtypes = [P, P, P, P, P, P, P, P]
         _lib.orc_bin.argtypes = [P, P, P, C.c_int, P, C.c_int64, P, P, P, P, P]
         _lib.orc_l1_seeds.argtypes = [P, P, P, P, C.c_int64, C.c_int64, C.c_double, C.c_double, P, P]
@@ -89,7 +90,8 @@ def _ptr(a: Optional[np.ndarray]):
 class _Args:
     """Keeps the contiguous arrays alive for the duration of a call."""
 
-    def __init__(self, scene, pose, intr, sigma, z_near, r_min, opacity_min=False):
+    def __init__(self, scene, pose, intr, sigma, z_near, r_min, opacity_min=False, tight_tiles=False,
+                 perspective=False):
         # float32 inputs are promoted exactly; float64 inputs (finite differences) pass as is
         self.pos = np.ascontiguousarray(scene.pos, dtype=np.float64)
         self.col = np.ascontiguousarray(scene.col, dtype=np.float64)
@@ -101,7 +103,8 @@ class _Args:
                          self.pos.shape[1], scene.n_faces, _ptr(self.face_sigma))
         self.pose = np.ascontiguousarray(np.asarray(pose, dtype=np.float64).reshape(-1))
         self.cam = _cam(intr)
-        self.par = _Par(sigma, z_near, r_min, 1.0 if opacity_min else 0.0)
+        self.par = _Par(sigma, z_near, r_min, 1.0 if opacity_min else 0.0, 1.0 if tight_tiles else 0.0,
+                        1.0 if perspective else 0.0)
 
 
 def _cam(intr) -> _Cam:
@@ -118,11 +121,13 @@ def max_threads() -> int:
 
 
 def render(scene, pose, intr, sigma=1.0, z_near=0.1, r_min=1e-3,
-           pixels: Optional[np.ndarray] = None, opacity_min: bool = False) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+           pixels: Optional[np.ndarray] = None, opacity_min: bool = False,
+           perspective: bool = False) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
     """Colour [3, P], depth [P], final transmittance [P] of the listed pixel indices
     (y*W + x), or of the whole frame when `pixels` is None (P = H*W).  `opacity_min` selects
-    the face opacity min(o_i) instead of the mean."""
-    a = _Args(scene, pose, intr, sigma, z_near, r_min, opacity_min)
+    the face opacity min(o_i) instead of the mean; `perspective` the perspective-correct
+    colour interpolation and plane depth."""
+    a = _Args(scene, pose, intr, sigma, z_near, r_min, opacity_min, perspective=perspective)
     pix = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int64)
     n = a.cam.width * a.cam.height if pix is None else pix.shape[0]
     col = np.zeros((3, n)); dep = np.zeros(n); tr = np.zeros(n)
@@ -136,13 +141,14 @@ def render(scene, pose, intr, sigma=1.0, z_near=0.1, r_min=1e-3,
 def backward(scene, pose, intr, g_color: np.ndarray, g_depth: np.ndarray,
              g_trans: Optional[np.ndarray] = None, sigma=1.0, z_near=0.1, r_min=1e-3,
              pixels: Optional[np.ndarray] = None, with_abs: bool = False, opacity_min: bool = False,
-             want_sigma: bool = False):
+             want_sigma: bool = False, perspective: bool = False):
     """Gradients (pos [3,N], col [3,N], opa [N], pose [6]) from the listed pixels' upstream
     gradients g_color [3,P], g_depth [P], g_trans [P].  With `with_abs`, also returns the
     per-element sums of absolute per-pixel contributions (pos, col, opa) -- the conditioning
     that bounds the rounding error of a lower-precision implementation.  With `want_sigma`
-    (scenes with per-face exponents), also returns dL/dsigma per face [M]."""
-    a = _Args(scene, pose, intr, sigma, z_near, r_min, opacity_min)
+    (scenes with per-face exponents), also returns dL/dsigma per face [M].  `perspective` as
+    for render."""
+    a = _Args(scene, pose, intr, sigma, z_near, r_min, opacity_min, perspective=perspective)
     pix = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int64)
     n = a.cam.width * a.cam.height if pix is None else pix.shape[0]
     gc = np.ascontiguousarray(np.asarray(g_color, np.float64).reshape(3, n))
@@ -151,13 +157,17 @@ def backward(scene, pose, intr, g_color: np.ndarray, g_depth: np.ndarray,
     N = a.pos.shape[1]
     gpos = np.zeros((3, N)); gcol = np.zeros((3, N)); gopa = np.zeros(N); gpose = np.zeros(6)
     if want_sigma:
-        gsig = np.zeros(max(int(a.sc.n_faces), 1))
+        M = int(a.sc.n_faces)
+        gsig = np.zeros(max(M, 1))
+        absv = [np.zeros((3, N)), np.zeros((3, N)), np.zeros(N), np.zeros(max(M, 1))] if with_abs else [None] * 4
         rc = lib().orc_backward_sigma(C.byref(a.sc), _ptr(a.pose), C.byref(a.cam), C.byref(a.par), _ptr(pix), n,
                                       _ptr(gc), _ptr(gd), _ptr(gt), _ptr(gpos), _ptr(gcol), _ptr(gopa), _ptr(gpose),
-                                      _ptr(gsig))
+                                      _ptr(gsig), *[_ptr(x) for x in absv])
         if rc:
             raise ValueError(f"orc_backward_sigma failed ({rc})")
-        return gpos, gcol, gopa, gpose, gsig[:int(a.sc.n_faces)]
+        if with_abs:
+            return gpos, gcol, gopa, gpose, gsig[:M], (absv[0], absv[1], absv[2], absv[3][:M])
+        return gpos, gcol, gopa, gpose, gsig[:M]
     if with_abs:
         apos = np.zeros((3, N)); acol = np.zeros((3, N)); aopa = np.zeros(N)
         rc = lib().orc_backward_abs(C.byref(a.sc), _ptr(a.pose), C.byref(a.cam), C.byref(a.par), _ptr(pix), n,
@@ -186,9 +196,11 @@ def project(scene, pose, intr, sigma=1.0, z_near=0.1, r_min=1e-3):
     return q, f, rect, tiles
 
 
-def bin_pairs(scene, poses: Sequence[np.ndarray], intrs: Sequence, sigma=1.0, z_near=0.1, r_min=1e-3):
-    """Reference tile lists: (tile[K], zbits[K], face[K], ranges[T_total, 2])."""
-    a = _Args(scene, poses[0], intrs[0], sigma, z_near, r_min)
+def bin_pairs(scene, poses: Sequence[np.ndarray], intrs: Sequence, sigma=1.0, z_near=0.1, r_min=1e-3,
+              tight_tiles=False):
+    """Reference tile lists: (tile[K], zbits[K], face[K], ranges[T_total, 2]); `tight_tiles`
+    keeps only the tiles of a face's rectangle that can hold a pixel the face covers."""
+    a = _Args(scene, poses[0], intrs[0], sigma, z_near, r_min, tight_tiles=tight_tiles)
     V = len(poses)
     ps = np.ascontiguousarray(np.stack([np.asarray(p, np.float64).reshape(12) for p in poses]))
     cams = (_Cam * V)(*[_cam(i) for i in intrs])

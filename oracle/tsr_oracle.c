@@ -55,7 +55,16 @@ typedef struct { int32_t width, height; double fx, fy, cx, cy; } orc_cam;
 /* opa_min: 0 = face opacity is the mean of its vertex opacities (Sec. 3.1); 1 = their minimum
  * (the Mesh Splatting rule the paper departs from), whose derivative goes to the vertex of
  * lowest opacity (lowest index on ties). */
-typedef struct { double sigma, z_near, r_min, opa_min; } orc_par;
+/* tight_tiles: 0 = a face is listed in every tile of its pixel rectangle (the conservative
+ * bounding-box rule); 1 = only in the tiles whose pixel centres inside that rectangle can be
+ * inside the face: for each edge k the smallest L_k over the tile's box of pixel centres is
+ * below 0 (the triangle-tile binning variant). */
+/* persp: 0 = colour interpolated with the screen-space (affine) barycentrics of the projected
+ * triangle and depth z_F (the reading of Sec. 3.1 and eq. 4); 1 = perspective-correct
+ * barycentrics mu_i = (lambda_i / z_i) / sum_j (lambda_j / z_j) for the colour and the depth of
+ * the face's plane along the pixel's ray, 1 / sum_j (lambda_j / z_j), in D (the variant).  The
+ * depth order stays that of z_F. */
+typedef struct { double sigma, z_near, r_min, opa_min, tight_tiles, persp; } orc_par;
 
 static int64_t vid(const orc_scene *s, int64_t m, int k) {
     return s->faces ? (int64_t)s->faces[3 * m + k] : 3 * m + k;
@@ -71,6 +80,7 @@ typedef struct {
     double area2, perim, r;
     double zf, of;
     double sig;           /* the face's window exponent sigma (eq. 3) */
+    int persp;            /* perspective-correct interpolation (orc_par.persp) */
     int kmin;             /* vertex of lowest opacity (lowest index on ties) */
     float zkey;
     double umin, umax, vmin, vmax;
@@ -91,6 +101,7 @@ static void face_setup(const orc_scene *s, const double *pose, const orc_cam *c,
     int64_t N = s->n_vertices;
     f->ok = 0;
     f->sig = s->face_sigma ? s->face_sigma[m] : p->sigma;
+    f->persp = p->persp != 0.0;
     for (int k = 0; k < 3; k++) {
         int64_t i = vid(s, m, k);
         f->v[k] = i;
@@ -188,6 +199,13 @@ static int64_t pixel_hits(const orc_scene *s, const face_t *F, int u, int v, hit
         if (n == cap) { cap *= 2; h = (hit_t *)realloc(h, sizeof(hit_t) * cap); }
         hit_t *e = &h[n++];
         e->zkey = f->zkey; e->m = m; e->alpha = alpha; e->I = I; e->rho = rho; e->zf = f->zf;
+        if (f->persp) {
+            /* perspective-correct weights and the plane's depth along the ray (1/z is affine) */
+            double w[3], W = 0;
+            for (int i = 0; i < 3; i++) { w[i] = lam[i] / f->vc[i][2]; W += w[i]; }
+            for (int i = 0; i < 3; i++) lam[i] = w[i] / W;
+            e->zf = 1.0 / W;
+        }
         for (int i = 0; i < 3; i++) e->lam[i] = lam[i];
         for (int ch = 0; ch < 3; ch++) {
             double acc = 0;
@@ -327,6 +345,16 @@ static void face_local_dual(const face_t *f, const orc_cam *c, double u, double 
     lam[0] = dn_scale(dn_div(dn_mul(L[1], len[1]), area), -1.0);
     lam[1] = dn_scale(dn_div(dn_mul(L[2], len[2]), area), -1.0);
     lam[2] = dn_scale(dn_div(dn_mul(L[0], len[0]), area), -1.0);
+    if (f->persp) {
+        dn w[3], W = dn_const(0);
+        for (int i = 0; i < 3; i++) {
+            w[i] = dn_div(lam[i], dn_var(f->vc[i][2], 3 * i + 2));
+            W = dn_add(W, w[i]);
+        }
+        for (int i = 0; i < 3; i++) lam[i] = dn_div(w[i], W);
+        *zf_out = dn_div(dn_const(1.0), W);
+        return;
+    }
     dn zf = dn_const(0);
     for (int k = 0; k < 3; k++) zf = dn_add(zf, dn_var(f->vc[k][2], 3 * k + 2));
     *zf_out = dn_scale(zf, 1.0 / 3.0);
@@ -343,7 +371,7 @@ static int backward_impl(const orc_scene *s, const double *pose, const orc_cam *
                          const int64_t *pix, int64_t npix, const double *gC, const double *gD,
                          const double *gT, double *grad_pos, double *grad_col, double *grad_opa,
                          double *grad_pose, double *abs_pos, double *abs_col, double *abs_opa,
-                         double *grad_sigma) {
+                         double *grad_sigma, double *abs_sigma) {
     int rc = check_args(s, pose, c, p);
     if (rc) return rc;
     int64_t M = s->n_faces, N = s->n_vertices;
@@ -421,6 +449,10 @@ static int backward_impl(const orc_scene *s, const double *pose, const orc_cam *
                 double gs = galpha * f->of * e->I * log(e->rho);
                 #pragma omp atomic
                 grad_sigma[e->m] += gs;
+                if (abs_sigma) {
+                    #pragma omp atomic
+                    abs_sigma[e->m] += fabs(gs);
+                }
             }
             for (int ch = 0; ch < 3; ch++) B[ch] = e->c[ch] * e->alpha + (1.0 - e->alpha) * B[ch];
             BD = e->zf * e->alpha + (1.0 - e->alpha) * BD;
@@ -458,7 +490,7 @@ int orc_backward_abs(const orc_scene *s, const double *pose, const orc_cam *c, c
                      const double *gT, double *grad_pos, double *grad_col, double *grad_opa,
                      double *grad_pose, double *abs_pos, double *abs_col, double *abs_opa) {
     return backward_impl(s, pose, c, p, pix, npix, gC, gD, gT, grad_pos, grad_col, grad_opa, grad_pose,
-                         abs_pos, abs_col, abs_opa, NULL);
+                         abs_pos, abs_col, abs_opa, NULL, NULL);
 }
 
 int orc_backward(const orc_scene *s, const double *pose, const orc_cam *c, const orc_par *p,
@@ -466,17 +498,19 @@ int orc_backward(const orc_scene *s, const double *pose, const orc_cam *c, const
                  const double *gT, double *grad_pos, double *grad_col, double *grad_opa,
                  double *grad_pose) {
     return backward_impl(s, pose, c, p, pix, npix, gC, gD, gT, grad_pos, grad_col, grad_opa, grad_pose,
-                         NULL, NULL, NULL, NULL);
+                         NULL, NULL, NULL, NULL, NULL);
 }
 
-/* As orc_backward, plus (+=) the gradient with respect to each face's window exponent:
- * grad_sigma[M] = sum over blended pixels of dL/dalpha o_F I ln(rho). */
+/* As orc_backward_abs, plus (+=) the gradient with respect to each face's window exponent,
+ * grad_sigma[M] = sum over blended pixels of dL/dalpha o_F I ln(rho), and (abs_sigma,
+ * nullable) the sums of its absolute per-pixel terms. */
 int orc_backward_sigma(const orc_scene *s, const double *pose, const orc_cam *c, const orc_par *p,
                        const int64_t *pix, int64_t npix, const double *gC, const double *gD,
                        const double *gT, double *grad_pos, double *grad_col, double *grad_opa,
-                       double *grad_pose, double *grad_sigma) {
+                       double *grad_pose, double *grad_sigma, double *abs_pos, double *abs_col,
+                       double *abs_opa, double *abs_sigma) {
     return backward_impl(s, pose, c, p, pix, npix, gC, gD, gT, grad_pos, grad_col, grad_opa, grad_pose,
-                         NULL, NULL, NULL, grad_sigma);
+                         abs_pos, abs_col, abs_opa, grad_sigma, abs_sigma);
 }
 
 /* L1 loss of eqs. (8)-(10) without the D-SSIM term, as means over pixels (and channels):
@@ -554,8 +588,24 @@ static int pair_cmp(const void *a, const void *b) {
     return (x->face > y->face) - (x->face < y->face);
 }
 
+/* Can tile (x, y) of face f's pixel rectangle r = [u0, u1, v0, v1] hold a pixel the face
+ * covers?  Every covered pixel p has L_k(p) < 0 for all three edges (eq. 2: rho > 0 needs
+ * phi < 0), and an affine L_k is smallest over the tile's box of pixel centres at one corner;
+ * the tile is kept when that smallest value is below 0 for every edge. */
+static int tile_may_cover(const face_t *f, const int r[4], int x, int y) {
+    double ulo = fmax(16.0 * x, r[0]), uhi = fmin(16.0 * x + 15.0, r[1]);
+    double vlo = fmax(16.0 * y, r[2]), vhi = fmin(16.0 * y + 15.0, r[3]);
+    for (int k = 0; k < 3; k++) {
+        double u = f->n[k][0] > 0 ? ulo : uhi, v = f->n[k][1] > 0 ? vlo : vhi;
+        double lmin = f->n[k][0] * u + f->n[k][1] * v + f->d[k];
+        if (!(lmin < 0)) return 0;
+    }
+    return 1;
+}
+
 /* Tile lists for views v = 0..n_views-1 (poses [V][12], cams [V]).  Every (tile, face) pair
- * of every face's tile rectangle, sorted by (view-major global tile, float32 z bits, face);
+ * of every face's tile rectangle (with tight_tiles, those tile_may_cover keeps), sorted by
+ * (view-major global tile, float32 z bits, face);
  * faces are numbered v*M + m.  Writes *K; if cap >= K also writes tile_out[K], zbits_out[K],
  * face_out[K] and ranges[2*T_total] (start, end per global tile).  Returns ORC_ECAP when the
  * arrays are too small (K is still set). */
@@ -586,6 +636,7 @@ int orc_bin(const orc_scene *s, const double *poses, const orc_cam *cams, int n_
             memcpy(&zb, &F[m].zkey, 4);
             for (int y = r[2] >> 4; y <= r[3] >> 4; y++)
                 for (int x = r[0] >> 4; x <= r[1] >> 4; x++) {
+                    if (p->tight_tiles != 0.0 && !tile_may_cover(&F[m], r, x, y)) continue;
                     if (total == pcap) {
                         pcap = pcap ? 2 * pcap : 1024;
                         pairs = (pair_t *)realloc(pairs, sizeof(pair_t) * (size_t)pcap);

@@ -186,6 +186,7 @@ int check_params(const tsr_params* p) {
   if (!(p->t_min >= 0.f && p->t_min < 1.f)) return fail(TSR_EINVAL, "t_min must be in [0, 1)");
   if (!(p->r_min >= 0.f) || !(p->z_near == p->z_near)) return fail(TSR_EINVAL, "bad r_min / z_near");
   if (p->opacity_min != 0 && p->opacity_min != 1) return fail(TSR_EINVAL, "opacity_min must be 0 or 1");
+  if (p->tight_tiles != 0 && p->tight_tiles != 1) return fail(TSR_EINVAL, "tight_tiles must be 0 or 1");
   return TSR_OK;
 }
 

@@ -8,6 +8,10 @@
 #include "tsr_device.h"
 #include "tsr_internal.h"
 
+// The FP64 face setup decides integers (visibility, pixel rectangles, tight tile lists) that
+// must equal a plain IEEE evaluation of the same formulas: no fused multiply-adds unless written.
+#pragma clang fp contract(off)
+
 namespace tsr {
 
 // ---------------------------------------------------------------------------- face setup
@@ -91,11 +95,57 @@ __device__ __forceinline__ void face_normals(FaceSetup& f) {
   for (int k = 0; k < 3; ++k) {
     const int k1 = (k + 1) % 3;
     double ex = f.q[k1][0] - f.q[k][0], ey = f.q[k1][1] - f.q[k][1];
-    const double il = f.so / f.len[k];        // normals only feed the float record
-    f.n[k][0] = ey * il;
-    f.n[k][1] = -ex * il;
+    f.n[k][0] = f.so * ey / f.len[k];
+    f.n[k][1] = -f.so * ex / f.len[k];
   }
   f.zf = (f.vc[0][2] + f.vc[1][2] + f.vc[2][2]) / 3.0;   // exact division: it decides the depth order
+}
+
+// Edge lines L_k(p) = n_k . p + d_k of a face after face_normals (eq. 2, d_k = -n_k . q_k).
+struct EdgeLines {
+  double n[3][2], d[3];
+  int u0, u1, v0, v1;    // the face's pixel rectangle
+};
+
+__device__ __forceinline__ void edge_lines(const FaceSetup& f, EdgeLines& e) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    e.n[k][0] = f.n[k][0];
+    e.n[k][1] = f.n[k][1];
+    e.d[k] = -(f.n[k][0] * f.q[k][0] + f.n[k][1] * f.q[k][1]);
+  }
+  e.u0 = f.u0; e.u1 = f.u1; e.v0 = f.v0; e.v1 = f.v1;
+}
+
+// Tight triangle-tile test: can view-local tile (x, y) hold a pixel the face covers?  A
+// covered pixel has every L_k < 0, and an affine L_k is smallest over the tile's box of pixel
+// centres (clipped to the face's rectangle) at one corner: the tile is kept when that smallest
+// value is below 0 for all three edges.
+__device__ __forceinline__ bool tile_may_cover(const EdgeLines& e, int x, int y) {
+  const double ulo = fmax(16.0 * x, (double)e.u0), uhi = fmin(16.0 * x + 15.0, (double)e.u1);
+  const double vlo = fmax(16.0 * y, (double)e.v0), vhi = fmin(16.0 * y + 15.0, (double)e.v1);
+  bool keep = true;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double u = e.n[k][0] > 0 ? ulo : uhi, v = e.n[k][1] > 0 ? vlo : vhi;
+    const double lmin = e.n[k][0] * u + e.n[k][1] * v + e.d[k];
+    keep = keep && (lmin < 0);
+  }
+  return keep;
+}
+
+// The owner lane's edge lines, read by the other lanes of the wave.
+__device__ __forceinline__ void shfl_lines(const EdgeLines& e, int owner, EdgeLines& o) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    o.n[k][0] = __shfl(e.n[k][0], owner, 64);
+    o.n[k][1] = __shfl(e.n[k][1], owner, 64);
+    o.d[k] = __shfl(e.d[k], owner, 64);
+  }
+  o.u0 = __shfl(e.u0, owner, 64);
+  o.u1 = __shfl(e.u1, owner, 64);
+  o.v0 = __shfl(e.v0, owner, 64);
+  o.v1 = __shfl(e.v1, owner, 64);
 }
 
 // Vertex colours [channel][vertex] and opacities of a face (loaded before its setup so that
@@ -238,6 +288,42 @@ __device__ __forceinline__ void wave_expand(int cnt, F&& fn) {
   }
 }
 
+// wave_expand for item functions that return whether they kept their item: returns, on each
+// lane, how many of its own items were kept (a ballot per round, masked to the lane's items).
+template <class F>
+__device__ __forceinline__ int wave_expand_count(int cnt, F&& fn) {
+  const int lane = threadIdx.x & 63;
+  int incl = cnt;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    int y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  const int total = __shfl(incl, 63, 64);
+  int kept = 0;
+  for (int base = 0; base < total; base += 64) {
+    const int j = base + lane;
+    int lo = 0, hi = 63;
+#pragma unroll
+    for (int s = 0; s < 6; ++s) {
+      int mid = (lo + hi) >> 1;
+      int im = __shfl(incl, mid, 64);
+      if (im > j) hi = mid; else lo = mid + 1;
+    }
+    const int owner = lo;
+    const int excl_owner = __shfl(incl, owner, 64) - __shfl(cnt, owner, 64);
+    const bool k = fn(j < total, owner, j - excl_owner);
+    const unsigned long long b = __ballot(k && j < total);
+    // this lane's items in the round: positions [incl - cnt, incl) relative to base
+    const int a = max(incl - cnt - base, 0), e = min(incl - base, 64);
+    if (e > a) {
+      const unsigned long long hi_mask = e == 64 ? ~0ull : ((1ull << e) - 1ull);
+      kept += __popcll(b & hi_mask & ~((1ull << a) - 1ull));
+    }
+  }
+  return kept;
+}
+
 // ---------------------------------------------------------------------------- kernels
 
 // One thread per (view, face), numbered face-major (the views of a face in adjacent lanes);
@@ -245,6 +331,7 @@ __device__ __forceinline__ void wave_expand(int cnt, F&& fn) {
 // pre-test on every lane rejects faces that are certainly culled; the remaining candidates
 // of the workgroup are compacted onto the first lanes, which run the exact FP64 setup (the
 // visibility decision, the pixel rectangle and, for visible faces, the record).
+template <bool TIGHT>
 __global__ __launch_bounds__(256, 6) void k_project(tsr_scene_dev sc, const float* __restrict__ poses, ViewTable vt,
                                                  float z_near, float r_min, float sigma, uint32_t* __restrict__ counts,
                                                  float* __restrict__ records, uint32_t* __restrict__ tile_cnt,
@@ -288,6 +375,8 @@ __global__ __launch_bounds__(256, 6) void k_project(tsr_scene_dev sc, const floa
   // ---- exact setup of the candidates, one per lane (in thread order)
   int ntiles = 0, tx0 = 0, ty0 = 0, tw = 1, th = 1, tile_base = 0, tiles_x = 1;
   uint32_t zbits = 0u;
+  uint32_t keep = 0xfu;        // tight binning: which tiles of a face over at most kSmallTiles are listed
+  EdgeLines el{};              // tight binning: the face's edge lines (read by the larger faces' items)
   int64_t g = 0;
   if (threadIdx.x < ncand) {
     g = (int64_t)s_cand[threadIdx.x];
@@ -312,8 +401,21 @@ __global__ __launch_bounds__(256, 6) void k_project(tsr_scene_dev sc, const floa
       face_normals(f);
       write_record(at, f, records + g * kRecDwords);
       zbits = __float_as_uint((float)f.zf);     // the record's z_F (set by face_normals)
+      if constexpr (TIGHT) {
+        edge_lines(f, el);
+        if (ntiles <= kSmallTiles) {
+          keep = 0u;
+#pragma unroll
+          for (int i = 0; i < kSmallTiles; ++i)
+            if (i < ntiles && tile_may_cover(el, tx0 + i % tw, ty0 + i / tw)) keep |= 1u << i;
+        }
+      }
     }
-    counts[g] = (uint32_t)ntiles;
+    // listed tiles (larger faces under tight binning: corrected after their items are decided)
+    counts[g] = ntiles <= kSmallTiles ? (uint32_t)__popc(keep & ((1u << ntiles) - 1u)) : (uint32_t)ntiles;
+  }
+  if constexpr (TIGHT) {
+    if (ntiles > 0 && ntiles <= kSmallTiles && (keep & ((1u << ntiles) - 1u)) == 0u) ntiles = 0;   // no tile left
   }
   __syncthreads();                    // s_wave is reused below
   // ---- visible (view, face) pairs of this workgroup, compacted (still in thread order) into its
@@ -343,17 +445,32 @@ __global__ __launch_bounds__(256, 6) void k_project(tsr_scene_dev sc, const floa
     uint32_t sl[kSmallTiles];
 #pragma unroll
     for (int i = 0; i < kSmallTiles; ++i)
-      sl[i] = i < ntiles ? atomicAdd(&tile_cnt[kTileCntStride * (tile_base + (ty0 + i / tw) * tiles_x + tx0 + i % tw)], 1u)
-                         : 0u;
+      sl[i] = (i < ntiles && ((keep >> i) & 1u))
+                  ? atomicAdd(&tile_cnt[kTileCntStride * (tile_base + (ty0 + i / tw) * tiles_x + tx0 + i % tw)], 1u)
+                  : kSkipSlot;
     ent[1] = make_uint4(sl[0], sl[1], sl[2], sl[3]);
   }
   const int big = ntiles > kSmallTiles ? ntiles : 0;
   if (wave_max_int(big) == 0) return;
-  wave_expand(big, [&](bool valid, int owner, int i) {
-    const int otx0 = __shfl(tx0, owner, 64), oty0 = __shfl(ty0, owner, 64), otw = __shfl(tw, owner, 64);
-    const int obase = __shfl(tile_base, owner, 64), otx = __shfl(tiles_x, owner, 64);
-    if (valid) atomicAdd(&tile_cnt[kTileCntStride * (obase + (oty0 + i / otw) * otx + otx0 + i % otw) + 2], 1u);
-  });
+  if constexpr (!TIGHT) {
+    wave_expand(big, [&](bool valid, int owner, int i) {
+      const int otx0 = __shfl(tx0, owner, 64), oty0 = __shfl(ty0, owner, 64), otw = __shfl(tw, owner, 64);
+      const int obase = __shfl(tile_base, owner, 64), otx = __shfl(tiles_x, owner, 64);
+      if (valid) atomicAdd(&tile_cnt[kTileCntStride * (obase + (oty0 + i / otw) * otx + otx0 + i % otw) + 2], 1u);
+    });
+  } else {
+    const int kept = wave_expand_count(big, [&](bool valid, int owner, int i) {
+      const int otx0 = __shfl(tx0, owner, 64), oty0 = __shfl(ty0, owner, 64), otw = __shfl(tw, owner, 64);
+      const int obase = __shfl(tile_base, owner, 64), otx = __shfl(tiles_x, owner, 64);
+      EdgeLines oe;
+      shfl_lines(el, owner, oe);
+      const int x = otx0 + i % otw, y = oty0 + i / otw;
+      const bool k = valid && tile_may_cover(oe, x, y);
+      if (k) atomicAdd(&tile_cnt[kTileCntStride * (obase + y * otx + x) + 2], 1u);
+      return k;
+    });
+    if (big > 0) counts[g] = (uint32_t)kept;
+  }
 }
 
 // Two workgroups of 1024 threads, working independently: (0) exclusive scan of the
@@ -501,12 +618,16 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* __restrict__ tile
 // in thread order), each reading its 32-byte visible-list entry.  Small faces store at their
 // recorded slot; larger faces take positions from the per-tile cursors, spread over the
 // wave.  A position outside its tile's range (never expected) is not written and is reported
-// through tsr_check.
+// through tsr_check.  Under tight binning a small face's skipped tiles carry kSkipSlot, and the
+// larger faces repeat the projection's FP64 setup (the same code on the same inputs, so the same
+// tile decisions) to list only the tiles the projection counted.
+template <bool TIGHT>
 __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ranges,
                                               uint32_t* __restrict__ cursor, uint32_t* __restrict__ overflow,
                                               uint64_t* __restrict__ pairs, const uint32_t* __restrict__ vis_cnt,
                                               const uint32_t* __restrict__ vis_off, const VisEntry* __restrict__ vis_list,
-                                              uint32_t* __restrict__ vis_dense) {
+                                              uint32_t* __restrict__ vis_dense, tsr_scene_dev sc,
+                                              const float* __restrict__ poses, ViewTable vt, float z_near, float r_min) {
   const uint32_t nvis = vis_cnt[blockIdx.x];
   const bool mine = threadIdx.x < nvis;
   const uint4* ent = reinterpret_cast<const uint4*>(vis_list + (int64_t)blockIdx.x * kProjBlock + threadIdx.x);
@@ -529,7 +650,7 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ range
     bool bad = false;
 #pragma unroll
     for (int i = 0; i < kSmallTiles; ++i)
-      if (i < ntiles) {
+      if (i < ntiles && slv[i] != kSkipSlot) {
         const int t = tile0 + (i / tw) * tiles_x + i % tw;
         const uint32_t pos = ranges[2 * t] + slv[i];
         if (pos < ranges[2 * t + 1]) pairs[pos] = key;
@@ -540,10 +661,36 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ range
   const int big = ntiles > kSmallTiles ? ntiles : 0;
   if (wave_max_int(big) == 0) return;
   const uint32_t key_hi = (uint32_t)(key >> 32), key_lo = (uint32_t)key;
+  EdgeLines el{};
+  int ltx0 = 0, lty0 = 0;      // view-local tile of tile0
+  if constexpr (TIGHT) {
+    if (big > 0) {
+      const int64_t M = vt.n_faces;
+      const int v = (int)((int64_t)e0.x / M);
+      const int64_t m = (int64_t)e0.x - (int64_t)v * M;
+      double R[9], t[3];
+      load_pose(poses, v, R, t);
+      int64_t vid[3];
+      face_vertices(sc, m, vid);
+      FaceSetup f;
+      setup_face(sc, vid, R, t, vt.v[v], z_near, r_min, f);   // visible: it was listed by the projection
+      face_normals(f);
+      edge_lines(f, el);
+      ltx0 = f.u0 >> 4;
+      lty0 = f.v0 >> 4;
+    }
+  }
   wave_expand(big, [&](bool valid, int owner, int i) {
     const int ot0 = __shfl(tile0, owner, 64), otw = __shfl(tw, owner, 64), otx = __shfl(tiles_x, owner, 64);
     const uint32_t khi = __shfl(key_hi, owner, 64), klo = __shfl(key_lo, owner, 64);
-    if (valid) {
+    bool keep = true;
+    if constexpr (TIGHT) {
+      EdgeLines oe;
+      shfl_lines(el, owner, oe);
+      const int ox = __shfl(ltx0, owner, 64), oy = __shfl(lty0, owner, 64);
+      keep = valid && tile_may_cover(oe, ox + i % otw, oy + i / otw);
+    }
+    if (valid && keep) {
       const int t = ot0 + (i / otw) * otx + i % otw;
       const uint32_t pos = ranges[2 * t] + atomicAdd(&cursor[kTileCntStride * t + 2], 1u);
       if (pos < ranges[2 * t + 1]) pairs[pos] = ((uint64_t)khi << 32) | klo;
@@ -868,9 +1015,14 @@ hipError_t launch_bin(const tsr_scene_dev& sc, const float* poses, const ViewTab
   // the tile counters and the long-tile counter are contiguous: one fill
   const int64_t n_cnt = kTileCntStride * (int64_t)vt.n_tiles + 1;
   TSR_LAUNCH("fill_tiles", k_fill_u32, dim3(grid_for(n_cnt, 256)), dim3(256), 0, st, tile_cnt, n_cnt, 0u);
-  if (nf > 0)
-    TSR_LAUNCH("project", k_project, dim3(grid_for(nf, kProjBlock)), dim3(kProjBlock), 0, st, sc, poses, vt, p.z_near, p.r_min, p.sigma, counts,
-                       records, tile_cnt, vis_cnt, vis_list);
+  if (nf > 0) {
+    if (p.tight_tiles)
+      TSR_LAUNCH("project", k_project<true>, dim3(grid_for(nf, kProjBlock)), dim3(kProjBlock), 0, st, sc, poses, vt, p.z_near,
+                 p.r_min, p.sigma, counts, records, tile_cnt, vis_cnt, vis_list);
+    else
+      TSR_LAUNCH("project", k_project<false>, dim3(grid_for(nf, kProjBlock)), dim3(kProjBlock), 0, st, sc, poses, vt, p.z_near,
+                 p.r_min, p.sigma, counts, records, tile_cnt, vis_cnt, vis_list);
+  }
   uint32_t* vis_off = reinterpret_cast<uint32_t*>(ws + L.vis_off);
   uint32_t* vis_total = reinterpret_cast<uint32_t*>(ws + L.vis_total);
   uint32_t* vis_dense = reinterpret_cast<uint32_t*>(ws + L.vis_dense);
@@ -879,9 +1031,14 @@ hipError_t launch_bin(const tsr_scene_dev& sc, const float* poses, const ViewTab
                      sort ? L.capacity : (int64_t)0x7fffffffffffffffll, K, overflow, vis_cnt, vis_off, vis_total,
                      n_seg, long_cnt, long_list);
   if (!sort) return hipGetLastError();
-  if (nf > 0)
-    TSR_LAUNCH("emit", k_emit, dim3(grid_for(nf, kProjBlock)), dim3(kProjBlock), 0, st, ranges, tile_cnt,
-               overflow, pairs, vis_cnt, vis_off, vis_list, vis_dense);
+  if (nf > 0) {
+    if (p.tight_tiles)
+      TSR_LAUNCH("emit", k_emit<true>, dim3(grid_for(nf, kProjBlock)), dim3(kProjBlock), 0, st, ranges, tile_cnt,
+                 overflow, pairs, vis_cnt, vis_off, vis_list, vis_dense, sc, poses, vt, p.z_near, p.r_min);
+    else
+      TSR_LAUNCH("emit", k_emit<false>, dim3(grid_for(nf, kProjBlock)), dim3(kProjBlock), 0, st, ranges, tile_cnt,
+                 overflow, pairs, vis_cnt, vis_off, vis_list, vis_dense, sc, poses, vt, p.z_near, p.r_min);
+  }
   // small tile counts: the order is built beside the sorts (hidden behind them); larger ones by
   // the backward set-up, and only for schedules that use it
   int* order = vt.n_tiles <= kOrderInSortMax ? reinterpret_cast<int*>(ws + L.order) : nullptr;

@@ -840,7 +840,7 @@ __global__ __launch_bounds__(256) void k_vertex_gather(tsr_scene_dev sc, ViewTab
       if (counts[g] == 0) continue;
       any = true;
       if (sig_acc) gsig += sig_acc[g];
-      static_assert(kGradDwords == 20 && sizeof(acc_t) == 4, "a staged row is five 16-byte vectors");
+      static_assert(kGradDwords == 20 && sizeof(acc_t) >= 4, "a staged row starts with five 16-byte vectors");
       const float4* stage = reinterpret_cast<const float4*>(grad_acc + g * kGradDwords);
 #pragma unroll
       for (int q = 0; q < 5; ++q) {

@@ -67,6 +67,7 @@ constexpr int kRegSortMax = 1024;      // tile lists up to this length are sorte
 constexpr int kWaveSortMax = 512;      // ... by one wave (longer ones by a whole workgroup)
 constexpr int kSmallTiles = 4;         // faces overlapping at most this many tiles record their slots
 constexpr int kTileCntStride = 4;     // dwords per tile in the tile-counter array
+constexpr uint32_t kSkipSlot = 0xffffffffu;   // recorded slot of a tile the tight binning leaves out
 
 // What the emission of one visible (view, face) pair needs, written by the projection in the
 // order of its workgroup's threads: id g = v * M + m, the global id of the first tile of its

@@ -141,15 +141,22 @@ class GpuExecutor:
         for v in range(max(1, max_views), 0, -1):
             if v > 1 and v * px > max_pixels:
                 continue
-            # pair room for the batch at the estimated density, and for one view at four times it
-            # (a view close to a wall can list several times the average; pairs cost 16 B each)
-            cap = max(self._capacity([intr] * v), 4 * self._capacity([intr]))
-            ws = self._workspace_bytes([intr] * v, cap)
+            ws = self.slot_workspace_bytes(v)
             if n_slots * (ws + v * px * self.OUT_BYTES_PER_PIXEL) <= budget:
                 self.slot_bytes = ws
                 return n_slots * ws, v
         raise ValueError(f"a budget of {budget} B cannot hold {n_slots} slot workspaces of one "
                          f"{intr.width}x{intr.height} view each")
+
+    def slot_workspace_bytes(self, v: int) -> int:
+        """Workspace of a slot for batches of v views at max_resolution: pair room for the batch
+        at the estimated density, and for one view at four times it (a view close to a wall can
+        list several times the average; pairs cost 16 B each)."""
+        from .scenes import intrinsics_for
+
+        intr = intrinsics_for(*self.max_resolution)
+        cap = max(self._capacity([intr] * v), 4 * self._capacity([intr]))
+        return self._workspace_bytes([intr] * v, cap)
 
     def batch_fits(self, intrs) -> bool:
         return self._workspace_bytes(intrs, self._capacity(intrs)) <= self.slot_bytes

@@ -7,9 +7,10 @@ import torch
 from paper_2605_31419_amd import raster
 
 
-def make(scene, intrs, poses, sigma=1.0, t_min=1e-6, fit=True, opacity_min=False):
+def make(scene, intrs, poses, sigma=1.0, t_min=1e-6, fit=True, opacity_min=False, tight_tiles=False):
     sc = raster.DeviceScene.from_numpy(scene)
-    rast = raster.Rasterizer(sc, intrs, raster.Params(sigma=sigma, t_min=t_min, opacity_min=opacity_min))
+    rast = raster.Rasterizer(sc, intrs, raster.Params(sigma=sigma, t_min=t_min, opacity_min=opacity_min,
+                                                      tight_tiles=tight_tiles))
     p = raster.poses_tensor(poses)
     if fit:
         rast.fit(p)

@@ -40,15 +40,18 @@ def _make(sc, intrs, poses, sigma=1.0):
 
 def _oracle_views(sc, poses, intrs, gcs, gds, gts):
     """Oracle gradients summed over the views (pose gradients concatenated per view):
-    [pos, col, opa, pose, dL/dsigma]."""
-    acc = [0.0, 0.0, 0.0, 0.0]
+    [pos, col, opa, pose, dL/dsigma], and the conditioning of each element (sums of absolute
+    per-pixel terms; None for the pose)."""
+    acc = [0.0] * 4
+    cond = [0.0] * 4
     gposes = []
     for v in range(len(poses)):
-        gp, gc, go, gpose, gs = O.backward(sc, poses[v], intrs[v], gcs[v], gds[v], None if gts is None else gts[v],
-                                           want_sigma=True)
+        gp, gc, go, gpose, gs, ab = O.backward(sc, poses[v], intrs[v], gcs[v], gds[v],
+                                               None if gts is None else gts[v], want_sigma=True, with_abs=True)
         acc = [acc[0] + gp, acc[1] + gc, acc[2] + go, acc[3] + gs]
+        cond = [c + x for c, x in zip(cond, ab)]
         gposes.append(gpose)
-    return [acc[0], acc[1], acc[2], np.concatenate(gposes), acc[3]]
+    return [acc[0], acc[1], acc[2], np.concatenate(gposes), acc[3]], [cond[0], cond[1], cond[2], None, cond[3]]
 
 
 @pytest.mark.parametrize("name", ["single_64x48", "tiny_ragged_50x37", "multi_view_mixed", "long_tile_800",
@@ -73,7 +76,7 @@ def test_backward_with_face_sigma(name):
     sc, poses, intrs = _case(name, 0.4, 2.5)
     rast, p = _make(sc, intrs, poses)
     P = rast.total_pixels
-    g = np.random.default_rng(43)
+    g = np.random.default_rng(42)            # the upstream gradients of the global-exponent backward test
     gc = g.normal(size=3 * P).astype(np.float32)
     gd = g.normal(size=P).astype(np.float32)
     gt = g.normal(size=P).astype(np.float32)
@@ -87,9 +90,9 @@ def test_backward_with_face_sigma(name):
     torch.cuda.synchronize()
     got = [x.cpu().numpy().astype(np.float64) for x in out] + [rast.grad_face_sigma.cpu().numpy().astype(np.float64)]
     gcs, gds, gts = G.per_view(rast, gc, 3), G.per_view(rast, gd, 1), G.per_view(rast, gt, 1)
-    ref = _oracle_views(sc, poses, intrs, gcs, gds, gts)
-    for nm, a, b in zip(["grad_pos", "grad_col", "grad_opa", "grad_pose", "grad_face_sigma"], got, ref):
-        ok, msg, _ = grad_close(a, b, name=nm)
+    ref, conds = _oracle_views(sc, poses, intrs, gcs, gds, gts)
+    for nm, a, b, cond in zip(["grad_pos", "grad_col", "grad_opa", "grad_pose", "grad_face_sigma"], got, ref, conds):
+        ok, msg, _ = grad_close(a, b, name=nm, cond=cond)
         _say("  " + msg)
         assert ok, msg
 
@@ -112,9 +115,9 @@ def test_train_l1_with_face_sigma(name):
     torch.cuda.synchronize()
     np.testing.assert_allclose(loss.cpu().numpy(), lossref, rtol=1e-5)
     got = [x.cpu().numpy().astype(np.float64) for x in out] + [rast.grad_face_sigma.cpu().numpy().astype(np.float64)]
-    acc = _oracle_views(sc, poses, intrs, [s_[0] for s_ in gseeds], [s_[1] for s_ in gseeds], None)
-    for nm, a, b in zip(["grad_pos", "grad_col", "grad_opa", "grad_pose", "grad_face_sigma"], got, acc):
-        ok, msg, _ = grad_close(a, b, name=nm)
+    acc, conds = _oracle_views(sc, poses, intrs, [s_[0] for s_ in gseeds], [s_[1] for s_ in gseeds], None)
+    for nm, a, b, cond in zip(["grad_pos", "grad_col", "grad_opa", "grad_pose", "grad_face_sigma"], got, acc, conds):
+        ok, msg, _ = grad_close(a, b, name=nm, cond=cond)
         _say("  " + msg)
         assert ok, msg
 

@@ -38,10 +38,10 @@ def _workload(name):
     return _CACHE[name]
 
 
-def _bins_equal(rast, w):
+def _bins_equal(rast, w, tight=False):
     K, pairs, ranges, counts, overflow = G.binning_arrays(rast)
     assert overflow == 0
-    tile, zb, face, oranges = O.bin_pairs(w.scene, w.poses, w.intr)
+    tile, zb, face, oranges = O.bin_pairs(w.scene, w.poses, w.intr, tight_tiles=tight)
     assert K == len(tile), (K, len(tile))
     assert np.array_equal(ranges.astype(np.int64), oranges)
     gz = (pairs >> np.uint64(32)).astype(np.uint32)
@@ -81,6 +81,27 @@ def test_fullsize_bins_and_sampled_pixels(name):
         err = max(np.abs(cs[v][:, pix] - oc).max(), np.abs(ds[v][pix] - od).max(), np.abs(ts[v][pix] - ot).max())
         _say(f"  view {v}: {pix.size} pixels, max abs err {err:.3e}, covered {(ot < 1).sum()}")
         assert err <= 1e-4
+
+
+@pytest.mark.parametrize("name", ["track_640x480", "track_1200x680_1M", "window_8x1200x680"])
+def test_fullsize_tight_bins_and_images(name):
+    """Tight triangle-tile lists at full size: bit-exact against the oracle binner; the whole
+    frame's images bitwise equal to those of the bounding-box lists."""
+    _say(f"[fullsize tight] case={name}")
+    w = _workload(name)
+    loose, p = G.make(w.scene, w.intr, w.poses)
+    loose.bin_and_sort(p)
+    K0, _ = _bins_equal(loose, w)
+    ref = [x.cpu().numpy() for x in loose.forward(p)]
+    del loose
+    rast, p = G.make(w.scene, w.intr, w.poses, tight_tiles=True)
+    rast.bin_and_sort(p)
+    K, counts = _bins_equal(rast, w, tight=True)
+    _say(f"  K = {K} of {K0} bounding-box pairs ({100.0 * (1 - K / max(K0, 1)):.1f} % fewer)")
+    got = [x.cpu().numpy() for x in rast.forward(p)]
+    torch.cuda.synchronize()
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
 
 
 def _rect_pixels(rect, m, W):

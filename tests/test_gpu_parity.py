@@ -24,15 +24,15 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def _oracle_bins(scene, poses, intrs, sigma=1.0):
-    tile, zb, face, ranges = O.bin_pairs(scene, poses, intrs, sigma=sigma)
+def _oracle_bins(scene, poses, intrs, sigma=1.0, tight=False):
+    tile, zb, face, ranges = O.bin_pairs(scene, poses, intrs, sigma=sigma, tight_tiles=tight)
     return tile, zb, face, ranges
 
 
-def _assert_bins_equal(rast, scene, poses, intrs):
+def _assert_bins_equal(rast, scene, poses, intrs, tight=False):
     K, pairs, ranges, counts, overflow = G.binning_arrays(rast)
     assert overflow == 0
-    tile, zb, face, oranges = _oracle_bins(scene, poses, intrs)
+    tile, zb, face, oranges = _oracle_bins(scene, poses, intrs, tight=tight)
     assert K == len(tile), (K, len(tile))
     assert np.array_equal(ranges.astype(np.int64), oranges), "tile ranges differ"
     got_z = (pairs >> np.uint64(32)).astype(np.uint32)
@@ -199,6 +199,47 @@ def test_binning_bit_exact(name):
     rast.bin_and_sort(p)
     K = _assert_bins_equal(rast, sc, poses, intrs)
     _say(f"  K = {K}")
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_tight_binning_bit_exact(name):
+    """Tight triangle-tile lists against the oracle binner with the same FP64 rule."""
+    _say(f"[tight binning] case={name}")
+    sc, poses, intrs = _case(name)
+    rast, p = G.make(sc, intrs, poses, tight_tiles=True)
+    rast.bin_and_sort(p)
+    K = _assert_bins_equal(rast, sc, poses, intrs, tight=True)
+    K_loose = len(_oracle_bins(sc, poses, intrs)[0])
+    _say(f"  K = {K} (bounding-box lists: {K_loose})")
+    assert K <= K_loose
+
+
+@pytest.mark.parametrize("name", ["single_64x48", "huge_faces_640x480", "multi_view_mixed", "long_tile_800",
+                                  "culling_boundaries_1200x680", "max_views_32"])
+def test_tight_binning_leaves_images_and_gradients_unchanged(name):
+    """The pairs tight binning drops have alpha = 0 at every pixel of their tile, so the
+    forward images are bitwise those of the bounding-box lists and the gradients equal up to
+    the order of the floating-point atomics; the fused step's loss likewise."""
+    sc, poses, intrs = _case(name)
+    outs = []
+    for tight in (False, True):
+        rast, p = G.make(sc, intrs, poses, tight_tiles=tight)
+        P = rast.total_pixels
+        g = np.random.default_rng(5)
+        gc, gd = G.to_dev(g.normal(size=3 * P)), G.to_dev(g.normal(size=P))
+        tc, td = G.to_dev(g.uniform(0, 1, 3 * P)), G.to_dev(g.uniform(0.5, 4, P))
+        rast.bin_and_sort(p)
+        img = [x.cpu().numpy() for x in rast.forward(p)]
+        grads = [x.cpu().numpy() for x in rast.backward(p, gc, gd, None)]
+        loss = torch.zeros(len(poses), device="cuda")
+        fused = [x.cpu().numpy() for x in rast.train_l1(p, tc, td, loss=loss)]
+        torch.cuda.synchronize()
+        outs.append((img, grads, fused, loss.cpu().numpy()))
+    for a, b in zip(outs[0][0], outs[1][0]):
+        assert np.array_equal(a, b)
+    for a, b in zip(outs[0][1] + outs[0][2], outs[1][1] + outs[1][2]):
+        np.testing.assert_allclose(b, a, rtol=1e-5, atol=1e-6 * max(np.abs(a).max(), 1e-30))
+    np.testing.assert_allclose(outs[1][3], outs[0][3], rtol=1e-6)
 
 
 def test_empty_scene_bins_nothing():

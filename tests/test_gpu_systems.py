@@ -452,7 +452,7 @@ def test_serving_under_a_tight_memory_budget():
     ex = GpuExecutor(dev)
     intr = S.intrinsics_for(1200, 680)
     out1 = ex.OUT_BYTES_PER_PIXEL * intr.width * intr.height
-    ws1 = ex._workspace_bytes([intr], ex._capacity([intr]))
+    ws1 = ex.slot_workspace_bytes(1)
     budget = 2 * (ws1 + out1) + out1
     torch.cuda.synchronize()
     base = torch.cuda.memory_allocated()

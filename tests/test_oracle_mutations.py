@@ -12,6 +12,8 @@ from oracle import oracle as O
 from tests import test_oracle_face_sigma as FSIG
 from tests import test_oracle_fd as FD
 from tests import test_oracle_pins as PINS
+from tests import test_oracle_perspective as PERSP
+from tests import test_oracle_tight_bins as TIGHT
 
 SRC = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle", "tsr_oracle.c")
 
@@ -45,6 +47,15 @@ MUTATIONS = {
                         "double gs = galpha * f->of * e->I * log2(e->rho);"),
     "sigma_grad_no_opacity": ("double gs = galpha * f->of * e->I * log(e->rho);",
                               "double gs = galpha * e->I * log(e->rho);"),
+    "tight_tiles_far_corner": ("double u = f->n[k][0] > 0 ? ulo : uhi, v = f->n[k][1] > 0 ? vlo : vhi;",
+                               "double u = f->n[k][0] > 0 ? uhi : ulo, v = f->n[k][1] > 0 ? vhi : vlo;"),
+    "persp_weight_times_depth": ("for (int i = 0; i < 3; i++) { w[i] = lam[i] / f->vc[i][2]; W += w[i]; }",
+                                 "for (int i = 0; i < 3; i++) { w[i] = lam[i] * f->vc[i][2]; W += w[i]; }"),
+    "persp_depth_not_inverted": ("e->zf = 1.0 / W;", "e->zf = W;"),
+    "persp_dual_depth_constant": ("w[i] = dn_div(lam[i], dn_var(f->vc[i][2], 3 * i + 2));",
+                                  "w[i] = dn_div(lam[i], dn_const(f->vc[i][2]));"),
+    "tight_tiles_box_unclipped": ("double ulo = fmax(16.0 * x, r[0]), uhi = fmin(16.0 * x + 15.0, r[1]);",
+                                  "double ulo = 16.0 * x, uhi = 16.0 * x + 15.0;"),
 }
 
 
@@ -67,7 +78,10 @@ def _pin_checks():
         out.append(lambda sigma=sigma, seed=seed: FD.test_gradients_match_finite_differences(sigma, seed))
     out += [lambda: FSIG.test_golden_right_triangle_with_its_own_exponent(0.7),
             FSIG.test_two_faces_use_their_own_exponents,
-            lambda: FSIG.test_gradients_under_face_sigma_match_finite_differences(41)]
+            lambda: FSIG.test_gradients_under_face_sigma_match_finite_differences(41),
+            TIGHT.test_right_triangle_closed_form, TIGHT.test_box_is_clipped_to_the_pixel_rectangle, lambda: TIGHT.test_between_exact_and_bounding_box(1),
+            TIGHT.test_thin_slanted_faces_drop_pairs,
+            PERSP.test_ray_meets_the_face_plane, lambda: PERSP.test_gradients_match_finite_differences(11)]
     return out
 
 
