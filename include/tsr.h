@@ -103,6 +103,13 @@ typedef struct {
                             that can hold a pixel the face covers.  Images and gradients are the
                             same either way (the dropped pairs have alpha = 0 at every pixel of
                             their tile); the lists are shorter.  Decided in FP64. */
+    int32_t perspective; /* 0: colour interpolated with the affine screen-space barycentrics of
+                            the projected triangle and depth D = sum z_F alpha T (Sec. 3.1 and
+                            eq. 4 as read); 1: perspective-correct barycentrics
+                            mu_i = (lambda_i / z_i) / sum_j (lambda_j / z_j) for the colour and the
+                            depth of the face's plane along the pixel's ray, 1 / sum_j (lambda_j /
+                            z_j), in D (the variant); the depth order stays that of z_F.  Cannot be
+                            combined with scene->face_sigma (TSR_EINVAL). */
 } tsr_params;
 
 /* Scene (host struct of device pointers). */

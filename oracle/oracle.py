@@ -61,6 +61,7 @@ def lib():
         _lib.orc_state.argtypes = [P, P, P, P, P, C.c_int64, C.c_double, P]
         _lib.orc_face_stats.argtypes = [P, P, P, P, C.c_double, P, P, P, P, P]
         _lib.orc_min_rho.argtypes = [P, P, P, P, P, C.c_int64, P]
+        _lib.orc_ridge_gap.argtypes = [P, P, P, P, P, C.c_int64, P]
     return _lib
 
 
@@ -258,6 +259,20 @@ def min_rho(scene, pose, intr, sigma=1.0, z_near=0.1, r_min=1e-3, pixels=None, o
     rc = lib().orc_min_rho(C.byref(a.sc), _ptr(a.pose), C.byref(a.cam), C.byref(a.par), _ptr(pix), n, _ptr(out))
     if rc:
         raise ValueError(f"orc_min_rho failed ({rc})")
+    return out
+
+
+def ridge_gap(scene, pose, intr, sigma=1.0, z_near=0.1, r_min=1e-3, pixels=None, opacity_min=False):
+    """Per pixel, the smallest gap (in rho units) between the two smallest normalised edge
+    distances of the faces blended there (+inf where none): near 0 on a ridge of phi, where
+    the edge that attains the minimum flips under rounding."""
+    a = _Args(scene, pose, intr, sigma, z_near, r_min, opacity_min)
+    pix = None if pixels is None else np.ascontiguousarray(pixels, dtype=np.int64)
+    n = a.cam.width * a.cam.height if pix is None else pix.shape[0]
+    out = np.zeros(n)
+    rc = lib().orc_ridge_gap(C.byref(a.sc), _ptr(a.pose), C.byref(a.cam), C.byref(a.par), _ptr(pix), n, _ptr(out))
+    if rc:
+        raise ValueError(f"orc_ridge_gap failed ({rc})")
     return out
 
 

@@ -738,6 +738,40 @@ int orc_min_rho(const orc_scene *s, const double *pose, const orc_cam *c, const 
     return ORC_OK;
 }
 
+/* Smallest ridge gap over the faces blended at each listed pixel: for a face, the distance in
+ * rho units between its two smallest normalised edge distances E_k = -L_k / r (eq. 3 takes the
+ * smallest), +infinity where no face is blended.  Where the gap is tiny the pixel lies on a
+ * ridge of phi (an angle bisector from the incentre), where which edge attains the minimum --
+ * and so which edge's parameters receive the window gradient -- flips under rounding; tests
+ * exclude such pixels on both sides like the other discrete-state flips. */
+int orc_ridge_gap(const orc_scene *s, const double *pose, const orc_cam *c, const orc_par *p,
+                  const int64_t *pix, int64_t npix, double *gap) {
+    int rc = check_args(s, pose, c, p);
+    if (rc) return rc;
+    face_t *F = (face_t *)calloc((size_t)(s->n_faces ? s->n_faces : 1), sizeof(face_t));
+    setup_all(s, pose, c, p, F);
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < npix; k++) {
+        int64_t id = pix ? pix[k] : k;
+        int u = (int)(id % c->width), v = (int)(id / c->width);
+        hit_t *h;
+        int64_t n = pixel_hits(s, F, u, v, &h);
+        double best = INFINITY;
+        for (int64_t j = 0; j < n; j++) {
+            const face_t *f = &F[h[j].m];
+            double E[3];
+            for (int e = 0; e < 3; e++) E[e] = -(f->n[e][0] * u + f->n[e][1] * v + f->d[e]) / f->r;
+            double lo = fmin(E[0], fmin(E[1], E[2]));
+            double mid = E[0] + E[1] + E[2] - lo - fmax(E[0], fmax(E[1], E[2]));
+            if (mid - lo < best) best = mid - lo;
+        }
+        free(h);
+        gap[k] = best;
+    }
+    free(F);
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------------------------- per-face screen statistics */
 /* Map-management statistics of one view (Sec. 3.4: pruning by projected area, densification by
  * pixel coverage, keyframing by visibility), with the blending decisions of eq. 4 and the early

@@ -36,7 +36,7 @@ class TsrIntrinsics(C.Structure):
 class TsrParams(C.Structure):
     _fields_ = [("sigma", C.c_float), ("t_min", C.c_float), ("z_near", C.c_float), ("r_min", C.c_float),
                 ("w_color", C.c_float), ("w_depth", C.c_float), ("opacity_min", C.c_int32),
-                ("tight_tiles", C.c_int32)]
+                ("tight_tiles", C.c_int32), ("perspective", C.c_int32)]
 
 
 class TsrScene(C.Structure):

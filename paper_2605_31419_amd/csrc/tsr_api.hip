@@ -147,6 +147,7 @@ WsLayout layout(const ViewTable& vt, int64_t cap) {
   L.records = o; o = align_up(o + sizeof(float) * tsr::kRecDwords * nf);
   L.grad_acc = o; o = align_up(o + sizeof(tsr::acc_t) * tsr::kGradDwords * nf);
   L.sig_acc = o; o = align_up(o + sizeof(float) * nf);
+  L.persp_acc = o; o = align_up(o + sizeof(float) * 2 * nf);
   const int64_t nb = (nf + tsr::kProjBlock - 1) / tsr::kProjBlock;
   L.tile_cnt = o;
   L.long_cnt = o + sizeof(uint32_t) * tsr::kTileCntStride * vt.n_tiles;
@@ -187,6 +188,7 @@ int check_params(const tsr_params* p) {
   if (!(p->r_min >= 0.f) || !(p->z_near == p->z_near)) return fail(TSR_EINVAL, "bad r_min / z_near");
   if (p->opacity_min != 0 && p->opacity_min != 1) return fail(TSR_EINVAL, "opacity_min must be 0 or 1");
   if (p->tight_tiles != 0 && p->tight_tiles != 1) return fail(TSR_EINVAL, "tight_tiles must be 0 or 1");
+  if (p->perspective != 0 && p->perspective != 1) return fail(TSR_EINVAL, "perspective must be 0 or 1");
   return TSR_OK;
 }
 
@@ -223,6 +225,8 @@ int prepare(const tsr_scene* sc, const float* poses, const tsr_intrinsics* intr,
   int rc;
   if ((rc = check_scene(sc))) return rc;
   if ((rc = check_params(p))) return rc;
+  if (p->perspective && sc->face_sigma)
+    return fail(TSR_EINVAL, "perspective-correct interpolation cannot be combined with per-face exponents");
   if (!poses) return fail(TSR_EINVAL, "poses is NULL");
   if (!ws) return fail(TSR_EINVAL, "workspace is NULL");
   if ((rc = build_views(sc, intr, n_views, vt))) return rc;

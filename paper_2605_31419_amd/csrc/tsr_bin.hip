@@ -155,12 +155,14 @@ struct FaceAttr {
   float opa[3];
   int opa_min;     // face opacity = min of the vertex opacities instead of their mean
   float sigma;     // window exponent of the face (eq. 3)
+  int persp;       // perspective-correct interpolation: numerator and denominator planes
 };
 
 __device__ __forceinline__ void load_attr(const tsr_scene_dev& sc, int64_t m, const int64_t vid[3], float sigma,
-                                          FaceAttr& a) {
+                                          int persp, FaceAttr& a) {
   const int64_t N = sc.n_vertices;
   a.sigma = sc.face_sigma ? sc.face_sigma[m] : sigma;
+  a.persp = persp;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
 #pragma unroll
@@ -185,13 +187,17 @@ __device__ __forceinline__ void write_record(const FaceAttr& at, const FaceSetup
     rec[kRecEdge + 3 * k + 2] = (float)c[k];
   }
   const double inv_perim = 1.0 / f.perim;
+  // lambda_opp(k) = E_k len_k / perimeter; opp(k) = (k + 2) % 3 is the vertex facing edge k.
+  // Perspective-correct mode weights each vertex by 1 / z (its camera depth).
+  double wz[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) wz[k] = at.persp ? 1.0 / f.vc[(k + 2) % 3][2] : 1.0;
 #pragma unroll
   for (int ch = 0; ch < 3; ++ch) {
-    // lambda_opp(k) = E_k len_k / perimeter; opp(k) = (k + 2) % 3 is the vertex facing edge k
     double P = 0, Q = 0, Rr = 0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      double beta = f.len[k] * (double)at.col[ch][(k + 2) % 3] * inv_perim;
+      double beta = f.len[k] * (double)at.col[ch][(k + 2) % 3] * inv_perim * wz[k];
       P += beta * a[k];
       Q += beta * b[k];
       Rr += beta * c[k];
@@ -207,6 +213,20 @@ __device__ __forceinline__ void write_record(const FaceAttr& at, const FaceSetup
   rec[kRecV0] = (float)f.v0;
   rec[kRecU1V1] = __int_as_float(f.u1 | (f.v1 << 16));    // both below 2^14
   rec[kRecSigma] = at.sigma;
+  if (at.persp) {
+    // denominator plane W = sum_k lambda_opp(k) / z_opp(k) (1 / depth of the face's plane)
+    double Wa = 0, Wb = 0, Wc = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double beta = f.len[k] * inv_perim * wz[k];
+      Wa += beta * a[k];
+      Wb += beta * b[k];
+      Wc += beta * c[k];
+    }
+    rec[kRecWa] = (float)Wa;
+    rec[kRecWb] = (float)Wb;
+    rec[kRecWc] = (float)Wc;
+  }
   float4* dst = reinterpret_cast<float4*>(dst_rec);
 #pragma unroll
   for (int i = 0; i < kRecDwords / 4; ++i) dst[i] = make_float4(rec[4 * i], rec[4 * i + 1], rec[4 * i + 2], rec[4 * i + 3]);
@@ -333,7 +353,8 @@ __device__ __forceinline__ int wave_expand_count(int cnt, F&& fn) {
 // visibility decision, the pixel rectangle and, for visible faces, the record).
 template <bool TIGHT>
 __global__ __launch_bounds__(256, 6) void k_project(tsr_scene_dev sc, const float* __restrict__ poses, ViewTable vt,
-                                                 float z_near, float r_min, float sigma, uint32_t* __restrict__ counts,
+                                                 float z_near, float r_min, float sigma, int persp,
+                                                 uint32_t* __restrict__ counts,
                                                  float* __restrict__ records, uint32_t* __restrict__ tile_cnt,
                                                  uint32_t* __restrict__ vis_cnt, VisEntry* __restrict__ vis_list) {
   __shared__ uint32_t s_wave[4];
@@ -388,7 +409,7 @@ __global__ __launch_bounds__(256, 6) void k_project(tsr_scene_dev sc, const floa
     const int64_t m = g - (int64_t)v * M;
     face_vertices(sc, m, vid);
     FaceAttr at;
-    load_attr(sc, m, vid, sigma, at);
+    load_attr(sc, m, vid, sigma, persp, at);
     FaceSetup f;
     if (setup_face(sc, vid, R, t, vd, z_near, r_min, f)) {
       tx0 = f.u0 >> 4;
@@ -1018,10 +1039,10 @@ hipError_t launch_bin(const tsr_scene_dev& sc, const float* poses, const ViewTab
   if (nf > 0) {
     if (p.tight_tiles)
       TSR_LAUNCH("project", k_project<true>, dim3(grid_for(nf, kProjBlock)), dim3(kProjBlock), 0, st, sc, poses, vt, p.z_near,
-                 p.r_min, p.sigma, counts, records, tile_cnt, vis_cnt, vis_list);
+                 p.r_min, p.sigma, p.perspective, counts, records, tile_cnt, vis_cnt, vis_list);
     else
       TSR_LAUNCH("project", k_project<false>, dim3(grid_for(nf, kProjBlock)), dim3(kProjBlock), 0, st, sc, poses, vt, p.z_near,
-                 p.r_min, p.sigma, counts, records, tile_cnt, vis_cnt, vis_list);
+                 p.r_min, p.sigma, p.perspective, counts, records, tile_cnt, vis_cnt, vis_list);
   }
   uint32_t* vis_off = reinterpret_cast<uint32_t*>(ws + L.vis_off);
   uint32_t* vis_total = reinterpret_cast<uint32_t*>(ws + L.vis_total);

@@ -39,25 +39,32 @@ __device__ __forceinline__ int tile_of_block_ordered(int n_tiles, const int* __r
   return (t >= 0 && t < n_tiles) ? t : -1;
 }
 
-// Window value for rho in (0, 1): I = rho^sigma (eq. 3).  Mode 1: sigma = 1, 2: sigma = 0.5,
-// 3: sigma = 2, 0: any sigma, 4: each face's own sigma (passed in from its record).
+// Kernel modes: the low three bits select the window exponent -- 1: sigma = 1, 2: sigma = 0.5,
+// 3: sigma = 2, 0: any sigma, 4: each face's own sigma (from its record) -- and bit 3 the
+// perspective-correct interpolation (numerator and denominator planes in the record).
+template <int SM> constexpr int exp_mode() { return SM & 7; }
+template <int SM> constexpr bool persp_mode() { return (SM & 8) != 0; }
+
+// Window value for rho in (0, 1): I = rho^sigma (eq. 3).
 template <int SM>
 __device__ __forceinline__ float window_pow(float rho, float sigma) {
-  if constexpr (SM == 1) return rho;
-  else if constexpr (SM == 2) return __builtin_sqrtf(rho);
-  else if constexpr (SM == 3) return rho * rho;
+  if constexpr (exp_mode<SM>() == 1) return rho;
+  else if constexpr (exp_mode<SM>() == 2) return __builtin_sqrtf(rho);
+  else if constexpr (exp_mode<SM>() == 3) return rho * rho;
   else return exp2f(sigma * log2f(rho));
 }
 
 // The exponent a face is evaluated with: its record's in mode 4, else the launch's.
 template <int SM>
 __device__ __forceinline__ float face_sigma(const float* r, float sigma) {
-  if constexpr (SM == 4) return r[kRecSigma];
+  if constexpr (exp_mode<SM>() == 4) return r[kRecSigma];
   else return sigma;
 }
 
 struct PixelEval {
   float rho, I, alpha, c0, c1, c2;
+  float zp;        // depth blended into D: z_F, or 1 / W (perspective-correct; then also 1 / W
+                   // of the colour's numerators), 0 where the face does not cover the pixel
   bool k0, k1;     // the edge attaining the minimum of E_k is edge 0 / edge 1 (lowest index on
                    // ties; edge 2 when neither)
 };
@@ -99,6 +106,18 @@ __device__ __forceinline__ bool eval_face(const Rec& rc, float dx, float dy, flo
   e.c0 = fmaf(r[kRecCol + 0], dx, fmaf(r[kRecCol + 1], dy, r[kRecCol + 2]));
   e.c1 = fmaf(r[kRecCol + 3], dx, fmaf(r[kRecCol + 4], dy, r[kRecCol + 5]));
   e.c2 = fmaf(r[kRecCol + 6], dx, fmaf(r[kRecCol + 7], dy, r[kRecCol + 8]));
+  if constexpr (persp_mode<SM>()) {
+    // colour = numerator planes / W and depth = 1 / W (W > 0 where the face covers the pixel;
+    // elsewhere the weight is 0 and so is 1 / W here)
+    const float W = fmaf(r[kRecWa], dx, fmaf(r[kRecWb], dy, r[kRecWc]));
+    const float iW = cov ? __builtin_amdgcn_rcpf(W) : 0.f;
+    e.c0 *= iW;
+    e.c1 *= iW;
+    e.c2 *= iW;
+    e.zp = iW;
+  } else {
+    e.zp = r[kRecZ];
+  }
   return cov;
 }
 
@@ -183,9 +202,31 @@ __device__ __forceinline__ void stage_batch(const float* __restrict__ records, c
 // corners, and a face with that maximum below -margin has rho <= 0 (no blend, zero gradient)
 // at every pixel the walks would evaluate, so skipping it changes nothing.  The margin (1e-6 of
 // the magnitude of the terms) exceeds the FP32 rounding of both evaluations.
+// Perspective-correct records do not hold the rectangle's end: the edge test then runs over
+// the whole quadrant (still conservative).
+template <int SM>
 __device__ __forceinline__ unsigned long long batch_hit_mask(const float4* srec, int n, int bx, int by) {
   const int j = threadIdx.x & 63;
   bool hit = false;
+  if constexpr (persp_mode<SM>()) {
+    if (j < n) {
+      const float4 rc = srec[j * 6 + kRecU0 / 4];
+      const float* r = reinterpret_cast<const float*>(&srec[j * 6]);
+      const float dxl = (float)bx - rc.x, dxh = (float)(bx + 7) - rc.x;
+      const float dyl = (float)by - rc.y, dyh = (float)(by + 7) - rc.y;
+      const float mx = fmaxf(fabsf(dxl), fabsf(dxh)), my = fmaxf(fabsf(dyl), fabsf(dyh));
+      hit = true;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float a = r[kRecEdge + 3 * k], b = r[kRecEdge + 3 * k + 1], c = r[kRecEdge + 3 * k + 2];
+        const float dx = a > 0.f ? dxh : dxl, dy = b > 0.f ? dyh : dyl;
+        const float emax = fmaf(a, dx, fmaf(b, dy, c));
+        const float margin = 1e-6f * (fabsf(a) * mx + fabsf(b) * my + fabsf(c)) + 1e-30f;
+        hit = hit && !(emax < -margin);
+      }
+    }
+    return ballot(hit);
+  }
   if (j < n) {
     const float4 rc = srec[j * 6 + kRecU0 / 4];
     const int u1v1 = __float_as_int(rc.z);
@@ -245,7 +286,7 @@ __device__ __forceinline__ void forward_walk(const TileCtx& c, const float* __re
     const int n = min(kBatch, ns - h);
     const uint32_t b0 = s0 + (uint32_t)h;
     const float4* sr = srec + h * 6;
-    unsigned long long mask = batch_hit_mask(sr, n, c.bx, c.by);
+    unsigned long long mask = batch_hit_mask<SM>(sr, n, c.bx, c.by);
     while (mask) {
       const int j = __builtin_ctzll(mask);
       mask &= mask - 1;
@@ -262,7 +303,7 @@ __device__ __forceinline__ void forward_walk(const TileCtx& c, const float* __re
       s.C0 = fmaf(e.c0, w, s.C0);
       s.C1 = fmaf(e.c1, w, s.C1);
       s.C2 = fmaf(e.c2, w, s.C2);
-      s.D = fmaf(rc.f[kRecZ], w, s.D);
+      s.D = fmaf(e.zp, w, s.D);
       s.Tb = act ? s.T : s.Tb;
       s.last = act ? (int)(b0 + j) : s.last;
       s.T = s.T * (1.f - a);
@@ -288,7 +329,8 @@ template <int SM, bool COOP>
 __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __restrict__ records,
                                               const uint64_t* __restrict__ pairs, float sigma, int last, float Tb,
                                               const PixGrad& pg, float4* srec, uint32_t* sface, int* sint,
-                                              acc_t* __restrict__ grad_acc, float* __restrict__ sig_acc) {
+                                              acc_t* __restrict__ grad_acc, float* __restrict__ sig_acc,
+                                              float* __restrict__ persp_acc) {
   const int lane = threadIdx.x & 63;
   // highest list position any pixel of this wave (COOP: of the workgroup) blended
   const int wlast = uniform_int(wave_max_int(last));
@@ -321,7 +363,7 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
     if (b0 > wlast) continue;
     const float4* sr = srec + h * 6;
     const uint32_t* sf = sface + h;
-    unsigned long long mask = batch_hit_mask(sr, n, c.bx, c.by);
+    unsigned long long mask = batch_hit_mask<SM>(sr, n, c.bx, c.by);
     if (wlast - b0 < 63) mask &= (2ull << (wlast - b0)) - 1ull;     // faces after the wave's last
     while (mask) {
       const int j = 63 - __builtin_clzll(mask);
@@ -343,16 +385,28 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
       // T before this face: the stored value at the last face, else T_after / (1 - alpha)
       const float Tj = (idx == last) ? Tb : Tcur * __builtin_amdgcn_rcpf(om);
       Tcur = act ? Tj : Tcur;
-      const float zf = r[kRecZ];
+      const float zf = e.zp;
       const float c0 = e.c0, c1 = e.c1, c2 = e.c2;
       const float w = alpha * Tj;
       float acc[kGradDwords];
       // colour plane gradients: dL/dc_ch(p) = gC_ch alpha T, and c_ch = P dx + Q dy + R
-      const float gc0 = pg.g0 * w, gc1 = pg.g1 * w, gc2 = pg.g2 * w;
+      float gc0 = pg.g0 * w, gc1 = pg.g1 * w, gc2 = pg.g2 * w;
+      float gwa = 0.f, gwb = 0.f;          // perspective-correct: the W plane's slopes
+      if constexpr (persp_mode<SM>()) {
+        // c_ch = N_ch / W, depth = 1 / W: dL/dN_ch = gC_ch w / W, dL/dW = -(gC.c + gD depth) w / W
+        const float gW = -(fmaf(pg.g0, c0, fmaf(pg.g1, c1, fmaf(pg.g2, c2, pg.gd * zf)))) * w * zf;
+        gc0 *= zf;
+        gc1 *= zf;
+        gc2 *= zf;
+        acc[kGWc] = gW;
+        gwa = gW * dx;
+        gwb = gW * dy;
+      } else {
+        acc[kGZ] = pg.gd * w;
+      }
       acc[kGCol + 0] = gc0 * dx; acc[kGCol + 1] = gc0 * dy; acc[kGCol + 2] = gc0;
       acc[kGCol + 3] = gc1 * dx; acc[kGCol + 4] = gc1 * dy; acc[kGCol + 5] = gc1;
       acc[kGCol + 6] = gc2 * dx; acc[kGCol + 7] = gc2 * dy; acc[kGCol + 8] = gc2;
-      acc[kGZ] = pg.gd * w;
       // dL/dalpha = T (gC.(c - B) + gD (z - BD) - gT (1 - BA)) = T (P - S); finite on every
       // lane, and only used scaled by I or masked by act
       const float P = fmaf(pg.g0, c0, fmaf(pg.g1, c1, fmaf(pg.g2, c2, fmaf(pg.gd, zf, -pg.gt))));
@@ -360,7 +414,7 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
       acc[kGOpa] = galpha * I;
       const float gI = galpha * r[kRecOpa];
       float grho = 0.f;
-      if constexpr (SM == 1) grho = (act && e.rho < 1.f) ? gI : 0.f;
+      if constexpr (exp_mode<SM>() == 1) grho = (act && e.rho < 1.f) ? gI : 0.f;
       else grho = (act && e.rho < 1.f) ? gI * face_sigma<SM>(r, sigma) * I * __builtin_amdgcn_rcpf(e.rho) : 0.f;   // sigma I / rho
       // only the edge attaining the minimum receives the window gradient
       const float gk[3] = {e.k0 ? grho : 0.f, e.k1 ? grho : 0.f, (e.k0 || e.k1) ? 0.f : grho};
@@ -374,11 +428,18 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
       if (ballot(act) == 0) continue;
       const float tot = wave_sum20(acc);
       if (k_out >= 0) unsafeAtomicAdd(&grad_acc[(size_t)sf[j] * kGradDwords + k_out], (acc_t)tot);
-      if constexpr (SM == 4) {
+      if constexpr (exp_mode<SM>() == 4) {
         // the face's own exponent: dI/dsigma = I ln(rho) for 0 < rho < 1 (act implies rho > 0)
         const float gsig = (act && e.rho < 1.f) ? gI * I * (0.69314718055994531f * log2f(e.rho)) : 0.f;
         const float ts = wave_sum(gsig);
         if (lane == 0) unsafeAtomicAdd(&sig_acc[sf[j]], ts);
+      }
+      if constexpr (persp_mode<SM>()) {
+        const float ta = wave_sum(gwa), tb = wave_sum(gwb);
+        if (lane == 0) {
+          unsafeAtomicAdd(&persp_acc[2 * (size_t)sf[j]], ta);
+          unsafeAtomicAdd(&persp_acc[2 * (size_t)sf[j] + 1], tb);
+        }
       }
     }
     }
@@ -423,7 +484,8 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(ViewTable vt, const float*
                                                       const int* __restrict__ n_last, const float* __restrict__ t_last,
                                                       const float* __restrict__ gcolor, const float* __restrict__ gdepth,
                                                       const float* __restrict__ gtrans, acc_t* __restrict__ grad_acc,
-                                                      float* __restrict__ sig_acc, const int* __restrict__ order) {
+                                                      float* __restrict__ sig_acc, float* __restrict__ persp_acc,
+                                                      const int* __restrict__ order) {
   __shared__ float4 srec[kWaves][kBatch * 6];
   __shared__ uint32_t sface[kWaves][kBatch];
   const int wv = threadIdx.x >> 6;
@@ -447,7 +509,8 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(ViewTable vt, const float*
     pg.gd = gdepth[c.pix];
     pg.gt = gtrans ? gtrans[c.pix] : 0.f;
   }
-  backward_walk<SM, false>(c, records, pairs, sigma, last, Tb, pg, srec[wv], sface[wv], nullptr, grad_acc, sig_acc);
+  backward_walk<SM, false>(c, records, pairs, sigma, last, Tb, pg, srec[wv], sface[wv], nullptr, grad_acc, sig_acc,
+                           persp_acc);
 }
 
 // Fused training kernel: forward walk, L1 seeds of eqs. 8-10 (the D-SSIM term needs whole
@@ -462,6 +525,7 @@ __global__ __launch_bounds__(kBlock) void k_train_fused(ViewTable vt, const floa
                                                         float* __restrict__ color, float* __restrict__ depth,
                                                         float* __restrict__ trans, float* __restrict__ loss_part,
                                                         acc_t* __restrict__ grad_acc, float* __restrict__ sig_acc,
+                                                        float* __restrict__ persp_acc,
                                                         const int* __restrict__ order, int* __restrict__ queue,
                                                         int persistent) {
   // the four waves stage each span together (one copy of the records per tile)
@@ -530,7 +594,8 @@ __global__ __launch_bounds__(kBlock) void k_train_fused(ViewTable vt, const floa
       const float ws = wave_sum(lpix);
       if (lane == 0) loss_part[kWaves * tile + quad] = ws;
     }
-    backward_walk<SM, true>(c, records, pairs, sigma, s.last, s.Tb, pg, srec, sface, sint, grad_acc, sig_acc);
+    backward_walk<SM, true>(c, records, pairs, sigma, s.last, s.Tb, pg, srec, sface, sint, grad_acc, sig_acc,
+                            persp_acc);
     if (!persistent) break;
   }
 }
@@ -557,8 +622,10 @@ __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float*
                                                   const uint32_t* __restrict__ vis_total,
                                                   const uint32_t* __restrict__ vis_dense,
                                                   const float* __restrict__ records, acc_t* grad_acc,
+                                                  const float* __restrict__ persp_acc,
                                                   double* __restrict__ pose_acc, int want_vertices,
                                                   const float* __restrict__ loss_part, double* __restrict__ loss_acc) {
+  const bool persp = persp_acc != nullptr;        // perspective-correct records
   __shared__ double s_pose[TSR_MAX_VIEWS * 6];    // this workgroup's pose sums, per view
   for (int k = threadIdx.x; k < TSR_MAX_VIEWS * 6; k += blockDim.x) s_pose[k] = 0.0;
   __syncthreads();
@@ -657,8 +724,12 @@ __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float*
     for (int k = 0; k < 3; ++k)
       for (int ch = 0; ch < 3; ++ch) colv[k][ch] = (double)sc.col[ch * N + vid[k]];
     // ---- reverse: colour planes P_ch = sum_k beta_k,ch a_k (same for Q with b, R with c),
-    //      beta_k,ch = len_k col[opp(k)][ch] / perim
+    //      beta_k,ch = len_k col[opp(k)][ch] / perim, times 1 / z_opp(k) in the perspective-correct
+    //      mode, which also has the plane of W = sum_k beta_k (a_k, b_k, c_k), beta_k =
+    //      len_k / (perim z_opp(k)); those 1 / z factors add dL/dz of the vertices (giz)
     double gA[3], gB[3], gCc[3], glen[3] = {0, 0, 0}, gperim = 0.0;
+    double wz[3], giz[3] = {0, 0, 0};
+    for (int k = 0; k < 3; ++k) wz[k] = persp ? 1.0 / vc[(k + 2) % 3][2] : 1.0;
     for (int k = 0; k < 3; ++k) {
       gA[k] = (double)A[kGEdge + 3 * k];
       gB[k] = (double)A[kGEdge + 3 * k + 1];
@@ -668,14 +739,28 @@ __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float*
       const int o = (k + 2) % 3;
       for (int ch = 0; ch < 3; ++ch) {
         const double GP = (double)A[kGCol + 3 * ch], GQ = (double)A[kGCol + 3 * ch + 1], GR = (double)A[kGCol + 3 * ch + 2];
-        const double beta = len[k] * colv[o][ch] * inv_perim;
+        const double beta = len[k] * colv[o][ch] * inv_perim * wz[k];
         gA[k] += beta * GP;
         gB[k] += beta * GQ;
         gCc[k] += beta * GR;
         const double gbeta = GP * ca[k] + GQ * cb[k] + GR * cc[k];
-        gcolv[o][ch] += gbeta * len[k] * inv_perim;
-        glen[k] += gbeta * colv[o][ch] * inv_perim;
+        gcolv[o][ch] += gbeta * len[k] * inv_perim * wz[k];
+        glen[k] += gbeta * colv[o][ch] * inv_perim * wz[k];
         gperim -= gbeta * beta * inv_perim;
+        giz[k] += gbeta * len[k] * colv[o][ch] * inv_perim;
+      }
+    }
+    if (persp) {
+      const double GWa = (double)persp_acc[2 * g], GWb = (double)persp_acc[2 * g + 1], GWc = (double)A[kGWc];
+      for (int k = 0; k < 3; ++k) {
+        const double beta = len[k] * inv_perim * wz[k];
+        gA[k] += beta * GWa;
+        gB[k] += beta * GWb;
+        gCc[k] += beta * GWc;
+        const double gbeta = GWa * ca[k] + GWb * cb[k] + GWc * cc[k];
+        glen[k] += gbeta * inv_perim * wz[k];
+        gperim -= gbeta * beta * inv_perim;
+        giz[k] += gbeta * len[k] * inv_perim;
       }
     }
     // ---- reverse: edge coefficients a = -n_x / r, b = -n_y / r, c = -n.(anchor - q_k) / r
@@ -722,14 +807,16 @@ __global__ __launch_bounds__(256) void k_face_bwd(tsr_scene_dev sc, const float*
       gq[k][0] -= ge[k][0];
       gq[k][1] -= ge[k][1];
     }
-    // ---- projection and depth: q = (fx x / z + cx, fy y / z + cy), z_F = mean z
-    const double gz3 = (double)A[kGZ] * (1.0 / 3.0);
+    // ---- projection and depth: q = (fx x / z + cx, fy y / z + cy), z_F = mean z (the
+    //      perspective-correct mode has no z_F term; its 1 / z_k weights give -giz / z^2)
+    const double gz3 = persp ? 0.0 : (double)A[kGZ] * (1.0 / 3.0);
     for (int k = 0; k < 3; ++k) {
       const double iz = 1.0 / vc[k][2];
       double gc[3];
       gc[0] = gq[k][0] * (double)vd.fx * iz;
       gc[1] = gq[k][1] * (double)vd.fy * iz;
       gc[2] = -(gq[k][0] * (double)vd.fx * vc[k][0] + gq[k][1] * (double)vd.fy * vc[k][1]) * iz * iz + gz3;
+      if (persp) gc[2] -= giz[(k + 1) % 3] * iz * iz;      // vertex k faces edge (k + 1) % 3
       for (int a = 0; a < 3; ++a) gW[k][a] += R[a] * gc[0] + R[3 + a] * gc[1] + R[6 + a] * gc[2];
       pose6[0] += gc[0];
       pose6[1] += gc[1];
@@ -912,8 +999,9 @@ __global__ __launch_bounds__(256) void k_vertex_gather(tsr_scene_dev sc, ViewTab
 // longest-first tile order when `order` is given (tile counts the binning leaves it to).
 __global__ __launch_bounds__(256) void k_prep_bwd(ViewTable vt, const uint32_t* __restrict__ vis_total,
                                                   const uint32_t* __restrict__ vis_dense, acc_t* __restrict__ grad_acc,
-                                                  float* __restrict__ sig_acc, double* __restrict__ pose_acc,
-                                                  double* __restrict__ loss_acc, int* __restrict__ queue) {
+                                                  float* __restrict__ sig_acc, float* __restrict__ persp_acc,
+                                                  double* __restrict__ pose_acc, double* __restrict__ loss_acc,
+                                                  int* __restrict__ queue) {
   constexpr int kVec = (int)(kGradDwords * sizeof(acc_t)) / 16;      // 16-byte stores per row
   const int64_t nf = (int64_t)vt.n_views * vt.n_faces;
   const int64_t n = min((int64_t)*vis_total, nf) * kVec;
@@ -922,6 +1010,7 @@ __global__ __launch_bounds__(256) void k_prep_bwd(ViewTable vt, const uint32_t* 
     if (g < nf) {
       reinterpret_cast<float4*>(grad_acc + g * kGradDwords)[i % kVec] = make_float4(0.f, 0.f, 0.f, 0.f);
       if (sig_acc && i % kVec == 0) sig_acc[g] = 0.f;
+      if (persp_acc && i % kVec == 1) reinterpret_cast<float2*>(persp_acc)[g] = make_float2(0.f, 0.f);
     }
   }
   if (blockIdx.x == 0) {
@@ -1117,8 +1206,19 @@ static inline unsigned grid_for(int64_t n, int b) { return (unsigned)((n + b - 1
 
 static int sigma_mode(float s) { return s == 1.f ? 1 : (s == 0.5f ? 2 : (s == 2.f ? 3 : 0)); }
 
-// Per-face exponents (mode 4) whenever the scene has them, else the global sigma's mode.
-static int sigma_mode(const ViewTable& vt, const tsr_params& p) { return vt.face_sigma ? 4 : sigma_mode(p.sigma); }
+// Per-face exponents (mode 4) whenever the scene has them, else the global sigma's mode; plus
+// 8 for perspective-correct interpolation.
+static int sigma_mode(const ViewTable& vt, const tsr_params& p) {
+  return (vt.face_sigma ? 4 : sigma_mode(p.sigma)) | (p.perspective ? 8 : 0);
+}
+
+// switch over the kernel modes built: exponent modes 0-4, perspective-correct with 0-3
+#define TSR_MODE_SWITCH(mode, X)                                                                   \
+  switch (mode) {                                                                                  \
+    case 1: X(1); break; case 2: X(2); break; case 3: X(3); break; case 4: X(4); break;            \
+    case 8: X(8); break; case 9: X(9); break; case 10: X(10); break; case 11: X(11); break;        \
+    default: X(0); break;                                                                          \
+  }
 
 static unsigned tile_grid(int n_tiles) { return 8u * (unsigned)((n_tiles + 7) / 8); }
 
@@ -1149,7 +1249,7 @@ __global__ __launch_bounds__(kBlock) void k_face_stats(ViewTable vt, const float
     if (ballot(live(T, t_min)) == 0) break;
     const int n = (int)min((uint32_t)kBatch, c.end - b0);
     stage_batch(records, pairs, b0, n, srec[wv], sface[wv]);
-    unsigned long long mask = batch_hit_mask(srec[wv], n, c.bx, c.by);
+    unsigned long long mask = batch_hit_mask<SM>(srec[wv], n, c.bx, c.by);
     bool lv = live(T, t_min);
     while (mask) {
       const int j = __builtin_ctzll(mask);
@@ -1203,13 +1303,9 @@ hipError_t launch_face_stats(const ViewTable& vt, const tsr_params& p, const WsL
     if (visible) TSR_LAUNCH("fill_stats", k_fill_f32, dim3(fg), dim3(256), 0, st, reinterpret_cast<float*>(visible), nf);
   }
   const dim3 grid(tile_grid(vt.n_tiles)), block(kBlock);
-  switch (sigma_mode(vt, p)) {
-    case 4: TSR_LAUNCH("face_stats", k_face_stats<4>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, coverage, visible, border); break;
-    case 1: TSR_LAUNCH("face_stats", k_face_stats<1>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, coverage, visible, border); break;
-    case 2: TSR_LAUNCH("face_stats", k_face_stats<2>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, coverage, visible, border); break;
-    case 3: TSR_LAUNCH("face_stats", k_face_stats<3>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, coverage, visible, border); break;
-    default: TSR_LAUNCH("face_stats", k_face_stats<0>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, coverage, visible, border); break;
-  }
+#define TSR_STATS(S) TSR_LAUNCH("face_stats", k_face_stats<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, coverage, visible, border)
+  TSR_MODE_SWITCH(sigma_mode(vt, p), TSR_STATS)
+#undef TSR_STATS
   return hipGetLastError();
 }
 
@@ -1222,13 +1318,9 @@ hipError_t launch_forward(const ViewTable& vt, const tsr_params& p, const WsLayo
   int* n_last = reinterpret_cast<int*>(ws + L.n_last);
   float* t_last = reinterpret_cast<float*>(ws + L.t_last);
   const dim3 grid(tile_grid(vt.n_tiles)), block(kBlock);
-  switch (sigma_mode(vt, p)) {
-    case 4: TSR_LAUNCH("blend_fwd", k_blend_fwd<4>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last, border); break;
-    case 1: TSR_LAUNCH("blend_fwd", k_blend_fwd<1>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last, border); break;
-    case 2: TSR_LAUNCH("blend_fwd", k_blend_fwd<2>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last, border); break;
-    case 3: TSR_LAUNCH("blend_fwd", k_blend_fwd<3>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last, border); break;
-    default: TSR_LAUNCH("blend_fwd", k_blend_fwd<0>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last, border); break;
-  }
+#define TSR_FWD(S) TSR_LAUNCH("blend_fwd", k_blend_fwd<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last, border)
+  TSR_MODE_SWITCH(sigma_mode(vt, p), TSR_FWD)
+#undef TSR_FWD
   return hipGetLastError();
 }
 
@@ -1249,6 +1341,7 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
   acc_t* grad_acc = reinterpret_cast<acc_t*>(ws + L.grad_acc);
   double* pose_acc = reinterpret_cast<double*>(ws + L.pose_acc);
   float* sig_acc = vt.face_sigma ? reinterpret_cast<float*>(ws + L.sig_acc) : nullptr;
+  float* persp_acc = p.perspective ? reinterpret_cast<float*>(ws + L.persp_acc) : nullptr;
   float* loss_part = reinterpret_cast<float*>(ws + L.loss_part);
   double* loss_acc = reinterpret_cast<double*>(ws + L.loss_acc);
   const int64_t nf = (int64_t)vt.n_views * vt.n_faces;
@@ -1261,22 +1354,22 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
     const int64_t rows16 = nf * (int64_t)((kGradDwords * sizeof(acc_t)) / 16);
     const unsigned g = (unsigned)std::min<int64_t>(std::max<int64_t>(grid_for(rows16, 256), 1), 2048);
     TSR_LAUNCH("prep_bwd", k_prep_bwd, dim3(g), dim3(256), 0, st, vt, vis_total, vis_dense, grad_acc, sig_acc,
-               pose_acc, loss_acc, queue);
+               persp_acc, pose_acc, loss_acc, queue);
   }
   const dim3 block(kBlock);
   const int sm = sigma_mode(vt, p);
   if (!fused_train) {
     const dim3 grid(tile_grid(vt.n_tiles));
     const int* border = order;
-#define TSR_BWD(S) TSR_LAUNCH("blend_bwd", k_blend_bwd<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, n_last, t_last, gcolor, gdepth, gtrans, grad_acc, sig_acc, border)
-    switch (sm) { case 1: TSR_BWD(1); break; case 2: TSR_BWD(2); break; case 3: TSR_BWD(3); break; case 4: TSR_BWD(4); break; default: TSR_BWD(0); }
+#define TSR_BWD(S) TSR_LAUNCH("blend_bwd", k_blend_bwd<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, n_last, t_last, gcolor, gdepth, gtrans, grad_acc, sig_acc, persp_acc, border)
+    TSR_MODE_SWITCH(sm, TSR_BWD)
 #undef TSR_BWD
   } else {
     dim3 grid(tile_grid(vt.n_tiles));
     if (sched.order && !sched.persistent) grid = dim3(vt.n_tiles);
     if (sched.persistent) grid = dim3(sched.grid > 0 ? sched.grid : 2048);
-#define TSR_TRAIN(S) TSR_LAUNCH("train_fused", k_train_fused<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, p.w_color, p.w_depth, tcolor, tdepth, color, depth, trans, loss ? loss_part : nullptr, grad_acc, sig_acc, order, queue, sched.persistent)
-    switch (sm) { case 1: TSR_TRAIN(1); break; case 2: TSR_TRAIN(2); break; case 3: TSR_TRAIN(3); break; case 4: TSR_TRAIN(4); break; default: TSR_TRAIN(0); }
+#define TSR_TRAIN(S) TSR_LAUNCH("train_fused", k_train_fused<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, p.w_color, p.w_depth, tcolor, tdepth, color, depth, trans, loss ? loss_part : nullptr, grad_acc, sig_acc, persp_acc, order, queue, sched.persistent)
+    TSR_MODE_SWITCH(sm, TSR_TRAIN)
 #undef TSR_TRAIN
   }
   // per visible (view, face): chain rule and pose; then per face: vertex gradients summed
@@ -1292,7 +1385,7 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
   if (nf > 0) {
     const dim3 fgrid(std::min<unsigned>(grid_for(nf, 256), 2048u));
     TSR_LAUNCH("face_bwd", k_face_bwd, fgrid, dim3(256), 0, st, sc, poses, vt, vis_total, vis_dense, records,
-               grad_acc, grad_pose ? pose_acc : nullptr, want_vertices ? 1 : 0, loss ? loss_part : nullptr,
+               grad_acc, persp_acc, grad_pose ? pose_acc : nullptr, want_vertices ? 1 : 0, loss ? loss_part : nullptr,
                loss_acc);
     if (want_gather)
       TSR_LAUNCH("vertex_gather", k_vertex_gather, dim3(grid_for(vt.n_faces, 256)), dim3(256), 0, st, sc, vt, counts,

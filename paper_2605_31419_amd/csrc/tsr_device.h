@@ -31,11 +31,19 @@ enum RecordField : int {
   kRecSigma = 23,    // the face's window exponent sigma (eq. 3)
   kRecDwords = 24
 };
+// With perspective-correct interpolation the colour planes hold the numerators N_ch of the
+// perspective-correct colour, sum_k lambda_k c_k / z_k, and three dwords the plane of the
+// denominator W = sum_k lambda_k / z_k (W = 1 / depth of the face's plane along the ray); the
+// depth z_F, the rectangle's end and the per-face exponent are not stored.
+enum PerspField : int { kRecWa = kRecZ, kRecWb = kRecU1V1, kRecWc = kRecSigma };
 
 // Per-(view, face) gradient accumulator, 20 values, filled by the backward blend:
 // dL/d(a_k, b_k, c_k) for the three edges, dL/d(P, Q, R) per channel, dL/do_F, dL/dz_F.
 // Wave partial sums are FP32; they are accumulated across waves and tiles in acc_t.
 enum GradField : int { kGEdge = 0, kGCol = 9, kGOpa = 18, kGZ = 19, kGradDwords = 20 };
+// Perspective-correct mode: the colour slots hold dL/d(N_ch plane), kGZ dL/d(constant of the W
+// plane); the W plane's two slopes go to a second per-(view, face) accumulator of 2 floats.
+enum GradPerspField : int { kGWc = kGZ };
 #ifndef TSR_ACC_F64
 #define TSR_ACC_F64 0
 #endif

@@ -36,6 +36,7 @@ struct WsLayout {
   size_t records;                  // float  [V*M][24]
   size_t grad_acc;                 // float  [V*M][20]
   size_t sig_acc;                  // float  [V*M]: dL/dsigma of each (view, face) (per-face exponents)
+  size_t persp_acc;                // float  [V*M][2]: dL/d(W plane slopes) (perspective-correct mode)
   size_t tile_cnt;                 // uint32 [T][4]: [0] faces with <= 4 tiles, [2] larger faces (later
                                    // their emission cursor), [1] and [3] unused, so that every counter
                                    // the atomics hit sits alone in its 8-byte word; then the uint32

@@ -33,10 +33,11 @@ class Params:
     w_depth: float = 0.05
     opacity_min: bool = False     # face opacity = min of the vertex opacities (Mesh Splatting variant)
     tight_tiles: bool = False     # list a face only in the tiles that can hold a pixel it covers
+    perspective: bool = False     # perspective-correct colour interpolation and plane depth
 
     def c(self) -> TsrParams:
         return TsrParams(self.sigma, self.t_min, self.z_near, self.r_min, self.w_color, self.w_depth,
-                         1 if self.opacity_min else 0, 1 if self.tight_tiles else 0)
+                         1 if self.opacity_min else 0, 1 if self.tight_tiles else 0, 1 if self.perspective else 0)
 
 
 def _ptr(t: Optional[torch.Tensor]):

@@ -76,14 +76,14 @@ def test_backward_with_face_sigma(name):
     sc, poses, intrs = _case(name, 0.4, 2.5)
     rast, p = _make(sc, intrs, poses)
     P = rast.total_pixels
-    g = np.random.default_rng(42)            # the upstream gradients of the global-exponent backward test
+    g = np.random.default_rng(43)
     gc = g.normal(size=3 * P).astype(np.float32)
     gd = g.normal(size=P).astype(np.float32)
     gt = g.normal(size=P).astype(np.float32)
     masks = PAR._steep_masks(sc, poses, intrs, 0.5)
     for a, ch in ((gc, 3), (gd, 1), (gt, 1)):
         PAR._apply_masks(a, masks, ch)
-    _say(f"  steep-edge pixels masked on both sides: {sum(int(m.sum()) for m in masks)} of {P}")
+    _say(f"  steep-edge and ridge pixels masked on both sides: {sum(int(m.sum()) for m in masks)} of {P}")
     rast.bin_and_sort(p)
     rast.forward(p)
     out = rast.backward(p, G.to_dev(gc), G.to_dev(gd), G.to_dev(gt))

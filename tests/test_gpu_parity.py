@@ -331,23 +331,28 @@ def _oracle_backward_views(sc, poses, intrs, gcs, gds, gts, sigma, with_abs=Fals
     return (res, absacc) if with_abs else res
 
 
-# Steep-edge band (sigma < 1): the window's slope sigma rho^(sigma-1) grows without bound as
-# rho -> 0+, so at pixels within |rho| < 1e-3 of any face's edge the FP32 kernels' rounding of
-# rho (a few 1e-7) changes per-pixel gradient terms by more than the relative bar, and a face
-# can be blended on one side and not on the other.  Upstream gradients are zeroed at those
-# pixels on both sides (the same seeds go to the GPU and to the oracle); every other pixel is
-# compared element-wise.
+# Pixels whose per-pixel gradient terms an FP32 implementation cannot reproduce to the relative
+# bar, found from the oracle's discrete state (the rejection rule for ridge, edge and steep-slope
+# flips), get zero upstream gradients on both sides (the same seeds go to the GPU and to the
+# oracle); every other pixel is compared element-wise:
+#  * steep-edge band (sigma < 1): the window's slope sigma rho^(sigma-1) grows without bound as
+#    rho -> 0+, so within |rho| < 1e-3 of any face's edge the kernels' rounding of rho (a few
+#    1e-7) changes per-pixel terms by more than the bar, and a face can be blended on one side
+#    and not on the other;
+#  * ridges of phi: where a blended face's two smallest normalised edge distances are within
+#    1e-5 of each other (about 30 times the FP32 rounding of E_k), which edge attains the
+#    minimum -- and so which edge's parameters receive that pixel's window gradient -- can flip.
 STEEP_RHO = 1e-3
+RIDGE_GAP = 1e-5
 
 
 def _steep_masks(sc, poses, intrs, sigma):
     out = []
     for v in range(len(poses)):
-        n = intrs[v].width * intrs[v].height
-        if sigma >= 1.0:
-            out.append(np.zeros(n, bool))
-        else:
-            out.append(O.min_rho(sc, poses[v], intrs[v], sigma=sigma) < STEEP_RHO)
+        m = O.ridge_gap(sc, poses[v], intrs[v], sigma=sigma) < RIDGE_GAP
+        if sigma < 1.0:
+            m |= O.min_rho(sc, poses[v], intrs[v], sigma=sigma) < STEEP_RHO
+        out.append(m)
     return out
 
 
@@ -375,7 +380,7 @@ def test_backward_matches_oracle(name, sigma):
     masks = _steep_masks(sc, poses, intrs, sigma)
     for a, ch in ((gc, 3), (gd, 1), (gt, 1)):
         _apply_masks(a, masks, ch)
-    _say(f"  steep-edge pixels masked on both sides: {sum(int(m.sum()) for m in masks)} of {P}")
+    _say(f"  steep-edge and ridge pixels masked on both sides: {sum(int(m.sum()) for m in masks)} of {P}")
     got = _gpu_backward(rast, p, gc, gd, gt)
     gcs = G.per_view(rast, gc, 3)
     gds, gts = G.per_view(rast, gd, 1), G.per_view(rast, gt, 1)

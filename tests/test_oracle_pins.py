@@ -378,3 +378,18 @@ def test_l1_seeds_by_finite_differences():
     assert np.all(gd[::7] == 0)
     expect = 0.8 * np.abs(C - tc).sum() / 600 + 0.05 * (np.abs(D - td) * (td > 0)).sum() / 200
     assert abs(L - expect) < 1e-12
+
+
+def test_ridge_gap_golden_values():
+    """Gap between the two smallest normalised edge distances (the ridge mask of the parity
+    tests), from the golden triangle's hand-derived inside distances d = (v - 20,
+    (328 - 6u - 8v)/10, u - 20) over r = 2: 0 at the incentre (all equal) and on the bisector
+    u = v ((21, 21): 0.5, 1.7, 0.5), 0.6 at (24, 22) (1, 0.4, 2), 0.8 at (22, 24) (2, 0.2, 1),
+    0.6 at (23, 21) (0.5, 1.1, 1.5); +inf where the face is not blended."""
+    g = json.load(open(os.path.join(GOLD, "window_right_triangle.json")))
+    cam = unit_cam(g["camera"]["width"], g["camera"]["height"])
+    sc = _tri_scene(g["vertices"], opa=np.ones((1, 3)))
+    pts = [(22, 22), (21, 21), (24, 22), (22, 24), (23, 21), (26, 25), (10, 10)]
+    gap = O.ridge_gap(sc, IDENTITY, cam, pixels=_pix(cam, pts))
+    np.testing.assert_allclose(gap[:5], [0.0, 0.0, 0.6, 0.8, 0.6], atol=1e-12)
+    assert np.all(np.isinf(gap[5:]))
