@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="(kept for older profiler commands: the 256 MiB device copy now always runs)")
     ap.add_argument("--no-sigma-half", action="store_true", help="skip the headline step at the paper's sigma = 0.5")
+    ap.add_argument("--tight-tiles", action="store_true",
+                    help="bin with the tight triangle-tile test (same images and gradients, shorter lists)")
     ap.add_argument("--serve-warmup", type=int, default=500)
     ap.add_argument("--only-single", action="store_true", help="skip the unfused and batched legs")
     ap.add_argument("--only-photometric", action="store_true",
@@ -75,11 +77,11 @@ def log(*a):
 class Case:
     """A rasterizer with its inputs, outputs and gradient buffers resident on the device."""
 
-    def __init__(self, raster, scenes, dev_scene, poses, intrs, target_poses, sigma=1.0):
+    def __init__(self, raster, scenes, dev_scene, poses, intrs, target_poses, sigma=1.0, tight_tiles=False):
         import torch
 
         self.torch = torch
-        self.rast = raster.Rasterizer(dev_scene, intrs, raster.Params(sigma=sigma))
+        self.rast = raster.Rasterizer(dev_scene, intrs, raster.Params(sigma=sigma, tight_tiles=tight_tiles))
         self.poses = raster.poses_tensor(poses)
         tposes = raster.poses_tensor(target_poses)
         self.K = self.rast.fit(self.poses, slack=1.5)
@@ -487,7 +489,7 @@ def main():
     log(f"[bench] generating the {args.faces}-face room soup")
     w = scenes.workload("track_1200x680_1M", n_faces=args.faces)
     dev = raster.DeviceScene.from_numpy(w.scene)
-    single = Case(raster, scenes, dev, w.poses, w.intr, w.target_poses)
+    single = Case(raster, scenes, dev, w.poses, w.intr, w.target_poses, tight_tiles=args.tight_tiles)
     E, K, m_vis, maxlen, meanlen = single.evaluations()
     log(f"[bench] single view: K={K} visible={m_vis} max list {maxlen} mean {meanlen:.1f} evals {E}")
     tuned = None
@@ -589,7 +591,7 @@ def main():
         g = scenes.rng(5500)
         bposes = scenes.room_trajectory(g, args.views)
         btargets = [scenes.perturb_pose(p, g) for p in bposes]
-        bcase = Case(raster, scenes, dev, bposes, [w.intr[0]] * args.views, btargets)
+        bcase = Case(raster, scenes, dev, bposes, [w.intr[0]] * args.views, btargets, tight_tiles=args.tight_tiles)
         Eb, Kb, mvb, maxb, meanb = bcase.evaluations()
         btuned = None
         if not args.no_tune:
@@ -608,29 +610,38 @@ def main():
                    "kernels_ms": {k: round(v, 4) for k, v in ktb.items()}, "schedule": btuned}
         log(f"[bench] batched {args.views} views: {msb:.3f} ms -> {batched['mpix_s']:.1f} Mpix/s")
         # the whole mapping energy over the same window: D-SSIM photometric term and depth L1,
-        # E_equi and E_norm against the sensor normals of the target depth
+        # E_equi and E_norm against the sensor normals of the target depth; one binning with the
+        # normals as extra channels of the walks, and (for comparison) the normal loss as a
+        # step of its own with a second binning
         from paper_2605_31419_amd.window import MappingWindow
-        bintr = [w.intr[0]] * args.views
-        win = MappingWindow(dev, bintr, w_ssim=0.2, w_equi=1.2, w_norm=0.05)
-        win.prepare(bcase.poses)
-        tnorm = raster.sensor_normals(bcase.td, bintr)
-        map_step = lambda: win.step(bcase.poses, bcase.tc, bcase.td, target_normals=tnorm)
-        msm = time_steps(map_step, max(5, args.steps // 4), args.warmup)
         from paper_2605_31419_amd import _lib
-        _lib.check(win.rast.lib.tsr_check(raster._ptr(win.rast.ws), raster._stream(), None), "tsr_check")
-        ktm, _ = kernel_times(map_step, max(2, args.profile_steps // 2))
-        batched["mapping_energy"] = {"weights": {"ssim": 0.2, "depth": 0.05, "equi": 1.2, "norm": 0.05},
-                                     "ms_per_step": msm, "mpix_s": bcase.pixels / (msm * 1e-3) / 1e6,
-                                     "kernels_ms": {k: round(v, 4) for k, v in ktm.items()}}
-        log(f"[bench] mapping energy over {args.views} views: {msm:.3f} ms")
-        del win, tnorm
+        bintr = [w.intr[0]] * args.views
+        tnorm = raster.sensor_normals(bcase.td, bintr)
+        energy = {"weights": {"ssim": 0.2, "depth": 0.05, "equi": 1.2, "norm": 0.05}}
+        for fused in (True, False):
+            win = MappingWindow(dev, bintr, w_ssim=0.2, w_equi=1.2, w_norm=0.05, fused_mapping=fused)
+            win.prepare(bcase.poses)
+            map_step = lambda: win.step(bcase.poses, bcase.tc, bcase.td, target_normals=tnorm)
+            msm = time_steps(map_step, max(5, args.steps // 4), args.warmup)
+            _lib.check(win.rast.lib.tsr_check(raster._ptr(win.rast.ws), raster._stream(), None), "tsr_check")
+            if fused:
+                ktm, _ = kernel_times(map_step, max(2, args.profile_steps // 2))
+                energy.update({"ms_per_step": msm, "mpix_s": bcase.pixels / (msm * 1e-3) / 1e6,
+                               "kernels_ms": {k: round(v, 4) for k, v in ktm.items()}})
+                log(f"[bench] mapping energy over {args.views} views, one binning: {msm:.3f} ms")
+            else:
+                energy["separate_normal_step_ms"] = msm
+                log(f"[bench] mapping energy over {args.views} views, normal loss binned separately: {msm:.3f} ms")
+            del win
+        batched["mapping_energy"] = energy
+        del tnorm
         del bcase
         torch.cuda.empty_cache()
 
     sigma_half = None
     if not args.no_sigma_half:
         # the headline step at the paper's rendering exponent (sigma = 0.5, square-root window)
-        hcase = Case(raster, scenes, dev, w.poses, w.intr, w.target_poses, sigma=0.5)
+        hcase = Case(raster, scenes, dev, w.poses, w.intr, w.target_poses, sigma=0.5, tight_tiles=args.tight_tiles)
         htuned = None
         if not args.no_tune:
             from paper_2605_31419_amd import autotune

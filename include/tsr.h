@@ -356,6 +356,34 @@ TSR_API int tsr_render_train_normal(const tsr_scene *scene, const float *poses, 
                             float *grad_pos, float *grad_opa, float *grad_pose, int accumulate, void *scratch,
                             size_t scratch_bytes, void *stream);
 
+/* The mapping energy's rendering terms in one step (Sec. 3.4): the photometric and depth
+ * terms of tsr_render_train_photometric and the normal term of tsr_render_train_normal on ONE
+ * binning of the scene's colours.  The forward pass composites each face's world unit normal
+ * as three more channels beside the colour (a normal is constant over its face, so it blends
+ * like a flat colour, with the eq. 4 weights), and the backward pass takes the colour, depth
+ * and normal seeds in one walk.  Per view:
+ *   loss[v]      = as tsr_render_train_photometric (w_color, w_depth from params, w_ssim);
+ *   loss_norm[v] = as tsr_render_train_normal's loss (w_norm).
+ * grad_pos [3][N], grad_col [3][N], grad_opa [N], grad_pose [n_views][6] (each may be NULL)
+ * receive the gradient of sum_v (loss[v] + loss_norm[v]), overwriting them; with per-face
+ * exponents, scene->grad_face_sigma receives that of both terms.  color and depth must not be
+ * NULL; trans, normal_map (N in the camera frame, packed like colour), loss and loss_norm may
+ * be.  target_color, target_depth as for the photometric step, target_normals as for the
+ * normal step (a zero vector marks an invalid pixel).  Requires a preceding tsr_bin_and_sort
+ * of the same scene (its colours, not the normals: the normals ride in the walks).
+ * scratch: device, 256-byte aligned, at least tsr_mapping_scratch_size bytes (the D-SSIM
+ * scratch + 32 per face + 24 per pixel + 2.5 KB), owned by the caller, no clearing needed.
+ * Soups only (faces == NULL): TSR_EINVAL otherwise.  Enqueued on `stream`; no allocation. */
+TSR_API int tsr_mapping_scratch_size(const tsr_scene *scene, const tsr_intrinsics *intr /* (host)[n_views] */,
+                                     int n_views, size_t *bytes /* (host) out */);
+TSR_API int tsr_render_train_mapping(const tsr_scene *scene, const float *poses, const tsr_intrinsics *intr,
+                                     int n_views, const tsr_params *params, void *ws, size_t ws_bytes,
+                                     const float *target_color, const float *target_depth,
+                                     const float *target_normals, float w_ssim, float w_norm, float *color,
+                                     float *depth, float *trans, float *normal_map, float *loss, float *loss_norm,
+                                     float *grad_pos, float *grad_col, float *grad_opa, float *grad_pose,
+                                     void *scratch, size_t scratch_bytes, void *stream);
+
 /* Synchronise `stream` and report device-side conditions of `ws`: TSR_ECAPACITY when the
  * last binning, or any binning since the previous tsr_check (e.g. inside a replayed graph),
  * overflowed; that condition is then cleared.  Writes the last K to *n_pairs when non-NULL.

@@ -63,16 +63,21 @@ def face_normals(pos: np.ndarray) -> np.ndarray:
 class _Soup:
     """A soup with the attributes the renderer reads."""
 
-    def __init__(self, pos, col, opa):
+    def __init__(self, pos, col, opa, face_sigma=None):
         self.pos, self.col, self.opa, self.faces = pos, col, opa, None
         self.n_faces = pos.shape[1] // 3
+        self.face_sigma = face_sigma
 
 
 def normal_scene(scene):
-    """The soup with every vertex colour replaced by its face's world normal."""
+    """The soup with every vertex colour replaced by its face's world normal; per-face window
+    exponents (when the scene has them) are kept, since the normal map is rendered with the
+    same blending weights as the colours."""
     n = face_normals(scene.pos)
     col = np.repeat(n, 3, axis=1)
-    return _Soup(np.asarray(scene.pos, np.float64), col, np.asarray(scene.opa, np.float64))
+    fs = getattr(scene, "face_sigma", None)
+    return _Soup(np.asarray(scene.pos, np.float64), col, np.asarray(scene.opa, np.float64),
+                 None if fs is None else np.asarray(fs, np.float64))
 
 
 def _rot(pose):

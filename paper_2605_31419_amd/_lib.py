@@ -24,7 +24,7 @@ TSR_EQUI_NOALLOC_MAX_FACES = 4194304
 TSR_TILE = 16
 
 EXPORTED = ["tsr_workspace_size", "tsr_workspace_init", "tsr_bin_and_sort", "tsr_count", "tsr_binning_view", "tsr_render_forward",
-            "tsr_render_backward", "tsr_render_train_l1", "tsr_pose_step", "tsr_pose_compose", "tsr_pose_tau_grad", "tsr_dssim_scratch_size", "tsr_dssim", "tsr_render_train_photometric", "tsr_equilateral_scratch_size", "tsr_equilateral", "tsr_equilateral_noalloc", "tsr_face_stats", "tsr_sensor_normals", "tsr_normal_scratch_size", "tsr_render_train_normal", "tsr_check", "tsr_last_error",
+            "tsr_render_backward", "tsr_render_train_l1", "tsr_pose_step", "tsr_pose_compose", "tsr_pose_tau_grad", "tsr_dssim_scratch_size", "tsr_dssim", "tsr_render_train_photometric", "tsr_equilateral_scratch_size", "tsr_equilateral", "tsr_equilateral_noalloc", "tsr_face_stats", "tsr_sensor_normals", "tsr_normal_scratch_size", "tsr_render_train_normal", "tsr_mapping_scratch_size", "tsr_render_train_mapping", "tsr_check", "tsr_last_error",
             "tsr_profile_enable", "tsr_profile_reset", "tsr_profile_read"]
 
 
@@ -96,6 +96,9 @@ def load() -> C.CDLL:
     lib.tsr_normal_scratch_size.argtypes = [P, P, I, P]
     lib.tsr_render_train_normal.argtypes = [P, P, P, I, P, P, C.c_size_t, P, C.c_float, P, P, P, P, P, I, P,
                                             C.c_size_t, P]
+    lib.tsr_mapping_scratch_size.argtypes = [P, P, I, P]
+    lib.tsr_render_train_mapping.argtypes = [P, P, P, I, P, P, C.c_size_t, P, P, P, C.c_float, C.c_float, P, P, P, P,
+                                             P, P, P, P, P, P, P, C.c_size_t, P]
     lib.tsr_check.argtypes = [P, P, P]
     lib.tsr_last_error.restype = C.c_char_p
     lib.tsr_profile_enable.argtypes = [I]

@@ -556,6 +556,44 @@ int tsr_render_train_normal(const tsr_scene* scene, const float* poses, const ts
   return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_render_train_normal launch");
 }
 
+int tsr_mapping_scratch_size(const tsr_scene* scene, const tsr_intrinsics* intr, int n_views, size_t* bytes) {
+  int rc;
+  if ((rc = check_scene(scene))) return rc;
+  if (!bytes) return fail(TSR_EINVAL, "bytes is NULL");
+  tsr::SsimTable t;
+  if (!intr || tsr::build_ssim_table(intr, n_views, &t) != 0)
+    return fail(TSR_EINVAL, "views: need 1 <= n_views <= %d and image sizes in (0, 16384]", TSR_MAX_VIEWS);
+  *bytes = tsr::mapping_scratch(tsr::ssim_scratch_bytes(t), scene->n_faces, t.n_pixels).total;
+  return TSR_OK;
+}
+
+int tsr_render_train_mapping(const tsr_scene* scene, const float* poses, const tsr_intrinsics* intr, int n_views,
+                             const tsr_params* params, void* ws, size_t ws_bytes, const float* target_color,
+                             const float* target_depth, const float* target_normals, float w_ssim, float w_norm,
+                             float* color, float* depth, float* trans, float* normal_map, float* loss,
+                             float* loss_norm, float* grad_pos, float* grad_col, float* grad_opa, float* grad_pose,
+                             void* scratch, size_t scratch_bytes, void* stream) {
+  ViewTable vt;
+  WsLayout L;
+  int rc = prepare(scene, poses, intr, n_views, params, ws, ws_bytes, &vt, &L);
+  if (rc) return rc;
+  if (scene->faces) return fail(TSR_EINVAL, "the mapping step needs a soup (faces == NULL)");
+  if (!target_color || !target_depth || !target_normals)
+    return fail(TSR_EINVAL, "target_color, target_depth or target_normals is NULL");
+  if (!color || !depth) return fail(TSR_EINVAL, "color or depth output is NULL (the D-SSIM term reads them)");
+  tsr::SsimTable t;
+  if (tsr::build_ssim_table(intr, n_views, &t) != 0) return fail(TSR_EINVAL, "bad D-SSIM view table");
+  if (!scratch) return fail(TSR_EINVAL, "scratch is NULL");
+  const size_t need = tsr::mapping_scratch(tsr::ssim_scratch_bytes(t), scene->n_faces, t.n_pixels).total;
+  if (scratch_bytes < need) return fail(TSR_EWORKSPACE, "mapping scratch of %zu bytes is below the %zu needed", scratch_bytes, need);
+  if (reinterpret_cast<uintptr_t>(scratch) & 255) return fail(TSR_EINVAL, "scratch must be 256-byte aligned");
+  hipError_t e = tsr::launch_train_mapping(dev_scene(scene, params), poses, vt, *params, L, static_cast<char*>(ws), t,
+                                           target_color, target_depth, target_normals, w_ssim, w_norm, color, depth,
+                                           trans, normal_map, loss, loss_norm, grad_pos, grad_col, grad_opa, grad_pose,
+                                           static_cast<char*>(scratch), static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_render_train_mapping launch");
+}
+
 int tsr_profile_enable(int on) {
   std::lock_guard<std::mutex> lk(tsr::g_prof_mu);
   tsr::g_prof_on = on != 0;

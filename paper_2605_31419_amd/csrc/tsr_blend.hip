@@ -44,6 +44,20 @@ __device__ __forceinline__ int tile_of_block_ordered(int n_tiles, const int* __r
 // perspective-correct interpolation (numerator and denominator planes in the record).
 template <int SM> constexpr int exp_mode() { return SM & 7; }
 template <int SM> constexpr bool persp_mode() { return (SM & 8) != 0; }
+// Bit 4: the separate forward and backward walks also composite each face's world normal (a
+// colour constant over the face) into a normal map and back-propagate its seeds (mapping step).
+template <int SM> constexpr bool normal_mode() { return (SM & 16) != 0; }
+
+// Normal channels: per face, not per view, indexed by m = g - v M for the record slot
+// g = v M + m.  The normal is a world quantity and its seeds are rotated into the world frame,
+// so the gradients of all views add into one entry per face.
+struct NormalIn {
+  const float4* nrm;       // [M] unit world normal (x, y, z, 0)
+  const float* seed;       // backward: [sum 3 P] dE/dN_w per pixel, packed like colour
+  float4* gacc;            // backward: [M] dE/dn_F summed over the views (x, y, z, 0)
+  float* map;              // forward: [sum 3 P] composited world normals, packed like colour
+  int64_t M;
+};
 
 // Window value for rho in (0, 1): I = rho^sigma (eq. 3).
 template <int SM>
@@ -179,12 +193,16 @@ __device__ __forceinline__ void stage_batch_block(const float* __restrict__ reco
 }
 
 // Per-wave staging: lane l reads the face id of entry l; the 6 n sixteen-byte pieces are then
-// loaded by the lanes in turn (piece i by lane i % 64, face id taken from lane i / 6).
+// loaded by the lanes in turn (piece i by lane i % 64, face id taken from lane i / 6).  With
+// the normal channels, lane l also stages the normal of face l into snrm.
 __device__ __forceinline__ void stage_batch(const float* __restrict__ records, const uint64_t* __restrict__ pairs,
-                                            uint32_t b0, int n, float4* srec, uint32_t* sface) {
+                                            uint32_t b0, int n, float4* srec, uint32_t* sface,
+                                            const float4* __restrict__ nrm = nullptr, int64_t moff = 0,
+                                            float4* snrm = nullptr) {
   const int lane = threadIdx.x & 63;
   const uint32_t f = lane < n ? (uint32_t)pairs[b0 + lane] : 0u;
   if (lane < n) sface[lane] = f;
+  if (nrm && lane < n) snrm[lane] = nrm[(int64_t)f - moff];
   const float4* rec4 = reinterpret_cast<const float4*>(records);
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
@@ -251,6 +269,7 @@ __device__ __forceinline__ unsigned long long batch_hit_mask(const float4* srec,
 
 struct FwdState {
   float T, C0, C1, C2, D, Tb;
+  float N0, N1, N2;        // composited world normal (normal channels)
   int last;
 };
 
@@ -265,9 +284,11 @@ __device__ __forceinline__ bool live(float T, float t_min) { return T >= t_min &
 template <int SM, bool COOP>
 __device__ __forceinline__ void forward_walk(const TileCtx& c, const float* __restrict__ records,
                                              const uint64_t* __restrict__ pairs, float sigma, float t_min,
-                                             float4* srec, uint32_t* sface, FwdState& s) {
+                                             float4* srec, uint32_t* sface, FwdState& s,
+                                             const NormalIn* nin = nullptr, float4* snrm = nullptr) {
   s.T = c.inside ? 1.f : 0.f;
   s.C0 = s.C1 = s.C2 = s.D = 0.f; s.Tb = 1.f; s.last = -1;
+  s.N0 = s.N1 = s.N2 = 0.f;
   const float dxb = (float)c.px, dyb = (float)c.py;
   constexpr int kStage = COOP ? kSpan : kBatch;     // faces staged at once
   for (uint32_t s0 = c.start; s0 < c.end; s0 += kStage) {
@@ -278,7 +299,10 @@ __device__ __forceinline__ void forward_walk(const TileCtx& c, const float* __re
       __syncthreads();
     } else {
       if (ballot(live(s.T, t_min)) == 0) break;
-      stage_batch(records, pairs, s0, ns, srec, sface);
+      if constexpr (normal_mode<SM>())
+        stage_batch(records, pairs, s0, ns, srec, sface, nin->nrm, (int64_t)c.view * nin->M, snrm);
+      else
+        stage_batch(records, pairs, s0, ns, srec, sface);
     }
     for (int h = 0; h < ns; h += kBatch) {
     bool lv = live(s.T, t_min);         // this lane still blends (carried across the visits)
@@ -304,6 +328,12 @@ __device__ __forceinline__ void forward_walk(const TileCtx& c, const float* __re
       s.C1 = fmaf(e.c1, w, s.C1);
       s.C2 = fmaf(e.c2, w, s.C2);
       s.D = fmaf(e.zp, w, s.D);
+      if constexpr (normal_mode<SM>()) {
+        const float4 nf = snrm[j];
+        s.N0 = fmaf(nf.x, w, s.N0);
+        s.N1 = fmaf(nf.y, w, s.N1);
+        s.N2 = fmaf(nf.z, w, s.N2);
+      }
       s.Tb = act ? s.T : s.Tb;
       s.last = act ? (int)(b0 + j) : s.last;
       s.T = s.T * (1.f - a);
@@ -314,9 +344,10 @@ __device__ __forceinline__ void forward_walk(const TileCtx& c, const float* __re
   }
 }
 
-// Per-pixel upstream gradients.
+// Per-pixel upstream gradients (gn: of the world normal map, normal channels).
 struct PixGrad {
   float g0, g1, g2, gd, gt;
+  float gn0 = 0.f, gn1 = 0.f, gn2 = 0.f;
 };
 
 // Back-to-front walk (Sec. 3.3).  T before each face is recovered by division from the
@@ -330,7 +361,8 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
                                               const uint64_t* __restrict__ pairs, float sigma, int last, float Tb,
                                               const PixGrad& pg, float4* srec, uint32_t* sface, int* sint,
                                               acc_t* __restrict__ grad_acc, float* __restrict__ sig_acc,
-                                              float* __restrict__ persp_acc) {
+                                              float* __restrict__ persp_acc, const NormalIn* nin = nullptr,
+                                              float4* snrm = nullptr) {
   const int lane = threadIdx.x & 63;
   // highest list position any pixel of this wave (COOP: of the workgroup) blended
   const int wlast = uniform_int(wave_max_int(last));
@@ -355,7 +387,10 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
       stage_batch_block(records, pairs, (uint32_t)s0, ns, srec, sface);
       __syncthreads();
     } else {
-      stage_batch(records, pairs, (uint32_t)s0, ns, srec, sface);
+      if constexpr (normal_mode<SM>())
+        stage_batch(records, pairs, (uint32_t)s0, ns, srec, sface, nin->nrm, (int64_t)c.view * nin->M, snrm);
+      else
+        stage_batch(records, pairs, (uint32_t)s0, ns, srec, sface);
     }
     for (int h = ((ns - 1) / kBatch) * kBatch; h >= 0; h -= kBatch) {
     const int b0 = s0 + h;
@@ -409,7 +444,13 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
       acc[kGCol + 6] = gc2 * dx; acc[kGCol + 7] = gc2 * dy; acc[kGCol + 8] = gc2;
       // dL/dalpha = T (gC.(c - B) + gD (z - BD) - gT (1 - BA)) = T (P - S); finite on every
       // lane, and only used scaled by I or masked by act
-      const float P = fmaf(pg.g0, c0, fmaf(pg.g1, c1, fmaf(pg.g2, c2, fmaf(pg.gd, zf, -pg.gt))));
+      float P = fmaf(pg.g0, c0, fmaf(pg.g1, c1, fmaf(pg.g2, c2, fmaf(pg.gd, zf, -pg.gt))));
+      float4 nf = make_float4(0.f, 0.f, 0.f, 0.f);
+      if constexpr (normal_mode<SM>()) {
+        // the face's normal is a colour constant over the face: it enters dL/dalpha like one
+        nf = snrm[j];
+        P = fmaf(pg.gn0, nf.x, fmaf(pg.gn1, nf.y, fmaf(pg.gn2, nf.z, P)));
+      }
       const float galpha = Tj * (P - S);
       acc[kGOpa] = galpha * I;
       const float gI = galpha * r[kRecOpa];
@@ -434,6 +475,16 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
         const float ts = wave_sum(gsig);
         if (lane == 0) unsafeAtomicAdd(&sig_acc[sf[j]], ts);
       }
+      if constexpr (normal_mode<SM>()) {
+        // dE/dn_F = sum over the face's pixels of gN alpha T
+        const float t0 = wave_sum(pg.gn0 * w), t1 = wave_sum(pg.gn1 * w), t2 = wave_sum(pg.gn2 * w);
+        if (lane == 0) {
+          float* ga = reinterpret_cast<float*>(nin->gacc + ((int64_t)sf[j] - (int64_t)c.view * nin->M));
+          unsafeAtomicAdd(&ga[0], t0);
+          unsafeAtomicAdd(&ga[1], t1);
+          unsafeAtomicAdd(&ga[2], t2);
+        }
+      }
       if constexpr (persp_mode<SM>()) {
         const float ta = wave_sum(gwa), tb = wave_sum(gwb);
         if (lane == 0) {
@@ -454,16 +505,18 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(ViewTable vt, const float*
                                                       const uint32_t* __restrict__ ranges, float sigma, float t_min,
                                                       float* __restrict__ color, float* __restrict__ depth,
                                                       float* __restrict__ trans, int* __restrict__ n_last,
-                                                      float* __restrict__ t_last, const int* __restrict__ order) {
+                                                      float* __restrict__ t_last, const int* __restrict__ order,
+                                                      NormalIn nin) {
   __shared__ float4 srec[kWaves][kBatch * 6];
   __shared__ uint32_t sface[kWaves][kBatch];
+  __shared__ float4 snrm[kWaves][normal_mode<SM>() ? kBatch : 1];
   const int wv = threadIdx.x >> 6;
   const int tile = tile_of_block_ordered(vt.n_tiles, order);
   if (tile < 0) return;
   TileCtx c;
   tile_ctx(vt, ranges, tile, wv, c);
   FwdState s;
-  forward_walk<SM, false>(c, records, pairs, sigma, t_min, srec[wv], sface[wv], s);
+  forward_walk<SM, false>(c, records, pairs, sigma, t_min, srec[wv], sface[wv], s, &nin, snrm[wv]);
   if (!c.inside) return;
   const int64_t hw = (int64_t)c.vd.width * c.vd.height;
   const int64_t off = (int64_t)c.py * c.vd.width + c.px;
@@ -471,6 +524,12 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(ViewTable vt, const float*
   cb[0] = s.C0;
   cb[hw] = s.C1;
   cb[2 * hw] = s.C2;
+  if constexpr (normal_mode<SM>()) {
+    float* nb = nin.map + 3 * c.vd.pix_off + off;
+    nb[0] = s.N0;
+    nb[hw] = s.N1;
+    nb[2 * hw] = s.N2;
+  }
   depth[c.pix] = s.D;
   if (trans) trans[c.pix] = s.T;
   n_last[c.pix] = s.last;
@@ -485,9 +544,10 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(ViewTable vt, const float*
                                                       const float* __restrict__ gcolor, const float* __restrict__ gdepth,
                                                       const float* __restrict__ gtrans, acc_t* __restrict__ grad_acc,
                                                       float* __restrict__ sig_acc, float* __restrict__ persp_acc,
-                                                      const int* __restrict__ order) {
+                                                      const int* __restrict__ order, NormalIn nin) {
   __shared__ float4 srec[kWaves][kBatch * 6];
   __shared__ uint32_t sface[kWaves][kBatch];
+  __shared__ float4 snrm[kWaves][normal_mode<SM>() ? kBatch : 1];
   const int wv = threadIdx.x >> 6;
   const int tile = tile_of_block_ordered(vt.n_tiles, order);
   if (tile < 0) return;
@@ -508,9 +568,15 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(ViewTable vt, const float*
     pg.g2 = gb[2 * hw];
     pg.gd = gdepth[c.pix];
     pg.gt = gtrans ? gtrans[c.pix] : 0.f;
+    if constexpr (normal_mode<SM>()) {
+      const float* sn = nin.seed + 3 * c.vd.pix_off + (int64_t)c.py * c.vd.width + c.px;
+      pg.gn0 = sn[0];
+      pg.gn1 = sn[hw];
+      pg.gn2 = sn[2 * hw];
+    }
   }
   backward_walk<SM, false>(c, records, pairs, sigma, last, Tb, pg, srec[wv], sface[wv], nullptr, grad_acc, sig_acc,
-                           persp_acc);
+                           persp_acc, &nin, snrm[wv]);
 }
 
 // Fused training kernel: forward walk, L1 seeds of eqs. 8-10 (the D-SSIM term needs whole
@@ -1219,6 +1285,14 @@ static int sigma_mode(const ViewTable& vt, const tsr_params& p) {
     case 8: X(8); break; case 9: X(9); break; case 10: X(10); break; case 11: X(11); break;        \
     default: X(0); break;                                                                          \
   }
+// The separate forward and backward walks with the normal channels.  A normal is constant
+// over its face, so perspective-correct interpolation leaves it unchanged.
+#define TSR_NORMAL_SWITCH(mode, X)                                                                 \
+  switch (mode) {                                                                                  \
+    case 17: X(17); break; case 18: X(18); break; case 19: X(19); break; case 20: X(20); break;    \
+    case 24: X(24); break; case 25: X(25); break; case 26: X(26); break; case 27: X(27); break;    \
+    default: X(16); break;                                                                         \
+  }
 
 static unsigned tile_grid(int n_tiles) { return 8u * (unsigned)((n_tiles + 7) / 8); }
 
@@ -1310,7 +1384,7 @@ hipError_t launch_face_stats(const ViewTable& vt, const tsr_params& p, const WsL
 }
 
 hipError_t launch_forward(const ViewTable& vt, const tsr_params& p, const WsLayout& L, char* ws, float* color,
-                          float* depth, float* trans, hipStream_t st) {
+                          float* depth, float* trans, hipStream_t st, const NormalChannels* nc) {
   const float* records = reinterpret_cast<const float*>(ws + L.records);
   const uint64_t* pairs = reinterpret_cast<const uint64_t*>(ws + L.pairs);
   const uint32_t* ranges = reinterpret_cast<const uint32_t*>(ws + L.ranges);
@@ -1318,8 +1392,14 @@ hipError_t launch_forward(const ViewTable& vt, const tsr_params& p, const WsLayo
   int* n_last = reinterpret_cast<int*>(ws + L.n_last);
   float* t_last = reinterpret_cast<float*>(ws + L.t_last);
   const dim3 grid(tile_grid(vt.n_tiles)), block(kBlock);
-#define TSR_FWD(S) TSR_LAUNCH("blend_fwd", k_blend_fwd<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last, border)
-  TSR_MODE_SWITCH(sigma_mode(vt, p), TSR_FWD)
+  NormalIn nin{};
+  if (nc) nin = NormalIn{reinterpret_cast<const float4*>(nc->face_normal), nullptr, nullptr, nc->map, vt.n_faces};
+#define TSR_FWD(S) TSR_LAUNCH("blend_fwd", k_blend_fwd<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last, border, nin)
+  if (nc) {
+    TSR_NORMAL_SWITCH(sigma_mode(vt, p) | 16, TSR_FWD)
+  } else {
+    TSR_MODE_SWITCH(sigma_mode(vt, p), TSR_FWD)
+  }
 #undef TSR_FWD
   return hipGetLastError();
 }
@@ -1329,7 +1409,7 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
                            const float* gtrans, const float* tcolor, const float* tdepth, float* color,
                            float* depth, float* trans, float* loss, float* grad_pos, float* grad_col,
                            float* grad_opa, float* grad_pose, bool fused_train, const TrainSchedule& sched,
-                           hipStream_t st) {
+                           hipStream_t st, const NormalChannels* nc) {
   const uint32_t* vis_total = reinterpret_cast<const uint32_t*>(ws + L.vis_total);
   const uint32_t* vis_dense = reinterpret_cast<const uint32_t*>(ws + L.vis_dense);
   const uint32_t* counts = reinterpret_cast<const uint32_t*>(ws + L.counts);
@@ -1361,8 +1441,16 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
   if (!fused_train) {
     const dim3 grid(tile_grid(vt.n_tiles));
     const int* border = order;
-#define TSR_BWD(S) TSR_LAUNCH("blend_bwd", k_blend_bwd<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, n_last, t_last, gcolor, gdepth, gtrans, grad_acc, sig_acc, persp_acc, border)
-    TSR_MODE_SWITCH(sm, TSR_BWD)
+    NormalIn nin{};
+    if (nc)
+      nin = NormalIn{reinterpret_cast<const float4*>(nc->face_normal), nc->seed,
+                     reinterpret_cast<float4*>(nc->grad), nullptr, vt.n_faces};
+#define TSR_BWD(S) TSR_LAUNCH("blend_bwd", k_blend_bwd<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, n_last, t_last, gcolor, gdepth, gtrans, grad_acc, sig_acc, persp_acc, border, nin)
+    if (nc) {
+      TSR_NORMAL_SWITCH(sm | 16, TSR_BWD)
+    } else {
+      TSR_MODE_SWITCH(sm, TSR_BWD)
+    }
 #undef TSR_BWD
   } else {
     dim3 grid(tile_grid(vt.n_tiles));

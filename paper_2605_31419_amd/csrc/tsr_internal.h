@@ -159,15 +159,26 @@ hipError_t launch_ws_init(char* ws, hipStream_t st);
 hipError_t launch_bin(const tsr_scene_dev& sc, const float* poses, const ViewTable& vt, const tsr_params& p,
                       const WsLayout& L, char* ws, bool sort, hipStream_t st);
 
+// Normal channels of the separate forward and backward walks (mapping step, Sec. 3.4): each
+// face's world unit normal composited like a colour constant over the face.  face_normal and
+// grad are [M][4] floats (x, y, z, 0) per face, summed over the views in grad (which the
+// caller zero-fills); map (forward) and seed (backward, dE/dN_w) are packed like colour.
+struct NormalChannels {
+  const float* face_normal;
+  float* map;
+  const float* seed;
+  float* grad;
+};
+
 hipError_t launch_forward(const ViewTable& vt, const tsr_params& p, const WsLayout& L, char* ws, float* color,
-                          float* depth, float* trans, hipStream_t st);
+                          float* depth, float* trans, hipStream_t st, const NormalChannels* nc = nullptr);
 
 hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const ViewTable& vt, const tsr_params& p,
                            const WsLayout& L, char* ws, const float* gcolor, const float* gdepth,
                            const float* gtrans, const float* tcolor, const float* tdepth, float* color,
                            float* depth, float* trans, float* loss, float* grad_pos, float* grad_col,
                            float* grad_opa, float* grad_pose, bool fused_train, const TrainSchedule& sched,
-                           hipStream_t st);
+                           hipStream_t st, const NormalChannels* nc = nullptr);
 
 // D-SSIM (Sec. 3.4, eq. 8): output tile of the stencil kernels and the window radius.
 constexpr int kSsimTW = 32;
@@ -224,6 +235,19 @@ hipError_t launch_train_normal(const tsr_scene_dev& sc, const float* poses, cons
                                const WsLayout& L, char* ws, const float* target, float w_norm, float* normal_map,
                                float* loss, float* grad_pos, float* grad_opa, float* grad_pose, bool accumulate,
                                char* scratch, int64_t n_pixels, hipStream_t st);
+
+// The full mapping energy on one binning (photometric, depth and normal terms): scratch
+// layout after the D-SSIM scratch (byte offsets from the start of the whole scratch).
+struct MappingScratch {
+  size_t nrm, gacc, nw, seed, count, acc, total;
+};
+MappingScratch mapping_scratch(size_t ssim_bytes, int64_t n_faces, int64_t n_pixels);
+hipError_t launch_train_mapping(const tsr_scene_dev& sc, const float* poses, const ViewTable& vt, const tsr_params& p,
+                                const WsLayout& L, char* ws, const SsimTable& t, const float* target_color,
+                                const float* target_depth, const float* target_normals, float w_ssim, float w_norm,
+                                float* color, float* depth, float* trans, float* normal_map, float* loss,
+                                float* loss_norm, float* grad_pos, float* grad_col, float* grad_opa,
+                                float* grad_pose, char* scratch, hipStream_t st);
 
 hipError_t launch_pose_step(float* poses, const float* grad_pose, int n_views, float lr_t, float lr_r,
                             hipStream_t st);

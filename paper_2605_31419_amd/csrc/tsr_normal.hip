@@ -213,6 +213,49 @@ __global__ void k_normal_finish(int n_views, const uint32_t* __restrict__ count,
     for (int k = 0; k < 3; ++k) grad_pose[6 * v + 3 + k] += (float)acc[4 * v + 1 + k];
 }
 
+// Face normals of the normal channels: [M] float4 (x, y, z, 0), FP64 arithmetic; a degenerate
+// face gets 0.
+__global__ __launch_bounds__(256) void k_face_normals(const float* __restrict__ pos, int64_t N, int64_t M,
+                                                      float4* __restrict__ nrm) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  double e1[3], e2[3], c[3];
+  load_face(pos, N, m, e1, e2);
+  cross3(e1, e2, c);
+  const double L = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+  const double il = L > 0.0 ? 1.0 / L : 0.0;
+  nrm[m] = make_float4((float)(c[0] * il), (float)(c[1] * il), (float)(c[2] * il), 0.f);
+}
+
+// dE/dn_F of the normal channels (summed over the views by the backward walk) through the
+// normalised cross product, added to the soup's vertex gradients (as k_normal_chain).
+__global__ __launch_bounds__(256) void k_normal_chain_faces(const float* __restrict__ pos, int64_t N, int64_t M,
+                                                            const float4* __restrict__ gacc,
+                                                            float* __restrict__ grad_pos) {
+  const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= M) return;
+  double e1[3], e2[3], c[3];
+  load_face(pos, N, m, e1, e2);
+  cross3(e1, e2, c);
+  const double L = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+  if (!(L > 0.0)) return;
+  const float4 g = gacc[m];
+  const double gn[3] = {(double)g.x, (double)g.y, (double)g.z};
+  double n[3], gc[3], g1[3], g2[3];
+  for (int ax = 0; ax < 3; ++ax) n[ax] = c[ax] / L;
+  const double dn = n[0] * gn[0] + n[1] * gn[1] + n[2] * gn[2];
+  for (int ax = 0; ax < 3; ++ax) gc[ax] = (gn[ax] - n[ax] * dn) / L;
+  cross3(e2, gc, g1);
+  cross3(gc, e1, g2);
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    float* gp = grad_pos + ax * N + 3 * m;
+    gp[0] = (float)((double)gp[0] - g1[ax] - g2[ax]);
+    gp[1] = (float)((double)gp[1] + g1[ax]);
+    gp[2] = (float)((double)gp[2] + g2[ax]);
+  }
+}
+
 __global__ void k_zero_words(uint32_t* __restrict__ p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0u;
 }
@@ -309,6 +352,67 @@ hipError_t launch_train_normal(const tsr_scene_dev& sc, const float* poses, cons
     if (out_pose)
       TSR_LAUNCH("add_grads", k_add_f32, dim3(1), dim3(256), 0, st, out_pose, grad_pose, (int64_t)6 * vt.n_views);
   }
+  return hipGetLastError();
+}
+
+MappingScratch mapping_scratch(size_t ssim_bytes, int64_t n_faces, int64_t n_pixels) {
+  auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+  MappingScratch z;
+  z.nrm = up(ssim_bytes);
+  z.gacc = up(z.nrm + 16 * (size_t)n_faces);
+  z.nw = up(z.gacc + 16 * (size_t)n_faces);
+  z.seed = up(z.nw + sizeof(float) * 3 * (size_t)n_pixels);
+  z.count = up(z.seed + sizeof(float) * 3 * (size_t)n_pixels);
+  z.acc = up(z.count + sizeof(uint32_t) * TSR_MAX_VIEWS);
+  z.total = up(z.acc + sizeof(double) * 4 * TSR_MAX_VIEWS);
+  return z;
+}
+
+// The whole mapping energy on the binning in `ws` (made with the scene's colours): one
+// forward that also composites the world normal map, the photometric / depth seeds and the
+// normal seeds, one backward that takes both, then the normal-to-vertex chain and the normal
+// loss's rotation term of the pose gradient.
+hipError_t launch_train_mapping(const tsr_scene_dev& sc, const float* poses, const ViewTable& vt, const tsr_params& p,
+                                const WsLayout& L, char* ws, const SsimTable& t, const float* target_color,
+                                const float* target_depth, const float* target_normals, float w_ssim, float w_norm,
+                                float* color, float* depth, float* trans, float* normal_map, float* loss,
+                                float* loss_norm, float* grad_pos, float* grad_col, float* grad_opa,
+                                float* grad_pose, char* scratch, hipStream_t st) {
+  const MappingScratch z = mapping_scratch(ssim_scratch_bytes(t), sc.n_faces, t.n_pixels);
+  float4* nrm = reinterpret_cast<float4*>(scratch + z.nrm);
+  float4* gacc = reinterpret_cast<float4*>(scratch + z.gacc);
+  float* nw = reinterpret_cast<float*>(scratch + z.nw);
+  float* seed = reinterpret_cast<float*>(scratch + z.seed);
+  uint32_t* count = reinterpret_cast<uint32_t*>(scratch + z.count);
+  double* acc = reinterpret_cast<double*>(scratch + z.acc);
+  const int64_t M = sc.n_faces, N = sc.n_vertices;
+  const unsigned fb = (unsigned)std::max<int64_t>((M + 255) / 256, 1);
+  // the per-face normal gradients, the valid counts and the FP64 sums start at zero
+  TSR_LAUNCH("zero_words", k_zero_words, dim3(std::min<unsigned>(fb, 2048u)), dim3(256), 0, st,
+             reinterpret_cast<uint32_t*>(gacc), 4 * M);
+  TSR_LAUNCH("zero_words", k_zero_words, dim3(1), dim3(256), 0, st, count,
+             (int64_t)((z.total - z.count) / sizeof(uint32_t)));
+  if (M > 0) TSR_LAUNCH("face_normals", k_face_normals, dim3(fb), dim3(256), 0, st, sc.pos, N, M, nrm);
+  const NormalChannels fc{reinterpret_cast<const float*>(nrm), nw, nullptr, nullptr};
+  hipError_t e = launch_forward(vt, p, L, ws, color, depth, trans, st, &fc);
+  if (e != hipSuccess) return e;
+  float *gc = nullptr, *gd = nullptr;
+  e = launch_photo_seeds(t, color, target_color, depth, target_depth, w_ssim, p.w_color, p.w_depth, loss, scratch,
+                         &gc, &gd, st);
+  if (e != hipSuccess) return e;
+  const dim3 pg(kNormBlocksPerView, vt.n_views);
+  TSR_LAUNCH("count_valid", k_count_valid, pg, dim3(256), 0, st, vt, target_normals, count);
+  TSR_LAUNCH("normal_seeds", k_normal_seeds, pg, dim3(256), 0, st, vt, poses, nw, target_normals, count, w_norm,
+             normal_map, seed, acc);
+  const NormalChannels bc{reinterpret_cast<const float*>(nrm), nullptr, seed, reinterpret_cast<float*>(gacc)};
+  TrainSchedule sched{0, 0, 0};
+  e = launch_backward(sc, poses, vt, p, L, ws, gc, gd, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                      grad_pos, grad_col, grad_opa, grad_pose, false, sched, st, &bc);
+  if (e != hipSuccess) return e;
+  if (grad_pos && M > 0)
+    TSR_LAUNCH("normal_chain", k_normal_chain_faces, dim3(fb), dim3(256), 0, st, sc.pos, N, M, gacc, grad_pos);
+  TSR_LAUNCH("normal_finish", k_normal_finish, dim3(1), dim3(64), 0, st, vt.n_views, count, acc, w_norm, loss_norm,
+             grad_pose);
   return hipGetLastError();
 }
 

@@ -296,6 +296,37 @@ class Rasterizer:
               "tsr_render_train_normal")
         return gp, go, gpose
 
+    def mapping_scratch(self) -> torch.Tensor:
+        """Scratch of the one-binning mapping step (allocated on first use)."""
+        if getattr(self, "_mscratch", None) is None:
+            nb = C.c_size_t()
+            check(self.lib.tsr_mapping_scratch_size(C.byref(self._cscene), self._cintr, self.n_views, C.byref(nb)),
+                  "tsr_mapping_scratch_size")
+            self._mscratch = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        return self._mscratch
+
+    def train_mapping(self, poses: torch.Tensor, target_color, target_depth, target_normals, w_ssim: float = 0.2,
+                      w_norm: float = 0.05, color=None, depth=None, trans=None, normal_map=None, loss=None,
+                      loss_norm=None, out=None, grad_face_sigma=None, stream=None):
+        """The photometric, depth and normal terms of the mapping energy on the binning held in
+        the workspace (``tsr_render_train_mapping``: one forward that also composites the normal
+        map, one backward that takes all seeds).  Returns (grad_pos, grad_col, grad_opa,
+        grad_pose) of the sum of both per-view losses, overwriting ``out``."""
+        self.generation += 1
+        P = self.total_pixels
+        color = color if color is not None else torch.empty(3 * P, device=self.device)
+        depth = depth if depth is not None else torch.empty(P, device=self.device)
+        gp, gc, go, gpose = out if out is not None else self.grad_buffers()
+        self._sigma_out(grad_face_sigma)
+        sc = self.mapping_scratch()
+        check(self.lib.tsr_render_train_mapping(*self._args(poses), _ptr(target_color), _ptr(target_depth),
+                                                _ptr(target_normals), float(w_ssim), float(w_norm), _ptr(color),
+                                                _ptr(depth), _ptr(trans), _ptr(normal_map), _ptr(loss),
+                                                _ptr(loss_norm), _ptr(gp), _ptr(gc), _ptr(go), _ptr(gpose), _ptr(sc),
+                                                C.c_size_t(sc.numel()), _stream(stream)),
+              "tsr_render_train_mapping")
+        return gp, gc, go, gpose
+
     def pose_step(self, poses: torch.Tensor, grad_pose: torch.Tensor, lr_trans: float, lr_rot: float,
                   stream=None) -> None:
         check(self.lib.tsr_pose_step(_ptr(poses), _ptr(grad_pose), self.n_views, lr_trans, lr_rot, _stream(stream)),

@@ -10,8 +10,11 @@ step uses the full loss with the D-SSIM term (``tsr_render_train_photometric``; 
 backward are then separate passes and the tile schedule is the default one).  ``w_equi`` adds
 the equilateral regulariser (eq. 14) and ``w_norm`` the normal loss against per-view target
 normals, both accumulated on the device into the same gradient buffers, giving the mapping
-energy E_pho + lambda_dep E_dep + lambda_norm E_norm + lambda_equi E_equi (the normal loss runs
-on a second workspace, since it bins the soup with its face normals as colours).
+energy E_pho + lambda_dep E_dep + lambda_norm E_norm + lambda_equi E_equi.  With the normal
+loss the step is ``tsr_render_train_mapping``: one binning, one forward that composites the
+face normals as three more channels, one backward that takes the colour, depth and normal
+seeds.  ``fused_mapping=False`` runs the normal loss as its own step instead (a second
+workspace binned with the face normals as colours), the slower form kept for comparison.
 """
 from __future__ import annotations
 
@@ -25,7 +28,7 @@ from . import autotune, raster
 class MappingWindow:
     def __init__(self, scene: raster.DeviceScene, intrs: Sequence, params: Optional[raster.Params] = None,
                  schedule=None, table: Optional[str] = None, w_ssim: float = 0.0, w_equi: float = 0.0,
-                 w_norm: float = 0.0):
+                 w_norm: float = 0.0, fused_mapping: bool = True):
         self.rast = raster.Rasterizer(scene, intrs, params or raster.Params())
         self.n_views = len(intrs)
         self.intrs = list(intrs)
@@ -41,7 +44,10 @@ class MappingWindow:
         self.w_norm = float(w_norm)
         self.equi_loss = torch.zeros(1, device="cuda")
         self.norm_loss = torch.zeros(self.n_views, device="cuda")
-        self.nrast = raster.Rasterizer(scene, intrs, params or raster.Params()) if self.w_norm > 0 else None
+        self.fused_mapping = bool(fused_mapping)
+        self.normal_map: Optional[torch.Tensor] = None
+        self.nrast = (raster.Rasterizer(scene, intrs, params or raster.Params())
+                      if self.w_norm > 0 and not self.fused_mapping else None)
 
     def prepare(self, poses: torch.Tensor, slack: float = 1.5) -> int:
         """Size the workspace and pick the schedule (table lookup) for these poses."""
@@ -61,6 +67,15 @@ class MappingWindow:
              check_capacity: bool = False, target_normals: Optional[torch.Tensor] = None):
         """One window iteration; returns (grad_pos, grad_col, grad_opa, grad_pose[V*6])."""
         self.rast.bin_and_sort(poses, check_capacity=check_capacity)
+        if self.w_norm > 0 and self.fused_mapping and target_normals is not None:
+            self.rast.train_mapping(poses, target_color, target_depth, target_normals, w_ssim=self.w_ssim,
+                                    w_norm=self.w_norm, color=self.color, depth=self.depth,
+                                    normal_map=self.normal_map, loss=self.loss, loss_norm=self.norm_loss,
+                                    out=self.grads)
+            if self.w_equi > 0:
+                raster.equilateral(self.rast.scene, weight=self.w_equi, grad=self.grads[0], accumulate=True,
+                                   loss=self.equi_loss)
+            return self.grads
         if self.w_ssim > 0:
             self.rast.train_photometric(poses, target_color, target_depth, w_ssim=self.w_ssim,
                                         color=self.color, depth=self.depth, loss=self.loss, out=self.grads)

@@ -192,6 +192,30 @@ def test_normal_entry_points_validation():
                                        None) == _lib.TSR_EWORKSPACE
 
 
+def test_mapping_step_validation():
+    """The one-binning mapping step: soups only, all three targets, colour and depth outputs,
+    and a scratch of at least the D-SSIM scratch + 32 bytes per face + 24 per pixel."""
+    lib = _lib.load()
+    p = C.c_void_p(256)
+    big = C.c_size_t(1 << 30)
+    sc, intr = _scene(10), _intr((64, 48))
+    need, ssim = C.c_size_t(), C.c_size_t()
+    assert lib.tsr_mapping_scratch_size(C.byref(sc), intr, 1, C.byref(need)) == 0
+    assert lib.tsr_dssim_scratch_size(intr, 1, C.byref(ssim)) == 0
+    assert need.value >= ssim.value + 32 * 10 + 24 * 64 * 48
+    assert lib.tsr_mapping_scratch_size(C.byref(sc), intr, 0, C.byref(need)) == _lib.TSR_EINVAL
+
+    def call(scene=sc, tn=p, color=p, scratch_bytes=need):
+        return lib.tsr_render_train_mapping(C.byref(scene), p, intr, 1, C.byref(_params()), p, big, p, p, tn, 0.2,
+                                            0.05, color, p, None, None, None, None, None, None, None, None, p,
+                                            scratch_bytes, None)
+    mesh = _lib.TsrScene(1, 1, 1, 1, 30, 10)
+    assert call(scene=mesh) == _lib.TSR_EINVAL
+    assert call(tn=None) == _lib.TSR_EINVAL
+    assert call(color=None) == _lib.TSR_EINVAL
+    assert call(scratch_bytes=C.c_size_t(need.value - 1)) == _lib.TSR_EWORKSPACE
+
+
 def test_equilateral_noalloc_validation():
     """The allocation-free E_equi variant validates like tsr_equilateral and refuses more than
     TSR_EQUI_NOALLOC_MAX_FACES faces before any device call."""

@@ -105,3 +105,25 @@ def test_gradient_matches_central_differences(seed):
             return sc, left_perturb(pose, t)
         check(gpose[k], fd(mkp))
     assert checked >= 0.8 * (checked + rejected), (checked, rejected)
+
+
+def test_per_face_exponents_reach_the_normal_map():
+    """Every face at exponent 2 with the global exponent 1 gives the normal map, loss and
+    gradients of the global exponent 2 (the normal map blends with the faces' own windows);
+    exponents that differ per face change the map."""
+    sc, intr = tiny_scene(5, n_faces=10, w=28, h=22, f=26.0)
+    g = np.random.default_rng(5)
+    pose = left_perturb(IDENTITY, g.normal(scale=0.03, size=6))
+    P = intr.width * intr.height
+    nb = g.normal(size=(3, P))
+    nb /= np.linalg.norm(nb, axis=0)
+    valid = g.uniform(size=P) < 0.8
+    two = S.Scene(sc.pos, sc.col, sc.opa, None, np.full(sc.n_faces, 2.0))
+    np.testing.assert_allclose(NR.render_normals(two, pose, intr, sigma=1.0),
+                               NR.render_normals(sc, pose, intr, sigma=2.0), atol=1e-14)
+    assert abs(NR.e_norm(two, pose, intr, nb, valid, sigma=1.0) - NR.e_norm(sc, pose, intr, nb, valid, sigma=2.0)) < 1e-14
+    for a, b in zip(NR.e_norm_grad(two, pose, intr, nb, valid, sigma=1.0),
+                    NR.e_norm_grad(sc, pose, intr, nb, valid, sigma=2.0)):
+        np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-14)
+    mixed = S.Scene(sc.pos, sc.col, sc.opa, None, g.uniform(0.5, 2.5, sc.n_faces))
+    assert np.abs(NR.render_normals(mixed, pose, intr) - NR.render_normals(sc, pose, intr)).max() > 1e-3
