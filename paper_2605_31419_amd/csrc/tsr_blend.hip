@@ -183,6 +183,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 static_assert(kSpan % kBatch == 0 && kSpan >= kBatch, "a staged span is walked as whole 64-face batches");
 static_assert(kSpan * (6 * sizeof(float4) + sizeof(uint32_t)) <= 48 * 1024, "a staged span fits the LDS budget");
 static_assert(kWaves * kWave == kBlock && kWaves == 4, "one wave per 8x8 quadrant of a 16x16 tile");
+static_assert(kGradDwords == 20, "normal channels: record terms in slots 0-19 of the 24-value wave sum");
 __device__ __forceinline__ void stage_batch_block(const float* __restrict__ records, const uint64_t* __restrict__ pairs,
                                                   uint32_t b0, int n, float4* srec, uint32_t* sface) {
   for (int i = threadIdx.x; i < n * 6; i += kBlock) {
@@ -374,7 +375,11 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
     __syncthreads();
     top = uniform_int(sint[0]);
   }
-  const int k_out = wave_sum20_slot();
+  // With terms beyond the record's 20 (normal channels: 3 in slots 20-22; perspective without
+  // them: the W plane's 2 slopes in slots 20-21; per-face exponent: slot 23) all go through one
+  // 24-value transposed sum.
+  constexpr bool kWide = normal_mode<SM>() || persp_mode<SM>() || exp_mode<SM>() == 4;
+  const int k_out = kWide ? wave_sum24_slot() : wave_sum20_slot();
   float Tcur = Tb;
   float S = 0.f;
   const float dxb = (float)c.px, dyb = (float)c.py;
@@ -423,7 +428,7 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
       const float zf = e.zp;
       const float c0 = e.c0, c1 = e.c1, c2 = e.c2;
       const float w = alpha * Tj;
-      float acc[kGradDwords];
+      float acc[kWide ? 24 : kGradDwords];
       // colour plane gradients: dL/dc_ch(p) = gC_ch alpha T, and c_ch = P dx + Q dy + R
       float gc0 = pg.g0 * w, gc1 = pg.g1 * w, gc2 = pg.g2 * w;
       float gwa = 0.f, gwb = 0.f;          // perspective-correct: the W plane's slopes
@@ -467,30 +472,43 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
       }
       S = fmaf(alpha, P, om * S);
       if (ballot(act) == 0) continue;
-      const float tot = wave_sum20(acc);
-      if (k_out >= 0) unsafeAtomicAdd(&grad_acc[(size_t)sf[j] * kGradDwords + k_out], (acc_t)tot);
-      if constexpr (exp_mode<SM>() == 4) {
-        // the face's own exponent: dI/dsigma = I ln(rho) for 0 < rho < 1 (act implies rho > 0)
-        const float gsig = (act && e.rho < 1.f) ? gI * I * (0.69314718055994531f * log2f(e.rho)) : 0.f;
-        const float ts = wave_sum(gsig);
-        if (lane == 0) unsafeAtomicAdd(&sig_acc[sf[j]], ts);
-      }
-      if constexpr (normal_mode<SM>()) {
-        // dE/dn_F = sum over the face's pixels of gN alpha T
-        const float t0 = wave_sum(pg.gn0 * w), t1 = wave_sum(pg.gn1 * w), t2 = wave_sum(pg.gn2 * w);
-        if (lane == 0) {
+      // the face's own exponent: dI/dsigma = I ln(rho) for 0 < rho < 1 (act implies rho > 0)
+      float gsig = 0.f;
+      if constexpr (exp_mode<SM>() == 4)
+        gsig = (act && e.rho < 1.f) ? gI * I * (0.69314718055994531f * log2f(e.rho)) : 0.f;
+      if constexpr (kWide) {
+        if constexpr (normal_mode<SM>()) {
+          // dE/dn_F = sum over the face's pixels of gN alpha T
+          acc[20] = pg.gn0 * w;
+          acc[21] = pg.gn1 * w;
+          acc[22] = pg.gn2 * w;
+        } else {
+          acc[20] = gwa;
+          acc[21] = gwb;
+          acc[22] = 0.f;
+        }
+        acc[23] = gsig;
+        const float tot = wave_sum24(acc);
+        if (k_out >= 0 && k_out < kGradDwords) {
+          unsafeAtomicAdd(&grad_acc[(size_t)sf[j] * kGradDwords + k_out], (acc_t)tot);
+        } else if (normal_mode<SM>() && k_out >= kGradDwords && k_out < 23) {
           float* ga = reinterpret_cast<float*>(nin->gacc + ((int64_t)sf[j] - (int64_t)c.view * nin->M));
-          unsafeAtomicAdd(&ga[0], t0);
-          unsafeAtomicAdd(&ga[1], t1);
-          unsafeAtomicAdd(&ga[2], t2);
+          unsafeAtomicAdd(&ga[k_out - kGradDwords], tot);
+        } else if (!normal_mode<SM>() && persp_mode<SM>() && (k_out == 20 || k_out == 21)) {
+          unsafeAtomicAdd(&persp_acc[2 * (size_t)sf[j] + (k_out - 20)], tot);
+        } else if (exp_mode<SM>() == 4 && k_out == 23) {
+          unsafeAtomicAdd(&sig_acc[sf[j]], tot);
         }
-      }
-      if constexpr (persp_mode<SM>()) {
-        const float ta = wave_sum(gwa), tb = wave_sum(gwb);
-        if (lane == 0) {
-          unsafeAtomicAdd(&persp_acc[2 * (size_t)sf[j]], ta);
-          unsafeAtomicAdd(&persp_acc[2 * (size_t)sf[j] + 1], tb);
+        if constexpr (normal_mode<SM>() && persp_mode<SM>()) {
+          const float ta = wave_sum(gwa), tb = wave_sum(gwb);
+          if (lane == 0) {
+            unsafeAtomicAdd(&persp_acc[2 * (size_t)sf[j]], ta);
+            unsafeAtomicAdd(&persp_acc[2 * (size_t)sf[j] + 1], tb);
+          }
         }
+      } else {
+        const float tot = wave_sum20(acc);
+        if (k_out >= 0) unsafeAtomicAdd(&grad_acc[(size_t)sf[j] * kGradDwords + k_out], (acc_t)tot);
       }
     }
     }

@@ -161,6 +161,50 @@ __device__ __forceinline__ float wave_sum20(const float* v) {
   return out;
 }
 
+// The same butterfly over 24 values: the third permlane16 pair (values 16..23) is split by bit 3
+// like the first two and then summed over bits 2..0; its totals are read on lanes x = 1 (bit 3
+// clear) and x = 9 (bit 3 set) of each row.  Result: value wave_sum24_slot() on the 24 lanes
+// where that is not -1.  Every lane must be active.
+__device__ __forceinline__ int wave_sum24_slot() {
+  const int r = (threadIdx.x & 63) >> 4, x = threadIdx.x & 15;
+  const int rmap = r == 0 ? 0 : (r == 1 ? 2 : (r == 2 ? 1 : 3));
+  const int b3 = (x >> 3) & 1;
+  if ((x & 3) == 0) return 4 * (2 * ((x >> 2) & 1) + b3) + rmap;
+  return (x & 7) == 1 ? 16 + 4 * b3 + rmap : -1;
+}
+
+__device__ __forceinline__ float wave_sum24(const float* v) {
+#pragma clang fp contract(off)
+  float s[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) {
+    const auto p = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[2 * i]), __float_as_uint(v[2 * i + 1]), false,
+                                                    false);
+    s[i] = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+  }
+  float t[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(s[2 * j]), __float_as_uint(s[2 * j + 1]), false,
+                                                    false);
+    t[j] = __uint_as_float(p[0]) + __uint_as_float(p[1]);
+  }
+  const int x = threadIdx.x & 15;
+  const bool b2 = x & 4, b3 = x & 8;
+  const float a0 = pair_level<0x128>(t[0], t[1], b3);                  // row_ror:8
+  const float a1 = pair_level<0x128>(t[2], t[3], b3);
+  float a2 = pair_level<0x128>(t[4], t[5], b3);
+  float bb = pair_level<0x141>(a0, a1, b2);                            // row_half_mirror
+  a2 += TSR_DPP(a2, 0x141, 0xF, 0xF);
+  bb += TSR_DPP(bb, 0x4E, 0xF, 0xF);                                   // quad_perm [2,3,0,1]
+  a2 += TSR_DPP(a2, 0x4E, 0xF, 0xF);
+  bb += TSR_DPP(bb, 0xB1, 0xF, 0xF);                                   // quad_perm [1,0,3,2]
+  a2 += TSR_DPP(a2, 0xB1, 0xF, 0xF);
+  float out = (x & 3) == 0 ? bb : a2;
+  asm volatile("" : "+v"(out));
+  return out;
+}
+
 __device__ __forceinline__ int wave_max_int(int v) {
   for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
   return v;
