@@ -252,7 +252,7 @@ TSR_API int tsr_pose_tau_grad(const float *tau, const float *grad_pose, int n_vi
  * weight * dloss[v]/dcolor (accumulate = 0) or has it added (accumulate != 0), so the L1
  * colour gradient of eq. 8 and this term can share one buffer for tsr_render_backward.
  * scratch: device, 256-byte aligned, at least tsr_dssim_scratch_size bytes (52 bytes per
- * pixel plus 16 per 32 x 16 tile and channel), owned by the caller; its contents need no
+ * pixel plus 16 per 32 x 32 tile and channel), owned by the caller; its contents need no
  * clearing.  Enqueued on `stream`; no allocation, no synchronisation (capturable).
  * Errors: TSR_EINVAL for NULL inputs, both outputs NULL, or a view size outside
  * (0, 16384]; TSR_EWORKSPACE for a short scratch. */

@@ -182,7 +182,7 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
 
 // D-SSIM (Sec. 3.4, eq. 8): output tile of the stencil kernels and the window radius.
 constexpr int kSsimTW = 32;
-constexpr int kSsimTH = 16;
+constexpr int kSsimTH = 32;
 constexpr int kSsimR = 5;               // 11 x 11 window
 
 // Per-view geometry of the D-SSIM kernels (a kernel argument).  Workgroup b works on view v

@@ -4,12 +4,16 @@
 // (s_x^2 + s_y^2 + C2)) over an 11 x 11 Gaussian window (standard deviation 1.5, weights
 // summing to 1), pixels outside the image counting as 0, s^2 = E[x^2] - mu^2.
 //
-// Two stencil passes, each a 32 x 16 output tile per workgroup with its 5-pixel halo staged in
-// LDS and the window applied as two 11-tap passes (the Gaussian window is separable):
+// Two stencil passes, each a 32 x 32 output tile per workgroup with its 5-pixel halo staged in
+// LDS and the window applied as two 11-tap passes (the Gaussian window is separable).  Both
+// passes are register-blocked: in the horizontal pass a thread reads 14 staged values of a row
+// (four 16-byte LDS reads) and produces 4 adjacent columns; in the vertical pass it reads 14
+// rows of one column and produces 4 adjacent rows.  Every output sums its 11 taps in the same
+// order as a one-output-per-thread loop would.
 //   k_ssim_stats: the five local moments -> SSIM(p) (summed per workgroup) and the three maps
 //     A = dS/dmu_x - 2 mu_x B - mu_y C, B = dS/ds_xx, C = dS/ds_xy;
-//   k_ssim_grad: dL/dx(p) = -(1/N) (W*A + 2 x(p) W*B + y(p) W*C)(p), W* the same window sum
-//     (the window is symmetric), N = 3 W H of the view;
+//   k_ssim_grad / k_photo_seeds: dL/dx(p) = -(1/N) (W*A + 2 x(p) W*B + y(p) W*C)(p), W* the
+//     same window sum (the window is symmetric), N = 3 W H of the view;
 // then k_ssim_loss adds the workgroups' sums of each view.
 #include "tsr_device.h"
 #include "tsr_internal.h"
@@ -21,8 +25,15 @@ namespace tsr {
 
 constexpr float kSsimC1 = 0.01f * 0.01f;
 constexpr float kSsimC2 = 0.03f * 0.03f;
+constexpr int kSsimTaps = 2 * kSsimR + 1;
 constexpr int kSsimIW = kSsimTW + 2 * kSsimR;   // staged columns
 constexpr int kSsimIH = kSsimTH + 2 * kSsimR;   // staged rows
+constexpr int kSsimLW = 44;                     // LDS row stride of the staged values (16-byte rows)
+constexpr int kSsimBlk = 4;                     // outputs per thread in each pass
+constexpr int kSsimSpan = kSsimBlk + 2 * kSsimR;   // inputs a thread reads per pass (14)
+static_assert(kSsimTW == 32 && kSsimTH == 32, "a 256-thread workgroup: 32 columns x 8 groups of 4 rows");
+static_assert(kSsimLW % 4 == 0 && kSsimLW >= kSsimIW && (kSsimTW - kSsimBlk) + 16 <= kSsimLW,
+              "the horizontal pass reads four aligned float4 per row inside the staged row");
 
 struct SsimTile {
   int v, ch, x0, y0, W, H;
@@ -47,82 +58,143 @@ __device__ __forceinline__ SsimTile ssim_tile(const SsimTable& t, int b) {
   return s;
 }
 
-// Stages the tile's window of Q images (zero outside the image), applies the horizontal
-// 11-tap pass into hs[q][row][col] (rows of the whole staged height, columns of the tile).
+// Stages the tile's window of Q images (zero outside the image) into in[q][row][col]: every
+// load of the thread is issued before the first LDS store, so their latencies overlap.
+constexpr int kSsimStageIters = (kSsimIH * kSsimIW + 255) / 256;
+
 template <int Q>
-__device__ __forceinline__ void ssim_stage_h(const SsimTile& s, const float* const* src, const float* g,
-                                             float (*in)[kSsimIH][kSsimIW], float (*hs)[kSsimIH][kSsimTW]) {
-  for (int i = threadIdx.x; i < kSsimIH * kSsimIW; i += blockDim.x) {
+__device__ __forceinline__ void ssim_stage(const SsimTile& s, const float* const* src, float (*in)[kSsimIH][kSsimLW]) {
+  float v[kSsimStageIters][Q];
+#pragma unroll
+  for (int it = 0; it < kSsimStageIters; ++it) {
+    const int i = threadIdx.x + 256 * it;
     const int r = i / kSsimIW, c = i - r * kSsimIW;
     const int gx = s.x0 - kSsimR + c, gy = s.y0 - kSsimR + r;
-    const bool in_img = gx >= 0 && gx < s.W && gy >= 0 && gy < s.H;
+    const bool ld = i < kSsimIH * kSsimIW && gx >= 0 && gx < s.W && gy >= 0 && gy < s.H;
     const int64_t e = s.plane + (int64_t)gy * s.W + gx;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) in[q][r][c] = in_img ? src[q][e] : 0.f;
+    for (int q = 0; q < Q; ++q) v[it][q] = ld ? src[q][e] : 0.f;
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < kSsimIH * kSsimTW; i += blockDim.x) {
-    const int r = i / kSsimTW, c = i - r * kSsimTW;
-    float acc[Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) acc[q] = 0.f;
+  for (int it = 0; it < kSsimStageIters; ++it) {
+    const int i = threadIdx.x + 256 * it;
+    const int r = i / kSsimIW, c = i - r * kSsimIW;
+    if (i < kSsimIH * kSsimIW) {
 #pragma unroll
-    for (int k = 0; k < 2 * kSsimR + 1; ++k) {
-#pragma unroll
-      for (int q = 0; q < Q; ++q) acc[q] = fmaf(g[k], in[q][r][c + k], acc[q]);
+      for (int q = 0; q < Q; ++q) in[q][r][c] = v[it][q];
     }
-#pragma unroll
-    for (int q = 0; q < Q; ++q) hs[q][r][c] = acc[q];
   }
-  __syncthreads();
+}
+
+// The kSsimSpan staged values of row r from column c0 (a multiple of 4) in four 16-byte reads.
+__device__ __forceinline__ void ssim_row_span(const float* row, int c0, float v[16]) {
+  const float4* p = reinterpret_cast<const float4*>(row + c0);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float4 a = p[j];
+    v[4 * j] = a.x; v[4 * j + 1] = a.y; v[4 * j + 2] = a.z; v[4 * j + 3] = a.w;
+  }
+}
+
+// Horizontal 11-tap pass of Q staged images into hs[q][row][col] (rows of the whole staged
+// height, the tile's columns), 4 adjacent columns per task.
+template <int Q>
+__device__ __forceinline__ void ssim_hpass(const float* g, float (*in)[kSsimIH][kSsimLW],
+                                           float (*hs)[kSsimIH][kSsimTW]) {
+  constexpr int kGroups = kSsimTW / kSsimBlk;
+  for (int task = threadIdx.x; task < kSsimIH * kGroups; task += blockDim.x) {
+    const int r = task / kGroups, c0 = (task - r * kGroups) * kSsimBlk;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      float v[16];
+      ssim_row_span(&in[q][r][0], c0, v);
+#pragma unroll
+      for (int o = 0; o < kSsimBlk; ++o) {
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < kSsimTaps; ++k) acc = fmaf(g[k], v[o + k], acc);
+        hs[q][r][c0 + o] = acc;
+      }
+    }
+  }
+}
+
+// Vertical 11-tap pass of Q horizontal sums at column c for rows r0 .. r0 + 3 of the tile.
+template <int Q>
+__device__ __forceinline__ void ssim_vpass(const float* g, float (*hs)[kSsimIH][kSsimTW], int r0, int c,
+                                           float m[kSsimBlk][Q]) {
+#pragma unroll
+  for (int o = 0; o < kSsimBlk; ++o)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) m[o][q] = 0.f;
+#pragma unroll
+  for (int k = 0; k < kSsimSpan; ++k) {
+    float v[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) v[q] = hs[q][r0 + k][c];
+#pragma unroll
+    for (int o = 0; o < kSsimBlk; ++o) {
+      const int kk = k - o;              // tap of output row r0 + o
+      if (kk >= 0 && kk < kSsimTaps) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) m[o][q] = fmaf(g[kk], v[q], m[o][q]);
+      }
+    }
+  }
 }
 
 __global__ __launch_bounds__(256) void k_ssim_stats(const float* __restrict__ color, const float* __restrict__ target,
                                                     SsimTable t, float* __restrict__ abc, int64_t n3,
                                                     double* __restrict__ partial) {
-  __shared__ float in[2][kSsimIH][kSsimIW];
+  __shared__ __align__(16) float in[2][kSsimIH][kSsimLW];
   __shared__ float hs[5][kSsimIH][kSsimTW];
   __shared__ double red[4];
   const SsimTile s = ssim_tile(t, blockIdx.x);
-  // stage x and y, then the horizontal pass of x, y, x^2, y^2, x y
-  for (int i = threadIdx.x; i < kSsimIH * kSsimIW; i += blockDim.x) {
-    const int r = i / kSsimIW, c = i - r * kSsimIW;
-    const int gx = s.x0 - kSsimR + c, gy = s.y0 - kSsimR + r;
-    const bool in_img = gx >= 0 && gx < s.W && gy >= 0 && gy < s.H;
-    const int64_t e = s.plane + (int64_t)gy * s.W + gx;
-    in[0][r][c] = in_img ? color[e] : 0.f;
-    in[1][r][c] = in_img ? target[e] : 0.f;
-  }
+  const float* src[2] = {color, target};
+  ssim_stage<2>(s, src, in);
   __syncthreads();
-  for (int i = threadIdx.x; i < kSsimIH * kSsimTW; i += blockDim.x) {
-    const int r = i / kSsimTW, c = i - r * kSsimTW;
-    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f;
+  // horizontal pass of x, y, x^2, y^2, x y: the squares and product formed once per staged value
+  constexpr int kGroups = kSsimTW / kSsimBlk;
+  for (int task = threadIdx.x; task < kSsimIH * kGroups; task += blockDim.x) {
+    const int r = task / kGroups, c0 = (task - r * kGroups) * kSsimBlk;
+    float x[16], y[16];
+    ssim_row_span(&in[0][r][0], c0, x);
+    ssim_row_span(&in[1][r][0], c0, y);
+    float xx[kSsimSpan], yy[kSsimSpan], xy[kSsimSpan];
 #pragma unroll
-    for (int k = 0; k < 2 * kSsimR + 1; ++k) {
-      const float x = in[0][r][c + k], y = in[1][r][c + k], w = t.g[k];
-      a0 = fmaf(w, x, a0);
-      a1 = fmaf(w, y, a1);
-      a2 = fmaf(w, x * x, a2);
-      a3 = fmaf(w, y * y, a3);
-      a4 = fmaf(w, x * y, a4);
+    for (int k = 0; k < kSsimSpan; ++k) {
+      xx[k] = x[k] * x[k];
+      yy[k] = y[k] * y[k];
+      xy[k] = x[k] * y[k];
     }
-    hs[0][r][c] = a0; hs[1][r][c] = a1; hs[2][r][c] = a2; hs[3][r][c] = a3; hs[4][r][c] = a4;
+#pragma unroll
+    for (int o = 0; o < kSsimBlk; ++o) {
+      float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f;
+#pragma unroll
+      for (int k = 0; k < kSsimTaps; ++k) {
+        const float w = t.g[k];
+        a0 = fmaf(w, x[o + k], a0);
+        a1 = fmaf(w, y[o + k], a1);
+        a2 = fmaf(w, xx[o + k], a2);
+        a3 = fmaf(w, yy[o + k], a3);
+        a4 = fmaf(w, xy[o + k], a4);
+      }
+      hs[0][r][c0 + o] = a0; hs[1][r][c0 + o] = a1; hs[2][r][c0 + o] = a2; hs[3][r][c0 + o] = a3; hs[4][r][c0 + o] = a4;
+    }
   }
   __syncthreads();
-  // vertical pass and the per-pixel SSIM terms
+  // vertical pass and the per-pixel SSIM terms, rows r0 .. r0 + 3 of column c
+  const int c = threadIdx.x & (kSsimTW - 1), r0 = (threadIdx.x / kSsimTW) * kSsimBlk;
+  float m[kSsimBlk][5];
+  ssim_vpass<5>(t.g, hs, r0, c, m);
   double sum = 0.0;
-  for (int i = threadIdx.x; i < kSsimTH * kSsimTW; i += blockDim.x) {
-    const int r = i / kSsimTW, c = i - r * kSsimTW;
-    const int gx = s.x0 + c, gy = s.y0 + r;
+  const int gx = s.x0 + c;
+#pragma unroll
+  for (int o = 0; o < kSsimBlk; ++o) {
+    const int gy = s.y0 + r0 + o;
     if (gx >= s.W || gy >= s.H) continue;
-    float m[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int k = 0; k < 2 * kSsimR + 1; ++k) {
-#pragma unroll
-      for (int q = 0; q < 5; ++q) m[q] = fmaf(t.g[k], hs[q][r + k][c], m[q]);
-    }
-    const float mx = m[0], my = m[1];
-    const float sxx = m[2] - mx * mx, syy = m[3] - my * my, sxy = m[4] - mx * my;
+    const float mx = m[o][0], my = m[o][1];
+    const float sxx = m[o][2] - mx * mx, syy = m[o][3] - my * my, sxy = m[o][4] - mx * my;
     const float n1 = 2.f * mx * my + kSsimC1, n2 = 2.f * sxy + kSsimC2;
     const float d1 = mx * mx + my * my + kSsimC1, d2 = sxx + syy + kSsimC2;
     const float inv = 1.f / (d1 * d2);
@@ -146,25 +218,37 @@ __global__ __launch_bounds__(256) void k_ssim_stats(const float* __restrict__ co
 __global__ __launch_bounds__(256) void k_ssim_grad(const float* __restrict__ color, const float* __restrict__ target,
                                                    SsimTable t, const float* __restrict__ abc, int64_t n3, float weight,
                                                    int accumulate, float* __restrict__ grad) {
-  __shared__ float in[3][kSsimIH][kSsimIW];
+  __shared__ __align__(16) float in[3][kSsimIH][kSsimLW];
   __shared__ float hs[3][kSsimIH][kSsimTW];
   const SsimTile s = ssim_tile(t, blockIdx.x);
-  const float* src[3] = {abc, abc + n3, abc + 2 * n3};
-  ssim_stage_h<3>(s, src, t.g, in, hs);
-  const float scale = -weight / (3.f * (float)s.W * (float)s.H);
-  for (int i = threadIdx.x; i < kSsimTH * kSsimTW; i += blockDim.x) {
-    const int r = i / kSsimTW, c = i - r * kSsimTW;
-    const int gx = s.x0 + c, gy = s.y0 + r;
-    if (gx >= s.W || gy >= s.H) continue;
-    float m[3] = {0.f, 0.f, 0.f};
+  // this thread's outputs: rows r0 .. r0 + 3 of column c; their colour values are loaded first
+  const int c = threadIdx.x & (kSsimTW - 1), r0 = (threadIdx.x / kSsimTW) * kSsimBlk;
+  const int gx = s.x0 + c;
+  float xo[kSsimBlk], yo[kSsimBlk], go[kSsimBlk];
 #pragma unroll
-    for (int k = 0; k < 2 * kSsimR + 1; ++k) {
-#pragma unroll
-      for (int q = 0; q < 3; ++q) m[q] = fmaf(t.g[k], hs[q][r + k][c], m[q]);
-    }
+  for (int o = 0; o < kSsimBlk; ++o) {
+    const int gy = s.y0 + r0 + o;
+    const bool ok = gx < s.W && gy < s.H;
     const int64_t e = s.plane + (int64_t)gy * s.W + gx;
-    const float g = scale * (m[0] + 2.f * color[e] * m[1] + target[e] * m[2]);
-    grad[e] = accumulate ? grad[e] + g : g;
+    xo[o] = ok ? color[e] : 0.f;
+    yo[o] = ok ? target[e] : 0.f;
+    go[o] = ok && accumulate ? grad[e] : 0.f;
+  }
+  const float* src[3] = {abc, abc + n3, abc + 2 * n3};
+  ssim_stage<3>(s, src, in);
+  __syncthreads();
+  ssim_hpass<3>(t.g, in, hs);
+  __syncthreads();
+  float m[kSsimBlk][3];
+  ssim_vpass<3>(t.g, hs, r0, c, m);
+  const float scale = -weight / (3.f * (float)s.W * (float)s.H);
+#pragma unroll
+  for (int o = 0; o < kSsimBlk; ++o) {
+    const int gy = s.y0 + r0 + o;
+    if (gx >= s.W || gy >= s.H) continue;
+    const int64_t e = s.plane + (int64_t)gy * s.W + gx;
+    const float g = scale * (m[o][0] + 2.f * xo[o] * m[o][1] + yo[o] * m[o][2]);
+    grad[e] = accumulate ? go[o] + g : g;
   }
 }
 
@@ -178,33 +262,48 @@ __global__ __launch_bounds__(256) void k_photo_seeds(const float* __restrict__ c
                                                      float w_ssim, float w_color, float w_depth,
                                                      float* __restrict__ gcolor, float* __restrict__ gdepth,
                                                      double* __restrict__ l1_partial) {
-  __shared__ float in[3][kSsimIH][kSsimIW];
+  __shared__ __align__(16) float in[3][kSsimIH][kSsimLW];
   __shared__ float hs[3][kSsimIH][kSsimTW];
   __shared__ double red[4];
   const SsimTile s = ssim_tile(t, blockIdx.x);
+  // this thread's outputs: rows r0 .. r0 + 3 of column c; their colour and depth values are
+  // loaded first, so that their latency overlaps the staging
+  const int c = threadIdx.x & (kSsimTW - 1), r0 = (threadIdx.x / kSsimTW) * kSsimBlk;
+  const int gx = s.x0 + c;
+  float xo[kSsimBlk], yo[kSsimBlk], dz[kSsimBlk], dt[kSsimBlk];
+#pragma unroll
+  for (int o = 0; o < kSsimBlk; ++o) {
+    const int gy = s.y0 + r0 + o;
+    const bool ok = gx < s.W && gy < s.H;
+    const int64_t e = s.plane + (int64_t)gy * s.W + gx;
+    const int64_t d = t.pix_off[s.v] + (int64_t)gy * s.W + gx;
+    xo[o] = ok ? color[e] : 0.f;
+    yo[o] = ok ? target[e] : 0.f;
+    dz[o] = ok && s.ch == 0 ? depth[d] : 0.f;
+    dt[o] = ok && s.ch == 0 ? tdepth[d] : 0.f;
+  }
   const float* src[3] = {abc, abc + n3, abc + 2 * n3};
-  ssim_stage_h<3>(s, src, t.g, in, hs);
+  ssim_stage<3>(s, src, in);
+  __syncthreads();
+  ssim_hpass<3>(t.g, in, hs);
+  __syncthreads();
+  float m[kSsimBlk][3];
+  ssim_vpass<3>(t.g, hs, r0, c, m);
   const float npix = (float)s.W * (float)s.H;
   const float k_ssim = -w_ssim / (3.f * npix), k_col = w_color / (3.f * npix), k_dep = w_depth / npix;
   float l1 = 0.f;
-  for (int i = threadIdx.x; i < kSsimTH * kSsimTW; i += blockDim.x) {
-    const int r = i / kSsimTW, c = i - r * kSsimTW;
-    const int gx = s.x0 + c, gy = s.y0 + r;
+#pragma unroll
+  for (int o = 0; o < kSsimBlk; ++o) {
+    const int gy = s.y0 + r0 + o;
     if (gx >= s.W || gy >= s.H) continue;
-    float m[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-    for (int k = 0; k < 2 * kSsimR + 1; ++k) {
-#pragma unroll
-      for (int q = 0; q < 3; ++q) m[q] = fmaf(t.g[k], hs[q][r + k][c], m[q]);
-    }
     const int64_t e = s.plane + (int64_t)gy * s.W + gx;
-    const float x = color[e], dc = x - target[e];
+    const float x = xo[o], dc = x - yo[o];
     const float sg = (float)((dc > 0.f) - (dc < 0.f));
-    gcolor[e] = k_ssim * (m[0] + 2.f * x * m[1] + target[e] * m[2]) + k_col * sg;
+    gcolor[e] = k_ssim * (m[o][0] + 2.f * x * m[o][1] + yo[o] * m[o][2]) + k_col * sg;
     l1 += k_col * fabsf(dc);
     if (s.ch == 0) {
       const int64_t d = t.pix_off[s.v] + (int64_t)gy * s.W + gx;
-      const float db = tdepth[d], dd = depth[d] - db;
+      const float db = dt[o], dd = dz[o] - db;
       const bool valid = db > 0.f;
       gdepth[d] = valid ? k_dep * (float)((dd > 0.f) - (dd < 0.f)) : 0.f;
       if (valid) l1 += k_dep * fabsf(dd);
