@@ -372,7 +372,8 @@ TSR_API int tsr_render_train_normal(const tsr_scene *scene, const float *poses, 
  * normal step (a zero vector marks an invalid pixel).  Requires a preceding tsr_bin_and_sort
  * of the same scene (its colours, not the normals: the normals ride in the walks).
  * scratch: device, 256-byte aligned, at least tsr_mapping_scratch_size bytes (the D-SSIM
- * scratch + 32 per face + 24 per pixel + 2.5 KB), owned by the caller, no clearing needed.
+ * scratch + 32 per face + 128 per 16 x 16 tile + 2.5 KB), owned by the caller, no clearing
+ * needed.
  * Soups only (faces == NULL): TSR_EINVAL otherwise.  Enqueued on `stream`; no allocation. */
 TSR_API int tsr_mapping_scratch_size(const tsr_scene *scene, const tsr_intrinsics *intr /* (host)[n_views] */,
                                      int n_views, size_t *bytes /* (host) out */);

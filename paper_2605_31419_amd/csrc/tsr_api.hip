@@ -435,7 +435,8 @@ int tsr_render_train_photometric(const tsr_scene* scene, const float* poses, con
   if (e != hipSuccess) return hip_fail(e, "tsr_render_train_photometric seeds");
   tsr::TrainSchedule sched{0, 0, 0};
   e = tsr::launch_backward(dev_scene(scene, params), poses, vt, *params, L, w, gc, gd, nullptr, nullptr, nullptr, nullptr,
-                           nullptr, nullptr, nullptr, grad_pos, grad_col, grad_opa, grad_pose, false, sched, st);
+                           nullptr, nullptr, nullptr, grad_pos, grad_col, grad_opa, grad_pose, false, sched, st, nullptr,
+                           true);
   return e == hipSuccess ? TSR_OK : hip_fail(e, "tsr_render_train_photometric backward");
 }
 
@@ -563,7 +564,9 @@ int tsr_mapping_scratch_size(const tsr_scene* scene, const tsr_intrinsics* intr,
   tsr::SsimTable t;
   if (!intr || tsr::build_ssim_table(intr, n_views, &t) != 0)
     return fail(TSR_EINVAL, "views: need 1 <= n_views <= %d and image sizes in (0, 16384]", TSR_MAX_VIEWS);
-  *bytes = tsr::mapping_scratch(tsr::ssim_scratch_bytes(t), scene->n_faces, t.n_pixels).total;
+  ViewTable vt;
+  if ((rc = build_views(scene, intr, n_views, &vt))) return rc;
+  *bytes = tsr::mapping_scratch(tsr::ssim_scratch_bytes(t), scene->n_faces, vt.n_tiles).total;
   return TSR_OK;
 }
 
@@ -584,7 +587,7 @@ int tsr_render_train_mapping(const tsr_scene* scene, const float* poses, const t
   tsr::SsimTable t;
   if (tsr::build_ssim_table(intr, n_views, &t) != 0) return fail(TSR_EINVAL, "bad D-SSIM view table");
   if (!scratch) return fail(TSR_EINVAL, "scratch is NULL");
-  const size_t need = tsr::mapping_scratch(tsr::ssim_scratch_bytes(t), scene->n_faces, t.n_pixels).total;
+  const size_t need = tsr::mapping_scratch(tsr::ssim_scratch_bytes(t), scene->n_faces, vt.n_tiles).total;
   if (scratch_bytes < need) return fail(TSR_EWORKSPACE, "mapping scratch of %zu bytes is below the %zu needed", scratch_bytes, need);
   if (reinterpret_cast<uintptr_t>(scratch) & 255) return fail(TSR_EINVAL, "scratch must be 256-byte aligned");
   hipError_t e = tsr::launch_train_mapping(dev_scene(scene, params), poses, vt, *params, L, static_cast<char*>(ws), t,

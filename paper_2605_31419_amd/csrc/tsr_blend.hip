@@ -51,11 +51,20 @@ template <int SM> constexpr bool normal_mode() { return (SM & 16) != 0; }
 // Normal channels: per face, not per view, indexed by m = g - v M for the record slot
 // g = v M + m.  The normal is a world quantity and its seeds are rotated into the world frame,
 // so the gradients of all views add into one entry per face.
+// The normal loss is evaluated where its inputs are: the forward rotates each pixel's
+// composited normal into the camera frame (N = R_CW N_w), compares it with the target and
+// leaves per-wave sums; the backward forms the seed dE/dN_w = R_CW^T dE/dN from the target and
+// the view's valid-pixel count.
 struct NormalIn {
   const float4* nrm;       // [M] unit world normal (x, y, z, 0)
-  const float* seed;       // backward: [sum 3 P] dE/dN_w per pixel, packed like colour
   float4* gacc;            // backward: [M] dE/dn_F summed over the views (x, y, z, 0)
-  float* map;              // forward: [sum 3 P] composited world normals, packed like colour
+  float* map;              // forward, may be null: [sum 3 P] N in the camera frame, packed like colour
+  const float* poses;      // [V][12] world-to-camera poses (row-major R, then t)
+  const float* target;     // [sum 3 P] target normals, packed like colour (zero vector: invalid)
+  const uint32_t* count;   // backward: [V] valid target pixels per view
+  float* part;             // forward: [n_tiles * 4][8] per-wave sums (valid pixels, sum of
+                           // 1 - N.N_bar, sum of N x N_bar)
+  float w_norm;
   int64_t M;
 };
 
@@ -184,6 +193,7 @@ static_assert(kSpan % kBatch == 0 && kSpan >= kBatch, "a staged span is walked a
 static_assert(kSpan * (6 * sizeof(float4) + sizeof(uint32_t)) <= 48 * 1024, "a staged span fits the LDS budget");
 static_assert(kWaves * kWave == kBlock && kWaves == 4, "one wave per 8x8 quadrant of a 16x16 tile");
 static_assert(kGradDwords == 20, "normal channels: record terms in slots 0-19 of the 24-value wave sum");
+static_assert(kWaves == kTileQuads, "normal-loss sums: one slot per wave of a tile");
 __device__ __forceinline__ void stage_batch_block(const float* __restrict__ records, const uint64_t* __restrict__ pairs,
                                                   uint32_t b0, int n, float4* srec, uint32_t* sface) {
   for (int i = threadIdx.x; i < n * 6; i += kBlock) {
@@ -535,19 +545,44 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(ViewTable vt, const float*
   tile_ctx(vt, ranges, tile, wv, c);
   FwdState s;
   forward_walk<SM, false>(c, records, pairs, sigma, t_min, srec[wv], sface[wv], s, &nin, snrm[wv]);
-  if (!c.inside) return;
   const int64_t hw = (int64_t)c.vd.width * c.vd.height;
   const int64_t off = (int64_t)c.py * c.vd.width + c.px;
+  if constexpr (normal_mode<SM>()) {
+    // N = R_CW N_w against the target (Sec. 3.4); the wave's sums go to part (all lanes active)
+    const float* R = nin.poses + 12 * c.view;
+    const float n0 = R[0] * s.N0 + R[1] * s.N1 + R[2] * s.N2;
+    const float n1 = R[3] * s.N0 + R[4] * s.N1 + R[5] * s.N2;
+    const float n2 = R[6] * s.N0 + R[7] * s.N1 + R[8] * s.N2;
+    float cnt = 0.f, l = 0.f, r0 = 0.f, r1 = 0.f, r2 = 0.f;
+    if (c.inside) {
+      const float* tb = nin.target + 3 * c.vd.pix_off + off;
+      const float b0 = tb[0], b1 = tb[hw], b2 = tb[2 * hw];
+      if (b0 != 0.f || b1 != 0.f || b2 != 0.f) {
+        cnt = 1.f;
+        l = 1.f - (n0 * b0 + n1 * b1 + n2 * b2);
+        r0 = n1 * b2 - n2 * b1;
+        r1 = n2 * b0 - n0 * b2;
+        r2 = n0 * b1 - n1 * b0;
+      }
+      if (nin.map) {
+        float* nb = nin.map + 3 * c.vd.pix_off + off;
+        nb[0] = n0;
+        nb[hw] = n1;
+        nb[2 * hw] = n2;
+      }
+    }
+    const float tc = wave_sum(cnt), tl = wave_sum(l), t0 = wave_sum(r0), t1 = wave_sum(r1), t2 = wave_sum(r2);
+    if ((threadIdx.x & 63) == 0) {
+      float4* pw = reinterpret_cast<float4*>(nin.part + kNormalPart * ((int64_t)tile * kWaves + wv));
+      pw[0] = make_float4(tc, tl, t0, t1);
+      pw[1] = make_float4(t2, 0.f, 0.f, 0.f);
+    }
+  }
+  if (!c.inside) return;
   float* cb = color + 3 * c.vd.pix_off + off;
   cb[0] = s.C0;
   cb[hw] = s.C1;
   cb[2 * hw] = s.C2;
-  if constexpr (normal_mode<SM>()) {
-    float* nb = nin.map + 3 * c.vd.pix_off + off;
-    nb[0] = s.N0;
-    nb[hw] = s.N1;
-    nb[2 * hw] = s.N2;
-  }
   depth[c.pix] = s.D;
   if (trans) trans[c.pix] = s.T;
   n_last[c.pix] = s.last;
@@ -587,10 +622,21 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(ViewTable vt, const float*
     pg.gd = gdepth[c.pix];
     pg.gt = gtrans ? gtrans[c.pix] : 0.f;
     if constexpr (normal_mode<SM>()) {
-      const float* sn = nin.seed + 3 * c.vd.pix_off + (int64_t)c.py * c.vd.width + c.px;
-      pg.gn0 = sn[0];
-      pg.gn1 = sn[hw];
-      pg.gn2 = sn[2 * hw];
+      // dE/dN = -(w_norm / valid count) N_bar at a valid pixel, then dE/dN_w = R_CW^T dE/dN
+      const float* tb = nin.target + 3 * c.vd.pix_off + (int64_t)c.py * c.vd.width + c.px;
+      const float b0 = tb[0], b1 = tb[hw], b2 = tb[2 * hw];
+      const uint32_t cn = nin.count[c.view];
+      const float inv = cn ? nin.w_norm / (float)cn : 0.f;
+      float g0 = 0.f, g1 = 0.f, g2 = 0.f;
+      if (b0 != 0.f || b1 != 0.f || b2 != 0.f) {
+        g0 = -inv * b0;
+        g1 = -inv * b1;
+        g2 = -inv * b2;
+      }
+      const float* R = nin.poses + 12 * c.view;
+      pg.gn0 = R[0] * g0 + R[3] * g1 + R[6] * g2;
+      pg.gn1 = R[1] * g0 + R[4] * g1 + R[7] * g2;
+      pg.gn2 = R[2] * g0 + R[5] * g1 + R[8] * g2;
     }
   }
   backward_walk<SM, false>(c, records, pairs, sigma, last, Tb, pg, srec[wv], sface[wv], nullptr, grad_acc, sig_acc,
@@ -1115,9 +1161,10 @@ __global__ __launch_bounds__(1024) void k_build_order(const uint32_t* __restrict
 
 // The longest-first order of the binning held in `ws`: built with the binning up to
 // kOrderInSortMax tiles, else here (enqueued on `st` before the kernels that read it).
-static const int* tile_order(const ViewTable& vt, const WsLayout& L, char* ws, hipStream_t st) {
+// `built`: a launch since the binning (a forward on the same stream) already built it.
+static const int* tile_order(const ViewTable& vt, const WsLayout& L, char* ws, hipStream_t st, bool built = false) {
   int* order = reinterpret_cast<int*>(ws + L.order);
-  if (vt.n_tiles > kOrderInSortMax)
+  if (vt.n_tiles > kOrderInSortMax && !built)
     TSR_LAUNCH("tile_order", k_build_order, dim3(1), dim3(1024), 0, st,
                reinterpret_cast<const uint32_t*>(ws + L.ranges), vt.n_tiles, order);
   return order;
@@ -1411,7 +1458,9 @@ hipError_t launch_forward(const ViewTable& vt, const tsr_params& p, const WsLayo
   float* t_last = reinterpret_cast<float*>(ws + L.t_last);
   const dim3 grid(tile_grid(vt.n_tiles)), block(kBlock);
   NormalIn nin{};
-  if (nc) nin = NormalIn{reinterpret_cast<const float4*>(nc->face_normal), nullptr, nullptr, nc->map, vt.n_faces};
+  if (nc)
+    nin = NormalIn{reinterpret_cast<const float4*>(nc->face_normal), nullptr, nc->map, nc->poses, nc->target,
+                   nullptr, nc->part, nc->w_norm, vt.n_faces};
 #define TSR_FWD(S) TSR_LAUNCH("blend_fwd", k_blend_fwd<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last, border, nin)
   if (nc) {
     TSR_NORMAL_SWITCH(sigma_mode(vt, p) | 16, TSR_FWD)
@@ -1427,7 +1476,7 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
                            const float* gtrans, const float* tcolor, const float* tdepth, float* color,
                            float* depth, float* trans, float* loss, float* grad_pos, float* grad_col,
                            float* grad_opa, float* grad_pose, bool fused_train, const TrainSchedule& sched,
-                           hipStream_t st, const NormalChannels* nc) {
+                           hipStream_t st, const NormalChannels* nc, bool order_built) {
   const uint32_t* vis_total = reinterpret_cast<const uint32_t*>(ws + L.vis_total);
   const uint32_t* vis_dense = reinterpret_cast<const uint32_t*>(ws + L.vis_dense);
   const uint32_t* counts = reinterpret_cast<const uint32_t*>(ws + L.counts);
@@ -1446,7 +1495,7 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
   const int* order = nullptr;
   int* queue = nullptr;
   // the separate backward always walks longest-first; the fused kernel when its schedule says so
-  if (!fused_train || sched.order) order = tile_order(vt, L, ws, st);
+  if (!fused_train || sched.order) order = tile_order(vt, L, ws, st, order_built);
   if (fused_train && sched.persistent) queue = reinterpret_cast<int*>(ws + L.hdr_queue);
   {
     const int64_t rows16 = nf * (int64_t)((kGradDwords * sizeof(acc_t)) / 16);
@@ -1461,8 +1510,8 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
     const int* border = order;
     NormalIn nin{};
     if (nc)
-      nin = NormalIn{reinterpret_cast<const float4*>(nc->face_normal), nc->seed,
-                     reinterpret_cast<float4*>(nc->grad), nullptr, vt.n_faces};
+      nin = NormalIn{reinterpret_cast<const float4*>(nc->face_normal), reinterpret_cast<float4*>(nc->grad), nullptr,
+                     nc->poses, nc->target, nc->count, nullptr, nc->w_norm, vt.n_faces};
 #define TSR_BWD(S) TSR_LAUNCH("blend_bwd", k_blend_bwd<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, n_last, t_last, gcolor, gdepth, gtrans, grad_acc, sig_acc, persp_acc, border, nin)
     if (nc) {
       TSR_NORMAL_SWITCH(sm | 16, TSR_BWD)

@@ -69,6 +69,8 @@ constexpr int kWaveSortMax = 512;      // ... by one wave (longer ones by a whol
 constexpr int kSmallTiles = 4;         // faces overlapping at most this many tiles record their slots
 constexpr int kTileCntStride = 4;     // dwords per tile in the tile-counter array
 constexpr uint32_t kSkipSlot = 0xffffffffu;   // recorded slot of a tile the tight binning leaves out
+constexpr int kTileQuads = 4;          // 8x8 quadrants of a 16x16 tile (one blend wave each)
+constexpr int kNormalPart = 8;         // floats of normal-loss sums per blend wave (mapping step)
 
 // What the emission of one visible (view, face) pair needs, written by the projection in the
 // order of its workgroup's threads: id g = v * M + m, the global id of the first tile of its
@@ -162,12 +164,18 @@ hipError_t launch_bin(const tsr_scene_dev& sc, const float* poses, const ViewTab
 // Normal channels of the separate forward and backward walks (mapping step, Sec. 3.4): each
 // face's world unit normal composited like a colour constant over the face.  face_normal and
 // grad are [M][4] floats (x, y, z, 0) per face, summed over the views in grad (which the
-// caller zero-fills); map (forward) and seed (backward, dE/dN_w) are packed like colour.
+// caller zero-fills); map (forward, may be null: N in the camera frame) and target are packed
+// like colour; part (forward) holds 8 floats per wave of each tile (kernel-written), count
+// (backward) the valid target pixels of each view.
 struct NormalChannels {
   const float* face_normal;
   float* map;
-  const float* seed;
   float* grad;
+  const float* poses;
+  const float* target;
+  const uint32_t* count;
+  float* part;
+  float w_norm;
 };
 
 hipError_t launch_forward(const ViewTable& vt, const tsr_params& p, const WsLayout& L, char* ws, float* color,
@@ -178,7 +186,9 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
                            const float* gtrans, const float* tcolor, const float* tdepth, float* color,
                            float* depth, float* trans, float* loss, float* grad_pos, float* grad_col,
                            float* grad_opa, float* grad_pose, bool fused_train, const TrainSchedule& sched,
-                           hipStream_t st, const NormalChannels* nc = nullptr);
+                           hipStream_t st, const NormalChannels* nc = nullptr, bool order_built = false);
+// (order_built: a forward since the binning, on the same stream, built the longest-first tile
+// order the separate backward walks in, so it is not built again.)
 
 // D-SSIM (Sec. 3.4, eq. 8): output tile of the stencil kernels and the window radius.
 constexpr int kSsimTW = 32;
@@ -239,9 +249,9 @@ hipError_t launch_train_normal(const tsr_scene_dev& sc, const float* poses, cons
 // The full mapping energy on one binning (photometric, depth and normal terms): scratch
 // layout after the D-SSIM scratch (byte offsets from the start of the whole scratch).
 struct MappingScratch {
-  size_t nrm, gacc, nw, seed, count, acc, total;
+  size_t nrm, gacc, part, count, acc, total;
 };
-MappingScratch mapping_scratch(size_t ssim_bytes, int64_t n_faces, int64_t n_pixels);
+MappingScratch mapping_scratch(size_t ssim_bytes, int64_t n_faces, int64_t n_tiles);
 hipError_t launch_train_mapping(const tsr_scene_dev& sc, const float* poses, const ViewTable& vt, const tsr_params& p,
                                 const WsLayout& L, char* ws, const SsimTable& t, const float* target_color,
                                 const float* target_depth, const float* target_normals, float w_ssim, float w_norm,

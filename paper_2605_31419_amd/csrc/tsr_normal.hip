@@ -2,9 +2,10 @@
 // E_norm = mean over valid pixels of (1 - N(p) . N_bar(p)), with N the rendered normal map.
 //
 // The rendered map composites each face's world unit normal like a colour that is constant
-// over the face, then rotates it into the camera frame: N = R_CW N_w.  The step therefore runs
-// the rasterizer itself on the soup with every vertex colour set to its face normal (binning,
-// forward, backward), and adds around it:
+// over the face, then rotates it into the camera frame: N = R_CW N_w.  Two forms:
+//
+// The normal step on its own (launch_train_normal) runs the rasterizer on the soup with every
+// vertex colour set to its face normal (binning, forward, backward), and adds around it:
 //   k_normal_colours  face normals (FP64) written as vertex colours;
 //   k_count_valid     valid target pixels per view (a target normal of 0 marks an invalid one);
 //   k_normal_seeds    N = R N_w, the loss sums, the colour seed dE/dN_w = R^T dE/dN and the
@@ -12,6 +13,13 @@
 //   k_normal_chain    the face-normal gradient (sum of its vertices' colour gradients) through
 //                     the normalised cross product into the vertex positions;
 //   k_normal_finish   per-view loss and the rotation term added to the pose gradient.
+//
+// The mapping step (launch_train_mapping) carries the normals as three more channels of the
+// photometric walks on the scene's own binning: k_face_normals writes them per face, the
+// forward compares N with the target per pixel and leaves per-wave sums that k_normal_reduce
+// turns into each view's valid count, loss and rotation term, the backward forms the seeds from
+// the target itself and sums dE/dn_F per face, and k_normal_chain_faces takes that through the
+// normalised cross product into the position gradients.
 #include "tsr_device.h"
 #include "tsr_internal.h"
 
@@ -214,11 +222,12 @@ __global__ void k_normal_finish(int n_views, const uint32_t* __restrict__ count,
 }
 
 // Face normals of the normal channels: [M] float4 (x, y, z, 0), FP64 arithmetic; a degenerate
-// face gets 0.
+// face gets 0.  Also zeroes the face's normal-gradient accumulator.
 __global__ __launch_bounds__(256) void k_face_normals(const float* __restrict__ pos, int64_t N, int64_t M,
-                                                      float4* __restrict__ nrm) {
+                                                      float4* __restrict__ nrm, float4* __restrict__ gacc) {
   const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= M) return;
+  gacc[m] = make_float4(0.f, 0.f, 0.f, 0.f);
   double e1[3], e2[3], c[3];
   load_face(pos, N, m, e1, e2);
   cross3(e1, e2, c);
@@ -339,7 +348,7 @@ hipError_t launch_train_normal(const tsr_scene_dev& sc, const float* poses, cons
              seed, acc);
   TrainSchedule sched{0, 0, 0};
   e = launch_backward(sn, poses, vt, p, L, ws, seed, zeros, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                      nullptr, grad_pos, grad_pos ? gcol : nullptr, grad_opa, grad_pose, false, sched, st);
+                      nullptr, grad_pos, grad_pos ? gcol : nullptr, grad_opa, grad_pose, false, sched, st, nullptr, true);
   if (e != hipSuccess) return e;
   if (grad_pos && M > 0)
     TSR_LAUNCH("normal_chain", k_normal_chain, dim3(fb), dim3(256), 0, st, sc.pos, N, M, gcol, grad_pos);
@@ -355,17 +364,71 @@ hipError_t launch_train_normal(const tsr_scene_dev& sc, const float* poses, cons
   return hipGetLastError();
 }
 
-MappingScratch mapping_scratch(size_t ssim_bytes, int64_t n_faces, int64_t n_pixels) {
+MappingScratch mapping_scratch(size_t ssim_bytes, int64_t n_faces, int64_t n_tiles) {
   auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
   MappingScratch z;
   z.nrm = up(ssim_bytes);
   z.gacc = up(z.nrm + 16 * (size_t)n_faces);
-  z.nw = up(z.gacc + 16 * (size_t)n_faces);
-  z.seed = up(z.nw + sizeof(float) * 3 * (size_t)n_pixels);
-  z.count = up(z.seed + sizeof(float) * 3 * (size_t)n_pixels);
+  z.part = up(z.gacc + 16 * (size_t)n_faces);
+  z.count = up(z.part + sizeof(float) * kNormalPart * kTileQuads * (size_t)n_tiles);
   z.acc = up(z.count + sizeof(uint32_t) * TSR_MAX_VIEWS);
   z.total = up(z.acc + sizeof(double) * 4 * TSR_MAX_VIEWS);
   return z;
+}
+
+// Per view, the forward's per-wave normal-loss sums in FP64: the valid-pixel count, the loss
+// sum, and the rotation term sum_p N x dE/dN = -(w_norm / count) sum_p N x N_bar, in the layout
+// k_normal_finish reads.  One 1024-thread workgroup per view, four slots per thread in flight;
+// overwrites count and acc.
+__global__ __launch_bounds__(1024) void k_normal_reduce(ViewTable vt, const float* __restrict__ part, float w_norm,
+                                                        uint32_t* __restrict__ count, double* __restrict__ acc) {
+  __shared__ double red[5][16];
+  const int v = blockIdx.x;
+  const ViewDesc vd = vt.v[v];
+  const int64_t w0 = (int64_t)vd.tile_off * kTileQuads;
+  const int64_t w1 = w0 + (int64_t)vd.tiles_x * vd.tiles_y * kTileQuads;
+  double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  static_assert(kNormalPart == 8, "a slot is two float4");
+  for (int64_t base = w0; base < w1; base += 4 * 1024) {
+    float4 a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t w = base + u * 1024 + threadIdx.x;
+      const float4* p = reinterpret_cast<const float4*>(part + kNormalPart * w);
+      a[u] = w < w1 ? p[0] : make_float4(0.f, 0.f, 0.f, 0.f);
+      b[u] = w < w1 ? p[1] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      s[0] += (double)a[u].x;
+      s[1] += (double)a[u].y;
+      s[2] += (double)a[u].z;
+      s[3] += (double)a[u].w;
+      s[4] += (double)b[u].x;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 5; ++k)
+    for (int o = 32; o > 0; o >>= 1) s[k] += __shfl_xor(s[k], o, 64);
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < 5; ++k) red[k][threadIdx.x >> 6] = s[k];
+  __syncthreads();
+  double tot[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    double t = 0.0;
+    for (int w = 0; w < 16; ++w) t += red[k][w];
+    tot[k] = t;
+  }
+  if (threadIdx.x == 0) {
+    const uint32_t cn = (uint32_t)tot[0];
+    const float inv = cn ? w_norm / (float)cn : 0.f;
+    count[v] = cn;
+    acc[4 * v] = tot[1];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc[4 * v + 1 + k] = -(double)inv * tot[2 + k];
+  }
 }
 
 // The whole mapping energy on the binning in `ws` (made with the scene's colours): one
@@ -378,36 +441,31 @@ hipError_t launch_train_mapping(const tsr_scene_dev& sc, const float* poses, con
                                 float* color, float* depth, float* trans, float* normal_map, float* loss,
                                 float* loss_norm, float* grad_pos, float* grad_col, float* grad_opa,
                                 float* grad_pose, char* scratch, hipStream_t st) {
-  const MappingScratch z = mapping_scratch(ssim_scratch_bytes(t), sc.n_faces, t.n_pixels);
+  const MappingScratch z = mapping_scratch(ssim_scratch_bytes(t), sc.n_faces, vt.n_tiles);
   float4* nrm = reinterpret_cast<float4*>(scratch + z.nrm);
   float4* gacc = reinterpret_cast<float4*>(scratch + z.gacc);
-  float* nw = reinterpret_cast<float*>(scratch + z.nw);
-  float* seed = reinterpret_cast<float*>(scratch + z.seed);
+  float* part = reinterpret_cast<float*>(scratch + z.part);
   uint32_t* count = reinterpret_cast<uint32_t*>(scratch + z.count);
   double* acc = reinterpret_cast<double*>(scratch + z.acc);
   const int64_t M = sc.n_faces, N = sc.n_vertices;
   const unsigned fb = (unsigned)std::max<int64_t>((M + 255) / 256, 1);
-  // the per-face normal gradients, the valid counts and the FP64 sums start at zero
-  TSR_LAUNCH("zero_words", k_zero_words, dim3(std::min<unsigned>(fb, 2048u)), dim3(256), 0, st,
-             reinterpret_cast<uint32_t*>(gacc), 4 * M);
-  TSR_LAUNCH("zero_words", k_zero_words, dim3(1), dim3(256), 0, st, count,
-             (int64_t)((z.total - z.count) / sizeof(uint32_t)));
-  if (M > 0) TSR_LAUNCH("face_normals", k_face_normals, dim3(fb), dim3(256), 0, st, sc.pos, N, M, nrm);
-  const NormalChannels fc{reinterpret_cast<const float*>(nrm), nw, nullptr, nullptr};
+  // face normals, and the per-face normal gradients set to zero (every other scratch entry is
+  // written before it is read)
+  if (M > 0) TSR_LAUNCH("face_normals", k_face_normals, dim3(fb), dim3(256), 0, st, sc.pos, N, M, nrm, gacc);
+  const NormalChannels fc{reinterpret_cast<const float*>(nrm), normal_map, nullptr, poses, target_normals, nullptr,
+                          part, w_norm};
   hipError_t e = launch_forward(vt, p, L, ws, color, depth, trans, st, &fc);
   if (e != hipSuccess) return e;
+  TSR_LAUNCH("normal_reduce", k_normal_reduce, dim3(vt.n_views), dim3(1024), 0, st, vt, part, w_norm, count, acc);
   float *gc = nullptr, *gd = nullptr;
   e = launch_photo_seeds(t, color, target_color, depth, target_depth, w_ssim, p.w_color, p.w_depth, loss, scratch,
                          &gc, &gd, st);
   if (e != hipSuccess) return e;
-  const dim3 pg(kNormBlocksPerView, vt.n_views);
-  TSR_LAUNCH("count_valid", k_count_valid, pg, dim3(256), 0, st, vt, target_normals, count);
-  TSR_LAUNCH("normal_seeds", k_normal_seeds, pg, dim3(256), 0, st, vt, poses, nw, target_normals, count, w_norm,
-             normal_map, seed, acc);
-  const NormalChannels bc{reinterpret_cast<const float*>(nrm), nullptr, seed, reinterpret_cast<float*>(gacc)};
+  const NormalChannels bc{reinterpret_cast<const float*>(nrm), nullptr, reinterpret_cast<float*>(gacc), poses,
+                          target_normals, count, nullptr, w_norm};
   TrainSchedule sched{0, 0, 0};
   e = launch_backward(sc, poses, vt, p, L, ws, gc, gd, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
-                      grad_pos, grad_col, grad_opa, grad_pose, false, sched, st, &bc);
+                      grad_pos, grad_col, grad_opa, grad_pose, false, sched, st, &bc, true);
   if (e != hipSuccess) return e;
   if (grad_pos && M > 0)
     TSR_LAUNCH("normal_chain", k_normal_chain_faces, dim3(fb), dim3(256), 0, st, sc.pos, N, M, gacc, grad_pos);

@@ -194,7 +194,7 @@ def test_normal_entry_points_validation():
 
 def test_mapping_step_validation():
     """The one-binning mapping step: soups only, all three targets, colour and depth outputs,
-    and a scratch of at least the D-SSIM scratch + 32 bytes per face + 24 per pixel."""
+    and a scratch of at least the D-SSIM scratch + 32 bytes per face + 128 per 16x16 tile."""
     lib = _lib.load()
     p = C.c_void_p(256)
     big = C.c_size_t(1 << 30)
@@ -202,7 +202,7 @@ def test_mapping_step_validation():
     need, ssim = C.c_size_t(), C.c_size_t()
     assert lib.tsr_mapping_scratch_size(C.byref(sc), intr, 1, C.byref(need)) == 0
     assert lib.tsr_dssim_scratch_size(intr, 1, C.byref(ssim)) == 0
-    assert need.value >= ssim.value + 32 * 10 + 24 * 64 * 48
+    assert need.value >= ssim.value + 32 * 10 + 128 * 4 * 3
     assert lib.tsr_mapping_scratch_size(C.byref(sc), intr, 0, C.byref(need)) == _lib.TSR_EINVAL
 
     def call(scene=sc, tn=p, color=p, scratch_bytes=need):
