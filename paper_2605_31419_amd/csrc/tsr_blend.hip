@@ -195,12 +195,18 @@ static_assert(kWaves * kWave == kBlock && kWaves == 4, "one wave per 8x8 quadran
 static_assert(kGradDwords == 20, "normal channels: record terms in slots 0-19 of the 24-value wave sum");
 static_assert(kWaves == kTileQuads, "normal-loss sums: one slot per wave of a tile");
 __device__ __forceinline__ void stage_batch_block(const float* __restrict__ records, const uint64_t* __restrict__ pairs,
-                                                  uint32_t b0, int n, float4* srec, uint32_t* sface) {
+                                                  uint32_t b0, int n, float4* srec, uint32_t* sface,
+                                                  const float4* __restrict__ nrm = nullptr, int64_t moff = 0,
+                                                  float4* snrm = nullptr) {
   for (int i = threadIdx.x; i < n * 6; i += kBlock) {
     const uint32_t face = (uint32_t)pairs[b0 + i / 6];
     srec[i] = reinterpret_cast<const float4*>(records)[(size_t)face * 6 + i % 6];
   }
-  for (int i = threadIdx.x; i < n; i += kBlock) sface[i] = (uint32_t)pairs[b0 + i];
+  for (int i = threadIdx.x; i < n; i += kBlock) {
+    const uint32_t face = (uint32_t)pairs[b0 + i];
+    sface[i] = face;
+    if (nrm) snrm[i] = nrm[(int64_t)face - moff];
+  }
 }
 
 // Per-wave staging: lane l reads the face id of entry l; the 6 n sixteen-byte pieces are then
@@ -306,7 +312,10 @@ __device__ __forceinline__ void forward_walk(const TileCtx& c, const float* __re
     const int ns = (int)min((uint32_t)kStage, c.end - s0);
     if constexpr (COOP) {
       if (__syncthreads_count(live(s.T, t_min)) == 0) break;
-      stage_batch_block(records, pairs, s0, ns, srec, sface);
+      if constexpr (normal_mode<SM>())
+        stage_batch_block(records, pairs, s0, ns, srec, sface, nin->nrm, (int64_t)c.view * nin->M, snrm);
+      else
+        stage_batch_block(records, pairs, s0, ns, srec, sface);
       __syncthreads();
     } else {
       if (ballot(live(s.T, t_min)) == 0) break;
@@ -340,7 +349,7 @@ __device__ __forceinline__ void forward_walk(const TileCtx& c, const float* __re
       s.C2 = fmaf(e.c2, w, s.C2);
       s.D = fmaf(e.zp, w, s.D);
       if constexpr (normal_mode<SM>()) {
-        const float4 nf = snrm[j];
+        const float4 nf = snrm[h + j];
         s.N0 = fmaf(nf.x, w, s.N0);
         s.N1 = fmaf(nf.y, w, s.N1);
         s.N2 = fmaf(nf.z, w, s.N2);
@@ -399,7 +408,10 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
     const int ns = s1 - s0;
     if constexpr (COOP) {
       __syncthreads();
-      stage_batch_block(records, pairs, (uint32_t)s0, ns, srec, sface);
+      if constexpr (normal_mode<SM>())
+        stage_batch_block(records, pairs, (uint32_t)s0, ns, srec, sface, nin->nrm, (int64_t)c.view * nin->M, snrm);
+      else
+        stage_batch_block(records, pairs, (uint32_t)s0, ns, srec, sface);
       __syncthreads();
     } else {
       if constexpr (normal_mode<SM>())
@@ -463,7 +475,7 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
       float4 nf = make_float4(0.f, 0.f, 0.f, 0.f);
       if constexpr (normal_mode<SM>()) {
         // the face's normal is a colour constant over the face: it enters dL/dalpha like one
-        nf = snrm[j];
+        nf = snrm[h + j];
         P = fmaf(pg.gn0, nf.x, fmaf(pg.gn1, nf.y, fmaf(pg.gn2, nf.z, P)));
       }
       const float galpha = Tj * (P - S);
@@ -527,7 +539,9 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
 
 // ---------------------------------------------------------------------------- kernels
 
-template <int SM>
+// COOP: the tile's list is staged cooperatively (one shared copy per workgroup, the four
+// quadrant waves in step), else per wave (four copies, each wave at its own pace).
+template <int SM, bool COOP>
 __global__ __launch_bounds__(kBlock) void k_blend_fwd(ViewTable vt, const float* __restrict__ records,
                                                       const uint64_t* __restrict__ pairs,
                                                       const uint32_t* __restrict__ ranges, float sigma, float t_min,
@@ -535,16 +549,23 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(ViewTable vt, const float*
                                                       float* __restrict__ trans, int* __restrict__ n_last,
                                                       float* __restrict__ t_last, const int* __restrict__ order,
                                                       NormalIn nin) {
-  __shared__ float4 srec[kWaves][kBatch * 6];
-  __shared__ uint32_t sface[kWaves][kBatch];
-  __shared__ float4 snrm[kWaves][normal_mode<SM>() ? kBatch : 1];
   const int wv = threadIdx.x >> 6;
   const int tile = tile_of_block_ordered(vt.n_tiles, order);
   if (tile < 0) return;
   TileCtx c;
   tile_ctx(vt, ranges, tile, wv, c);
   FwdState s;
-  forward_walk<SM, false>(c, records, pairs, sigma, t_min, srec[wv], sface[wv], s, &nin, snrm[wv]);
+  if constexpr (COOP) {
+    __shared__ float4 srec[kSpan * 6];
+    __shared__ uint32_t sface[kSpan];
+    __shared__ float4 snrm[normal_mode<SM>() ? kSpan : 1];
+    forward_walk<SM, true>(c, records, pairs, sigma, t_min, srec, sface, s, &nin, snrm);
+  } else {
+    __shared__ float4 srec[kWaves][kBatch * 6];
+    __shared__ uint32_t sface[kWaves][kBatch];
+    __shared__ float4 snrm[kWaves][normal_mode<SM>() ? kBatch : 1];
+    forward_walk<SM, false>(c, records, pairs, sigma, t_min, srec[wv], sface[wv], s, &nin, snrm[wv]);
+  }
   const int64_t hw = (int64_t)c.vd.width * c.vd.height;
   const int64_t off = (int64_t)c.py * c.vd.width + c.px;
   if constexpr (normal_mode<SM>()) {
@@ -589,7 +610,7 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(ViewTable vt, const float*
   t_last[c.pix] = s.Tb;
 }
 
-template <int SM>
+template <int SM, bool COOP>
 __global__ __launch_bounds__(kBlock) void k_blend_bwd(ViewTable vt, const float* __restrict__ records,
                                                       const uint64_t* __restrict__ pairs,
                                                       const uint32_t* __restrict__ ranges, float sigma,
@@ -598,9 +619,6 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(ViewTable vt, const float*
                                                       const float* __restrict__ gtrans, acc_t* __restrict__ grad_acc,
                                                       float* __restrict__ sig_acc, float* __restrict__ persp_acc,
                                                       const int* __restrict__ order, NormalIn nin) {
-  __shared__ float4 srec[kWaves][kBatch * 6];
-  __shared__ uint32_t sface[kWaves][kBatch];
-  __shared__ float4 snrm[kWaves][normal_mode<SM>() ? kBatch : 1];
   const int wv = threadIdx.x >> 6;
   const int tile = tile_of_block_ordered(vt.n_tiles, order);
   if (tile < 0) return;
@@ -639,8 +657,20 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(ViewTable vt, const float*
       pg.gn2 = R[2] * g0 + R[5] * g1 + R[8] * g2;
     }
   }
-  backward_walk<SM, false>(c, records, pairs, sigma, last, Tb, pg, srec[wv], sface[wv], nullptr, grad_acc, sig_acc,
-                           persp_acc, &nin, snrm[wv]);
+  if constexpr (COOP) {
+    __shared__ float4 srec[kSpan * 6];
+    __shared__ uint32_t sface[kSpan];
+    __shared__ float4 snrm[normal_mode<SM>() ? kSpan : 1];
+    __shared__ int sint[4];
+    backward_walk<SM, true>(c, records, pairs, sigma, last, Tb, pg, srec, sface, sint, grad_acc, sig_acc, persp_acc,
+                            &nin, snrm);
+  } else {
+    __shared__ float4 srec[kWaves][kBatch * 6];
+    __shared__ uint32_t sface[kWaves][kBatch];
+    __shared__ float4 snrm[kWaves][normal_mode<SM>() ? kBatch : 1];
+    backward_walk<SM, false>(c, records, pairs, sigma, last, Tb, pg, srec[wv], sface[wv], nullptr, grad_acc, sig_acc,
+                             persp_acc, &nin, snrm[wv]);
+  }
 }
 
 // Fused training kernel: forward walk, L1 seeds of eqs. 8-10 (the D-SSIM term needs whole
@@ -1361,6 +1391,12 @@ static int sigma_mode(const ViewTable& vt, const tsr_params& p) {
 
 static unsigned tile_grid(int n_tiles) { return 8u * (unsigned)((n_tiles + 7) / 8); }
 
+// Staging of the separate forward and backward kernels: cooperative for several views (their
+// records outgrow the caches, and one shared copy per tile is read instead of four), per wave
+// for one (measured on an MI355X at 1200x680 with 1M faces: 8 views 0.32 -> 0.28 ms forward and
+// 0.72 -> 0.70 ms backward cooperatively, one view 0.068 -> 0.074 ms forward).
+static bool separate_coop(const ViewTable& vt) { return vt.n_views > 1; }
+
 // Per-face screen statistics of binned views: the same front-to-back walk and blending
 // decisions as the forward pass (one wave per 8x8 quadrant, per-wave staging).  Each pixel
 // counts 1 for the coverage of the face with the largest blending weight alpha T along its
@@ -1461,7 +1497,13 @@ hipError_t launch_forward(const ViewTable& vt, const tsr_params& p, const WsLayo
   if (nc)
     nin = NormalIn{reinterpret_cast<const float4*>(nc->face_normal), nullptr, nc->map, nc->poses, nc->target,
                    nullptr, nc->part, nc->w_norm, vt.n_faces};
-#define TSR_FWD(S) TSR_LAUNCH("blend_fwd", k_blend_fwd<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, trans, n_last, t_last, border, nin)
+  const bool coop = separate_coop(vt);
+#define TSR_FWD(S)                                                                                 \
+  {                                                                                                \
+    auto kf = coop ? k_blend_fwd<S, true> : k_blend_fwd<S, false>;                                 \
+    TSR_LAUNCH("blend_fwd", kf, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, p.t_min, color, depth, \
+               trans, n_last, t_last, border, nin);                                                \
+  }
   if (nc) {
     TSR_NORMAL_SWITCH(sigma_mode(vt, p) | 16, TSR_FWD)
   } else {
@@ -1512,7 +1554,13 @@ hipError_t launch_backward(const tsr_scene_dev& sc, const float* poses, const Vi
     if (nc)
       nin = NormalIn{reinterpret_cast<const float4*>(nc->face_normal), reinterpret_cast<float4*>(nc->grad), nullptr,
                      nc->poses, nc->target, nc->count, nullptr, nc->w_norm, vt.n_faces};
-#define TSR_BWD(S) TSR_LAUNCH("blend_bwd", k_blend_bwd<S>, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, n_last, t_last, gcolor, gdepth, gtrans, grad_acc, sig_acc, persp_acc, border, nin)
+    const bool coop = separate_coop(vt);
+#define TSR_BWD(S)                                                                                 \
+  {                                                                                                \
+    auto kb = coop ? k_blend_bwd<S, true> : k_blend_bwd<S, false>;                                 \
+    TSR_LAUNCH("blend_bwd", kb, grid, block, 0, st, vt, records, pairs, ranges, p.sigma, n_last, t_last, gcolor, \
+               gdepth, gtrans, grad_acc, sig_acc, persp_acc, border, nin);                         \
+  }
     if (nc) {
       TSR_NORMAL_SWITCH(sm | 16, TSR_BWD)
     } else {
