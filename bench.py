@@ -58,6 +58,8 @@ def parse():
                     help="bin with the tight triangle-tile test (same images and gradients, shorter lists)")
     ap.add_argument("--serve-warmup", type=int, default=500)
     ap.add_argument("--only-single", action="store_true", help="skip the unfused and batched legs")
+    ap.add_argument("--only-window", action="store_true",
+                    help="time only the 8-view mapping window (fused L1 step and the whole mapping energy)")
     ap.add_argument("--only-photometric", action="store_true",
                     help="after the headline step, time only the full photometric step (D-SSIM term)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default tile schedule (no autotuning)")
@@ -475,6 +477,65 @@ def cpu_baseline(w, n_pix, seed=7):
                 "reference_binner_1200x680_1M": {"s": t_bin, "note": "orc_bin: FP64 projection, pairs, std sort"}}}
 
 
+def batched_leg(args, raster, scenes, dev, w):
+    """The 8-view mapping window over the headline map: the fused L1 step over every (view, tile)
+    (autotuned schedule) and the whole mapping energy (D-SSIM photometric and depth terms, E_equi
+    and E_norm against the sensor normals of the target depth), with one binning and, for
+    comparison, with the normal loss binned on its own."""
+    import torch
+
+    g = scenes.rng(5500)
+    bposes = scenes.room_trajectory(g, args.views)
+    btargets = [scenes.perturb_pose(p, g) for p in bposes]
+    bcase = Case(raster, scenes, dev, bposes, [w.intr[0]] * args.views, btargets, tight_tiles=args.tight_tiles)
+    Eb, Kb, mvb, maxb, meanb = bcase.evaluations()
+    btuned = None
+    if not args.no_tune:
+        from paper_2605_31419_amd import autotune
+        bbest, btimes = autotune.tune(bcase.rast, bcase.poses, bcase.tc, bcase.td, reps=3)
+        bcase.rast.schedule = bbest
+        btuned = {"schedule": list(bbest), "candidates_ms": {k: round(v, 4) for k, v in btimes.items()}}
+        log(f"[bench] batched autotuned schedule {bbest}: {json.dumps(btuned['candidates_ms'])}")
+    bst = step_stats(bcase.step, max(10, args.steps // 2), args.warmup)
+    msb = bst["mean"]
+    bcase.check()
+    ktb, _ = kernel_times(bcase.step, max(2, args.profile_steps // 2))
+    batched = {"n_views": args.views, "ms_per_step": msb, "step_stats_ms": bst,
+               "mpix_s": bcase.pixels / (msb * 1e-3) / 1e6,
+               "K": Kb, "visible": mvb, "max_list": maxb, "mean_list": meanb,
+               "kernels_ms": {k: round(v, 4) for k, v in ktb.items()}, "schedule": btuned}
+    log(f"[bench] batched {args.views} views: {msb:.3f} ms -> {batched['mpix_s']:.1f} Mpix/s")
+    # the whole mapping energy over the same window: D-SSIM photometric term and depth L1,
+    # E_equi and E_norm against the sensor normals of the target depth; one binning with the
+    # normals as extra channels of the walks, and (for comparison) the normal loss as a
+    # step of its own with a second binning
+    from paper_2605_31419_amd.window import MappingWindow
+    from paper_2605_31419_amd import _lib
+    bintr = [w.intr[0]] * args.views
+    tnorm = raster.sensor_normals(bcase.td, bintr)
+    energy = {"weights": {"ssim": 0.2, "depth": 0.05, "equi": 1.2, "norm": 0.05}}
+    for fused in (True, False):
+        win = MappingWindow(dev, bintr, w_ssim=0.2, w_equi=1.2, w_norm=0.05, fused_mapping=fused)
+        win.prepare(bcase.poses)
+        map_step = lambda: win.step(bcase.poses, bcase.tc, bcase.td, target_normals=tnorm)
+        msm = time_steps(map_step, max(5, args.steps // 4), args.warmup)
+        _lib.check(win.rast.lib.tsr_check(raster._ptr(win.rast.ws), raster._stream(), None), "tsr_check")
+        if fused:
+            ktm, _ = kernel_times(map_step, max(2, args.profile_steps // 2))
+            energy.update({"ms_per_step": msm, "mpix_s": bcase.pixels / (msm * 1e-3) / 1e6,
+                           "kernels_ms": {k: round(v, 4) for k, v in ktm.items()}})
+            log(f"[bench] mapping energy over {args.views} views, one binning: {msm:.3f} ms")
+        else:
+            energy["separate_normal_step_ms"] = msm
+            log(f"[bench] mapping energy over {args.views} views, normal loss binned separately: {msm:.3f} ms")
+        del win
+    batched["mapping_energy"] = energy
+    del tnorm
+    del bcase
+    torch.cuda.empty_cache()
+    return batched
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -489,6 +550,11 @@ def main():
     log(f"[bench] generating the {args.faces}-face room soup")
     w = scenes.workload("track_1200x680_1M", n_faces=args.faces)
     dev = raster.DeviceScene.from_numpy(w.scene)
+    if args.only_window:
+        batched = batched_leg(args, raster, scenes, dev, w)
+        print(json.dumps({"metric": f"mapping window: {args.views} views of 1200x680, fwd+bwd Mpix/s",
+                          "value": batched["mpix_s"], "unit": "Mpix/s", "batched": batched}), flush=True)
+        return
     single = Case(raster, scenes, dev, w.poses, w.intr, w.target_poses, tight_tiles=args.tight_tiles)
     E, K, m_vis, maxlen, meanlen = single.evaluations()
     log(f"[bench] single view: K={K} visible={m_vis} max list {maxlen} mean {meanlen:.1f} evals {E}")
@@ -588,55 +654,7 @@ def main():
 
     batched = None
     if not args.no_batched:
-        g = scenes.rng(5500)
-        bposes = scenes.room_trajectory(g, args.views)
-        btargets = [scenes.perturb_pose(p, g) for p in bposes]
-        bcase = Case(raster, scenes, dev, bposes, [w.intr[0]] * args.views, btargets, tight_tiles=args.tight_tiles)
-        Eb, Kb, mvb, maxb, meanb = bcase.evaluations()
-        btuned = None
-        if not args.no_tune:
-            from paper_2605_31419_amd import autotune
-            bbest, btimes = autotune.tune(bcase.rast, bcase.poses, bcase.tc, bcase.td, reps=3)
-            bcase.rast.schedule = bbest
-            btuned = {"schedule": list(bbest), "candidates_ms": {k: round(v, 4) for k, v in btimes.items()}}
-            log(f"[bench] batched autotuned schedule {bbest}: {json.dumps(btuned['candidates_ms'])}")
-        bst = step_stats(bcase.step, max(10, args.steps // 2), args.warmup)
-        msb = bst["mean"]
-        bcase.check()
-        ktb, _ = kernel_times(bcase.step, max(2, args.profile_steps // 2))
-        batched = {"n_views": args.views, "ms_per_step": msb, "step_stats_ms": bst,
-                   "mpix_s": bcase.pixels / (msb * 1e-3) / 1e6,
-                   "K": Kb, "visible": mvb, "max_list": maxb, "mean_list": meanb,
-                   "kernels_ms": {k: round(v, 4) for k, v in ktb.items()}, "schedule": btuned}
-        log(f"[bench] batched {args.views} views: {msb:.3f} ms -> {batched['mpix_s']:.1f} Mpix/s")
-        # the whole mapping energy over the same window: D-SSIM photometric term and depth L1,
-        # E_equi and E_norm against the sensor normals of the target depth; one binning with the
-        # normals as extra channels of the walks, and (for comparison) the normal loss as a
-        # step of its own with a second binning
-        from paper_2605_31419_amd.window import MappingWindow
-        from paper_2605_31419_amd import _lib
-        bintr = [w.intr[0]] * args.views
-        tnorm = raster.sensor_normals(bcase.td, bintr)
-        energy = {"weights": {"ssim": 0.2, "depth": 0.05, "equi": 1.2, "norm": 0.05}}
-        for fused in (True, False):
-            win = MappingWindow(dev, bintr, w_ssim=0.2, w_equi=1.2, w_norm=0.05, fused_mapping=fused)
-            win.prepare(bcase.poses)
-            map_step = lambda: win.step(bcase.poses, bcase.tc, bcase.td, target_normals=tnorm)
-            msm = time_steps(map_step, max(5, args.steps // 4), args.warmup)
-            _lib.check(win.rast.lib.tsr_check(raster._ptr(win.rast.ws), raster._stream(), None), "tsr_check")
-            if fused:
-                ktm, _ = kernel_times(map_step, max(2, args.profile_steps // 2))
-                energy.update({"ms_per_step": msm, "mpix_s": bcase.pixels / (msm * 1e-3) / 1e6,
-                               "kernels_ms": {k: round(v, 4) for k, v in ktm.items()}})
-                log(f"[bench] mapping energy over {args.views} views, one binning: {msm:.3f} ms")
-            else:
-                energy["separate_normal_step_ms"] = msm
-                log(f"[bench] mapping energy over {args.views} views, normal loss binned separately: {msm:.3f} ms")
-            del win
-        batched["mapping_energy"] = energy
-        del tnorm
-        del bcase
-        torch.cuda.empty_cache()
+        batched = batched_leg(args, raster, scenes, dev, w)
 
     sigma_half = None
     if not args.no_sigma_half:
