@@ -351,8 +351,10 @@ __device__ __forceinline__ int wave_expand_count(int cnt, F&& fn) {
 // pre-test on every lane rejects faces that are certainly culled; the remaining candidates
 // of the workgroup are compacted onto the first lanes, which run the exact FP64 setup (the
 // visibility decision, the pixel rectangle and, for visible faces, the record).
+// Four workgroups per CU: the FP64 setup then fits its registers without spilling (six
+// spilled 28 registers to scratch and took 57 us against 48 us at 1200x680 with 1M faces).
 template <bool TIGHT>
-__global__ __launch_bounds__(256, 6) void k_project(tsr_scene_dev sc, const float* __restrict__ poses, ViewTable vt,
+__global__ __launch_bounds__(256, 4) void k_project(tsr_scene_dev sc, const float* __restrict__ poses, ViewTable vt,
                                                  float z_near, float r_min, float sigma, int persp,
                                                  uint32_t* __restrict__ counts,
                                                  float* __restrict__ records, uint32_t* __restrict__ tile_cnt,
@@ -499,9 +501,9 @@ __global__ __launch_bounds__(256, 6) void k_project(tsr_scene_dev sc, const floa
 // visible list); (1) exclusive scan of the tile counts into ranges, pair total K, overflow check against the capacity (all
 // ranges empty on overflow), the small-face counts left in tile_cnt2 as the base of the
 // larger faces' emission cursors, and the list of tiles too long for the one-wave sort.  Both
-// scans run in rounds of kScanRound entries, each thread taking kScanPer consecutive ones (12:
-// the most the 128 registers of a 1024-thread workgroup hold without spilling).
-constexpr int kScanPer = 12;
+// scans run in rounds of kScanRound entries, each thread taking kScanPer consecutive ones (10:
+// with 12 the 128 registers of a 1024-thread workgroup spill).
+constexpr int kScanPer = 10;
 constexpr int kScanRound = 1024 * kScanPer;
 
 __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* __restrict__ tile_cnt, uint32_t* __restrict__ ranges,

@@ -378,22 +378,22 @@ MappingScratch mapping_scratch(size_t ssim_bytes, int64_t n_faces, int64_t n_til
 
 // Per view, the forward's per-wave normal-loss sums in FP64: the valid-pixel count, the loss
 // sum, and the rotation term sum_p N x dE/dN = -(w_norm / count) sum_p N x N_bar, in the layout
-// k_normal_finish reads.  One 1024-thread workgroup per view, four slots per thread in flight;
+// k_normal_finish reads.  One 256-thread workgroup per view, four slots per thread in flight;
 // overwrites count and acc.
-__global__ __launch_bounds__(1024) void k_normal_reduce(ViewTable vt, const float* __restrict__ part, float w_norm,
-                                                        uint32_t* __restrict__ count, double* __restrict__ acc) {
-  __shared__ double red[5][16];
+__global__ __launch_bounds__(256) void k_normal_reduce(ViewTable vt, const float* __restrict__ part, float w_norm,
+                                                       uint32_t* __restrict__ count, double* __restrict__ acc) {
+  __shared__ double red[4];
   const int v = blockIdx.x;
   const ViewDesc vd = vt.v[v];
   const int64_t w0 = (int64_t)vd.tile_off * kTileQuads;
   const int64_t w1 = w0 + (int64_t)vd.tiles_x * vd.tiles_y * kTileQuads;
   double s[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   static_assert(kNormalPart == 8, "a slot is two float4");
-  for (int64_t base = w0; base < w1; base += 4 * 1024) {
+  for (int64_t base = w0; base < w1; base += 4 * 256) {
     float4 a[4], b[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int64_t w = base + u * 1024 + threadIdx.x;
+      const int64_t w = base + u * 256 + threadIdx.x;
       const float4* p = reinterpret_cast<const float4*>(part + kNormalPart * w);
       a[u] = w < w1 ? p[0] : make_float4(0.f, 0.f, 0.f, 0.f);
       b[u] = w < w1 ? p[1] : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -407,20 +407,9 @@ __global__ __launch_bounds__(1024) void k_normal_reduce(ViewTable vt, const floa
       s[4] += (double)b[u].x;
     }
   }
-#pragma unroll
-  for (int k = 0; k < 5; ++k)
-    for (int o = 32; o > 0; o >>= 1) s[k] += __shfl_xor(s[k], o, 64);
-  if ((threadIdx.x & 63) == 0)
-#pragma unroll
-    for (int k = 0; k < 5; ++k) red[k][threadIdx.x >> 6] = s[k];
-  __syncthreads();
   double tot[5];
 #pragma unroll
-  for (int k = 0; k < 5; ++k) {
-    double t = 0.0;
-    for (int w = 0; w < 16; ++w) t += red[k][w];
-    tot[k] = t;
-  }
+  for (int k = 0; k < 5; ++k) tot[k] = block_sum256(s[k], red);
   if (threadIdx.x == 0) {
     const uint32_t cn = (uint32_t)tot[0];
     const float inv = cn ? w_norm / (float)cn : 0.f;
@@ -456,7 +445,7 @@ hipError_t launch_train_mapping(const tsr_scene_dev& sc, const float* poses, con
                           part, w_norm};
   hipError_t e = launch_forward(vt, p, L, ws, color, depth, trans, st, &fc);
   if (e != hipSuccess) return e;
-  TSR_LAUNCH("normal_reduce", k_normal_reduce, dim3(vt.n_views), dim3(1024), 0, st, vt, part, w_norm, count, acc);
+  TSR_LAUNCH("normal_reduce", k_normal_reduce, dim3(vt.n_views), dim3(256), 0, st, vt, part, w_norm, count, acc);
   float *gc = nullptr, *gd = nullptr;
   e = launch_photo_seeds(t, color, target_color, depth, target_depth, w_ssim, p.w_color, p.w_depth, loss, scratch,
                          &gc, &gd, st);
