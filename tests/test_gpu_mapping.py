@@ -217,3 +217,50 @@ def test_indexed_meshes_are_refused():
     z3, z1 = torch.zeros(3 * n, device="cuda"), torch.zeros(n, device="cuda")
     with pytest.raises(RuntimeError):
         rast.train_mapping(p, z3, z1, z3)
+
+
+def test_mapping_step_replays_from_a_captured_graph():
+    """The one-binning mapping step with E_equi (binning, forward with the normal channels, the
+    D-SSIM stencils, the normal reduction, backward, chain, regulariser) captured in a HIP graph:
+    the window's outputs are overwritten with NaN between replays, and every replay gives the
+    eager step's losses and gradients (up to the order of the floating-point atomics)."""
+    from paper_2605_31419_amd.window import MappingWindow
+    _say("[mapping] graph capture, 3 views of a 20k-face room at 160x120")
+    sc = S.room_soup(41, 20_000, size_range=(0.01, 0.08))
+    dev = raster.DeviceScene.from_numpy(sc)
+    g = S.rng(42)
+    poses = raster.poses_tensor([S.random_room_pose(g) for _ in range(3)])
+    intrs = [S.intrinsics_for(160, 120)] * 3
+    P = 3 * 160 * 120
+    gt = np.random.default_rng(43)
+    tc = G.to_dev(gt.uniform(0, 1, 3 * P))
+    td = G.to_dev(gt.uniform(0.5, 4.0, P))
+    tn = raster.sensor_normals(td, intrs)
+    win = MappingWindow(dev, intrs, w_ssim=W_SSIM, w_equi=1.2, w_norm=W_NORM)
+    win.prepare(poses)
+    eager = [x.clone() for x in win.step(poses, tc, td, target_normals=tn)]
+    eloss = [win.loss.clone(), win.norm_loss.clone(), win.equi_loss.clone()]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        win.step(poses, tc, td, target_normals=tn)          # warm-up on the capture stream's kind
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        out = win.step(poses, tc, td, target_normals=tn)
+    for rep in range(3):
+        for x in list(out) + [win.loss, win.norm_loss, win.equi_loss, win.color]:
+            x.fill_(float("nan"))
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        from paper_2605_31419_amd import _lib
+        _lib.check(win.rast.lib.tsr_check(raster._ptr(win.rast.ws), raster._stream(), None), "tsr_check")
+        for a, b in zip([win.loss, win.norm_loss, win.equi_loss], eloss):
+            np.testing.assert_allclose(a.cpu().numpy(), b.cpu().numpy(), rtol=1e-6, atol=1e-9)
+        for nm, a, b in zip(["grad_pos", "grad_col", "grad_opa", "grad_pose"], out, eager):
+            ok, msg, _ = grad_close(a.cpu().numpy().astype(np.float64), b.cpu().numpy().astype(np.float64), name=nm)
+            if rep == 0:
+                _say("  " + msg)
+            assert ok, (rep, msg)
