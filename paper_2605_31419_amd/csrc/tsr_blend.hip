@@ -12,6 +12,7 @@ namespace tsr {
 
 constexpr int kBatch = 64;                 // faces per hit mask (one lane each)
 constexpr int kSpan = 256;                 // faces staged at once by a cooperative workgroup
+constexpr int kSepSpan = 128;              // ... in the separate forward and backward kernels
 constexpr int kWaves = kBlock / kWave;     // waves per workgroup: one per 8x8 quadrant
 
 // Tiles whose list is longer than this many faces raise their wave priority (0 = off).  The
@@ -190,6 +191,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // Cooperative kernels always run kBlock threads; the staging loops below stride by kBlock, so
 // a span of any length up to kSpan is staged completely (every entry's face id and record).
 static_assert(kSpan % kBatch == 0 && kSpan >= kBatch, "a staged span is walked as whole 64-face batches");
+static_assert(kSepSpan % kBatch == 0 && kSepSpan >= kBatch && kSepSpan <= kSpan, "as kSpan");
 static_assert(kSpan * (6 * sizeof(float4) + sizeof(uint32_t)) <= 48 * 1024, "a staged span fits the LDS budget");
 static_assert(kWaves * kWave == kBlock && kWaves == 4, "one wave per 8x8 quadrant of a 16x16 tile");
 static_assert(kGradDwords == 20, "normal channels: record terms in slots 0-19 of the 24-value wave sum");
@@ -298,7 +300,7 @@ __device__ __forceinline__ bool live(float T, float t_min) { return T >= t_min &
 // Front-to-back walk over the tile list (eq. 4).  A pixel stops after the face that takes
 // its transmittance below t_min.  Records each pixel's last blended face and the
 // transmittance just before it.
-template <int SM, bool COOP>
+template <int SM, bool COOP, int SPAN = kSpan>
 __device__ __forceinline__ void forward_walk(const TileCtx& c, const float* __restrict__ records,
                                              const uint64_t* __restrict__ pairs, float sigma, float t_min,
                                              float4* srec, uint32_t* sface, FwdState& s,
@@ -307,7 +309,7 @@ __device__ __forceinline__ void forward_walk(const TileCtx& c, const float* __re
   s.C0 = s.C1 = s.C2 = s.D = 0.f; s.Tb = 1.f; s.last = -1;
   s.N0 = s.N1 = s.N2 = 0.f;
   const float dxb = (float)c.px, dyb = (float)c.py;
-  constexpr int kStage = COOP ? kSpan : kBatch;     // faces staged at once
+  constexpr int kStage = COOP ? SPAN : kBatch;      // faces staged at once
   for (uint32_t s0 = c.start; s0 < c.end; s0 += kStage) {
     const int ns = (int)min((uint32_t)kStage, c.end - s0);
     if constexpr (COOP) {
@@ -376,7 +378,7 @@ struct PixGrad {
 // S = gC.B + gD BD - gT BA, so S is carried instead: with P = gC.c + gD z - gT for the face,
 // dL/dalpha = T (P - S) and S <- alpha P + (1 - alpha) S.  Per-face sums of the 20
 // record-parameter gradients are reduced over the wave and added to grad_acc.
-template <int SM, bool COOP>
+template <int SM, bool COOP, int SPAN = kSpan>
 __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __restrict__ records,
                                               const uint64_t* __restrict__ pairs, float sigma, int last, float Tb,
                                               const PixGrad& pg, float4* srec, uint32_t* sface, int* sint,
@@ -402,7 +404,7 @@ __device__ __forceinline__ void backward_walk(const TileCtx& c, const float* __r
   float Tcur = Tb;
   float S = 0.f;
   const float dxb = (float)c.px, dyb = (float)c.py;
-  constexpr int kStage = COOP ? kSpan : kBatch;     // faces staged at once
+  constexpr int kStage = COOP ? SPAN : kBatch;      // faces staged at once
   for (int s1 = top + 1; s1 > (int)c.start; s1 -= kStage) {
     const int s0 = max((int)c.start, s1 - kStage);
     const int ns = s1 - s0;
@@ -556,10 +558,10 @@ __global__ __launch_bounds__(kBlock) void k_blend_fwd(ViewTable vt, const float*
   tile_ctx(vt, ranges, tile, wv, c);
   FwdState s;
   if constexpr (COOP) {
-    __shared__ float4 srec[kSpan * 6];
-    __shared__ uint32_t sface[kSpan];
-    __shared__ float4 snrm[normal_mode<SM>() ? kSpan : 1];
-    forward_walk<SM, true>(c, records, pairs, sigma, t_min, srec, sface, s, &nin, snrm);
+    __shared__ float4 srec[kSepSpan * 6];
+    __shared__ uint32_t sface[kSepSpan];
+    __shared__ float4 snrm[normal_mode<SM>() ? kSepSpan : 1];
+    forward_walk<SM, true, kSepSpan>(c, records, pairs, sigma, t_min, srec, sface, s, &nin, snrm);
   } else {
     __shared__ float4 srec[kWaves][kBatch * 6];
     __shared__ uint32_t sface[kWaves][kBatch];
@@ -658,12 +660,12 @@ __global__ __launch_bounds__(kBlock) void k_blend_bwd(ViewTable vt, const float*
     }
   }
   if constexpr (COOP) {
-    __shared__ float4 srec[kSpan * 6];
-    __shared__ uint32_t sface[kSpan];
-    __shared__ float4 snrm[normal_mode<SM>() ? kSpan : 1];
+    __shared__ float4 srec[kSepSpan * 6];
+    __shared__ uint32_t sface[kSepSpan];
+    __shared__ float4 snrm[normal_mode<SM>() ? kSepSpan : 1];
     __shared__ int sint[4];
-    backward_walk<SM, true>(c, records, pairs, sigma, last, Tb, pg, srec, sface, sint, grad_acc, sig_acc, persp_acc,
-                            &nin, snrm);
+    backward_walk<SM, true, kSepSpan>(c, records, pairs, sigma, last, Tb, pg, srec, sface, sint, grad_acc, sig_acc,
+                                      persp_acc, &nin, snrm);
   } else {
     __shared__ float4 srec[kWaves][kBatch * 6];
     __shared__ uint32_t sface[kWaves][kBatch];
@@ -1394,7 +1396,9 @@ static unsigned tile_grid(int n_tiles) { return 8u * (unsigned)((n_tiles + 7) / 
 // Staging of the separate forward and backward kernels: cooperative for several views (their
 // records outgrow the caches, and one shared copy per tile is read instead of four), per wave
 // for one (measured on an MI355X at 1200x680 with 1M faces: 8 views 0.32 -> 0.28 ms forward and
-// 0.72 -> 0.70 ms backward cooperatively, one view 0.068 -> 0.074 ms forward).
+// 0.72 -> 0.70 ms backward cooperatively, one view 0.068 -> 0.074 ms forward).  Their spans are
+// 128 faces (the fused kernel's 256 would cap them at five workgroups per CU by LDS; the 8-view
+// mapping step took 1.98 ms with 256, 1.90 with 192 and 1.89 with 128).
 static bool separate_coop(const ViewTable& vt) { return vt.n_views > 1; }
 
 // Per-face screen statistics of binned views: the same front-to-back walk and blending
