@@ -251,3 +251,94 @@ def test_fullsize_separate_backward_region_seeds(name):
         ok, msg, bad = grad_close(a, b, name=nm, cond=cond)
         _say(f"  {msg}")
         assert ok, msg
+
+
+@pytest.mark.parametrize("name", ["track_1200x680_1M", "window_8x1200x680"])
+def test_fullsize_mapping_normal_term_regions(name):
+    """The one-binning mapping step at full size with only its normal term (L1 and D-SSIM
+    weights 0), target normals valid only inside the sampled faces' rectangles: the normal map
+    there, the normal loss and every position, opacity and pose gradient equal the normal
+    reference over those pixels (the rasteriser backward of the normal-coloured soup, the
+    normalised-cross-product chain and the rotation term); the colour gradients are exactly 0."""
+    from oracle import normals as NR
+    _say(f"[fullsize mapping, normal term] case={name}")
+    w = _workload(name)
+    g = np.random.default_rng(91)
+    faces = _sample_faces(w, g)
+    w_norm = 0.05
+    ns = NR.normal_scene(w.scene)
+    N = w.scene.n_vertices
+    tn, regions, nbars = [], [], []
+    for v in range(len(w.poses)):
+        intr = w.intr[v]
+        P = intr.width * intr.height
+        qv, fv, rv, tv = O.project(w.scene, w.poses[v], intr)
+        reg = [_rect_pixels(rv, m, intr.width) for m in faces if tv[m] > 0]
+        reg = np.unique(np.concatenate(reg)) if reg else np.zeros(0, np.int64)
+        nb = g.normal(size=(3, reg.size))
+        nb /= np.linalg.norm(nb, axis=0)
+        t = np.zeros((3, P), np.float32)
+        t[:, reg] = nb
+        tn.append(t)
+        regions.append(reg)
+        nbars.append(t[:, reg].astype(np.float64))
+    ref_p, ref_o = np.zeros((3, N)), np.zeros(N)
+    abs_p, abs_o = np.zeros((3, N)), np.zeros(N)
+    gcol_n = np.zeros((3, N))
+    ref_pose, ref_loss, ref_maps = [], [], []
+    for v in range(len(w.poses)):
+        reg, nb = regions[v], nbars[v]
+        R = np.asarray(w.poses[v], np.float64).reshape(12)[:9].reshape(3, 3)
+        if reg.size == 0:
+            ref_pose.append(np.zeros(6)); ref_loss.append(0.0); ref_maps.append(None)
+            continue
+        gN = -(w_norm / reg.size) * nb
+        rp, rc, ro, rpose, (ap, ac, ao) = O.backward(ns, w.poses[v], w.intr[v], R.T @ gN, np.zeros(reg.size), None,
+                                                     pixels=reg, with_abs=True)
+        ref_p += rp; ref_o += ro; abs_p += ap; abs_o += ao; gcol_n += rc
+        Nmap = R @ O.render(ns, w.poses[v], w.intr[v], pixels=reg)[0]
+        rpose = np.array(rpose, np.float64).reshape(6)
+        rpose[3:] += np.sum(np.cross(Nmap, gN, axis=0), axis=1)
+        ref_pose.append(rpose)
+        ref_loss.append(w_norm * float(np.sum(1.0 - np.sum(Nmap * nb, axis=0))) / reg.size)
+        ref_maps.append(Nmap)
+    # the face-normal gradients (sums of the vertex-colour gradients) through n = c / |c|
+    pos = np.asarray(w.scene.pos, np.float64)
+    e1, e2 = pos[:, 1::3] - pos[:, 0::3], pos[:, 2::3] - pos[:, 0::3]
+    cr = np.cross(e1, e2, axis=0)
+    L = np.linalg.norm(cr, axis=0)
+    ok = L > 0
+    n = np.where(ok, cr / np.where(ok, L, 1.0), 0.0)
+    gn = gcol_n[:, 0::3] + gcol_n[:, 1::3] + gcol_n[:, 2::3]
+    gc = np.where(ok, (gn - n * np.sum(n * gn, axis=0)) / np.where(ok, L, 1.0), 0.0)
+    ge1, ge2 = np.cross(e2, gc, axis=0), np.cross(gc, e1, axis=0)
+    ref_p[:, 1::3] += ge1
+    ref_p[:, 2::3] += ge2
+    ref_p[:, 0::3] -= ge1 + ge2
+    rast = raster.Rasterizer(raster.DeviceScene.from_numpy(w.scene), w.intr,
+                             raster.Params(w_color=0.0, w_depth=0.0))
+    p = raster.poses_tensor(w.poses)
+    rast.fit(p)
+    rast.bin_and_sort(p)
+    Ptot = rast.total_pixels
+    nmap = torch.empty(3 * Ptot, device="cuda")
+    nloss = torch.empty(len(w.poses), device="cuda")
+    tc = torch.full((3 * Ptot,), 0.5, device="cuda")
+    td = torch.full((Ptot,), 2.0, device="cuda")
+    out = rast.train_mapping(p, tc, td, G.to_dev(np.concatenate([t.reshape(-1) for t in tn])), w_ssim=0.0,
+                             w_norm=w_norm, normal_map=nmap, loss_norm=nloss)
+    torch.cuda.synchronize()
+    gp, gcol, go, gpose = [x.cpu().numpy().astype(np.float64) for x in out]
+    assert np.all(gcol == 0.0)
+    np.testing.assert_allclose(nloss.cpu().numpy(), ref_loss, rtol=1e-5, atol=1e-9)
+    maps = G.per_view(rast, nmap.cpu().numpy(), 3)
+    for v in range(len(w.poses)):
+        if ref_maps[v] is not None:
+            err = np.abs(maps[v][:, regions[v]] - ref_maps[v]).max()
+            assert err <= 1e-5, (v, err)
+    _say(f"  regions: {[int(r.size) for r in regions]} pixels; losses {nloss.cpu().numpy()}")
+    for nm, a, b, cond in zip(["grad_pos", "grad_opa", "grad_pose"], [gp, go, gpose],
+                              [ref_p, ref_o, np.concatenate(ref_pose)], [abs_p, abs_o, None]):
+        ok_, msg, _ = grad_close(a.reshape(-1), b.reshape(-1), name=nm, cond=None if cond is None else cond.reshape(-1))
+        _say("  " + msg)
+        assert ok_, msg
