@@ -40,6 +40,19 @@ struct SsimTile {
   int64_t plane;          // offset of this channel plane in the packed colour arrays
 };
 
+// Workgroups are dealt round-robin to the 8 XCDs: each XCD gets a contiguous range of tiles
+// (grid padded to a multiple of 8), so the halo a tile shares with the tiles above and below
+// it is read through the same L2.  Returns the tile (channel-major over the views) or -1.
+__device__ __forceinline__ int ssim_block(const SsimTable& t) {
+  const int total = t.blk_off[t.n_views];
+  const int per = (total + 7) >> 3;
+  const int idx = (int)(blockIdx.x >> 3);
+  const int b = (int)(blockIdx.x & 7) * per + idx;
+  return (idx < per && b < total) ? b : -1;
+}
+
+static unsigned ssim_grid(const SsimTable& t) { return 8u * (unsigned)((t.blk_off[t.n_views] + 7) / 8); }
+
 __device__ __forceinline__ SsimTile ssim_tile(const SsimTable& t, int b) {
   SsimTile s;
   int v = 0;
@@ -149,7 +162,9 @@ __global__ __launch_bounds__(256) void k_ssim_stats(const float* __restrict__ co
   __shared__ __align__(16) float in[2][kSsimIH][kSsimLW];
   __shared__ float hs[5][kSsimIH][kSsimTW];
   __shared__ double red[4];
-  const SsimTile s = ssim_tile(t, blockIdx.x);
+  const int b = ssim_block(t);
+  if (b < 0) return;                       // whole workgroup
+  const SsimTile s = ssim_tile(t, b);
   const float* src[2] = {color, target};
   ssim_stage<2>(s, src, in);
   __syncthreads();
@@ -212,7 +227,7 @@ __global__ __launch_bounds__(256) void k_ssim_stats(const float* __restrict__ co
   for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
   __syncthreads();
-  if (threadIdx.x == 0) partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  if (threadIdx.x == 0) partial[b] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 __global__ __launch_bounds__(256) void k_ssim_grad(const float* __restrict__ color, const float* __restrict__ target,
@@ -220,7 +235,9 @@ __global__ __launch_bounds__(256) void k_ssim_grad(const float* __restrict__ col
                                                    int accumulate, float* __restrict__ grad) {
   __shared__ __align__(16) float in[3][kSsimIH][kSsimLW];
   __shared__ float hs[3][kSsimIH][kSsimTW];
-  const SsimTile s = ssim_tile(t, blockIdx.x);
+  const int b = ssim_block(t);
+  if (b < 0) return;                       // whole workgroup
+  const SsimTile s = ssim_tile(t, b);
   // this thread's outputs: rows r0 .. r0 + 3 of column c; their colour values are loaded first
   const int c = threadIdx.x & (kSsimTW - 1), r0 = (threadIdx.x / kSsimTW) * kSsimBlk;
   const int gx = s.x0 + c;
@@ -265,7 +282,9 @@ __global__ __launch_bounds__(256) void k_photo_seeds(const float* __restrict__ c
   __shared__ __align__(16) float in[3][kSsimIH][kSsimLW];
   __shared__ float hs[3][kSsimIH][kSsimTW];
   __shared__ double red[4];
-  const SsimTile s = ssim_tile(t, blockIdx.x);
+  const int b = ssim_block(t);
+  if (b < 0) return;                       // whole workgroup
+  const SsimTile s = ssim_tile(t, b);
   // this thread's outputs: rows r0 .. r0 + 3 of column c; their colour and depth values are
   // loaded first, so that their latency overlaps the staging
   const int c = threadIdx.x & (kSsimTW - 1), r0 = (threadIdx.x / kSsimTW) * kSsimBlk;
@@ -313,7 +332,7 @@ __global__ __launch_bounds__(256) void k_photo_seeds(const float* __restrict__ c
   for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
   __syncthreads();
-  if (threadIdx.x == 0) l1_partial[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  if (threadIdx.x == 0) l1_partial[b] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
 // loss[v] = w_ssim (1 - sum of SSIM / (3 W H)) + the view's L1 partials (when given).
@@ -412,10 +431,9 @@ hipError_t launch_dssim(const SsimTable& t, const float* color, const float* tar
   const int64_t n3 = 3 * t.n_pixels;
   float* abc = reinterpret_cast<float*>(scratch + z.abc);
   double* partial = reinterpret_cast<double*>(scratch + z.partial);
-  const int blocks = t.blk_off[t.n_views];
-  TSR_LAUNCH("ssim_stats", k_ssim_stats, dim3(blocks), dim3(256), 0, st, color, target, t, abc, n3, partial);
+  TSR_LAUNCH("ssim_stats", k_ssim_stats, dim3(ssim_grid(t)), dim3(256), 0, st, color, target, t, abc, n3, partial);
   if (grad)
-    TSR_LAUNCH("ssim_grad", k_ssim_grad, dim3(blocks), dim3(256), 0, st, color, target, t, abc, n3, weight,
+    TSR_LAUNCH("ssim_grad", k_ssim_grad, dim3(ssim_grid(t)), dim3(256), 0, st, color, target, t, abc, n3, weight,
                accumulate ? 1 : 0, grad);
   if (loss)
     TSR_LAUNCH("ssim_loss", k_ssim_loss, dim3(t.n_views), dim3(1024), 0, st, t, partial, (const double*)nullptr, 1.f,
@@ -433,9 +451,8 @@ hipError_t launch_photo_seeds(const SsimTable& t, const float* color, const floa
   double* l1_partial = reinterpret_cast<double*>(scratch + z.l1_partial);
   *gcolor = reinterpret_cast<float*>(scratch + z.gcolor);
   *gdepth = reinterpret_cast<float*>(scratch + z.gdepth);
-  const int blocks = t.blk_off[t.n_views];
-  TSR_LAUNCH("ssim_stats", k_ssim_stats, dim3(blocks), dim3(256), 0, st, color, target, t, abc, n3, partial);
-  TSR_LAUNCH("photo_seeds", k_photo_seeds, dim3(blocks), dim3(256), 0, st, color, target, depth, tdepth, t, abc, n3,
+  TSR_LAUNCH("ssim_stats", k_ssim_stats, dim3(ssim_grid(t)), dim3(256), 0, st, color, target, t, abc, n3, partial);
+  TSR_LAUNCH("photo_seeds", k_photo_seeds, dim3(ssim_grid(t)), dim3(256), 0, st, color, target, depth, tdepth, t, abc, n3,
              w_ssim, w_color, w_depth, *gcolor, *gdepth, l1_partial);
   if (loss)
     TSR_LAUNCH("ssim_loss", k_ssim_loss, dim3(t.n_views), dim3(1024), 0, st, t, partial, (const double*)l1_partial,
