@@ -72,29 +72,44 @@ __device__ __forceinline__ SsimTile ssim_tile(const SsimTable& t, int b) {
 }
 
 // Stages the tile's window of Q images (zero outside the image) into in[q][row][col]: every
-// load of the thread is issued before the first LDS store, so their latencies overlap.
+// load of the thread is issued before the first LDS store, so their latencies overlap.  Entry
+// i = tid + 256 k sits at row i / 42, column i % 42; from one entry to the thread's next the
+// row advances by 6 and the column by 4 (256 = 6 * 42 + 4), so no division is repeated, and a
+// window wholly inside the image (most tiles) skips the per-entry bounds tests.
 constexpr int kSsimStageIters = (kSsimIH * kSsimIW + 255) / 256;
+static_assert(kSsimIW == 42 && 256 == 6 * kSsimIW + 4, "staging steps of 6 rows and 4 columns");
 
 template <int Q>
 __device__ __forceinline__ void ssim_stage(const SsimTile& s, const float* const* src, float (*in)[kSsimIH][kSsimLW]) {
+  const int x0 = s.x0 - kSsimR, y0 = s.y0 - kSsimR;
+  const bool interior = x0 >= 0 && y0 >= 0 && x0 + kSsimIW <= s.W && y0 + kSsimIH <= s.H;   // workgroup-uniform
+  const float* base[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) base[q] = src[q] + s.plane;
+  int r = (int)threadIdx.x / kSsimIW, c = (int)threadIdx.x - r * kSsimIW;
   float v[kSsimStageIters][Q];
+  int rr[kSsimStageIters], cc[kSsimStageIters];
 #pragma unroll
   for (int it = 0; it < kSsimStageIters; ++it) {
-    const int i = threadIdx.x + 256 * it;
-    const int r = i / kSsimIW, c = i - r * kSsimIW;
-    const int gx = s.x0 - kSsimR + c, gy = s.y0 - kSsimR + r;
-    const bool ld = i < kSsimIH * kSsimIW && gx >= 0 && gx < s.W && gy >= 0 && gy < s.H;
-    const int64_t e = s.plane + (int64_t)gy * s.W + gx;
+    const int gx = x0 + c, gy = y0 + r;
+    const bool ld = r < kSsimIH && (interior || (gx >= 0 && gx < s.W && gy >= 0 && gy < s.H));
+    const int off = gy * s.W + gx;         // < 2^28 for images up to 16384 x 16384
 #pragma unroll
-    for (int q = 0; q < Q; ++q) v[it][q] = ld ? src[q][e] : 0.f;
+    for (int q = 0; q < Q; ++q) v[it][q] = ld ? base[q][off] : 0.f;
+    rr[it] = r;
+    cc[it] = c;
+    c += 4;
+    r += 6;
+    if (c >= kSsimIW) {
+      c -= kSsimIW;
+      ++r;
+    }
   }
 #pragma unroll
   for (int it = 0; it < kSsimStageIters; ++it) {
-    const int i = threadIdx.x + 256 * it;
-    const int r = i / kSsimIW, c = i - r * kSsimIW;
-    if (i < kSsimIH * kSsimIW) {
+    if (rr[it] < kSsimIH) {
 #pragma unroll
-      for (int q = 0; q < Q; ++q) in[q][r][c] = v[it][q];
+      for (int q = 0; q < Q; ++q) in[q][rr[it]][cc[it]] = v[it][q];
     }
   }
 }
