@@ -227,11 +227,12 @@ __global__ __launch_bounds__(256) void k_ssim_stats(const float* __restrict__ co
     const float sxx = m[o][2] - mx * mx, syy = m[o][3] - my * my, sxy = m[o][4] - mx * my;
     const float n1 = 2.f * mx * my + kSsimC1, n2 = 2.f * sxy + kSsimC2;
     const float d1 = mx * mx + my * my + kSsimC1, d2 = sxx + syy + kSsimC2;
+    // one division: 1/d1 = d2 inv and 1/d2 = d1 inv
     const float inv = 1.f / (d1 * d2);
     const float S = n1 * n2 * inv;
-    const float B = -S / d2;
+    const float B = -S * d1 * inv;
     const float C = 2.f * n1 * inv;
-    const float A = 2.f * my * n2 * inv - 2.f * mx * S / d1 - 2.f * mx * B - my * C;
+    const float A = 2.f * my * n2 * inv - 2.f * mx * S * d2 * inv - 2.f * mx * B - my * C;
     const int64_t e = s.plane + (int64_t)gy * s.W + gx;
     abc[e] = A;
     abc[n3 + e] = B;
