@@ -529,6 +529,14 @@ def batched_leg(args, raster, scenes, dev, w):
             energy["separate_normal_step_ms"] = msm
             log(f"[bench] mapping energy over {args.views} views, normal loss binned separately: {msm:.3f} ms")
         del win
+    # the same step at the paper's rendering exponent (sigma = 0.5)
+    win = MappingWindow(dev, bintr, raster.Params(sigma=0.5), w_ssim=0.2, w_equi=1.2, w_norm=0.05)
+    win.prepare(bcase.poses)
+    map_half = lambda: win.step(bcase.poses, bcase.tc, bcase.td, target_normals=tnorm)
+    energy["sigma_0_5_ms_per_step"] = time_steps(map_half, max(5, args.steps // 4), args.warmup)
+    _lib.check(win.rast.lib.tsr_check(raster._ptr(win.rast.ws), raster._stream(), None), "tsr_check")
+    log(f"[bench] mapping energy over {args.views} views at sigma = 0.5: {energy['sigma_0_5_ms_per_step']:.3f} ms")
+    del win
     batched["mapping_energy"] = energy
     del tnorm
     del bcase
