@@ -271,3 +271,35 @@ def test_mapping_step_replays_from_a_captured_graph():
             if rep == 0:
                 _say("  " + msg)
             assert ok, (rep, msg)
+
+
+def test_mapping_step_on_an_empty_soup():
+    """No faces: the image is the background (colour 0, depth 0), the normal map is 0, so every
+    valid pixel adds 1 to the mean of 1 - N.N_bar (normal loss = w_norm), the photometric loss
+    is the oracle's for a background render, and the pose gradient is 0."""
+    from oracle import dssim as D
+    _say("[mapping] empty soup")
+    sc = S.Scene(np.zeros((3, 0), np.float32), np.zeros((3, 0), np.float32), np.zeros(0, np.float32))
+    intr = S.intrinsics_for(64, 48)
+    rast = raster.Rasterizer(raster.DeviceScene.from_numpy(sc), [intr])
+    p = raster.poses_tensor([IDENTITY])
+    rast.bin_and_sort(p)
+    P = intr.width * intr.height
+    g = np.random.default_rng(750)
+    tc = g.uniform(0.1, 1, size=(3, P)).astype(np.float32)
+    td = g.uniform(0.5, 4.0, size=P).astype(np.float32)
+    nb, valid = _normal_targets(751, P)
+    loss = torch.zeros(1, device="cuda")
+    nloss = torch.zeros(1, device="cuda")
+    nmap = torch.full((3 * P,), 7.0, device="cuda")
+    out = rast.train_mapping(p, G.to_dev(tc), G.to_dev(td), G.to_dev(nb), w_ssim=W_SSIM, w_norm=W_NORM,
+                             normal_map=nmap, loss=loss, loss_norm=nloss)
+    torch.cuda.synchronize()
+    oc, od, _ = O.render(sc, IDENTITY, intr)
+    L, _, _ = O.l1_seeds(oc, od, tc, td, P)
+    c3, t3 = np.asarray(oc, np.float64).reshape(3, intr.height, intr.width), tc.astype(np.float64).reshape(3, intr.height, intr.width)
+    lref = L + W_SSIM * D.dssim(c3, t3)
+    np.testing.assert_allclose(float(loss.cpu()[0]), lref, rtol=1e-5, atol=2e-5)
+    np.testing.assert_allclose(float(nloss.cpu()[0]), W_NORM, rtol=1e-6)
+    assert np.all(nmap.cpu().numpy() == 0.0)
+    assert np.all(out[3].cpu().numpy() == 0.0)
