@@ -366,7 +366,9 @@ TSR_API int tsr_render_train_normal(const tsr_scene *scene, const float *poses, 
  *   loss_norm[v] = as tsr_render_train_normal's loss (w_norm).
  * grad_pos [3][N], grad_col [3][N], grad_opa [N], grad_pose [n_views][6] (each may be NULL)
  * receive the gradient of sum_v (loss[v] + loss_norm[v]), overwriting them; with per-face
- * exponents, scene->grad_face_sigma receives that of both terms.  color and depth must not be
+ * exponents, scene->grad_face_sigma receives that of both terms.  With params->perspective the
+ * colour and depth are interpolated perspective-correctly; a normal, constant over its face, is
+ * the same either way.  color and depth must not be
  * NULL; trans, normal_map (N in the camera frame, packed like colour), loss and loss_norm may
  * be.  target_color, target_depth as for the photometric step, target_normals as for the
  * normal step (a zero vector marks an invalid pixel).  Requires a preceding tsr_bin_and_sort
