@@ -165,9 +165,11 @@ def test_mapping_step_views_of_different_sizes():
     _run(sc, poses, intrs, 710)
 
 
-def test_mapping_step_with_face_sigma():
-    _say("[mapping] per-face exponents in [1, 2.5]")
-    sc0, poses, intrs = PAR._case("tiny_ragged_50x37")
+@pytest.mark.parametrize("name", ["tiny_ragged_50x37", "multi_view_mixed"])
+def test_mapping_step_with_face_sigma(name):
+    """Per-face exponents in [1, 2.5]; one view (per-wave staging) and three (cooperative)."""
+    _say(f"[mapping] per-face exponents in [1, 2.5], case={name}")
+    sc0, poses, intrs = PAR._case(name)
     g = np.random.default_rng(720)
     sc = S.Scene(sc0.pos, sc0.col, sc0.opa, None, g.uniform(1.0, 2.5, sc0.n_faces).astype(np.float32))
     _run(sc, poses, intrs, 720, face_sigma=True)
