@@ -4,6 +4,7 @@
  * argument validation -- the paths that return before any device work, so no GPU is needed --
  * and checks the return codes and the error message.  Exits non-zero on any surprise. */
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include "tsr.h"
@@ -39,6 +40,12 @@ int main(void) {
     CHECK(tsr_equilateral_scratch_size(1000, &bytes), TSR_OK);
     CHECK(tsr_equilateral_scratch_size(-1, &bytes), TSR_EINVAL);
     CHECK(tsr_normal_scratch_size(&sc, intr, 3, &bytes), TSR_OK);
+    size_t dss = 0;
+    CHECK(tsr_dssim_scratch_size(intr, 3, &dss), TSR_OK);
+    CHECK(tsr_mapping_scratch_size(&sc, intr, 3, &bytes), TSR_OK);
+    if (bytes < dss + 32 * 1000) { fprintf(stderr, "mapping scratch not sized\n"); return 1; }
+    CHECK(tsr_mapping_scratch_size(&sc, intr, 0, &bytes), TSR_EINVAL);
+    CHECK(tsr_mapping_scratch_size(&sc, intr, 1, NULL), TSR_EINVAL);
     /* argument validation of the device entry points: every call below fails before any
        device work */
     float poses[36] = {0};
@@ -76,6 +83,33 @@ int main(void) {
     CHECK(tsr_equilateral(&sc, 1.f, 0, NULL, NULL, NULL, 0, NULL), TSR_EINVAL);
     CHECK(tsr_face_stats(&sc, poses, intr, 1, &par, NULL, 0, NULL, NULL, NULL, NULL), TSR_EINVAL);
     CHECK(tsr_sensor_normals(NULL, intr, 1, NULL, NULL), TSR_EINVAL);
+    /* the mapping step: every refusal below comes before the first launch; the buffers are
+       host memory, which the validation never dereferences */
+    size_t wsb = 0, msb = 0;
+    CHECK(tsr_workspace_size(&sc, intr, 1, 0, &wsb), TSR_OK);
+    CHECK(tsr_mapping_scratch_size(&sc, intr, 1, &msb), TSR_OK);
+    char *ws = malloc(wsb), *scr = malloc(msb + 512);
+    float *f = (float *)dummy;
+    if (!ws || !scr) { fprintf(stderr, "host allocation failed\n"); return 1; }
+    char *scr_al = scr + (256 - ((size_t)scr & 255)) % 256;
+#define MAP(scene_, poses_, ws_, wsb_, tc_, col_, scr_, scrb_) \
+    tsr_render_train_mapping(scene_, poses_, intr, 1, &par, ws_, wsb_, tc_, f, f, 0.2f, 0.1f, col_, f, f, f, f, f, f, \
+                             f, f, f, scr_, scrb_, NULL)
+    CHECK(MAP(&sc, NULL, ws, wsb, f, f, scr_al, msb), TSR_EINVAL);            /* no poses */
+    CHECK(MAP(&sc, poses, NULL, wsb, f, f, scr_al, msb), TSR_EINVAL);         /* no workspace */
+    CHECK(MAP(&sc, poses, ws, 16, f, f, scr_al, msb), TSR_EWORKSPACE);        /* workspace too small */
+    tsr_scene indexed = sc;
+    indexed.faces = (const int32_t *)dummy;
+    indexed.n_vertices = 600;
+    CHECK(MAP(&indexed, poses, ws, wsb, f, f, scr_al, msb), TSR_EINVAL);      /* indexed mesh */
+    CHECK(MAP(&sc, poses, ws, wsb, NULL, f, scr_al, msb), TSR_EINVAL);        /* no colour target */
+    CHECK(MAP(&sc, poses, ws, wsb, f, NULL, scr_al, msb), TSR_EINVAL);        /* no colour output */
+    CHECK(MAP(&sc, poses, ws, wsb, f, f, NULL, msb), TSR_EINVAL);             /* no scratch */
+    CHECK(MAP(&sc, poses, ws, wsb, f, f, scr_al, msb - 1), TSR_EWORKSPACE);   /* scratch too small */
+    CHECK(MAP(&sc, poses, ws, wsb, f, f, scr_al + 4, msb), TSR_EINVAL);       /* scratch misaligned */
+#undef MAP
+    free(ws);
+    free(scr);
     CHECK(tsr_profile_reset(), TSR_OK);
     char buf[256];
     CHECK(tsr_profile_read(buf, sizeof buf), TSR_OK);
