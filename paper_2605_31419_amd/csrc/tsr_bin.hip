@@ -759,17 +759,19 @@ __device__ __forceinline__ int lower_bound_u64(const uint64_t* a, int n, uint64_
 // register as both operands, v_permlane16_swap leaves rows (0,0,2,2) in its first result and
 // (1,1,3,3) in its second; v_permlane32_swap leaves halves (0,0) and (1,1).  Every lane of
 // the wave must be active; j must fold to a constant once the caller's loops are unrolled.
+// Every source lane of these DPP patterns lies in its own row, so with bound_ctrl set no lane
+// takes the "old" operand and the compiler needs no register for it.
 __device__ __forceinline__ uint32_t lane_xor_u32(uint32_t x, int j) {
   const int lane = threadIdx.x & 63;
   const int xi = (int)x;
   switch (j) {
-    case 1: return (uint32_t)__builtin_amdgcn_update_dpp(0, xi, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
-    case 2: return (uint32_t)__builtin_amdgcn_update_dpp(0, xi, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    case 1: return (uint32_t)__builtin_amdgcn_update_dpp(0, xi, 0xB1, 0xF, 0xF, true);    // quad_perm [1,0,3,2]
+    case 2: return (uint32_t)__builtin_amdgcn_update_dpp(0, xi, 0x4E, 0xF, 0xF, true);    // quad_perm [2,3,0,1]
     case 4: {
-      const int y = __builtin_amdgcn_update_dpp(0, xi, 0x141, 0xF, 0xF, false);          // row_half_mirror
-      return (uint32_t)__builtin_amdgcn_update_dpp(0, y, 0x1B, 0xF, 0xF, false);         // quad_perm [3,2,1,0]
+      const int y = __builtin_amdgcn_update_dpp(0, xi, 0x141, 0xF, 0xF, true);           // row_half_mirror
+      return (uint32_t)__builtin_amdgcn_update_dpp(0, y, 0x1B, 0xF, 0xF, true);          // quad_perm [3,2,1,0]
     }
-    case 8: return (uint32_t)__builtin_amdgcn_update_dpp(0, xi, 0x128, 0xF, 0xF, false);  // row_ror:8
+    case 8: return (uint32_t)__builtin_amdgcn_update_dpp(0, xi, 0x128, 0xF, 0xF, true);   // row_ror:8
     case 16: {
       const auto p = __builtin_amdgcn_permlane16_swap(x, x, false, false);
       return (lane & 16) ? p[0] : p[1];
@@ -787,12 +789,13 @@ __device__ __forceinline__ uint64_t lane_xor_u64(uint64_t x, int j) {
 }
 
 // One compare-exchange of a bitonic network: key a at position e meets its partner b; the
-// lower position of the pair keeps the minimum when the run of length kk ascends.
+// lower position of the pair keeps the minimum when the run of length kk ascends, the upper
+// one when it descends.  b replaces a exactly when it is the key to keep: one 64-bit compare
+// against a per-position flag (a function of lane bits and constants once unrolled) and a
+// select, rather than forming both the minimum and the maximum.
 __device__ __forceinline__ uint64_t bitonic_keep(uint64_t a, uint64_t b, int e, int j, int kk) {
-  const bool up = (e & kk) == 0;
-  const bool lower = (e & j) == 0;
-  const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
-  return (lower == up) ? lo : hi;
+  const bool keep_min = ((e & kk) == 0) == ((e & j) == 0);
+  return ((b < a) == keep_min) ? b : a;
 }
 
 // Register bitonic sort of up to 64 * R keys held by one wave (key e = r * 64 + lane).
