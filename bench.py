@@ -362,8 +362,10 @@ def serving_leg(raster, w, dev, n_queries, n_warm, seed=4400):
     saturated throughput, then open-loop Poisson arrivals at 25 / 50 / 80 % of it, each over
     n_queries after n_warm warm-up queries, p50 / p99 latency per rate (8 GB budget, 4 slots,
     batches of up to 8 views).  The plain single-view path (one slot, one view per launch) is
-    run at the same offered rates, and the batched server again under a tight 512 MB budget.
-    Outputs are dropped at completion, so the budget bounds the server's memory."""
+    run at the same offered rates, and the batched server again under a tight 512 MB budget
+    with one slot (a slot's workspace holds about 230 B per (view, face) besides its pairs, so
+    two slots of a 1200x680 view of the 1M-face map do not fit in 512 MB).  Outputs are dropped
+    at completion, so the budget bounds the server's memory."""
     from paper_2605_31419_amd import scenes
     from paper_2605_31419_amd.serve import GpuExecutor, Server, run_poisson
 
@@ -395,8 +397,8 @@ def serving_leg(raster, w, dev, n_queries, n_warm, seed=4400):
         log(f"[bench] serving at {q:.0f} qps: p50 {st['p50_ms']:.2f} / p99 {st['p99_ms']:.2f} ms "
             f"(plain single view p50 {pl['p50_ms']:.2f} / p99 {pl['p99_ms']:.2f} ms)")
     try:
-        tight_sat = run(1e7, slots=2, budget=512 << 20)
-        tight_q = run(0.25 * sat["qps"], slots=2, budget=512 << 20)
+        tight_sat = run(1e7, slots=1, budget=512 << 20)
+        tight_q = run(0.25 * tight_sat["qps"], slots=1, budget=512 << 20)
         out["tight_512MB"] = {"saturated": tight_sat, "at_25pct": tight_q}
         log(f"[bench] serving, 512 MB budget: {tight_sat['qps']:.0f} qps saturated, "
             f"p99 {tight_q['p99_ms']:.2f} ms at {tight_q['offered_qps']:.0f} qps")
