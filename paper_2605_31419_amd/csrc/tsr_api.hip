@@ -148,7 +148,7 @@ WsLayout layout(const ViewTable& vt, int64_t cap) {
   L.grad_acc = o; o = align_up(o + sizeof(tsr::acc_t) * tsr::kGradDwords * nf);
   L.sig_acc = o; o = align_up(o + sizeof(float) * nf);
   L.persp_acc = o; o = align_up(o + sizeof(float) * 2 * nf);
-  const int64_t nb = (nf + tsr::kProjBlock - 1) / tsr::kProjBlock;
+  const int64_t nb = tsr::proj_segments(nf, vt.n_views);
   L.tile_cnt = o;
   L.long_cnt = o + sizeof(uint32_t) * tsr::kTileCntStride * vt.n_tiles;
   o = align_up(o + sizeof(uint32_t) * (tsr::kTileCntStride * vt.n_tiles + 1));

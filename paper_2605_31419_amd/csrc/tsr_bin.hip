@@ -240,14 +240,14 @@ __device__ __forceinline__ void write_record(const FaceAttr& at, const FaceSetup
 // FP64 value by at most 4 ulp-units of sum |R_ai w_i| + |t_a| (bound used: 1e-6 x that sum);
 // the projection adds the propagated coordinate error, the reciprocal (<= 1 ulp) and two
 // roundings (bound used: 4x the first-order estimate, plus 1e-4 px).
-__device__ __forceinline__ bool surely_culled(const tsr_scene_dev& sc, const int64_t vid[3],
-                                              const float* __restrict__ pose, const ViewDesc& vd, float z_near) {
-  const int64_t N = sc.n_vertices;
+// The world positions w[vertex][axis] are loaded by the caller (several faces' loads in flight).
+__device__ __forceinline__ bool surely_culled(const float w[3][3], const float* __restrict__ pose, const ViewDesc& vd,
+                                              float z_near) {
   float ulo = INFINITY, uhi = -INFINITY, vlo = INFINITY, vhi = -INFINITY;
   bool finite = true;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const float w0 = sc.pos[vid[k]], w1 = sc.pos[N + vid[k]], w2 = sc.pos[2 * N + vid[k]];
+    const float w0 = w[k][0], w1 = w[k][1], w2 = w[k][2];
     float c[3], e[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -346,158 +346,211 @@ __device__ __forceinline__ int wave_expand_count(int cnt, F&& fn) {
 
 // ---------------------------------------------------------------------------- kernels
 
-// One thread per (view, face), numbered face-major (the views of a face in adjacent lanes);
-// per-(view, face) arrays are indexed by g = v * M + m.  Two stages: the FP32
-// pre-test on every lane rejects faces that are certainly culled; the remaining candidates
-// of the workgroup are compacted onto the first lanes, which run the exact FP64 setup (the
-// visibility decision, the pixel rectangle and, for visible faces, the record).
+// Projection workgroups of 256 threads, each taking ROUNDS x 256 consecutive (view, face)
+// pairs, numbered face-major (the views of a face in adjacent lanes); per-(view, face) arrays
+// are indexed by g = v * M + m (below 2^31: the entry points refuse larger V * M).  Two stages:
+// the FP32 pre-test rejects the pairs that are certainly culled (the positions of all rounds
+// are loaded before any test, so that their loads overlap); the remaining candidates are
+// compacted in pair order into LDS and taken 256 at a time by the exact FP64 setup (the
+// visibility decision, the pixel rectangle and, for visible faces, the record), one candidate
+// per lane.  One round for a single view: its 3,900 workgroups of one partly used FP64 wave
+// each overlap well, and workgroup b compacts its visible pairs (wave ballots, per-wave counts
+// in LDS) into visible-list segment b.  Four rounds for several views (face-major, a workgroup
+// of one round holds 256 / V faces): the FP64 waves are then full and the workgroups four times
+// fewer (8 views of 1200x680 with 1M faces: 244 -> 190 us; one view 39 -> 44 us), and wave w of
+// workgroup b appends its visible pairs of every chunk (at most 4 x 64) to segment 4 b + w, so
+// the four segments stay balanced for the emission (one segment per chunk doubled the
+// emission's time) and the compaction needs no barrier.
 // Four workgroups per CU: the FP64 setup then fits its registers without spilling (six
 // spilled 28 registers to scratch and took 57 us against 48 us at 1200x680 with 1M faces).
-template <bool TIGHT>
+template <bool TIGHT, int ROUNDS>
 __global__ __launch_bounds__(256, 4) void k_project(tsr_scene_dev sc, const float* __restrict__ poses, ViewTable vt,
                                                  float z_near, float r_min, float sigma, int persp,
                                                  uint32_t* __restrict__ counts,
                                                  float* __restrict__ records, uint32_t* __restrict__ tile_cnt,
                                                  uint32_t* __restrict__ vis_cnt, VisEntry* __restrict__ vis_list) {
+  static_assert(kProjBlock == 256, "four waves per projection workgroup: s_wave, s_cnt and the chunk size");
+  constexpr int kPairs = ROUNDS * kProjBlock;
   __shared__ uint32_t s_wave[4];
-  __shared__ uint32_t s_cand[kProjBlock];
-  const int64_t M = vt.n_faces;
+  __shared__ uint32_t s_cnt[ROUNDS][4];
+  __shared__ uint32_t s_cand[kPairs];
+  const uint32_t M = (uint32_t)vt.n_faces, V = (uint32_t)vt.n_views, NF = V * M;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint64_t below = (1ull << lane) - 1ull;
+  const uint32_t first = blockIdx.x * (uint32_t)kPairs;
+  uint32_t ncand = 0u;
   {
-    // threads are numbered face-major (idx = m V + v), so the views of one face are adjacent
-    // lanes sharing its vertex loads; per-(view, face) arrays stay indexed by g = v M + m
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool cand = false;
-    int64_t g = 0;
-    if (idx < (int64_t)vt.n_views * M) {
-      const int64_t m = idx / vt.n_views;
-      const int v = (int)(idx - m * vt.n_views);
-      g = (int64_t)v * M + m;
-      int64_t vid[3];
-      face_vertices(sc, m, vid);
-      cand = !surely_culled(sc, vid, poses + 12 * v, vt.v[v], z_near);
-      if (!cand) counts[g] = 0u;
-    }
-    const unsigned long long mask = __ballot(cand);
-    if (lane == 0) s_wave[wave] = (uint32_t)__popcll(mask);
-    __syncthreads();
-    uint32_t off = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-    for (int w = 0; w < wave; ++w) off += s_wave[w];
-    if (cand) s_cand[off] = (uint32_t)g;
-  }
-  const uint32_t ncand = s_wave[0] + s_wave[1] + s_wave[2] + s_wave[3];
-  const int nact = (int)((ncand + 63u) >> 6);              // waves that hold a candidate below
-  __syncthreads();
-  if (ncand == 0u) {
-    if (threadIdx.x == 0) vis_cnt[blockIdx.x] = 0u;
-    return;
-  }
-  // Whole waves without a candidate leave now, so their slots go to other workgroups during
-  // the FP64 stage; the barriers below then wait for the remaining waves only.
-  if (wave >= nact) return;
-  // ---- exact setup of the candidates, one per lane (in thread order)
-  int ntiles = 0, tx0 = 0, ty0 = 0, tw = 1, th = 1, tile_base = 0, tiles_x = 1;
-  uint32_t zbits = 0u;
-  uint32_t keep = 0xfu;        // tight binning: which tiles of a face over at most kSmallTiles are listed
-  EdgeLines el{};              // tight binning: the face's edge lines (read by the larger faces' items)
-  int64_t g = 0;
-  if (threadIdx.x < ncand) {
-    g = (int64_t)s_cand[threadIdx.x];
-    const int v = (int)(g / M);
-    const ViewDesc& vd = vt.v[v];
-    double R[9], t[3];
-    load_pose(poses, v, R, t);
-    int64_t vid[3];
-    const int64_t m = g - (int64_t)v * M;
-    face_vertices(sc, m, vid);
-    FaceAttr at;
-    load_attr(sc, m, vid, sigma, persp, at);
-    FaceSetup f;
-    if (setup_face(sc, vid, R, t, vd, z_near, r_min, f)) {
-      tx0 = f.u0 >> 4;
-      ty0 = f.v0 >> 4;
-      tw = (f.u1 >> 4) - tx0 + 1;
-      th = (f.v1 >> 4) - ty0 + 1;
-      ntiles = tw * th;
-      tile_base = vd.tile_off;
-      tiles_x = vd.tiles_x;
-      face_normals(f);
-      write_record(at, f, records + g * kRecDwords);
-      zbits = __float_as_uint((float)f.zf);     // the record's z_F (set by face_normals)
-      if constexpr (TIGHT) {
-        edge_lines(f, el);
-        if (ntiles <= kSmallTiles) {
-          keep = 0u;
+    float w[ROUNDS][3][3];
+    uint32_t gr[ROUNDS];
+    int vr[ROUNDS];
+    const int64_t N = sc.n_vertices;
 #pragma unroll
-          for (int i = 0; i < kSmallTiles; ++i)
-            if (i < ntiles && tile_may_cover(el, tx0 + i % tw, ty0 + i / tw)) keep |= 1u << i;
+    for (int r = 0; r < ROUNDS; ++r) {
+      const uint32_t idx = first + (uint32_t)(r * kProjBlock) + threadIdx.x;
+      const uint32_t id = idx < NF ? idx : 0u;        // lanes past the end test pair 0 and drop it
+      const uint32_t m = id / V;
+      vr[r] = (int)(id - m * V);
+      gr[r] = (uint32_t)vr[r] * M + m;
+      int64_t vid[3];
+      face_vertices(sc, (int64_t)m, vid);
+#pragma unroll
+      for (int k = 0; k < 3; ++k)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) w[r][k][a] = sc.pos[a * N + vid[k]];
+    }
+    unsigned long long mask[ROUNDS];
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+      const bool in = first + (uint32_t)(r * kProjBlock) + threadIdx.x < NF;
+      const bool cand = in && !surely_culled(w[r], poses + 12 * vr[r], vt.v[vr[r]], z_near);
+      if (in && !cand) counts[gr[r]] = 0u;
+      mask[r] = __ballot(cand);
+      if (lane == 0) s_cnt[r][wave] = (uint32_t)__popcll(mask[r]);
+    }
+    __syncthreads();
+    // candidates in pair order: round, then wave, then lane
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+      uint32_t off = ncand + (uint32_t)__popcll(mask[r] & below);
+      for (int q = 0; q < 4; ++q) {
+        if (q < wave) off += s_cnt[r][q];
+        ncand += s_cnt[r][q];
+      }
+      if ((mask[r] >> lane) & 1ull) s_cand[off] = gr[r];
+    }
+  }
+  const int seg0 = (int)blockIdx.x * ROUNDS;
+  const int nchunk = (int)((ncand + kProjBlock - 1u) / kProjBlock);
+  if constexpr (ROUNDS == 1)
+    if (nchunk == 0 && threadIdx.x == 0) vis_cnt[seg0] = 0u;
+  __syncthreads();                                // s_cand complete
+  uint32_t wcount = 0u;                           // several rounds: this wave's visible pairs so far
+  // Chunk c of the candidates; false for a wave that has left (in the last chunk, whole waves
+  // without a candidate leave at once, so their slots go to other workgroups during the FP64
+  // stage; the barriers below then wait for the remaining waves only).
+  auto chunk = [&](int c) -> bool {
+    const uint32_t left = ncand - (uint32_t)(c * kProjBlock);
+    const int nact = left >= (uint32_t)kProjBlock ? 4 : (int)((left + 63u) >> 6);
+    if (wave >= nact) return false;
+    // ---- exact setup of the chunk's candidates, one per lane (in pair order)
+    int ntiles = 0, tx0 = 0, ty0 = 0, tw = 1, th = 1, tile_base = 0, tiles_x = 1;
+    uint32_t zbits = 0u;
+    uint32_t keep = 0xfu;        // tight binning: which tiles of a face over at most kSmallTiles are listed
+    EdgeLines el{};              // tight binning: the face's edge lines (read by the larger faces' items)
+    uint32_t g = 0u;
+    if (threadIdx.x < left) {
+      g = s_cand[c * kProjBlock + threadIdx.x];
+      const uint32_t v = g / M;
+      const ViewDesc& vd = vt.v[v];
+      double R[9], t[3];
+      load_pose(poses, (int)v, R, t);
+      int64_t vid[3];
+      const int64_t m = (int64_t)(g - v * M);
+      face_vertices(sc, m, vid);
+      FaceAttr at;
+      load_attr(sc, m, vid, sigma, persp, at);
+      FaceSetup f;
+      if (setup_face(sc, vid, R, t, vd, z_near, r_min, f)) {
+        tx0 = f.u0 >> 4;
+        ty0 = f.v0 >> 4;
+        tw = (f.u1 >> 4) - tx0 + 1;
+        th = (f.v1 >> 4) - ty0 + 1;
+        ntiles = tw * th;
+        tile_base = vd.tile_off;
+        tiles_x = vd.tiles_x;
+        face_normals(f);
+        write_record(at, f, records + (int64_t)g * kRecDwords);
+        zbits = __float_as_uint((float)f.zf);     // the record's z_F (set by face_normals)
+        if constexpr (TIGHT) {
+          edge_lines(f, el);
+          if (ntiles <= kSmallTiles) {
+            keep = 0u;
+#pragma unroll
+            for (int i = 0; i < kSmallTiles; ++i)
+              if (i < ntiles && tile_may_cover(el, tx0 + i % tw, ty0 + i / tw)) keep |= 1u << i;
+          }
         }
       }
+      // listed tiles (larger faces under tight binning: corrected after their items are decided)
+      counts[g] = ntiles <= kSmallTiles ? (uint32_t)__popc(keep & ((1u << ntiles) - 1u)) : (uint32_t)ntiles;
     }
-    // listed tiles (larger faces under tight binning: corrected after their items are decided)
-    counts[g] = ntiles <= kSmallTiles ? (uint32_t)__popc(keep & ((1u << ntiles) - 1u)) : (uint32_t)ntiles;
-  }
-  if constexpr (TIGHT) {
-    if (ntiles > 0 && ntiles <= kSmallTiles && (keep & ((1u << ntiles) - 1u)) == 0u) ntiles = 0;   // no tile left
-  }
-  __syncthreads();                    // s_wave is reused below
-  // ---- visible (view, face) pairs of this workgroup, compacted (still in thread order) into its
-  //      own segment of the visible list: a wave ballot and per-wave counts in LDS, no atomics
-  const bool vis = ntiles > 0;
-  uint4* ent = nullptr;
-  {
-    const unsigned long long mask = __ballot(vis);
-    if (lane == 0) s_wave[wave] = (uint32_t)__popcll(mask);
-    __syncthreads();
-    uint32_t off = (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-    for (int w = 0; w < wave; ++w) off += s_wave[w];
-    ent = reinterpret_cast<uint4*>(vis_list + (int64_t)blockIdx.x * kProjBlock + off);
-    if (vis)
-      ent[0] = make_uint4((uint32_t)g, (uint32_t)(tile_base + ty0 * tiles_x + tx0),
-                          (uint32_t)(tw - 1) | ((uint32_t)(th - 1) << 10) | ((uint32_t)(tiles_x - 1) << 20), zbits);
-    if (threadIdx.x == 0) {
-      uint32_t nvis = 0u;
-      for (int w = 0; w < nact; ++w) nvis += s_wave[w];
-      vis_cnt[blockIdx.x] = nvis;
+    if constexpr (TIGHT) {
+      if (ntiles > 0 && ntiles <= kSmallTiles && (keep & ((1u << ntiles) - 1u)) == 0u) ntiles = 0;   // no tile left
     }
-  }
-  // ---- per-tile counts.  A face overlapping at most kSmallTiles tiles takes its slot in each
-  //      tile from the returning atomic and records it, so emission needs no atomics for it;
-  //      larger faces are counted separately and spread over the wave.
-  if (vis && ntiles <= kSmallTiles) {
-    uint32_t sl[kSmallTiles];
+    // ---- visible (view, face) pairs, in pair order, into the visible list: the workgroup's
+    //      segment (one round) or the wave's own (several); wave ballots, no atomics
+    const bool vis = ntiles > 0;
+    uint4* ent = nullptr;
+    {
+      const unsigned long long vmask = __ballot(vis);
+      uint32_t off = (uint32_t)__popcll(vmask & below);
+      int seg = seg0;
+      if constexpr (ROUNDS == 1) {
+        if (lane == 0) s_wave[wave] = (uint32_t)__popcll(vmask);
+        __syncthreads();
+        for (int q = 0; q < wave; ++q) off += s_wave[q];
+        if (threadIdx.x == 0) {
+          uint32_t nvis = 0u;
+          for (int q = 0; q < nact; ++q) nvis += s_wave[q];
+          vis_cnt[seg] = nvis;
+        }
+      } else {
+        seg = seg0 + wave;
+        off += wcount;
+        wcount += (uint32_t)__popcll(vmask);
+      }
+      ent = reinterpret_cast<uint4*>(vis_list + (int64_t)seg * kProjBlock + off);
+      if (vis)
+        ent[0] = make_uint4(g, (uint32_t)(tile_base + ty0 * tiles_x + tx0),
+                            (uint32_t)(tw - 1) | ((uint32_t)(th - 1) << 10) | ((uint32_t)(tiles_x - 1) << 20), zbits);
+    }
+    // ---- per-tile counts.  A face overlapping at most kSmallTiles tiles takes its slot in each
+    //      tile from the returning atomic and records it, so emission needs no atomics for it;
+    //      larger faces are counted separately and spread over the wave.
+    if (vis && ntiles <= kSmallTiles) {
+      uint32_t sl[kSmallTiles];
 #pragma unroll
-    for (int i = 0; i < kSmallTiles; ++i)
-      sl[i] = (i < ntiles && ((keep >> i) & 1u))
-                  ? atomicAdd(&tile_cnt[kTileCntStride * (tile_base + (ty0 + i / tw) * tiles_x + tx0 + i % tw)], 1u)
-                  : kSkipSlot;
-    ent[1] = make_uint4(sl[0], sl[1], sl[2], sl[3]);
-  }
-  const int big = ntiles > kSmallTiles ? ntiles : 0;
-  if (wave_max_int(big) == 0) return;
-  if constexpr (!TIGHT) {
-    wave_expand(big, [&](bool valid, int owner, int i) {
-      const int otx0 = __shfl(tx0, owner, 64), oty0 = __shfl(ty0, owner, 64), otw = __shfl(tw, owner, 64);
-      const int obase = __shfl(tile_base, owner, 64), otx = __shfl(tiles_x, owner, 64);
-      if (valid) atomicAdd(&tile_cnt[kTileCntStride * (obase + (oty0 + i / otw) * otx + otx0 + i % otw) + 2], 1u);
-    });
+      for (int i = 0; i < kSmallTiles; ++i)
+        sl[i] = (i < ntiles && ((keep >> i) & 1u))
+                    ? atomicAdd(&tile_cnt[kTileCntStride * (tile_base + (ty0 + i / tw) * tiles_x + tx0 + i % tw)], 1u)
+                    : kSkipSlot;
+      ent[1] = make_uint4(sl[0], sl[1], sl[2], sl[3]);
+    }
+    const int big = ntiles > kSmallTiles ? ntiles : 0;
+    if (wave_max_int(big) == 0) return true;
+    if constexpr (!TIGHT) {
+      wave_expand(big, [&](bool valid, int owner, int i) {
+        const int otx0 = __shfl(tx0, owner, 64), oty0 = __shfl(ty0, owner, 64), otw = __shfl(tw, owner, 64);
+        const int obase = __shfl(tile_base, owner, 64), otx = __shfl(tiles_x, owner, 64);
+        if (valid) atomicAdd(&tile_cnt[kTileCntStride * (obase + (oty0 + i / otw) * otx + otx0 + i % otw) + 2], 1u);
+      });
+    } else {
+      const int kept = wave_expand_count(big, [&](bool valid, int owner, int i) {
+        const int otx0 = __shfl(tx0, owner, 64), oty0 = __shfl(ty0, owner, 64), otw = __shfl(tw, owner, 64);
+        const int obase = __shfl(tile_base, owner, 64), otx = __shfl(tiles_x, owner, 64);
+        EdgeLines oe;
+        shfl_lines(el, owner, oe);
+        const int x = otx0 + i % otw, y = oty0 + i / otw;
+        const bool k = valid && tile_may_cover(oe, x, y);
+        if (k) atomicAdd(&tile_cnt[kTileCntStride * (obase + y * otx + x) + 2], 1u);
+        return k;
+      });
+      if (big > 0) counts[g] = (uint32_t)kept;
+    }
+    return true;
+  };
+  if constexpr (ROUNDS == 1) {
+    if (nchunk > 0) chunk(0);                    // straight-line: no loop for the compiler to hoist into
   } else {
-    const int kept = wave_expand_count(big, [&](bool valid, int owner, int i) {
-      const int otx0 = __shfl(tx0, owner, 64), oty0 = __shfl(ty0, owner, 64), otw = __shfl(tw, owner, 64);
-      const int obase = __shfl(tile_base, owner, 64), otx = __shfl(tiles_x, owner, 64);
-      EdgeLines oe;
-      shfl_lines(el, owner, oe);
-      const int x = otx0 + i % otw, y = oty0 + i / otw;
-      const bool k = valid && tile_may_cover(oe, x, y);
-      if (k) atomicAdd(&tile_cnt[kTileCntStride * (obase + y * otx + x) + 2], 1u);
-      return k;
-    });
-    if (big > 0) counts[g] = (uint32_t)kept;
+    static_assert(ROUNDS * kWave <= kProjBlock, "a wave's visible pairs of every chunk fit its segment");
+    for (int c = 0; c < nchunk; ++c)
+      if (!chunk(c)) break;
+    if (lane == 0) vis_cnt[seg0 + wave] = wcount;
   }
 }
 
 // Two workgroups of 1024 threads, working independently: (0) exclusive scan of the
-// visible-face counts of the projection workgroups (offsets of their segments in the dense
+// visible-face counts of the visible-list segments (offsets of the segments in the dense
 // visible list); (1) exclusive scan of the tile counts into ranges, pair total K, overflow check against the capacity (all
 // ranges empty on overflow), the small-face counts left in tile_cnt2 as the base of the
 // larger faces' emission cursors, and the list of tiles too long for the one-wave sort.  Both
@@ -637,8 +690,8 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* __restrict__ tile
 }
 
 // Emission of (float32 z_F bits << 32 | face) into each overlapped tile's bucket.  One
-// workgroup per projection workgroup, one lane per visible face of its segment (compacted,
-// in thread order), each reading its 32-byte visible-list entry.  Small faces store at their
+// workgroup per visible-list segment, one lane per visible face of the segment (compacted,
+// in pair order), each reading its 32-byte visible-list entry.  Small faces store at their
 // recorded slot; larger faces take positions from the per-tile cursors, spread over the
 // wave.  A position outside its tile's range (never expected) is not written and is reported
 // through tsr_check.  Under tight binning a small face's skipped tiles carry kSkipSlot, and the
@@ -1042,27 +1095,33 @@ hipError_t launch_bin(const tsr_scene_dev& sc, const float* poses, const ViewTab
   const int64_t n_cnt = kTileCntStride * (int64_t)vt.n_tiles + 1;
   TSR_LAUNCH("fill_tiles", k_fill_u32, dim3(grid_for(n_cnt, 256)), dim3(256), 0, st, tile_cnt, n_cnt, 0u);
   if (nf > 0) {
-    if (p.tight_tiles)
-      TSR_LAUNCH("project", k_project<true>, dim3(grid_for(nf, kProjBlock)), dim3(kProjBlock), 0, st, sc, poses, vt, p.z_near,
-                 p.r_min, p.sigma, p.perspective, counts, records, tile_cnt, vis_cnt, vis_list);
-    else
-      TSR_LAUNCH("project", k_project<false>, dim3(grid_for(nf, kProjBlock)), dim3(kProjBlock), 0, st, sc, poses, vt, p.z_near,
-                 p.r_min, p.sigma, p.perspective, counts, records, tile_cnt, vis_cnt, vis_list);
+    // one pre-test round per projection workgroup for a single view, four for several
+#define TSR_PROJECT(T, R)                                                                                   \
+  TSR_LAUNCH("project", (k_project<T, R>), dim3(grid_for(nf, (int64_t)R * kProjBlock)), dim3(kProjBlock), 0, st, sc, \
+             poses, vt, p.z_near, p.r_min, p.sigma, p.perspective, counts, records, tile_cnt, vis_cnt, vis_list)
+    if (proj_rounds(vt.n_views) == 1) {
+      if (p.tight_tiles) TSR_PROJECT(true, 1);
+      else TSR_PROJECT(false, 1);
+    } else {
+      if (p.tight_tiles) TSR_PROJECT(true, 4);
+      else TSR_PROJECT(false, 4);
+    }
+#undef TSR_PROJECT
   }
   uint32_t* vis_off = reinterpret_cast<uint32_t*>(ws + L.vis_off);
   uint32_t* vis_total = reinterpret_cast<uint32_t*>(ws + L.vis_total);
   uint32_t* vis_dense = reinterpret_cast<uint32_t*>(ws + L.vis_dense);
-  const int n_seg = (int)((nf + kProjBlock - 1) / kProjBlock);
+  const int n_seg = (int)proj_segments(nf, vt.n_views);
   TSR_LAUNCH("scan_tiles", k_scan_tiles, dim3(2), dim3(1024), 0, st, tile_cnt, ranges, vt.n_tiles,
                      sort ? L.capacity : (int64_t)0x7fffffffffffffffll, K, overflow, vis_cnt, vis_off, vis_total,
                      n_seg, long_cnt, long_list);
   if (!sort) return hipGetLastError();
   if (nf > 0) {
     if (p.tight_tiles)
-      TSR_LAUNCH("emit", k_emit<true>, dim3(grid_for(nf, kProjBlock)), dim3(kProjBlock), 0, st, ranges, tile_cnt,
+      TSR_LAUNCH("emit", k_emit<true>, dim3(n_seg), dim3(kProjBlock), 0, st, ranges, tile_cnt,
                  overflow, pairs, vis_cnt, vis_off, vis_list, vis_dense, sc, poses, vt, p.z_near, p.r_min);
     else
-      TSR_LAUNCH("emit", k_emit<false>, dim3(grid_for(nf, kProjBlock)), dim3(kProjBlock), 0, st, ranges, tile_cnt,
+      TSR_LAUNCH("emit", k_emit<false>, dim3(n_seg), dim3(kProjBlock), 0, st, ranges, tile_cnt,
                  overflow, pairs, vis_cnt, vis_off, vis_list, vis_dense, sc, poses, vt, p.z_near, p.r_min);
   }
   // small tile counts: the order is built beside the sorts (hidden behind them); larger ones by

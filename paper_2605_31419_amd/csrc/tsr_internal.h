@@ -43,11 +43,11 @@ struct WsLayout {
                                    // long-tile counter (all filled together)
   size_t long_cnt;                 // uint32: tiles whose list is too long for the register sort
   size_t long_list;                // uint32 [T]: those tiles
-  size_t vis_cnt;                  // uint32 [NB]: visible (view, face) pairs of each projection workgroup
+  size_t vis_cnt;                  // uint32 [NB]: visible (view, face) pairs of each visible-list segment
   size_t vis_off;                  // uint32 [NB]: exclusive scan of vis_cnt
   size_t vis_total;                // uint32: total visible (view, face) pairs
-  size_t vis_list;                 // VisEntry [NB][256]: the visible (view, face) pairs of projection
-                                   // workgroup b (first vis_cnt[b] entries)
+  size_t vis_list;                 // VisEntry [NB][256]: the visible (view, face) pairs of segment b
+                                   // (first vis_cnt[b] entries)
   size_t vis_dense;                // uint32 [V*M]: the same ids, compacted (first vis_total entries)
   size_t ranges;                   // uint32 [T][2]
   size_t order;                    // int32  [T] tile schedule (longest lists first)
@@ -63,7 +63,15 @@ struct WsLayout {
 constexpr int kOrderBuckets = 1024;    // tile-length buckets of the longest-first schedule
 constexpr int kSumCopies = 64;         // copies of the FP64 pose / loss sums (workgroup b adds into
                                        // copy b % kSumCopies, so few atomics meet on one address)
-constexpr int kProjBlock = 256;        // faces per projection workgroup (one visible-list segment each)
+constexpr int kProjBlock = 256;        // threads per projection workgroup; entries per visible-list segment
+
+// Pre-test rounds per projection workgroup (kProjBlock pairs each) and the visible-list
+// segments that the projection writes: one per workgroup for one round, one per wave for four.
+inline int proj_rounds(int n_views) { return n_views == 1 ? 1 : 4; }
+inline int64_t proj_segments(int64_t n_pairs, int n_views) {
+  const int64_t r = proj_rounds(n_views);
+  return r * ((n_pairs + r * kProjBlock - 1) / (r * kProjBlock));
+}
 constexpr int kRegSortMax = 1024;      // tile lists up to this length are sorted in registers
 constexpr int kWaveSortMax = 512;      // ... by one wave (longer ones by a whole workgroup)
 constexpr int kSmallTiles = 4;         // faces overlapping at most this many tiles record their slots
