@@ -360,7 +360,8 @@ __device__ __forceinline__ int wave_expand_count(int cnt, F&& fn) {
 // fewer (8 views of 1200x680 with 1M faces: 244 -> 190 us; one view 39 -> 44 us), and wave w of
 // workgroup b appends its visible pairs of every chunk (at most 4 x 64) to segment 4 b + w, so
 // the four segments stay balanced for the emission (one segment per chunk doubled the
-// emission's time) and the compaction needs no barrier.
+// emission's time) and the compaction needs no barrier.  The dense visible list then follows
+// the segments, not pair order (the face backward's gathers lose a little locality: +6 us).
 // Four workgroups per CU: the FP64 setup then fits its registers without spilling (six
 // spilled 28 registers to scratch and took 57 us against 48 us at 1200x680 with 1M faces).
 template <bool TIGHT, int ROUNDS>
@@ -430,16 +431,22 @@ __global__ __launch_bounds__(256, 4) void k_project(tsr_scene_dev sc, const floa
   // stage; the barriers below then wait for the remaining waves only).
   auto chunk = [&](int c) -> bool {
     const uint32_t left = ncand - (uint32_t)(c * kProjBlock);
-    const int nact = left >= (uint32_t)kProjBlock ? 4 : (int)((left + 63u) >> 6);
+    // One round: candidate c * 256 + tid.  Several: the chunk's candidates round-robin over the
+    // waves (c * 256 + 4 lane + wave), so that the views of one face, adjacent in pair order, land
+    // in different waves' segments and the emission's expansion of larger faces is spread evenly
+    // (8 views: emission 101 -> 69 us; with a contiguous quarter of the chunk per wave 84 us).
+    const int slot = ROUNDS == 1 ? (int)threadIdx.x : lane * 4 + wave;
+    const int nact = ROUNDS == 1 ? (left >= (uint32_t)kProjBlock ? 4 : (int)((left + 63u) >> 6))
+                                 : (left >= 4u ? 4 : (int)left);
     if (wave >= nact) return false;
-    // ---- exact setup of the chunk's candidates, one per lane (in pair order)
+    // ---- exact setup of the chunk's candidates, one per lane
     int ntiles = 0, tx0 = 0, ty0 = 0, tw = 1, th = 1, tile_base = 0, tiles_x = 1;
     uint32_t zbits = 0u;
     uint32_t keep = 0xfu;        // tight binning: which tiles of a face over at most kSmallTiles are listed
     EdgeLines el{};              // tight binning: the face's edge lines (read by the larger faces' items)
     uint32_t g = 0u;
-    if (threadIdx.x < left) {
-      g = s_cand[c * kProjBlock + threadIdx.x];
+    if ((uint32_t)slot < left) {
+      g = s_cand[c * kProjBlock + slot];
       const uint32_t v = g / M;
       const ViewDesc& vd = vt.v[v];
       double R[9], t[3];
@@ -477,7 +484,7 @@ __global__ __launch_bounds__(256, 4) void k_project(tsr_scene_dev sc, const floa
     if constexpr (TIGHT) {
       if (ntiles > 0 && ntiles <= kSmallTiles && (keep & ((1u << ntiles) - 1u)) == 0u) ntiles = 0;   // no tile left
     }
-    // ---- visible (view, face) pairs, in pair order, into the visible list: the workgroup's
+    // ---- visible (view, face) pairs into the visible list, in candidate order: the workgroup's
     //      segment (one round) or the wave's own (several); wave ballots, no atomics
     const bool vis = ntiles > 0;
     uint4* ent = nullptr;
