@@ -704,6 +704,8 @@ __global__ __launch_bounds__(1024) void k_scan_tiles(uint32_t* __restrict__ tile
 // through tsr_check.  Under tight binning a small face's skipped tiles carry kSkipSlot, and the
 // larger faces repeat the projection's FP64 setup (the same code on the same inputs, so the same
 // tile decisions) to list only the tiles the projection counted.
+constexpr int kEmitU = 4;          // larger-face tiles per lane per expansion round of the emission
+
 template <bool TIGHT>
 __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ ranges,
                                               uint32_t* __restrict__ cursor, uint32_t* __restrict__ overflow,
@@ -763,7 +765,33 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ range
       lty0 = f.v0 >> 4;
     }
   }
-  wave_expand(big, [&](bool valid, int owner, int i) {
+  // The larger faces' tiles spread over the wave (owner lane by binary search over the wave's
+  // inclusive prefix of the counts), kEmitU items per lane per round: a round resolves its
+  // items' tiles and keys, then issues all their cursor atomics (without a branch, so nothing
+  // waits between them; under tight binning a tile the face does not cover adds 0 to its own
+  // cursor), then stores, so that a face over hundreds of tiles waits on one atomic round trip
+  // per kEmitU x 64 of its tiles rather than per 64 (1200x680 with 1M faces: the larger faces
+  // took 12.7 us of the emission's 21: now 8.7).  Items past the last full round go one per
+  // lane, with a branch around each atomic (repeating real items with adds of 0 to fill the
+  // last round instead multiplied the atomics on the busiest cursors: 17 -> 22 us).
+  const int lane = threadIdx.x & 63;
+  int incl = big;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  const int total = __shfl(incl, 63, 64);
+  // item j of the wave: its tile, its key, and whether the face lists that tile
+  auto item = [&](int j, int& t, uint64_t& key2) -> bool {
+    int lo = 0, hi = 63;
+#pragma unroll
+    for (int st = 0; st < 6; ++st) {             // smallest lane with incl > j
+      const int mid = (lo + hi) >> 1;
+      if (__shfl(incl, mid, 64) > j) hi = mid; else lo = mid + 1;
+    }
+    const int owner = lo;
+    const int i = j - (__shfl(incl, owner, 64) - __shfl(big, owner, 64));
     const int ot0 = __shfl(tile0, owner, 64), otw = __shfl(tw, owner, 64), otx = __shfl(tiles_x, owner, 64);
     const uint32_t khi = __shfl(key_hi, owner, 64), klo = __shfl(key_lo, owner, 64);
     bool keep = true;
@@ -771,15 +799,45 @@ __global__ __launch_bounds__(256) void k_emit(const uint32_t* __restrict__ range
       EdgeLines oe;
       shfl_lines(el, owner, oe);
       const int ox = __shfl(ltx0, owner, 64), oy = __shfl(lty0, owner, 64);
-      keep = valid && tile_may_cover(oe, ox + i % otw, oy + i / otw);
+      keep = tile_may_cover(oe, ox + i % otw, oy + i / otw);
     }
-    if (valid && keep) {
-      const int t = ot0 + (i / otw) * otx + i % otw;
+    t = ot0 + (i / otw) * otx + i % otw;
+    key2 = ((uint64_t)khi << 32) | klo;
+    return keep;
+  };
+  int base = 0;
+  for (; base + kWave * kEmitU <= total; base += kWave * kEmitU) {
+    int tt[kEmitU];
+    uint64_t kk[kEmitU];
+    bool ok[kEmitU];
+#pragma unroll
+    for (int u = 0; u < kEmitU; ++u) ok[u] = item(base + u * kWave + lane, tt[u], kk[u]);
+    uint32_t r0[kEmitU], r1[kEmitU], slot[kEmitU];
+#pragma unroll
+    for (int u = 0; u < kEmitU; ++u) {
+      r0[u] = ranges[2 * tt[u]];
+      r1[u] = ranges[2 * tt[u] + 1];
+      slot[u] = atomicAdd(&cursor[kTileCntStride * tt[u] + 2], ok[u] ? 1u : 0u);
+    }
+#pragma unroll
+    for (int u = 0; u < kEmitU; ++u)
+      if (ok[u]) {
+        const uint32_t pos = r0[u] + slot[u];
+        if (pos < r1[u]) pairs[pos] = kk[u];
+        else atomicOr(&overflow[2], 2u);
+      }
+  }
+  for (; base < total; base += kWave) {
+    const int j = base + lane;
+    int t;
+    uint64_t key2;
+    const bool keep = item(j, t, key2);
+    if (j < total && keep) {
       const uint32_t pos = ranges[2 * t] + atomicAdd(&cursor[kTileCntStride * t + 2], 1u);
-      if (pos < ranges[2 * t + 1]) pairs[pos] = ((uint64_t)khi << 32) | klo;
+      if (pos < ranges[2 * t + 1]) pairs[pos] = key2;
       else atomicOr(&overflow[2], 2u);
     }
-  });
+  }
 }
 
 // ---------------------------------------------------------------------------- per-tile sort
