@@ -201,6 +201,35 @@ def test_binning_bit_exact(name):
     _say(f"  K = {K}")
 
 
+def _one_tile_scene(n, seed):
+    """n faces each covering pixel centres of the single tile of a 16x16 view (so that the
+    tile's list holds exactly n pairs), at depths drawn from 40 values (many equal keys, whose
+    order is the face id)."""
+    g = np.random.default_rng(seed)
+    c = g.uniform(5.5, 9.5, size=(n, 1, 2))
+    ang = g.uniform(0, 2 * np.pi, size=(n, 1)) + np.array([0.0, 2 * np.pi / 3, 4 * np.pi / 3])
+    r = g.uniform(3.0, 4.0, size=(n, 3))
+    px = c + np.stack([r * np.cos(ang), r * np.sin(ang)], axis=2)       # inradius >= 1.5 px
+    z = (1.0 + 0.05 * g.integers(0, 40, size=(n, 1, 1))) * np.ones((n, 3, 1))
+    v = np.concatenate([(px - 7.5) * z / 20.0, z], axis=2)
+    return plain_scene(v, col=g.uniform(0, 1, (n, 3, 3)), opa=g.uniform(0.3, 1, (n, 3)))
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 127, 128, 129, 255, 256, 257, 511, 512, 513, 1023, 1024, 1025,
+                               4096, 4097])
+def test_tile_sort_at_every_length_boundary(n):
+    """One tile listing exactly n faces, at each boundary of the sort's paths (one-wave sorts
+    of 1, 2, 4 and 8 keys per lane, the workgroup register sort up to 1,024 keys, the LDS sort
+    up to 4,096, the merge beyond), with many equal depths: the list bit-exact against the
+    oracle binner."""
+    _say(f"[tile sort] one tile of {n} faces")
+    sc = _one_tile_scene(n, seed=n)
+    intrs = [S.Intrinsics(16, 16, 20.0, 20.0, 7.5, 7.5)]
+    rast, p = G.make(sc, intrs, [IDENTITY])
+    rast.bin_and_sort(p)
+    assert _assert_bins_equal(rast, sc, [IDENTITY], intrs) == n
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_tight_binning_bit_exact(name):
     """Tight triangle-tile lists against the oracle binner with the same FP64 rule."""
