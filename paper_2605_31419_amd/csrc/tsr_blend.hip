@@ -292,10 +292,12 @@ struct FwdState {
   int last;
 };
 
-// A pixel blends faces while its transmittance is at least t_min and not zero.  T never
+// A pixel blends faces while its transmittance is at least t_min and positive.  T never
 // increases, so this is the rule "stop after the face that takes T below t_min, or to 0"
-// (t_min < 1) without a separate state; pixels outside the image start at T = 0.
-__device__ __forceinline__ bool live(float T, float t_min) { return T >= t_min && T > 0.f; }
+// (t_min < 1) without a separate state; pixels outside the image start at T = 0.  One
+// comparison against max(t_min, FLT_MIN) (hoisted by the compiler) tests both: the two differ
+// only for t_min = 0 at a subnormal T, where nothing visible is left to blend.
+__device__ __forceinline__ bool live(float T, float t_min) { return T >= fmaxf(t_min, 1.17549435e-38f); }
 
 // Front-to-back walk over the tile list (eq. 4).  A pixel stops after the face that takes
 // its transmittance below t_min.  Records each pixel's last blended face and the
