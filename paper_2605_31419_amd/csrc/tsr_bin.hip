@@ -431,14 +431,17 @@ __global__ __launch_bounds__(256, 4) void k_project(tsr_scene_dev sc, const floa
   // stage; the barriers below then wait for the remaining waves only).
   auto chunk = [&](int c) -> bool {
     const uint32_t left = ncand - (uint32_t)(c * kProjBlock);
-    // One round: candidate c * 256 + tid.  Several: the chunk's candidates round-robin over the
-    // waves (c * 256 + 4 lane + wave), so that the views of one face, adjacent in pair order, land
-    // in different waves' segments and the emission's expansion of larger faces is spread evenly
+    // One round: candidate 64 w' + lane, w' the wave counted from wave b mod 4 of workgroup b,
+    // so that the FP64 waves of neighbouring workgroups do not all sit on the same SIMD
+    // (44.0 -> 42.5 us).  Several: the chunk's candidates round-robin over the waves
+    // (c * 256 + 4 lane + wave), so that the views of one face, adjacent in pair order, land in
+    // different waves' segments and the emission's expansion of larger faces is spread evenly
     // (8 views: emission 101 -> 69 us; with a contiguous quarter of the chunk per wave 84 us).
-    const int slot = ROUNDS == 1 ? (int)threadIdx.x : lane * 4 + wave;
+    const int wr = ROUNDS == 1 ? ((wave - (int)(blockIdx.x & 3u)) & 3) : wave;
+    const int slot = ROUNDS == 1 ? wr * kWave + lane : lane * 4 + wave;
     const int nact = ROUNDS == 1 ? (left >= (uint32_t)kProjBlock ? 4 : (int)((left + 63u) >> 6))
                                  : (left >= 4u ? 4 : (int)left);
-    if (wave >= nact) return false;
+    if (wr >= nact) return false;
     // ---- exact setup of the chunk's candidates, one per lane
     int ntiles = 0, tx0 = 0, ty0 = 0, tw = 1, th = 1, tile_base = 0, tiles_x = 1;
     uint32_t zbits = 0u;
@@ -493,10 +496,10 @@ __global__ __launch_bounds__(256, 4) void k_project(tsr_scene_dev sc, const floa
       uint32_t off = (uint32_t)__popcll(vmask & below);
       int seg = seg0;
       if constexpr (ROUNDS == 1) {
-        if (lane == 0) s_wave[wave] = (uint32_t)__popcll(vmask);
+        if (lane == 0) s_wave[wr] = (uint32_t)__popcll(vmask);
         __syncthreads();
-        for (int q = 0; q < wave; ++q) off += s_wave[q];
-        if (threadIdx.x == 0) {
+        for (int q = 0; q < wr; ++q) off += s_wave[q];
+        if (wr == 0 && lane == 0) {
           uint32_t nvis = 0u;
           for (int q = 0; q < nact; ++q) nvis += s_wave[q];
           vis_cnt[seg] = nvis;
